@@ -1,0 +1,439 @@
+"""Completed double-layer BIE and the rigid-body mobility MVP (oracle, FP64).
+
+Test infrastructure only (see the package docstring).
+
+The paper only fixes the structure of the mobility product, M ~ P M^stk P^T with
+a second-kind boundary integral equation solved by GMRES inside every product
+(Sec. 2, Fig. 1; Sec. 5.1, "tolerances"). The integral equation itself is not
+written in the paper. The reading used throughout this repository is the
+completed double-layer (Power-Miranda) second-kind formulation:
+
+  exterior velocity   u(x) = D[q](x) + V[F,T](x)
+  double layer        D[q](x) = 3/(4 pi) * int r (r.q(y)) (r.n(y)) / |r|^5 dS_y,
+                      r = x - y, n the outward normal, so that D[const] is
+                      -const inside a surface, -const/2 on it, 0 outside
+  completion          V[F,T](x) = 1/(8 pi mu) sum_j F_j/|r_j| + r_j (r_j.F_j)/|r_j|^3
+                                               + T_j x r_j/|r_j|^3,  r_j = x - c_j
+  equation on Gamma   (1/2 I + D + P)[q] = u_s - V[F,T]
+  rigid motion        U_i + Omega_i x (x - c_i) = -P_i[q]
+                      U_i = -1/(4 pi a^2) int q,  Omega_i = -3/(8 pi a^4) int (y-c_i) x q
+
+P_i is the orthogonal projector (in the quadrature inner product) onto the six
+rigid motions of particle i, and u_s the prescribed slip (zero for the
+collisional products). The double layer carries no force or torque, so the
+particles feel exactly F, T.
+
+Discretisation (one fixed rule so that every implementation computes the same
+discrete operator):
+  * nodes and weights of grid.sphere_grid on every sphere;
+  * off-particle interactions by the plain node rule, sum_y w_y K(x,y) q_y;
+  * near particle pairs (gap < near_gap): the source density is carried to an
+    upsampled grid (near_up x n_theta by near_up x n_phi, by its degree-p
+    spherical-harmonic projection) and summed with constant-density
+    subtraction, sum_f w_f K(x,y_f) (q_f - q_{f*(x)}), f*(x) the upsampled
+    node nearest to x (lowest index on ties). The subtraction uses
+    D_j[const](x) = 0 outside sphere j. This stands in for the paper's
+    near-singular evaluation, which the paper names by cost only (Sec. 5.1);
+  * the weakly singular self interaction by a rotated-pole rule: for each target
+    node x0 the sphere is re-gridded with x0 at the pole (Gauss-Legendre in the
+    polar angle theta' on [0, pi] with 3 n_theta points, trapezoid in phi' with
+    2 n_phi points); the sin(theta') Jacobian cancels the 1/|r| singularity; the
+    density is carried to the rotated nodes by its degree-p spherical-harmonic
+    projection. This is the self-quadrature whose O(p^4) cost the paper quotes
+    (Sec. 5.1).
+
+Vector layout in this module: surface fields are (N, 3) arrays, node-major,
+particle-major (all nodes of particle 0, then particle 1, ...).
+"""
+import numpy as np
+import scipy.linalg
+
+from . import grid as _grid
+
+FOUR_PI = 4.0 * np.pi
+
+
+class Geometry:
+    """Centres plus the per-sphere grid of one suspension (plain container)."""
+
+    def __init__(self, centers, radius=1.0, n_theta=8, n_phi=16, mu=1.0,
+                 near_gap=None, near_up=2):
+        self.c = np.array(centers, dtype=np.float64).reshape(-1, 3)
+        self.M = self.c.shape[0]
+        self.a = float(radius)
+        self.mu = float(mu)
+        self.n_theta, self.n_phi = int(n_theta), int(n_phi)
+        self.o, self.nrm, self.w = _grid.sphere_grid(self.n_theta, self.n_phi, self.a)
+        self.n = self.o.shape[0]
+        self.N = self.M * self.n
+        self.near_gap = 0.5 * self.a if near_gap is None else float(near_gap)
+        self.near_up = int(near_up)
+        self.x = (self.c[:, None, :] + self.o[None, :, :]).reshape(-1, 3)
+        self.normals = np.tile(self.nrm, (self.M, 1))
+        self.weights = np.tile(self.w, self.M)
+
+    def nodes(self, i):
+        s = slice(i * self.n, (i + 1) * self.n)
+        return s
+
+    def pair_class(self):
+        """(M, M) int array: 2 on the diagonal, 1 for near pairs, 0 otherwise."""
+        d = np.linalg.norm(self.c[:, None, :] - self.c[None, :, :], axis=2)
+        cls = np.where(d - 2.0 * self.a < self.near_gap, 1, 0)
+        np.fill_diagonal(cls, 2)
+        return cls
+
+
+# ---------------------------------------------------------------- kernels
+
+def dl_kernel(x, y, ny):
+    """3x3 double-layer kernel matrices K(x, y), shape (m, k, 3, 3).
+
+    K(x, y) q = 3/(4 pi) r (r.q)(r.n_y)/|r|^5 with r = x - y.
+    Pinned by: D[const] = -const at a sphere centre and ~0 outside
+    (tests/test_oracle_bie.py).
+    """
+    r = x[:, None, :] - y[None, :, :]
+    r2 = np.einsum('mki,mki->mk', r, r)
+    rn = np.einsum('mki,ki->mk', r, ny)
+    coef = (3.0 / FOUR_PI) * rn / (r2 * r2 * np.sqrt(r2))
+    return coef[:, :, None, None] * r[:, :, :, None] * r[:, :, None, :]
+
+
+def dl_apply(x, y, ny, wq):
+    """sum_y K(x, y) wq_y for targets x (m,3), sources y (k,3); returns (m,3)."""
+    out = np.zeros((x.shape[0], 3))
+    for s in range(0, x.shape[0], 256):
+        r = x[s:s + 256, None, :] - y[None, :, :]
+        r2 = np.einsum('mki,mki->mk', r, r)
+        rn = np.einsum('mki,ki->mk', r, ny)
+        rq = np.einsum('mki,ki->mk', r, wq)
+        coef = (3.0 / FOUR_PI) * rn * rq / (r2 * r2 * np.sqrt(r2))
+        out[s:s + 256] = np.einsum('mk,mki->mi', coef, r)
+    return out
+
+
+def nearest_node(x, y):
+    """Index of the source node nearest to each target (first index on ties)."""
+    d2 = ((x[:, None, :] - y[None, :, :]) ** 2).sum(axis=2)
+    return np.argmin(d2, axis=1)
+
+
+def completion(geom, FT, x=None):
+    """Stokeslet + rotlet field V[F,T] at points x (default: all nodes), (m,3).
+
+    FT is (M, 6): (Fx, Fy, Fz, Tx, Ty, Tz) per particle, the layout of the
+    paper's force vector (Sec. 2).
+    """
+    x = geom.x if x is None else x
+    FT = np.asarray(FT, dtype=np.float64).reshape(geom.M, 6)
+    out = np.zeros((x.shape[0], 3))
+    for j in range(geom.M):
+        r = x - geom.c[j]
+        d = np.linalg.norm(r, axis=1)
+        F, T = FT[j, :3], FT[j, 3:]
+        out += (F[None, :] / d[:, None]
+                + r * (r @ F)[:, None] / d[:, None] ** 3
+                + np.cross(T[None, :], r) / d[:, None] ** 3)
+    return out / (8.0 * np.pi * geom.mu)
+
+
+def janus_slip(geom, axes, speed):
+    """Janus slip u_s(x) = -s (e - (e.n) n) on the cap n.e > 0, else 0.
+
+    The paper's Janus interaction model is cited, not defined (Sec. 6); this
+    tangential half-cap slip is the reading used here. An isolated sphere then
+    swims along +e at s/3.
+    """
+    axes = np.asarray(axes, dtype=np.float64).reshape(geom.M, 3)
+    e = np.repeat(axes, geom.n, axis=0)
+    n = geom.normals
+    en = np.einsum('ki,ki->k', e, n)
+    u = -speed * (e - en[:, None] * n)
+    u[en <= 0.0] = 0.0
+    return u
+
+
+# --------------------------------------------------------- rigid projection
+
+def rigid_moments(geom, q):
+    """Per particle: sum w q (M,3) and sum w (y-c) x q (M,3)."""
+    q = q.reshape(geom.M, geom.n, 3)
+    wq = q * geom.w[None, :, None]
+    f = wq.sum(axis=1)
+    t = np.cross(geom.o[None, :, :], wq).sum(axis=1)
+    return f, t
+
+
+def rigid_projection(geom, q):
+    """P[q] (N,3): projection onto each particle's six rigid motions."""
+    f, t = rigid_moments(geom, q)
+    a = geom.a
+    U = f / (FOUR_PI * a * a)
+    W = t * (3.0 / (8.0 * np.pi * a ** 4))
+    out = U[:, None, :] + np.cross(W[:, None, :], geom.o[None, :, :])
+    return out.reshape(-1, 3)
+
+
+def rigid_velocity(geom, q):
+    """(U, Omega) per particle = -P[q] read as a rigid motion, (M, 6)."""
+    f, t = rigid_moments(geom, q)
+    a = geom.a
+    U = -f / (FOUR_PI * a * a)
+    W = -t * (3.0 / (8.0 * np.pi * a ** 4))
+    return np.concatenate([U, W], axis=1)
+
+
+# --------------------------------------------------------------- self block
+
+def _rot(theta, phi):
+    ct, st, cp, sp = np.cos(theta), np.sin(theta), np.cos(phi), np.sin(phi)
+    Ry = np.array([[ct, 0.0, st], [0.0, 1.0, 0.0], [-st, 0.0, ct]])
+    Rz = np.array([[cp, -sp, 0.0], [sp, cp, 0.0], [0.0, 0.0, 1.0]])
+    return Rz @ Ry
+
+
+_SELF_CACHE = {}
+
+
+def self_block(n_theta, n_phi, radius, theta_factor=3, phi_factor=2):
+    """Self-interaction matrix S of one sphere, shape (3, n, 3, n).
+
+    (S q)[c, i] = sum_{d,k} S[c, i, d, k] q[d, k] approximates the principal
+    value int_Gamma K(x_i, y) q(y) dS_y by the rotated-pole rule described in
+    the module docstring, computed target by target.
+    Pinned by: rigid motions map to minus half of themselves; the single-sphere
+    drag laws (tests/test_oracle_bie.py).
+    """
+    key = (n_theta, n_phi, float(radius), theta_factor, phi_factor)
+    if key in _SELF_CACHE:
+        return _SELF_CACHE[key]
+    a = float(radius)
+    p = n_theta - 1
+    o, nrm, w = _grid.sphere_grid(n_theta, n_phi, a)
+    n = o.shape[0]
+    th_n, ph_n = _grid.grid_angles(n_theta, n_phi)
+    _, _, w_unit = _grid.sphere_grid(n_theta, n_phi, 1.0)
+    Ygw = _grid.real_sh(p, th_n, ph_n) * w_unit[:, None]      # (n, L)
+
+    xi, wx = np.polynomial.legendre.leggauss(theta_factor * n_theta)
+    thp = 0.5 * np.pi * (xi + 1.0)
+    wth = 0.5 * np.pi * wx
+    nphp = phi_factor * n_phi
+    php = 2.0 * np.pi * np.arange(nphp) / nphp
+    TH = np.repeat(thp, nphp)
+    PH = np.tile(php, theta_factor * n_theta)
+    loc = np.stack([np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH)], axis=1)
+    Wz = a * a * np.sin(TH) * np.repeat(wth, nphp) * (2.0 * np.pi / nphp)
+
+    S = np.zeros((3, n, 3, n))
+    for i in range(n):
+        R = _rot(th_n[i], ph_n[i])
+        u = loc @ R.T
+        thz = np.arccos(np.clip(u[:, 2], -1.0, 1.0))
+        phz = np.arctan2(u[:, 1], u[:, 0])
+        Yz = _grid.real_sh(p, thz, phz)                        # (nz, L)
+        K = dl_kernel(o[i:i + 1], a * u, u)[0]                 # (nz, 3, 3)
+        G = np.einsum('z,zcd,zl->cdl', Wz, K, Yz)              # (3, 3, L)
+        S[:, i, :, :] = G @ Ygw.T                              # (3, 3, n)
+    _SELF_CACHE[key] = S
+    return S
+
+
+def self_block_nodemajor(S):
+    """Reshape (3, n, 3, n) to a (3n, 3n) matrix acting on (n, 3) node-major vectors."""
+    n = S.shape[1]
+    return S.transpose(1, 0, 3, 2).reshape(3 * n, 3 * n)
+
+
+# ------------------------------------------------------ operator (1/2 + D + P)
+
+_UP_CACHE = {}
+
+
+def upsample_matrix(n_theta, n_phi, up):
+    """(n_fine, n) map from grid values to the up-times finer grid (degree-p projection)."""
+    key = (n_theta, n_phi, up)
+    if key not in _UP_CACHE:
+        thf, phf = _grid.grid_angles(up * n_theta, up * n_phi)
+        _UP_CACHE[key] = _grid.projection_to_points(n_theta, n_phi, thf, phf)
+    return _UP_CACHE[key]
+
+
+def near_sources(geom, j):
+    """Upsampled nodes, normals and weights of sphere j used for near pairs."""
+    of, nf, wf = _grid.sphere_grid(geom.near_up * geom.n_theta, geom.near_up * geom.n_phi, geom.a)
+    return geom.c[j] + of, nf, wf
+
+
+def near_block(geom, i, j):
+    """Dense (n, 3, n, 3) near-pair block: upsampled plain rule with subtraction."""
+    cache = geom.__dict__.setdefault('_near_cache', {})
+    if (i, j) in cache:
+        return cache[(i, j)]
+    X = geom.x[geom.nodes(i)]
+    yf, nf, wf = near_sources(geom, j)
+    I = upsample_matrix(geom.n_theta, geom.n_phi, geom.near_up)
+    K = dl_kernel(X, yf, nf) * wf[None, :, None, None]          # (n, nf, 3, 3)
+    fs = nearest_node(X, yf)
+    blk = np.einsum('mfcd,fk->mckd', K, I)
+    blk -= np.einsum('mcd,mk->mckd', K.sum(axis=1), I[fs])
+    cache[(i, j)] = blk
+    return blk
+
+
+def offdiag_block(geom, i, j, near):
+    """Dense (3n, 3n) block of D mapping q on sphere j to targets on sphere i."""
+    if near:
+        return near_block(geom, i, j).reshape(3 * geom.n, 3 * geom.n)
+    si, sj = geom.nodes(i), geom.nodes(j)
+    K = dl_kernel(geom.x[si], geom.x[sj], geom.normals[sj]) * geom.w[None, :, None, None]
+    return K.transpose(0, 2, 1, 3).reshape(3 * geom.n, 3 * geom.n)
+
+
+def dense_operator(geom):
+    """Assembled (3N, 3N) matrix of (1/2 I + D + P) on node-major vectors."""
+    n3 = 3 * geom.n
+    A = np.zeros((3 * geom.N, 3 * geom.N))
+    S = self_block_nodemajor(self_block(geom.n_theta, geom.n_phi, geom.a))
+    cls = geom.pair_class()
+    for i in range(geom.M):
+        for j in range(geom.M):
+            blk = S if i == j else offdiag_block(geom, i, j, cls[i, j] == 1)
+            A[i * n3:(i + 1) * n3, j * n3:(j + 1) * n3] = blk
+    A += 0.5 * np.eye(3 * geom.N)
+    # rigid projection, column by column of each sphere
+    a = geom.a
+    for i in range(geom.M):
+        o = geom.o
+        cx = np.zeros((geom.n, 3, 3))
+        cx[:, 0, 1], cx[:, 0, 2] = -o[:, 2], o[:, 1]
+        cx[:, 1, 0], cx[:, 1, 2] = o[:, 2], -o[:, 0]
+        cx[:, 2, 0], cx[:, 2, 1] = -o[:, 1], o[:, 0]
+        Ptr = np.kron(np.ones((geom.n, 1)), np.kron(geom.w[None, :], np.eye(3))) / (FOUR_PI * a * a)
+        Prot = -np.einsum('mab,kbc,k->makc', cx, cx, geom.w).reshape(n3, n3) * (3.0 / (8.0 * np.pi * a ** 4))
+        A[i * n3:(i + 1) * n3, i * n3:(i + 1) * n3] += Ptr + Prot
+    return A
+
+
+def offdiag_apply(geom, q, i_targets=None):
+    """Off-particle part of D applied to q (N,3); returns (N,3) (or rows of i_targets)."""
+    q = q.reshape(geom.N, 3)
+    wq = q * geom.weights[:, None]
+    cls = geom.pair_class()
+    tgts = range(geom.M) if i_targets is None else i_targets
+    out = np.zeros((geom.N, 3))
+    for i in tgts:
+        si = geom.nodes(i)
+        xi = geom.x[si]
+        acc = np.zeros((geom.n, 3))
+        for j in range(geom.M):
+            if j == i:
+                continue
+            sj = geom.nodes(j)
+            if cls[i, j] == 1:
+                acc += np.einsum('mckd,kd->mc', near_block(geom, i, j), q[sj])
+            else:
+                acc += dl_apply(xi, geom.x[sj], geom.normals[sj], wq[sj])
+        out[si] = acc
+    return out
+
+
+def self_apply(geom, q):
+    """Self-interaction part of D (block diagonal), (N,3) -> (N,3)."""
+    S = self_block(geom.n_theta, geom.n_phi, geom.a)
+    qq = q.reshape(geom.M, geom.n, 3)
+    return np.einsum('cidk,mkd->mic', S, qq).reshape(-1, 3)
+
+
+def operator_apply(geom, q):
+    """Matrix-free (1/2 I + D + P)[q] for (N,3) densities."""
+    q = q.reshape(geom.N, 3)
+    return 0.5 * q + self_apply(geom, q) + offdiag_apply(geom, q) + rigid_projection(geom, q)
+
+
+# ------------------------------------------------------------------- GMRES
+
+def gmres(apply, rhs, tol=1e-13, restart=50, maxiter=1000):
+    """Restarted GMRES (modified Gram-Schmidt Arnoldi, Givens rotations).
+
+    Textbook GMRES(m): stops when the residual norm falls below tol * ||rhs||.
+    Returns (x, iterations, final relative residual estimate).
+    """
+    b = rhs.ravel().astype(np.float64)
+    x = np.zeros_like(b)
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return x, 0, 0.0
+    its = 0
+    while True:
+        r = b - apply(x.reshape(rhs.shape)).ravel()
+        beta = np.linalg.norm(r)
+        if beta <= tol * bnorm or its >= maxiter:
+            return x, its, beta / bnorm
+        V = np.zeros((restart + 1, b.size))
+        H = np.zeros((restart + 1, restart))
+        cs, sn = np.zeros(restart), np.zeros(restart)
+        g = np.zeros(restart + 1)
+        g[0] = beta
+        V[0] = r / beta
+        k = 0
+        for k in range(restart):
+            its += 1
+            wv = apply(V[k].reshape(rhs.shape)).ravel()
+            for i in range(k + 1):
+                H[i, k] = V[i] @ wv
+                wv -= H[i, k] * V[i]
+            H[k + 1, k] = np.linalg.norm(wv)
+            if H[k + 1, k] > 0.0:
+                V[k + 1] = wv / H[k + 1, k]
+            for i in range(k):
+                t = cs[i] * H[i, k] + sn[i] * H[i + 1, k]
+                H[i + 1, k] = -sn[i] * H[i, k] + cs[i] * H[i + 1, k]
+                H[i, k] = t
+            den = np.hypot(H[k, k], H[k + 1, k])
+            cs[k], sn[k] = H[k, k] / den, H[k + 1, k] / den
+            H[k, k] = den
+            H[k + 1, k] = 0.0
+            g[k + 1] = -sn[k] * g[k]
+            g[k] = cs[k] * g[k]
+            if abs(g[k + 1]) <= tol * bnorm or its >= maxiter:
+                break
+        m = k + 1
+        y = np.linalg.solve(np.triu(H[:m, :m]), g[:m])
+        x += V[:m].T @ y
+
+
+# --------------------------------------------------------------- mobility
+
+def solve_density(geom, rhs, dense=None, tol=1e-13):
+    """Density q solving (1/2 I + D + P) q = rhs; dense LU when a matrix is given."""
+    if dense is not None:
+        lu = geom.__dict__.get('_lu')
+        if lu is None or lu[0] is not dense:
+            lu = (dense, scipy.linalg.lu_factor(dense))
+            geom._lu = lu
+        return scipy.linalg.lu_solve(lu[1], rhs.ravel()).reshape(-1, 3)
+    q, _, _ = gmres(lambda v: operator_apply(geom, v), rhs, tol=tol)
+    return q.reshape(-1, 3)
+
+
+def mobility_apply(geom, FT, dense=None, tol=1e-13):
+    """U = M F: rigid velocities (M, 6) for forces/torques FT (M, 6).
+
+    Sec. 2, eq. (mobility): the mobility product; Fig. 1: it is applied as
+    lift (V[F,T]), second-kind surface solve, projection (-P[q]).
+    Pinned by: Stokes drag U = F/(6 pi mu a), Omega = T/(8 pi mu a^3) for a
+    single sphere; far-field two-sphere mobilities; symmetry and definiteness
+    of the assembled matrix (tests/test_oracle_bie.py).
+    """
+    rhs = -completion(geom, FT)
+    q = solve_density(geom, rhs, dense, tol)
+    return rigid_velocity(geom, q)
+
+
+def nc_velocity(geom, axes, speed, dense=None, tol=1e-13):
+    """Slip-driven rigid velocities U_nc (M, 6) with F = T = 0 (Sec. 2, eq. (mobility))."""
+    rhs = janus_slip(geom, axes, speed)
+    q = solve_density(geom, rhs, dense, tol)
+    return rigid_velocity(geom, q)

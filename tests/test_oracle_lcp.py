@@ -1,0 +1,187 @@
+"""Pins of the oracle's LCP layer: prox, step size, BFGS, solvers."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bie, dynamics, lcp
+from paper_2604_10089_amd import inputs
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), 'golden', 'closed_forms.json')))
+
+
+def _spd(n, seed, kappa=10.0):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return Q @ np.diag(np.linspace(1.0, kappa, n)) @ Q.T
+
+
+def _bfgs_memory(A, r, seed):
+    rng = np.random.default_rng(seed)
+    qn = lcp.QuasiNewton(A.shape[0])
+    for _ in range(r):
+        s = rng.standard_normal(A.shape[0])
+        qn.update(s, A @ s)
+    return qn
+
+
+@pytest.mark.parametrize("n,r,seed", [(8, 3, 0), (8, 6, 1), (40, 5, 2), (40, 12, 3)])
+def test_prox_kkt_and_primal(n, r, seed):
+    A = _spd(n, seed)
+    qn = _bfgs_memory(A, r, seed + 10)
+    B = qn.dense()
+    xt = np.random.default_rng(seed + 20).standard_normal(n) * 2.0
+    xh, steps, conv = lcp.prox_ssn(xt, np.array(qn.U).T, np.array(qn.V).T)
+    assert conv
+    lam = B @ (xh - xt)
+    scale = max(1.0, np.abs(xt).max())
+    assert xh.min() >= 0.0
+    assert lam.min() >= -1e-12 * scale
+    assert np.abs(xh * lam).max() <= 1e-12 * scale * scale
+    assert np.abs(xh - lcp.prox_primal(B, xt)).max() <= 1e-10 * scale
+
+
+def test_prox_rank_zero_is_projection():
+    xt = np.array([1.0, -2.0, 0.0, 3.5])
+    xh, _, _ = lcp.prox_ssn(xt, None, None)
+    assert np.array_equal(xh, np.maximum(xt, 0.0))
+
+
+def test_bfgs_secant_and_inverse():
+    n = 12
+    A = _spd(n, 4)
+    rng = np.random.default_rng(5)
+    qn = lcp.QuasiNewton(n)
+    H = np.eye(n)
+    for _ in range(6):
+        s = rng.standard_normal(n)
+        y = A @ s
+        assert qn.update(s, y)
+        assert np.abs(qn.B_apply(s) - y).max() <= 1e-12 * np.abs(y).max()
+        rho = 1.0 / (y @ s)
+        E = np.eye(n) - rho * np.outer(s, y)
+        H = E @ H @ E.T + rho * np.outer(s, s)        # textbook inverse BFGS update
+    assert np.abs(H @ qn.dense() - np.eye(n)).max() < 1e-10
+    g = rng.standard_normal(n)
+    assert np.abs(qn.H_apply(g) - H @ g).max() < 1e-10 * np.abs(H @ g).max()
+
+
+def test_step_size_is_constrained_minimiser():
+    n = 10
+    A = _spd(n, 6)
+    rng = np.random.default_rng(7)
+    for trial in range(20):
+        x = np.maximum(rng.standard_normal(n), 0.0)
+        b = rng.standard_normal(n)
+        g = A @ x + b
+        xh = np.maximum(x - 0.3 * g + 0.1 * rng.standard_normal(n), 0.0)
+        p = xh - x
+        if p @ g >= 0:
+            continue
+        eta, reset = lcp.step_size(g, x, p, A @ p)
+        assert not reset
+        neg = p < 0
+        emax = np.min(-x[neg] / p[neg]) if neg.any() else 1e6
+        grid = np.linspace(0.0, emax, 20001)
+        fvals = [lcp.objective(A, b, x + e * p) for e in grid]
+        assert lcp.objective(A, b, x + eta * p) <= min(fvals) + 1e-12
+        assert (x + eta * p).min() >= -1e-14
+        alpha = 0.49   # Lemma 1, sufficient decrease in the form of eq. (suffDecSimp)
+        assert 0.5 * eta * (p @ A @ p) <= -(1 - alpha) * (g @ p) + 1e-14
+
+
+def test_step_size_edge_cases():
+    g = np.array([1.0, 1.0])
+    x = np.array([1.0, 1.0])
+    assert lcp.step_size(g, x, np.array([1.0, 0.0]), np.array([1.0, 0.0])) == (1.0, True)   # ascent
+    assert lcp.step_size(g, x, np.array([-1.0, 0.0]), np.array([1.0, 0.0])) == (1.0, True)   # pAp < 0
+
+
+def test_secant_transfer_invariant():
+    n = 9
+    rng = np.random.default_rng(8)
+    Ahat = _spd(n, 9)
+    corr = lcp.QuasiNewton(n, b0_apply=lambda v: Ahat @ v)
+    Bk = Ahat.copy()
+    S = [rng.standard_normal(n) for _ in range(4)]
+    Y = [Bk @ s for s in S]
+    s = rng.standard_normal(n)
+    y = _spd(n, 10) @ s
+    assert corr.update(s, y)
+    S2, Y2 = lcp.secant_transfer(S, Y, corr.U[0], corr.V[0])
+    Bk1 = Bk + np.outer(corr.U[0], corr.U[0]) - np.outer(corr.V[0], corr.V[0])
+    for sh, yh in zip(S2, Y2):
+        assert np.abs(Bk1 @ sh - yh).max() < 1e-12 * np.abs(yh).max()
+    assert np.abs(Bk1 @ s - y).max() < 1e-12 * np.abs(y).max()
+
+
+def _dense_lcp(g, A, pairs):
+    mob = lambda FT: bie.mobility_apply(g, FT, dense=A)
+    Aop = lcp.lcp_operator(mob, g.c, pairs)
+    n = pairs.shape[0]
+    return Aop, np.column_stack([Aop(np.eye(n)[k]) for k in range(n)])
+
+
+def _check_complementarity(x, Ad, b):
+    w = Ad @ x + b
+    sx, sw = max(1.0, np.abs(x).max()), max(1.0, np.abs(b).max())
+    assert x.min() >= 0.0
+    assert w.min() >= -1e-10 * sw
+    assert np.abs(x * w).max() <= 1e-10 * sx * sw
+
+
+@pytest.fixture(scope="module")
+def tiny_lcps(tiny_cases):
+    out = []
+    for seed, g, A in tiny_cases:
+        pairs, gaps = dynamics.find_contacts(g.c, 1.0, 0.1)
+        Aop, Ad = _dense_lcp(g, A, pairs)
+        glo = bie.Geometry(g.c, 1.0, 4, 8)
+        Alo_d = bie.dense_operator(glo)
+        Alo = lcp.lcp_operator(lambda FT, glo=glo, Alo_d=Alo_d: bie.mobility_apply(glo, FT, dense=Alo_d), g.c, pairs)
+        axes = -g.c / np.linalg.norm(g.c, axis=1)[:, None]
+        b_real = lcp.lcp_b(gaps, 0.1, g.c, pairs, bie.nc_velocity(g, axes, 1.0, dense=A))
+        xs, ws = inputs.planted_lcp(seed, pairs.shape[0])
+        out.append(dict(seed=seed, Aop=Aop, Ad=Ad, Alo=Alo, b_real=b_real, x_pl=xs, b_pl=ws - Ad @ xs))
+    return out
+
+
+def test_lcp_matrix_positive_definite(tiny_lcps):
+    for c in tiny_lcps:
+        Ad = c['Ad']
+        assert np.linalg.eigvalsh(0.5 * (Ad + Ad.T)).min() > 0.0
+        assert np.linalg.norm(Ad - Ad.T) / np.linalg.norm(Ad) < 0.1
+
+
+@pytest.mark.parametrize("solver", ["mono", "bb", "bi"])
+def test_solvers_match_brute_force(tiny_lcps, solver):
+    for c in tiny_lcps:
+        for b, xref in ((c['b_real'], None), (c['b_pl'], c['x_pl'])):
+            xbf = lcp.brute_force_lcp(c['Ad'], b)
+            if xref is not None:
+                assert np.abs(xbf - xref).max() < 1e-12
+            kw = dict(tol_abs=1e-12, tol_rel=1e-15)
+            if solver == 'mono':
+                x, Ax, st = lcp.mono_pqn(c['Aop'], b, **kw)
+            elif solver == 'bb':
+                x, Ax, st = lcp.bb_pgd(c['Aop'], b, tau0=3 * np.pi, k_max=500, **kw)
+            else:
+                x, Ax, st = lcp.bi_pqn(c['Aop'], c['Alo'], b, **kw)
+            assert st['converged']
+            assert np.abs(x - xbf).max() <= 1e-10 * max(np.abs(xbf).max(), 1e-300)
+            _check_complementarity(x, c['Ad'], b)
+            # MVP reuse (Remark after Alg. 2): recurrence vs fresh product
+            assert np.abs(Ax - c['Ad'] @ x).max() <= 1e-12 * max(1.0, np.abs(c['Ad'] @ x).max())
+
+
+def test_mvp_counts_in_paper_range(tiny_lcps):
+    """Soft check only (parity unpinned): Table 2's counts come from another discretisation."""
+    soft = GOLD['paper_table2_mvps_soft']
+    counts = []
+    for c in tiny_lcps:
+        _, _, sm = lcp.mono_pqn(c['Aop'], c['b_pl'])
+        _, _, sb = lcp.bb_pgd(c['Aop'], c['b_pl'], tau0=3 * np.pi)
+        counts.append((sm['mvp'], sb['mvp']))
+    for m, bb in counts:
+        assert m <= 3 * soft['mono_pqn_median'] and bb <= 5 * soft['bb_pgd_median']
