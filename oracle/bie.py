@@ -30,8 +30,9 @@ discrete operator):
   * near particle pairs (gap < near_gap): the source density is carried to an
     upsampled grid (near_up x n_theta by near_up x n_phi, by its degree-p
     spherical-harmonic projection) and summed with constant-density
-    subtraction, sum_f w_f K(x,y_f) (q_f - q_{f*(x)}), f*(x) the upsampled
-    node nearest to x (lowest index on ties). The subtraction uses
+    subtraction, sum_f w_f K(x,y_f) (q_f - q_j(x*)), where x* is the foot
+    point of x on sphere j (the surface point nearest to x) and q_j(x*) the
+    degree-p expansion of the density there. The subtraction uses
     D_j[const](x) = 0 outside sphere j. This stands in for the paper's
     near-singular evaluation, which the paper names by cost only (Sec. 5.1);
   * the weakly singular self interaction by a rotated-pole rule: for each target
@@ -111,12 +112,6 @@ def dl_apply(x, y, ny, wq):
         coef = (3.0 / FOUR_PI) * rn * rq / (r2 * r2 * np.sqrt(r2))
         out[s:s + 256] = np.einsum('mk,mki->mi', coef, r)
     return out
-
-
-def nearest_node(x, y):
-    """Index of the source node nearest to each target (first index on ties)."""
-    d2 = ((x[:, None, :] - y[None, :, :]) ** 2).sum(axis=2)
-    return np.argmin(d2, axis=1)
 
 
 def completion(geom, FT, x=None):
@@ -275,9 +270,12 @@ def near_block(geom, i, j):
     yf, nf, wf = near_sources(geom, j)
     I = upsample_matrix(geom.n_theta, geom.n_phi, geom.near_up)
     K = dl_kernel(X, yf, nf) * wf[None, :, None, None]          # (n, nf, 3, 3)
-    fs = nearest_node(X, yf)
+    u = X - geom.c[j]
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    Ifoot = _grid.projection_to_points(geom.n_theta, geom.n_phi, np.arccos(np.clip(u[:, 2], -1.0, 1.0)),
+                                       np.arctan2(u[:, 1], u[:, 0]))   # (n, n)
     blk = np.einsum('mfcd,fk->mckd', K, I)
-    blk -= np.einsum('mcd,mk->mckd', K.sum(axis=1), I[fs])
+    blk -= np.einsum('mcd,mk->mckd', K.sum(axis=1), Ifoot)
     cache[(i, j)] = blk
     return blk
 
