@@ -1,0 +1,180 @@
+/* bipqn.h -- C ABI of the MI355X (gfx950) mobility-product and PQN/Bi-PQN library.
+ *
+ * The operations follow the statement of the problem in Rummel, Jensen, Becker,
+ * Corona, "A Bifidelity Proximal Quasi-Newton Method for Dense Rigid Body
+ * Suspension Collision Resolution":
+ *   - the rigid-body mobility product U = M F (Sec. 2, eq. (mobility); Fig. 1),
+ *     computed by a second-kind boundary integral solve with GMRES inside;
+ *   - the LCP 0 <= A x + b  perp  x >= 0 with A = D^T M D and
+ *     b = Phi/dt + D^T U_nc (Sec. 3, eq. (LCP), eq. (defAandb)), solved by
+ *     BB-PGD (eq. (spectralStepSize)), Mono-PQN (Alg. 1) or Bi-PQN (Alg. 4);
+ *   - one forward-Euler step of the linearised DVI (Sec. 3, eq. (dvi)).
+ *
+ * Conventions (all entry points):
+ *   - Every function returns pqn_status; PQN_OK = 0. A negative status means
+ *     nothing was written to the outputs; pqn_last_error() then returns a
+ *     message (thread-local, valid until the next call on the same thread).
+ *     PQN_WARN_NOT_CONVERGED means outputs were written but an iteration cap
+ *     was hit; the stats structure says which.
+ *   - Pointers without a _dev suffix in the function name are HOST pointers
+ *     owned by the caller; the library copies in and out and returns after
+ *     the work has finished. _dev functions take DEVICE pointers on the
+ *     context's device and return after the work has finished on the
+ *     context's stream.
+ *   - Forces/velocities are particle-major [M][6]: (Fx,Fy,Fz,Tx,Ty,Tz) and
+ *     (Ux,Uy,Uz,Wx,Wy,Wz), the layout of the paper's vectors F and U (Sec. 2).
+ *   - Surface fields are SoA [3][N] (all x components, then y, then z), node
+ *     index t = sphere*n + theta_row*n_phi + phi_col, n = n_theta*n_phi,
+ *     theta rows in ascending cos(theta).
+ *   - A context is not thread-safe; use one context per host thread/stream.
+ */
+#ifndef BIPQN_H
+#define BIPQN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pqn_ctx pqn_ctx;
+
+typedef enum {
+  PQN_OK = 0,
+  PQN_WARN_NOT_CONVERGED = 1,
+  PQN_ERR_INVALID = -1, /* bad argument or size */
+  PQN_ERR_DEVICE = -2,  /* HIP runtime error */
+  PQN_ERR_OOM = -3,     /* device allocation failed */
+  PQN_ERR_NUMERIC = -4, /* NaN/Inf encountered */
+  PQN_ERR_STATE = -5    /* call not valid in the context's state */
+} pqn_status;
+
+typedef enum { PQN_FP64 = 0, PQN_MIXED = 1 } pqn_precision;
+typedef enum { PQN_BBPGD = 0, PQN_MONO = 1, PQN_BI = 2 } pqn_solver;
+typedef enum { PQN_HIFI = 0, PQN_LOFI = 1 } pqn_fidelity;
+
+/* Context description; copied by pqn_create. Zero fields take the defaults
+ * given in brackets. */
+typedef struct {
+  int32_t n_particles;      /* M spheres (> 0) */
+  double radius;            /* sphere radius a [1] */
+  double mu;                /* viscosity [1] */
+  int32_t n_theta, n_phi;   /* high-fidelity grid: Gauss-Legendre x trapezoid; p = n_theta - 1 */
+  int32_t n_theta_lo, n_phi_lo; /* low-fidelity grid; 0 = none (Bi-PQN then unavailable) */
+  double gmres_tol;         /* relative residual of each high-fidelity BIE solve [1e-8] */
+  double gmres_tol_lo;      /* same, low fidelity [1e-8] */
+  int32_t gmres_restart;    /* Krylov restart length [50] */
+  int32_t gmres_max_iter;   /* iteration cap per solve [500] */
+  double near_gap;          /* sphere pairs with gap < near_gap use the near rule [0.5 a] */
+  int32_t near_up;          /* upsampling factor of the near rule [2] */
+  double slip_speed;        /* Janus slip magnitude s [1] */
+  int32_t precision;        /* pqn_precision of the far-field pair sums [PQN_FP64] */
+  int32_t refine_sweeps;    /* mixed precision: outer refinement sweeps with an FP64 residual [0] */
+  int32_t targets_per_thread; /* far FP32 kernel: 1 or 2 [2] */
+  int32_t far_chunks;       /* far kernels: source-sphere chunks (grid y); 0 = automatic */
+  int32_t device;           /* HIP device ordinal [0] */
+  void* stream;             /* hipStream_t to run on; NULL = the library creates one */
+  int32_t profile;          /* 1 = time every far pair-sum launch with HIP events */
+} pqn_config_desc;
+
+typedef struct {
+  int32_t gmres_iters;      /* Krylov iterations (all sweeps) */
+  int32_t matvecs;          /* BIE operator applications */
+  int32_t refine_sweeps;    /* FP64-residual refinement sweeps done */
+  int32_t converged;        /* 1 if the last residual met the tolerance */
+  double rel_residual;      /* final relative residual (GMRES estimate, or FP64 residual after refinement) */
+  double t_total_ms;        /* wall time of the call */
+  double t_far_ms;          /* summed far pair-sum kernel time (profile = 1) */
+  int32_t n_far;            /* far pair-sum launches */
+} pqn_mvp_stats;
+
+typedef struct {
+  int32_t k_max;            /* outer iteration cap [100] */
+  int32_t k_max_inner;      /* Bi-PQN: low-fidelity products per subproblem / initial solve [50] */
+  int32_t j_max;            /* semi-smooth Newton steps per prox (Alg. 3) [50] */
+  double kkt_tol_abs;       /* ||min(x, Ax+b)||_2 tolerance, eq. (kkt-error) [1e-8] */
+  double kkt_tol_rel;       /* relative change tolerance, eq. (kkt-error) [1e-8] */
+} pqn_lcp_opts;
+
+typedef struct {
+  int32_t iters;            /* outer iterations */
+  int32_t mvp_hi;           /* high-fidelity LCP products A[.] (each one BIE solve) */
+  int32_t mvp_lo;           /* low-fidelity LCP products (Bi-PQN) */
+  double emvp;              /* mvp_hi + mvp_lo * t_lo/t_hi (E-MVPs, Sec. 6) */
+  double lo_hi_cost_ratio;  /* measured t_lo/t_hi of this call */
+  double kkt_abs;           /* final absolute KKT error */
+  int32_t converged;
+  int32_t ssn_steps;        /* semi-smooth Newton steps in total */
+  double t_total_ms;
+  int32_t gmres_iters;      /* Krylov iterations over all products */
+} pqn_lcp_stats;
+
+typedef struct {
+  int32_t n_contacts;       /* |A| of eq. (collisional-set) */
+  int32_t n_active;         /* contacts with x > 0 */
+  pqn_lcp_stats lcp;
+  int32_t gmres_iters_nc;   /* Krylov iterations of the U_nc solve */
+  double t_total_ms;
+} pqn_step_stats;
+
+/* Create a context for M spheres (centers [M][3], janus_axes [M][3] unit vectors;
+ * axes may be NULL = no slip). Builds the grids, the singular self blocks (FP64,
+ * host) and allocates device memory. */
+pqn_status pqn_create(const pqn_config_desc* desc, const double* centers, const double* janus_axes, pqn_ctx** out);
+pqn_status pqn_destroy(pqn_ctx* ctx);
+
+/* Replace / read the configuration (sphere centres and Janus axes, [M][3]). */
+pqn_status pqn_set_state(pqn_ctx* ctx, const double* centers, const double* janus_axes);
+pqn_status pqn_get_state(const pqn_ctx* ctx, double* centers, double* janus_axes);
+/* Far pair-sum precision (pqn_precision) for subsequent calls. */
+pqn_status pqn_set_precision(pqn_ctx* ctx, int32_t precision);
+
+/* U = M F (Sec. 2, eq. (mobility); Fig. 1): FT, UO [M][6]. */
+pqn_status pqn_mobility_apply(pqn_ctx* ctx, const double* FT, double* UO, int32_t fidelity, pqn_mvp_stats* stats);
+pqn_status pqn_mobility_apply_dev(pqn_ctx* ctx, const double* FT_dev, double* UO_dev, int32_t fidelity,
+                                  pqn_mvp_stats* stats);
+/* Slip-driven rigid velocities U_nc (F = T = 0), UO [M][6]. */
+pqn_status pqn_nc_velocity(pqn_ctx* ctx, double* UO, int32_t fidelity, pqn_mvp_stats* stats);
+
+/* Candidate contacts (eq. (collisional-set)): pairs i < j with gap |c_i - c_j| - 2a <= delta,
+ * lexicographic order. pairs [cap][2], gaps [cap]. If more than cap pairs exist, returns
+ * PQN_ERR_INVALID with *n_out set to the number needed. */
+pqn_status pqn_find_contacts(pqn_ctx* ctx, double delta, int32_t cap, int32_t* n_out, int32_t* pairs, double* gaps);
+
+/* One LCP product Ax = D^T M D x (eq. (defAandb)); pairs [n][2] (i, j), x, Ax [n]. */
+pqn_status pqn_lcp_apply(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const double* x, double* Ax, int32_t fidelity);
+
+/* Solve 0 <= A x + b perp x >= 0 (eq. (LCP)). x: on entry ignored (the solvers start
+ * at 0), on exit the solution. opts may be NULL (defaults). */
+pqn_status pqn_lcp_solve(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const double* b, double* x, int32_t solver,
+                         const pqn_lcp_opts* opts, pqn_lcp_stats* stats);
+
+/* One step (eq. (dvi)): contacts(delta) -> U_nc -> b = Phi/dt + D^T U_nc -> LCP ->
+ * U = U_nc + M D x -> centres += dt U, Janus axes rotated by Omega dt. */
+pqn_status pqn_step(pqn_ctx* ctx, double dt, double delta, int32_t solver, const pqn_lcp_opts* opts,
+                    pqn_step_stats* stats);
+
+/* Operator-level entry points (stage-by-stage checks of the discrete BIE).
+ * pqn_bie_apply: y = (1/2 I + D + P) q for q, y [3][N] host arrays.
+ * pqn_get_self_block: S [3n][3n] rows (c*n+i), columns (d*n+k).
+ * pqn_get_grid: node offsets [n][3] and weights [n] of one sphere. */
+pqn_status pqn_bie_apply(pqn_ctx* ctx, int32_t fidelity, const double* q, double* y);
+pqn_status pqn_get_self_block(pqn_ctx* ctx, int32_t fidelity, double* S);
+/* pqn_bie_solve: q solving (1/2 I + D + P) q = rhs by GMRES (plus refinement in mixed
+ * precision), rhs, q [3][N] host arrays. */
+pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, double* q, pqn_mvp_stats* stats);
+pqn_status pqn_get_grid(pqn_ctx* ctx, int32_t fidelity, int32_t* n_nodes, double* offsets, double* weights);
+
+/* Host-only (no device needed): the grid and singular self block of one sphere as
+ * pqn_create builds them. offsets [n][3], weights [n], S [3n][3n] (any may be NULL),
+ * n = n_theta * n_phi. */
+pqn_status pqn_host_self_block(int32_t n_theta, int32_t n_phi, double radius, double* offsets, double* weights,
+                               double* S);
+
+const char* pqn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIPQN_H */

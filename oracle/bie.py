@@ -189,9 +189,18 @@ def _rot(theta, phi):
 
 
 _SELF_CACHE = {}
+_SELF_ROW_CACHE = {}
 
 
-def self_block(n_theta, n_phi, radius, theta_factor=3, phi_factor=2):
+def self_block_row(n_theta, n_phi, radius, i):
+    """Row block S[:, i, :, :] (3, 3, n) of the self block for local target node i."""
+    key = (n_theta, n_phi, float(radius), int(i))
+    if key not in _SELF_ROW_CACHE:
+        _SELF_ROW_CACHE[key] = self_block(n_theta, n_phi, radius, rows=[int(i)])[:, int(i), :, :]
+    return _SELF_ROW_CACHE[key]
+
+
+def self_block(n_theta, n_phi, radius, theta_factor=3, phi_factor=2, rows=None):
     """Self-interaction matrix S of one sphere, shape (3, n, 3, n).
 
     (S q)[c, i] = sum_{d,k} S[c, i, d, k] q[d, k] approximates the principal
@@ -201,7 +210,7 @@ def self_block(n_theta, n_phi, radius, theta_factor=3, phi_factor=2):
     drag laws (tests/test_oracle_bie.py).
     """
     key = (n_theta, n_phi, float(radius), theta_factor, phi_factor)
-    if key in _SELF_CACHE:
+    if rows is None and key in _SELF_CACHE:
         return _SELF_CACHE[key]
     a = float(radius)
     p = n_theta - 1
@@ -222,7 +231,7 @@ def self_block(n_theta, n_phi, radius, theta_factor=3, phi_factor=2):
     Wz = a * a * np.sin(TH) * np.repeat(wth, nphp) * (2.0 * np.pi / nphp)
 
     S = np.zeros((3, n, 3, n))
-    for i in range(n):
+    for i in (range(n) if rows is None else rows):
         R = _rot(th_n[i], ph_n[i])
         u = loc @ R.T
         thz = np.arccos(np.clip(u[:, 2], -1.0, 1.0))
@@ -231,7 +240,8 @@ def self_block(n_theta, n_phi, radius, theta_factor=3, phi_factor=2):
         K = dl_kernel(o[i:i + 1], a * u, u)[0]                 # (nz, 3, 3)
         G = np.einsum('z,zcd,zl->cdl', Wz, K, Yz)              # (3, 3, L)
         S[:, i, :, :] = G @ Ygw.T                              # (3, 3, n)
-    _SELF_CACHE[key] = S
+    if rows is None:
+        _SELF_CACHE[key] = S
     return S
 
 
@@ -342,6 +352,34 @@ def self_apply(geom, q):
     S = self_block(geom.n_theta, geom.n_phi, geom.a)
     qq = q.reshape(geom.M, geom.n, 3)
     return np.einsum('cidk,mkd->mic', S, qq).reshape(-1, 3)
+
+
+def operator_rows(geom, q, targets):
+    """Rows of (1/2 I + D + P)[q] at the given global node indices, (len(targets), 3).
+
+    The same definition as operator_apply, evaluated target by target, for
+    suspensions too large to apply whole.
+    """
+    q = q.reshape(geom.N, 3)
+    wq = q * geom.weights[:, None]
+    cls = geom.pair_class()
+    P = rigid_projection(geom, q)
+    out = np.zeros((len(targets), 3))
+    for row, t in enumerate(targets):
+        i, k = divmod(int(t), geom.n)
+        xt = geom.x[t:t + 1]
+        Sk = self_block_row(geom.n_theta, geom.n_phi, geom.a, k)
+        acc = 0.5 * q[t] + np.einsum('cdm,md->c', Sk, q[geom.nodes(i)]) + P[t]
+        for j in range(geom.M):
+            if j == i:
+                continue
+            sj = geom.nodes(j)
+            if cls[i, j] == 1:
+                acc = acc + np.einsum('ckd,kd->c', near_block(geom, i, j)[k], q[sj])
+            else:
+                acc = acc + dl_apply(xt, geom.x[sj], geom.normals[sj], wq[sj])[0]
+        out[row] = acc
+    return out
 
 
 def operator_apply(geom, q):

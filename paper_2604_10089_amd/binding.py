@@ -1,0 +1,281 @@
+"""Thin ctypes binding of libbipqn.so: argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy arrays
+to pointers and back. Names follow the C ABI in include/bipqn.h. Loading fails
+loudly when the library has not been built.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, 'libbipqn.so')
+
+PQN_OK, PQN_WARN_NOT_CONVERGED = 0, 1
+PQN_FP64, PQN_MIXED = 0, 1
+PQN_BBPGD, PQN_MONO, PQN_BI = 0, 1, 2
+PQN_HIFI, PQN_LOFI = 0, 1
+SOLVERS = {'bb': PQN_BBPGD, 'mono': PQN_MONO, 'bi': PQN_BI}
+
+
+class ConfigDesc(C.Structure):
+    _fields_ = [('n_particles', C.c_int32), ('radius', C.c_double), ('mu', C.c_double),
+                ('n_theta', C.c_int32), ('n_phi', C.c_int32), ('n_theta_lo', C.c_int32), ('n_phi_lo', C.c_int32),
+                ('gmres_tol', C.c_double), ('gmres_tol_lo', C.c_double), ('gmres_restart', C.c_int32),
+                ('gmres_max_iter', C.c_int32), ('near_gap', C.c_double), ('near_up', C.c_int32),
+                ('slip_speed', C.c_double), ('precision', C.c_int32), ('refine_sweeps', C.c_int32),
+                ('targets_per_thread', C.c_int32), ('far_chunks', C.c_int32), ('device', C.c_int32),
+                ('stream', C.c_void_p), ('profile', C.c_int32)]
+
+
+class MvpStats(C.Structure):
+    _fields_ = [('gmres_iters', C.c_int32), ('matvecs', C.c_int32), ('refine_sweeps', C.c_int32),
+                ('converged', C.c_int32), ('rel_residual', C.c_double), ('t_total_ms', C.c_double),
+                ('t_far_ms', C.c_double), ('n_far', C.c_int32)]
+
+
+class LcpOpts(C.Structure):
+    _fields_ = [('k_max', C.c_int32), ('k_max_inner', C.c_int32), ('j_max', C.c_int32),
+                ('kkt_tol_abs', C.c_double), ('kkt_tol_rel', C.c_double)]
+
+
+class LcpStats(C.Structure):
+    _fields_ = [('iters', C.c_int32), ('mvp_hi', C.c_int32), ('mvp_lo', C.c_int32), ('emvp', C.c_double),
+                ('lo_hi_cost_ratio', C.c_double), ('kkt_abs', C.c_double), ('converged', C.c_int32),
+                ('ssn_steps', C.c_int32), ('t_total_ms', C.c_double), ('gmres_iters', C.c_int32)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [('n_contacts', C.c_int32), ('n_active', C.c_int32), ('lcp', LcpStats),
+                ('gmres_iters_nc', C.c_int32), ('t_total_ms', C.c_double)]
+
+
+def _struct_dict(s):
+    out = {}
+    for name, _ in s._fields_:
+        v = getattr(s, name)
+        out[name] = _struct_dict(v) if isinstance(v, C.Structure) else v
+    return out
+
+
+_LIB = None
+_P = C.POINTER
+_D = _P(C.c_double)
+_I = _P(C.c_int32)
+
+
+def lib():
+    """Load libbipqn.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f'{LIB_PATH} is missing: build it first (python -m paper_2604_10089_amd.build)')
+    L = C.CDLL(LIB_PATH)
+    V = C.c_void_p
+    sig = {
+        'pqn_create': (C.c_int, [_P(ConfigDesc), _D, _D, _P(V)]),
+        'pqn_destroy': (C.c_int, [V]),
+        'pqn_set_state': (C.c_int, [V, _D, _D]),
+        'pqn_get_state': (C.c_int, [V, _D, _D]),
+        'pqn_set_precision': (C.c_int, [V, C.c_int32]),
+        'pqn_mobility_apply': (C.c_int, [V, _D, _D, C.c_int32, _P(MvpStats)]),
+        'pqn_mobility_apply_dev': (C.c_int, [V, V, V, C.c_int32, _P(MvpStats)]),
+        'pqn_nc_velocity': (C.c_int, [V, _D, C.c_int32, _P(MvpStats)]),
+        'pqn_find_contacts': (C.c_int, [V, C.c_double, C.c_int32, _I, _I, _D]),
+        'pqn_lcp_apply': (C.c_int, [V, C.c_int32, _I, _D, _D, C.c_int32]),
+        'pqn_lcp_solve': (C.c_int, [V, C.c_int32, _I, _D, _D, C.c_int32, _P(LcpOpts), _P(LcpStats)]),
+        'pqn_step': (C.c_int, [V, C.c_double, C.c_double, C.c_int32, _P(LcpOpts), _P(StepStats)]),
+        'pqn_bie_apply': (C.c_int, [V, C.c_int32, _D, _D]),
+        'pqn_get_self_block': (C.c_int, [V, C.c_int32, _D]),
+        'pqn_bie_solve': (C.c_int, [V, C.c_int32, _D, _D, _P(MvpStats)]),
+        'pqn_get_grid': (C.c_int, [V, C.c_int32, _I, _D, _D]),
+        'pqn_host_self_block': (C.c_int, [C.c_int32, C.c_int32, C.c_double, _D, _D, _D]),
+        'pqn_last_error': (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = L
+    return L
+
+
+class PqnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f'status {status}: {msg}')
+        self.status = status
+
+
+def _check(status, allow_warn=True):
+    if status < 0 or (status == PQN_WARN_NOT_CONVERGED and not allow_warn):
+        raise PqnError(status, lib().pqn_last_error().decode())
+    return status
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def pqn_host_self_block(n_theta, n_phi, radius=1.0):
+    """(offsets [n,3], weights [n], S [3n,3n]) built on the host without a device."""
+    n = n_theta * n_phi
+    off = np.zeros((n, 3))
+    w = np.zeros(n)
+    S = np.zeros((3 * n, 3 * n))
+    _check(lib().pqn_host_self_block(n_theta, n_phi, radius, _dptr(off), _dptr(w), _dptr(S)))
+    return off, w, S
+
+
+class Context:
+    """Owns one pqn_ctx. Methods carry the C ABI names without the prefix."""
+
+    def __init__(self, centers, axes=None, n_theta=8, n_phi=16, lo=None, radius=1.0, mu=1.0,
+                 gmres_tol=1e-8, gmres_tol_lo=None, restart=50, max_iter=500, near_gap=0.0, near_up=2,
+                 slip=1.0, precision='fp64', refine=0, tpt=2, far_chunks=0, device=0, stream=None,
+                 profile=False):
+        c = _f64(centers).reshape(-1, 3)
+        self.M = c.shape[0]
+        d = ConfigDesc()
+        d.n_particles = self.M
+        d.radius, d.mu = radius, mu
+        d.n_theta, d.n_phi = n_theta, n_phi
+        if lo is not None:
+            d.n_theta_lo, d.n_phi_lo = lo
+        d.gmres_tol = gmres_tol
+        d.gmres_tol_lo = gmres_tol if gmres_tol_lo is None else gmres_tol_lo
+        d.gmres_restart, d.gmres_max_iter = restart, max_iter
+        d.near_gap, d.near_up, d.slip_speed = near_gap, near_up, slip
+        d.precision = PQN_MIXED if precision == 'mixed' else PQN_FP64
+        d.refine_sweeps = refine
+        d.targets_per_thread = tpt
+        d.far_chunks = far_chunks
+        d.device = device
+        d.stream = stream
+        d.profile = 1 if profile else 0
+        self.n_theta, self.n_phi, self.lo = n_theta, n_phi, lo
+        ax = None if axes is None else _f64(axes).reshape(-1, 3)
+        h = C.c_void_p()
+        _check(lib().pqn_create(C.byref(d), _dptr(c), None if ax is None else _dptr(ax), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, 'h', None):
+            lib().pqn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_state(self, centers, axes=None):
+        c = _f64(centers).reshape(-1, 3)
+        ax = None if axes is None else _f64(axes).reshape(-1, 3)
+        _check(lib().pqn_set_state(self.h, _dptr(c), None if ax is None else _dptr(ax)))
+
+    def get_state(self):
+        c = np.zeros((self.M, 3))
+        ax = np.zeros((self.M, 3))
+        _check(lib().pqn_get_state(self.h, _dptr(c), _dptr(ax)))
+        return c, ax
+
+    def set_precision(self, precision):
+        _check(lib().pqn_set_precision(self.h, PQN_MIXED if precision == 'mixed' else PQN_FP64))
+
+    def mobility_apply(self, FT, fidelity=PQN_HIFI):
+        FT = _f64(FT, (self.M, 6))
+        UO = np.zeros((self.M, 6))
+        st = MvpStats()
+        status = _check(lib().pqn_mobility_apply(self.h, _dptr(FT), _dptr(UO), fidelity, C.byref(st)))
+        return UO, dict(_struct_dict(st), status=status)
+
+    def mobility_apply_dev(self, FT_ptr, UO_ptr, fidelity=PQN_HIFI):
+        st = MvpStats()
+        status = _check(lib().pqn_mobility_apply_dev(self.h, C.c_void_p(FT_ptr), C.c_void_p(UO_ptr), fidelity,
+                                                     C.byref(st)))
+        return dict(_struct_dict(st), status=status)
+
+    def nc_velocity(self, fidelity=PQN_HIFI):
+        UO = np.zeros((self.M, 6))
+        st = MvpStats()
+        status = _check(lib().pqn_nc_velocity(self.h, _dptr(UO), fidelity, C.byref(st)))
+        return UO, dict(_struct_dict(st), status=status)
+
+    def find_contacts(self, delta):
+        n = C.c_int32(0)
+        L = lib()
+        st = L.pqn_find_contacts(self.h, delta, 0, C.byref(n), None, None)
+        if st < 0 and n.value == 0:
+            _check(st)
+        cap = max(n.value, 1)
+        pairs = np.zeros((cap, 2), dtype=np.int32)
+        gaps = np.zeros(cap)
+        _check(L.pqn_find_contacts(self.h, delta, cap, C.byref(n), pairs.ctypes.data_as(_I), _dptr(gaps)))
+        return pairs[:n.value].copy(), gaps[:n.value].copy()
+
+    def lcp_apply(self, pairs, x, fidelity=PQN_HIFI):
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        x = _f64(x)
+        Ax = np.zeros(pairs.shape[0])
+        _check(lib().pqn_lcp_apply(self.h, pairs.shape[0], pairs.ctypes.data_as(_I), _dptr(x), _dptr(Ax),
+                                   fidelity))
+        return Ax
+
+    def lcp_solve(self, pairs, b, solver='mono', k_max=0, k_max_inner=0, j_max=0, tol_abs=0.0, tol_rel=0.0):
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        b = _f64(b)
+        x = np.zeros(pairs.shape[0])
+        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel)
+        st = LcpStats()
+        status = _check(lib().pqn_lcp_solve(self.h, pairs.shape[0], pairs.ctypes.data_as(_I), _dptr(b), _dptr(x),
+                                            SOLVERS.get(solver, solver), C.byref(o), C.byref(st)))
+        return x, dict(_struct_dict(st), status=status)
+
+    def step(self, dt, delta, solver='mono', k_max=0, k_max_inner=0, j_max=0, tol_abs=0.0, tol_rel=0.0):
+        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel)
+        st = StepStats()
+        status = _check(lib().pqn_step(self.h, dt, delta, SOLVERS.get(solver, solver), C.byref(o), C.byref(st)))
+        return dict(_struct_dict(st), status=status)
+
+    def bie_apply(self, q_soa, fidelity=PQN_HIFI):
+        q = _f64(q_soa).ravel()
+        y = np.zeros_like(q)
+        _check(lib().pqn_bie_apply(self.h, fidelity, _dptr(q), _dptr(y)))
+        return y.reshape(3, -1)
+
+    def bie_solve(self, rhs_soa, fidelity=PQN_HIFI):
+        r = _f64(rhs_soa).ravel()
+        q = np.zeros_like(r)
+        st = MvpStats()
+        status = _check(lib().pqn_bie_solve(self.h, fidelity, _dptr(r), _dptr(q), C.byref(st)))
+        return q.reshape(3, -1), dict(_struct_dict(st), status=status)
+
+    def get_self_block(self, fidelity=PQN_HIFI):
+        n = self.get_grid(fidelity)[0].shape[0]
+        S = np.zeros((3 * n, 3 * n))
+        _check(lib().pqn_get_self_block(self.h, fidelity, _dptr(S)))
+        return S
+
+    def get_grid(self, fidelity=PQN_HIFI):
+        n = C.c_int32(0)
+        _check(lib().pqn_get_grid(self.h, fidelity, C.byref(n), None, None))
+        off = np.zeros((n.value, 3))
+        w = np.zeros(n.value)
+        _check(lib().pqn_get_grid(self.h, fidelity, C.byref(n), _dptr(off), _dptr(w)))
+        return off, w

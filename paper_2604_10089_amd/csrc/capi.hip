@@ -1,0 +1,293 @@
+// extern "C" entry points: argument checks, host/device copies, error mapping.
+#include <cstring>
+
+#include "context.hpp"
+#include "lcp.hpp"
+
+using namespace bipqn;
+
+static thread_local std::string g_last_error;
+
+static pqn_status fail(pqn_status s, const std::string& m) {
+  g_last_error = m;
+  return s;
+}
+
+template <class F>
+static pqn_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(PQN_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(PQN_ERR_INVALID, e.what());
+  }
+}
+
+static void fill_defaults(pqn_config_desc& c) {
+  if (c.radius <= 0) c.radius = 1.0;
+  if (c.mu <= 0) c.mu = 1.0;
+  if (c.gmres_tol <= 0) c.gmres_tol = 1e-8;
+  if (c.gmres_tol_lo <= 0) c.gmres_tol_lo = 1e-8;
+  if (c.gmres_restart <= 0) c.gmres_restart = 50;
+  if (c.gmres_max_iter <= 0) c.gmres_max_iter = 500;
+  if (c.near_gap <= 0) c.near_gap = 0.5 * c.radius;
+  if (c.near_up <= 0) c.near_up = 2;
+  if (c.slip_speed == 0) c.slip_speed = 1.0;
+  if (c.targets_per_thread <= 0) c.targets_per_thread = 2;
+}
+
+extern "C" {
+
+const char* pqn_last_error(void) { return g_last_error.c_str(); }
+
+pqn_status pqn_create(const pqn_config_desc* desc, const double* centers, const double* janus_axes, pqn_ctx** out) {
+  return guarded([&]() -> pqn_status {
+    if (!desc || !centers || !out) return fail(PQN_ERR_INVALID, "pqn_create: NULL argument");
+    *out = nullptr;
+    pqn_config_desc c = *desc;
+    fill_defaults(c);
+    if (c.n_particles <= 0) return fail(PQN_ERR_INVALID, "n_particles must be > 0");
+    if (c.n_theta < 2 || c.n_phi < 2 * c.n_theta - 1)
+      return fail(PQN_ERR_INVALID, "high-fidelity grid needs n_theta >= 2 and n_phi >= 2 n_theta - 1");
+    if (c.n_theta_lo != 0 && (c.n_theta_lo < 2 || c.n_phi_lo < 2 * c.n_theta_lo - 1))
+      return fail(PQN_ERR_INVALID, "low-fidelity grid needs n_theta >= 2 and n_phi >= 2 n_theta - 1");
+    if (c.precision != PQN_FP64 && c.precision != PQN_MIXED) return fail(PQN_ERR_INVALID, "bad precision");
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (c.device < 0 || c.device >= ndev) return fail(PQN_ERR_DEVICE, "no such HIP device");
+    HIPCHK(hipSetDevice(c.device));
+    std::unique_ptr<pqn_ctx> ctx(new pqn_ctx());
+    ctx->cfg = c;
+    ctx->M = c.n_particles;
+    ctx->a = c.radius;
+    ctx->mu = c.mu;
+    ctx->device = c.device;
+    if (c.stream) {
+      ctx->stream = (hipStream_t)c.stream;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+      ctx->own_stream = true;
+    }
+    ctx->setup_level(ctx->hi, c.n_theta, c.n_phi, c.gmres_tol);
+    if (c.n_theta_lo > 0) {
+      ctx->setup_level(ctx->lo, c.n_theta_lo, c.n_phi_lo, c.gmres_tol_lo);
+      ctx->has_lo = true;
+    }
+    ctx->FT.alloc(6 * (size_t)ctx->M);
+    ctx->UO.alloc(6 * (size_t)ctx->M);
+    ctx->set_configuration(centers, janus_axes);
+    *out = ctx.release();
+    return PQN_OK;
+  });
+}
+
+pqn_status pqn_destroy(pqn_ctx* ctx) {
+  if (!ctx) return PQN_OK;
+  return guarded([&]() -> pqn_status {
+    HIPCHK(hipSetDevice(ctx->device));
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+    return PQN_OK;
+  });
+}
+
+pqn_status pqn_set_state(pqn_ctx* ctx, const double* centers, const double* janus_axes) {
+  return guarded([&]() -> pqn_status {
+    if (!ctx || !centers) return fail(PQN_ERR_INVALID, "pqn_set_state: NULL argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    ctx->set_configuration(centers, janus_axes ? janus_axes : (ctx->has_axes ? ctx->axes.data() : nullptr));
+    return PQN_OK;
+  });
+}
+
+pqn_status pqn_get_state(const pqn_ctx* ctx, double* centers, double* janus_axes) {
+  if (!ctx) return fail(PQN_ERR_INVALID, "pqn_get_state: NULL context");
+  if (centers) std::memcpy(centers, ctx->centers.data(), ctx->centers.size() * sizeof(double));
+  if (janus_axes) std::memcpy(janus_axes, ctx->axes.data(), ctx->axes.size() * sizeof(double));
+  return PQN_OK;
+}
+
+pqn_status pqn_set_precision(pqn_ctx* ctx, int32_t precision) {
+  if (!ctx) return fail(PQN_ERR_INVALID, "NULL context");
+  if (precision != PQN_FP64 && precision != PQN_MIXED) return fail(PQN_ERR_INVALID, "bad precision");
+  ctx->cfg.precision = precision;
+  return PQN_OK;
+}
+
+static pqn_status mobility_common(pqn_ctx* ctx, const double* FT_dev, const double* axes_dev, double* UO_dev,
+                                  int32_t fidelity, pqn_mvp_stats* stats) {
+  Timer tm;
+  Level& lv = ctx->level(fidelity);
+  pqn_mvp_stats st{};
+  ctx->n_matvec = 0;
+  ctx->n_far = 0;
+  ctx->mobility(lv, FT_dev, axes_dev, UO_dev, &st);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  st.t_far_ms = ctx->end_far_timing();
+  st.matvecs = ctx->n_matvec;
+  st.n_far = ctx->n_far;
+  st.t_total_ms = tm.ms();
+  if (stats) *stats = st;
+  return st.converged ? PQN_OK : PQN_WARN_NOT_CONVERGED;
+}
+
+pqn_status pqn_mobility_apply_dev(pqn_ctx* ctx, const double* FT_dev, double* UO_dev, int32_t fidelity,
+                                  pqn_mvp_stats* stats) {
+  return guarded([&]() -> pqn_status {
+    if (!ctx || !FT_dev || !UO_dev) return fail(PQN_ERR_INVALID, "pqn_mobility_apply_dev: NULL argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    return mobility_common(ctx, FT_dev, nullptr, UO_dev, fidelity, stats);
+  });
+}
+
+pqn_status pqn_mobility_apply(pqn_ctx* ctx, const double* FT, double* UO, int32_t fidelity, pqn_mvp_stats* stats) {
+  return guarded([&]() -> pqn_status {
+    if (!ctx || !FT || !UO) return fail(PQN_ERR_INVALID, "pqn_mobility_apply: NULL argument");
+    for (int k = 0; k < 6 * ctx->M; ++k)
+      if (!std::isfinite(FT[k])) return fail(PQN_ERR_NUMERIC, "non-finite force/torque");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipMemcpyAsync(ctx->FT.p, FT, 6 * (size_t)ctx->M * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    pqn_status s = mobility_common(ctx, ctx->FT.p, nullptr, ctx->UO.p, fidelity, stats);
+    HIPCHK(hipMemcpyAsync(UO, ctx->UO.p, 6 * (size_t)ctx->M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return s;
+  });
+}
+
+pqn_status pqn_nc_velocity(pqn_ctx* ctx, double* UO, int32_t fidelity, pqn_mvp_stats* stats) {
+  return guarded([&]() -> pqn_status {
+    if (!ctx || !UO) return fail(PQN_ERR_INVALID, "pqn_nc_velocity: NULL argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!ctx->has_axes) {
+      std::fill(UO, UO + 6 * ctx->M, 0.0);
+      if (stats) *stats = pqn_mvp_stats{};
+      return PQN_OK;
+    }
+    pqn_status s = mobility_common(ctx, nullptr, ctx->dax.p, ctx->UO.p, fidelity, stats);
+    HIPCHK(hipMemcpyAsync(UO, ctx->UO.p, 6 * (size_t)ctx->M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return s;
+  });
+}
+
+pqn_status pqn_bie_apply(pqn_ctx* ctx, int32_t fidelity, const double* q, double* y) {
+  return guarded([&]() -> pqn_status {
+    if (!ctx || !q || !y) return fail(PQN_ERR_INVALID, "pqn_bie_apply: NULL argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    Level& lv = ctx->level(fidelity);
+    const size_t len = 3 * (size_t)lv.N;
+    HIPCHK(hipMemcpyAsync(lv.rhs.p, q, len * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    ctx->apply_operator(lv, ctx->cfg.precision, lv.rhs.p, lv.tmp.p);
+    HIPCHK(hipMemcpyAsync(y, lv.tmp.p, len * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->end_far_timing();
+    return PQN_OK;
+  });
+}
+
+pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, double* q, pqn_mvp_stats* stats) {
+  return guarded([&]() -> pqn_status {
+    if (!ctx || !rhs || !q) return fail(PQN_ERR_INVALID, "pqn_bie_solve: NULL argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    Timer tm;
+    Level& lv = ctx->level(fidelity);
+    const size_t len = 3 * (size_t)lv.N;
+    ctx->n_matvec = 0;
+    ctx->n_far = 0;
+    HIPCHK(hipMemcpyAsync(lv.rhs.p, rhs, len * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    pqn_mvp_stats st{};
+    ctx->solve(lv, lv.rhs.p, lv.x.p, &st);
+    HIPCHK(hipMemcpyAsync(q, lv.x.p, len * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    st.t_far_ms = ctx->end_far_timing();
+    st.matvecs = ctx->n_matvec;
+    st.n_far = ctx->n_far;
+    st.t_total_ms = tm.ms();
+    if (stats) *stats = st;
+    return st.converged ? PQN_OK : PQN_WARN_NOT_CONVERGED;
+  });
+}
+
+pqn_status pqn_get_self_block(pqn_ctx* ctx, int32_t fidelity, double* S) {
+  return guarded([&]() -> pqn_status {
+    if (!ctx || !S) return fail(PQN_ERR_INVALID, "pqn_get_self_block: NULL argument");
+    Level& lv = ctx->level(fidelity);
+    std::memcpy(S, lv.tab.S.data(), lv.tab.S.size() * sizeof(double));
+    return PQN_OK;
+  });
+}
+
+pqn_status pqn_get_grid(pqn_ctx* ctx, int32_t fidelity, int32_t* n_nodes, double* offsets, double* weights) {
+  return guarded([&]() -> pqn_status {
+    if (!ctx) return fail(PQN_ERR_INVALID, "pqn_get_grid: NULL context");
+    Level& lv = ctx->level(fidelity);
+    if (n_nodes) *n_nodes = lv.n;
+    if (offsets) std::memcpy(offsets, lv.tab.off.data(), lv.tab.off.size() * sizeof(double));
+    if (weights) std::memcpy(weights, lv.tab.w.data(), lv.tab.w.size() * sizeof(double));
+    return PQN_OK;
+  });
+}
+
+pqn_status pqn_host_self_block(int32_t n_theta, int32_t n_phi, double radius, double* offsets, double* weights,
+                               double* S) {
+  return guarded([&]() -> pqn_status {
+    if (!(radius > 0.0)) return fail(PQN_ERR_INVALID, "radius must be > 0");
+    SphereTables t;
+    build_sphere_tables(n_theta, n_phi, radius, 1, t);
+    if (offsets) std::memcpy(offsets, t.off.data(), t.off.size() * sizeof(double));
+    if (weights) std::memcpy(weights, t.w.data(), t.w.size() * sizeof(double));
+    if (S) std::memcpy(S, t.S.data(), t.S.size() * sizeof(double));
+    return PQN_OK;
+  });
+}
+
+pqn_status pqn_find_contacts(pqn_ctx* ctx, double delta, int32_t cap, int32_t* n_out, int32_t* pairs, double* gaps) {
+  return guarded([&]() -> pqn_status {
+    if (!ctx || !n_out || (cap > 0 && (!pairs || !gaps)) || cap < 0)
+      return fail(PQN_ERR_INVALID, "pqn_find_contacts: bad argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    int n = lcp_find_contacts(*ctx, delta);
+    *n_out = n;
+    if (n > cap) return fail(PQN_ERR_INVALID, "pqn_find_contacts: cap too small");
+    lcp_copy_contacts(*ctx, n, pairs, gaps);
+    return PQN_OK;
+  });
+}
+
+pqn_status pqn_lcp_apply(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const double* x, double* Ax,
+                         int32_t fidelity) {
+  return guarded([&]() -> pqn_status {
+    if (!ctx || n < 0 || (n > 0 && (!pairs || !x || !Ax))) return fail(PQN_ERR_INVALID, "pqn_lcp_apply: bad argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    lcp_check_pairs(*ctx, n, pairs);
+    return lcp_apply_host(*ctx, n, pairs, x, Ax, fidelity);
+  });
+}
+
+pqn_status pqn_lcp_solve(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const double* b, double* x, int32_t solver,
+                         const pqn_lcp_opts* opts, pqn_lcp_stats* stats) {
+  return guarded([&]() -> pqn_status {
+    if (!ctx || n < 0 || (n > 0 && (!pairs || !b || !x))) return fail(PQN_ERR_INVALID, "pqn_lcp_solve: bad argument");
+    if (solver != PQN_BBPGD && solver != PQN_MONO && solver != PQN_BI) return fail(PQN_ERR_INVALID, "bad solver");
+    if (solver == PQN_BI && !ctx->has_lo) return fail(PQN_ERR_STATE, "Bi-PQN needs a low-fidelity grid");
+    HIPCHK(hipSetDevice(ctx->device));
+    lcp_check_pairs(*ctx, n, pairs);
+    return lcp_solve_host(*ctx, n, pairs, b, x, solver, opts, stats);
+  });
+}
+
+pqn_status pqn_step(pqn_ctx* ctx, double dt, double delta, int32_t solver, const pqn_lcp_opts* opts,
+                    pqn_step_stats* stats) {
+  return guarded([&]() -> pqn_status {
+    if (!ctx || !(dt > 0.0) || !std::isfinite(delta)) return fail(PQN_ERR_INVALID, "pqn_step: bad argument");
+    if (solver != PQN_BBPGD && solver != PQN_MONO && solver != PQN_BI) return fail(PQN_ERR_INVALID, "bad solver");
+    if (solver == PQN_BI && !ctx->has_lo) return fail(PQN_ERR_STATE, "Bi-PQN needs a low-fidelity grid");
+    HIPCHK(hipSetDevice(ctx->device));
+    return lcp_step(*ctx, dt, delta, solver, opts, stats);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Shared definitions of the bipqn HIP library (host and device).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+namespace bipqn {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kMaxNear = 16;          // near partners per sphere (gap < near_gap)
+constexpr int kMaxDegree = 40;        // largest spherical-harmonic degree p supported
+
+// Index of the real harmonic (l, m, kind) in the degree-ordered basis:
+// l outer; within l: m = 0, then (cos m phi, sin m phi) for m = 1..l.
+__host__ __device__ inline int sh_index(int l, int m, int sinpart) {
+  return l * l + (m == 0 ? 0 : 2 * m - 1 + sinpart);
+}
+
+// Orthonormal real spherical harmonics of degree <= p at the unit direction
+// with cos/sin of the polar angle (ct, st) and of the azimuth (cp, sp).
+// Fully normalised associated Legendre functions by the standard three-term
+// recurrence in l at fixed m; azimuthal factors by the angle-addition
+// recurrence. The callback receives (index, value) for every basis function,
+// so device code can contract on the fly without storing (p+1)^2 values.
+template <class F>
+__host__ __device__ inline void real_sh_visit(int p, double ct, double st, double cp, double sp, F&& f) {
+  const double inv4pi = 1.0 / (4.0 * kPi);
+  double pmm = sqrt(inv4pi);             // P_0^0 normalised
+  double cm = 1.0, sm = 0.0;             // cos(m phi), sin(m phi)
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) {
+      pmm *= -sqrt((2.0 * m + 1.0) / (2.0 * m)) * st;
+      double c2 = cm * cp - sm * sp;
+      double s2 = sm * cp + cm * sp;
+      cm = c2;
+      sm = s2;
+    }
+    const double fac = (m == 0) ? 1.0 : sqrt(2.0);
+    // l = m
+    double plm2 = 0.0, plm1 = pmm;
+    if (m == 0) {
+      f(sh_index(m, 0, 0), plm1);
+    } else {
+      f(sh_index(m, m, 0), fac * plm1 * cm);
+      f(sh_index(m, m, 1), fac * plm1 * sm);
+    }
+    for (int l = m + 1; l <= p; ++l) {
+      double a = sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)m * m));
+      double b = (l - 1 > m) ? sqrt(((double)(l - 1) * (l - 1) - (double)m * m) / (4.0 * (l - 1) * (l - 1) - 1.0)) : 0.0;
+      double pl = a * (ct * plm1 - b * plm2);
+      plm2 = plm1;
+      plm1 = pl;
+      if (m == 0) {
+        f(sh_index(l, 0, 0), pl);
+      } else {
+        f(sh_index(l, m, 0), fac * pl * cm);
+        f(sh_index(l, m, 1), fac * pl * sm);
+      }
+    }
+  }
+}
+
+// Host-side tables of one sphere grid (one fidelity level).
+struct SphereTables {
+  int n_theta = 0, n_phi = 0, n = 0, p = 0, L = 0;
+  double radius = 1.0;
+  std::vector<double> off;      // [n][3] node offsets from the centre
+  std::vector<double> w;        // [n] quadrature weights (sum 4 pi a^2)
+  std::vector<double> S;        // [3n][3n] self block, SoA rows (c*n+i), cols (d*n+k)
+  std::vector<double> T;        // [L][n] analysis: coefficients = T q
+  int up = 2, nt_up = 0, np_up = 0, n_up = 0;
+  std::vector<double> off_up;   // [n_up][3] upsampled grid offsets
+  std::vector<double> w_up;     // [n_up]
+  std::vector<double> Y_up;     // [n_up][L] synthesis on the upsampled grid
+};
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, SphereTables& t);
+
+}  // namespace bipqn

@@ -1,0 +1,1179 @@
+// LCP layer on the device: contacts, A = D^T M D products, and the PQN solvers.
+//
+// The quasi-Newton iterations run in single-workgroup kernels (n contacts and
+// r memory pairs are small: ~10^2 and <= 32); the host only sequences them
+// around the mobility solves and reads a few flags per iteration.
+#include "lcp.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+namespace bipqn {
+
+constexpr int kT = 256;  // threads of the single-workgroup kernels (4 waves)
+
+struct PqnScal {
+  int r, conv, stationary, reset, ssn_steps, ssn_fail, have_prev, nonzero;
+  double e, e_prev, eta, tol_abs, tol_rel, tau;
+};
+
+// One PQN engine's device workspace (vectors of length n, memory [kRmax][n]).
+struct PqnDev {
+  int n;
+  double *b, *x, *Ax, *g, *p, *Ap, *xt, *xh, *w, *t1, *t2;
+  double *U, *V, *S, *Y, *rho, *CiV;
+  PqnScal* sc;
+};
+
+// Bi-PQN outer state: high-fidelity corrections (Uc, Vc) of B^(k) = A^ + Uc Uc^T - Vc Vc^T,
+// the transferred low-fidelity secant pairs and A^ x.
+struct BiDev {
+  int n;
+  double *Uc, *Vc, *Slow, *Ylow, *Alox, *Alos, *Bs, *tmp;
+  int* cnt;  // [0] = rc (corrections), [1] = number of low pairs
+};
+
+// --------------------------------------------------------- block helpers
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__device__ inline double block_min(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  return fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+}
+
+__device__ inline double bdot(const double* a, const double* b, int n, double* red) {
+  double s = 0.0;
+  for (int e = threadIdx.x; e < n; e += kT) s = fma(a[e], b[e], s);
+  return block_sum(s, red);
+}
+
+// Solve A X = B in place (A m x m, B m x nr, row-major, shared memory) by
+// Gaussian elimination with partial pivoting; returns false if singular.
+__device__ bool block_solve(double* A, int lda, double* B, int ldb, int m, int nr, double* fac, int* flag) {
+  for (int k = 0; k < m; ++k) {
+    if (threadIdx.x == 0) {
+      int piv = k;
+      double best = fabs(A[k * lda + k]);
+      for (int i = k + 1; i < m; ++i)
+        if (fabs(A[i * lda + k]) > best) {
+          best = fabs(A[i * lda + k]);
+          piv = i;
+        }
+      *flag = best > 0.0 ? 1 : 0;
+      if (piv != k) {
+        for (int j = 0; j < m; ++j) {
+          double t = A[k * lda + j];
+          A[k * lda + j] = A[piv * lda + j];
+          A[piv * lda + j] = t;
+        }
+        for (int j = 0; j < nr; ++j) {
+          double t = B[k * ldb + j];
+          B[k * ldb + j] = B[piv * ldb + j];
+          B[piv * ldb + j] = t;
+        }
+      }
+    }
+    __syncthreads();
+    if (!*flag) return false;
+    const double pv = A[k * lda + k];
+    for (int i = k + 1 + threadIdx.x; i < m; i += kT) fac[i] = A[i * lda + k] / pv;
+    __syncthreads();
+    const int wA = m - k, wtot = wA + nr;
+    for (int idx = threadIdx.x; idx < (m - k - 1) * wtot; idx += kT) {
+      const int i = k + 1 + idx / wtot, c = idx % wtot;
+      if (c < wA)
+        A[i * lda + k + c] -= fac[i] * A[k * lda + k + c];
+      else
+        B[i * ldb + (c - wA)] -= fac[i] * B[k * ldb + (c - wA)];
+    }
+    __syncthreads();
+  }
+  for (int c = threadIdx.x; c < nr; c += kT)
+    for (int k = m - 1; k >= 0; --k) {
+      double v = B[k * ldb + c];
+      for (int j = k + 1; j < m; ++j) v -= A[k * lda + j] * B[j * ldb + c];
+      B[k * ldb + c] = v / A[k * lda + k];
+    }
+  __syncthreads();
+  return true;
+}
+
+// BFGS append of the pair (s, y) to B = I + U U^T - V V^T (or to a given B s):
+// u = y/sqrt(y.s), v = B s/sqrt(s.B s); skipped when y.s <= 1e-12 |s||y| or s.B s <= 0.
+// bs_given != nullptr supplies B s (Bi-PQN corrections); otherwise B s = s + U(U^T s) - V(V^T s).
+// When the memory is full it restarts from the identity.
+__device__ void bfgs_append(int n, double* U, double* V, double* S, double* Y, double* rho, int* r_io,
+                            const double* s, const double* y, const double* bs_given, double* bs_buf, double* red,
+                            double* coefs) {
+  int r = *r_io;
+  const double ys = bdot(y, s, n, red), ss = bdot(s, s, n, red), yy = bdot(y, y, n, red);
+  if (!(ys > 1e-12 * sqrt(ss) * sqrt(yy))) return;
+  if (r >= kRmax) r = 0;
+  const double* bs = bs_given;
+  if (!bs) {
+    for (int a = 0; a < 2 * r; ++a) {
+      const double* vec = a < r ? U + (size_t)a * n : V + (size_t)(a - r) * n;
+      double d = bdot(vec, s, n, red);
+      if (threadIdx.x == 0) coefs[a] = d;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += kT) {
+      double v = s[e];
+      for (int a = 0; a < r; ++a) v = fma(U[(size_t)a * n + e], coefs[a], v);
+      for (int a = 0; a < r; ++a) v = fma(-V[(size_t)a * n + e], coefs[r + a], v);
+      bs_buf[e] = v;
+    }
+    __syncthreads();
+    bs = bs_buf;
+  }
+  const double sbs = bdot(s, bs, n, red);
+  if (!(sbs > 0.0)) {
+    *r_io = r;
+    return;
+  }
+  const double iu = 1.0 / sqrt(ys), iv = 1.0 / sqrt(sbs);
+  for (int e = threadIdx.x; e < n; e += kT) {
+    U[(size_t)r * n + e] = y[e] * iu;
+    V[(size_t)r * n + e] = bs[e] * iv;
+    if (S) S[(size_t)r * n + e] = s[e];
+    if (Y) Y[(size_t)r * n + e] = y[e];
+  }
+  if (threadIdx.x == 0 && rho) rho[r] = 1.0 / ys;
+  __syncthreads();
+  *r_io = r + 1;
+}
+
+// ------------------------------------------------------------ contacts
+
+// Pairs i < j with |c_i - c_j| - 2a <= delta, lexicographic. One workgroup:
+// rows are taken 256 at a time, counted, scanned, then written.
+__global__ __launch_bounds__(kT) void k_contacts(const double* __restrict__ ctr, int M, double a, double delta,
+                                                 int cap, int* __restrict__ pairs, double* __restrict__ gaps,
+                                                 int* __restrict__ count) {
+  __shared__ int cnt[kT];
+  int base = 0;
+  for (int r0 = 0; r0 < M; r0 += kT) {
+    const int i = r0 + threadIdx.x;
+    int c = 0;
+    if (i < M)
+      for (int j = i + 1; j < M; ++j) {
+        const double dx = ctr[3 * i] - ctr[3 * j], dy = ctr[3 * i + 1] - ctr[3 * j + 1],
+                     dz = ctr[3 * i + 2] - ctr[3 * j + 2];
+        if (sqrt(dx * dx + dy * dy + dz * dz) - 2.0 * a <= delta) ++c;
+      }
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int run = 0;
+      for (int t = 0; t < kT; ++t) {
+        const int v = cnt[t];
+        cnt[t] = run;
+        run += v;
+      }
+    }
+    __syncthreads();
+    int o = base + cnt[threadIdx.x];
+    if (i < M)
+      for (int j = i + 1; j < M; ++j) {
+        const double dx = ctr[3 * i] - ctr[3 * j], dy = ctr[3 * i + 1] - ctr[3 * j + 1],
+                     dz = ctr[3 * i + 2] - ctr[3 * j + 2];
+        const double gp = sqrt(dx * dx + dy * dy + dz * dz) - 2.0 * a;
+        if (gp <= delta) {
+          if (o < cap) {
+            pairs[2 * o] = i;
+            pairs[2 * o + 1] = j;
+            gaps[o] = gp;
+          }
+          ++o;
+        }
+      }
+    __syncthreads();
+    if (threadIdx.x == kT - 1) cnt[0] = o;  // last thread holds the running end
+    __syncthreads();
+    base = cnt[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = base;
+}
+
+// FT = D x: force -x_l n_l on i, +x_l n_l on j (n_l = unit c_j - c_i), no torque.
+__global__ __launch_bounds__(kT) void k_D_scatter(const double* __restrict__ ctr, const int* __restrict__ pairs,
+                                                  const double* __restrict__ x, int n, int M,
+                                                  double* __restrict__ FT) {
+  const int i = blockIdx.x * kT + threadIdx.x;
+  if (i >= M) return;
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int l = 0; l < n; ++l) {
+    const int pi = pairs[2 * l], pj = pairs[2 * l + 1];
+    if (pi != i && pj != i) continue;
+    const double dx = ctr[3 * pj] - ctr[3 * pi], dy = ctr[3 * pj + 1] - ctr[3 * pi + 1],
+                 dz = ctr[3 * pj + 2] - ctr[3 * pi + 2];
+    const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    const double sg = (pj == i) ? x[l] : -x[l];
+    f[0] += sg * dx * inv;
+    f[1] += sg * dy * inv;
+    f[2] += sg * dz * inv;
+  }
+  FT[6 * i] = f[0];
+  FT[6 * i + 1] = f[1];
+  FT[6 * i + 2] = f[2];
+  FT[6 * i + 3] = FT[6 * i + 4] = FT[6 * i + 5] = 0.0;
+}
+
+// out_l = n_l . (U_j - U_i)
+__global__ __launch_bounds__(kT) void k_DT_gather(const double* __restrict__ ctr, const int* __restrict__ pairs,
+                                                  const double* __restrict__ UO, int n, double* __restrict__ out) {
+  const int l = blockIdx.x * kT + threadIdx.x;
+  if (l >= n) return;
+  const int pi = pairs[2 * l], pj = pairs[2 * l + 1];
+  const double dx = ctr[3 * pj] - ctr[3 * pi], dy = ctr[3 * pj + 1] - ctr[3 * pi + 1],
+               dz = ctr[3 * pj + 2] - ctr[3 * pi + 2];
+  const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+  out[l] = inv * (dx * (UO[6 * pj] - UO[6 * pi]) + dy * (UO[6 * pj + 1] - UO[6 * pi + 1]) +
+                  dz * (UO[6 * pj + 2] - UO[6 * pi + 2]));
+}
+
+// ------------------------------------------------------------ PQN engine
+
+// Reset an engine: memory cleared; x, Ax either zero or kept (warm start).
+__global__ __launch_bounds__(kT) void k_pqn_init(PqnDev d, int keep_x, double tol_abs, double tol_rel) {
+  for (int e = threadIdx.x; e < d.n; e += kT)
+    if (!keep_x) d.x[e] = d.Ax[e] = 0.0;
+  if (threadIdx.x == 0) {
+    PqnScal z{};
+    z.tol_abs = tol_abs;
+    z.tol_rel = tol_rel;
+    *d.sc = z;
+  }
+}
+
+// Replay secant pairs (columns of Sw, Yw) into the engine's memory (warm start).
+__global__ __launch_bounds__(kT) void k_pqn_replay(PqnDev d, const double* __restrict__ Sw,
+                                                   const double* __restrict__ Yw, int npairs) {
+  __shared__ double red[4];
+  __shared__ double coefs[2 * kRmax];
+  __shared__ int r;
+  if (threadIdx.x == 0) r = d.sc->r;
+  __syncthreads();
+  const int first = npairs > kRmax ? npairs - kRmax : 0;
+  for (int k = first; k < npairs; ++k) {
+    int rr = r;
+    bfgs_append(d.n, d.U, d.V, d.S, d.Y, d.rho, &rr, Sw + (size_t)k * d.n, Yw + (size_t)k * d.n, nullptr, d.t1,
+                red, coefs);
+    __syncthreads();
+    if (threadIdx.x == 0) r = rr;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) d.sc->r = r;
+}
+
+// KKT check, x~ = x - H g (two-loop recursion, H0 = I), prox by semi-smooth
+// Newton (Prop. 1, Alg. 3), p = x^ - x.
+__global__ __launch_bounds__(kT) void k_pqn_prepare(PqnDev d, int jmax) {
+  __shared__ double red[4];
+  __shared__ double Jm[2 * kRmax * 2 * kRmax];
+  __shared__ double Lv[2 * kRmax];
+  __shared__ double Gm[kRmax * kRmax];
+  __shared__ double Xm[kRmax * kRmax];
+  __shared__ double z[2 * kRmax];
+  __shared__ double fac[2 * kRmax];
+  __shared__ double alpha[kRmax];
+  __shared__ int flag, stop, conv;
+  const int n = d.n;
+  const int r = d.sc->r;
+  // 1. gradient and KKT error (eq. (kkt-error))
+  double s = 0.0;
+  for (int e = threadIdx.x; e < n; e += kT) {
+    const double g = d.Ax[e] + d.b[e];
+    d.g[e] = g;
+    const double m = fmin(d.x[e], g);
+    s = fma(m, m, s);
+  }
+  const double err = sqrt(block_sum(s, red));
+  if (threadIdx.x == 0) {
+    PqnScal* sc = d.sc;
+    const double mx = fmax(err, sc->e_prev);
+    int c = err < sc->tol_abs;
+    if (!c && sc->have_prev && mx > 0.0 && fabs(err - sc->e_prev) / mx < sc->tol_rel) c = 1;
+    sc->e = err;
+    if (!c) {
+      sc->e_prev = err;
+      sc->have_prev = 1;
+    }
+    sc->conv = c;
+    sc->stationary = 0;
+    conv = c;
+  }
+  __syncthreads();
+  if (conv) return;
+  // 2. two-loop recursion: t1 = H g
+  for (int e = threadIdx.x; e < n; e += kT) d.t1[e] = d.g[e];
+  __syncthreads();
+  for (int i = r - 1; i >= 0; --i) {
+    const double al = d.rho[i] * bdot(d.S + (size_t)i * n, d.t1, n, red);
+    if (threadIdx.x == 0) alpha[i] = al;
+    for (int e = threadIdx.x; e < n; e += kT) d.t1[e] = fma(-al, d.Y[(size_t)i * n + e], d.t1[e]);
+    __syncthreads();
+  }
+  for (int i = 0; i < r; ++i) {
+    const double be = d.rho[i] * bdot(d.Y + (size_t)i * n, d.t1, n, red);
+    __syncthreads();
+    const double cf = alpha[i] - be;
+    for (int e = threadIdx.x; e < n; e += kT) d.t1[e] = fma(cf, d.S[(size_t)i * n + e], d.t1[e]);
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n; e += kT) d.xt[e] = d.x[e] - d.t1[e];
+  __syncthreads();
+  // 3. weighted prox (D = I): x^ = (x~ + C^{-1} V a~ - U a)_+, C = I + U U^T
+  if (r == 0) {
+    for (int e = threadIdx.x; e < n; e += kT) d.xh[e] = fmax(d.xt[e], 0.0);
+  } else {
+    // Gm = I + U^T U, Xm = U^T V; Xm <- Gm^{-1} Xm; CiV = V - U Xm (Woodbury)
+    for (int ent = threadIdx.x; ent < 2 * r * r; ent += kT) {
+      const int which = ent / (r * r), ab = ent % (r * r), a = ab / r, b = ab % r;
+      const double* u = d.U + (size_t)a * n;
+      const double* v = which == 0 ? d.U + (size_t)b * n : d.V + (size_t)b * n;
+      double t = 0.0;
+      for (int e = 0; e < n; ++e) t = fma(u[e], v[e], t);
+      if (which == 0)
+        Gm[a * r + b] = t + (a == b ? 1.0 : 0.0);
+      else
+        Xm[a * r + b] = t;
+    }
+    __syncthreads();
+    block_solve(Gm, r, Xm, r, r, r, fac, &flag);
+    for (int e = threadIdx.x; e < n; e += kT)
+      for (int c = 0; c < r; ++c) {
+        double v = d.V[(size_t)c * n + e];
+        for (int a = 0; a < r; ++a) v = fma(-d.U[(size_t)a * n + e], Xm[a * r + c], v);
+        d.CiV[(size_t)c * n + e] = v;
+      }
+    for (int k = threadIdx.x; k < 2 * r; k += kT) z[k] = 0.0;
+    __syncthreads();
+    const int m2 = 2 * r;
+    int steps = 0;
+    for (int j = 0; j < jmax; ++j) {
+      ++steps;
+      // w = x~ + CiV a~ - U a; t2 = x~ + CiV a~; x^ = w_+; Lambda = [w > 0]
+      for (int e = threadIdx.x; e < n; e += kT) {
+        double t2 = d.xt[e];
+        for (int c = 0; c < r; ++c) t2 = fma(d.CiV[(size_t)c * n + e], z[r + c], t2);
+        double w = t2;
+        for (int a = 0; a < r; ++a) w = fma(-d.U[(size_t)a * n + e], z[a], w);
+        d.t2[e] = t2;
+        d.w[e] = w;
+        d.xh[e] = fmax(w, 0.0);
+      }
+      __syncthreads();
+      // L~ = [a + U^T (t2 - x^); a~ + V^T (x~ - x^)] and its Jacobian (printed J_L)
+      for (int ent = threadIdx.x; ent < m2 * m2 + m2; ent += kT) {
+        if (ent < m2) {
+          const bool top = ent < r;
+          const double* u = top ? d.U + (size_t)ent * n : d.V + (size_t)(ent - r) * n;
+          double t = 0.0;
+          for (int e = 0; e < n; ++e) t = fma(u[e], (top ? d.t2[e] : d.xt[e]) - d.xh[e], t);
+          Lv[ent] = z[ent] + t;
+        } else {
+          const int q = ent - m2, row = q / m2, col = q % m2;
+          const bool rtop = row < r, ctop = col < r;
+          const double* u = rtop ? d.U + (size_t)row * n : d.V + (size_t)(row - r) * n;
+          const double* v = ctop ? d.U + (size_t)col * n : d.CiV + (size_t)(col - r) * n;
+          double t = 0.0;
+          if (rtop && !ctop) {
+            for (int e = 0; e < n; ++e) t = fma(u[e] * (d.w[e] > 0.0 ? 0.0 : 1.0), v[e], t);
+          } else {
+            for (int e = 0; e < n; ++e) t = fma(u[e] * (d.w[e] > 0.0 ? 1.0 : 0.0), v[e], t);
+          }
+          if (!rtop && !ctop) t = -t;
+          Jm[row * m2 + col] = t + (row == col ? 1.0 : 0.0);
+        }
+      }
+      __syncthreads();
+      const bool ok = block_solve(Jm, m2, Lv, 1, m2, 1, fac, &flag);
+      if (threadIdx.x == 0) {
+        double dn = 0.0, zn = 0.0;
+        if (ok)
+          for (int k = 0; k < m2; ++k) {
+            z[k] -= Lv[k];
+            dn += Lv[k] * Lv[k];
+            zn += z[k] * z[k];
+          }
+        stop = !ok || sqrt(dn) <= 1e-14 * fmax(1.0, sqrt(zn));
+        if (!ok) d.sc->ssn_fail += 1;
+      }
+      __syncthreads();
+      if (stop) break;
+    }
+    for (int e = threadIdx.x; e < n; e += kT) {
+      double w = d.xt[e];
+      for (int c = 0; c < r; ++c) w = fma(d.CiV[(size_t)c * n + e], z[r + c], w);
+      for (int a = 0; a < r; ++a) w = fma(-d.U[(size_t)a * n + e], z[a], w);
+      d.xh[e] = fmax(w, 0.0);
+    }
+    if (threadIdx.x == 0) d.sc->ssn_steps += steps;
+  }
+  __syncthreads();
+  // 4. search direction
+  double nz = 0.0;
+  for (int e = threadIdx.x; e < n; e += kT) {
+    const double pe = d.xh[e] - d.x[e];
+    d.p[e] = pe;
+    nz += pe != 0.0 ? 1.0 : 0.0;
+  }
+  nz = block_sum(nz, red);
+  if (threadIdx.x == 0) d.sc->stationary = nz == 0.0;
+}
+
+// Optimal over-relaxation (Alg. 2) and the updates x += eta p, A x += eta A p,
+// then the BFGS update with s = eta p, y = eta A p.
+__device__ double step_size_block(const double* g, const double* x, const double* p, const double* Ap, int n,
+                                  double* red, int* reset) {
+  const double pAp = bdot(p, Ap, n, red);
+  const double gp = bdot(p, g, n, red);
+  double lim = INFINITY;
+  for (int e = threadIdx.x; e < n; e += kT)
+    if (p[e] < 0.0) lim = fmin(lim, -x[e] / p[e]);
+  lim = block_min(lim, red);
+  if (!(pAp > 0.0)) {
+    *reset = 1;
+    return 1.0;
+  }
+  const double eta1 = -gp / pAp;
+  if (!(eta1 > 0.0)) {
+    *reset = 1;
+    return 1.0;
+  }
+  *reset = 0;
+  return fmin(eta1, lim);
+}
+
+__global__ __launch_bounds__(kT) void k_pqn_accept(PqnDev d) {
+  __shared__ double red[4];
+  __shared__ double coefs[2 * kRmax];
+  const int n = d.n;
+  int reset = 0;
+  const double eta = step_size_block(d.g, d.x, d.p, d.Ap, n, red, &reset);
+  for (int e = threadIdx.x; e < n; e += kT) {
+    d.x[e] = fmax(fma(eta, d.p[e], d.x[e]), 0.0);
+    d.Ax[e] = fma(eta, d.Ap[e], d.Ax[e]);
+    d.xt[e] = eta * d.p[e];   // s
+    d.xh[e] = eta * d.Ap[e];  // y
+  }
+  __syncthreads();
+  int r = reset ? 0 : d.sc->r;
+  bfgs_append(n, d.U, d.V, d.S, d.Y, d.rho, &r, d.xt, d.xh, nullptr, d.t1, red, coefs);
+  if (threadIdx.x == 0) {
+    d.sc->r = r;
+    d.sc->eta = eta;
+    d.sc->reset = reset;
+  }
+}
+
+// BB-PGD (eq. (spectralStepSize), eta = 1): KKT check, tau_bb, x+ = (x - tau g)_+.
+// t1/t2 keep the previous x and A x; the product of the new x is the next A x.
+__global__ __launch_bounds__(kT) void k_bb_prepare(PqnDev d, double tau0) {
+  __shared__ double red[4];
+  __shared__ int conv;
+  const int n = d.n;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < n; e += kT) {
+    const double g = d.Ax[e] + d.b[e];
+    d.g[e] = g;
+    const double m = fmin(d.x[e], g);
+    s = fma(m, m, s);
+  }
+  const double err = sqrt(block_sum(s, red));
+  if (threadIdx.x == 0) {
+    PqnScal* sc = d.sc;
+    const double mx = fmax(err, sc->e_prev);
+    int c = err < sc->tol_abs;
+    if (!c && sc->have_prev && mx > 0.0 && fabs(err - sc->e_prev) / mx < sc->tol_rel) c = 1;
+    sc->e = err;
+    sc->conv = c;
+    conv = c;
+  }
+  __syncthreads();
+  if (conv) return;
+  double tau = d.sc->have_prev ? d.sc->tau : tau0;
+  if (d.sc->have_prev) {
+    double dxdx = 0.0, dxdg = 0.0;
+    for (int e = threadIdx.x; e < n; e += kT) {
+      const double dx = d.x[e] - d.t1[e], dg = d.Ax[e] - d.t2[e];
+      dxdx = fma(dx, dx, dxdx);
+      dxdg = fma(dx, dg, dxdg);
+    }
+    dxdx = block_sum(dxdx, red);
+    dxdg = block_sum(dxdg, red);
+    if (dxdg > 0.0) tau = dxdx / dxdg;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n; e += kT) {
+    d.t1[e] = d.x[e];
+    d.t2[e] = d.Ax[e];
+    d.x[e] = fmax(d.x[e] - tau * d.g[e], 0.0);
+  }
+  if (threadIdx.x == 0) {
+    d.sc->tau = tau;
+    d.sc->e_prev = err;
+    d.sc->have_prev = 1;
+  }
+}
+
+// Low-rank correction: out = base + Uc (Uc^T v) - Vc (Vc^T v).
+__global__ __launch_bounds__(kT) void k_lowrank(BiDev B, const double* __restrict__ base,
+                                                const double* __restrict__ v, double* __restrict__ out) {
+  __shared__ double red[4];
+  __shared__ double cf[2 * kRmax];
+  const int n = B.n, rc = B.cnt[0];
+  for (int a = 0; a < 2 * rc; ++a) {
+    const double* u = a < rc ? B.Uc + (size_t)a * n : B.Vc + (size_t)(a - rc) * n;
+    const double t = bdot(u, v, n, red);
+    if (threadIdx.x == 0) cf[a] = t;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n; e += kT) {
+    double o = base ? base[e] : 0.0;
+    for (int a = 0; a < rc; ++a) o = fma(B.Uc[(size_t)a * n + e], cf[a], o);
+    for (int a = 0; a < rc; ++a) o = fma(-B.Vc[(size_t)a * n + e], cf[rc + a], o);
+    out[e] = o;
+  }
+}
+
+// Bi-PQN outer step, first half: gradient, KKT check, subproblem data
+// c = A x + b - B x with B x = A^ x + corrections (eq. (pqnSubproblem)).
+// Writes the inner engine's b (= c), x and A x (= B x).
+__global__ __launch_bounds__(kT) void k_bi_prepare(PqnDev o, BiDev B, PqnDev in) {
+  __shared__ double red[4];
+  __shared__ double cf[2 * kRmax];
+  __shared__ int conv;
+  const int n = o.n, rc = B.cnt[0];
+  double s = 0.0;
+  for (int e = threadIdx.x; e < n; e += kT) {
+    const double g = o.Ax[e] + o.b[e];
+    o.g[e] = g;
+    const double m = fmin(o.x[e], g);
+    s = fma(m, m, s);
+  }
+  const double err = sqrt(block_sum(s, red));
+  if (threadIdx.x == 0) {
+    PqnScal* sc = o.sc;
+    const double mx = fmax(err, sc->e_prev);
+    int c = err < sc->tol_abs;
+    if (!c && sc->have_prev && mx > 0.0 && fabs(err - sc->e_prev) / mx < sc->tol_rel) c = 1;
+    sc->e = err;
+    if (!c) {
+      sc->e_prev = err;
+      sc->have_prev = 1;
+    }
+    sc->conv = c;
+    conv = c;
+  }
+  __syncthreads();
+  if (conv) return;
+  for (int a = 0; a < 2 * rc; ++a) {
+    const double* u = a < rc ? B.Uc + (size_t)a * n : B.Vc + (size_t)(a - rc) * n;
+    const double t = bdot(u, o.x, n, red);
+    if (threadIdx.x == 0) cf[a] = t;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n; e += kT) {
+    double bx = B.Alox[e];
+    for (int a = 0; a < rc; ++a) bx = fma(B.Uc[(size_t)a * n + e], cf[a], bx);
+    for (int a = 0; a < rc; ++a) bx = fma(-B.Vc[(size_t)a * n + e], cf[rc + a], bx);
+    in.b[e] = o.g[e] - bx;
+    in.x[e] = o.x[e];
+    in.Ax[e] = bx;
+  }
+}
+
+// p = x^ - x (inner result minus outer iterate); flags a zero step.
+__global__ __launch_bounds__(kT) void k_bi_direction(PqnDev o, PqnDev in) {
+  __shared__ double red[4];
+  double nz = 0.0;
+  for (int e = threadIdx.x; e < o.n; e += kT) {
+    const double pe = in.x[e] - o.x[e];
+    o.p[e] = pe;
+    nz += pe != 0.0 ? 1.0 : 0.0;
+  }
+  nz = block_sum(nz, red);
+  if (threadIdx.x == 0) o.sc->stationary = nz == 0.0;
+}
+
+// Bi-PQN outer step, second half (after the high-fidelity product A p):
+// eta* (Alg. 2), A^ s = eta (A^ x^ - A^ x) (App. E.2), BFGS correction of
+// B^(k) with B^(k) s = A^ s + corrections, secant transfer of the subproblem
+// pairs Y <- Y^ + u (u.S^) - v (v.S^), and x, A x, A^ x updates.
+__global__ __launch_bounds__(kT) void k_bi_accept(PqnDev o, BiDev B, PqnDev in) {
+  __shared__ double red[4];
+  __shared__ double cf[4 * kRmax];
+  const int n = o.n;
+  int reset = 0;
+  const double eta = step_size_block(o.g, o.x, o.p, o.Ap, n, red, &reset);
+  int rc = B.cnt[0];
+  // A^ x^ = B x^ - corrections(x^), with B x^ the inner engine's final A x
+  for (int a = 0; a < 2 * rc; ++a) {
+    const double* u = a < rc ? B.Uc + (size_t)a * n : B.Vc + (size_t)(a - rc) * n;
+    const double t1 = bdot(u, in.x, n, red);
+    const double t2 = bdot(u, o.p, n, red);
+    if (threadIdx.x == 0) {
+      cf[a] = t1;
+      cf[2 * kRmax + a] = eta * t2;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n; e += kT) {
+    double alxh = in.Ax[e];
+    double cs = 0.0;
+    for (int a = 0; a < rc; ++a) {
+      alxh = fma(-B.Uc[(size_t)a * n + e], cf[a], alxh);
+      cs = fma(B.Uc[(size_t)a * n + e], cf[2 * kRmax + a], cs);
+    }
+    for (int a = 0; a < rc; ++a) {
+      alxh = fma(B.Vc[(size_t)a * n + e], cf[rc + a], alxh);
+      cs = fma(-B.Vc[(size_t)a * n + e], cf[2 * kRmax + rc + a], cs);
+    }
+    const double alos = eta * (alxh - B.Alox[e]);
+    B.Alos[e] = alos;
+    B.Bs[e] = reset ? alos : alos + cs;
+    o.xt[e] = eta * o.p[e];   // s
+    o.xh[e] = eta * o.Ap[e];  // y
+  }
+  __syncthreads();
+  // subproblem pairs S^, Y^ (dropped after a memory reset)
+  const int nlow = reset ? 0 : min(in.sc->r, kRmax);
+  if (reset) rc = 0;
+  int rnew = rc;
+  bfgs_append(n, B.Uc, B.Vc, nullptr, nullptr, nullptr, &rnew, o.xt, o.xh, B.Bs, nullptr, red, cf);
+  const bool added = rnew == rc + 1 || (rc >= kRmax && rnew == 1);
+  const double* u = added ? B.Uc + (size_t)(rnew - 1) * n : nullptr;
+  const double* v = added ? B.Vc + (size_t)(rnew - 1) * n : nullptr;
+  for (int k = 0; k < nlow; ++k) {
+    const double* sh = in.S + (size_t)k * n;
+    const double* yh = in.Y + (size_t)k * n;
+    double us = 0.0, vs = 0.0;
+    if (added) {
+      us = bdot(u, sh, n, red);
+      vs = bdot(v, sh, n, red);
+    }
+    for (int e = threadIdx.x; e < n; e += kT) {
+      B.Slow[(size_t)k * n + e] = sh[e];
+      B.Ylow[(size_t)k * n + e] = added ? yh[e] + u[e] * us - v[e] * vs : yh[e];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n; e += kT) {
+    o.x[e] = fmax(fma(eta, o.p[e], o.x[e]), 0.0);
+    o.Ax[e] = fma(eta, o.Ap[e], o.Ax[e]);
+    B.Alox[e] += B.Alos[e];
+  }
+  if (threadIdx.x == 0) {
+    B.cnt[0] = rnew;
+    B.cnt[1] = nlow;
+    o.sc->eta = eta;
+    o.sc->reset = reset;
+  }
+}
+
+// y += eta * x with eta read from the device (recurrence of M D x for the step).
+__global__ void k_axpy_dev(double* __restrict__ y, const double* __restrict__ x, const PqnScal* __restrict__ sc,
+                           int len) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < len) y[e] = fma(sc->eta, x[e], y[e]);
+}
+
+// Nonzero test of a vector (Bi-PQN: whether x^(0) needs a high-fidelity product).
+__global__ __launch_bounds__(kT) void k_nonzero(const double* __restrict__ x, int n, PqnScal* sc) {
+  __shared__ double red[4];
+  double c = 0.0;
+  for (int e = threadIdx.x; e < n; e += kT) c += x[e] != 0.0 ? 1.0 : 0.0;
+  c = block_sum(c, red);
+  if (threadIdx.x == 0) sc->nonzero = c > 0.0;
+}
+
+// KKT error of x = 0: |min(0, b)|_2 (into sc->e).
+__global__ __launch_bounds__(kT) void k_kkt_zero(const double* __restrict__ b, int n, PqnScal* sc) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int e = threadIdx.x; e < n; e += kT) {
+    const double m = fmin(0.0, b[e]);
+    s = fma(m, m, s);
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) sc->e = sqrt(s);
+}
+
+// Forward Euler of centres and Rodrigues rotation of the Janus axes.
+__global__ void k_euler(double* __restrict__ ctr, double* __restrict__ axes, const double* __restrict__ Unc,
+                        const double* __restrict__ MDx, int M, double dt, int has_axes) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  double U[6];
+  for (int c = 0; c < 6; ++c) U[c] = Unc[6 * i + c] + (MDx ? MDx[6 * i + c] : 0.0);
+  for (int c = 0; c < 3; ++c) ctr[3 * i + c] += dt * U[c];
+  if (!has_axes) return;
+  const double wn = sqrt(U[3] * U[3] + U[4] * U[4] + U[5] * U[5]);
+  const double th = wn * dt;
+  if (th == 0.0) return;
+  const double k[3] = {U[3] / wn, U[4] / wn, U[5] / wn};
+  const double e[3] = {axes[3 * i], axes[3 * i + 1], axes[3 * i + 2]};
+  const double ke = k[0] * e[0] + k[1] * e[1] + k[2] * e[2];
+  const double kxe[3] = {k[1] * e[2] - k[2] * e[1], k[2] * e[0] - k[0] * e[2], k[0] * e[1] - k[1] * e[0]};
+  const double c = cos(th), s = sin(th);
+  for (int q = 0; q < 3; ++q) axes[3 * i + q] = e[q] * c + kxe[q] * s + k[q] * ke * (1.0 - c);
+}
+
+// ------------------------------------------------------- host-side driver
+
+struct Engine {
+  DevArray<double> vec, mem;
+  DevArray<PqnScal> sc;
+  PqnDev d{};
+  void alloc(int n) {
+    vec.alloc((size_t)11 * n);
+    mem.alloc((size_t)5 * kRmax * n + kRmax);
+    sc.alloc(1);
+    double* v = vec.p;
+    d.n = n;
+    d.b = v;
+    d.x = v + n;
+    d.Ax = v + 2 * n;
+    d.g = v + 3 * n;
+    d.p = v + 4 * n;
+    d.Ap = v + 5 * n;
+    d.xt = v + 6 * n;
+    d.xh = v + 7 * n;
+    d.w = v + 8 * n;
+    d.t1 = v + 9 * n;
+    d.t2 = v + 10 * n;
+    double* m = mem.p;
+    d.U = m;
+    d.V = m + (size_t)kRmax * n;
+    d.S = m + (size_t)2 * kRmax * n;
+    d.Y = m + (size_t)3 * kRmax * n;
+    d.CiV = m + (size_t)4 * kRmax * n;
+    d.rho = m + (size_t)5 * kRmax * n;
+    d.sc = sc.p;
+  }
+};
+
+struct LcpState {
+  int cap = 0;
+  DevArray<int> pairs, cpairs, ccount;
+  DevArray<double> cgaps;
+  Engine outer, inner;
+  DevArray<double> bivec;
+  DevArray<int> bicnt;
+  BiDev bi{};
+  DevArray<double> MDx, MDp, Unc;
+  void ensure(int n, int M) {
+    if (n <= cap && MDx.p) return;
+    cap = std::max(n, 1);
+    pairs.alloc(2 * (size_t)cap);
+    outer.alloc(cap);
+    inner.alloc(cap);
+    bivec.alloc((size_t)(4 * kRmax + 4) * cap);
+    bicnt.alloc(2);
+    double* v = bivec.p;
+    bi.Uc = v;
+    bi.Vc = v + (size_t)kRmax * cap;
+    bi.Slow = v + (size_t)2 * kRmax * cap;
+    bi.Ylow = v + (size_t)3 * kRmax * cap;
+    bi.Alox = v + (size_t)4 * kRmax * cap;
+    bi.Alos = bi.Alox + cap;
+    bi.Bs = bi.Alos + cap;
+    bi.tmp = bi.Bs + cap;
+    bi.cnt = bicnt.p;
+    MDx.alloc(6 * (size_t)M);
+    MDp.alloc(6 * (size_t)M);
+    Unc.alloc(6 * (size_t)M);
+  }
+  void set_n(int n) {
+    outer.d.n = n;
+    inner.d.n = n;
+    bi.n = n;
+  }
+};
+
+void lcp_release(LcpState* st) { delete st; }
+
+static LcpState& state(pqn_ctx_impl& ctx) {
+  if (!ctx.lcp) ctx.lcp = new LcpState();
+  return *ctx.lcp;
+}
+
+void lcp_check_pairs(pqn_ctx_impl& ctx, int n, const int32_t* pairs) {
+  for (int l = 0; l < n; ++l) {
+    const int i = pairs[2 * l], j = pairs[2 * l + 1];
+    if (i < 0 || j < 0 || i >= ctx.M || j >= ctx.M || i == j)
+      throw Error(PQN_ERR_INVALID, "contact pair with an invalid sphere index");
+  }
+}
+
+int lcp_find_contacts(pqn_ctx_impl& ctx, double delta) {
+  LcpState& st = state(ctx);
+  const int cap = ctx.M * 12 + 16;  // more contacts than 6 per sphere cannot occur without overlap
+  st.cpairs.alloc(2 * (size_t)cap);
+  st.cgaps.alloc(cap);
+  st.ccount.alloc(1);
+  hipLaunchKernelGGL(k_contacts, dim3(1), dim3(kT), 0, ctx.stream, ctx.ctr.p, ctx.M, ctx.a, delta, cap,
+                     st.cpairs.p, st.cgaps.p, st.ccount.p);
+  int n = 0;
+  HIPCHK(hipMemcpyAsync(&n, st.ccount.p, sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+  HIPCHK(hipStreamSynchronize(ctx.stream));
+  if (n > cap) throw Error(PQN_ERR_INVALID, "more contacts than 12 per sphere: overlapping spheres?");
+  return n;
+}
+
+void lcp_copy_contacts(pqn_ctx_impl& ctx, int n, int32_t* pairs, double* gaps) {
+  LcpState& st = state(ctx);
+  if (n == 0) return;
+  HIPCHK(hipMemcpyAsync(pairs, st.cpairs.p, 2 * (size_t)n * sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+  HIPCHK(hipMemcpyAsync(gaps, st.cgaps.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  HIPCHK(hipStreamSynchronize(ctx.stream));
+}
+
+// One LCP product out = D^T M D v on the device; M D v also left in UO_out.
+static void lcp_mvp(pqn_ctx_impl& ctx, Level& lv, int n, const int* pairs_dev, const double* v, double* out,
+                    double* UO_out, int* gmres_its) {
+  hipLaunchKernelGGL(k_D_scatter, dim3((ctx.M + kT - 1) / kT), dim3(kT), 0, ctx.stream, ctx.ctr.p, pairs_dev, v, n,
+                     ctx.M, ctx.FT.p);
+  pqn_mvp_stats ms{};
+  ctx.mobility(lv, ctx.FT.p, nullptr, UO_out, &ms);
+  hipLaunchKernelGGL(k_DT_gather, dim3((n + kT - 1) / kT), dim3(kT), 0, ctx.stream, ctx.ctr.p, pairs_dev, UO_out, n,
+                     out);
+  HIPCHK(hipGetLastError());
+  if (gmres_its) *gmres_its += ms.gmres_iters;
+}
+
+pqn_status lcp_apply_host(pqn_ctx_impl& ctx, int n, const int32_t* pairs, const double* x, double* Ax,
+                          int fidelity) {
+  if (n == 0) return PQN_OK;
+  LcpState& st = state(ctx);
+  st.ensure(n, ctx.M);
+  st.set_n(n);
+  Level& lv = ctx.level(fidelity);
+  HIPCHK(hipMemcpyAsync(st.pairs.p, pairs, 2 * (size_t)n * sizeof(int), hipMemcpyHostToDevice, ctx.stream));
+  double* xd = st.outer.d.t1;
+  double* yd = st.outer.d.t2;
+  HIPCHK(hipMemcpyAsync(xd, x, (size_t)n * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
+  lcp_mvp(ctx, lv, n, st.pairs.p, xd, yd, ctx.UO.p, nullptr);
+  HIPCHK(hipMemcpyAsync(Ax, yd, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  HIPCHK(hipStreamSynchronize(ctx.stream));
+  ctx.end_far_timing();
+  return PQN_OK;
+}
+
+struct SolveCounters {
+  int mvp_hi = 0, mvp_lo = 0, gmres = 0;
+  double t_hi = 0.0, t_lo = 0.0;
+};
+
+static PqnScal read_scal(pqn_ctx_impl& ctx, const PqnScal* d) {
+  PqnScal h{};
+  HIPCHK(hipMemcpyAsync(&h, d, sizeof(PqnScal), hipMemcpyDeviceToHost, ctx.stream));
+  HIPCHK(hipStreamSynchronize(ctx.stream));
+  return h;
+}
+
+// Mono-PQN (Alg. 1) on an engine; mvp(v, out, md) computes out = A v (md: M D v or null).
+// Returns whether it converged; the engine holds x, A x and the memory.
+template <class Mvp>
+static bool run_mono(pqn_ctx_impl& ctx, Engine& E, int k_max, int j_max, Mvp&& mvp, double* MDx, int M,
+                     int* iters) {
+  bool conv = false;
+  int k = 0;
+  for (k = 0; k < k_max; ++k) {
+    hipLaunchKernelGGL(k_pqn_prepare, dim3(1), dim3(kT), 0, ctx.stream, E.d, j_max);
+    HIPCHK(hipGetLastError());
+    PqnScal s = read_scal(ctx, E.d.sc);
+    if (!std::isfinite(s.e)) throw Error(PQN_ERR_NUMERIC, "non-finite KKT error in PQN");
+    if (s.conv || s.stationary) {
+      conv = true;
+      break;
+    }
+    mvp(E.d.p, E.d.Ap, MDx ? ctx.lcp->MDp.p : nullptr);
+    hipLaunchKernelGGL(k_pqn_accept, dim3(1), dim3(kT), 0, ctx.stream, E.d);
+    if (MDx)
+      hipLaunchKernelGGL(k_axpy_dev, dim3((6 * M + 255) / 256), dim3(256), 0, ctx.stream, MDx, ctx.lcp->MDp.p,
+                         E.d.sc, 6 * M);
+    HIPCHK(hipGetLastError());
+  }
+  if (!conv) {
+    // final KKT evaluation (no product needed: A x is carried by the recurrence)
+    hipLaunchKernelGGL(k_pqn_prepare, dim3(1), dim3(kT), 0, ctx.stream, E.d, j_max);
+    PqnScal s = read_scal(ctx, E.d.sc);
+    conv = s.conv;
+  }
+  if (iters) *iters += k;
+  return conv;
+}
+
+static pqn_lcp_opts opts_or_default(const pqn_lcp_opts* o) {
+  pqn_lcp_opts r{100, 50, 50, 1e-8, 1e-8};
+  if (o) {
+    if (o->k_max > 0) r.k_max = o->k_max;
+    if (o->k_max_inner > 0) r.k_max_inner = o->k_max_inner;
+    if (o->j_max > 0) r.j_max = o->j_max;
+    if (o->kkt_tol_abs > 0) r.kkt_tol_abs = o->kkt_tol_abs;
+    if (o->kkt_tol_rel > 0) r.kkt_tol_rel = o->kkt_tol_rel;
+  }
+  return r;
+}
+
+// Solve the LCP with b (device, length n) on the stored pairs. x ends in
+// st.outer.d.x; MDx (if non-null) receives M D x.
+static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opts& o, double* MDx,
+                         pqn_lcp_stats* stats) {
+  LcpState& st = *ctx.lcp;
+  SolveCounters cnt;
+  Level& hi = ctx.hi;
+  const int M = ctx.M;
+  auto timed = [&](bool lo, auto&& f) {
+    Timer t;
+    f();
+    HIPCHK(hipStreamSynchronize(ctx.stream));
+    (lo ? cnt.t_lo : cnt.t_hi) += t.ms();
+    (lo ? cnt.mvp_lo : cnt.mvp_hi) += 1;
+  };
+  auto mvp_hi = [&](const double* v, double* out, double* md) {
+    timed(false, [&] { lcp_mvp(ctx, hi, n, st.pairs.p, v, out, md ? md : ctx.UO.p, &cnt.gmres); });
+  };
+  if (MDx) HIPCHK(hipMemsetAsync(MDx, 0, 6 * (size_t)M * sizeof(double), ctx.stream));
+  bool conv = false;
+  int iters = 0;
+  int ssn = 0;
+  double kkt = 0.0;
+  hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, st.outer.d, 0, o.kkt_tol_abs, o.kkt_tol_rel);
+  if (solver == PQN_MONO) {
+    conv = run_mono(ctx, st.outer, o.k_max, o.j_max, mvp_hi, MDx, M, &iters);
+    PqnScal s = read_scal(ctx, st.outer.d.sc);
+    ssn = s.ssn_steps;
+    kkt = s.e;
+  } else if (solver == PQN_BBPGD) {
+    const double tau0 = 3.0 * kPi * ctx.mu * ctx.a;  // inverse of twice the single-sphere mobility
+    int k = 0;
+    for (k = 0; k < o.k_max; ++k) {
+      hipLaunchKernelGGL(k_bb_prepare, dim3(1), dim3(kT), 0, ctx.stream, st.outer.d, tau0);
+      PqnScal s = read_scal(ctx, st.outer.d.sc);
+      if (!std::isfinite(s.e)) throw Error(PQN_ERR_NUMERIC, "non-finite KKT error in BB-PGD");
+      kkt = s.e;
+      if (s.conv) {
+        conv = true;
+        break;
+      }
+      mvp_hi(st.outer.d.x, st.outer.d.Ax, MDx);
+    }
+    if (!conv) {
+      hipLaunchKernelGGL(k_bb_prepare, dim3(1), dim3(kT), 0, ctx.stream, st.outer.d, tau0);
+      PqnScal s = read_scal(ctx, st.outer.d.sc);
+      conv = s.conv;
+      kkt = s.e;
+    }
+    iters = k;
+  } else {
+    Level& lo = ctx.lo;
+    Engine& I = st.inner;
+    Engine& O = st.outer;
+    BiDev& B = st.bi;
+    auto mvp_lo_plain = [&](const double* v, double* out, double*) {
+      timed(true, [&] { lcp_mvp(ctx, lo, n, st.pairs.p, v, out, ctx.UO.p, &cnt.gmres); });
+    };
+    // low-fidelity initial solve from x^(-1) = 0 with tolerance 1e-2 * KKT(0), KKT(0) = |min(0, b)|
+    HIPCHK(hipMemcpyAsync(I.d.b, O.d.b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+    hipLaunchKernelGGL(k_kkt_zero, dim3(1), dim3(kT), 0, ctx.stream, O.d.b, n, O.d.sc);
+    const double e0 = read_scal(ctx, O.d.sc).e;
+    PqnScal si{};
+    si.tol_abs = std::max(1e-12, 1e-2 * e0);
+    si.tol_rel = o.kkt_tol_rel;
+    HIPCHK(hipMemcpyAsync(I.d.sc, &si, sizeof(PqnScal), hipMemcpyHostToDevice, ctx.stream));
+    hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, I.d, 0, si.tol_abs, si.tol_rel);
+    int in_iters = 0;
+    run_mono(ctx, I, o.k_max_inner, o.j_max, mvp_lo_plain, nullptr, M, &in_iters);
+    PqnScal sI = read_scal(ctx, I.d.sc);
+    ssn += sI.ssn_steps;
+    // outer state: x = x0, A^ x = inner A x, pairs = inner memory, no corrections
+    PqnScal so{};
+    so.tol_abs = o.kkt_tol_abs;
+    so.tol_rel = o.kkt_tol_rel;
+    HIPCHK(hipMemcpyAsync(O.d.sc, &so, sizeof(PqnScal), hipMemcpyHostToDevice, ctx.stream));
+    HIPCHK(hipMemcpyAsync(O.d.x, I.d.x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+    HIPCHK(hipMemcpyAsync(B.Alox, I.d.Ax, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+    int nlow = std::min(sI.r, kRmax);
+    if (nlow > 0) {
+      HIPCHK(hipMemcpyAsync(B.Slow, I.d.S, (size_t)nlow * n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+      HIPCHK(hipMemcpyAsync(B.Ylow, I.d.Y, (size_t)nlow * n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+    }
+    int hcnt[2] = {0, nlow};
+    HIPCHK(hipMemcpyAsync(B.cnt, hcnt, 2 * sizeof(int), hipMemcpyHostToDevice, ctx.stream));
+    hipLaunchKernelGGL(k_nonzero, dim3(1), dim3(kT), 0, ctx.stream, O.d.x, n, O.d.sc);
+    PqnScal snz = read_scal(ctx, O.d.sc);
+    if (snz.nonzero) {
+      mvp_hi(O.d.x, O.d.Ax, MDx);
+    } else {
+      HIPCHK(hipMemsetAsync(O.d.Ax, 0, (size_t)n * sizeof(double), ctx.stream));
+    }
+    auto mvp_B = [&](const double* v, double* out, double*) {
+      timed(true, [&] { lcp_mvp(ctx, lo, n, st.pairs.p, v, B.tmp, ctx.UO.p, &cnt.gmres); });
+      hipLaunchKernelGGL(k_lowrank, dim3(1), dim3(kT), 0, ctx.stream, B, B.tmp, v, out);
+    };
+    int k = 0;
+    for (k = 0; k < o.k_max; ++k) {
+      hipLaunchKernelGGL(k_bi_prepare, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
+      PqnScal so2 = read_scal(ctx, O.d.sc);
+      if (!std::isfinite(so2.e)) throw Error(PQN_ERR_NUMERIC, "non-finite KKT error in Bi-PQN");
+      kkt = so2.e;
+      if (so2.conv) {
+        conv = true;
+        break;
+      }
+      // subproblem: Mono-PQN on B^(k) from x, warm-started with the stored pairs
+      int hc[2];
+      HIPCHK(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+      HIPCHK(hipStreamSynchronize(ctx.stream));
+      PqnScal sin{};
+      sin.tol_abs = std::max(1e-12, 1e-2 * so2.e);
+      sin.tol_rel = o.kkt_tol_rel;
+      sin.ssn_steps = 0;
+      HIPCHK(hipMemcpyAsync(I.d.sc, &sin, sizeof(PqnScal), hipMemcpyHostToDevice, ctx.stream));
+      hipLaunchKernelGGL(k_pqn_replay, dim3(1), dim3(kT), 0, ctx.stream, I.d, B.Slow, B.Ylow, hc[1]);
+      run_mono(ctx, I, o.k_max_inner, o.j_max, mvp_B, nullptr, M, &in_iters);
+      PqnScal sI2 = read_scal(ctx, I.d.sc);
+      ssn += sI2.ssn_steps;
+      hipLaunchKernelGGL(k_bi_direction, dim3(1), dim3(kT), 0, ctx.stream, O.d, I.d);
+      PqnScal sd = read_scal(ctx, O.d.sc);
+      if (sd.stationary) {
+        conv = true;
+        break;
+      }
+      mvp_hi(O.d.p, O.d.Ap, MDx ? st.MDp.p : nullptr);
+      hipLaunchKernelGGL(k_bi_accept, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
+      if (MDx)
+        hipLaunchKernelGGL(k_axpy_dev, dim3((6 * M + 255) / 256), dim3(256), 0, ctx.stream, MDx, st.MDp.p, O.d.sc,
+                           6 * M);
+      HIPCHK(hipGetLastError());
+    }
+    if (!conv) {
+      hipLaunchKernelGGL(k_bi_prepare, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
+      PqnScal sf = read_scal(ctx, O.d.sc);
+      conv = sf.conv;
+      kkt = sf.e;
+    }
+    iters = k;
+  }
+  HIPCHK(hipStreamSynchronize(ctx.stream));
+  if (stats) {
+    stats->iters = iters;
+    stats->mvp_hi = cnt.mvp_hi;
+    stats->mvp_lo = cnt.mvp_lo;
+    const double ratio = (cnt.mvp_lo > 0 && cnt.mvp_hi > 0) ? (cnt.t_lo / cnt.mvp_lo) / (cnt.t_hi / cnt.mvp_hi) : 0.0;
+    stats->lo_hi_cost_ratio = ratio;
+    stats->emvp = cnt.mvp_hi + cnt.mvp_lo * ratio;
+    stats->kkt_abs = kkt;
+    stats->converged = conv ? 1 : 0;
+    stats->ssn_steps = ssn;
+    stats->gmres_iters = cnt.gmres;
+  }
+  return conv;
+}
+
+pqn_status lcp_solve_host(pqn_ctx_impl& ctx, int n, const int32_t* pairs, const double* b, double* x, int solver,
+                          const pqn_lcp_opts* opts, pqn_lcp_stats* stats) {
+  Timer tm;
+  pqn_lcp_stats st_local{};
+  if (n == 0) {
+    if (stats) *stats = st_local;
+    return PQN_OK;
+  }
+  for (int l = 0; l < n; ++l)
+    if (!std::isfinite(b[l])) throw Error(PQN_ERR_NUMERIC, "non-finite b");
+  LcpState& st = state(ctx);
+  st.ensure(n, ctx.M);
+  st.set_n(n);
+  const pqn_lcp_opts o = opts_or_default(opts);
+  HIPCHK(hipMemcpyAsync(st.pairs.p, pairs, 2 * (size_t)n * sizeof(int), hipMemcpyHostToDevice, ctx.stream));
+  HIPCHK(hipMemcpyAsync(st.outer.d.b, b, (size_t)n * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
+  const bool conv = solve_device(ctx, n, solver, o, nullptr, &st_local);
+  HIPCHK(hipMemcpyAsync(x, st.outer.d.x, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  HIPCHK(hipStreamSynchronize(ctx.stream));
+  ctx.end_far_timing();
+  st_local.t_total_ms = tm.ms();
+  if (stats) *stats = st_local;
+  return conv ? PQN_OK : PQN_WARN_NOT_CONVERGED;
+}
+
+// b = Phi/dt + D^T U_nc (eq. (defAandb))
+__global__ void k_make_b(const double* __restrict__ gaps, const double* __restrict__ dtu, double dt, int n,
+                         double* __restrict__ b) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < n) b[l] = gaps[l] / dt + dtu[l];
+}
+
+pqn_status lcp_step(pqn_ctx_impl& ctx, double dt, double delta, int solver, const pqn_lcp_opts* opts,
+                    pqn_step_stats* stats) {
+  Timer tm;
+  pqn_step_stats ss{};
+  LcpState& st = state(ctx);
+  const int M = ctx.M;
+  const int n = lcp_find_contacts(ctx, delta);
+  st.ensure(n, M);
+  st.set_n(std::max(n, 1));
+  // U_nc from the slip-driven solve (F = T = 0)
+  pqn_mvp_stats ms{};
+  if (ctx.has_axes) {
+    ctx.mobility(ctx.hi, nullptr, ctx.dax.p, st.Unc.p, &ms);
+  } else {
+    HIPCHK(hipMemsetAsync(st.Unc.p, 0, 6 * (size_t)M * sizeof(double), ctx.stream));
+  }
+  ss.gmres_iters_nc = ms.gmres_iters;
+  ss.n_contacts = n;
+  bool conv = true;
+  double* MDx = nullptr;
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(st.pairs.p, st.cpairs.p, 2 * (size_t)n * sizeof(int), hipMemcpyDeviceToDevice,
+                          ctx.stream));
+    hipLaunchKernelGGL(k_DT_gather, dim3((n + kT - 1) / kT), dim3(kT), 0, ctx.stream, ctx.ctr.p, st.pairs.p,
+                       st.Unc.p, n, st.outer.d.t1);
+    hipLaunchKernelGGL(k_make_b, dim3((n + 255) / 256), dim3(256), 0, ctx.stream, st.cgaps.p, st.outer.d.t1, dt, n,
+                       st.outer.d.b);
+    const pqn_lcp_opts o = opts_or_default(opts);
+    conv = solve_device(ctx, n, solver, o, st.MDx.p, &ss.lcp);
+    MDx = st.MDx.p;
+    std::vector<double> hx(n);
+    HIPCHK(hipMemcpyAsync(hx.data(), st.outer.d.x, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+    HIPCHK(hipStreamSynchronize(ctx.stream));
+    for (double v : hx) ss.n_active += v > 0.0;
+  }
+  hipLaunchKernelGGL(k_euler, dim3((M + 255) / 256), dim3(256), 0, ctx.stream, ctx.ctr.p, ctx.dax.p, st.Unc.p, MDx,
+                     M, dt, ctx.has_axes ? 1 : 0);
+  HIPCHK(hipGetLastError());
+  std::vector<double> c(3 * (size_t)M), ax(3 * (size_t)M);
+  HIPCHK(hipMemcpyAsync(c.data(), ctx.ctr.p, c.size() * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  HIPCHK(hipMemcpyAsync(ax.data(), ctx.dax.p, ax.size() * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  HIPCHK(hipStreamSynchronize(ctx.stream));
+  ctx.end_far_timing();
+  ctx.set_configuration(c.data(), ctx.has_axes ? ax.data() : nullptr);
+  ss.t_total_ms = tm.ms();
+  if (stats) *stats = ss;
+  return conv ? PQN_OK : PQN_WARN_NOT_CONVERGED;
+}
+
+}  // namespace bipqn

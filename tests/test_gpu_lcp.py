@@ -1,0 +1,113 @@
+"""GPU parity of the LCP layer (products, BB-PGD, Mono-PQN, Bi-PQN, step) vs oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import bie, dynamics, lcp
+from paper_2604_10089_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cases():
+    out = []
+    for seed in (0, 2):
+        c = inputs.workload('tiny', seed)['centers']
+        g = bie.Geometry(c, 1.0, 8, 16)
+        A = bie.dense_operator(g)
+        glo = bie.Geometry(c, 1.0, 4, 8)
+        Alo = bie.dense_operator(glo)
+        pairs, gaps = dynamics.find_contacts(c, 1.0, 0.1)
+        Aop = lcp.lcp_operator(lambda F, g=g, A=A: bie.mobility_apply(g, F, dense=A), c, pairs)
+        n = pairs.shape[0]
+        Ad = np.column_stack([Aop(np.eye(n)[k]) for k in range(n)])
+        axes = -c / np.linalg.norm(c, axis=1)[:, None]
+        b_real = lcp.lcp_b(gaps, 0.1, c, pairs, bie.nc_velocity(g, axes, 1.0, dense=A))
+        xs, ws = inputs.planted_lcp(seed, n)
+        out.append(dict(c=c, g=g, A=A, glo=glo, Alo=Alo, pairs=pairs, gaps=gaps, Ad=Ad, axes=axes,
+                        b_real=b_real, x_pl=xs, b_pl=ws - Ad @ xs))
+    return out
+
+
+def test_lcp_apply_matches_oracle(cases):
+    for cs in cases:
+        x = np.random.default_rng(1).uniform(0, 1, cs['pairs'].shape[0])
+        with binding.Context(cs['c'], None, 8, 16, lo=(4, 8), gmres_tol=1e-13) as ctx:
+            Ax = ctx.lcp_apply(cs['pairs'], x)
+            Alox = ctx.lcp_apply(cs['pairs'], x, fidelity=binding.PQN_LOFI)
+        assert np.abs(Ax - cs['Ad'] @ x).max() < 1e-10 * np.abs(cs['Ad'] @ x).max()
+        Alo_ref = lcp.lcp_operator(lambda F: bie.mobility_apply(cs['glo'], F, dense=cs['Alo']), cs['c'],
+                                   cs['pairs'])(x)
+        assert np.abs(Alox - Alo_ref).max() < 1e-10 * np.abs(Alo_ref).max()
+
+
+@pytest.mark.parametrize("solver", ["mono", "bb", "bi"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lcp_solve_matches_brute_force(cases, solver, prec):
+    # FP64: solve to 1e-12 and compare at 1e-10. Mixed: each fresh product carries the FP32
+    # far-field rounding (~1e-8 relative), so the KKT floor is ~1e-9; compare x at 1e-6.
+    tol = 1e-10 if prec == 'fp64' else 1e-6
+    kkt = (1e-12, 1e-15) if prec == 'fp64' else (1e-9, 1e-9)
+    for cs in cases:
+        for name, b in (('real', cs['b_real']), ('planted', cs['b_pl'])):
+            say('lcp_solve', solver, prec, name)
+            xbf = lcp.brute_force_lcp(cs['Ad'], b)
+            with binding.Context(cs['c'], None, 8, 16, lo=(4, 8), gmres_tol=1e-12, precision=prec) as ctx:
+                x, st = ctx.lcp_solve(cs['pairs'], b, solver, tol_abs=kkt[0], tol_rel=kkt[1], k_max=400)
+            assert st['converged'] == 1, st
+            assert np.abs(x - xbf).max() <= tol * max(np.abs(xbf).max(), 1e-300), (x, xbf, st)
+            assert x.min() >= 0.0
+            if solver == 'bi':
+                assert st['mvp_lo'] >= 1 or np.all(xbf == 0)
+
+
+def test_lcp_solver_counts_match_oracle(cases):
+    """Same algorithm on the same operator: iteration counts agree (MVP counts may differ by rounding)."""
+    cs = cases[0]
+    b = cs['b_pl']
+    Aop = lcp.lcp_operator(lambda F: bie.mobility_apply(cs['g'], F, dense=cs['A']), cs['c'], cs['pairs'])
+    Alo = lcp.lcp_operator(lambda F: bie.mobility_apply(cs['glo'], F, dense=cs['Alo']), cs['c'], cs['pairs'])
+    _, _, sm = lcp.mono_pqn(Aop, b)
+    _, _, sb = lcp.bi_pqn(Aop, Alo, b)
+    with binding.Context(cs['c'], None, 8, 16, lo=(4, 8), gmres_tol=1e-13) as ctx:
+        _, gm = ctx.lcp_solve(cs['pairs'], b, 'mono')
+        _, gb = ctx.lcp_solve(cs['pairs'], b, 'bi')
+    assert abs(gm['mvp_hi'] - sm['mvp']) <= 1
+    assert abs(gb['mvp_hi'] - sb['mvp_hi']) <= 1
+    say('mono', gm['mvp_hi'], sm['mvp'], 'bi', gb['mvp_hi'], gb['mvp_lo'], sb['mvp_hi'], sb['mvp_lo'])
+
+
+@pytest.mark.parametrize("solver", ["mono", "bi", "bb"])
+def test_step_matches_oracle(cases, solver):
+    cs = cases[0]
+    say('step', solver)
+    c1, ax1, info = dynamics.step(cs['c'], cs['axes'], 1.0, (8, 16), (4, 8), 0.1, 0.1, 1.0, solver=solver,
+                                  lcp_opts=dict(tol_abs=1e-12, tol_rel=1e-15), tol_gmres=1e-13)
+    with binding.Context(cs['c'], cs['axes'], 8, 16, lo=(4, 8), gmres_tol=1e-13) as ctx:
+        st = ctx.step(0.1, 0.1, solver, tol_abs=1e-12, tol_rel=1e-15)
+        c2, ax2 = ctx.get_state()
+    assert st['n_contacts'] == info['pairs'].shape[0]
+    assert st['n_active'] == int((info['x'] > 0).sum())
+    assert np.abs(c2 - c1).max() < 1e-10
+    assert np.abs(ax2 - ax1).max() < 1e-10
+
+
+def test_lcp_edge_cases(cases):
+    cs = cases[0]
+    with binding.Context(cs['c'], None, 8, 16, lo=(4, 8)) as ctx:
+        x, st = ctx.lcp_solve(np.zeros((0, 2), np.int32), np.zeros(0), 'bi')
+        assert x.shape == (0,)
+        # b >= 0: x = 0 with no product at all
+        x, st = ctx.lcp_solve(cs['pairs'], np.abs(cs['b_real']) + 0.1, 'mono')
+        assert np.all(x == 0.0) and st['mvp_hi'] == 0
+        with pytest.raises(binding.PqnError):
+            ctx.lcp_solve(np.array([[0, 99]], np.int32), np.array([-1.0]), 'mono')
+        with pytest.raises(binding.PqnError):
+            ctx.lcp_solve(cs['pairs'], np.full(cs['pairs'].shape[0], np.nan), 'mono')

@@ -1,0 +1,153 @@
+"""GPU parity of the mobility product: HIP library (through the C ABI) vs oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import bie, dynamics, grid
+from paper_2604_10089_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def soa(q):
+    return np.ascontiguousarray(q.T)
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = inputs.workload('tiny', 0)
+    c = w['centers']
+    g = bie.Geometry(c, 1.0, 8, 16)
+    return c, g, bie.dense_operator(g)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_bie_apply_tiny(tiny, prec, tol):
+    c, g, A = tiny
+    say('bie_apply tiny', prec)
+    q = np.random.default_rng(3).standard_normal((g.N, 3))
+    with binding.Context(c, None, 8, 16, precision=prec) as ctx:
+        y = ctx.bie_apply(soa(q))
+    ref = (A @ q.ravel()).reshape(-1, 3).T
+    assert rel(y, ref) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_mobility_tiny(tiny, prec, tol):
+    c, g, A = tiny
+    say('mobility tiny', prec)
+    FT = inputs.random_forces(7, g.M)
+    with binding.Context(c, None, 8, 16, gmres_tol=1e-13, precision=prec, refine=0) as ctx:
+        U, st = ctx.mobility_apply(FT)
+    Uo = bie.mobility_apply(g, FT, dense=A)
+    assert st['converged'] == 1
+    assert rel(U[:, :3], Uo[:, :3]) < tol
+    assert rel(U[:, 3:], Uo[:, 3:]) < tol
+
+
+def test_mixed_refinement_reaches_fp64_operator(tiny):
+    c, g, A = tiny
+    FT = inputs.random_forces(8, g.M)
+    with binding.Context(c, None, 8, 16, gmres_tol=1e-12, precision='mixed', refine=3) as ctx:
+        U, st = ctx.mobility_apply(FT)
+    Uo = bie.mobility_apply(g, FT, dense=A)
+    assert st['refine_sweeps'] >= 1
+    assert rel(U, Uo) < 1e-9
+
+
+@pytest.mark.parametrize("nt", [6, 12])
+def test_single_sphere_drag(nt):
+    say('drag', nt)
+    FT = np.array([[1.0, -2.0, 0.5, 0.3, 0.7, -0.2]])
+    with binding.Context([[0.5, 0.0, -1.0]], None, nt, 2 * nt, radius=1.5, mu=2.0, gmres_tol=1e-13) as ctx:
+        U, _ = ctx.mobility_apply(FT)
+    assert np.abs(U[0, :3] * 6 * np.pi * 2.0 * 1.5 - FT[0, :3]).max() < 1e-10
+    assert np.abs(U[0, 3:] * 8 * np.pi * 2.0 * 1.5 ** 3 - FT[0, 3:]).max() < 1e-10
+
+
+def test_nc_velocity_tiny(tiny):
+    c, g, A = tiny
+    axes = inputs.janus_axes(4, g.M)
+    with binding.Context(c, axes, 8, 16, gmres_tol=1e-13) as ctx:
+        U, _ = ctx.nc_velocity()
+    Uo = bie.nc_velocity(g, axes, 1.0, dense=A)
+    assert rel(U, Uo) < 1e-10
+
+
+def test_zero_forces_give_zero_velocity(tiny):
+    c, g, A = tiny
+    with binding.Context(c, None, 8, 16) as ctx:
+        U, st = ctx.mobility_apply(np.zeros((g.M, 6)))
+    assert np.all(U == 0.0) and st['gmres_iters'] == 0
+
+
+def test_contacts_match_oracle():
+    for seed in range(3):
+        c = inputs.workload('tiny', seed)['centers']
+        with binding.Context(c, None, 4, 8) as ctx:
+            pairs, gaps = ctx.find_contacts(0.1)
+            none, _ = ctx.find_contacts(-1.0)
+        po, go = dynamics.find_contacts(c, 1.0, 0.1)
+        assert np.array_equal(pairs, po) and np.abs(gaps - go).max() < 1e-14
+        assert none.shape[0] == 0
+
+
+def _sample_targets(g, k, seed):
+    rng = np.random.default_rng(seed)
+    t = set(rng.choice(g.N, size=k, replace=False).tolist())
+    t.update([0, g.n - 1, g.N - 1])        # first, last of the first sphere, last overall
+    return sorted(t)
+
+
+@pytest.mark.parametrize("name,prec,tol", [("lattice27", "fp64", 1e-12), ("lattice27", "mixed", 1e-6),
+                                           ("rsa216", "fp64", 1e-12), ("rsa216", "mixed", 1e-6)])
+def test_bie_apply_sampled_rows(name, prec, tol):
+    w = inputs.workload(name, 0)
+    c = w['centers']
+    g = bie.Geometry(c, 1.0, w['n_theta'], w['n_phi'])
+    say('bie_apply rows', name, prec, 'N', g.N)
+    q = np.random.default_rng(11).standard_normal((g.N, 3))
+    with binding.Context(c, None, w['n_theta'], w['n_phi'], precision=prec) as ctx:
+        y = ctx.bie_apply(soa(q))
+    tg = _sample_targets(g, 12, 5)
+    ref = bie.operator_rows(g, q, tg)
+    scale = np.abs(ref).max()
+    assert np.abs(y[:, tg].T - ref).max() < tol * scale
+
+
+def test_bie_solve_residual_rsa216():
+    """Full-size property: the GPU density solves the oracle's equation at sampled rows."""
+    w = inputs.workload('rsa216', 0)
+    c = w['centers']
+    g = bie.Geometry(c, 1.0, w['n_theta'], w['n_phi'])
+    rhs = -bie.completion(g, inputs.random_forces(2, g.M))
+    tg = _sample_targets(g, 8, 6)
+    for prec, tol in (("fp64", 1e-9), ("mixed", 2e-6)):
+        say('bie_solve rsa216', prec)
+        with binding.Context(c, None, w['n_theta'], w['n_phi'], gmres_tol=1e-10, precision=prec) as ctx:
+            q, st = ctx.bie_solve(soa(rhs))
+        res = bie.operator_rows(g, q.T, tg) - rhs[tg]
+        assert np.abs(res).max() < tol * np.abs(rhs).max(), (prec, st)
+
+
+def test_mixed_vs_fp64_mobility_rsa216():
+    w = inputs.workload('rsa216', 0)
+    c = w['centers']
+    FT = inputs.random_forces(3, c.shape[0])
+    out = {}
+    for prec in ('fp64', 'mixed'):
+        say('mobility rsa216', prec)
+        with binding.Context(c, None, w['n_theta'], w['n_phi'], gmres_tol=1e-10, precision=prec) as ctx:
+            out[prec], st = ctx.mobility_apply(FT)
+    for blk in (slice(0, 3), slice(3, 6)):
+        assert rel(out['mixed'][:, blk], out['fp64'][:, blk]) < 1e-6
