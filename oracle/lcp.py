@@ -10,6 +10,11 @@ recursions a fast implementation uses.
 
 Readings of the paper taken here (each also listed in the design notes):
   * Alg. 1 search step: x~ = x - H (A x + b), tau = 1 (Table 1; Lemma 1).
+  * Initial metric: Prop. 1 allows any positive diagonal D; Alg. 1 prints
+    H^(0) = I, which is not invariant to the units of A. Here the first step
+    uses H^(0) = I and, once its product A p is known, the quasi-Newton matrix
+    starts from B0 = sigma I with sigma = p.Ap/p.p (no extra product). sigma is
+    kept for the rest of one LCP solve (all Bi-PQN subproblems included).
   * Stopping rule: the KKT errors of eq. (kkt-error), 2-norm, absolute OR
     relative change below tolerance.
   * Prop. 1 root function: L~(a, a~) = [a; a~] + L(a, a~) with L as printed;
@@ -115,9 +120,10 @@ class QuasiNewton:
     Pinned by: B+ s = y and H B = I (tests/test_oracle_lcp.py).
     """
 
-    def __init__(self, n, b0_apply=None):
+    def __init__(self, n, b0_apply=None, sigma=1.0):
         self.n = n
         self.b0 = b0_apply
+        self.sigma = float(sigma)
         self.U, self.V, self.S, self.Y = [], [], [], []
 
     def lowrank(self, v):
@@ -129,7 +135,7 @@ class QuasiNewton:
         return out
 
     def dense(self):
-        B = np.eye(self.n)
+        B = self.sigma * np.eye(self.n)
         for u in self.U:
             B += np.outer(u, u)
         for v in self.V:
@@ -137,7 +143,7 @@ class QuasiNewton:
         return B
 
     def B_apply(self, s, b0s=None):
-        base = s.copy() if self.b0 is None else (self.b0(s) if b0s is None else b0s)
+        base = self.sigma * s if self.b0 is None else (self.b0(s) if b0s is None else b0s)
         return base + self.lowrank(s)
 
     def H_apply(self, g):
@@ -297,7 +303,7 @@ def bb_pgd(Aop, b, x0=None, tau0=1.0, k_max=200, tol_abs=1e-8, tol_rel=1e-8):
 
 
 def mono_pqn(Aop, b, x0=None, Ax0=None, k_max=100, tol_abs=1e-8, tol_rel=1e-8,
-             pairs=(), j_max=50):
+             pairs=(), j_max=50, sigma=None):
     """Mono-PQN (Alg. 1) with the SSN prox (Alg. 3) and eta* (Alg. 2).
 
     One product A[p] per iteration; A x is carried by the recurrence
@@ -315,7 +321,10 @@ def mono_pqn(Aop, b, x0=None, Ax0=None, k_max=100, tol_abs=1e-8, tol_rel=1e-8,
         mvp += 1
     else:
         Ax = np.zeros(n)
-    qn = QuasiNewton(n)
+    pairs = list(pairs)
+    if pairs and sigma is None:
+        raise ValueError('warm-start pairs need the metric scale sigma they were built with')
+    qn = QuasiNewton(n, sigma=1.0 if sigma is None else sigma)
     for s, y in pairs:
         qn.update(s, y)
     e_prev = None
@@ -333,7 +342,7 @@ def mono_pqn(Aop, b, x0=None, Ax0=None, k_max=100, tol_abs=1e-8, tol_rel=1e-8,
         xt = x - qn.H_apply(g)
         Um = np.array(qn.U).T if qn.U else None
         Vm = np.array(qn.V).T if qn.V else None
-        xh, nj, _ = prox_ssn(xt, Um, Vm, jmax=j_max)
+        xh, nj, _ = prox_ssn(xt, Um, Vm, d=np.full(n, qn.sigma), jmax=j_max)
         ssn_total += nj
         p = xh - x
         if not np.any(p != 0.0):
@@ -341,9 +350,13 @@ def mono_pqn(Aop, b, x0=None, Ax0=None, k_max=100, tol_abs=1e-8, tol_rel=1e-8,
             break
         Ap = Aop(p)
         mvp += 1
+        if sigma is None:
+            pAp = float(p @ Ap)
+            sigma = pAp / float(p @ p) if pAp > 0.0 else 1.0
+            qn.sigma = sigma
         eta, reset = step_size(g, x, p, Ap)
         if reset:
-            qn = QuasiNewton(n)
+            qn = QuasiNewton(n, sigma=sigma)
         x = np.maximum(x + eta * p, 0.0)
         Ax = Ax + eta * Ap
         qn.update(eta * p, eta * Ap)
@@ -352,7 +365,7 @@ def mono_pqn(Aop, b, x0=None, Ax0=None, k_max=100, tol_abs=1e-8, tol_rel=1e-8,
         hist.append(e)
         conv = _converged(e, e_prev, tol_abs, tol_rel)
     return x, Ax, Stats(iters=len(hist) - 1, mvp=mvp, kkt=hist[-1], converged=conv,
-                        hist=hist, S=list(qn.S), Y=list(qn.Y), ssn=ssn_total)
+                        hist=hist, S=list(qn.S), Y=list(qn.Y), ssn=ssn_total, sigma=sigma)
 
 
 def secant_transfer(S, Y, u, v):
@@ -383,6 +396,7 @@ def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_
                             tol_abs=tol0, tol_rel=tol_rel, j_max=j_max)
     mvp_lo = st0['mvp']
     S, Y = st0['S'], st0['Y']
+    sigma = st0['sigma']
     if np.any(x != 0.0):
         Ax = Ahi(x)
         mvp_hi = 1
@@ -406,8 +420,9 @@ def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_
         Bop = lambda v: Alo(v) + corr.lowrank(v)
         tol_in = max(1e-12, 1e-2 * e)
         xh, Bxh, st = mono_pqn(Bop, c, x, Bx, k_max=k_max_inner, tol_abs=tol_in,
-                               tol_rel=tol_rel, pairs=list(zip(S, Y)), j_max=j_max)
+                               tol_rel=tol_rel, pairs=list(zip(S, Y)), j_max=j_max, sigma=sigma)
         mvp_lo += st['mvp']
+        sigma = st['sigma']
         p = xh - x
         if not np.any(p != 0.0):
             conv = True

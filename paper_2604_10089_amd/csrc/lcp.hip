@@ -12,9 +12,11 @@ namespace bipqn {
 
 constexpr int kT = 256;  // threads of the single-workgroup kernels (4 waves)
 
+// sigma: scale of the initial metric B0 = sigma I (0 = not yet set; the first
+// step then uses H0 = I and sets sigma = p.Ap/p.p from its own product).
 struct PqnScal {
   int r, conv, stationary, reset, ssn_steps, ssn_fail, have_prev, nonzero;
-  double e, e_prev, eta, tol_abs, tol_rel, tau;
+  double e, e_prev, eta, tol_abs, tol_rel, tau, sigma;
 };
 
 // One PQN engine's device workspace (vectors of length n, memory [kRmax][n]).
@@ -117,13 +119,13 @@ __device__ bool block_solve(double* A, int lda, double* B, int ldb, int m, int n
   return true;
 }
 
-// BFGS append of the pair (s, y) to B = I + U U^T - V V^T (or to a given B s):
+// BFGS append of the pair (s, y) to B = sigma I + U U^T - V V^T (or to a given B s):
 // u = y/sqrt(y.s), v = B s/sqrt(s.B s); skipped when y.s <= 1e-12 |s||y| or s.B s <= 0.
-// bs_given != nullptr supplies B s (Bi-PQN corrections); otherwise B s = s + U(U^T s) - V(V^T s).
+// bs_given != nullptr supplies B s (Bi-PQN corrections); otherwise B s = sigma s + U(U^T s) - V(V^T s).
 // When the memory is full it restarts from the identity.
 __device__ void bfgs_append(int n, double* U, double* V, double* S, double* Y, double* rho, int* r_io,
                             const double* s, const double* y, const double* bs_given, double* bs_buf, double* red,
-                            double* coefs) {
+                            double* coefs, double sigma) {
   int r = *r_io;
   const double ys = bdot(y, s, n, red), ss = bdot(s, s, n, red), yy = bdot(y, y, n, red);
   if (!(ys > 1e-12 * sqrt(ss) * sqrt(yy))) return;
@@ -137,7 +139,7 @@ __device__ void bfgs_append(int n, double* U, double* V, double* S, double* Y, d
     }
     __syncthreads();
     for (int e = threadIdx.x; e < n; e += kT) {
-      double v = s[e];
+      double v = sigma * s[e];
       for (int a = 0; a < r; ++a) v = fma(U[(size_t)a * n + e], coefs[a], v);
       for (int a = 0; a < r; ++a) v = fma(-V[(size_t)a * n + e], coefs[r + a], v);
       bs_buf[e] = v;
@@ -278,7 +280,7 @@ __global__ __launch_bounds__(kT) void k_pqn_replay(PqnDev d, const double* __res
   for (int k = first; k < npairs; ++k) {
     int rr = r;
     bfgs_append(d.n, d.U, d.V, d.S, d.Y, d.rho, &rr, Sw + (size_t)k * d.n, Yw + (size_t)k * d.n, nullptr, d.t1,
-                red, coefs);
+                red, coefs, d.sc->sigma > 0.0 ? d.sc->sigma : 1.0);
     __syncthreads();
     if (threadIdx.x == 0) r = rr;
     __syncthreads();
@@ -334,6 +336,10 @@ __global__ __launch_bounds__(kT) void k_pqn_prepare(PqnDev d, int jmax) {
     for (int e = threadIdx.x; e < n; e += kT) d.t1[e] = fma(-al, d.Y[(size_t)i * n + e], d.t1[e]);
     __syncthreads();
   }
+  const double sigma = d.sc->sigma > 0.0 ? d.sc->sigma : 1.0;
+  const double isig = 1.0 / sigma;
+  for (int e = threadIdx.x; e < n; e += kT) d.t1[e] *= isig;   // H0 = I / sigma
+  __syncthreads();
   for (int i = 0; i < r; ++i) {
     const double be = d.rho[i] * bdot(d.Y + (size_t)i * n, d.t1, n, red);
     __syncthreads();
@@ -343,11 +349,11 @@ __global__ __launch_bounds__(kT) void k_pqn_prepare(PqnDev d, int jmax) {
   }
   for (int e = threadIdx.x; e < n; e += kT) d.xt[e] = d.x[e] - d.t1[e];
   __syncthreads();
-  // 3. weighted prox (D = I): x^ = (x~ + C^{-1} V a~ - U a)_+, C = I + U U^T
+  // 3. weighted prox (D = sigma I): x^ = (x~ + C^{-1} V a~ - U a / sigma)_+, C = sigma I + U U^T
   if (r == 0) {
     for (int e = threadIdx.x; e < n; e += kT) d.xh[e] = fmax(d.xt[e], 0.0);
   } else {
-    // Gm = I + U^T U, Xm = U^T V; Xm <- Gm^{-1} Xm; CiV = V - U Xm (Woodbury)
+    // Gm = sigma I + U^T U, Xm = U^T V; Xm <- Gm^{-1} Xm; CiV = (V - U Xm)/sigma (Woodbury)
     for (int ent = threadIdx.x; ent < 2 * r * r; ent += kT) {
       const int which = ent / (r * r), ab = ent % (r * r), a = ab / r, b = ab % r;
       const double* u = d.U + (size_t)a * n;
@@ -355,7 +361,7 @@ __global__ __launch_bounds__(kT) void k_pqn_prepare(PqnDev d, int jmax) {
       double t = 0.0;
       for (int e = 0; e < n; ++e) t = fma(u[e], v[e], t);
       if (which == 0)
-        Gm[a * r + b] = t + (a == b ? 1.0 : 0.0);
+        Gm[a * r + b] = t + (a == b ? sigma : 0.0);
       else
         Xm[a * r + b] = t;
     }
@@ -365,7 +371,7 @@ __global__ __launch_bounds__(kT) void k_pqn_prepare(PqnDev d, int jmax) {
       for (int c = 0; c < r; ++c) {
         double v = d.V[(size_t)c * n + e];
         for (int a = 0; a < r; ++a) v = fma(-d.U[(size_t)a * n + e], Xm[a * r + c], v);
-        d.CiV[(size_t)c * n + e] = v;
+        d.CiV[(size_t)c * n + e] = v * isig;
       }
     for (int k = threadIdx.x; k < 2 * r; k += kT) z[k] = 0.0;
     __syncthreads();
@@ -373,12 +379,13 @@ __global__ __launch_bounds__(kT) void k_pqn_prepare(PqnDev d, int jmax) {
     int steps = 0;
     for (int j = 0; j < jmax; ++j) {
       ++steps;
-      // w = x~ + CiV a~ - U a; t2 = x~ + CiV a~; x^ = w_+; Lambda = [w > 0]
+      // w = x~ + CiV a~ - U a / sigma; t2 = x~ + CiV a~; x^ = w_+; Lambda = [w > 0]
       for (int e = threadIdx.x; e < n; e += kT) {
         double t2 = d.xt[e];
         for (int c = 0; c < r; ++c) t2 = fma(d.CiV[(size_t)c * n + e], z[r + c], t2);
-        double w = t2;
-        for (int a = 0; a < r; ++a) w = fma(-d.U[(size_t)a * n + e], z[a], w);
+        double ua = 0.0;
+        for (int a = 0; a < r; ++a) ua = fma(d.U[(size_t)a * n + e], z[a], ua);
+        const double w = t2 - ua * isig;
         d.t2[e] = t2;
         d.w[e] = w;
         d.xh[e] = fmax(w, 0.0);
@@ -403,6 +410,7 @@ __global__ __launch_bounds__(kT) void k_pqn_prepare(PqnDev d, int jmax) {
           } else {
             for (int e = 0; e < n; ++e) t = fma(u[e] * (d.w[e] > 0.0 ? 1.0 : 0.0), v[e], t);
           }
+          if (ctop) t *= isig;      // columns D^{-1} U
           if (!rtop && !ctop) t = -t;
           Jm[row * m2 + col] = t + (row == col ? 1.0 : 0.0);
         }
@@ -426,8 +434,9 @@ __global__ __launch_bounds__(kT) void k_pqn_prepare(PqnDev d, int jmax) {
     for (int e = threadIdx.x; e < n; e += kT) {
       double w = d.xt[e];
       for (int c = 0; c < r; ++c) w = fma(d.CiV[(size_t)c * n + e], z[r + c], w);
-      for (int a = 0; a < r; ++a) w = fma(-d.U[(size_t)a * n + e], z[a], w);
-      d.xh[e] = fmax(w, 0.0);
+      double ua = 0.0;
+      for (int a = 0; a < r; ++a) ua = fma(d.U[(size_t)a * n + e], z[a], ua);
+      d.xh[e] = fmax(w - ua * isig, 0.0);
     }
     if (threadIdx.x == 0) d.sc->ssn_steps += steps;
   }
@@ -471,6 +480,12 @@ __global__ __launch_bounds__(kT) void k_pqn_accept(PqnDev d) {
   __shared__ double coefs[2 * kRmax];
   const int n = d.n;
   int reset = 0;
+  double sigma = d.sc->sigma;
+  if (!(sigma > 0.0)) {
+    // first step: the metric scale is the curvature of this step's own product
+    const double pAp = bdot(d.p, d.Ap, n, red), pp = bdot(d.p, d.p, n, red);
+    sigma = pAp > 0.0 ? pAp / pp : 1.0;
+  }
   const double eta = step_size_block(d.g, d.x, d.p, d.Ap, n, red, &reset);
   for (int e = threadIdx.x; e < n; e += kT) {
     d.x[e] = fmax(fma(eta, d.p[e], d.x[e]), 0.0);
@@ -480,8 +495,9 @@ __global__ __launch_bounds__(kT) void k_pqn_accept(PqnDev d) {
   }
   __syncthreads();
   int r = reset ? 0 : d.sc->r;
-  bfgs_append(n, d.U, d.V, d.S, d.Y, d.rho, &r, d.xt, d.xh, nullptr, d.t1, red, coefs);
+  bfgs_append(n, d.U, d.V, d.S, d.Y, d.rho, &r, d.xt, d.xh, nullptr, d.t1, red, coefs, sigma);
   if (threadIdx.x == 0) {
+    d.sc->sigma = sigma;
     d.sc->r = r;
     d.sc->eta = eta;
     d.sc->reset = reset;
@@ -662,7 +678,7 @@ __global__ __launch_bounds__(kT) void k_bi_accept(PqnDev o, BiDev B, PqnDev in) 
   const int nlow = reset ? 0 : min(in.sc->r, kRmax);
   if (reset) rc = 0;
   int rnew = rc;
-  bfgs_append(n, B.Uc, B.Vc, nullptr, nullptr, nullptr, &rnew, o.xt, o.xh, B.Bs, nullptr, red, cf);
+  bfgs_append(n, B.Uc, B.Vc, nullptr, nullptr, nullptr, &rnew, o.xt, o.xh, B.Bs, nullptr, red, cf, 1.0);
   const bool added = rnew == rc + 1 || (rc >= kRmax && rnew == 1);
   const double* u = added ? B.Uc + (size_t)(rnew - 1) * n : nullptr;
   const double* v = added ? B.Vc + (size_t)(rnew - 1) * n : nullptr;
@@ -1010,6 +1026,7 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
     run_mono(ctx, I, o.k_max_inner, o.j_max, mvp_lo_plain, nullptr, M, &in_iters);
     PqnScal sI = read_scal(ctx, I.d.sc);
     ssn += sI.ssn_steps;
+    double sigma_in = sI.sigma;   // metric scale carried into every subproblem
     // outer state: x = x0, A^ x = inner A x, pairs = inner memory, no corrections
     PqnScal so{};
     so.tol_abs = o.kkt_tol_abs;
@@ -1053,11 +1070,13 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
       sin.tol_abs = std::max(1e-12, 1e-2 * so2.e);
       sin.tol_rel = o.kkt_tol_rel;
       sin.ssn_steps = 0;
+      sin.sigma = sigma_in;
       HIPCHK(hipMemcpyAsync(I.d.sc, &sin, sizeof(PqnScal), hipMemcpyHostToDevice, ctx.stream));
       hipLaunchKernelGGL(k_pqn_replay, dim3(1), dim3(kT), 0, ctx.stream, I.d, B.Slow, B.Ylow, hc[1]);
       run_mono(ctx, I, o.k_max_inner, o.j_max, mvp_B, nullptr, M, &in_iters);
       PqnScal sI2 = read_scal(ctx, I.d.sc);
       ssn += sI2.ssn_steps;
+      sigma_in = sI2.sigma;
       hipLaunchKernelGGL(k_bi_direction, dim3(1), dim3(kT), 0, ctx.stream, O.d, I.d);
       PqnScal sd = read_scal(ctx, O.d.sc);
       if (sd.stationary) {
