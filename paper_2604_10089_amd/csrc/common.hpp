@@ -71,6 +71,7 @@ struct SphereTables {
   std::vector<double> w;        // [n] quadrature weights (sum 4 pi a^2)
   std::vector<double> S;        // [3n][3n] self block, SoA rows (c*n+i), cols (d*n+k)
   std::vector<double> T;        // [L][n] analysis: coefficients = T q
+  std::vector<double> G;        // [3n][3L] self block on coefficients: S = G (I3 x T)
   int up = 2, nt_up = 0, np_up = 0, n_up = 0;
   std::vector<double> off_up;   // [n_up][3] upsampled grid offsets
   std::vector<double> w_up;     // [n_up]

@@ -27,7 +27,7 @@ void pqn_ctx_impl::setup_level(Level& lv, int nt, int np, double tol) {
   lv.p = t.p;
   lv.off.upload(t.off.data(), t.off.size(), stream);
   lv.w.upload(t.w.data(), t.w.size(), stream);
-  lv.S.upload(t.S.data(), t.S.size(), stream);
+  lv.G.upload(t.G.data(), t.G.size(), stream);
   lv.T.upload(t.T.data(), t.T.size(), stream);
   lv.Yup.upload(t.Y_up.data(), t.Y_up.size(), stream);
   std::vector<double4> ou(t.n_up);
@@ -47,7 +47,7 @@ void pqn_ctx_impl::setup_level(Level& lv, int nt, int np, double tol) {
   lv.near_part.alloc((size_t)kMaxNear * 3 * N);
   lv.coef.alloc((size_t)3 * M * lv.L);
   lv.qup.alloc((size_t)3 * M * lv.nup);
-  lv.selfo.alloc((size_t)3 * N);
+  lv.selfo.alloc((size_t)9 * N);
   lv.mom.alloc((size_t)6 * M);
   lv.restart = cfg.gmres_restart;
   lv.max_iter = cfg.gmres_max_iter;
@@ -96,6 +96,16 @@ void pqn_ctx_impl::set_configuration(const double* c, const double* ax) {
     }
     max_slots = std::max(max_slots, h_npart[i]);
   }
+  // ordered near pairs (target sphere, source sphere, partner slot)
+  std::vector<int> nl;
+  for (int i = 0; i < M; ++i)
+    for (int s = 0; s < h_npart[i]; ++s) {
+      nl.push_back(i);
+      nl.push_back(h_partners[(size_t)i * kMaxNear + s]);
+      nl.push_back(s);
+    }
+  n_near = (int)nl.size() / 3;
+  near_list.upload(nl.data(), nl.size(), stream);
   ctr.upload(centers.data(), centers.size(), stream);
   dax.upload(axes.data(), axes.size(), stream);
   cls.upload(hc.data(), hc.size(), stream);
@@ -132,14 +142,14 @@ void pqn_ctx_impl::apply_operator(Level& lv, int precision, const double* q, dou
   const int n = lv.n, N = lv.N, L = lv.L, nup = lv.nup;
   hipStream_t s = stream;
   const double scale = 3.0 / (4.0 * kPi * a);
-  if (max_slots > 0) {
-    // harmonic coefficients of every sphere's density, then its values on the upsampled grid
-    launch_gemm64(s, L, M, n, lv.T.p, n, q, N, n, 0, n, lv.coef.p, (long)M * L, L, 0, L, 3);
-    launch_gemm64(s, nup, M, L, lv.Yup.p, L, lv.coef.p, (long)M * L, L, 0, L, lv.qup.p, (long)M * nup, nup, 0, nup,
-                  3);
-  }
-  // singular self interaction: per sphere (3n x 3n) block times the sphere's density
-  launch_gemm64(s, 3 * n, M, 3 * n, lv.S.p, 3 * n, q, 0, n, N, n, lv.selfo.p, 0, n, N, n, 1);
+  // harmonic coefficients of every sphere's density (per component): coef = T q
+  launch_gemm64(s, L, M, n, lv.T.p, n, 0, q, N, n, 0, n, lv.coef.p, (long)M * L, L, 0, L, 3);
+  // singular self interaction on the coefficients, one partial per source component d:
+  // self_d = G[:, d block] coef_d
+  launch_gemm64(s, 3 * n, M, L, lv.G.p, 3 * L, L, lv.coef.p, (long)M * L, L, 0, L, lv.selfo.p, 3L * N, n, N, n, 3);
+  if (n_near > 0)   // density on the upsampled grid of every sphere: qup = Yup coef
+    launch_gemm64(s, nup, M, L, lv.Yup.p, L, 0, lv.coef.p, (long)M * L, L, 0, L, lv.qup.p, (long)M * nup, nup, 0,
+                  nup, 3);
   begin_far_timing();
   if (precision == PQN_MIXED) {
     launch_pack32(s, q, lv.off.p, lv.w.p, n, N, lv.src32.p);
@@ -153,11 +163,11 @@ void pqn_ctx_impl::apply_operator(Level& lv, int precision, const double* q, dou
     ++ev_used;
   }
   ++n_far;
-  launch_near64(s, max_slots, ctr.p, lv.off.p, lv.offup.p, lv.qup.p, lv.coef.p, partners.p, npart.p, n, M, N, nup,
-                lv.p, L, scale, lv.near_part.p);
+  launch_near64p(s, n_near, ctr.p, lv.off.p, lv.offup.p, lv.qup.p, lv.coef.p, near_list.p, n, M, N, nup, lv.p, L,
+                 scale, lv.near_part.p);
   launch_moments(s, q, lv.off.p, lv.w.p, n, M, N, lv.mom.p);
-  launch_combine(s, q, lv.selfo.p, lv.far_part.p, lv.nchunks, lv.near_part.p, npart.p, lv.mom.p, lv.off.p, n, N, a,
-                 y);
+  launch_combine(s, q, lv.selfo.p, 3, lv.far_part.p, lv.nchunks, lv.near_part.p, npart.p, lv.mom.p, lv.off.p, n, N,
+                 a, y);
   HIPCHK(hipGetLastError());
   ++n_matvec;
 }

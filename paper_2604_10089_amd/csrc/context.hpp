@@ -60,7 +60,7 @@ struct Timer {
 struct Level {
   SphereTables tab;
   int M = 0, n = 0, N = 0, L = 0, nup = 0, p = 0;
-  DevArray<double> off, w, S, T, Yup;
+  DevArray<double> off, w, G, T, Yup;
   DevArray<double4> offup;
   // per-matvec work buffers
   DevArray<float4> src32;
@@ -91,8 +91,8 @@ struct pqn_ctx_impl {
   // configuration-dependent tables shared by both levels
   DevArray<double> ctr, dax;
   DevArray<unsigned char> cls;
-  DevArray<int> partners, npart;
-  int max_slots = 0;
+  DevArray<int> partners, npart, near_list;
+  int max_slots = 0, n_near = 0;
   std::vector<int> h_partners, h_npart;
   DevArray<double> FT, UO;
   // profiling of far launches

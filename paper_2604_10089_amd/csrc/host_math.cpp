@@ -190,6 +190,27 @@ void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, Sph
     for (int q = 0; q < t.L; ++q) t.T[(size_t)q * t.n + k] = Y[q] * wu;
   }
   build_self_block(t);
+  // G = S (I3 x Ygrid): since T Ygrid = I (exact quadrature of orthonormal harmonics),
+  // S = G (I3 x T) and the self term can act on the harmonic coefficients.
+  {
+    std::vector<double> Yg((size_t)t.n * t.L);
+    for (int k = 0; k < t.n; ++k) {
+      double st = std::sqrt(1.0 - ct[k] * ct[k]);
+      sh_row(t.p, ct[k], st, std::cos(ph[k]), std::sin(ph[k]), &Yg[(size_t)k * t.L]);
+    }
+    const int n = t.n, L = t.L;
+    t.G.assign((size_t)9 * n * L, 0.0);
+    for (int r = 0; r < 3 * n; ++r)
+      for (int d = 0; d < 3; ++d) {
+        const double* srow = &t.S[(size_t)r * 3 * n + (size_t)d * n];
+        double* grow = &t.G[(size_t)r * 3 * L + (size_t)d * L];
+        for (int k = 0; k < n; ++k) {
+          const double sv = srow[k];
+          const double* yk = &Yg[(size_t)k * L];
+          for (int l = 0; l < L; ++l) grow[l] += sv * yk[l];
+        }
+      }
+  }
   // upsampled grid for near pairs and the synthesis matrix on it
   t.up = near_up;
   t.nt_up = near_up * n_theta;

@@ -246,6 +246,60 @@ __global__ __launch_bounds__(256) void k_near64(const double* __restrict__ ctr, 
   pb[2 * N + t] = scale * az;
 }
 
+// Same sum, organised by near sphere pair: grid (pair, 64-target chunk). All
+// lanes of a wave share the source sphere j, so the upsampled source stream and
+// the harmonic coefficients of q_j are wave-uniform (scalar loads).
+__global__ __launch_bounds__(64) void k_near64p(const double* __restrict__ ctr, const double* __restrict__ off,
+                                                const double4* __restrict__ offup, const double* __restrict__ qup,
+                                                const double* __restrict__ coef, const int* __restrict__ npairs,
+                                                int n, int M, int N, int nup, int p, int L, double scale,
+                                                double* __restrict__ near_part) {
+  const int i = npairs[3 * blockIdx.x], j = npairs[3 * blockIdx.x + 1], slot = npairs[3 * blockIdx.x + 2];
+  const int k = blockIdx.y * 64 + threadIdx.x;
+  const bool valid = k < n;
+  const int kk = valid ? k : n - 1;
+  const int t = i * n + kk;
+  const double Xx = (ctr[3 * i] + off[3 * kk]) - ctr[3 * j];
+  const double Xy = (ctr[3 * i + 1] + off[3 * kk + 1]) - ctr[3 * j + 1];
+  const double Xz = (ctr[3 * i + 2] + off[3 * kk + 2]) - ctr[3 * j + 2];
+  const double rho = sqrt(Xx * Xx + Xy * Xy);
+  const double R = sqrt(rho * rho + Xz * Xz);
+  const double ct = Xz / R, st = rho / R;
+  const double cp = rho > 0.0 ? Xx / rho : 1.0, sp = rho > 0.0 ? Xy / rho : 0.0;
+  const size_t ML = (size_t)M * L;
+  const double* cx = coef + (size_t)j * L;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  real_sh_visit(p, ct, st, cp, sp, [&](int idx, double y) {
+    fx = fma(y, cx[idx], fx);
+    fy = fma(y, cx[ML + idx], fy);
+    fz = fma(y, cx[2 * ML + idx], fz);
+  });
+  const size_t MU = (size_t)M * nup;
+  const double* qx = qup + (size_t)j * nup;
+  double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll 2
+  for (int f = 0; f < nup; ++f) {
+    const double4 o = offup[f];
+    const double rx = Xx - o.x, ry = Xy - o.y, rz = Xz - o.z;
+    const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+    const double ri = rsqrt(r2);
+    const double ri2 = ri * ri;
+    const double dqx = qx[f] - fx, dqy = qx[MU + f] - fy, dqz = qx[2 * MU + f] - fz;
+    const double rn = fma(rx, o.x, fma(ry, o.y, rz * o.z));
+    const double rq = o.w * fma(rx, dqx, fma(ry, dqy, rz * dqz));
+    const double c = rn * rq * ri * ri2 * ri2;
+    ax = fma(c, rx, ax);
+    ay = fma(c, ry, ay);
+    az = fma(c, rz, az);
+  }
+  if (valid) {
+    double* pb = near_part + (size_t)slot * 3 * N;
+    pb[t] = scale * ax;
+    pb[N + t] = scale * ay;
+    pb[2 * N + t] = scale * az;
+  }
+}
+
 // ------------------------------------------------------------------ GEMM
 //
 // C(r, col) = sum_k A[r * lda + k] * B(k, col), FP64, 64x64 tiles, BK = 16.
@@ -253,23 +307,25 @@ __global__ __launch_bounds__(256) void k_near64(const double* __restrict__ ctr, 
 // C(r, col) is stored at C[z * Cz + (r / rb) * rbs + col * ldc + r % rb]: one
 // kernel covers the per-sphere block products on the SoA field layout.
 
-constexpr int GBM = 64, GBN = 64, GBK = 16;
+constexpr int GBM = 32, GBN = 32, GBK = 16;
 
-__global__ __launch_bounds__(256) void k_gemm64(int R, int Cn, int K, const double* __restrict__ A, int lda,
-                                                const double* __restrict__ B, long Bz, int kb, long kbs, int ldb,
-                                                double* __restrict__ C, long Cz, int rb, long rbs, int ldc) {
+// One wave per 32x32 output tile, 4x4 outputs per lane (rows ty+8e, cols tx+8f).
+__global__ __launch_bounds__(64) void k_gemm64(int R, int Cn, int K, const double* __restrict__ A, int lda, long Az,
+                                               const double* __restrict__ B, long Bz, int kb, long kbs, int ldb,
+                                               double* __restrict__ C, long Cz, int rb, long rbs, int ldc) {
   __shared__ double As[GBK][GBM + 1];
   __shared__ double Bs[GBK][GBN + 1];
   const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;
+  const int tx = tid % 8, ty = tid / 8;
   const int r0 = blockIdx.x * GBM, c0 = blockIdx.y * GBN;
+  A += (size_t)blockIdx.z * Az;
   B += (size_t)blockIdx.z * Bz;
   C += (size_t)blockIdx.z * Cz;
   double acc[4][4] = {};
   for (int k0 = 0; k0 < K; k0 += GBK) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = tid + e * 256;        // 0..1023
+    for (int e = 0; e < 8; ++e) {
+      const int idx = tid + e * 64;         // 0..511
       const int ar = idx / GBK, ak = idx % GBK;
       const int gr = r0 + ar, gk = k0 + ak;
       As[ak][ar] = (gr < R && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
@@ -283,8 +339,8 @@ __global__ __launch_bounds__(256) void k_gemm64(int R, int Cn, int K, const doub
       double a[4], b[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        a[e] = As[kk][ty + 16 * e];
-        b[e] = Bs[kk][tx + 16 * e];
+        a[e] = As[kk][ty + 8 * e];
+        b[e] = Bs[kk][tx + 8 * e];
       }
 #pragma unroll
       for (int e = 0; e < 4; ++e)
@@ -295,11 +351,11 @@ __global__ __launch_bounds__(256) void k_gemm64(int R, int Cn, int K, const doub
   }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const int gr = r0 + ty + 16 * e;
+    const int gr = r0 + ty + 8 * e;
     if (gr >= R) continue;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      const int gc = c0 + tx + 16 * f;
+      const int gc = c0 + tx + 8 * f;
       if (gc < Cn) C[(size_t)(gr / rb) * rbs + (size_t)gc * ldc + gr % rb] = acc[e][f];
     }
   }
@@ -395,9 +451,9 @@ __global__ void k_rigid_velocity(const double* __restrict__ mom, int M, double a
   }
 }
 
-// y = q/2 + self + sum(far partials) + sum(near partials) + P[q].
+// y = q/2 + sum(self partials) + sum(far partials) + sum(near partials) + P[q].
 __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ q, const double* __restrict__ selfo,
-                                                 const double* __restrict__ far_part, int nchunks,
+                                                 int nself, const double* __restrict__ far_part, int nchunks,
                                                  const double* __restrict__ near_part, const int* __restrict__ npart,
                                                  const double* __restrict__ mom, const double* __restrict__ off,
                                                  int n, int N, double a, double* __restrict__ y) {
@@ -413,7 +469,8 @@ __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ q, c
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const size_t e = (size_t)c * N + t;
-    double v = 0.5 * q[e] + selfo[e] + P[c];
+    double v = 0.5 * q[e] + P[c];
+    for (int h = 0; h < nself; ++h) v += selfo[(size_t)h * 3 * N + e];
     for (int h = 0; h < nchunks; ++h) v += far_part[(size_t)h * 3 * N + e];
     for (int h = 0; h < np; ++h) v += near_part[(size_t)h * 3 * N + e];
     y[e] = v;
@@ -509,10 +566,17 @@ void launch_near64(hipStream_t s, int max_slots, const double* ctr, const double
   hipLaunchKernelGGL(k_near64, dim3(nblk(N), max_slots), dim3(256), 0, s, ctr, off, offup, qup, coef, partners,
                      npart, n, M, N, nup, p, L, scale, near_part);
 }
-void launch_gemm64(hipStream_t s, int R, int Cn, int K, const double* A, int lda, const double* B, long Bz, int kb,
-                   long kbs, int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch) {
-  hipLaunchKernelGGL(k_gemm64, dim3((R + GBM - 1) / GBM, (Cn + GBN - 1) / GBN, batch), dim3(256), 0, s, R, Cn, K, A,
-                     lda, B, Bz, kb, kbs, ldb, C, Cz, rb, rbs, ldc);
+void launch_gemm64(hipStream_t s, int R, int Cn, int K, const double* A, int lda, long Az, const double* B, long Bz,
+                   int kb, long kbs, int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch) {
+  hipLaunchKernelGGL(k_gemm64, dim3((R + GBM - 1) / GBM, (Cn + GBN - 1) / GBN, batch), dim3(64), 0, s, R, Cn, K, A,
+                     lda, Az, B, Bz, kb, kbs, ldb, C, Cz, rb, rbs, ldc);
+}
+void launch_near64p(hipStream_t s, int npairs_count, const double* ctr, const double* off, const double4* offup,
+                    const double* qup, const double* coef, const int* npairs, int n, int M, int N, int nup, int p,
+                    int L, double scale, double* near_part) {
+  if (npairs_count <= 0) return;
+  hipLaunchKernelGGL(k_near64p, dim3(npairs_count, (n + 63) / 64), dim3(64), 0, s, ctr, off, offup, qup, coef,
+                     npairs, n, M, N, nup, p, L, scale, near_part);
 }
 void launch_rhs(hipStream_t s, const double* ctr, const double* FT, const double* axes, const double* off, int n,
                 int M, int N, double a, double mu, double slip, double* rhs) {
@@ -525,11 +589,11 @@ void launch_moments(hipStream_t s, const double* q, const double* off, const dou
 void launch_rigid_velocity(hipStream_t s, const double* mom, int M, double a, double* UO) {
   hipLaunchKernelGGL(k_rigid_velocity, dim3(nblk(M, 64)), dim3(64), 0, s, mom, M, a, UO);
 }
-void launch_combine(hipStream_t s, const double* q, const double* selfo, const double* far_part, int nchunks,
-                    const double* near_part, const int* npart, const double* mom, const double* off, int n, int N,
-                    double a, double* y) {
-  hipLaunchKernelGGL(k_combine, dim3(nblk(N)), dim3(256), 0, s, q, selfo, far_part, nchunks, near_part, npart, mom,
-                     off, n, N, a, y);
+void launch_combine(hipStream_t s, const double* q, const double* selfo, int nself, const double* far_part,
+                    int nchunks, const double* near_part, const int* npart, const double* mom, const double* off,
+                    int n, int N, double a, double* y) {
+  hipLaunchKernelGGL(k_combine, dim3(nblk(N)), dim3(256), 0, s, q, selfo, nself, far_part, nchunks, near_part, npart,
+                     mom, off, n, N, a, y);
 }
 void launch_dots(hipStream_t s, const double* V, long ldv, int nvec, const double* w, long len, int nb,
                  double* partial, double* out) {
