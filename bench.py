@@ -1,16 +1,20 @@
-"""Benchmark: mobility MVPs/s and GPair-evals/s on the 216-sphere suspension.
+"""Benchmark: batched mobility MVPs/s and GPair-evals/s on the 216-sphere suspension.
 
-One timed step = one complete high-fidelity mobility product U = M F (random
-forces and torques already resident in HBM, GMRES to 1e-8, mixed precision:
-FP32 far pair sums, FP64 everything else) on 216 spheres of radius 1 at volume
-fraction 0.3 with 12x24 nodes per sphere (62,208 nodes). The same JSON line
-reports the plain FP64 path, the mixed-vs-FP64 error of every velocity block,
-the far pair-sum kernel against the FP32 vector roofline (HIP events on the
-library's stream), one Bi-PQN LCP solve with a planted solution on the
-suspension's contact set (low fidelity 6x12), and the CPU oracle's rate on a
-bounded sample of the same operator.
+One timed step = one batched mobility product of K = 6 independent force sets
+U_r = M F_r on 216 spheres of radius 1 at volume fraction 0.3 with 12x24 nodes
+per sphere (62,208 nodes): six GMRES solves (tolerance 1e-8) in lockstep whose
+pair sums share one geometry pass, mixed precision (FP32 far pair sums, FP64
+everything else), forces resident in HBM. value = force sets per second.
 
-Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline] [--no-lcp]
+The same JSON line reports: the single-force-set rate and the plain FP64 path
+(both K = 1 and K = 6), the mixed-vs-FP64 error of every velocity block, the
+far pair-sum kernel against the FP32 vector roofline (HIP events on the
+library's stream), the 32-suspension uneven batch (one far launch per GMRES
+iteration) against the same suspensions one by one, one Bi-PQN and one
+Mono-PQN solve of a planted LCP on the suspension's contact set (low fidelity
+6x12), and the CPU oracle's rate on a bounded sample of the same operator.
+
+Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline] [--no-lcp] [--no-batch]
 """
 import argparse
 import json
@@ -25,7 +29,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR = 157.3      # TFLOP/s, MI355X FP32 vector (vendor figure, packed issue)
 PEAK_FP32_NONPACKED = 78.6    # TFLOP/s, 256 CU x 64 lanes x 2 flop x 2.4 GHz (no packed FP32)
-FLOP_PER_PAIR = 30            # algorithmic flops of one far pair evaluation (single right-hand side)
+K_RHS = 6
+
+
+def flop_per_pair(K):
+    """Algorithmic flops of one far pair with K densities (FMA = 2, rsqrt = 1): 18 shared + 12 per density."""
+    return 18 + 12 * K
 
 
 def far_pairs(centers, n, near_gap=0.5, radius=1.0):
@@ -34,17 +43,18 @@ def far_pairs(centers, n, near_gap=0.5, radius=1.0):
     M = c.shape[0]
     near = (d < near_gap).sum() - M      # ordered near pairs (diagonal excluded)
     far = M * (M - 1) - near
-    return far * n * n, near * n * (4 * n)
+    return far * n * n
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
-    ap.add_argument('--steps', type=int, default=10)
-    ap.add_argument('--warmup', type=int, default=2)
+    ap.add_argument('--steps', type=int, default=5)
+    ap.add_argument('--warmup', type=int, default=1)
     ap.add_argument('--seed', type=int, default=0)
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-lcp', action='store_true')
+    ap.add_argument('--no-batch', action='store_true')
     ap.add_argument('--tpt', type=int, default=2)
     ap.add_argument('--chunks', type=int, default=0)
     args = ap.parse_args()
@@ -56,6 +66,9 @@ def main():
     import torch
     from paper_2604_10089_amd import binding, inputs
 
+    def log(*a):
+        print('[bench]', *a, file=sys.stderr, flush=True)
+
     dev = torch.device('cuda:0')
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
@@ -65,44 +78,50 @@ def main():
     nt, nph = w['n_theta'], w['n_phi']
     n = nt * nph
     K, W = args.steps, args.warmup
-    FTs = [torch.tensor(inputs.random_forces(100 + k, M), dtype=torch.float64, device=dev) for k in range(max(K, 1))]
-    UO = torch.zeros((M, 6), dtype=torch.float64, device=dev)
+    pf = far_pairs(c, n)
 
-    def ctx_for(prec, profile):
+    def ctx_for(prec, profile=True):
         return binding.Context(c, None, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision=prec, tpt=args.tpt,
                                far_chunks=args.chunks, stream=stream.cuda_stream, profile=profile)
 
-    res = {}
-    for prec in ('mixed', 'fp64'):
-        ctx = ctx_for(prec, True)
-        for k in range(W):
-            ctx.mobility_apply_dev(FTs[k % len(FTs)].data_ptr(), UO.data_ptr())
-        steps = K if prec == 'mixed' else max(2, K // 2)
+    FT6 = [inputs.random_forces(100 + k, M, k=K_RHS) for k in range(max(K, 1) + W)]
+
+    def run_multi(ctx, steps, warm, kr):
+        for k in range(warm):
+            ctx.mobility_apply_multi(FT6[k][:kr])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        its = far_ms = nfar = 0
+        its = far_ms = nfar = mv = 0
         for k in range(steps):
-            st = ctx.mobility_apply_dev(FTs[k % len(FTs)].data_ptr(), UO.data_ptr())
+            _, st = ctx.mobility_apply_multi(FT6[warm + k][:kr])
             its += st['gmres_iters']
             far_ms += st['t_far_ms']
             nfar += st['n_far']
+            mv += st['matvecs']
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        res[prec] = dict(steps=steps, sec=t1 - t0, gmres_iters=its / steps, far_ms=far_ms / max(nfar, 1),
-                         matvecs_per_mvp=nfar / steps)
-        print(f'[bench] {prec}: {steps} MVPs in {t1 - t0:.3f} s, {its / steps:.1f} GMRES its/MVP, '
-              f'far kernel {far_ms / max(nfar, 1):.3f} ms/launch', file=sys.stderr, flush=True)
-        ctx.close()
+        sec = time.perf_counter() - t0
+        return dict(steps=steps, sec=sec, mvps=steps * kr / sec, gmres_iters=its / (steps * kr),
+                    far_ms=far_ms / max(nfar, 1), matvecs_per_mvp=mv / (steps * kr), far_launches=nfar)
 
-    # accuracy of mixed vs FP64 on the same forces (per velocity block)
-    errs = []
-    cm, cf = ctx_for('mixed', False), ctx_for('fp64', False)
-    for k in range(2):
-        F = FTs[k].cpu().numpy()
-        Um, _ = cm.mobility_apply(F)
-        Uf, _ = cf.mobility_apply(F)
-        for blk in (slice(0, 3), slice(3, 6)):
-            errs.append(float(np.abs(Um[:, blk] - Uf[:, blk]).max() / np.abs(Uf[:, blk]).max()))
+    res = {}
+    cm = ctx_for('mixed')
+    res['mixed6'] = run_multi(cm, K, W, K_RHS)
+    log('mixed K=6', res['mixed6'])
+    res['mixed1'] = run_multi(cm, max(2, K // 2), 1, 1)
+    log('mixed K=1', res['mixed1'])
+    cf = ctx_for('fp64')
+    res['fp64_6'] = run_multi(cf, max(1, K // 3), 1, K_RHS)
+    log('fp64 K=6', res['fp64_6'])
+    res['fp64_1'] = run_multi(cf, max(1, K // 3), 1, 1)
+    log('fp64 K=1', res['fp64_1'])
+
+    # accuracy of mixed vs FP64 on the same six force sets (per velocity block)
+    Um, _ = cm.mobility_apply_multi(FT6[0])
+    Uf, _ = cf.mobility_apply_multi(FT6[0])
+    errs = {}
+    for name, blk in (('translation', slice(0, 3)), ('rotation', slice(3, 6))):
+        errs['max_' + name] = float(max(np.abs(Um[r][:, blk] - Uf[r][:, blk]).max() / np.abs(Uf[r][:, blk]).max()
+                                        for r in range(K_RHS)))
     cf.close()
 
     lcp_info = None
@@ -114,49 +133,86 @@ def main():
         x, ls = cm.lcp_solve(pairs, b, 'bi')
         t1 = time.perf_counter()
         x2, lm = cm.lcp_solve(pairs, b, 'mono')
-        lcp_info = dict(n_contacts=int(pairs.shape[0]), bi_sec=t1 - t0, bi_mvp_hi=ls['mvp_hi'],
-                        bi_mvp_lo=ls['mvp_lo'], bi_emvp=round(ls['emvp'], 2),
-                        lo_hi_cost_ratio=round(ls['lo_hi_cost_ratio'], 4),
-                        bi_x_rel_err=float(np.abs(x - xs).max() / np.abs(xs).max()),
-                        mono_mvp=lm['mvp_hi'], mono_sec=lm['t_total_ms'] / 1e3,
-                        mono_x_rel_err=float(np.abs(x2 - xs).max() / np.abs(xs).max()))
-        print(f'[bench] Bi-PQN planted LCP n={pairs.shape[0]}: {ls["mvp_hi"]} hi + {ls["mvp_lo"]} lo MVPs, '
-              f'{t1 - t0:.3f} s', file=sys.stderr, flush=True)
+        t2 = time.perf_counter()
+        x3, lb = cm.lcp_solve(pairs, b, 'bb')
+        lcp_info = dict(n_contacts=int(pairs.shape[0]), planted_active=int((xs > 0).sum()),
+                        bi=dict(sec=round(t1 - t0, 3), mvp_hi=ls['mvp_hi'], mvp_lo=ls['mvp_lo'],
+                                emvp=round(ls['emvp'], 2), lo_hi_cost_ratio=round(ls['lo_hi_cost_ratio'], 4),
+                                x_rel_err=float(np.abs(x - xs).max() / np.abs(xs).max())),
+                        mono=dict(sec=round(t2 - t1, 3), mvp=lm['mvp_hi'],
+                                  x_rel_err=float(np.abs(x2 - xs).max() / np.abs(xs).max())),
+                        bbpgd=dict(mvp=lb['mvp_hi'], x_rel_err=float(np.abs(x3 - xs).max() / np.abs(xs).max())))
+        log('lcp', lcp_info)
     cm.close()
 
-    pf, pn = far_pairs(c, n)
-    mixed = res['mixed']
-    mvps = mixed['steps'] / mixed['sec']
-    pairs_per_mvp = mixed['matvecs_per_mvp'] * pf
-    achieved = FLOP_PER_PAIR * pf / (mixed['far_ms'] * 1e-3) / 1e12
-    fp64 = res['fp64']
+    batch_info = None
+    if not args.no_batch:
+        inst = inputs.batched_suspensions(args.seed)
+        FTb = [inputs.random_forces(500 + b, ci.shape[0]) for b, (ci, _, _) in enumerate(inst)]
+        kw = dict(gmres_tol=1e-8, precision='mixed', tpt=args.tpt, stream=stream.cuda_stream)
+        with binding.BatchContext(inst, **kw) as bc:
+            bc.mobility_apply(FTb)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 3
+            for _ in range(reps):
+                _, bst = bc.mobility_apply(FTb)
+            torch.cuda.synchronize()
+            tb = (time.perf_counter() - t0) / reps
+        singles = [binding.Context(ci, None, nti, npi, **kw) for ci, nti, npi in inst]
+        for ctx_b, F in zip(singles, FTb):
+            ctx_b.mobility_apply(F)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for ctx_b, F in zip(singles, FTb):
+            ctx_b.mobility_apply(F)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        for ctx_b in singles:
+            ctx_b.close()
+        batch_info = dict(instances=len(inst), nodes=int(sum(ci.shape[0] * nti * npi for ci, nti, npi in inst)),
+                          batched_sec=round(tb, 4), mvps_batched=round(len(inst) / tb, 2),
+                          one_by_one_sec=round(ts, 4), mvps_one_by_one=round(len(inst) / ts, 2),
+                          speedup=round(ts / tb, 3), lockstep_iterations=bst['n_far'])
+        log('batch', batch_info)
+
+    m6 = res['mixed6']
+    achieved = flop_per_pair(K_RHS) * pf / (m6['far_ms'] * 1e-3) / 1e12
+    achieved1 = flop_per_pair(1) * pf / (res['mixed1']['far_ms'] * 1e-3) / 1e12
     out = {
-        'metric': 'mobility MVPs/s (216 spheres, mixed FP32/FP64, GMRES 1e-8)',
-        'value': round(mvps, 4),
+        'metric': 'batched mobility MVPs/s (216 spheres, 6 force sets per pass, mixed FP32/FP64, GMRES 1e-8)',
+        'value': round(m6['mvps'], 4),
         'unit': 'MVP/s',
         'n_gpus': 1, 'steps': K, 'warmup': W,
-        'ms_per_step': round(1e3 * mixed['sec'] / mixed['steps'], 3),
+        'ms_per_step': round(1e3 * m6['sec'] / m6['steps'], 3),
         'higher_is_better': True, 'scaling': 'weak', 'vs_baseline': None,
         'dtype': 'f32+f64', 'data': 'synthetic',
         'config': {'workload': 'rsa216: 216 spheres a=1, RSA phi=0.3, 12x24 nodes (62,208), near gap 0.5, '
-                               'random F,T, GMRES tol 1e-8', 'n_nodes': M * n, 'far_pairs_per_matvec': int(pf)},
-        'gpair_evals_per_s': round(pairs_per_mvp * mvps / 1e9, 2),
-        'fp64_mvps_per_s': round(fp64['steps'] / fp64['sec'], 4),
-        'speedup_mixed_vs_fp64': round(mvps / (fp64['steps'] / fp64['sec']), 3),
-        'mixed_rel_err_vs_fp64': {'max_translation': max(errs[0::2]), 'max_rotation': max(errs[1::2])},
-        'gmres_iters_per_mvp': {'mixed': mixed['gmres_iters'], 'fp64': fp64['gmres_iters']},
-        'far_kernel_ms': {'mixed_fp32': round(mixed['far_ms'], 4), 'fp64': round(fp64['far_ms'], 4)},
-        'roofline': {'bound': 'alu', 'kernel': 'k_far32', 'achieved': round(achieved, 3),
+                               '6 random force sets per step, GMRES tol 1e-8', 'n_nodes': M * n,
+                   'force_sets_per_step': K_RHS, 'far_pairs_per_matvec': int(pf)},
+        'gpair_evals_per_s': round(m6['matvecs_per_mvp'] * pf * m6['mvps'] / 1e9, 2),
+        'single_mvps_per_s': {'mixed': round(res['mixed1']['mvps'], 4), 'fp64': round(res['fp64_1']['mvps'], 4)},
+        'batched_mvps_per_s': {'mixed': round(m6['mvps'], 4), 'fp64': round(res['fp64_6']['mvps'], 4)},
+        'speedup_mixed_vs_fp64': {'K6': round(m6['mvps'] / res['fp64_6']['mvps'], 3),
+                                  'K1': round(res['mixed1']['mvps'] / res['fp64_1']['mvps'], 3)},
+        'mixed_rel_err_vs_fp64': errs,
+        'gmres_iters_per_mvp': {k: round(v['gmres_iters'], 2) for k, v in res.items()},
+        'far_kernel_ms': {k: round(v['far_ms'], 4) for k, v in res.items()},
+        'roofline': {'bound': 'alu', 'kernel': 'k_far32<1,6>', 'achieved': round(achieved, 3),
                      'peak': PEAK_FP32_VECTOR, 'unit': 'TFLOP/s', 'frac': round(achieved / PEAK_FP32_VECTOR, 4),
-                     'frac_of_nonpacked_peak': round(achieved / PEAK_FP32_NONPACKED, 4), 'traffic': None},
+                     'frac_of_nonpacked_peak': round(achieved / PEAK_FP32_NONPACKED, 4),
+                     'flop_per_pair': flop_per_pair(K_RHS), 'traffic': None,
+                     'k1': {'kernel': 'k_far32<2,1>', 'achieved': round(achieved1, 3),
+                            'frac': round(achieved1 / PEAK_FP32_VECTOR, 4)}},
         'lcp': lcp_info,
+        'batch32': batch_info,
     }
     if not args.no_cpu_baseline:
-        out['cpu_baseline'] = cpu_baseline(w, c, nt, nph, mixed)
+        out['cpu_baseline'] = cpu_baseline(c, nt, nph, res['mixed1'])
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(w, c, nt, nph, mixed):
+def cpu_baseline(c, nt, nph, mixed):
     """The oracle's operator rows on a bounded sample of targets, scaled to one MVP."""
     from oracle import bie
     g = bie.Geometry(c, 1.0, nt, nph)
@@ -174,7 +230,7 @@ def cpu_baseline(w, c, nt, nph, mixed):
     mvp_s = matvec_s * mixed['matvecs_per_mvp']
     return {'value': round(1.0 / mvp_s, 8), 'unit': 'MVP/s', 'cores': 1, 'kind': 'oracle',
             'sample': f'{k} operator rows of the 216-sphere operator (one target node against all '
-                      f'62,208 sources each), scaled by N = {g.N} rows per matvec and '
+                      f'62,208 sources each, ~15 s), scaled by N = {g.N} rows per matvec and '
                       f'{mixed["matvecs_per_mvp"]:.1f} matvecs per MVP'}
 
 

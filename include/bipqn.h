@@ -133,6 +133,10 @@ pqn_status pqn_set_precision(pqn_ctx* ctx, int32_t precision);
 pqn_status pqn_mobility_apply(pqn_ctx* ctx, const double* FT, double* UO, int32_t fidelity, pqn_mvp_stats* stats);
 pqn_status pqn_mobility_apply_dev(pqn_ctx* ctx, const double* FT_dev, double* UO_dev, int32_t fidelity,
                                   pqn_mvp_stats* stats);
+/* K <= 6 force sets at once: FT, UO [K][M][6]. The K boundary-integral solves run in
+ * lockstep and share every geometry pass of the pair sums (multi-right-hand-side). */
+pqn_status pqn_mobility_apply_multi(pqn_ctx* ctx, int32_t k_rhs, const double* FT, double* UO, int32_t fidelity,
+                                    pqn_mvp_stats* stats);
 /* Slip-driven rigid velocities U_nc (F = T = 0), UO [M][6]. */
 pqn_status pqn_nc_velocity(pqn_ctx* ctx, double* UO, int32_t fidelity, pqn_mvp_stats* stats);
 
@@ -153,6 +157,18 @@ pqn_status pqn_lcp_solve(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const do
  * U = U_nc + M D x -> centres += dt U, Janus axes rotated by Omega dt. */
 pqn_status pqn_step(pqn_ctx* ctx, double dt, double delta, int32_t solver, const pqn_lcp_opts* opts,
                     pqn_step_stats* stats);
+
+/* Batched independent suspensions of uneven size (one descriptor and one [M_b][3]
+ * centre array per suspension; janus_axes may be NULL). The suspensions must share
+ * precision, restart length, refinement, device and targets_per_thread; the first
+ * descriptor's stream is used for all. The returned context accepts only the
+ * pqn_batch_* calls and pqn_destroy. */
+pqn_status pqn_batch_create(int32_t n_inst, const pqn_config_desc* descs, const double* const* centers,
+                            const double* const* janus_axes, pqn_ctx** out);
+/* One mobility product per suspension (FT[b], UO[b]: [M_b][6] host arrays), all GMRES
+ * iterations in lockstep, every far pair sum of an iteration in one launch ordered by
+ * decreasing cost. stats: aggregate over the suspensions. */
+pqn_status pqn_batch_mobility_apply(pqn_ctx* ctx, const double* const* FT, double* const* UO, pqn_mvp_stats* stats);
 
 /* Operator-level entry points (stage-by-stage checks of the discrete BIE).
  * pqn_bie_apply: y = (1/2 I + D + P) q for q, y [3][N] host arrays.

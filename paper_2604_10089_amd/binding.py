@@ -92,6 +92,9 @@ def lib():
         'pqn_bie_solve': (C.c_int, [V, C.c_int32, _D, _D, _P(MvpStats)]),
         'pqn_get_grid': (C.c_int, [V, C.c_int32, _I, _D, _D]),
         'pqn_host_self_block': (C.c_int, [C.c_int32, C.c_int32, C.c_double, _D, _D, _D]),
+        'pqn_mobility_apply_multi': (C.c_int, [V, C.c_int32, _D, _D, C.c_int32, _P(MvpStats)]),
+        'pqn_batch_create': (C.c_int, [C.c_int32, _P(ConfigDesc), _P(_D), _P(_D), _P(V)]),
+        'pqn_batch_mobility_apply': (C.c_int, [V, _P(_D), _P(_D), _P(MvpStats)]),
         'pqn_last_error': (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -133,6 +136,72 @@ def pqn_host_self_block(n_theta, n_phi, radius=1.0):
     S = np.zeros((3 * n, 3 * n))
     _check(lib().pqn_host_self_block(n_theta, n_phi, radius, _dptr(off), _dptr(w), _dptr(S)))
     return off, w, S
+
+
+def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_tol_lo=None, restart=50,
+          max_iter=500, near_gap=0.0, near_up=2, slip=1.0, precision='fp64', refine=0, tpt=2, far_chunks=0,
+          device=0, stream=None, profile=False):
+    d = ConfigDesc()
+    d.n_particles = M
+    d.radius, d.mu = radius, mu
+    d.n_theta, d.n_phi = n_theta, n_phi
+    if lo is not None:
+        d.n_theta_lo, d.n_phi_lo = lo
+    d.gmres_tol = gmres_tol
+    d.gmres_tol_lo = gmres_tol if gmres_tol_lo is None else gmres_tol_lo
+    d.gmres_restart, d.gmres_max_iter = restart, max_iter
+    d.near_gap, d.near_up, d.slip_speed = near_gap, near_up, slip
+    d.precision = PQN_MIXED if precision == 'mixed' else PQN_FP64
+    d.refine_sweeps = refine
+    d.targets_per_thread = tpt
+    d.far_chunks = far_chunks
+    d.device = device
+    d.stream = stream
+    d.profile = 1 if profile else 0
+    return d
+
+
+class BatchContext:
+    """Independent suspensions of uneven size in one batch context (pqn_batch_*)."""
+
+    def __init__(self, instances, **kw):
+        """instances: list of (centers [M,3], n_theta, n_phi); kw: shared settings as in Context."""
+        n = len(instances)
+        descs = (ConfigDesc * n)()
+        self._centers = [_f64(c).reshape(-1, 3) for c, _, _ in instances]
+        self.Ms = [c.shape[0] for c in self._centers]
+        for b, (c, nt, nph) in enumerate(instances):
+            descs[b] = _desc(self.Ms[b], nt, nph, **kw)
+        cp = (_D * n)(*[_dptr(c) for c in self._centers])
+        h = C.c_void_p()
+        _check(lib().pqn_batch_create(n, descs, cp, None, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, 'h', None):
+            lib().pqn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def mobility_apply(self, FTs):
+        F = [_f64(f, (m, 6)) for f, m in zip(FTs, self.Ms)]
+        U = [np.zeros((m, 6)) for m in self.Ms]
+        fp = (_D * len(F))(*[_dptr(f) for f in F])
+        up = (_D * len(U))(*[_dptr(u) for u in U])
+        st = MvpStats()
+        status = _check(lib().pqn_batch_mobility_apply(self.h, fp, up, C.byref(st)))
+        return U, dict(_struct_dict(st), status=status)
 
 
 class Context:
@@ -203,6 +272,14 @@ class Context:
         UO = np.zeros((self.M, 6))
         st = MvpStats()
         status = _check(lib().pqn_mobility_apply(self.h, _dptr(FT), _dptr(UO), fidelity, C.byref(st)))
+        return UO, dict(_struct_dict(st), status=status)
+
+    def mobility_apply_multi(self, FT, fidelity=PQN_HIFI):
+        FT = _f64(FT).reshape(-1, self.M, 6)
+        UO = np.zeros_like(FT)
+        st = MvpStats()
+        status = _check(lib().pqn_mobility_apply_multi(self.h, FT.shape[0], _dptr(FT), _dptr(UO), fidelity,
+                                                       C.byref(st)))
         return UO, dict(_struct_dict(st), status=status)
 
     def mobility_apply_dev(self, FT_ptr, UO_ptr, fidelity=PQN_HIFI):

@@ -39,9 +39,47 @@ static void fill_defaults(pqn_config_desc& c) {
   if (c.targets_per_thread <= 0) c.targets_per_thread = 2;
 }
 
+static bool is_batch(const pqn_ctx* ctx) { return ctx && ctx->is_batch; }
+
 extern "C" {
 
 const char* pqn_last_error(void) { return g_last_error.c_str(); }
+
+static std::string check_desc(const pqn_config_desc& c) {
+  if (c.n_particles <= 0) return "n_particles must be > 0";
+  if (c.n_theta < 2 || c.n_phi < 2 * c.n_theta - 1)
+    return "high-fidelity grid needs n_theta >= 2 and n_phi >= 2 n_theta - 1";
+  if (c.n_theta_lo != 0 && (c.n_theta_lo < 2 || c.n_phi_lo < 2 * c.n_theta_lo - 1))
+    return "low-fidelity grid needs n_theta >= 2 and n_phi >= 2 n_theta - 1";
+  if (c.precision != PQN_FP64 && c.precision != PQN_MIXED) return "bad precision";
+  return "";
+}
+
+// Build one suspension's context on the given stream (nullptr: create one).
+static std::unique_ptr<pqn_ctx_impl> make_context(const pqn_config_desc& c, const double* centers,
+                                                  const double* janus_axes, hipStream_t stream) {
+  std::unique_ptr<pqn_ctx_impl> ctx(new pqn_ctx_impl());
+  ctx->cfg = c;
+  ctx->M = c.n_particles;
+  ctx->a = c.radius;
+  ctx->mu = c.mu;
+  ctx->device = c.device;
+  if (stream) {
+    ctx->stream = stream;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    ctx->own_stream = true;
+  }
+  ctx->setup_level(ctx->hi, c.n_theta, c.n_phi, c.gmres_tol);
+  if (c.n_theta_lo > 0) {
+    ctx->setup_level(ctx->lo, c.n_theta_lo, c.n_phi_lo, c.gmres_tol_lo);
+    ctx->has_lo = true;
+  }
+  ctx->FT.alloc(6 * (size_t)kMaxRhs * ctx->M);
+  ctx->UO.alloc(6 * (size_t)kMaxRhs * ctx->M);
+  ctx->set_configuration(centers, janus_axes);
+  return ctx;
+}
 
 pqn_status pqn_create(const pqn_config_desc* desc, const double* centers, const double* janus_axes, pqn_ctx** out) {
   return guarded([&]() -> pqn_status {
@@ -49,38 +87,132 @@ pqn_status pqn_create(const pqn_config_desc* desc, const double* centers, const 
     *out = nullptr;
     pqn_config_desc c = *desc;
     fill_defaults(c);
-    if (c.n_particles <= 0) return fail(PQN_ERR_INVALID, "n_particles must be > 0");
-    if (c.n_theta < 2 || c.n_phi < 2 * c.n_theta - 1)
-      return fail(PQN_ERR_INVALID, "high-fidelity grid needs n_theta >= 2 and n_phi >= 2 n_theta - 1");
-    if (c.n_theta_lo != 0 && (c.n_theta_lo < 2 || c.n_phi_lo < 2 * c.n_theta_lo - 1))
-      return fail(PQN_ERR_INVALID, "low-fidelity grid needs n_theta >= 2 and n_phi >= 2 n_theta - 1");
-    if (c.precision != PQN_FP64 && c.precision != PQN_MIXED) return fail(PQN_ERR_INVALID, "bad precision");
+    const std::string bad = check_desc(c);
+    if (!bad.empty()) return fail(PQN_ERR_INVALID, bad);
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
     if (c.device < 0 || c.device >= ndev) return fail(PQN_ERR_DEVICE, "no such HIP device");
     HIPCHK(hipSetDevice(c.device));
-    std::unique_ptr<pqn_ctx> ctx(new pqn_ctx());
-    ctx->cfg = c;
-    ctx->M = c.n_particles;
-    ctx->a = c.radius;
-    ctx->mu = c.mu;
-    ctx->device = c.device;
-    if (c.stream) {
-      ctx->stream = (hipStream_t)c.stream;
-    } else {
-      HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
-      ctx->own_stream = true;
-    }
-    ctx->setup_level(ctx->hi, c.n_theta, c.n_phi, c.gmres_tol);
-    if (c.n_theta_lo > 0) {
-      ctx->setup_level(ctx->lo, c.n_theta_lo, c.n_phi_lo, c.gmres_tol_lo);
-      ctx->has_lo = true;
-    }
-    ctx->FT.alloc(6 * (size_t)ctx->M);
-    ctx->UO.alloc(6 * (size_t)ctx->M);
-    ctx->set_configuration(centers, janus_axes);
-    *out = ctx.release();
+    std::unique_ptr<pqn_ctx_impl> ctx = make_context(c, centers, janus_axes, (hipStream_t)c.stream);
+    *out = static_cast<pqn_ctx*>(ctx.release());
     return PQN_OK;
+  });
+}
+
+pqn_status pqn_batch_create(int32_t n_inst, const pqn_config_desc* descs, const double* const* centers,
+                            const double* const* janus_axes, pqn_ctx** out) {
+  return guarded([&]() -> pqn_status {
+    if (n_inst <= 0 || !descs || !centers || !out) return fail(PQN_ERR_INVALID, "pqn_batch_create: bad argument");
+    *out = nullptr;
+    pqn_config_desc c0 = descs[0];
+    fill_defaults(c0);
+    for (int b = 0; b < n_inst; ++b) {
+      pqn_config_desc c = descs[b];
+      fill_defaults(c);
+      const std::string bad = check_desc(c);
+      if (!bad.empty()) return fail(PQN_ERR_INVALID, "instance " + std::to_string(b) + ": " + bad);
+      if (!centers[b]) return fail(PQN_ERR_INVALID, "pqn_batch_create: NULL centres");
+      if (c.precision != c0.precision || c.gmres_restart != c0.gmres_restart || c.device != c0.device ||
+          c.targets_per_thread != c0.targets_per_thread || c.refine_sweeps != c0.refine_sweeps)
+        return fail(PQN_ERR_INVALID, "batched instances must share precision, restart, refinement, device and tiling");
+    }
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (c0.device < 0 || c0.device >= ndev) return fail(PQN_ERR_DEVICE, "no such HIP device");
+    HIPCHK(hipSetDevice(c0.device));
+    std::unique_ptr<pqn_ctx_impl> parent(new pqn_ctx_impl());
+    parent->cfg = c0;
+    parent->device = c0.device;
+    parent->is_batch = true;
+    if (c0.stream) {
+      parent->stream = (hipStream_t)c0.stream;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&parent->stream, hipStreamNonBlocking));
+      parent->own_stream = true;
+    }
+    for (int b = 0; b < n_inst; ++b) {
+      pqn_config_desc c = descs[b];
+      fill_defaults(c);
+      parent->children.push_back(make_context(c, centers[b], janus_axes ? janus_axes[b] : nullptr, parent->stream));
+    }
+    *out = static_cast<pqn_ctx*>(parent.release());
+    return PQN_OK;
+  });
+}
+
+pqn_status pqn_batch_mobility_apply(pqn_ctx* ctx, const double* const* FT, double* const* UO, pqn_mvp_stats* stats) {
+  return guarded([&]() -> pqn_status {
+    if (!ctx || !FT || !UO) return fail(PQN_ERR_INVALID, "pqn_batch_mobility_apply: NULL argument");
+    if (!ctx->is_batch) return fail(PQN_ERR_STATE, "pqn_batch_mobility_apply needs a batch context");
+    HIPCHK(hipSetDevice(ctx->device));
+    Timer tm;
+    const int nb = (int)ctx->children.size();
+    for (int b = 0; b < nb; ++b) {
+      if (!FT[b] || !UO[b]) return fail(PQN_ERR_INVALID, "pqn_batch_mobility_apply: NULL force/velocity array");
+      for (int k = 0; k < 6 * ctx->children[b]->M; ++k)
+        if (!std::isfinite(FT[b][k])) return fail(PQN_ERR_NUMERIC, "non-finite force/torque");
+    }
+    ctx->n_matvec = 0;
+    ctx->n_far = 0;
+    std::vector<SysRef> sys;
+    for (int b = 0; b < nb; ++b) {
+      pqn_ctx_impl& c = *ctx->children[b];
+      HIPCHK(hipMemcpyAsync(c.FT.p, FT[b], 6 * (size_t)c.M * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+      SysBuf& sb = c.hi.sb(0);
+      launch_rhs(ctx->stream, c.ctr.p, c.FT.p, nullptr, c.hi.off.p, c.hi.n, c.M, c.hi.N, c.a, c.mu, c.cfg.slip_speed,
+                 sb.rhs.p);
+      sys.push_back(SysRef{&c, &c.hi, 0, sb.rhs.p, sb.x.p, c.hi.tol});
+    }
+    pqn_mvp_stats st{};
+    ctx->solve_lockstep(sys, &st);
+    for (int b = 0; b < nb; ++b) {
+      pqn_ctx_impl& c = *ctx->children[b];
+      Work& w = c.hi.wk(0);
+      launch_moments(ctx->stream, c.hi.sb(0).x.p, c.hi.off.p, c.hi.w.p, c.hi.n, c.M, c.hi.N, w.mom.p);
+      launch_rigid_velocity(ctx->stream, w.mom.p, c.M, c.a, c.UO.p);
+      HIPCHK(hipMemcpyAsync(UO[b], c.UO.p, 6 * (size_t)c.M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    st.t_far_ms = ctx->end_far_timing();
+    st.matvecs = ctx->n_matvec;
+    st.n_far = ctx->n_far;
+    st.t_total_ms = tm.ms();
+    if (stats) *stats = st;
+    return st.converged ? PQN_OK : PQN_WARN_NOT_CONVERGED;
+  });
+}
+
+pqn_status pqn_mobility_apply_multi(pqn_ctx* ctx, int32_t k_rhs, const double* FT, double* UO, int32_t fidelity,
+                                    pqn_mvp_stats* stats) {
+  return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_mobility_apply_multi needs a single-suspension context");
+    if (!ctx || !FT || !UO || k_rhs < 1 || k_rhs > kMaxRhs)
+      return fail(PQN_ERR_INVALID, "pqn_mobility_apply_multi: bad argument (1 <= k_rhs <= 6)");
+    for (int k = 0; k < 6 * ctx->M * k_rhs; ++k)
+      if (!std::isfinite(FT[k])) return fail(PQN_ERR_NUMERIC, "non-finite force/torque");
+    HIPCHK(hipSetDevice(ctx->device));
+    Timer tm;
+    Level& lv = ctx->level(fidelity);
+    const size_t m6 = 6 * (size_t)ctx->M;
+    HIPCHK(hipMemcpyAsync(ctx->FT.p, FT, k_rhs * m6 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    const double* fp[kMaxRhs];
+    double* up[kMaxRhs];
+    for (int r = 0; r < k_rhs; ++r) {
+      fp[r] = ctx->FT.p + r * m6;
+      up[r] = ctx->UO.p + r * m6;
+    }
+    ctx->n_matvec = 0;
+    ctx->n_far = 0;
+    pqn_mvp_stats st{};
+    ctx->mobility_multi(lv, k_rhs, fp, nullptr, up, &st);
+    HIPCHK(hipMemcpyAsync(UO, ctx->UO.p, k_rhs * m6 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    st.t_far_ms = ctx->end_far_timing();
+    st.matvecs = ctx->n_matvec;
+    st.n_far = ctx->n_far;
+    st.t_total_ms = tm.ms();
+    if (stats) *stats = st;
+    return st.converged ? PQN_OK : PQN_WARN_NOT_CONVERGED;
   });
 }
 
@@ -89,13 +221,14 @@ pqn_status pqn_destroy(pqn_ctx* ctx) {
   return guarded([&]() -> pqn_status {
     HIPCHK(hipSetDevice(ctx->device));
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    delete ctx;
+    delete static_cast<pqn_ctx_impl*>(ctx);
     return PQN_OK;
   });
 }
 
 pqn_status pqn_set_state(pqn_ctx* ctx, const double* centers, const double* janus_axes) {
   return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_set_state needs a single-suspension context");
     if (!ctx || !centers) return fail(PQN_ERR_INVALID, "pqn_set_state: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
     ctx->set_configuration(centers, janus_axes ? janus_axes : (ctx->has_axes ? ctx->axes.data() : nullptr));
@@ -104,6 +237,7 @@ pqn_status pqn_set_state(pqn_ctx* ctx, const double* centers, const double* janu
 }
 
 pqn_status pqn_get_state(const pqn_ctx* ctx, double* centers, double* janus_axes) {
+  if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_get_state needs a single-suspension context");
   if (!ctx) return fail(PQN_ERR_INVALID, "pqn_get_state: NULL context");
   if (centers) std::memcpy(centers, ctx->centers.data(), ctx->centers.size() * sizeof(double));
   if (janus_axes) std::memcpy(janus_axes, ctx->axes.data(), ctx->axes.size() * sizeof(double));
@@ -111,6 +245,7 @@ pqn_status pqn_get_state(const pqn_ctx* ctx, double* centers, double* janus_axes
 }
 
 pqn_status pqn_set_precision(pqn_ctx* ctx, int32_t precision) {
+  if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_set_precision needs a single-suspension context");
   if (!ctx) return fail(PQN_ERR_INVALID, "NULL context");
   if (precision != PQN_FP64 && precision != PQN_MIXED) return fail(PQN_ERR_INVALID, "bad precision");
   ctx->cfg.precision = precision;
@@ -137,6 +272,7 @@ static pqn_status mobility_common(pqn_ctx* ctx, const double* FT_dev, const doub
 pqn_status pqn_mobility_apply_dev(pqn_ctx* ctx, const double* FT_dev, double* UO_dev, int32_t fidelity,
                                   pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_mobility_apply_dev needs a single-suspension context");
     if (!ctx || !FT_dev || !UO_dev) return fail(PQN_ERR_INVALID, "pqn_mobility_apply_dev: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
     return mobility_common(ctx, FT_dev, nullptr, UO_dev, fidelity, stats);
@@ -145,6 +281,7 @@ pqn_status pqn_mobility_apply_dev(pqn_ctx* ctx, const double* FT_dev, double* UO
 
 pqn_status pqn_mobility_apply(pqn_ctx* ctx, const double* FT, double* UO, int32_t fidelity, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_mobility_apply needs a single-suspension context");
     if (!ctx || !FT || !UO) return fail(PQN_ERR_INVALID, "pqn_mobility_apply: NULL argument");
     for (int k = 0; k < 6 * ctx->M; ++k)
       if (!std::isfinite(FT[k])) return fail(PQN_ERR_NUMERIC, "non-finite force/torque");
@@ -159,6 +296,7 @@ pqn_status pqn_mobility_apply(pqn_ctx* ctx, const double* FT, double* UO, int32_
 
 pqn_status pqn_nc_velocity(pqn_ctx* ctx, double* UO, int32_t fidelity, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_nc_velocity needs a single-suspension context");
     if (!ctx || !UO) return fail(PQN_ERR_INVALID, "pqn_nc_velocity: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
     if (!ctx->has_axes) {
@@ -175,13 +313,15 @@ pqn_status pqn_nc_velocity(pqn_ctx* ctx, double* UO, int32_t fidelity, pqn_mvp_s
 
 pqn_status pqn_bie_apply(pqn_ctx* ctx, int32_t fidelity, const double* q, double* y) {
   return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_bie_apply needs a single-suspension context");
     if (!ctx || !q || !y) return fail(PQN_ERR_INVALID, "pqn_bie_apply: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
     Level& lv = ctx->level(fidelity);
     const size_t len = 3 * (size_t)lv.N;
-    HIPCHK(hipMemcpyAsync(lv.rhs.p, q, len * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    ctx->apply_operator(lv, ctx->cfg.precision, lv.rhs.p, lv.tmp.p);
-    HIPCHK(hipMemcpyAsync(y, lv.tmp.p, len * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    SysBuf& b = lv.sb(0);
+    HIPCHK(hipMemcpyAsync(b.rhs.p, q, len * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    ctx->apply_operator(lv, ctx->cfg.precision, b.rhs.p, b.tmp.p);
+    HIPCHK(hipMemcpyAsync(y, b.tmp.p, len * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->end_far_timing();
     return PQN_OK;
@@ -190,6 +330,7 @@ pqn_status pqn_bie_apply(pqn_ctx* ctx, int32_t fidelity, const double* q, double
 
 pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, double* q, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_bie_solve needs a single-suspension context");
     if (!ctx || !rhs || !q) return fail(PQN_ERR_INVALID, "pqn_bie_solve: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
     Timer tm;
@@ -197,10 +338,12 @@ pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, doub
     const size_t len = 3 * (size_t)lv.N;
     ctx->n_matvec = 0;
     ctx->n_far = 0;
-    HIPCHK(hipMemcpyAsync(lv.rhs.p, rhs, len * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    SysBuf& b = lv.sb(0);
+    HIPCHK(hipMemcpyAsync(b.rhs.p, rhs, len * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     pqn_mvp_stats st{};
-    ctx->solve(lv, lv.rhs.p, lv.x.p, &st);
-    HIPCHK(hipMemcpyAsync(q, lv.x.p, len * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<SysRef> sys{SysRef{ctx, &lv, 0, b.rhs.p, b.x.p, lv.tol}};
+    ctx->solve_lockstep(sys, &st);
+    HIPCHK(hipMemcpyAsync(q, b.x.p, len * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     st.t_far_ms = ctx->end_far_timing();
     st.matvecs = ctx->n_matvec;
@@ -213,6 +356,7 @@ pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, doub
 
 pqn_status pqn_get_self_block(pqn_ctx* ctx, int32_t fidelity, double* S) {
   return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_get_self_block needs a single-suspension context");
     if (!ctx || !S) return fail(PQN_ERR_INVALID, "pqn_get_self_block: NULL argument");
     Level& lv = ctx->level(fidelity);
     std::memcpy(S, lv.tab.S.data(), lv.tab.S.size() * sizeof(double));
@@ -222,6 +366,7 @@ pqn_status pqn_get_self_block(pqn_ctx* ctx, int32_t fidelity, double* S) {
 
 pqn_status pqn_get_grid(pqn_ctx* ctx, int32_t fidelity, int32_t* n_nodes, double* offsets, double* weights) {
   return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_get_grid needs a single-suspension context");
     if (!ctx) return fail(PQN_ERR_INVALID, "pqn_get_grid: NULL context");
     Level& lv = ctx->level(fidelity);
     if (n_nodes) *n_nodes = lv.n;
@@ -246,6 +391,7 @@ pqn_status pqn_host_self_block(int32_t n_theta, int32_t n_phi, double radius, do
 
 pqn_status pqn_find_contacts(pqn_ctx* ctx, double delta, int32_t cap, int32_t* n_out, int32_t* pairs, double* gaps) {
   return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_find_contacts needs a single-suspension context");
     if (!ctx || !n_out || (cap > 0 && (!pairs || !gaps)) || cap < 0)
       return fail(PQN_ERR_INVALID, "pqn_find_contacts: bad argument");
     HIPCHK(hipSetDevice(ctx->device));
@@ -260,6 +406,7 @@ pqn_status pqn_find_contacts(pqn_ctx* ctx, double delta, int32_t cap, int32_t* n
 pqn_status pqn_lcp_apply(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const double* x, double* Ax,
                          int32_t fidelity) {
   return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_lcp_apply needs a single-suspension context");
     if (!ctx || n < 0 || (n > 0 && (!pairs || !x || !Ax))) return fail(PQN_ERR_INVALID, "pqn_lcp_apply: bad argument");
     HIPCHK(hipSetDevice(ctx->device));
     lcp_check_pairs(*ctx, n, pairs);
@@ -270,6 +417,7 @@ pqn_status pqn_lcp_apply(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const do
 pqn_status pqn_lcp_solve(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const double* b, double* x, int32_t solver,
                          const pqn_lcp_opts* opts, pqn_lcp_stats* stats) {
   return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_lcp_solve needs a single-suspension context");
     if (!ctx || n < 0 || (n > 0 && (!pairs || !b || !x))) return fail(PQN_ERR_INVALID, "pqn_lcp_solve: bad argument");
     if (solver != PQN_BBPGD && solver != PQN_MONO && solver != PQN_BI) return fail(PQN_ERR_INVALID, "bad solver");
     if (solver == PQN_BI && !ctx->has_lo) return fail(PQN_ERR_STATE, "Bi-PQN needs a low-fidelity grid");
@@ -282,6 +430,7 @@ pqn_status pqn_lcp_solve(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const do
 pqn_status pqn_step(pqn_ctx* ctx, double dt, double delta, int32_t solver, const pqn_lcp_opts* opts,
                     pqn_step_stats* stats) {
   return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_step needs a single-suspension context");
     if (!ctx || !(dt > 0.0) || !std::isfinite(delta)) return fail(PQN_ERR_INVALID, "pqn_step: bad argument");
     if (solver != PQN_BBPGD && solver != PQN_MONO && solver != PQN_BI) return fail(PQN_ERR_INVALID, "bad solver");
     if (solver == PQN_BI && !ctx->has_lo) return fail(PQN_ERR_STATE, "Bi-PQN needs a low-fidelity grid");

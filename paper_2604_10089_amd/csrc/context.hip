@@ -1,4 +1,5 @@
-// Context set-up, the discrete BIE operator, GMRES and the mobility product.
+// Context set-up, the discrete BIE operator on groups of densities, lockstep
+// GMRES and the mobility product.
 #include "context.hpp"
 
 #include <algorithm>
@@ -6,9 +7,41 @@
 
 namespace bipqn {
 
+Work& Level::wk(int k) {
+  while ((int)work.size() <= k) work.emplace_back(new Work());
+  Work& w = *work[k];
+  if (!w.far_part.p) {
+    w.far_part.alloc((size_t)nchunks * 3 * N);
+    w.near_part.alloc((size_t)kMaxNear * 3 * N);
+    w.coef.alloc((size_t)3 * M * L);
+    w.qup.alloc((size_t)3 * M * nup);
+    w.selfo.alloc((size_t)9 * N);
+    w.mom.alloc((size_t)6 * M);
+  }
+  return w;
+}
+
+SysBuf& Level::sb(int k) {
+  while ((int)sys.size() <= k) sys.emplace_back(new SysBuf());
+  SysBuf& b = *sys[k];
+  if (!b.V.p) {
+    const size_t len = 3 * (size_t)N;
+    b.V.alloc((size_t)(restart + 1) * len);
+    b.x.alloc(len);
+    b.r.alloc(len);
+    b.rhs.alloc(len);
+    b.tmp.alloc(len);
+    b.d.alloc(len);
+    b.partial.alloc((size_t)nb_dots * (restart + 1));
+    b.ycoef.alloc((size_t)restart + 1);
+  }
+  return b;
+}
+
 pqn_ctx_impl::~pqn_ctx_impl() {
   lcp_release(lcp);
   lcp = nullptr;
+  children.clear();
   for (auto& e : ev_pool) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -41,28 +74,12 @@ void pqn_ctx_impl::setup_level(Level& lv, int nt, int np, double tol) {
   nch = std::min(nch, M);
   lv.spc = (M + nch - 1) / nch;
   lv.nchunks = (M + lv.spc - 1) / lv.spc;
-  lv.src32.alloc(2 * (size_t)N);
-  lv.src64.alloc(4 * (size_t)N);
-  lv.far_part.alloc((size_t)lv.nchunks * 3 * N);
-  lv.near_part.alloc((size_t)kMaxNear * 3 * N);
-  lv.coef.alloc((size_t)3 * M * lv.L);
-  lv.qup.alloc((size_t)3 * M * lv.nup);
-  lv.selfo.alloc((size_t)9 * N);
-  lv.mom.alloc((size_t)6 * M);
+  lv.src.alloc((size_t)N * src64_stride(kMaxRhs));
   lv.restart = cfg.gmres_restart;
   lv.max_iter = cfg.gmres_max_iter;
   lv.tol = tol;
   const size_t len = 3 * (size_t)N;
-  lv.V.alloc((size_t)(lv.restart + 1) * len);
-  lv.x.alloc(len);
-  lv.r.alloc(len);
-  lv.rhs.alloc(len);
-  lv.tmp.alloc(len);
-  lv.d.alloc(len);
   lv.nb_dots = (int)std::min<long>(256, std::max<long>(1, (long)(len / 2048)));
-  lv.partial.alloc((size_t)lv.nb_dots * (lv.restart + 1));
-  lv.h.alloc(4 * (size_t)(lv.restart + 2));
-  lv.ycoef.alloc((size_t)lv.restart + 1);
 }
 
 void pqn_ctx_impl::set_configuration(const double* c, const double* ax) {
@@ -105,12 +122,12 @@ void pqn_ctx_impl::set_configuration(const double* c, const double* ax) {
       nl.push_back(s);
     }
   n_near = (int)nl.size() / 3;
-  near_list.upload(nl.data(), nl.size(), stream);
   ctr.upload(centers.data(), centers.size(), stream);
   dax.upload(axes.data(), axes.size(), stream);
   cls.upload(hc.data(), hc.size(), stream);
   partners.upload(h_partners.data(), h_partners.size(), stream);
   npart.upload(h_npart.data(), h_npart.size(), stream);
+  near_list.upload(nl.data(), nl.size(), stream);
   HIPCHK(hipStreamSynchronize(stream));
 }
 
@@ -125,6 +142,12 @@ void pqn_ctx_impl::begin_far_timing() {
   HIPCHK(hipEventRecord(ev_pool[ev_used].first, stream));
 }
 
+void pqn_ctx_impl::end_far_launch() {
+  if (!cfg.profile) return;
+  HIPCHK(hipEventRecord(ev_pool[ev_used].second, stream));
+  ++ev_used;
+}
+
 double pqn_ctx_impl::end_far_timing() {
   // called after the stream has been synchronised: sums and recycles the events
   double t = 0.0;
@@ -137,184 +160,372 @@ double pqn_ctx_impl::end_far_timing() {
   return t;
 }
 
-// y = (1/2 I + D + P) q on the level's grid; q, y device [3][N].
-void pqn_ctx_impl::apply_operator(Level& lv, int precision, const double* q, double* y) {
-  const int n = lv.n, N = lv.N, L = lv.L, nup = lv.nup;
+// y_r = (1/2 I + D + P) q_r for every density of every group.
+void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
   hipStream_t s = stream;
-  const double scale = 3.0 / (4.0 * kPi * a);
-  // harmonic coefficients of every sphere's density (per component): coef = T q
-  launch_gemm64(s, L, M, n, lv.T.p, n, 0, q, N, n, 0, n, lv.coef.p, (long)M * L, L, 0, L, 3);
-  // singular self interaction on the coefficients, one partial per source component d:
-  // self_d = G[:, d block] coef_d
-  launch_gemm64(s, 3 * n, M, L, lv.G.p, 3 * L, L, lv.coef.p, (long)M * L, L, 0, L, lv.selfo.p, 3L * N, n, N, n, 3);
-  if (n_near > 0)   // density on the upsampled grid of every sphere: qup = Yup coef
-    launch_gemm64(s, nup, M, L, lv.Yup.p, L, 0, lv.coef.p, (long)M * L, L, 0, L, lv.qup.p, (long)M * nup, nup, 0,
-                  nup, 3);
+  const int prec = precision == PQN_MIXED ? 1 : 0;
+  bool all_single = groups.size() > 1;
+  for (MvGroup& gr : groups) {
+    Level& lv = *gr.lv;
+    pqn_ctx_impl& c = *gr.c;
+    const int n = lv.n, N = lv.N, L = lv.L, nup = lv.nup, M = lv.M;
+    QPtrs qp{};
+    for (int r = 0; r < gr.K; ++r) {
+      Work& w = lv.wk(gr.slot0 + r);
+      // harmonic coefficients of every sphere's density (per component): coef = T q
+      launch_gemm64(s, L, M, n, lv.T.p, n, 0, gr.in[r], N, n, 0, n, w.coef.p, (long)M * L, L, 0, L, 3);
+      // singular self interaction on the coefficients, one partial per source component
+      launch_gemm64(s, 3 * n, M, L, lv.G.p, 3 * L, L, w.coef.p, (long)M * L, L, 0, L, w.selfo.p, 3L * N, n, N, n,
+                    3);
+      if (c.n_near > 0)  // density on the upsampled grid of every sphere: qup = Yup coef
+        launch_gemm64(s, nup, M, L, lv.Yup.p, L, 0, w.coef.p, (long)M * L, L, 0, L, w.qup.p, (long)M * nup, nup, 0,
+                      nup, 3);
+      qp.p[r] = gr.in[r];
+    }
+    launch_pack(s, prec, gr.K, qp, lv.off.p, lv.w.p, n, N, lv.src.p);
+    if (gr.K != 1) all_single = false;
+  }
   begin_far_timing();
-  if (precision == PQN_MIXED) {
-    launch_pack32(s, q, lv.off.p, lv.w.p, n, N, lv.src32.p);
-    launch_far32(s, lv.tpt, lv.src32.p, lv.off.p, ctr.p, cls.p, n, M, N, lv.spc, lv.nchunks, scale, lv.far_part.p);
+  if (all_single) {
+    // every suspension's far pair sum in one launch, largest tiles first
+    struct Item {
+      FarDesc d;
+      long cost;
+    };
+    std::vector<Item> items;
+    const int tpt = cfg.targets_per_thread == 1 ? 1 : 2;
+    for (MvGroup& gr : groups) {
+      Level& lv = *gr.lv;
+      FarDesc d{};
+      d.src = lv.src.p;
+      d.off = lv.off.p;
+      d.ctr = gr.c->ctr.p;
+      d.cls = gr.c->cls.p;
+      d.part = lv.wk(gr.slot0).far_part.p;
+      d.n = lv.n;
+      d.M = lv.M;
+      d.N = lv.N;
+      d.spc = lv.spc;
+      d.ntb = prec == 1 ? (lv.N + 256 * tpt - 1) / (256 * tpt) : (lv.N + 255) / 256;
+      d.scale = 3.0 / (4.0 * kPi * gr.c->a);
+      items.push_back({d, (long)lv.n * lv.n * lv.spc});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+    std::vector<FarDesc> ds;
+    int total = 0;
+    for (Item& it : items) {
+      it.d.item0 = total;
+      total += it.d.ntb * ((it.d.M + it.d.spc - 1) / it.d.spc);
+      ds.push_back(it.d);
+    }
+    fdesc.upload(ds.data(), ds.size(), s);
+    launch_far_multi(s, prec, tpt, fdesc.p, (int)ds.size(), total);
   } else {
-    launch_pack64(s, q, lv.off.p, lv.w.p, n, N, lv.src64.p);
-    launch_far64(s, lv.src64.p, lv.off.p, ctr.p, cls.p, n, M, N, lv.spc, lv.nchunks, scale, lv.far_part.p);
+    for (MvGroup& gr : groups) {
+      Level& lv = *gr.lv;
+      OPtrs op{};
+      for (int r = 0; r < gr.K; ++r) op.p[r] = lv.wk(gr.slot0 + r).far_part.p;
+      launch_far(s, prec, gr.K, lv.tpt, lv.src.p, lv.off.p, gr.c->ctr.p, gr.c->cls.p, lv.n, lv.M, lv.N, lv.spc,
+                 lv.nchunks, 3.0 / (4.0 * kPi * gr.c->a), op);
+    }
   }
-  if (cfg.profile) {
-    HIPCHK(hipEventRecord(ev_pool[ev_used].second, s));
-    ++ev_used;
-  }
+  end_far_launch();
   ++n_far;
-  launch_near64p(s, n_near, ctr.p, lv.off.p, lv.offup.p, lv.qup.p, lv.coef.p, near_list.p, n, M, N, nup, lv.p, L,
-                 scale, lv.near_part.p);
-  launch_moments(s, q, lv.off.p, lv.w.p, n, M, N, lv.mom.p);
-  launch_combine(s, q, lv.selfo.p, 3, lv.far_part.p, lv.nchunks, lv.near_part.p, npart.p, lv.mom.p, lv.off.p, n, N,
-                 a, y);
+  for (MvGroup& gr : groups) {
+    Level& lv = *gr.lv;
+    pqn_ctx_impl& c = *gr.c;
+    QPtrs qu{}, cf{};
+    OPtrs np{};
+    for (int r = 0; r < gr.K; ++r) {
+      Work& w = lv.wk(gr.slot0 + r);
+      qu.p[r] = w.qup.p;
+      cf.p[r] = w.coef.p;
+      np.p[r] = w.near_part.p;
+    }
+    launch_near(s, gr.K, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, qu, cf, c.near_list.p, lv.n, lv.M, lv.N, lv.nup,
+                lv.p, lv.L, 3.0 / (4.0 * kPi * c.a), np);
+    for (int r = 0; r < gr.K; ++r) {
+      Work& w = lv.wk(gr.slot0 + r);
+      launch_moments(s, gr.in[r], lv.off.p, lv.w.p, lv.n, lv.M, lv.N, w.mom.p);
+      launch_combine(s, gr.in[r], w.selfo.p, 3, w.far_part.p, lv.nchunks, w.near_part.p, c.npart.p, w.mom.p,
+                     lv.off.p, lv.n, lv.N, c.a, gr.out[r]);
+    }
+    n_matvec += gr.K;
+  }
   HIPCHK(hipGetLastError());
-  ++n_matvec;
+}
+
+void pqn_ctx_impl::apply_operator(Level& lv, int precision, const double* q, double* y) {
+  std::vector<MvGroup> g(1);
+  g[0] = MvGroup{this, &lv, 1, 0, {q}, {y}};
+  matvec_groups(g, precision);
 }
 
 double pqn_ctx_impl::dot_host(const double* x, const double* y, long len, Level& lv) {
-  launch_dots(stream, x, len, 1, y, len, lv.nb_dots, lv.partial.p, lv.h.p);
+  SysBuf& b = lv.sb(0);
+  hdev.alloc(4);
+  launch_dots(stream, x, len, 1, y, len, lv.nb_dots, b.partial.p, hdev.p);
   double v = 0.0;
-  HIPCHK(hipMemcpyAsync(&v, lv.h.p, sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(&v, hdev.p, sizeof(double), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
   return v;
 }
 
-// Restarted GMRES(m): classical Gram-Schmidt with one reorthogonalisation
-// (CGS2) in FP64 on the device, Givens rotations and the small least-squares
-// problem on the host. x is overwritten (initial guess 0).
-int pqn_ctx_impl::gmres(Level& lv, int precision, const double* rhs, double* x, double tol, double* relres,
-                        bool* conv) {
-  const long len = 3L * lv.N;
-  const int m = lv.restart;
+namespace {
+struct GmState {
+  std::vector<double> H, cs, sn, g;
+  double bnorm = 0.0;
+  int k = 0;
+  bool active = false, restart = false;
+};
+}  // namespace
+
+// Restarted GMRES(m) on many systems in lockstep: every iteration applies the
+// operator to all active systems at once (one joint launch of the pair sums)
+// and reads back all Hessenberg columns in one copy. Per system: classical
+// Gram-Schmidt with one reorthogonalisation (CGS2) in FP64 on the device,
+// Givens rotations on the host; restarts from the true residual.
+void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
+  const int ns = (int)sys.size();
+  if (ns == 0) return;
+  const int m = sys[0].lv->restart;
+  const int hs = 2 * (m + 1) + 2;
+  hdev.alloc((size_t)ns * hs);
+  hhost.assign((size_t)ns * hs, 0.0);
   hipStream_t s = stream;
-  double* V = lv.V.p;
-  const double bnorm = std::sqrt(dot_host(rhs, rhs, len, lv));
-  if (!std::isfinite(bnorm)) throw Error(PQN_ERR_NUMERIC, "non-finite right-hand side");
-  launch_scale_copy(s, x, rhs, 0.0, len);  // x = 0 (rhs finite)
-  *conv = true;
-  *relres = 0.0;
-  if (bnorm == 0.0) return 0;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hbuf(2 * (m + 1) + 1);
-  int its = 0;
-  double beta = bnorm;
-  const double* r0 = rhs;
+  std::vector<GmState> st(ns);
+  auto len_of = [&](int i) { return 3L * sys[i].lv->N; };
+  auto readback = [&]() {
+    HIPCHK(hipMemcpyAsync(hhost.data(), hdev.p, (size_t)ns * hs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  };
+  auto nrm_slot = [&](int i) { return hdev.p + (size_t)i * hs + 2 * (m + 1); };
+  // right-hand side norms
+  for (int i = 0; i < ns; ++i) {
+    SysBuf& b = sys[i].lv->sb(sys[i].slot);
+    launch_dots(s, sys[i].rhs, len_of(i), 1, sys[i].rhs, len_of(i), sys[i].lv->nb_dots, b.partial.p, nrm_slot(i));
+  }
+  readback();
+  auto start_cycle = [&](int i, const double* r0, double beta) {
+    SysBuf& b = sys[i].lv->sb(sys[i].slot);
+    launch_scale_copy(s, b.V.p, r0, 1.0 / beta, len_of(i));
+    GmState& g = st[i];
+    g.H.assign((size_t)(m + 1) * m, 0.0);
+    g.cs.assign(m, 0.0);
+    g.sn.assign(m, 0.0);
+    g.g.assign(m + 1, 0.0);
+    g.g[0] = beta;
+    g.k = 0;
+    g.active = true;
+    g.restart = false;
+  };
+  for (int i = 0; i < ns; ++i) {
+    const double bn = std::sqrt(std::max(0.0, hhost[(size_t)i * hs + 2 * (m + 1)]));
+    if (!std::isfinite(bn)) throw Error(PQN_ERR_NUMERIC, "non-finite right-hand side");
+    st[i].bnorm = bn;
+    launch_scale_copy(s, sys[i].x, sys[i].rhs, 0.0, len_of(i));  // x = 0 (rhs finite)
+    sys[i].its = 0;
+    sys[i].relres = 0.0;
+    sys[i].conv = true;
+    if (bn > 0.0) {
+      sys[i].conv = false;
+      start_cycle(i, sys[i].rhs, bn);
+    }
+  }
+  auto build_groups = [&](const std::vector<int>& idx, bool use_x) {
+    std::vector<MvGroup> groups;
+    for (int i : idx) {
+      SysBuf& b = sys[i].lv->sb(sys[i].slot);
+      const double* in = use_x ? sys[i].x : b.V.p + (size_t)st[i].k * len_of(i);
+      double* out = use_x ? b.r.p : b.V.p + (size_t)(st[i].k + 1) * len_of(i);
+      MvGroup* g = nullptr;
+      for (MvGroup& gg : groups)
+        if (gg.c == sys[i].c && gg.lv == sys[i].lv && gg.K < kMaxRhs && gg.slot0 + gg.K == sys[i].slot) g = &gg;
+      if (!g) {
+        groups.push_back(MvGroup{sys[i].c, sys[i].lv, 0, sys[i].slot, {}, {}});
+        g = &groups.back();
+      }
+      g->in[g->K] = in;
+      g->out[g->K] = out;
+      ++g->K;
+    }
+    return groups;
+  };
   for (;;) {
-    launch_scale_copy(s, V, r0, 1.0 / beta, len);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int k = 0, done_k = 0;
-    bool stop = false;
-    for (k = 0; k < m; ++k) {
-      double* vk = V + (size_t)k * len;
-      double* w = V + (size_t)(k + 1) * len;
-      apply_operator(lv, precision, vk, w);
+    std::vector<int> act;
+    for (int i = 0; i < ns; ++i)
+      if (st[i].active) act.push_back(i);
+    if (act.empty()) break;
+    std::vector<MvGroup> groups = build_groups(act, false);
+    matvec_groups(groups, precision);
+    for (int i : act) {
+      SysBuf& b = sys[i].lv->sb(sys[i].slot);
+      const long len = len_of(i);
+      const int k = st[i].k;
+      double* w = b.V.p + (size_t)(k + 1) * len;
+      double* hp = hdev.p + (size_t)i * hs;
       for (int pass = 0; pass < 2; ++pass) {
-        double* hp = lv.h.p + pass * (m + 1);
-        launch_dots(s, V, len, k + 1, w, len, lv.nb_dots, lv.partial.p, hp);
-        launch_combo(s, w, 1.0, V, len, k + 1, hp, -1.0, len);
+        launch_dots(s, b.V.p, len, k + 1, w, len, sys[i].lv->nb_dots, b.partial.p, hp + pass * (m + 1));
+        launch_combo(s, w, 1.0, b.V.p, len, k + 1, hp + pass * (m + 1), -1.0, len);
       }
-      launch_dots(s, w, len, 1, w, len, lv.nb_dots, lv.partial.p, lv.h.p + 2 * (m + 1));
-      HIPCHK(hipMemcpyAsync(hbuf.data(), lv.h.p, (2 * (m + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      ++its;
-      for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = hbuf[i] + hbuf[m + 1 + i];
-      const double hn = std::sqrt(std::max(0.0, hbuf[2 * (m + 1)]));
+      launch_dots(s, w, len, 1, w, len, sys[i].lv->nb_dots, b.partial.p, hp + 2 * (m + 1));
+    }
+    readback();
+    std::vector<int> need_restart;
+    for (int i : act) {
+      GmState& g = st[i];
+      SysRef& sr = sys[i];
+      SysBuf& b = sr.lv->sb(sr.slot);
+      const long len = len_of(i);
+      const int k = g.k;
+      const double* hb = &hhost[(size_t)i * hs];
+      ++sr.its;
+      for (int r = 0; r <= k; ++r) g.H[(size_t)r * m + k] = hb[r] + hb[m + 1 + r];
+      const double hn = std::sqrt(std::max(0.0, hb[2 * (m + 1)]));
       if (!std::isfinite(hn)) throw Error(PQN_ERR_NUMERIC, "non-finite value in GMRES");
-      H[(size_t)(k + 1) * m + k] = hn;
-      if (hn > 0.0) launch_scale_copy(s, w, w, 1.0 / hn, len);
-      for (int i = 0; i < k; ++i) {
-        const double t0 = cs[i] * H[(size_t)i * m + k] + sn[i] * H[(size_t)(i + 1) * m + k];
-        H[(size_t)(i + 1) * m + k] = -sn[i] * H[(size_t)i * m + k] + cs[i] * H[(size_t)(i + 1) * m + k];
-        H[(size_t)i * m + k] = t0;
+      g.H[(size_t)(k + 1) * m + k] = hn;
+      for (int r = 0; r < k; ++r) {
+        const double t0 = g.cs[r] * g.H[(size_t)r * m + k] + g.sn[r] * g.H[(size_t)(r + 1) * m + k];
+        g.H[(size_t)(r + 1) * m + k] = -g.sn[r] * g.H[(size_t)r * m + k] + g.cs[r] * g.H[(size_t)(r + 1) * m + k];
+        g.H[(size_t)r * m + k] = t0;
       }
-      const double den = std::hypot(H[(size_t)k * m + k], H[(size_t)(k + 1) * m + k]);
+      const double den = std::hypot(g.H[(size_t)k * m + k], g.H[(size_t)(k + 1) * m + k]);
       if (!(den > 0.0)) throw Error(PQN_ERR_NUMERIC, "GMRES breakdown: zero Hessenberg column");
-      cs[k] = H[(size_t)k * m + k] / den;
-      sn[k] = H[(size_t)(k + 1) * m + k] / den;
-      H[(size_t)k * m + k] = den;
-      H[(size_t)(k + 1) * m + k] = 0.0;
-      g[k + 1] = -sn[k] * g[k];
-      g[k] = cs[k] * g[k];
-      done_k = k + 1;
-      *relres = std::fabs(g[k + 1]) / bnorm;
-      if (std::fabs(g[k + 1]) <= tol * bnorm || hn == 0.0) {
-        stop = true;
-        break;
+      g.cs[k] = g.H[(size_t)k * m + k] / den;
+      g.sn[k] = g.H[(size_t)(k + 1) * m + k] / den;
+      g.H[(size_t)k * m + k] = den;
+      g.H[(size_t)(k + 1) * m + k] = 0.0;
+      g.g[k + 1] = -g.sn[k] * g.g[k];
+      g.g[k] = g.cs[k] * g.g[k];
+      sr.relres = std::fabs(g.g[k + 1]) / g.bnorm;
+      const bool conv = std::fabs(g.g[k + 1]) <= sr.tol * g.bnorm || hn == 0.0;
+      const bool full = (k + 1 == m) || sr.its >= sr.lv->max_iter;
+      if (!conv && !full) {
+        launch_scale_copy(s, b.V.p + (size_t)(k + 1) * len, b.V.p + (size_t)(k + 1) * len, 1.0 / hn, len);
+        g.k = k + 1;
+        continue;
       }
-      if (its >= lv.max_iter) break;
+      // end of cycle: y = H^{-1} g (upper triangular), x += V y
+      const int dk = k + 1;
+      std::vector<double> y(dk);
+      for (int r = dk - 1; r >= 0; --r) {
+        double v = g.g[r];
+        for (int c2 = r + 1; c2 < dk; ++c2) v -= g.H[(size_t)r * m + c2] * y[c2];
+        y[r] = v / g.H[(size_t)r * m + r];
+      }
+      HIPCHK(hipMemcpyAsync(b.ycoef.p, y.data(), dk * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_combo(s, sr.x, 1.0, b.V.p, len, dk, b.ycoef.p, 1.0, len);
+      g.active = false;
+      if (conv) {
+        sr.conv = true;
+      } else if (sr.its >= sr.lv->max_iter) {
+        sr.conv = false;
+      } else {
+        need_restart.push_back(i);
+      }
     }
-    // y = H^{-1} g (upper triangular), x += V y
-    std::vector<double> y(done_k);
-    for (int i = done_k - 1; i >= 0; --i) {
-      double v = g[i];
-      for (int j = i + 1; j < done_k; ++j) v -= H[(size_t)i * m + j] * y[j];
-      y[i] = v / H[(size_t)i * m + i];
+    if (!need_restart.empty()) {
+      // true residual r = rhs - A x of the systems that exhausted a cycle
+      std::vector<MvGroup> rg = build_groups(need_restart, true);
+      matvec_groups(rg, precision);
+      for (int i : need_restart) {
+        SysBuf& b = sys[i].lv->sb(sys[i].slot);
+        launch_axpby(s, b.r.p, sys[i].rhs, 1.0, -1.0, len_of(i));
+        launch_dots(s, b.r.p, len_of(i), 1, b.r.p, len_of(i), sys[i].lv->nb_dots, b.partial.p, nrm_slot(i));
+      }
+      readback();
+      for (int i : need_restart) {
+        SysBuf& b = sys[i].lv->sb(sys[i].slot);
+        const double beta = std::sqrt(std::max(0.0, hhost[(size_t)i * hs + 2 * (m + 1)]));
+        sys[i].relres = beta / st[i].bnorm;
+        if (beta <= sys[i].tol * st[i].bnorm) {
+          sys[i].conv = true;
+        } else {
+          start_cycle(i, b.r.p, beta);
+        }
+      }
     }
-    HIPCHK(hipMemcpyAsync(lv.ycoef.p, y.data(), done_k * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_combo(s, x, 1.0, V, len, done_k, lv.ycoef.p, 1.0, len);
-    if (stop) {
-      *conv = true;
-      return its;
-    }
-    if (its >= lv.max_iter) {
-      *conv = false;
-      return its;
-    }
-    // restart from the true residual
-    apply_operator(lv, precision, x, lv.r.p);
-    launch_axpby(s, lv.r.p, rhs, 1.0, -1.0, len);  // r = rhs - A x
-    beta = std::sqrt(dot_host(lv.r.p, lv.r.p, len, lv));
-    *relres = beta / bnorm;
-    if (beta <= tol * bnorm) {
-      *conv = true;
-      return its;
-    }
-    r0 = lv.r.p;
   }
 }
 
-// Solve (1/2 + D + P) x = rhs in the context's precision. Mixed precision:
-// GMRES on the operator with FP32 far pair sums, then optional refinement
-// sweeps whose residual uses the FP64 operator.
-void pqn_ctx_impl::solve(Level& lv, const double* rhs, double* x, pqn_mvp_stats* st) {
-  const long len = 3L * lv.N;
-  double rel = 0.0;
-  bool conv = false;
+// Solve every system in the context's precision. Mixed precision: GMRES on the
+// operator with FP32 far pair sums, then optional refinement sweeps whose
+// residual uses the FP64 operator.
+void pqn_ctx_impl::solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st) {
   const int prec = cfg.precision;
-  int its = gmres(lv, prec, rhs, x, lv.tol, &rel, &conv);
+  gmres_lockstep(sys, prec);
+  int its = 0;
+  for (SysRef& r : sys) its += r.its;
   int sweeps = 0;
   if (prec == PQN_MIXED && cfg.refine_sweeps > 0) {
-    const double bnorm = std::sqrt(dot_host(rhs, rhs, len, lv));
-    for (int sw = 0; sw < cfg.refine_sweeps && bnorm > 0.0; ++sw) {
-      apply_operator(lv, PQN_FP64, x, lv.tmp.p);
-      launch_axpby(stream, lv.tmp.p, rhs, 1.0, -1.0, len);  // tmp = rhs - A64 x
-      const double rn = std::sqrt(dot_host(lv.tmp.p, lv.tmp.p, len, lv));
-      rel = rn / bnorm;
-      conv = rel <= lv.tol;
-      if (conv) break;
+    const int ns = (int)sys.size();
+    std::vector<double> bn(ns);
+    for (int i = 0; i < ns; ++i) {
+      const long len = 3L * sys[i].lv->N;
+      bn[i] = std::sqrt(dot_host(sys[i].rhs, sys[i].rhs, len, *sys[i].lv));
+    }
+    for (int sw = 0; sw < cfg.refine_sweeps; ++sw) {
+      std::vector<MvGroup> groups;
+      for (int i = 0; i < ns; ++i) {
+        SysBuf& b = sys[i].lv->sb(sys[i].slot);
+        groups.push_back(MvGroup{sys[i].c, sys[i].lv, 1, sys[i].slot, {sys[i].x}, {b.tmp.p}});
+      }
+      matvec_groups(groups, PQN_FP64);
+      std::vector<SysRef> corr;
+      std::vector<int> owner;
+      for (int i = 0; i < ns; ++i) {
+        SysBuf& b = sys[i].lv->sb(sys[i].slot);
+        const long len = 3L * sys[i].lv->N;
+        launch_axpby(stream, b.tmp.p, sys[i].rhs, 1.0, -1.0, len);  // tmp = rhs - A64 x
+        const double rn = std::sqrt(dot_host(b.tmp.p, b.tmp.p, len, *sys[i].lv));
+        sys[i].relres = bn[i] > 0.0 ? rn / bn[i] : 0.0;
+        sys[i].conv = sys[i].relres <= sys[i].tol;
+        if (!sys[i].conv && bn[i] > 0.0) {
+          corr.push_back(
+              SysRef{sys[i].c, sys[i].lv, sys[i].slot, b.tmp.p, b.d.p, std::min(0.5, sys[i].tol * bn[i] / rn)});
+          owner.push_back(i);
+        }
+      }
+      if (corr.empty()) break;
       ++sweeps;
-      // correction d for A_mixed d = tmp, to the tolerance that makes |r| <= tol |rhs|
-      double rel2 = 0.0;
-      bool c2 = false;
-      its += gmres(lv, prec, lv.tmp.p, lv.d.p, std::min(0.5, lv.tol * bnorm / rn), &rel2, &c2);
-      launch_axpby(stream, x, lv.d.p, 1.0, 1.0, len);
+      gmres_lockstep(corr, prec);  // corrections d for A_mixed d = rhs - A64 x
+      for (size_t j = 0; j < corr.size(); ++j) {
+        its += corr[j].its;
+        const int i = owner[j];
+        launch_axpby(stream, sys[i].x, corr[j].x, 1.0, 1.0, 3L * sys[i].lv->N);
+      }
     }
   }
   if (st) {
     st->gmres_iters += its;
     st->refine_sweeps += sweeps;
-    st->rel_residual = rel;
+    double rr = 0.0;
+    bool conv = true;
+    for (SysRef& r : sys) {
+      rr = std::max(rr, r.relres);
+      conv = conv && r.conv;
+    }
+    st->rel_residual = rr;
     st->converged = conv ? 1 : 0;
   }
 }
 
-void pqn_ctx_impl::mobility(Level& lv, const double* FT_dev, const double* axes_dev, double* UO_dev,
-                            pqn_mvp_stats* st) {
-  launch_rhs(stream, ctr.p, FT_dev, axes_dev, lv.off.p, lv.n, M, lv.N, a, mu, cfg.slip_speed, lv.rhs.p);
-  solve(lv, lv.rhs.p, lv.x.p, st);
-  launch_moments(stream, lv.x.p, lv.off.p, lv.w.p, lv.n, M, lv.N, lv.mom.p);
-  launch_rigid_velocity(stream, lv.mom.p, M, a, UO_dev);
+void pqn_ctx_impl::mobility_multi(Level& lv, int K, const double* const* FT_dev, const double* axes_dev,
+                                  double* const* UO_dev, pqn_mvp_stats* st) {
+  if (K < 1 || K > kMaxRhs) throw Error(PQN_ERR_INVALID, "between 1 and 6 force sets per call");
+  std::vector<SysRef> sys;
+  for (int r = 0; r < K; ++r) {
+    SysBuf& b = lv.sb(r);
+    launch_rhs(stream, ctr.p, FT_dev ? FT_dev[r] : nullptr, axes_dev, lv.off.p, lv.n, M, lv.N, a, mu,
+               cfg.slip_speed, b.rhs.p);
+    sys.push_back(SysRef{this, &lv, r, b.rhs.p, b.x.p, lv.tol});
+  }
+  solve_lockstep(sys, st);
+  for (int r = 0; r < K; ++r) {
+    Work& w = lv.wk(r);
+    launch_moments(stream, lv.sb(r).x.p, lv.off.p, lv.w.p, lv.n, M, lv.N, w.mom.p);
+    launch_rigid_velocity(stream, w.mom.p, M, a, UO_dev[r]);
+  }
   HIPCHK(hipGetLastError());
 }
 

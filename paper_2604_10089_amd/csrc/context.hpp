@@ -1,5 +1,5 @@
 // Library context: device tables and buffers of both fidelity levels, the BIE
-// operator, GMRES and the mobility product.
+// operator on groups of densities, lockstep GMRES and the mobility product.
 #pragma once
 #include <chrono>
 #include <memory>
@@ -57,25 +57,59 @@ struct Timer {
   }
 };
 
+// Work buffers of one density (one right-hand side) on one level.
+struct Work {
+  DevArray<double> far_part, near_part, coef, qup, selfo, mom;
+};
+
+// Krylov storage of one linear system on one level.
+struct SysBuf {
+  DevArray<double> V, x, r, rhs, tmp, d, partial, ycoef;
+};
+
 struct Level {
   SphereTables tab;
   int M = 0, n = 0, N = 0, L = 0, nup = 0, p = 0;
   DevArray<double> off, w, G, T, Yup;
   DevArray<double4> offup;
-  // per-matvec work buffers
-  DevArray<float4> src32;
-  DevArray<double2> src64;
-  DevArray<double> far_part, near_part, coef, qup, selfo, mom;
+  DevArray<double> src;  // packed far sources, up to kMaxRhs densities (FP64 record is the larger)
   int nchunks = 1, spc = 1, tpt = 2;
-  // GMRES
   int restart = 50, max_iter = 500;
   double tol = 1e-8;
-  DevArray<double> V, x, r, rhs, tmp, d, partial, h, ycoef;
   int nb_dots = 128;
+  std::vector<std::unique_ptr<Work>> work;
+  std::vector<std::unique_ptr<SysBuf>> sys;
+  Work& wk(int k);
+  SysBuf& sb(int k);
 };
 
 struct LcpState;
 void lcp_release(LcpState* st);
+struct pqn_ctx_impl;
+
+// A group of K densities on one level of one context: K operator applications
+// that share the geometry pass of the pair sums.
+struct MvGroup {
+  pqn_ctx_impl* c;
+  Level* lv;
+  int K;
+  int slot0;  // work slots slot0 .. slot0+K-1
+  const double* in[kMaxRhs];
+  double* out[kMaxRhs];
+};
+
+// One linear system (1/2 + D + P) x = rhs in the lockstep GMRES engine.
+struct SysRef {
+  pqn_ctx_impl* c;
+  Level* lv;
+  int slot;
+  const double* rhs;
+  double* x;
+  double tol;
+  int its = 0;
+  double relres = 0.0;
+  bool conv = false;
+};
 
 struct pqn_ctx_impl {
   pqn_config_desc cfg{};
@@ -95,16 +129,22 @@ struct pqn_ctx_impl {
   int max_slots = 0, n_near = 0;
   std::vector<int> h_partners, h_npart;
   DevArray<double> FT, UO;
+  // lockstep GMRES scratch: per-system Hessenberg columns, read back in one copy
+  DevArray<double> hdev;
+  std::vector<double> hhost;
+  DevArray<FarDesc> fdesc;
   // profiling of far launches
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   size_t ev_used = 0;
-  // counters of the current call
   int n_matvec = 0, n_far = 0;
-  // LCP workspaces (lcp.hip)
-  struct LcpState* lcp = nullptr;
+  LcpState* lcp = nullptr;
+  // batched suspensions: one child context per suspension, sharing the stream
+  bool is_batch = false;
+  std::vector<std::unique_ptr<pqn_ctx_impl>> children;
   ~pqn_ctx_impl();
 
   Level& level(int fidelity) {
+    if (is_batch) throw Error(PQN_ERR_STATE, "this entry point takes a single-suspension context");
     if (fidelity == PQN_LOFI) {
       if (!has_lo) throw Error(PQN_ERR_STATE, "no low-fidelity grid in this context");
       return lo;
@@ -114,13 +154,22 @@ struct pqn_ctx_impl {
   }
   void setup_level(Level& lv, int nt, int np, double tol);
   void set_configuration(const double* c, const double* ax);
+  // operator on groups of densities (all on this context's stream)
+  void matvec_groups(std::vector<MvGroup>& groups, int precision);
   void apply_operator(Level& lv, int precision, const double* q, double* y);
-  // GMRES on (1/2 + D + P) x = rhs (device arrays of length 3N); returns iterations
-  int gmres(Level& lv, int precision, const double* rhs, double* x, double tol, double* relres, bool* conv);
-  void solve(Level& lv, const double* rhs, double* x, pqn_mvp_stats* st);
-  void mobility(Level& lv, const double* FT_dev, const double* axes_dev, double* UO_dev, pqn_mvp_stats* st);
+  // lockstep GMRES over systems; every system's x is overwritten (initial guess 0)
+  void gmres_lockstep(std::vector<SysRef>& sys, int precision);
+  // solve in the context's precision with optional FP64-residual refinement
+  void solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st);
+  // mobility products of K force sets on one level (K <= kMaxRhs)
+  void mobility_multi(Level& lv, int K, const double* const* FT_dev, const double* axes_dev,
+                      double* const* UO_dev, pqn_mvp_stats* st);
+  void mobility(Level& lv, const double* FT_dev, const double* axes_dev, double* UO_dev, pqn_mvp_stats* st) {
+    mobility_multi(lv, 1, &FT_dev, axes_dev, &UO_dev, st);
+  }
   double dot_host(const double* x, const double* y, long len, Level& lv);
   void begin_far_timing();
+  void end_far_launch();
   double end_far_timing();
 };
 

@@ -7,79 +7,92 @@
 namespace bipqn {
 
 // --------------------------------------------------------------- packing
+//
+// Far-tile sources for K densities sharing one geometry pass. FP32 record of a
+// node: {o.x, o.y, o.z, wq_0.x, wq_0.y, wq_0.z, wq_1.x, ...} padded to a
+// multiple of 4 floats; FP64 record padded to a multiple of 2 doubles.
 
-// Far-tile sources: {o.x, o.y, o.z, wq.x} {wq.y, wq.z, 0, 0} per node, FP32.
-__global__ __launch_bounds__(256) void k_pack32(const double* __restrict__ q, const double* __restrict__ off,
-                                                const double* __restrict__ w, int n, int N,
-                                                float4* __restrict__ src) {
+template <int K>
+__global__ __launch_bounds__(256) void k_pack32(QPtrs q, const double* __restrict__ off,
+                                                const double* __restrict__ w, int n, int N, float* __restrict__ src) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N) return;
+  constexpr int S = src32_stride(K);
   const int k = t % n;
   const double wk = w[k];
-  src[2 * t] = make_float4((float)off[3 * k], (float)off[3 * k + 1], (float)off[3 * k + 2], (float)(wk * q[t]));
-  src[2 * t + 1] = make_float4((float)(wk * q[N + t]), (float)(wk * q[2 * N + t]), 0.f, 0.f);
+  float* d = src + (size_t)t * S;
+  d[0] = (float)off[3 * k];
+  d[1] = (float)off[3 * k + 1];
+  d[2] = (float)off[3 * k + 2];
+#pragma unroll
+  for (int r = 0; r < K; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d[3 + 3 * r + c] = (float)(wk * q.p[r][(size_t)c * N + t]);
+#pragma unroll
+  for (int e = 3 + 3 * K; e < S; ++e) d[e] = 0.f;
 }
 
-// FP64 sources: {o.x, o.y, o.z, wq.x, wq.y, wq.z, 0, 0} per node.
-__global__ __launch_bounds__(256) void k_pack64(const double* __restrict__ q, const double* __restrict__ off,
-                                                const double* __restrict__ w, int n, int N,
-                                                double2* __restrict__ src) {
+template <int K>
+__global__ __launch_bounds__(256) void k_pack64(QPtrs q, const double* __restrict__ off,
+                                                const double* __restrict__ w, int n, int N, double* __restrict__ src) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N) return;
+  constexpr int S = src64_stride(K);
   const int k = t % n;
   const double wk = w[k];
-  src[4 * t] = make_double2(off[3 * k], off[3 * k + 1]);
-  src[4 * t + 1] = make_double2(off[3 * k + 2], wk * q[t]);
-  src[4 * t + 2] = make_double2(wk * q[N + t], wk * q[2 * N + t]);
-  src[4 * t + 3] = make_double2(0.0, 0.0);
+  double* d = src + (size_t)t * S;
+  d[0] = off[3 * k];
+  d[1] = off[3 * k + 1];
+  d[2] = off[3 * k + 2];
+#pragma unroll
+  for (int r = 0; r < K; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d[3 + 3 * r + c] = wk * q.p[r][(size_t)c * N + t];
+#pragma unroll
+  for (int e = 3 + 3 * K; e < S; ++e) d[e] = 0.0;
 }
 
 // ----------------------------------------------------------- far pair sum
 //
-// u(x) += 3/(4 pi a) sum_y r (r.wq_y)(r.o_y)/|r|^5, r = x - y, over source
-// spheres j != i that are not near sphere i. One thread owns TPT targets; the
-// grid's y dimension splits the source spheres into chunks. The source node
-// stream is wave-uniform, so its loads go through the scalar unit and its
-// values enter the VALU as scalar operands. Target positions are taken
-// relative to the source sphere's centre, X = (c_i - c_j) + o_x, formed in
-// FP64 and rounded once, so r = X - o_y carries no large-coordinate
-// cancellation. Each sphere's contribution (one tile) is summed in the pair
-// precision and added to an FP64 accumulator.
+// u_r(x) += 3/(4 pi a) sum_y r (r.wq_r,y)(r.o_y)/|r|^5, r = x - y, for every
+// density r < K, over source spheres j != i that are not near sphere i. One
+// thread owns TPT targets; the grid's y dimension splits the source spheres
+// into chunks. The source stream is wave-uniform, so its loads go through the
+// scalar unit and its values enter the VALU as scalar operands; r, |r|^-5 and
+// r.o are shared by the K densities. Target positions are taken relative to
+// the source sphere's centre, X = (c_i - c_j) + o_x, formed in FP64 and
+// rounded once, so r = X - o_y carries no large-coordinate cancellation. Each
+// sphere's contribution (one tile) is summed in the pair precision and added
+// to an FP64 accumulator.
 
-template <int TPT>
-__global__ __launch_bounds__(256) void k_far32(const float4* __restrict__ src, const double* __restrict__ off,
-                                               const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
-                                               int n, int M, int N, int spc, double scale,
-                                               double* __restrict__ part) {
-  const int j0 = blockIdx.y * spc;
+template <int TPT, int K>
+__device__ __forceinline__ void far32_body(int tb, int chunk, const float* __restrict__ src,
+                                           const double* __restrict__ off, const double* __restrict__ ctr,
+                                           const unsigned char* __restrict__ cls, int n, int M, int N, int spc,
+                                           double scale, const OPtrs& part) {
+  constexpr int S = src32_stride(K);
+  const int j0 = chunk * spc;
   const int j1 = min(M, j0 + spc);
   int ti[TPT];
   bool valid[TPT];
-  double px[TPT], py[TPT], pz[TPT];
-  double ax[TPT], ay[TPT], az[TPT];
+  double px[TPT], py[TPT], pz[TPT], ox[TPT], oy[TPT], oz[TPT];
+  double acc[TPT][K][3];
 #pragma unroll
   for (int u = 0; u < TPT; ++u) {
-    const int t = blockIdx.x * 256 * TPT + u * 256 + threadIdx.x;
+    const int t = tb * 256 * TPT + u * 256 + threadIdx.x;
     valid[u] = t < N;
     const int tt = valid[u] ? t : N - 1;
     const int i = tt / n;
     const int k = tt - i * n;
     ti[u] = i;
-    px[u] = ctr[3 * i] + 0.0;
+    px[u] = ctr[3 * i];
     py[u] = ctr[3 * i + 1];
     pz[u] = ctr[3 * i + 2];
-    // keep the offset separately to form (c_i - c_j) + o_x per tile
-    ax[u] = off[3 * k];
-    ay[u] = off[3 * k + 1];
-    az[u] = off[3 * k + 2];
-  }
-  double ox[TPT], oy[TPT], oz[TPT];
+    ox[u] = off[3 * k];
+    oy[u] = off[3 * k + 1];
+    oz[u] = off[3 * k + 2];
 #pragma unroll
-  for (int u = 0; u < TPT; ++u) {
-    ox[u] = ax[u];
-    oy[u] = ay[u];
-    oz[u] = az[u];
-    ax[u] = ay[u] = az[u] = 0.0;
+    for (int r = 0; r < K; ++r) acc[u][r][0] = acc[u][r][1] = acc[u][r][2] = 0.0;
   }
   for (int j = j0; j < j1; ++j) {
     const double cjx = ctr[3 * j], cjy = ctr[3 * j + 1], cjz = ctr[3 * j + 2];
@@ -91,169 +104,178 @@ __global__ __launch_bounds__(256) void k_far32(const float4* __restrict__ src, c
       any |= act[u];
     }
     if (!__any(any)) continue;
-    float Xx[TPT], Xy[TPT], Xz[TPT], sx[TPT], sy[TPT], sz[TPT];
+    float Xx[TPT], Xy[TPT], Xz[TPT], sm[TPT][K][3];
 #pragma unroll
     for (int u = 0; u < TPT; ++u) {
       Xx[u] = act[u] ? (float)((px[u] - cjx) + ox[u]) : 1.0e4f;
       Xy[u] = act[u] ? (float)((py[u] - cjy) + oy[u]) : 0.0f;
       Xz[u] = act[u] ? (float)((pz[u] - cjz) + oz[u]) : 0.0f;
-      sx[u] = sy[u] = sz[u] = 0.0f;
+#pragma unroll
+      for (int r = 0; r < K; ++r) sm[u][r][0] = sm[u][r][1] = sm[u][r][2] = 0.0f;
     }
-    const float4* s = src + 2 * (size_t)j * n;
+    const float* sp = src + (size_t)j * n * S;
 #pragma unroll 4
     for (int kk = 0; kk < n; ++kk) {
-      const float4 a = s[2 * kk];
-      const float4 b = s[2 * kk + 1];
+      const float* e = sp + (size_t)kk * S;
+      const float sx = e[0], sy = e[1], sz = e[2];
 #pragma unroll
       for (int u = 0; u < TPT; ++u) {
-        const float rx = Xx[u] - a.x, ry = Xy[u] - a.y, rz = Xz[u] - a.z;
+        const float rx = Xx[u] - sx, ry = Xy[u] - sy, rz = Xz[u] - sz;
         const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
         const float ri = __builtin_amdgcn_rsqf(r2);
         const float ri2 = ri * ri;
-        const float rn = fmaf(rx, a.x, fmaf(ry, a.y, rz * a.z));
-        const float rq = fmaf(rx, a.w, fmaf(ry, b.x, rz * b.y));
-        const float c = rn * rq * ri * ri2 * ri2;
-        sx[u] = fmaf(c, rx, sx[u]);
-        sy[u] = fmaf(c, ry, sy[u]);
-        sz[u] = fmaf(c, rz, sz[u]);
+        const float rn = fmaf(rx, sx, fmaf(ry, sy, rz * sz));
+        const float wgt = rn * ri * ri2 * ri2;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+          const float rq = fmaf(rx, e[3 + 3 * r], fmaf(ry, e[4 + 3 * r], rz * e[5 + 3 * r]));
+          const float c = wgt * rq;
+          sm[u][r][0] = fmaf(c, rx, sm[u][r][0]);
+          sm[u][r][1] = fmaf(c, ry, sm[u][r][1]);
+          sm[u][r][2] = fmaf(c, rz, sm[u][r][2]);
+        }
       }
     }
 #pragma unroll
-    for (int u = 0; u < TPT; ++u) {
-      if (act[u]) {
-        ax[u] += (double)sx[u];
-        ay[u] += (double)sy[u];
-        az[u] += (double)sz[u];
-      }
-    }
+    for (int u = 0; u < TPT; ++u)
+      if (act[u])
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[u][r][c] += (double)sm[u][r][c];
   }
-  double* pb = part + (size_t)blockIdx.y * 3 * N;
 #pragma unroll
   for (int u = 0; u < TPT; ++u) {
-    const int t = blockIdx.x * 256 * TPT + u * 256 + threadIdx.x;
-    if (valid[u]) {
-      pb[t] = scale * ax[u];
-      pb[N + t] = scale * ay[u];
-      pb[2 * N + t] = scale * az[u];
-    }
+    const int t = tb * 256 * TPT + u * 256 + threadIdx.x;
+    if (valid[u])
+#pragma unroll
+      for (int r = 0; r < K; ++r) {
+        double* pb = part.p[r] + (size_t)chunk * 3 * N;
+        pb[t] = scale * acc[u][r][0];
+        pb[N + t] = scale * acc[u][r][1];
+        pb[2 * N + t] = scale * acc[u][r][2];
+      }
   }
 }
 
-__global__ __launch_bounds__(256) void k_far64(const double2* __restrict__ src, const double* __restrict__ off,
+template <int TPT, int K>
+__global__ __launch_bounds__(256) void k_far32(const float* __restrict__ src, const double* __restrict__ off,
                                                const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
-                                               int n, int M, int N, int spc, double scale,
-                                               double* __restrict__ part) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
+                                               int n, int M, int N, int spc, double scale, OPtrs part) {
+  far32_body<TPT, K>(blockIdx.x, blockIdx.y, src, off, ctr, cls, n, M, N, spc, scale, part);
+}
+
+// Many suspensions in one launch: block b takes work item b of a list ordered
+// by decreasing cost (instance, target block, source chunk); the hardware
+// dispatches blocks in order, so the largest tiles start first.
+template <int TPT>
+__global__ __launch_bounds__(256) void k_far32_multi(const FarDesc* __restrict__ desc, int ndesc) {
+  const int item = blockIdx.x;
+  int d = 0;
+  while (d + 1 < ndesc && desc[d + 1].item0 <= item) ++d;
+  const FarDesc D = desc[d];
+  const int local = item - D.item0;
+  const int tb = local % D.ntb, chunk = local / D.ntb;
+  OPtrs part;
+  part.p[0] = D.part;
+  far32_body<TPT, 1>(tb, chunk, (const float*)D.src, D.off, D.ctr, D.cls, D.n, D.M, D.N, D.spc, D.scale, part);
+}
+
+template <int K>
+__device__ __forceinline__ void far64_body(int tb, int chunk, const double* __restrict__ src,
+                                           const double* __restrict__ off, const double* __restrict__ ctr,
+                                           const unsigned char* __restrict__ cls, int n, int M, int N, int spc,
+                                           double scale, const OPtrs& part) {
+  constexpr int S = src64_stride(K);
+  const int t = tb * 256 + threadIdx.x;
   const bool valid = t < N;
   const int tt = valid ? t : N - 1;
   const int i = tt / n;
   const int k = tt - i * n;
   const double px = ctr[3 * i], py = ctr[3 * i + 1], pz = ctr[3 * i + 2];
   const double ox = off[3 * k], oy = off[3 * k + 1], oz = off[3 * k + 2];
-  const int j0 = blockIdx.y * spc;
+  const int j0 = chunk * spc;
   const int j1 = min(M, j0 + spc);
-  double ax = 0.0, ay = 0.0, az = 0.0;
+  double acc[K][3];
+#pragma unroll
+  for (int r = 0; r < K; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
   for (int j = j0; j < j1; ++j) {
     const bool act = valid && cls[i * M + j] == 0;
     if (!__any(act)) continue;
     const double Xx = act ? (px - ctr[3 * j]) + ox : 1.0e4;
     const double Xy = act ? (py - ctr[3 * j + 1]) + oy : 0.0;
     const double Xz = act ? (pz - ctr[3 * j + 2]) + oz : 0.0;
-    double sx = 0.0, sy = 0.0, sz = 0.0;
-    const double2* s = src + 4 * (size_t)j * n;
+    double sm[K][3];
+#pragma unroll
+    for (int r = 0; r < K; ++r) sm[r][0] = sm[r][1] = sm[r][2] = 0.0;
+    const double* sp = src + (size_t)j * n * S;
 #pragma unroll 2
     for (int kk = 0; kk < n; ++kk) {
-      const double2 a = s[4 * kk], b = s[4 * kk + 1], c2 = s[4 * kk + 2];
-      const double rx = Xx - a.x, ry = Xy - a.y, rz = Xz - b.x;
+      const double* e = sp + (size_t)kk * S;
+      const double rx = Xx - e[0], ry = Xy - e[1], rz = Xz - e[2];
       const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
       const double ri = rsqrt(r2);
       const double ri2 = ri * ri;
-      const double rn = fma(rx, a.x, fma(ry, a.y, rz * b.x));
-      const double rq = fma(rx, b.y, fma(ry, c2.x, rz * c2.y));
-      const double c = rn * rq * ri * ri2 * ri2;
-      sx = fma(c, rx, sx);
-      sy = fma(c, ry, sy);
-      sz = fma(c, rz, sz);
+      const double rn = fma(rx, e[0], fma(ry, e[1], rz * e[2]));
+      const double wgt = rn * ri * ri2 * ri2;
+#pragma unroll
+      for (int r = 0; r < K; ++r) {
+        const double rq = fma(rx, e[3 + 3 * r], fma(ry, e[4 + 3 * r], rz * e[5 + 3 * r]));
+        const double c = wgt * rq;
+        sm[r][0] = fma(c, rx, sm[r][0]);
+        sm[r][1] = fma(c, ry, sm[r][1]);
+        sm[r][2] = fma(c, rz, sm[r][2]);
+      }
     }
-    if (act) {
-      ax += sx;
-      ay += sy;
-      az += sz;
+    if (act)
+#pragma unroll
+      for (int r = 0; r < K; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[r][c] += sm[r][c];
+  }
+  if (valid)
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      double* pb = part.p[r] + (size_t)chunk * 3 * N;
+      pb[t] = scale * acc[r][0];
+      pb[N + t] = scale * acc[r][1];
+      pb[2 * N + t] = scale * acc[r][2];
     }
-  }
-  if (valid) {
-    double* pb = part + (size_t)blockIdx.y * 3 * N;
-    pb[t] = scale * ax;
-    pb[N + t] = scale * ay;
-    pb[2 * N + t] = scale * az;
-  }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_far64(const double* __restrict__ src, const double* __restrict__ off,
+                                               const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
+                                               int n, int M, int N, int spc, double scale, OPtrs part) {
+  far64_body<K>(blockIdx.x, blockIdx.y, src, off, ctr, cls, n, M, N, spc, scale, part);
+}
+
+__global__ __launch_bounds__(256) void k_far64_multi(const FarDesc* __restrict__ desc, int ndesc) {
+  const int item = blockIdx.x;
+  int d = 0;
+  while (d + 1 < ndesc && desc[d + 1].item0 <= item) ++d;
+  const FarDesc D = desc[d];
+  const int local = item - D.item0;
+  const int tb = local % D.ntb, chunk = local / D.ntb;
+  OPtrs part;
+  part.p[0] = D.part;
+  far64_body<1>(tb, chunk, (const double*)D.src, D.off, D.ctr, D.cls, D.n, D.M, D.N, D.spc, D.scale, part);
 }
 
 // ---------------------------------------------------------- near pair sum
 //
-// For each target and each near partner sphere j (grid y = partner slot):
-// sum over the upsampled nodes f of sphere j of w_f K(x, y_f)(q_f - q_j(x*)),
-// x* the foot point of x on sphere j, q_j(x*) evaluated from the degree-p
-// harmonic coefficients of the density (constant-density subtraction).
+// For each target and each near partner sphere j: sum over the upsampled nodes
+// f of sphere j of w_f K(x, y_f)(q_f - q_j(x*)), x* the foot point of x on
+// sphere j and q_j(x*) the degree-p harmonic expansion of the density there
+// (constant-density subtraction). Grid (near pair, 64-target chunk): all lanes
+// of a wave share the source sphere j, so the upsampled source stream and the
+// harmonic coefficients are wave-uniform (scalar loads). K densities share r.
 
-__global__ __launch_bounds__(256) void k_near64(const double* __restrict__ ctr, const double* __restrict__ off,
-                                                const double4* __restrict__ offup, const double* __restrict__ qup,
-                                                const double* __restrict__ coef, const int* __restrict__ partners,
-                                                const int* __restrict__ npart, int n, int M, int N, int nup, int p,
-                                                int L, double scale, double* __restrict__ near_part) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  const int slot = blockIdx.y;
-  if (t >= N) return;
-  const int i = t / n;
-  if (slot >= npart[i]) return;
-  const int j = partners[i * kMaxNear + slot];
-  const int k = t - i * n;
-  const double Xx = (ctr[3 * i] + off[3 * k]) - ctr[3 * j];
-  const double Xy = (ctr[3 * i + 1] + off[3 * k + 1]) - ctr[3 * j + 1];
-  const double Xz = (ctr[3 * i + 2] + off[3 * k + 2]) - ctr[3 * j + 2];
-  const double rho = sqrt(Xx * Xx + Xy * Xy);
-  const double R = sqrt(rho * rho + Xz * Xz);
-  const double ct = Xz / R, st = rho / R;
-  const double cp = rho > 0.0 ? Xx / rho : 1.0, sp = rho > 0.0 ? Xy / rho : 0.0;
-  const size_t ML = (size_t)M * L;
-  const double* cx = coef + (size_t)j * L;
-  double fx = 0.0, fy = 0.0, fz = 0.0;
-  real_sh_visit(p, ct, st, cp, sp, [&](int idx, double y) {
-    fx = fma(y, cx[idx], fx);
-    fy = fma(y, cx[ML + idx], fy);
-    fz = fma(y, cx[2 * ML + idx], fz);
-  });
-  const size_t MU = (size_t)M * nup;
-  const double* qx = qup + (size_t)j * nup;
-  double ax = 0.0, ay = 0.0, az = 0.0;
-  for (int f = 0; f < nup; ++f) {
-    const double4 o = offup[f];
-    const double rx = Xx - o.x, ry = Xy - o.y, rz = Xz - o.z;
-    const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-    const double ri = rsqrt(r2);
-    const double ri2 = ri * ri;
-    const double dqx = qx[f] - fx, dqy = qx[MU + f] - fy, dqz = qx[2 * MU + f] - fz;
-    const double rn = fma(rx, o.x, fma(ry, o.y, rz * o.z));
-    const double rq = o.w * fma(rx, dqx, fma(ry, dqy, rz * dqz));
-    const double c = rn * rq * ri * ri2 * ri2;
-    ax = fma(c, rx, ax);
-    ay = fma(c, ry, ay);
-    az = fma(c, rz, az);
-  }
-  double* pb = near_part + (size_t)slot * 3 * N;
-  pb[t] = scale * ax;
-  pb[N + t] = scale * ay;
-  pb[2 * N + t] = scale * az;
-}
-
-// Same sum, organised by near sphere pair: grid (pair, 64-target chunk). All
-// lanes of a wave share the source sphere j, so the upsampled source stream and
-// the harmonic coefficients of q_j are wave-uniform (scalar loads).
-__global__ __launch_bounds__(64) void k_near64p(const double* __restrict__ ctr, const double* __restrict__ off,
-                                                const double4* __restrict__ offup, const double* __restrict__ qup,
-                                                const double* __restrict__ coef, const int* __restrict__ npairs,
-                                                int n, int M, int N, int nup, int p, int L, double scale,
-                                                double* __restrict__ near_part) {
+template <int K>
+__global__ __launch_bounds__(64) void k_near64(const double* __restrict__ ctr, const double* __restrict__ off,
+                                               const double4* __restrict__ offup, QPtrs qup, QPtrs coef,
+                                               const int* __restrict__ npairs, int n, int M, int N, int nup, int p,
+                                               int L, double scale, OPtrs near_part) {
   const int i = npairs[3 * blockIdx.x], j = npairs[3 * blockIdx.x + 1], slot = npairs[3 * blockIdx.x + 2];
   const int k = blockIdx.y * 64 + threadIdx.x;
   const bool valid = k < n;
@@ -267,37 +289,49 @@ __global__ __launch_bounds__(64) void k_near64p(const double* __restrict__ ctr, 
   const double ct = Xz / R, st = rho / R;
   const double cp = rho > 0.0 ? Xx / rho : 1.0, sp = rho > 0.0 ? Xy / rho : 0.0;
   const size_t ML = (size_t)M * L;
-  const double* cx = coef + (size_t)j * L;
-  double fx = 0.0, fy = 0.0, fz = 0.0;
+  double f[K][3];
+#pragma unroll
+  for (int r = 0; r < K; ++r) f[r][0] = f[r][1] = f[r][2] = 0.0;
   real_sh_visit(p, ct, st, cp, sp, [&](int idx, double y) {
-    fx = fma(y, cx[idx], fx);
-    fy = fma(y, cx[ML + idx], fy);
-    fz = fma(y, cx[2 * ML + idx], fz);
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const double* cx = coef.p[r] + (size_t)j * L;
+      f[r][0] = fma(y, cx[idx], f[r][0]);
+      f[r][1] = fma(y, cx[ML + idx], f[r][1]);
+      f[r][2] = fma(y, cx[2 * ML + idx], f[r][2]);
+    }
   });
   const size_t MU = (size_t)M * nup;
-  const double* qx = qup + (size_t)j * nup;
-  double ax = 0.0, ay = 0.0, az = 0.0;
+  double a[K][3];
+#pragma unroll
+  for (int r = 0; r < K; ++r) a[r][0] = a[r][1] = a[r][2] = 0.0;
 #pragma unroll 2
-  for (int f = 0; f < nup; ++f) {
-    const double4 o = offup[f];
+  for (int fi = 0; fi < nup; ++fi) {
+    const double4 o = offup[fi];
     const double rx = Xx - o.x, ry = Xy - o.y, rz = Xz - o.z;
     const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
     const double ri = rsqrt(r2);
     const double ri2 = ri * ri;
-    const double dqx = qx[f] - fx, dqy = qx[MU + f] - fy, dqz = qx[2 * MU + f] - fz;
     const double rn = fma(rx, o.x, fma(ry, o.y, rz * o.z));
-    const double rq = o.w * fma(rx, dqx, fma(ry, dqy, rz * dqz));
-    const double c = rn * rq * ri * ri2 * ri2;
-    ax = fma(c, rx, ax);
-    ay = fma(c, ry, ay);
-    az = fma(c, rz, az);
+    const double wgt = o.w * rn * ri * ri2 * ri2;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const double* qx = qup.p[r] + (size_t)j * nup + fi;
+      const double dqx = qx[0] - f[r][0], dqy = qx[MU] - f[r][1], dqz = qx[2 * MU] - f[r][2];
+      const double c = wgt * fma(rx, dqx, fma(ry, dqy, rz * dqz));
+      a[r][0] = fma(c, rx, a[r][0]);
+      a[r][1] = fma(c, ry, a[r][1]);
+      a[r][2] = fma(c, rz, a[r][2]);
+    }
   }
-  if (valid) {
-    double* pb = near_part + (size_t)slot * 3 * N;
-    pb[t] = scale * ax;
-    pb[N + t] = scale * ay;
-    pb[2 * N + t] = scale * az;
-  }
+  if (valid)
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      double* pb = near_part.p[r] + (size_t)slot * 3 * N;
+      pb[t] = scale * a[r][0];
+      pb[N + t] = scale * a[r][1];
+      pb[2 * N + t] = scale * a[r][2];
+    }
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -539,44 +573,91 @@ __global__ __launch_bounds__(256) void k_axpby(double* __restrict__ y, const dou
 
 static inline unsigned nblk(long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
-void launch_pack32(hipStream_t s, const double* q, const double* off, const double* w, int n, int N, float4* src) {
-  hipLaunchKernelGGL(k_pack32, dim3(nblk(N)), dim3(256), 0, s, q, off, w, n, N, src);
-}
-void launch_pack64(hipStream_t s, const double* q, const double* off, const double* w, int n, int N, double2* src) {
-  hipLaunchKernelGGL(k_pack64, dim3(nblk(N)), dim3(256), 0, s, q, off, w, n, N, src);
-}
-void launch_far32(hipStream_t s, int tpt, const float4* src, const double* off, const double* ctr,
-                  const unsigned char* cls, int n, int M, int N, int spc, int nchunks, double scale, double* part) {
-  if (tpt == 2)
-    hipLaunchKernelGGL(k_far32<2>, dim3(nblk(N, 512), nchunks), dim3(256), 0, s, src, off, ctr, cls, n, M, N, spc,
-                       scale, part);
+template <int K>
+static void pack_k(hipStream_t s, int prec, const QPtrs& q, const double* off, const double* w, int n, int N,
+                   void* src) {
+  if (prec == 1)
+    hipLaunchKernelGGL(k_pack32<K>, dim3(nblk(N)), dim3(256), 0, s, q, off, w, n, N, (float*)src);
   else
-    hipLaunchKernelGGL(k_far32<1>, dim3(nblk(N, 256), nchunks), dim3(256), 0, s, src, off, ctr, cls, n, M, N, spc,
-                       scale, part);
+    hipLaunchKernelGGL(k_pack64<K>, dim3(nblk(N)), dim3(256), 0, s, q, off, w, n, N, (double*)src);
 }
-void launch_far64(hipStream_t s, const double2* src, const double* off, const double* ctr, const unsigned char* cls,
-                  int n, int M, int N, int spc, int nchunks, double scale, double* part) {
-  hipLaunchKernelGGL(k_far64, dim3(nblk(N), nchunks), dim3(256), 0, s, src, off, ctr, cls, n, M, N, spc, scale,
-                     part);
+
+void launch_pack(hipStream_t s, int prec, int K, const QPtrs& q, const double* off, const double* w, int n, int N,
+                 void* src) {
+  switch (K) {
+    case 1: pack_k<1>(s, prec, q, off, w, n, N, src); break;
+    case 2: pack_k<2>(s, prec, q, off, w, n, N, src); break;
+    case 3: pack_k<3>(s, prec, q, off, w, n, N, src); break;
+    case 4: pack_k<4>(s, prec, q, off, w, n, N, src); break;
+    case 5: pack_k<5>(s, prec, q, off, w, n, N, src); break;
+    default: pack_k<6>(s, prec, q, off, w, n, N, src); break;
+  }
 }
-void launch_near64(hipStream_t s, int max_slots, const double* ctr, const double* off, const double4* offup,
-                   const double* qup, const double* coef, const int* partners, const int* npart, int n, int M, int N,
-                   int nup, int p, int L, double scale, double* near_part) {
-  if (max_slots <= 0) return;
-  hipLaunchKernelGGL(k_near64, dim3(nblk(N), max_slots), dim3(256), 0, s, ctr, off, offup, qup, coef, partners,
-                     npart, n, M, N, nup, p, L, scale, near_part);
+
+template <int K>
+static void far_k(hipStream_t s, int prec, int tpt, const void* src, const double* off, const double* ctr,
+                  const unsigned char* cls, int n, int M, int N, int spc, int nchunks, double scale,
+                  const OPtrs& part) {
+  if (prec == 1) {
+    if (tpt == 2)
+      hipLaunchKernelGGL((k_far32<2, K>), dim3(nblk(N, 512), nchunks), dim3(256), 0, s, (const float*)src, off, ctr,
+                         cls, n, M, N, spc, scale, part);
+    else
+      hipLaunchKernelGGL((k_far32<1, K>), dim3(nblk(N, 256), nchunks), dim3(256), 0, s, (const float*)src, off, ctr,
+                         cls, n, M, N, spc, scale, part);
+  } else {
+    hipLaunchKernelGGL(k_far64<K>, dim3(nblk(N), nchunks), dim3(256), 0, s, (const double*)src, off, ctr, cls, n, M,
+                       N, spc, scale, part);
+  }
 }
+
+void launch_far(hipStream_t s, int prec, int K, int tpt, const void* src, const double* off, const double* ctr,
+                const unsigned char* cls, int n, int M, int N, int spc, int nchunks, double scale, const OPtrs& part) {
+  switch (K) {
+    case 1: far_k<1>(s, prec, tpt, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
+    case 2: far_k<2>(s, prec, tpt, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
+    case 3: far_k<3>(s, prec, 1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
+    case 4: far_k<4>(s, prec, 1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
+    case 5: far_k<5>(s, prec, 1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
+    default: far_k<6>(s, prec, 1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
+  }
+}
+
+void launch_far_multi(hipStream_t s, int prec, int tpt, const FarDesc* desc, int ndesc, int nitems) {
+  if (nitems <= 0) return;
+  if (prec == 1) {
+    if (tpt == 2)
+      hipLaunchKernelGGL(k_far32_multi<2>, dim3(nitems), dim3(256), 0, s, desc, ndesc);
+    else
+      hipLaunchKernelGGL(k_far32_multi<1>, dim3(nitems), dim3(256), 0, s, desc, ndesc);
+  } else {
+    hipLaunchKernelGGL(k_far64_multi, dim3(nitems), dim3(256), 0, s, desc, ndesc);
+  }
+}
+
+void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, const double* off, const double4* offup,
+                 const QPtrs& qup, const QPtrs& coef, const int* npairs, int n, int M, int N, int nup, int p, int L,
+                 double scale, const OPtrs& near_part) {
+  if (npairs_count <= 0) return;
+  const dim3 g(npairs_count, (n + 63) / 64);
+#define NEARK(KK)                                                                                                 \
+  hipLaunchKernelGGL(k_near64<KK>, g, dim3(64), 0, s, ctr, off, offup, qup, coef, npairs, n, M, N, nup, p, L, scale, \
+                     near_part)
+  switch (K) {
+    case 1: NEARK(1); break;
+    case 2: NEARK(2); break;
+    case 3: NEARK(3); break;
+    case 4: NEARK(4); break;
+    case 5: NEARK(5); break;
+    default: NEARK(6); break;
+  }
+#undef NEARK
+}
+
 void launch_gemm64(hipStream_t s, int R, int Cn, int K, const double* A, int lda, long Az, const double* B, long Bz,
                    int kb, long kbs, int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch) {
   hipLaunchKernelGGL(k_gemm64, dim3((R + GBM - 1) / GBM, (Cn + GBN - 1) / GBN, batch), dim3(64), 0, s, R, Cn, K, A,
                      lda, Az, B, Bz, kb, kbs, ldb, C, Cz, rb, rbs, ldc);
-}
-void launch_near64p(hipStream_t s, int npairs_count, const double* ctr, const double* off, const double4* offup,
-                    const double* qup, const double* coef, const int* npairs, int n, int M, int N, int nup, int p,
-                    int L, double scale, double* near_part) {
-  if (npairs_count <= 0) return;
-  hipLaunchKernelGGL(k_near64p, dim3(npairs_count, (n + 63) / 64), dim3(64), 0, s, ctr, off, offup, qup, coef,
-                     npairs, n, M, N, nup, p, L, scale, near_part);
 }
 void launch_rhs(hipStream_t s, const double* ctr, const double* FT, const double* axes, const double* off, int n,
                 int M, int N, double a, double mu, double slip, double* rhs) {

@@ -4,20 +4,41 @@
 
 namespace bipqn {
 
-void launch_pack32(hipStream_t s, const double* q, const double* off, const double* w, int n, int N, float4* src);
-void launch_pack64(hipStream_t s, const double* q, const double* off, const double* w, int n, int N, double2* src);
-void launch_far32(hipStream_t s, int tpt, const float4* src, const double* off, const double* ctr,
-                  const unsigned char* cls, int n, int M, int N, int spc, int nchunks, double scale, double* part);
-void launch_far64(hipStream_t s, const double2* src, const double* off, const double* ctr, const unsigned char* cls,
-                  int n, int M, int N, int spc, int nchunks, double scale, double* part);
-void launch_near64(hipStream_t s, int max_slots, const double* ctr, const double* off, const double4* offup,
-                   const double* qup, const double* coef, const int* partners, const int* npart, int n, int M, int N,
-                   int nup, int p, int L, double scale, double* near_part);
+constexpr int kMaxRhs = 6;   // densities sharing one geometry pass
+
+struct QPtrs {
+  const double* p[kMaxRhs];
+};
+struct OPtrs {
+  double* p[kMaxRhs];
+};
+
+__host__ __device__ constexpr int src32_stride(int K) { return ((3 + 3 * K + 3) / 4) * 4; }
+__host__ __device__ constexpr int src64_stride(int K) { return ((3 + 3 * K + 1) / 2) * 2; }
+
+// One suspension's far pair sum inside a multi-suspension launch (single density).
+struct FarDesc {
+  const void* src;
+  const double* off;
+  const double* ctr;
+  const unsigned char* cls;
+  double* part;
+  int n, M, N, spc, ntb, item0;
+  double scale;
+};
+
+// prec: 0 = FP64 pair sums, 1 = FP32 pair sums (mixed)
+void launch_pack(hipStream_t s, int prec, int K, const QPtrs& q, const double* off, const double* w, int n, int N,
+                 void* src);
+void launch_far(hipStream_t s, int prec, int K, int tpt, const void* src, const double* off, const double* ctr,
+                const unsigned char* cls, int n, int M, int N, int spc, int nchunks, double scale, const OPtrs& part);
+void launch_far_multi(hipStream_t s, int prec, int tpt, const FarDesc* desc, int ndesc, int nitems);
+void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, const double* off, const double4* offup,
+                 const QPtrs& qup, const QPtrs& coef, const int* npairs, int n, int M, int N, int nup, int p, int L,
+                 double scale, const OPtrs& near_part);
 void launch_gemm64(hipStream_t s, int R, int Cn, int K, const double* A, int lda, long Az, const double* B, long Bz,
                    int kb, long kbs, int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch);
-void launch_near64p(hipStream_t s, int npairs_count, const double* ctr, const double* off, const double4* offup,
-                    const double* qup, const double* coef, const int* npairs, int n, int M, int N, int nup, int p,
-                    int L, double scale, double* near_part);
+
 void launch_rhs(hipStream_t s, const double* ctr, const double* FT, const double* axes, const double* off, int n,
                 int M, int N, double a, double mu, double slip, double* rhs);
 void launch_moments(hipStream_t s, const double* q, const double* off, const double* w, int n, int M, int N,

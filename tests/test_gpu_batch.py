@@ -1,0 +1,107 @@
+"""GPU parity of the batched paths: K densities per geometry pass, and many
+suspensions of uneven size in lockstep with one far launch per iteration."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import bie
+from paper_2604_10089_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("K", [2, 3, 6])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_multi_rhs_matches_single(K, prec):
+    w = inputs.workload('tiny', 1)
+    c = w['centers']
+    FT = inputs.random_forces(20, c.shape[0], k=K)
+    say('multi', K, prec)
+    with binding.Context(c, None, 8, 16, gmres_tol=1e-12, precision=prec) as ctx:
+        U, st = ctx.mobility_apply_multi(FT)
+        singles = [ctx.mobility_apply(FT[r])[0] for r in range(K)]
+    assert st['converged'] == 1
+    for r in range(K):
+        assert rel(U[r], singles[r]) < (1e-11 if prec == 'fp64' else 1e-7)
+
+
+def test_multi_rhs_matches_oracle():
+    w = inputs.workload('tiny', 0)
+    c = w['centers']
+    g = bie.Geometry(c, 1.0, 8, 16)
+    A = bie.dense_operator(g)
+    FT = inputs.random_forces(21, c.shape[0], k=6)
+    with binding.Context(c, None, 8, 16, gmres_tol=1e-13) as ctx:
+        U, _ = ctx.mobility_apply_multi(FT)
+    for r in range(6):
+        assert rel(U[r], bie.mobility_apply(g, FT[r], dense=A)) < 1e-10
+
+
+def test_multi_rhs_full_size_vs_single():
+    w = inputs.workload('rsa216', 0)
+    c = w['centers']
+    FT = inputs.random_forces(22, c.shape[0], k=3)
+    with binding.Context(c, None, w['n_theta'], w['n_phi'], gmres_tol=1e-9, precision='mixed') as ctx:
+        U, st = ctx.mobility_apply_multi(FT)
+        U0, _ = ctx.mobility_apply(FT[1])
+    say('multi rsa216', st)
+    assert rel(U[1], U0) < 1e-7
+
+
+def _instances(seed, count):
+    out = []
+    rng = np.random.default_rng(seed)
+    for b in range(count):
+        c = inputs.workload('tiny', 10 + b)['centers']
+        nt = int(rng.choice([6, 8]))
+        out.append((c, nt, 2 * nt))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_matches_single_contexts_and_oracle(prec):
+    inst = _instances(3, 5)
+    FTs = [inputs.random_forces(30 + b, c.shape[0]) for b, (c, _, _) in enumerate(inst)]
+    say('batch', prec)
+    with binding.BatchContext(inst, gmres_tol=1e-12, precision=prec) as bc:
+        U, st = bc.mobility_apply(FTs)
+    assert st['converged'] == 1
+    for b, (c, nt, nph) in enumerate(inst):
+        with binding.Context(c, None, nt, nph, gmres_tol=1e-12, precision=prec) as ctx:
+            Us, _ = ctx.mobility_apply(FTs[b])
+        assert rel(U[b], Us) < (1e-11 if prec == 'fp64' else 1e-7)
+        g = bie.Geometry(c, 1.0, nt, nph)
+        Uo = bie.mobility_apply(g, FTs[b], dense=bie.dense_operator(g))
+        assert rel(U[b], Uo) < (1e-10 if prec == 'fp64' else 1e-6)
+
+
+def test_batch_uneven_full_workload():
+    """The 32-suspension workload (8-27 spheres, 8x16..16x32 grids): batch vs per-instance contexts."""
+    inst = inputs.batched_suspensions(0)
+    FTs = [inputs.random_forces(40 + b, c.shape[0]) for b, (c, _, _) in enumerate(inst)]
+    with binding.BatchContext(inst, gmres_tol=1e-8, precision='mixed') as bc:
+        U, st = bc.mobility_apply(FTs)
+    say('batch32', st)
+    assert st['converged'] == 1
+    for b in (0, 7, 31):
+        c, nt, nph = inst[b]
+        with binding.Context(c, None, nt, nph, gmres_tol=1e-8, precision='mixed') as ctx:
+            Us, _ = ctx.mobility_apply(FTs[b])
+        assert rel(U[b], Us) < 1e-6
+
+
+def test_batch_context_rejects_single_calls():
+    inst = _instances(4, 2)
+    with binding.BatchContext(inst) as bc:
+        with pytest.raises(binding.PqnError):
+            binding._check(binding.lib().pqn_nc_velocity(bc.h, binding._dptr(np.zeros((8, 6))), 0, None))

@@ -156,3 +156,11 @@ def test_mobility_nearly_symmetric_and_positive(tiny_cases):
         asym = np.linalg.norm(M6 - M6.T) / np.linalg.norm(M6)
         assert asym < 5e-2
         assert np.linalg.eigvalsh(0.5 * (M6 + M6.T)).min() > 0.0
+
+
+def test_operator_rows_equal_full_apply(tiny_cases):
+    seed, g, A = tiny_cases[1]
+    q = np.random.default_rng(9).standard_normal((g.N, 3))
+    full = (A @ q.ravel()).reshape(-1, 3)
+    tg = [0, 5, 127, 128, 700, g.N - 1]
+    assert np.abs(bie.operator_rows(g, q, tg) - full[tg]).max() < 1e-12 * np.abs(full).max()
