@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VECTOR = 157.3      # TFLOP/s, MI355X FP32 vector (vendor figure, packed issue)
 PEAK_FP32_NONPACKED = 78.6    # TFLOP/s, 256 CU x 64 lanes x 2 flop x 2.4 GHz (no packed FP32)
 K_RHS = 6
+PROBE_BYTES = 256 << 20       # reference copy for the HBM byte counters
 
 
 def flop_per_pair(K):
@@ -57,6 +58,9 @@ def main():
     ap.add_argument('--no-batch', action='store_true')
     ap.add_argument('--tpt', type=int, default=2)
     ap.add_argument('--chunks', type=int, default=0)
+    ap.add_argument('--counters-probe', action='store_true',
+                    help='short run for rocprofv3 --pmc: a 256 MiB device copy (scale reference for FETCH_SIZE/'
+                         'WRITE_SIZE) and one single-force-set product on the 216-sphere workload')
     args = ap.parse_args()
     if args.gpus != 1:
         print(f'bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on one MI355X; '
@@ -84,7 +88,21 @@ def main():
         return binding.Context(c, None, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision=prec, tpt=args.tpt,
                                far_chunks=args.chunks, stream=stream.cuda_stream, profile=profile)
 
-    FT6 = [inputs.random_forces(100 + k, M, k=K_RHS) for k in range(max(K, 1) + W)]
+    FT6 = [inputs.random_forces(100 + k, M, k=K_RHS) for k in range(max(K, 2) + W + 2)]
+
+    if args.counters_probe:
+        ref = torch.empty(PROBE_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(ref)
+        torch.cuda.synchronize()
+        dst.copy_(ref)                      # reads and writes PROBE_BYTES once each
+        torch.cuda.synchronize()
+        cm = ctx_for('mixed', profile=False)
+        _, st = cm.mobility_apply_multi(FT6[0][:1])
+        torch.cuda.synchronize()
+        cm.close()
+        print(json.dumps({'probe_bytes': PROBE_BYTES, 'far_launches': st['n_far'],
+                          'far_pairs_per_launch': int(pf)}), flush=True)
+        return
 
     def run_multi(ctx, steps, warm, kr):
         for k in range(warm):

@@ -7,6 +7,30 @@
 
 namespace bipqn {
 
+constexpr int kMultiDotBlocks = 16;  // reduction blocks per vector in the segmented dot kernel
+
+// Host staging of typed descriptor arrays, uploaded in one copy.
+struct DescPack {
+  std::vector<char> host;
+  template <class T>
+  size_t add(const std::vector<T>& v) {
+    const size_t off = (host.size() + 63) & ~size_t(63);
+    host.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+char* pqn_ctx_impl::push_desc_pack(const std::vector<char>& pack) {
+  if (pack.size() > ddesc.count) {
+    // growing the table: wait for kernels still reading the old one
+    HIPCHK(hipStreamSynchronize(stream));
+    ddesc.alloc(std::max<size_t>(pack.size() * 2, 1 << 16));
+  }
+  HIPCHK(hipMemcpyAsync(ddesc.p, pack.data(), pack.size(), hipMemcpyHostToDevice, stream));
+  return ddesc.p;
+}
+
 Work& Level::wk(int k) {
   while ((int)work.size() <= k) work.emplace_back(new Work());
   Work& w = *work[k];
@@ -32,7 +56,7 @@ SysBuf& Level::sb(int k) {
     b.rhs.alloc(len);
     b.tmp.alloc(len);
     b.d.alloc(len);
-    b.partial.alloc((size_t)nb_dots * (restart + 1));
+    b.partial.alloc((size_t)std::max(nb_dots, kMultiDotBlocks) * (restart + 1));
     b.ycoef.alloc((size_t)restart + 1);
   }
   return b;
@@ -165,6 +189,12 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
   hipStream_t s = stream;
   const int prec = precision == PQN_MIXED ? 1 : 0;
   bool all_single = groups.size() > 1;
+  for (MvGroup& gr : groups)
+    if (gr.K != 1) all_single = false;
+  if (all_single) {
+    matvec_batched(groups, prec);
+    return;
+  }
   for (MvGroup& gr : groups) {
     Level& lv = *gr.lv;
     pqn_ctx_impl& c = *gr.c;
@@ -252,6 +282,100 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
     }
     n_matvec += gr.K;
   }
+  HIPCHK(hipGetLastError());
+}
+
+// Many suspensions (one density each): every phase of the operator is one
+// segmented launch over all of them.
+void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
+  hipStream_t s = stream;
+  std::vector<GemmDesc> ga, gb;
+  std::vector<PackDesc> pk;
+  std::vector<NearDesc> nd;
+  std::vector<MomDesc> md;
+  std::vector<CombDesc> cd;
+  int nga = 0, ngb = 0, npk = 0, nnd = 0, nmd = 0, ncd = 0;
+  auto gemm = [](std::vector<GemmDesc>& v, int& blocks, int R, int Cn, int K, const double* A, int lda,
+                 const double* B, int kb, long kbs, int ldb, double* C, int rb, long rbs, int ldc) {
+    GemmDesc d{A, B, C, kbs, rbs, R, Cn, K, lda, kb, ldb, rb, ldc, (R + 31) / 32, blocks};
+    blocks += d.tr * ((Cn + 31) / 32);
+    v.push_back(d);
+  };
+  for (MvGroup& gr : groups) {
+    Level& lv = *gr.lv;
+    pqn_ctx_impl& c = *gr.c;
+    Work& w = lv.wk(gr.slot0);
+    const int n = lv.n, N = lv.N, L = lv.L, nup = lv.nup, M = lv.M;
+    for (int comp = 0; comp < 3; ++comp) {
+      gemm(ga, nga, L, M, n, lv.T.p, n, gr.in[0] + (size_t)comp * N, n, 0, n, w.coef.p + (size_t)comp * M * L, L, 0,
+           L);
+      gemm(gb, ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, w.coef.p + (size_t)comp * M * L, L, 0, L,
+           w.selfo.p + (size_t)comp * 3 * N, n, N, n);
+      if (c.n_near > 0)
+        gemm(gb, ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L, 0, L,
+             w.qup.p + (size_t)comp * M * nup, nup, 0, nup);
+    }
+    pk.push_back(PackDesc{gr.in[0], lv.off.p, lv.w.p, lv.src.p, n, N, npk});
+    npk += N;
+    if (c.n_near > 0) {
+      const int nch = (n + 63) / 64;
+      nd.push_back(NearDesc{c.ctr.p, lv.off.p, lv.offup.p, w.qup.p, w.coef.p, c.near_list.p, w.near_part.p,
+                            3.0 / (4.0 * kPi * c.a), n, M, N, nup, lv.p, L, nch, nnd});
+      nnd += c.n_near * nch;
+    }
+    md.push_back(MomDesc{gr.in[0], lv.off.p, lv.w.p, w.mom.p, n, N, nmd});
+    nmd += M;
+    cd.push_back(CombDesc{gr.in[0], w.selfo.p, w.far_part.p, w.near_part.p, c.npart.p, w.mom.p, lv.off.p, gr.out[0],
+                          c.a, lv.nchunks, n, N, ncd});
+    ncd += N;
+  }
+  DescPack dp;
+  const size_t oa = dp.add(ga), ob = dp.add(gb), op = dp.add(pk), on = dp.add(nd), om = dp.add(md), oc = dp.add(cd);
+  char* base = push_desc_pack(dp.host);
+  launch_gemm64_multi(s, (const GemmDesc*)(base + oa), (int)ga.size(), nga);   // coef = T q
+  launch_gemm64_multi(s, (const GemmDesc*)(base + ob), (int)gb.size(), ngb);   // self, qup
+  launch_pack_multi(s, (const PackDesc*)(base + op), (int)pk.size(), npk, prec);
+  begin_far_timing();
+  {
+    struct Item {
+      FarDesc d;
+      long cost;
+    };
+    std::vector<Item> items;
+    const int tpt = cfg.targets_per_thread == 1 ? 1 : 2;
+    for (MvGroup& gr : groups) {
+      Level& lv = *gr.lv;
+      FarDesc d{};
+      d.src = lv.src.p;
+      d.off = lv.off.p;
+      d.ctr = gr.c->ctr.p;
+      d.cls = gr.c->cls.p;
+      d.part = lv.wk(gr.slot0).far_part.p;
+      d.n = lv.n;
+      d.M = lv.M;
+      d.N = lv.N;
+      d.spc = lv.spc;
+      d.ntb = prec == 1 ? (lv.N + 256 * tpt - 1) / (256 * tpt) : (lv.N + 255) / 256;
+      d.scale = 3.0 / (4.0 * kPi * gr.c->a);
+      items.push_back({d, (long)lv.n * lv.n * lv.spc});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+    std::vector<FarDesc> ds;
+    int total = 0;
+    for (Item& it : items) {
+      it.d.item0 = total;
+      total += it.d.ntb * ((it.d.M + it.d.spc - 1) / it.d.spc);
+      ds.push_back(it.d);
+    }
+    fdesc.upload(ds.data(), ds.size(), s);
+    launch_far_multi(s, prec, tpt, fdesc.p, (int)ds.size(), total);
+  }
+  end_far_launch();
+  ++n_far;
+  if (!nd.empty()) launch_near_multi(s, (const NearDesc*)(base + on), (int)nd.size(), nnd);
+  launch_moments_multi(s, (const MomDesc*)(base + om), (int)md.size(), nmd);
+  launch_combine_multi(s, (const CombDesc*)(base + oc), (int)cd.size(), ncd);
+  n_matvec += (int)groups.size();
   HIPCHK(hipGetLastError());
 }
 
@@ -358,20 +482,52 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
     if (act.empty()) break;
     std::vector<MvGroup> groups = build_groups(act, false);
     matvec_groups(groups, precision);
-    for (int i : act) {
-      SysBuf& b = sys[i].lv->sb(sys[i].slot);
-      const long len = len_of(i);
-      const int k = st[i].k;
-      double* w = b.V.p + (size_t)(k + 1) * len;
-      double* hp = hdev.p + (size_t)i * hs;
-      for (int pass = 0; pass < 2; ++pass) {
-        launch_dots(s, b.V.p, len, k + 1, w, len, sys[i].lv->nb_dots, b.partial.p, hp + pass * (m + 1));
-        launch_combo(s, w, 1.0, b.V.p, len, k + 1, hp + pass * (m + 1), -1.0, len);
+    if (act.size() == 1) {
+      for (int i : act) {
+        SysBuf& b = sys[i].lv->sb(sys[i].slot);
+        const long len = len_of(i);
+        const int k = st[i].k;
+        double* w = b.V.p + (size_t)(k + 1) * len;
+        double* hp = hdev.p + (size_t)i * hs;
+        for (int pass = 0; pass < 2; ++pass) {
+          launch_dots(s, b.V.p, len, k + 1, w, len, sys[i].lv->nb_dots, b.partial.p, hp + pass * (m + 1));
+          launch_combo(s, w, 1.0, b.V.p, len, k + 1, hp + pass * (m + 1), -1.0, len);
+        }
+        launch_dots(s, w, len, 1, w, len, sys[i].lv->nb_dots, b.partial.p, hp + 2 * (m + 1));
       }
-      launch_dots(s, w, len, 1, w, len, sys[i].lv->nb_dots, b.partial.p, hp + 2 * (m + 1));
+    } else {
+      // CGS2 of every active system with segmented launches
+      std::vector<DotDesc> dd[2], dn;
+      std::vector<ComboDesc> cd[2];
+      int nv[2] = {0, 0}, nn = 0, ne[2] = {0, 0};
+      for (int i : act) {
+        SysBuf& b = sys[i].lv->sb(sys[i].slot);
+        const long len = len_of(i);
+        const int k = st[i].k;
+        double* w = b.V.p + (size_t)(k + 1) * len;
+        double* hp = hdev.p + (size_t)i * hs;
+        for (int pass = 0; pass < 2; ++pass) {
+          dd[pass].push_back(DotDesc{b.V.p, w, b.partial.p, hp + pass * (m + 1), len, len, nv[pass]});
+          nv[pass] += k + 1;
+          cd[pass].push_back(ComboDesc{w, b.V.p, hp + pass * (m + 1), -1.0, 1.0, len, len, k + 1, ne[pass]});
+          ne[pass] += (int)len;
+        }
+        dn.push_back(DotDesc{w, w, b.partial.p, hp + 2 * (m + 1), len, len, nn});
+        nn += 1;
+      }
+      DescPack dp;
+      const size_t o0 = dp.add(dd[0]), o1 = dp.add(cd[0]), o2 = dp.add(dd[1]), o3 = dp.add(cd[1]), o4 = dp.add(dn);
+      char* base = push_desc_pack(dp.host);
+      launch_dots_multi(s, (const DotDesc*)(base + o0), (int)dd[0].size(), nv[0], kMultiDotBlocks);
+      launch_combo_multi(s, (const ComboDesc*)(base + o1), (int)cd[0].size(), ne[0]);
+      launch_dots_multi(s, (const DotDesc*)(base + o2), (int)dd[1].size(), nv[1], kMultiDotBlocks);
+      launch_combo_multi(s, (const ComboDesc*)(base + o3), (int)cd[1].size(), ne[1]);
+      launch_dots_multi(s, (const DotDesc*)(base + o4), (int)dn.size(), nn, kMultiDotBlocks);
     }
     readback();
     std::vector<int> need_restart;
+    std::vector<ComboDesc> scale_list;
+    int scale_total = 0;
     for (int i : act) {
       GmState& g = st[i];
       SysRef& sr = sys[i];
@@ -401,7 +557,9 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
       const bool conv = std::fabs(g.g[k + 1]) <= sr.tol * g.bnorm || hn == 0.0;
       const bool full = (k + 1 == m) || sr.its >= sr.lv->max_iter;
       if (!conv && !full) {
-        launch_scale_copy(s, b.V.p + (size_t)(k + 1) * len, b.V.p + (size_t)(k + 1) * len, 1.0 / hn, len);
+        scale_list.push_back(ComboDesc{b.V.p + (size_t)(k + 1) * len, nullptr, nullptr, 0.0, 1.0 / hn, 0, len, 0,
+                                       scale_total});
+        scale_total += (int)len;
         g.k = k + 1;
         continue;
       }
@@ -423,6 +581,15 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
       } else {
         need_restart.push_back(i);
       }
+    }
+    if (scale_list.size() == 1) {
+      const ComboDesc& c0 = scale_list[0];
+      launch_scale_copy(s, c0.w, c0.w, c0.beta, c0.len);
+    } else if (!scale_list.empty()) {
+      DescPack dp;
+      const size_t o = dp.add(scale_list);
+      char* base = push_desc_pack(dp.host);
+      launch_combo_multi(s, (const ComboDesc*)(base + o), (int)scale_list.size(), scale_total);
     }
     if (!need_restart.empty()) {
       // true residual r = rhs - A x of the systems that exhausted a cycle

@@ -133,6 +133,8 @@ struct pqn_ctx_impl {
   DevArray<double> hdev;
   std::vector<double> hhost;
   DevArray<FarDesc> fdesc;
+  DevArray<char> ddesc;  // segment descriptors of the multi-suspension kernels
+  char* push_desc_pack(const std::vector<char>& pack);
   // profiling of far launches
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   size_t ev_used = 0;
@@ -156,6 +158,7 @@ struct pqn_ctx_impl {
   void set_configuration(const double* c, const double* ax);
   // operator on groups of densities (all on this context's stream)
   void matvec_groups(std::vector<MvGroup>& groups, int precision);
+  void matvec_batched(std::vector<MvGroup>& groups, int prec);
   void apply_operator(Level& lv, int precision, const double* q, double* y);
   // lockstep GMRES over systems; every system's x is overwritten (initial guess 0)
   void gmres_lockstep(std::vector<SysRef>& sys, int precision);

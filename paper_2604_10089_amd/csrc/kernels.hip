@@ -272,12 +272,12 @@ __global__ __launch_bounds__(256) void k_far64_multi(const FarDesc* __restrict__
 // harmonic coefficients are wave-uniform (scalar loads). K densities share r.
 
 template <int K>
-__global__ __launch_bounds__(64) void k_near64(const double* __restrict__ ctr, const double* __restrict__ off,
-                                               const double4* __restrict__ offup, QPtrs qup, QPtrs coef,
-                                               const int* __restrict__ npairs, int n, int M, int N, int nup, int p,
-                                               int L, double scale, OPtrs near_part) {
-  const int i = npairs[3 * blockIdx.x], j = npairs[3 * blockIdx.x + 1], slot = npairs[3 * blockIdx.x + 2];
-  const int k = blockIdx.y * 64 + threadIdx.x;
+__device__ __forceinline__ void near_body(int pair, int chunk, const double* __restrict__ ctr,
+                                          const double* __restrict__ off, const double4* __restrict__ offup,
+                                          const QPtrs& qup, const QPtrs& coef, const int* __restrict__ npairs, int n,
+                                          int M, int N, int nup, int p, int L, double scale, const OPtrs& near_part) {
+  const int i = npairs[3 * pair], j = npairs[3 * pair + 1], slot = npairs[3 * pair + 2];
+  const int k = chunk * 64 + threadIdx.x;
   const bool valid = k < n;
   const int kk = valid ? k : n - 1;
   const int t = i * n + kk;
@@ -334,6 +334,14 @@ __global__ __launch_bounds__(64) void k_near64(const double* __restrict__ ctr, c
     }
 }
 
+template <int K>
+__global__ __launch_bounds__(64) void k_near64(const double* __restrict__ ctr, const double* __restrict__ off,
+                                               const double4* __restrict__ offup, QPtrs qup, QPtrs coef,
+                                               const int* __restrict__ npairs, int n, int M, int N, int nup, int p,
+                                               int L, double scale, OPtrs near_part) {
+  near_body<K>(blockIdx.x, blockIdx.y, ctr, off, offup, qup, coef, npairs, n, M, N, nup, p, L, scale, near_part);
+}
+
 // ------------------------------------------------------------------ GEMM
 //
 // C(r, col) = sum_k A[r * lda + k] * B(k, col), FP64, 64x64 tiles, BK = 16.
@@ -344,17 +352,14 @@ __global__ __launch_bounds__(64) void k_near64(const double* __restrict__ ctr, c
 constexpr int GBM = 32, GBN = 32, GBK = 16;
 
 // One wave per 32x32 output tile, 4x4 outputs per lane (rows ty+8e, cols tx+8f).
-__global__ __launch_bounds__(64) void k_gemm64(int R, int Cn, int K, const double* __restrict__ A, int lda, long Az,
-                                               const double* __restrict__ B, long Bz, int kb, long kbs, int ldb,
-                                               double* __restrict__ C, long Cz, int rb, long rbs, int ldc) {
+__device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, const double* __restrict__ A,
+                                          int lda, const double* __restrict__ B, int kb, long kbs, int ldb,
+                                          double* __restrict__ C, int rb, long rbs, int ldc) {
   __shared__ double As[GBK][GBM + 1];
   __shared__ double Bs[GBK][GBN + 1];
   const int tid = threadIdx.x;
   const int tx = tid % 8, ty = tid / 8;
-  const int r0 = blockIdx.x * GBM, c0 = blockIdx.y * GBN;
-  A += (size_t)blockIdx.z * Az;
-  B += (size_t)blockIdx.z * Bz;
-  C += (size_t)blockIdx.z * Cz;
+  const int r0 = bx * GBM, c0 = by * GBN;
   double acc[4][4] = {};
   for (int k0 = 0; k0 < K; k0 += GBK) {
 #pragma unroll
@@ -393,6 +398,13 @@ __global__ __launch_bounds__(64) void k_gemm64(int R, int Cn, int K, const doubl
       if (gc < Cn) C[(size_t)(gr / rb) * rbs + (size_t)gc * ldc + gr % rb] = acc[e][f];
     }
   }
+}
+
+__global__ __launch_bounds__(64) void k_gemm64(int R, int Cn, int K, const double* __restrict__ A, int lda, long Az,
+                                               const double* __restrict__ B, long Bz, int kb, long kbs, int ldb,
+                                               double* __restrict__ C, long Cz, int rb, long rbs, int ldc) {
+  gemm_tile(blockIdx.x, blockIdx.y, R, Cn, K, A + (size_t)blockIdx.z * Az, lda, B + (size_t)blockIdx.z * Bz, kb, kbs,
+            ldb, C + (size_t)blockIdx.z * Cz, rb, rbs, ldc);
 }
 
 // ------------------------------------------------- completion and slip RHS
@@ -445,10 +457,8 @@ __global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ ctr, con
 // ------------------------------------------ rigid moments and projection
 
 // mom[j] = (sum w q, sum w o x q) over the nodes of sphere j (one block each).
-__global__ __launch_bounds__(256) void k_moments(const double* __restrict__ q, const double* __restrict__ off,
-                                                 const double* __restrict__ w, int n, int N,
-                                                 double* __restrict__ mom) {
-  const int j = blockIdx.x;
+__device__ __forceinline__ void moments_body(int j, const double* __restrict__ q, const double* __restrict__ off,
+                                             const double* __restrict__ w, int n, int N, double* __restrict__ mom) {
   double m[6] = {0, 0, 0, 0, 0, 0};
   for (int k = threadIdx.x; k < n; k += 256) {
     const int t = j * n + k;
@@ -474,6 +484,12 @@ __global__ __launch_bounds__(256) void k_moments(const double* __restrict__ q, c
   if (threadIdx.x < 6) mom[6 * j + threadIdx.x] = red[threadIdx.x][0];
 }
 
+__global__ __launch_bounds__(256) void k_moments(const double* __restrict__ q, const double* __restrict__ off,
+                                                 const double* __restrict__ w, int n, int N,
+                                                 double* __restrict__ mom) {
+  moments_body(blockIdx.x, q, off, w, n, N, mom);
+}
+
 // UO[j] = -(f/(4 pi a^2), 3 t/(8 pi a^4)): the rigid motion -P_j[q].
 __global__ void k_rigid_velocity(const double* __restrict__ mom, int M, double a, double* __restrict__ UO) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -486,13 +502,11 @@ __global__ void k_rigid_velocity(const double* __restrict__ mom, int M, double a
 }
 
 // y = q/2 + sum(self partials) + sum(far partials) + sum(near partials) + P[q].
-__global__ __launch_bounds__(256) void k_combine(const double* __restrict__ q, const double* __restrict__ selfo,
-                                                 int nself, const double* __restrict__ far_part, int nchunks,
-                                                 const double* __restrict__ near_part, const int* __restrict__ npart,
-                                                 const double* __restrict__ mom, const double* __restrict__ off,
-                                                 int n, int N, double a, double* __restrict__ y) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= N) return;
+__device__ __forceinline__ void combine_elem(int t, const double* __restrict__ q, const double* __restrict__ selfo,
+                                             int nself, const double* __restrict__ far_part, int nchunks,
+                                             const double* __restrict__ near_part, const int* __restrict__ npart,
+                                             const double* __restrict__ mom, const double* __restrict__ off, int n,
+                                             int N, double a, double* __restrict__ y) {
   const int i = t / n, k = t - i * n;
   const double s1 = 1.0 / (4.0 * kPi * a * a), s2 = 3.0 / (8.0 * kPi * a * a * a * a);
   const double* mj = mom + 6 * i;
@@ -509,6 +523,15 @@ __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ q, c
     for (int h = 0; h < np; ++h) v += near_part[(size_t)h * 3 * N + e];
     y[e] = v;
   }
+}
+
+__global__ __launch_bounds__(256) void k_combine(const double* __restrict__ q, const double* __restrict__ selfo,
+                                                 int nself, const double* __restrict__ far_part, int nchunks,
+                                                 const double* __restrict__ near_part, const int* __restrict__ npart,
+                                                 const double* __restrict__ mom, const double* __restrict__ off,
+                                                 int n, int N, double a, double* __restrict__ y) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t < N) combine_elem(t, q, selfo, nself, far_part, nchunks, near_part, npart, mom, off, n, N, a, y);
 }
 
 // ---------------------------------------------------------------- Arnoldi
@@ -567,6 +590,125 @@ __global__ __launch_bounds__(256) void k_axpby(double* __restrict__ y, const dou
                                                double b, long len) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e < len) y[e] = a * x[e] + b * y[e];
+}
+
+// ----------------------------------------------- many suspensions at once
+//
+// Every per-iteration kernel of the batched GMRES has a segmented form: one
+// launch covers all systems; a descriptor table gives each system's pointers
+// and sizes, and `start` is the first block (or element, or vector) of that
+// system in the launch. Blocks find their system by binary search.
+
+template <class D>
+__device__ __forceinline__ int find_seg(const D* __restrict__ d, int nd, int idx) {
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].start <= idx)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(64) void k_gemm64_multi(const GemmDesc* __restrict__ d, int nd) {
+  const int b = blockIdx.x;
+  const GemmDesc D = d[find_seg(d, nd, b)];
+  const int local = b - D.start;
+  gemm_tile(local % D.tr, local / D.tr, D.R, D.Cn, D.K, D.A, D.lda, D.B, D.kb, D.kbs, D.ldb, D.C, D.rb, D.rbs, D.ldc);
+}
+
+__global__ __launch_bounds__(256) void k_pack_multi(const PackDesc* __restrict__ d, int nd, int fp32) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const PackDesc D = d[find_seg(d, nd, g)];
+  const int t = g - D.start;
+  if (t < 0 || t >= D.N) return;
+  const int k = t % D.n;
+  const double wk = D.w[k];
+  if (fp32) {
+    float* e = (float*)D.src + (size_t)t * src32_stride(1);
+    e[0] = (float)D.off[3 * k];
+    e[1] = (float)D.off[3 * k + 1];
+    e[2] = (float)D.off[3 * k + 2];
+    for (int c = 0; c < 3; ++c) e[3 + c] = (float)(wk * D.q[(size_t)c * D.N + t]);
+    e[6] = e[7] = 0.f;
+  } else {
+    double* e = (double*)D.src + (size_t)t * src64_stride(1);
+    e[0] = D.off[3 * k];
+    e[1] = D.off[3 * k + 1];
+    e[2] = D.off[3 * k + 2];
+    for (int c = 0; c < 3; ++c) e[3 + c] = wk * D.q[(size_t)c * D.N + t];
+  }
+}
+
+__global__ __launch_bounds__(64) void k_near64_multi(const NearDesc* __restrict__ d, int nd) {
+  const int b = blockIdx.x;
+  const NearDesc D = d[find_seg(d, nd, b)];
+  const int local = b - D.start;
+  QPtrs qu{}, cf{};
+  OPtrs np{};
+  qu.p[0] = D.qup;
+  cf.p[0] = D.coef;
+  np.p[0] = D.part;
+  near_body<1>(local / D.nch, local % D.nch, D.ctr, D.off, D.offup, qu, cf, D.pairs, D.n, D.M, D.N, D.nup, D.p,
+               D.L, D.scale, np);
+}
+
+__global__ __launch_bounds__(256) void k_moments_multi(const MomDesc* __restrict__ d, int nd) {
+  const MomDesc D = d[find_seg(d, nd, blockIdx.x)];
+  moments_body(blockIdx.x - D.start, D.q, D.off, D.w, D.n, D.N, D.mom);
+}
+
+__global__ __launch_bounds__(256) void k_combine_multi(const CombDesc* __restrict__ d, int nd) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const CombDesc D = d[find_seg(d, nd, g)];
+  const int t = g - D.start;
+  if (t < 0 || t >= D.N) return;
+  combine_elem(t, D.q, D.selfo, 3, D.far, D.nchunks, D.near, D.npart, D.mom, D.off, D.n, D.N, D.a, D.y);
+}
+
+// partial[v][b] for the vectors of every system (grid: nb x total vectors)
+__global__ __launch_bounds__(256) void k_dots_multi(const DotDesc* __restrict__ d, int nd) {
+  const DotDesc D = d[find_seg(d, nd, blockIdx.y)];
+  const int v = blockIdx.y - D.start;
+  const double* x = D.V + (size_t)v * D.ldv;
+  double s = 0.0;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < D.len; e += (long)gridDim.x * 256) s = fma(x[e], D.w[e], s);
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) D.partial[(size_t)v * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_dots_finish_multi(const DotDesc* __restrict__ d, int nd, int nb) {
+  const DotDesc D = d[find_seg(d, nd, blockIdx.x)];
+  const int v = blockIdx.x - D.start;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) s += D.partial[(size_t)v * nb + b];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) D.out[v] = red[0];
+}
+
+// w = beta w + alpha sum_v h[v] V_v for every system (elementwise, segmented)
+__global__ __launch_bounds__(256) void k_combo_multi(const ComboDesc* __restrict__ d, int nd) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const ComboDesc D = d[find_seg(d, nd, g)];
+  const long e = g - D.start;
+  if (e < 0 || e >= D.len) return;
+  double s = 0.0;
+  for (int v = 0; v < D.nvec; ++v) s = fma(D.h[v], D.V[(size_t)v * D.ldv + e], s);
+  D.w[e] = (D.beta == 0.0 ? 0.0 : D.beta * D.w[e]) + D.alpha * s;
 }
 
 // ------------------------------------------------------------- launchers
@@ -692,4 +834,31 @@ void launch_axpby(hipStream_t s, double* y, const double* x, double a, double b,
   hipLaunchKernelGGL(k_axpby, dim3(nblk(len)), dim3(256), 0, s, y, x, a, b, len);
 }
 
+}  // namespace bipqn
+
+namespace bipqn {
+static inline unsigned nblk2(long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+void launch_gemm64_multi(hipStream_t s, const GemmDesc* d, int nd, int nblocks) {
+  if (nblocks > 0) hipLaunchKernelGGL(k_gemm64_multi, dim3(nblocks), dim3(64), 0, s, d, nd);
+}
+void launch_pack_multi(hipStream_t s, const PackDesc* d, int nd, int total, int fp32) {
+  if (total > 0) hipLaunchKernelGGL(k_pack_multi, dim3(nblk2(total)), dim3(256), 0, s, d, nd, fp32);
+}
+void launch_near_multi(hipStream_t s, const NearDesc* d, int nd, int nblocks) {
+  if (nblocks > 0) hipLaunchKernelGGL(k_near64_multi, dim3(nblocks), dim3(64), 0, s, d, nd);
+}
+void launch_moments_multi(hipStream_t s, const MomDesc* d, int nd, int nblocks) {
+  if (nblocks > 0) hipLaunchKernelGGL(k_moments_multi, dim3(nblocks), dim3(256), 0, s, d, nd);
+}
+void launch_combine_multi(hipStream_t s, const CombDesc* d, int nd, int total) {
+  if (total > 0) hipLaunchKernelGGL(k_combine_multi, dim3(nblk2(total)), dim3(256), 0, s, d, nd);
+}
+void launch_dots_multi(hipStream_t s, const DotDesc* d, int nd, int nvec_total, int nb) {
+  if (nvec_total <= 0) return;
+  hipLaunchKernelGGL(k_dots_multi, dim3(nb, nvec_total), dim3(256), 0, s, d, nd);
+  hipLaunchKernelGGL(k_dots_finish_multi, dim3(nvec_total), dim3(256), 0, s, d, nd, nb);
+}
+void launch_combo_multi(hipStream_t s, const ComboDesc* d, int nd, int total) {
+  if (total > 0) hipLaunchKernelGGL(k_combo_multi, dim3(nblk2(total)), dim3(256), 0, s, d, nd);
+}
 }  // namespace bipqn

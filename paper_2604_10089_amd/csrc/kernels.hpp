@@ -27,6 +27,78 @@ struct FarDesc {
   double scale;
 };
 
+// Segment descriptors of the multi-suspension kernels; `start` is the first
+// block (GEMM, near, moments), element (pack, combine, combo) or vector (dots)
+// of the segment in the launch.
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  long kbs, rbs;
+  int R, Cn, K, lda, kb, ldb, rb, ldc, tr, start;
+};
+struct PackDesc {
+  const double* q;
+  const double* off;
+  const double* w;
+  void* src;
+  int n, N, start;
+};
+struct NearDesc {
+  const double* ctr;
+  const double* off;
+  const double4* offup;
+  const double* qup;
+  const double* coef;
+  const int* pairs;
+  double* part;
+  double scale;
+  int n, M, N, nup, p, L, nch, start;
+};
+struct MomDesc {
+  const double* q;
+  const double* off;
+  const double* w;
+  double* mom;
+  int n, N, start;
+};
+struct CombDesc {
+  const double* q;
+  const double* selfo;
+  const double* far;
+  const double* near;
+  const int* npart;
+  const double* mom;
+  const double* off;
+  double* y;
+  double a;
+  int nchunks, n, N, start;
+};
+struct DotDesc {
+  const double* V;
+  const double* w;
+  double* partial;
+  double* out;
+  long ldv, len;
+  int start;
+};
+struct ComboDesc {
+  double* w;
+  const double* V;
+  const double* h;
+  double alpha, beta;
+  long ldv, len;
+  int nvec, start;
+};
+
+void launch_gemm64_multi(hipStream_t s, const GemmDesc* d, int nd, int nblocks);
+void launch_pack_multi(hipStream_t s, const PackDesc* d, int nd, int total, int fp32);
+void launch_near_multi(hipStream_t s, const NearDesc* d, int nd, int nblocks);
+void launch_moments_multi(hipStream_t s, const MomDesc* d, int nd, int nblocks);
+void launch_combine_multi(hipStream_t s, const CombDesc* d, int nd, int total);
+void launch_dots_multi(hipStream_t s, const DotDesc* d, int nd, int nvec_total, int nb);
+void launch_combo_multi(hipStream_t s, const ComboDesc* d, int nd, int total);
+
 // prec: 0 = FP64 pair sums, 1 = FP32 pair sums (mixed)
 void launch_pack(hipStream_t s, int prec, int K, const QPtrs& q, const double* off, const double* w, int n, int N,
                  void* src);
