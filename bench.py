@@ -32,6 +32,28 @@ PEAK_FP32_NONPACKED = 78.6    # TFLOP/s, 256 CU x 64 lanes x 2 flop x 2.4 GHz (n
 K_RHS = 6
 PROBE_BYTES = 256 << 20       # reference copy for the HBM byte counters
 
+# HBM bytes of one k_far32<1,6> launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# (profiles/k_far32_rsa216_hbm_traffic.md), scaled by what the counters read for a
+# 256 MiB copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0). Valid only for the far-kernel
+# source it was measured on: reported as null once that source changes.
+FAR_TRAFFIC = {'kernel': 'k_far32<1,6>', 'source_sha1': '64873811609cbfcc4edb2a5406ed271fee0fd600',
+               'fetch_kib': 47096.68, 'write_kib': 271188.0, 'fetch_scale': 2.0, 'write_scale': 1.0}
+
+
+def far_source_sha1():
+    import hashlib
+    src = open(os.path.join(ROOT, 'paper_2604_10089_amd', 'csrc', 'kernels.hip')).read()
+    a = src.index('// ----------------------------------------------------------- far pair sum')
+    b = src.index('template <int K>\n__device__ __forceinline__ void far64_body')
+    return hashlib.sha1(src[a:b].encode()).hexdigest()
+
+
+def far_traffic_bytes():
+    t = FAR_TRAFFIC
+    if far_source_sha1() != t['source_sha1']:
+        return None
+    return int(1024 * (t['fetch_kib'] * t['fetch_scale'] + t['write_kib'] * t['write_scale']))
+
 
 def flop_per_pair(K):
     """Algorithmic flops of one far pair with K densities (FMA = 2, rsqrt = 1): 18 shared + 12 per density."""
@@ -56,11 +78,11 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-lcp', action='store_true')
     ap.add_argument('--no-batch', action='store_true')
-    ap.add_argument('--tpt', type=int, default=2)
-    ap.add_argument('--chunks', type=int, default=0)
+    ap.add_argument('--tpt', type=int, default=None, help='targets per thread (default: autotuned)')
+    ap.add_argument('--chunks', type=int, default=None, help='far source chunks (default: autotuned)')
     ap.add_argument('--counters-probe', action='store_true',
                     help='short run for rocprofv3 --pmc: a 256 MiB device copy (scale reference for FETCH_SIZE/'
-                         'WRITE_SIZE) and one single-force-set product on the 216-sphere workload')
+                         'WRITE_SIZE) and one six-force-set product on the 216-sphere workload')
     args = ap.parse_args()
     if args.gpus != 1:
         print(f'bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on one MI355X; '
@@ -86,7 +108,7 @@ def main():
 
     def ctx_for(prec, profile=True):
         return binding.Context(c, None, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision=prec, tpt=args.tpt,
-                               far_chunks=args.chunks, stream=stream.cuda_stream, profile=profile)
+                               far_chunks=args.chunks, stream=stream.cuda_stream, profile=profile, tune_K=K_RHS)
 
     FT6 = [inputs.random_forces(100 + k, M, k=K_RHS) for k in range(max(K, 2) + W + 2)]
 
@@ -97,7 +119,7 @@ def main():
         dst.copy_(ref)                      # reads and writes PROBE_BYTES once each
         torch.cuda.synchronize()
         cm = ctx_for('mixed', profile=False)
-        _, st = cm.mobility_apply_multi(FT6[0][:1])
+        _, st = cm.mobility_apply_multi(FT6[0])
         torch.cuda.synchronize()
         cm.close()
         print(json.dumps({'probe_bytes': PROBE_BYTES, 'far_launches': st['n_far'],
@@ -167,7 +189,7 @@ def main():
     if not args.no_batch:
         inst = inputs.batched_suspensions(args.seed)
         FTb = [inputs.random_forces(500 + b, ci.shape[0]) for b, (ci, _, _) in enumerate(inst)]
-        kw = dict(gmres_tol=1e-8, precision='mixed', tpt=args.tpt, stream=stream.cuda_stream)
+        kw = dict(gmres_tol=1e-8, precision='mixed', tpt=args.tpt or 2, stream=stream.cuda_stream)
         with binding.BatchContext(inst, **kw) as bc:
             bc.mobility_apply(FTb)
             torch.cuda.synchronize()
@@ -219,7 +241,8 @@ def main():
         'roofline': {'bound': 'alu', 'kernel': 'k_far32<1,6>', 'achieved': round(achieved, 3),
                      'peak': PEAK_FP32_VECTOR, 'unit': 'TFLOP/s', 'frac': round(achieved / PEAK_FP32_VECTOR, 4),
                      'frac_of_nonpacked_peak': round(achieved / PEAK_FP32_NONPACKED, 4),
-                     'flop_per_pair': flop_per_pair(K_RHS), 'traffic': None,
+                     'flop_per_pair': flop_per_pair(K_RHS), 'traffic': far_traffic_bytes(),
+                     'traffic_unit': 'HBM bytes per launch',
                      'k1': {'kernel': 'k_far32<2,1>', 'achieved': round(achieved1, 3),
                             'frac': round(achieved1 / PEAK_FP32_VECTOR, 4)}},
         'lcp': lcp_info,

@@ -204,15 +204,33 @@ class BatchContext:
         return U, dict(_struct_dict(st), status=status)
 
 
+def tuned_shape(precision, K, M, n):
+    """(tpt, far_chunks) from the autotuner's cache for this shape, else the library defaults."""
+    try:
+        from paper_2604_10089_amd import autotune
+        hit = autotune.lookup(precision, K, M, n)
+    except Exception:
+        hit = None
+    return hit if hit is not None else (2, 0)
+
+
 class Context:
-    """Owns one pqn_ctx. Methods carry the C ABI names without the prefix."""
+    """Owns one pqn_ctx. Methods carry the C ABI names without the prefix.
+
+    tpt / far_chunks = None take the autotuned launch shape for (precision,
+    single density, sphere count, grid) when the cache has one.
+    """
 
     def __init__(self, centers, axes=None, n_theta=8, n_phi=16, lo=None, radius=1.0, mu=1.0,
                  gmres_tol=1e-8, gmres_tol_lo=None, restart=50, max_iter=500, near_gap=0.0, near_up=2,
-                 slip=1.0, precision='fp64', refine=0, tpt=2, far_chunks=0, device=0, stream=None,
-                 profile=False):
+                 slip=1.0, precision='fp64', refine=0, tpt=None, far_chunks=None, device=0, stream=None,
+                 profile=False, tune_K=1):
         c = _f64(centers).reshape(-1, 3)
         self.M = c.shape[0]
+        if tpt is None or far_chunks is None:
+            t2, c2 = tuned_shape(precision, tune_K, self.M, n_theta * n_phi)
+            tpt = t2 if tpt is None else tpt
+            far_chunks = c2 if far_chunks is None else far_chunks
         d = ConfigDesc()
         d.n_particles = self.M
         d.radius, d.mu = radius, mu

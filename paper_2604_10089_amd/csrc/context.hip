@@ -21,6 +21,14 @@ struct DescPack {
   }
 };
 
+// One GEMM problem of a segmented launch: C(r, col) = sum_k A[r lda + k] B[col ldb + k].
+static void push_gemm(std::vector<GemmDesc>& v, int& blocks, int R, int Cn, int K, const double* A, int lda,
+                      const double* B, int ldb, double* C, int rb, long rbs, int ldc) {
+  GemmDesc d{A, B, C, rbs, R, Cn, K, lda, ldb, rb, ldc, (R + 31) / 32, blocks};
+  blocks += d.tr * ((Cn + 31) / 32);
+  v.push_back(d);
+}
+
 char* pqn_ctx_impl::push_desc_pack(const std::vector<char>& pack) {
   if (pack.size() > ddesc.count) {
     // growing the table: wait for kernels still reading the old one
@@ -200,57 +208,32 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
     pqn_ctx_impl& c = *gr.c;
     const int n = lv.n, N = lv.N, L = lv.L, nup = lv.nup, M = lv.M;
     QPtrs qp{};
+    std::vector<GemmDesc> ga, gb;
+    int nga = 0, ngb = 0;
     for (int r = 0; r < gr.K; ++r) {
       Work& w = lv.wk(gr.slot0 + r);
-      // harmonic coefficients of every sphere's density (per component): coef = T q
-      launch_gemm64(s, L, M, n, lv.T.p, n, 0, gr.in[r], N, n, 0, n, w.coef.p, (long)M * L, L, 0, L, 3);
-      // singular self interaction on the coefficients, one partial per source component
-      launch_gemm64(s, 3 * n, M, L, lv.G.p, 3 * L, L, w.coef.p, (long)M * L, L, 0, L, w.selfo.p, 3L * N, n, N, n,
-                    3);
-      if (c.n_near > 0)  // density on the upsampled grid of every sphere: qup = Yup coef
-        launch_gemm64(s, nup, M, L, lv.Yup.p, L, 0, w.coef.p, (long)M * L, L, 0, L, w.qup.p, (long)M * nup, nup, 0,
-                      nup, 3);
+      for (int comp = 0; comp < 3; ++comp) {
+        // harmonic coefficients of every sphere's density: coef = T q
+        push_gemm(ga, nga, L, M, n, lv.T.p, n, gr.in[r] + (size_t)comp * N, n, w.coef.p + (size_t)comp * M * L, L, 0,
+                  L);
+        // singular self interaction on the coefficients, one partial per source component
+        push_gemm(gb, ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, w.coef.p + (size_t)comp * M * L, L,
+                  w.selfo.p + (size_t)comp * 3 * N, n, N, n);
+        if (c.n_near > 0)  // density on the upsampled grid of every sphere: qup = Yup coef
+          push_gemm(gb, ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L,
+                    w.qup.p + (size_t)comp * M * nup, nup, 0, nup);
+      }
       qp.p[r] = gr.in[r];
     }
+    DescPack dp;
+    const size_t oa = dp.add(ga), ob = dp.add(gb);
+    char* base = push_desc_pack(dp.host);
+    launch_gemm64_multi(s, (const GemmDesc*)(base + oa), (int)ga.size(), nga);
+    launch_gemm64_multi(s, (const GemmDesc*)(base + ob), (int)gb.size(), ngb);
     launch_pack(s, prec, gr.K, qp, lv.off.p, lv.w.p, n, N, lv.src.p);
-    if (gr.K != 1) all_single = false;
   }
   begin_far_timing();
-  if (all_single) {
-    // every suspension's far pair sum in one launch, largest tiles first
-    struct Item {
-      FarDesc d;
-      long cost;
-    };
-    std::vector<Item> items;
-    const int tpt = cfg.targets_per_thread == 1 ? 1 : 2;
-    for (MvGroup& gr : groups) {
-      Level& lv = *gr.lv;
-      FarDesc d{};
-      d.src = lv.src.p;
-      d.off = lv.off.p;
-      d.ctr = gr.c->ctr.p;
-      d.cls = gr.c->cls.p;
-      d.part = lv.wk(gr.slot0).far_part.p;
-      d.n = lv.n;
-      d.M = lv.M;
-      d.N = lv.N;
-      d.spc = lv.spc;
-      d.ntb = prec == 1 ? (lv.N + 256 * tpt - 1) / (256 * tpt) : (lv.N + 255) / 256;
-      d.scale = 3.0 / (4.0 * kPi * gr.c->a);
-      items.push_back({d, (long)lv.n * lv.n * lv.spc});
-    }
-    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
-    std::vector<FarDesc> ds;
-    int total = 0;
-    for (Item& it : items) {
-      it.d.item0 = total;
-      total += it.d.ntb * ((it.d.M + it.d.spc - 1) / it.d.spc);
-      ds.push_back(it.d);
-    }
-    fdesc.upload(ds.data(), ds.size(), s);
-    launch_far_multi(s, prec, tpt, fdesc.p, (int)ds.size(), total);
-  } else {
+  {
     for (MvGroup& gr : groups) {
       Level& lv = *gr.lv;
       OPtrs op{};
@@ -295,25 +278,20 @@ void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
   std::vector<MomDesc> md;
   std::vector<CombDesc> cd;
   int nga = 0, ngb = 0, npk = 0, nnd = 0, nmd = 0, ncd = 0;
-  auto gemm = [](std::vector<GemmDesc>& v, int& blocks, int R, int Cn, int K, const double* A, int lda,
-                 const double* B, int kb, long kbs, int ldb, double* C, int rb, long rbs, int ldc) {
-    GemmDesc d{A, B, C, kbs, rbs, R, Cn, K, lda, kb, ldb, rb, ldc, (R + 31) / 32, blocks};
-    blocks += d.tr * ((Cn + 31) / 32);
-    v.push_back(d);
-  };
+
   for (MvGroup& gr : groups) {
     Level& lv = *gr.lv;
     pqn_ctx_impl& c = *gr.c;
     Work& w = lv.wk(gr.slot0);
     const int n = lv.n, N = lv.N, L = lv.L, nup = lv.nup, M = lv.M;
     for (int comp = 0; comp < 3; ++comp) {
-      gemm(ga, nga, L, M, n, lv.T.p, n, gr.in[0] + (size_t)comp * N, n, 0, n, w.coef.p + (size_t)comp * M * L, L, 0,
-           L);
-      gemm(gb, ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, w.coef.p + (size_t)comp * M * L, L, 0, L,
-           w.selfo.p + (size_t)comp * 3 * N, n, N, n);
+      push_gemm(ga, nga, L, M, n, lv.T.p, n, gr.in[0] + (size_t)comp * N, n, w.coef.p + (size_t)comp * M * L, L, 0,
+                L);
+      push_gemm(gb, ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, w.coef.p + (size_t)comp * M * L, L,
+                w.selfo.p + (size_t)comp * 3 * N, n, N, n);
       if (c.n_near > 0)
-        gemm(gb, ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L, 0, L,
-             w.qup.p + (size_t)comp * M * nup, nup, 0, nup);
+        push_gemm(gb, ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L,
+                  w.qup.p + (size_t)comp * M * nup, nup, 0, nup);
     }
     pk.push_back(PackDesc{gr.in[0], lv.off.p, lv.w.p, lv.src.p, n, N, npk});
     npk += N;
@@ -327,7 +305,7 @@ void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
     nmd += M;
     cd.push_back(CombDesc{gr.in[0], w.selfo.p, w.far_part.p, w.near_part.p, c.npart.p, w.mom.p, lv.off.p, gr.out[0],
                           c.a, lv.nchunks, n, N, ncd});
-    ncd += N;
+    ncd += 3 * N;
   }
   DescPack dp;
   const size_t oa = dp.add(ga), ob = dp.add(gb), op = dp.add(pk), on = dp.add(nd), om = dp.add(md), oc = dp.add(cd);

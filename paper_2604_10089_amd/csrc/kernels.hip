@@ -352,9 +352,12 @@ __global__ __launch_bounds__(64) void k_near64(const double* __restrict__ ctr, c
 constexpr int GBM = 32, GBN = 32, GBK = 16;
 
 // One wave per 32x32 output tile, 4x4 outputs per lane (rows ty+8e, cols tx+8f).
+// A is row-major (lda); B(k, col) = B[col * ldb + k] (k contiguous); C(r, col)
+// is stored at C[(r / rb) * rbs + col * ldc + r % rb]. Tile loads run along k,
+// so consecutive lanes read consecutive addresses of A rows and B columns.
 __device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, const double* __restrict__ A,
-                                          int lda, const double* __restrict__ B, int kb, long kbs, int ldb,
-                                          double* __restrict__ C, int rb, long rbs, int ldc) {
+                                          int lda, const double* __restrict__ B, int ldb, double* __restrict__ C,
+                                          int rb, long rbs, int ldc) {
   __shared__ double As[GBK][GBM + 1];
   __shared__ double Bs[GBK][GBN + 1];
   const int tid = threadIdx.x;
@@ -364,13 +367,12 @@ __device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, 
   for (int k0 = 0; k0 < K; k0 += GBK) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int idx = tid + e * 64;         // 0..511
-      const int ar = idx / GBK, ak = idx % GBK;
-      const int gr = r0 + ar, gk = k0 + ak;
-      As[ak][ar] = (gr < R && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
-      const int bk = idx / GBN, bc = idx % GBN;
-      const int gk2 = k0 + bk, gc = c0 + bc;
-      Bs[bk][bc] = (gk2 < K && gc < Cn) ? B[(size_t)(gk2 / kb) * kbs + (size_t)gc * ldb + gk2 % kb] : 0.0;
+      const int idx = tid + e * 64;          // 0..511: k fastest
+      const int kk = idx % GBK, rc = idx / GBK;
+      const int gk = k0 + kk;
+      const int gr = r0 + rc, gc = c0 + rc;
+      As[kk][rc] = (gr < R && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
+      Bs[kk][rc] = (gc < Cn && gk < K) ? B[(size_t)gc * ldb + gk] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -392,19 +394,20 @@ __device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, 
   for (int e = 0; e < 4; ++e) {
     const int gr = r0 + ty + 8 * e;
     if (gr >= R) continue;
+    const size_t rowbase = (size_t)(gr / rb) * rbs + gr % rb;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       const int gc = c0 + tx + 8 * f;
-      if (gc < Cn) C[(size_t)(gr / rb) * rbs + (size_t)gc * ldc + gr % rb] = acc[e][f];
+      if (gc < Cn) C[rowbase + (size_t)gc * ldc] = acc[e][f];
     }
   }
 }
 
 __global__ __launch_bounds__(64) void k_gemm64(int R, int Cn, int K, const double* __restrict__ A, int lda, long Az,
-                                               const double* __restrict__ B, long Bz, int kb, long kbs, int ldb,
+                                               const double* __restrict__ B, long Bz, int ldb,
                                                double* __restrict__ C, long Cz, int rb, long rbs, int ldc) {
-  gemm_tile(blockIdx.x, blockIdx.y, R, Cn, K, A + (size_t)blockIdx.z * Az, lda, B + (size_t)blockIdx.z * Bz, kb, kbs,
-            ldb, C + (size_t)blockIdx.z * Cz, rb, rbs, ldc);
+  gemm_tile(blockIdx.x, blockIdx.y, R, Cn, K, A + (size_t)blockIdx.z * Az, lda, B + (size_t)blockIdx.z * Bz, ldb,
+            C + (size_t)blockIdx.z * Cz, rb, rbs, ldc);
 }
 
 // ------------------------------------------------- completion and slip RHS
@@ -501,28 +504,31 @@ __global__ void k_rigid_velocity(const double* __restrict__ mom, int M, double a
   }
 }
 
-// y = q/2 + sum(self partials) + sum(far partials) + sum(near partials) + P[q].
-__device__ __forceinline__ void combine_elem(int t, const double* __restrict__ q, const double* __restrict__ selfo,
+// y = q/2 + sum(self partials) + sum(far partials) + sum(near partials) + P[q],
+// one thread per (component, node): element e = c * N + t.
+__device__ __forceinline__ void combine_elem(int e, const double* __restrict__ q, const double* __restrict__ selfo,
                                              int nself, const double* __restrict__ far_part, int nchunks,
                                              const double* __restrict__ near_part, const int* __restrict__ npart,
                                              const double* __restrict__ mom, const double* __restrict__ off, int n,
                                              int N, double a, double* __restrict__ y) {
+  const int c = e / N, t = e - c * N;
   const int i = t / n, k = t - i * n;
   const double s1 = 1.0 / (4.0 * kPi * a * a), s2 = 3.0 / (8.0 * kPi * a * a * a * a);
   const double* mj = mom + 6 * i;
   const double ox = off[3 * k], oy = off[3 * k + 1], oz = off[3 * k + 2];
-  const double P[3] = {s1 * mj[0] + s2 * (mj[4] * oz - mj[5] * oy), s1 * mj[1] + s2 * (mj[5] * ox - mj[3] * oz),
-                       s1 * mj[2] + s2 * (mj[3] * oy - mj[4] * ox)};
+  double P;
+  if (c == 0)
+    P = s1 * mj[0] + s2 * (mj[4] * oz - mj[5] * oy);
+  else if (c == 1)
+    P = s1 * mj[1] + s2 * (mj[5] * ox - mj[3] * oz);
+  else
+    P = s1 * mj[2] + s2 * (mj[3] * oy - mj[4] * ox);
+  double v = 0.5 * q[e] + P;
+  for (int h = 0; h < nself; ++h) v += selfo[(size_t)h * 3 * N + e];
+  for (int h = 0; h < nchunks; ++h) v += far_part[(size_t)h * 3 * N + e];
   const int np = npart[i];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const size_t e = (size_t)c * N + t;
-    double v = 0.5 * q[e] + P[c];
-    for (int h = 0; h < nself; ++h) v += selfo[(size_t)h * 3 * N + e];
-    for (int h = 0; h < nchunks; ++h) v += far_part[(size_t)h * 3 * N + e];
-    for (int h = 0; h < np; ++h) v += near_part[(size_t)h * 3 * N + e];
-    y[e] = v;
-  }
+  for (int h = 0; h < np; ++h) v += near_part[(size_t)h * 3 * N + e];
+  y[e] = v;
 }
 
 __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ q, const double* __restrict__ selfo,
@@ -530,8 +536,8 @@ __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ q, c
                                                  const double* __restrict__ near_part, const int* __restrict__ npart,
                                                  const double* __restrict__ mom, const double* __restrict__ off,
                                                  int n, int N, double a, double* __restrict__ y) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t < N) combine_elem(t, q, selfo, nself, far_part, nchunks, near_part, npart, mom, off, n, N, a, y);
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e < 3 * N) combine_elem(e, q, selfo, nself, far_part, nchunks, near_part, npart, mom, off, n, N, a, y);
 }
 
 // ---------------------------------------------------------------- Arnoldi
@@ -616,7 +622,7 @@ __global__ __launch_bounds__(64) void k_gemm64_multi(const GemmDesc* __restrict_
   const int b = blockIdx.x;
   const GemmDesc D = d[find_seg(d, nd, b)];
   const int local = b - D.start;
-  gemm_tile(local % D.tr, local / D.tr, D.R, D.Cn, D.K, D.A, D.lda, D.B, D.kb, D.kbs, D.ldb, D.C, D.rb, D.rbs, D.ldc);
+  gemm_tile(local % D.tr, local / D.tr, D.R, D.Cn, D.K, D.A, D.lda, D.B, D.ldb, D.C, D.rb, D.rbs, D.ldc);
 }
 
 __global__ __launch_bounds__(256) void k_pack_multi(const PackDesc* __restrict__ d, int nd, int fp32) {
@@ -663,9 +669,9 @@ __global__ __launch_bounds__(256) void k_moments_multi(const MomDesc* __restrict
 __global__ __launch_bounds__(256) void k_combine_multi(const CombDesc* __restrict__ d, int nd) {
   const int g = blockIdx.x * 256 + threadIdx.x;
   const CombDesc D = d[find_seg(d, nd, g)];
-  const int t = g - D.start;
-  if (t < 0 || t >= D.N) return;
-  combine_elem(t, D.q, D.selfo, 3, D.far, D.nchunks, D.near, D.npart, D.mom, D.off, D.n, D.N, D.a, D.y);
+  const int e = g - D.start;
+  if (e < 0 || e >= 3 * D.N) return;
+  combine_elem(e, D.q, D.selfo, 3, D.far, D.nchunks, D.near, D.npart, D.mom, D.off, D.n, D.N, D.a, D.y);
 }
 
 // partial[v][b] for the vectors of every system (grid: nb x total vectors)
@@ -797,9 +803,9 @@ void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, cons
 }
 
 void launch_gemm64(hipStream_t s, int R, int Cn, int K, const double* A, int lda, long Az, const double* B, long Bz,
-                   int kb, long kbs, int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch) {
+                   int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch) {
   hipLaunchKernelGGL(k_gemm64, dim3((R + GBM - 1) / GBM, (Cn + GBN - 1) / GBN, batch), dim3(64), 0, s, R, Cn, K, A,
-                     lda, Az, B, Bz, kb, kbs, ldb, C, Cz, rb, rbs, ldc);
+                     lda, Az, B, Bz, ldb, C, Cz, rb, rbs, ldc);
 }
 void launch_rhs(hipStream_t s, const double* ctr, const double* FT, const double* axes, const double* off, int n,
                 int M, int N, double a, double mu, double slip, double* rhs) {
@@ -815,8 +821,8 @@ void launch_rigid_velocity(hipStream_t s, const double* mom, int M, double a, do
 void launch_combine(hipStream_t s, const double* q, const double* selfo, int nself, const double* far_part,
                     int nchunks, const double* near_part, const int* npart, const double* mom, const double* off,
                     int n, int N, double a, double* y) {
-  hipLaunchKernelGGL(k_combine, dim3(nblk(N)), dim3(256), 0, s, q, selfo, nself, far_part, nchunks, near_part, npart,
-                     mom, off, n, N, a, y);
+  hipLaunchKernelGGL(k_combine, dim3(nblk(3L * N)), dim3(256), 0, s, q, selfo, nself, far_part, nchunks, near_part,
+                     npart, mom, off, n, N, a, y);
 }
 void launch_dots(hipStream_t s, const double* V, long ldv, int nvec, const double* w, long len, int nb,
                  double* partial, double* out) {

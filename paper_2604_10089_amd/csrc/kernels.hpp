@@ -34,8 +34,8 @@ struct GemmDesc {
   const double* A;
   const double* B;
   double* C;
-  long kbs, rbs;
-  int R, Cn, K, lda, kb, ldb, rb, ldc, tr, start;
+  long rbs;
+  int R, Cn, K, lda, ldb, rb, ldc, tr, start;
 };
 struct PackDesc {
   const double* q;
@@ -108,8 +108,10 @@ void launch_far_multi(hipStream_t s, int prec, int tpt, const FarDesc* desc, int
 void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, const double* off, const double4* offup,
                  const QPtrs& qup, const QPtrs& coef, const int* npairs, int n, int M, int N, int nup, int p, int L,
                  double scale, const OPtrs& near_part);
+// C(r, col) = sum_k A[r * lda + k] B[col * ldb + k], stored at C[(r / rb) * rbs + col * ldc + r % rb];
+// grid z = batch with strides Az, Bz, Cz.
 void launch_gemm64(hipStream_t s, int R, int Cn, int K, const double* A, int lda, long Az, const double* B, long Bz,
-                   int kb, long kbs, int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch);
+                   int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch);
 
 void launch_rhs(hipStream_t s, const double* ctr, const double* FT, const double* axes, const double* off, int n,
                 int M, int N, double a, double mu, double slip, double* rhs);
