@@ -75,6 +75,8 @@ typedef struct {
   int32_t device;           /* HIP device ordinal [0] */
   void* stream;             /* hipStream_t to run on; NULL = the library creates one */
   int32_t profile;          /* 1 = time every far pair-sum launch with HIP events */
+  int32_t use_graphs;       /* 1 = replay each GMRES iteration of a single linear system from a
+                               captured hipGraph (one per Arnoldi index; ignored when profile = 1) */
 } pqn_config_desc;
 
 typedef struct {
@@ -86,6 +88,7 @@ typedef struct {
   double t_total_ms;        /* wall time of the call */
   double t_far_ms;          /* summed far pair-sum kernel time (profile = 1) */
   int32_t n_far;            /* far pair-sum launches */
+  int32_t graph_launches;   /* GMRES iterations replayed from captured graphs (use_graphs = 1) */
 } pqn_mvp_stats;
 
 typedef struct {

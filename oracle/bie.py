@@ -290,6 +290,18 @@ def near_block(geom, i, j):
     return blk
 
 
+def near_row(geom, i, j, k):
+    """Row (3, n, 3) of the near block for the single target node k of sphere i."""
+    X = geom.x[geom.nodes(i)][k:k + 1]
+    yf, nf, wf = near_sources(geom, j)
+    I = upsample_matrix(geom.n_theta, geom.n_phi, geom.near_up)
+    K = dl_kernel(X, yf, nf)[0] * wf[:, None, None]              # (nf, 3, 3)
+    u = (X[0] - geom.c[j]) / np.linalg.norm(X[0] - geom.c[j])
+    Ifoot = _grid.projection_to_points(geom.n_theta, geom.n_phi, np.array([np.arccos(np.clip(u[2], -1.0, 1.0))]),
+                                       np.array([np.arctan2(u[1], u[0])]))[0]
+    return np.einsum('fcd,fk->ckd', K, I) - np.einsum('cd,k->ckd', K.sum(axis=0), Ifoot)
+
+
 def offdiag_block(geom, i, j, near):
     """Dense (3n, 3n) block of D mapping q on sphere j to targets on sphere i."""
     if near:
@@ -375,7 +387,7 @@ def operator_rows(geom, q, targets):
                 continue
             sj = geom.nodes(j)
             if cls[i, j] == 1:
-                acc = acc + np.einsum('ckd,kd->c', near_block(geom, i, j)[k], q[sj])
+                acc = acc + np.einsum('ckd,kd->c', near_row(geom, i, j, k), q[sj])
             else:
                 acc = acc + dl_apply(xt, geom.x[sj], geom.normals[sj], wq[sj])[0]
         out[row] = acc

@@ -26,13 +26,13 @@ class ConfigDesc(C.Structure):
                 ('gmres_max_iter', C.c_int32), ('near_gap', C.c_double), ('near_up', C.c_int32),
                 ('slip_speed', C.c_double), ('precision', C.c_int32), ('refine_sweeps', C.c_int32),
                 ('targets_per_thread', C.c_int32), ('far_chunks', C.c_int32), ('device', C.c_int32),
-                ('stream', C.c_void_p), ('profile', C.c_int32)]
+                ('stream', C.c_void_p), ('profile', C.c_int32), ('use_graphs', C.c_int32)]
 
 
 class MvpStats(C.Structure):
     _fields_ = [('gmres_iters', C.c_int32), ('matvecs', C.c_int32), ('refine_sweeps', C.c_int32),
                 ('converged', C.c_int32), ('rel_residual', C.c_double), ('t_total_ms', C.c_double),
-                ('t_far_ms', C.c_double), ('n_far', C.c_int32)]
+                ('t_far_ms', C.c_double), ('n_far', C.c_int32), ('graph_launches', C.c_int32)]
 
 
 class LcpOpts(C.Structure):
@@ -140,7 +140,7 @@ def pqn_host_self_block(n_theta, n_phi, radius=1.0):
 
 def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_tol_lo=None, restart=50,
           max_iter=500, near_gap=0.0, near_up=2, slip=1.0, precision='fp64', refine=0, tpt=2, far_chunks=0,
-          device=0, stream=None, profile=False):
+          device=0, stream=None, profile=False, graphs=False):
     d = ConfigDesc()
     d.n_particles = M
     d.radius, d.mu = radius, mu
@@ -158,6 +158,7 @@ def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_
     d.device = device
     d.stream = stream
     d.profile = 1 if profile else 0
+    d.use_graphs = 1 if graphs else 0
     return d
 
 
@@ -224,7 +225,7 @@ class Context:
     def __init__(self, centers, axes=None, n_theta=8, n_phi=16, lo=None, radius=1.0, mu=1.0,
                  gmres_tol=1e-8, gmres_tol_lo=None, restart=50, max_iter=500, near_gap=0.0, near_up=2,
                  slip=1.0, precision='fp64', refine=0, tpt=None, far_chunks=None, device=0, stream=None,
-                 profile=False, tune_K=1):
+                 profile=False, tune_K=1, graphs=False):
         c = _f64(centers).reshape(-1, 3)
         self.M = c.shape[0]
         if tpt is None or far_chunks is None:
@@ -248,6 +249,7 @@ class Context:
         d.device = device
         d.stream = stream
         d.profile = 1 if profile else 0
+        d.use_graphs = 1 if graphs else 0
         self.n_theta, self.n_phi, self.lo = n_theta, n_phi, lo
         ax = None if axes is None else _f64(axes).reshape(-1, 3)
         h = C.c_void_p()

@@ -153,6 +153,7 @@ pqn_status pqn_batch_mobility_apply(pqn_ctx* ctx, const double* const* FT, doubl
         if (!std::isfinite(FT[b][k])) return fail(PQN_ERR_NUMERIC, "non-finite force/torque");
     }
     ctx->n_matvec = 0;
+    ctx->n_graph_launch = 0;
     ctx->n_far = 0;
     std::vector<SysRef> sys;
     for (int b = 0; b < nb; ++b) {
@@ -176,6 +177,7 @@ pqn_status pqn_batch_mobility_apply(pqn_ctx* ctx, const double* const* FT, doubl
     st.t_far_ms = ctx->end_far_timing();
     st.matvecs = ctx->n_matvec;
     st.n_far = ctx->n_far;
+    st.graph_launches = ctx->n_graph_launch;
     st.t_total_ms = tm.ms();
     if (stats) *stats = st;
     return st.converged ? PQN_OK : PQN_WARN_NOT_CONVERGED;
@@ -202,6 +204,7 @@ pqn_status pqn_mobility_apply_multi(pqn_ctx* ctx, int32_t k_rhs, const double* F
       up[r] = ctx->UO.p + r * m6;
     }
     ctx->n_matvec = 0;
+    ctx->n_graph_launch = 0;
     ctx->n_far = 0;
     pqn_mvp_stats st{};
     ctx->mobility_multi(lv, k_rhs, fp, nullptr, up, &st);
@@ -210,6 +213,7 @@ pqn_status pqn_mobility_apply_multi(pqn_ctx* ctx, int32_t k_rhs, const double* F
     st.t_far_ms = ctx->end_far_timing();
     st.matvecs = ctx->n_matvec;
     st.n_far = ctx->n_far;
+    st.graph_launches = ctx->n_graph_launch;
     st.t_total_ms = tm.ms();
     if (stats) *stats = st;
     return st.converged ? PQN_OK : PQN_WARN_NOT_CONVERGED;
@@ -258,12 +262,14 @@ static pqn_status mobility_common(pqn_ctx* ctx, const double* FT_dev, const doub
   Level& lv = ctx->level(fidelity);
   pqn_mvp_stats st{};
   ctx->n_matvec = 0;
+  ctx->n_graph_launch = 0;
   ctx->n_far = 0;
   ctx->mobility(lv, FT_dev, axes_dev, UO_dev, &st);
   HIPCHK(hipStreamSynchronize(ctx->stream));
   st.t_far_ms = ctx->end_far_timing();
   st.matvecs = ctx->n_matvec;
   st.n_far = ctx->n_far;
+  st.graph_launches = ctx->n_graph_launch;
   st.t_total_ms = tm.ms();
   if (stats) *stats = st;
   return st.converged ? PQN_OK : PQN_WARN_NOT_CONVERGED;
@@ -337,6 +343,7 @@ pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, doub
     Level& lv = ctx->level(fidelity);
     const size_t len = 3 * (size_t)lv.N;
     ctx->n_matvec = 0;
+    ctx->n_graph_launch = 0;
     ctx->n_far = 0;
     SysBuf& b = lv.sb(0);
     HIPCHK(hipMemcpyAsync(b.rhs.p, rhs, len * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
@@ -348,6 +355,7 @@ pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, doub
     st.t_far_ms = ctx->end_far_timing();
     st.matvecs = ctx->n_matvec;
     st.n_far = ctx->n_far;
+    st.graph_launches = ctx->n_graph_launch;
     st.t_total_ms = tm.ms();
     if (stats) *stats = st;
     return st.converged ? PQN_OK : PQN_WARN_NOT_CONVERGED;

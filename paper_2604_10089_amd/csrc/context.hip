@@ -161,6 +161,7 @@ void pqn_ctx_impl::set_configuration(const double* c, const double* ax) {
   npart.upload(h_npart.data(), h_npart.size(), stream);
   near_list.upload(nl.data(), nl.size(), stream);
   HIPCHK(hipStreamSynchronize(stream));
+  ++config_epoch;
 }
 
 void pqn_ctx_impl::begin_far_timing() {
@@ -373,6 +374,120 @@ double pqn_ctx_impl::dot_host(const double* x, const double* y, long len, Level&
   return v;
 }
 
+// Descriptor tables of the two segmented GEMM phases of one operator
+// application to the single density q (context c, level lv, work slot).
+IterTables pqn_ctx_impl::iteration_tables(pqn_ctx_impl& c, Level& lv, int slot, const double* q,
+                                           std::vector<char>& bytes) {
+  Work& w = lv.wk(slot);
+  const int n = lv.n, N = lv.N, L = lv.L, nup = lv.nup, M = lv.M;
+  std::vector<GemmDesc> ga, gb;
+  IterTables t{};
+  for (int comp = 0; comp < 3; ++comp) {
+    push_gemm(ga, t.nga, L, M, n, lv.T.p, n, q + (size_t)comp * N, n, w.coef.p + (size_t)comp * M * L, L, 0, L);
+    push_gemm(gb, t.ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, w.coef.p + (size_t)comp * M * L, L,
+              w.selfo.p + (size_t)comp * 3 * N, n, N, n);
+    if (c.n_near > 0)
+      push_gemm(gb, t.ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L,
+                w.qup.p + (size_t)comp * M * nup, nup, 0, nup);
+  }
+  DescPack dp;
+  t.oa = dp.add(ga);
+  t.ob = dp.add(gb);
+  t.na = (int)ga.size();
+  t.nb = (int)gb.size();
+  bytes = dp.host;
+  return t;
+}
+
+// Kernels of one GMRES iteration on one system: w = A q, then two classical
+// Gram-Schmidt passes against V[0..nvec) and the squared norm of w, with every
+// Hessenberg entry written to hp. Kernel launches only (no copies or fills),
+// so the sequence can be captured in a graph.
+void pqn_ctx_impl::iteration_launches(pqn_ctx_impl& c, Level& lv, int slot, int prec, const double* q, double* w,
+                                      const double* V, int nvec, double* hp, int m, const char* dtab,
+                                      const IterTables& t) {
+  hipStream_t s = stream;
+  Work& wk = lv.wk(slot);
+  SysBuf& b = lv.sb(slot);
+  const long len = 3L * lv.N;
+  const double scale = 3.0 / (4.0 * kPi * c.a);
+  launch_gemm64_multi(s, (const GemmDesc*)(dtab + t.oa), t.na, t.nga);
+  launch_gemm64_multi(s, (const GemmDesc*)(dtab + t.ob), t.nb, t.ngb);
+  QPtrs qp{};
+  qp.p[0] = q;
+  launch_pack(s, prec, 1, qp, lv.off.p, lv.w.p, lv.n, lv.N, lv.src.p);
+  OPtrs op{};
+  op.p[0] = wk.far_part.p;
+  launch_far(s, prec, 1, lv.tpt, lv.src.p, lv.off.p, c.ctr.p, c.cls.p, lv.n, lv.M, lv.N, lv.spc, lv.nchunks, scale,
+             op);
+  QPtrs qu{}, cf{};
+  OPtrs np{};
+  qu.p[0] = wk.qup.p;
+  cf.p[0] = wk.coef.p;
+  np.p[0] = wk.near_part.p;
+  launch_near(s, 1, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, qu, cf, c.near_list.p, lv.n, lv.M, lv.N, lv.nup, lv.p,
+              lv.L, scale, np);
+  launch_moments(s, q, lv.off.p, lv.w.p, lv.n, lv.M, lv.N, wk.mom.p);
+  launch_combine(s, q, wk.selfo.p, 3, wk.far_part.p, lv.nchunks, wk.near_part.p, c.npart.p, wk.mom.p, lv.off.p, lv.n,
+                 lv.N, c.a, w);
+  for (int pass = 0; pass < 2; ++pass) {
+    launch_dots(s, V, len, nvec, w, len, lv.nb_dots, b.partial.p, hp + pass * (m + 1));
+    launch_combo(s, w, 1.0, V, len, nvec, hp + pass * (m + 1), -1.0, len);
+  }
+  launch_dots(s, w, len, 1, w, len, lv.nb_dots, b.partial.p, hp + 2 * (m + 1));
+}
+
+// Replay the graph of GMRES iteration k of one system, capturing it on first
+// use. Graphs hold device pointers of the level's buffers and the context's
+// geometry, so they are rebuilt after any configuration change.
+void pqn_ctx_impl::launch_iteration_graph(pqn_ctx_impl& c, Level& lv, int slot, int prec, int k, double* hp, int m) {
+  while ((int)lv.graphs.size() <= slot) lv.graphs.emplace_back(new GraphCache());
+  GraphCache& gc = *lv.graphs[slot];
+  if (gc.epoch != c.config_epoch || gc.prec != prec || (int)gc.execs.size() != m || gc.hp != hp) {
+    HIPCHK(hipStreamSynchronize(stream));
+    gc.clear();
+    gc.execs.assign(m, nullptr);
+    gc.epoch = c.config_epoch;
+    gc.prec = prec;
+    gc.hp = hp;
+  }
+  SysBuf& b = lv.sb(slot);
+  const long len = 3L * lv.N;
+  const double* q = b.V.p + (size_t)k * len;
+  double* w = b.V.p + (size_t)(k + 1) * len;
+  if (!gc.execs[k]) {
+    std::vector<char> bytes;
+    const IterTables t = iteration_tables(c, lv, slot, q, bytes);
+    const size_t stride = (bytes.size() + 255) & ~size_t(255);
+    if (!gc.dtab.p || gc.stride < stride) {
+      // every cached graph points into the old table: drop them all
+      HIPCHK(hipStreamSynchronize(stream));
+      gc.clear();
+      gc.execs.assign(m, nullptr);
+      gc.stride = stride;
+      gc.dtab.release();
+      gc.dtab.alloc(gc.stride * m);
+    }
+    char* tab = gc.dtab.p + gc.stride * k;
+    HIPCHK(hipMemcpyAsync(tab, bytes.data(), bytes.size(), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    iteration_launches(c, lv, slot, prec, q, w, b.V.p, k + 1, hp, m, tab, t);
+    const hipError_t ce = hipStreamEndCapture(stream, &graph);
+    HIPCHK(ce);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(ie);
+    gc.execs[k] = exec;
+  }
+  HIPCHK(hipGraphLaunch(gc.execs[k], stream));
+  ++n_graph_launch;
+  ++n_far;
+  ++n_matvec;
+}
+
 namespace {
 struct GmState {
   std::vector<double> H, cs, sn, g;
@@ -458,9 +573,18 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
     for (int i = 0; i < ns; ++i)
       if (st[i].active) act.push_back(i);
     if (act.empty()) break;
-    std::vector<MvGroup> groups = build_groups(act, false);
-    matvec_groups(groups, precision);
-    if (act.size() == 1) {
+    const bool graph_iter = ns == 1 && cfg.use_graphs && !cfg.profile;
+    if (graph_iter) {
+      const int i = act[0];
+      launch_iteration_graph(*sys[i].c, *sys[i].lv, sys[i].slot, precision == PQN_MIXED ? 1 : 0, st[i].k,
+                             hdev.p + (size_t)i * hs, m);
+    } else {
+      std::vector<MvGroup> groups = build_groups(act, false);
+      matvec_groups(groups, precision);
+    }
+    if (graph_iter) {
+      // operator and CGS2 already in the replayed graph
+    } else if (act.size() == 1) {
       for (int i : act) {
         SysBuf& b = sys[i].lv->sb(sys[i].slot);
         const long len = len_of(i);

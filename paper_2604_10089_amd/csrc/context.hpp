@@ -67,6 +67,28 @@ struct SysBuf {
   DevArray<double> V, x, r, rhs, tmp, d, partial, ycoef;
 };
 
+// Offsets and sizes of the segmented GEMM descriptor tables of one iteration.
+struct IterTables {
+  size_t oa = 0, ob = 0;
+  int na = 0, nga = 0, nb = 0, ngb = 0;
+};
+
+// Captured GMRES iterations of one linear system (one graph per Arnoldi index k).
+struct GraphCache {
+  int prec = -1;
+  unsigned long epoch = 0;
+  const double* hp = nullptr;  // Hessenberg staging the graphs write to
+  std::vector<hipGraphExec_t> execs;
+  DevArray<char> dtab;  // per-k descriptor tables read by the captured kernels
+  size_t stride = 0;
+  void clear() {
+    for (hipGraphExec_t& e : execs)
+      if (e) (void)hipGraphExecDestroy(e);
+    execs.clear();
+  }
+  ~GraphCache() { clear(); }
+};
+
 struct Level {
   SphereTables tab;
   int M = 0, n = 0, N = 0, L = 0, nup = 0, p = 0;
@@ -79,6 +101,7 @@ struct Level {
   int nb_dots = 128;
   std::vector<std::unique_ptr<Work>> work;
   std::vector<std::unique_ptr<SysBuf>> sys;
+  std::vector<std::unique_ptr<GraphCache>> graphs;
   Work& wk(int k);
   SysBuf& sb(int k);
 };
@@ -139,6 +162,8 @@ struct pqn_ctx_impl {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   size_t ev_used = 0;
   int n_matvec = 0, n_far = 0;
+  unsigned long config_epoch = 1;  // bumped by every configuration change (invalidates graphs)
+  int n_graph_launch = 0;
   LcpState* lcp = nullptr;
   // batched suspensions: one child context per suspension, sharing the stream
   bool is_batch = false;
@@ -159,6 +184,11 @@ struct pqn_ctx_impl {
   // operator on groups of densities (all on this context's stream)
   void matvec_groups(std::vector<MvGroup>& groups, int precision);
   void matvec_batched(std::vector<MvGroup>& groups, int prec);
+  // one GMRES iteration of a single system (operator + CGS2), kernels only, for capture
+  IterTables iteration_tables(pqn_ctx_impl& c, Level& lv, int slot, const double* q, std::vector<char>& bytes);
+  void iteration_launches(pqn_ctx_impl& c, Level& lv, int slot, int prec, const double* q, double* w,
+                          const double* V, int nvec, double* hp, int m, const char* dtab, const IterTables& t);
+  void launch_iteration_graph(pqn_ctx_impl& c, Level& lv, int slot, int prec, int k, double* hp, int m);
   void apply_operator(Level& lv, int precision, const double* q, double* y);
   // lockstep GMRES over systems; every system's x is overwritten (initial guess 0)
   void gmres_lockstep(std::vector<SysRef>& sys, int precision);
