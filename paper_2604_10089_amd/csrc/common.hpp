@@ -76,7 +76,14 @@ struct SphereTables {
   std::vector<double> off_up;   // [n_up][3] upsampled grid offsets
   std::vector<double> w_up;     // [n_up]
   std::vector<double> Y_up;     // [n_up][L] synthesis on the upsampled grid
+  std::vector<double> shab;     // [L][2] Legendre recurrence factors (sh_recurrence_table)
 };
+
+// Factors of the normalised Legendre recurrence used by real_sh_visit, one
+// pair per (l, m) at slot sh_index(l, m, 0): for l > m the three-term
+// coefficients (a_lm, b_lm) of P_l^m = a_lm (cos(theta) P_{l-1}^m - b_lm P_{l-2}^m);
+// for l = m > 0 the order step -sqrt((2m+1)/(2m)) (P_m^m = step sin(theta) P_{m-1}^{m-1}).
+std::vector<double> sh_recurrence_table(int p);
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, SphereTables& t);

@@ -95,6 +95,7 @@ void pqn_ctx_impl::setup_level(Level& lv, int nt, int np, double tol) {
   lv.G.upload(t.G.data(), t.G.size(), stream);
   lv.T.upload(t.T.data(), t.T.size(), stream);
   lv.Yup.upload(t.Y_up.data(), t.Y_up.size(), stream);
+  lv.shab.upload(t.shab.data(), t.shab.size(), stream);
   std::vector<double4> ou(t.n_up);
   for (int f = 0; f < t.n_up; ++f)
     ou[f] = make_double4(t.off_up[3 * f], t.off_up[3 * f + 1], t.off_up[3 * f + 2], t.w_up[f]);
@@ -256,8 +257,8 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
       cf.p[r] = w.coef.p;
       np.p[r] = w.near_part.p;
     }
-    launch_near(s, gr.K, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, qu, cf, c.near_list.p, lv.n, lv.M, lv.N, lv.nup,
-                lv.p, lv.L, 3.0 / (4.0 * kPi * c.a), np);
+    launch_near(s, gr.K, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, qu, cf, c.near_list.p, lv.n, lv.M, lv.N,
+                lv.nup, lv.p, lv.L, 3.0 / (4.0 * kPi * c.a), np);
     for (int r = 0; r < gr.K; ++r) {
       Work& w = lv.wk(gr.slot0 + r);
       launch_moments(s, gr.in[r], lv.off.p, lv.w.p, lv.n, lv.M, lv.N, w.mom.p);
@@ -298,7 +299,7 @@ void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
     npk += N;
     if (c.n_near > 0) {
       const int nch = (n + 63) / 64;
-      nd.push_back(NearDesc{c.ctr.p, lv.off.p, lv.offup.p, w.qup.p, w.coef.p, c.near_list.p, w.near_part.p,
+      nd.push_back(NearDesc{c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, w.qup.p, w.coef.p, c.near_list.p, w.near_part.p,
                             3.0 / (4.0 * kPi * c.a), n, M, N, nup, lv.p, L, nch, nnd});
       nnd += c.n_near * nch;
     }
@@ -425,8 +426,8 @@ void pqn_ctx_impl::iteration_launches(pqn_ctx_impl& c, Level& lv, int slot, int 
   qu.p[0] = wk.qup.p;
   cf.p[0] = wk.coef.p;
   np.p[0] = wk.near_part.p;
-  launch_near(s, 1, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, qu, cf, c.near_list.p, lv.n, lv.M, lv.N, lv.nup, lv.p,
-              lv.L, scale, np);
+  launch_near(s, 1, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, qu, cf, c.near_list.p, lv.n, lv.M, lv.N,
+              lv.nup, lv.p, lv.L, scale, np);
   launch_moments(s, q, lv.off.p, lv.w.p, lv.n, lv.M, lv.N, wk.mom.p);
   launch_combine(s, q, wk.selfo.p, 3, wk.far_part.p, lv.nchunks, wk.near_part.p, c.npart.p, wk.mom.p, lv.off.p, lv.n,
                  lv.N, c.a, w);

@@ -92,7 +92,7 @@ struct GraphCache {
 struct Level {
   SphereTables tab;
   int M = 0, n = 0, N = 0, L = 0, nup = 0, p = 0;
-  DevArray<double> off, w, G, T, Yup;
+  DevArray<double> off, w, G, T, Yup, shab;
   DevArray<double4> offup;
   DevArray<double> src;  // packed far sources, up to kMaxRhs densities (FP64 record is the larger)
   int nchunks = 1, spc = 1, tpt = 2;

@@ -169,6 +169,21 @@ static void build_self_block(SphereTables& t) {
   }
 }
 
+std::vector<double> sh_recurrence_table(int p) {
+  const int L = (p + 1) * (p + 1);
+  std::vector<double> t(2 * (size_t)L, 0.0);
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) t[2 * sh_index(m, m, 0)] = -std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+    for (int l = m + 1; l <= p; ++l) {
+      const int s = sh_index(l, m, 0);
+      t[2 * s] = std::sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)m * m));
+      t[2 * s + 1] =
+          (l - 1 > m) ? std::sqrt(((double)(l - 1) * (l - 1) - (double)m * m) / (4.0 * (l - 1) * (l - 1) - 1.0)) : 0.0;
+    }
+  }
+  return t;
+}
+
 void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, SphereTables& t) {
   if (n_theta < 2 || n_phi < 2 * n_theta - 1 || n_theta - 1 > kMaxDegree)
     throw std::runtime_error("grid must have n_theta >= 2, n_phi >= 2 n_theta - 1, degree <= 40");
@@ -223,6 +238,7 @@ void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, Sph
     double st = std::sqrt(1.0 - ctu[f] * ctu[f]);
     sh_row(t.p, ctu[f], st, std::cos(phu[f]), std::sin(phu[f]), &t.Y_up[(size_t)f * t.L]);
   }
+  t.shab = sh_recurrence_table(t.p);
 }
 
 }  // namespace bipqn

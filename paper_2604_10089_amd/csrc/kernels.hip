@@ -264,49 +264,118 @@ __global__ __launch_bounds__(256) void k_far64_multi(const FarDesc* __restrict__
 
 // ---------------------------------------------------------- near pair sum
 //
-// For each target and each near partner sphere j: sum over the upsampled nodes
-// f of sphere j of w_f K(x, y_f)(q_f - q_j(x*)), x* the foot point of x on
-// sphere j and q_j(x*) the degree-p harmonic expansion of the density there
-// (constant-density subtraction). Grid (near pair, 64-target chunk): all lanes
-// of a wave share the source sphere j, so the upsampled source stream and the
-// harmonic coefficients are wave-uniform (scalar loads). K densities share r.
+// For each target x on sphere i and near partner j: the sum over the upsampled
+// nodes f of sphere j of w_f K(x, y_f) (q_f - q_j(x*)), x* the foot point of x
+// on sphere j and q_j(x*) the degree-p harmonic expansion of the density there
+// (constant-density subtraction). For K >= 2 densities the subtracted part is
+// applied after the loop as (sum_f w_f K(x, y_f)) q_j(x*): the 3x3 kernel
+// moment is shared by all densities.
+//
+// Grid (near pair, 64-target chunk), block = kNearWaves waves on the same 64
+// targets. Wave w takes the w-th share of the source nodes and the harmonic
+// orders m = w (mod kNearWaves) of the foot-point expansion; the partial sums
+// meet in LDS and are added in wave order, so results do not depend on timing.
+// Within a wave the source records and coefficients are uniform (scalar loads).
 
+constexpr int kNearWaves = 4;
+
+// Partial foot-point values: orders m = wv (mod kNearWaves) of sum_lm c_lm Y_lm(x*).
+template <int K>
+__device__ __forceinline__ void foot_part(int p, double ct, double st, double cp, double sp,
+                                          const double* __restrict__ shab, const QPtrs& coef, size_t jL, size_t ML,
+                                          int wv, double (&f)[K][3]) {
+  double pmm = sqrt(1.0 / (4.0 * kPi));
+  double cm = 1.0, sm = 0.0;
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) {
+      pmm *= shab[2 * sh_index(m, m, 0)] * st;
+      const double c2 = cm * cp - sm * sp, s2 = sm * cp + cm * sp;
+      cm = c2;
+      sm = s2;
+    }
+    if (m % kNearWaves != wv) continue;
+    const double fac = m == 0 ? 1.0 : sqrt(2.0);
+    const double yc = fac * cm, ys = fac * sm;
+    double plm2 = 0.0, plm1 = pmm;
+    for (int l = m; l <= p; ++l) {
+      const int ic = sh_index(l, m, 0);
+      if (l > m) {
+        const double pl = shab[2 * ic] * (ct * plm1 - shab[2 * ic + 1] * plm2);
+        plm2 = plm1;
+        plm1 = pl;
+      }
+      const double vc = plm1 * yc;
+#pragma unroll
+      for (int r = 0; r < K; ++r) {
+        const double* cx = coef.p[r] + jL + ic;
+        f[r][0] = fma(vc, cx[0], f[r][0]);
+        f[r][1] = fma(vc, cx[ML], f[r][1]);
+        f[r][2] = fma(vc, cx[2 * ML], f[r][2]);
+      }
+      if (m > 0) {
+        const double vs = plm1 * ys;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+          const double* cx = coef.p[r] + jL + ic + 1;
+          f[r][0] = fma(vs, cx[0], f[r][0]);
+          f[r][1] = fma(vs, cx[ML], f[r][1]);
+          f[r][2] = fma(vs, cx[2 * ML], f[r][2]);
+        }
+      }
+    }
+  }
+}
+
+// lds: kNearWaves * 3K * 64 doubles.
 template <int K>
 __device__ __forceinline__ void near_body(int pair, int chunk, const double* __restrict__ ctr,
                                           const double* __restrict__ off, const double4* __restrict__ offup,
-                                          const QPtrs& qup, const QPtrs& coef, const int* __restrict__ npairs, int n,
-                                          int M, int N, int nup, int p, int L, double scale, const OPtrs& near_part) {
+                                          const double* __restrict__ shab, const QPtrs& qup, const QPtrs& coef,
+                                          const int* __restrict__ npairs, int n, int M, int N, int nup, int p, int L,
+                                          double scale, const OPtrs& near_part, double* __restrict__ lds) {
+  constexpr int C = 3 * K;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int i = npairs[3 * pair], j = npairs[3 * pair + 1], slot = npairs[3 * pair + 2];
-  const int k = chunk * 64 + threadIdx.x;
+  const int k = chunk * 64 + lane;
   const bool valid = k < n;
   const int kk = valid ? k : n - 1;
   const int t = i * n + kk;
   const double Xx = (ctr[3 * i] + off[3 * kk]) - ctr[3 * j];
   const double Xy = (ctr[3 * i + 1] + off[3 * kk + 1]) - ctr[3 * j + 1];
   const double Xz = (ctr[3 * i + 2] + off[3 * kk + 2]) - ctr[3 * j + 2];
-  const double rho = sqrt(Xx * Xx + Xy * Xy);
-  const double R = sqrt(rho * rho + Xz * Xz);
-  const double ct = Xz / R, st = rho / R;
-  const double cp = rho > 0.0 ? Xx / rho : 1.0, sp = rho > 0.0 ? Xy / rho : 0.0;
-  const size_t ML = (size_t)M * L;
+  const size_t ML = (size_t)M * L, MU = (size_t)M * nup;
   double f[K][3];
+  {
+    const double rho = sqrt(Xx * Xx + Xy * Xy);
+    const double R = sqrt(rho * rho + Xz * Xz);
+    const double ct = Xz / R, st = rho / R;
+    const double cp = rho > 0.0 ? Xx / rho : 1.0, sp = rho > 0.0 ? Xy / rho : 0.0;
 #pragma unroll
-  for (int r = 0; r < K; ++r) f[r][0] = f[r][1] = f[r][2] = 0.0;
-  real_sh_visit(p, ct, st, cp, sp, [&](int idx, double y) {
+    for (int r = 0; r < K; ++r) f[r][0] = f[r][1] = f[r][2] = 0.0;
+    foot_part<K>(p, ct, st, cp, sp, shab, coef, (size_t)j * L, ML, wv, f);
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
-      const double* cx = coef.p[r] + (size_t)j * L;
-      f[r][0] = fma(y, cx[idx], f[r][0]);
-      f[r][1] = fma(y, cx[ML + idx], f[r][1]);
-      f[r][2] = fma(y, cx[2 * ML + idx], f[r][2]);
+    for (int r = 0; r < K; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) lds[(wv * C + 3 * r + c) * 64 + lane] = f[r][c];
+  }
+  __syncthreads();
+  if constexpr (K == 1) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double v = lds[c * 64 + lane];
+#pragma unroll
+      for (int w = 1; w < kNearWaves; ++w) v += lds[(w * C + c) * 64 + lane];
+      f[0][c] = v;
     }
-  });
-  const size_t MU = (size_t)M * nup;
+  }
+  const int f0 = (wv * nup) / kNearWaves, f1 = ((wv + 1) * nup) / kNearWaves;
   double a[K][3];
 #pragma unroll
   for (int r = 0; r < K; ++r) a[r][0] = a[r][1] = a[r][2] = 0.0;
+  double mxx = 0.0, mxy = 0.0, mxz = 0.0, myy = 0.0, myz = 0.0, mzz = 0.0;
 #pragma unroll 2
-  for (int fi = 0; fi < nup; ++fi) {
+  for (int fi = f0; fi < f1; ++fi) {
     const double4 o = offup[fi];
     const double rx = Xx - o.x, ry = Xy - o.y, rz = Xz - o.z;
     const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
@@ -314,32 +383,79 @@ __device__ __forceinline__ void near_body(int pair, int chunk, const double* __r
     const double ri2 = ri * ri;
     const double rn = fma(rx, o.x, fma(ry, o.y, rz * o.z));
     const double wgt = o.w * rn * ri * ri2 * ri2;
-#pragma unroll
-    for (int r = 0; r < K; ++r) {
-      const double* qx = qup.p[r] + (size_t)j * nup + fi;
-      const double dqx = qx[0] - f[r][0], dqy = qx[MU] - f[r][1], dqz = qx[2 * MU] - f[r][2];
+    if constexpr (K == 1) {
+      const double* qx = qup.p[0] + (size_t)j * nup + fi;
+      const double dqx = qx[0] - f[0][0], dqy = qx[MU] - f[0][1], dqz = qx[2 * MU] - f[0][2];
       const double c = wgt * fma(rx, dqx, fma(ry, dqy, rz * dqz));
-      a[r][0] = fma(c, rx, a[r][0]);
-      a[r][1] = fma(c, ry, a[r][1]);
-      a[r][2] = fma(c, rz, a[r][2]);
+      a[0][0] = fma(c, rx, a[0][0]);
+      a[0][1] = fma(c, ry, a[0][1]);
+      a[0][2] = fma(c, rz, a[0][2]);
+    } else {
+      const double wx = wgt * rx, wy = wgt * ry, wz = wgt * rz;
+      mxx = fma(wx, rx, mxx);
+      mxy = fma(wx, ry, mxy);
+      mxz = fma(wx, rz, mxz);
+      myy = fma(wy, ry, myy);
+      myz = fma(wy, rz, myz);
+      mzz = fma(wz, rz, mzz);
+#pragma unroll
+      for (int r = 0; r < K; ++r) {
+        const double* qx = qup.p[r] + (size_t)j * nup + fi;
+        const double d = fma(wx, qx[0], fma(wy, qx[MU], wz * qx[2 * MU]));
+        a[r][0] = fma(d, rx, a[r][0]);
+        a[r][1] = fma(d, ry, a[r][1]);
+        a[r][2] = fma(d, rz, a[r][2]);
+      }
     }
   }
-  if (valid)
+  __syncthreads();  // every wave has read the foot-point partials
+  if constexpr (K > 1) {
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      double q3[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double v = lds[(3 * r + c) * 64 + lane];
+#pragma unroll
+        for (int w = 1; w < kNearWaves; ++w) v += lds[(w * C + 3 * r + c) * 64 + lane];
+        q3[c] = v;
+      }
+      a[r][0] -= fma(mxx, q3[0], fma(mxy, q3[1], mxz * q3[2]));
+      a[r][1] -= fma(mxy, q3[0], fma(myy, q3[1], myz * q3[2]));
+      a[r][2] -= fma(mxz, q3[0], fma(myz, q3[1], mzz * q3[2]));
+    }
+    __syncthreads();  // foot-point partials consumed: the buffer takes the results
+  }
+#pragma unroll
+  for (int r = 0; r < K; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) lds[(wv * C + 3 * r + c) * 64 + lane] = a[r][c];
+  __syncthreads();
+  if (wv == 0 && valid) {
 #pragma unroll
     for (int r = 0; r < K; ++r) {
       double* pb = near_part.p[r] + (size_t)slot * 3 * N;
-      pb[t] = scale * a[r][0];
-      pb[N + t] = scale * a[r][1];
-      pb[2 * N + t] = scale * a[r][2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double v = lds[(3 * r + c) * 64 + lane];
+#pragma unroll
+        for (int w = 1; w < kNearWaves; ++w) v += lds[(w * C + 3 * r + c) * 64 + lane];
+        pb[(size_t)c * N + t] = scale * v;
+      }
     }
+  }
 }
 
 template <int K>
-__global__ __launch_bounds__(64) void k_near64(const double* __restrict__ ctr, const double* __restrict__ off,
-                                               const double4* __restrict__ offup, QPtrs qup, QPtrs coef,
-                                               const int* __restrict__ npairs, int n, int M, int N, int nup, int p,
-                                               int L, double scale, OPtrs near_part) {
-  near_body<K>(blockIdx.x, blockIdx.y, ctr, off, offup, qup, coef, npairs, n, M, N, nup, p, L, scale, near_part);
+__global__ __launch_bounds__(64 * kNearWaves) void k_near64(const double* __restrict__ ctr,
+                                                            const double* __restrict__ off,
+                                                            const double4* __restrict__ offup,
+                                                            const double* __restrict__ shab, QPtrs qup, QPtrs coef,
+                                                            const int* __restrict__ npairs, int n, int M, int N,
+                                                            int nup, int p, int L, double scale, OPtrs near_part) {
+  __shared__ double lds[kNearWaves * 3 * K * 64];
+  near_body<K>(blockIdx.x, blockIdx.y, ctr, off, offup, shab, qup, coef, npairs, n, M, N, nup, p, L, scale, near_part,
+               lds);
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -648,7 +764,8 @@ __global__ __launch_bounds__(256) void k_pack_multi(const PackDesc* __restrict__
   }
 }
 
-__global__ __launch_bounds__(64) void k_near64_multi(const NearDesc* __restrict__ d, int nd) {
+__global__ __launch_bounds__(64 * kNearWaves) void k_near64_multi(const NearDesc* __restrict__ d, int nd) {
+  __shared__ double lds[kNearWaves * 3 * 64];
   const int b = blockIdx.x;
   const NearDesc D = d[find_seg(d, nd, b)];
   const int local = b - D.start;
@@ -657,8 +774,8 @@ __global__ __launch_bounds__(64) void k_near64_multi(const NearDesc* __restrict_
   qu.p[0] = D.qup;
   cf.p[0] = D.coef;
   np.p[0] = D.part;
-  near_body<1>(local / D.nch, local % D.nch, D.ctr, D.off, D.offup, qu, cf, D.pairs, D.n, D.M, D.N, D.nup, D.p,
-               D.L, D.scale, np);
+  near_body<1>(local / D.nch, local % D.nch, D.ctr, D.off, D.offup, D.shab, qu, cf, D.pairs, D.n, D.M, D.N, D.nup,
+               D.p, D.L, D.scale, np, lds);
 }
 
 __global__ __launch_bounds__(256) void k_moments_multi(const MomDesc* __restrict__ d, int nd) {
@@ -784,13 +901,13 @@ void launch_far_multi(hipStream_t s, int prec, int tpt, const FarDesc* desc, int
 }
 
 void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, const double* off, const double4* offup,
-                 const QPtrs& qup, const QPtrs& coef, const int* npairs, int n, int M, int N, int nup, int p, int L,
-                 double scale, const OPtrs& near_part) {
+                 const double* shab, const QPtrs& qup, const QPtrs& coef, const int* npairs, int n, int M, int N,
+                 int nup, int p, int L, double scale, const OPtrs& near_part) {
   if (npairs_count <= 0) return;
   const dim3 g(npairs_count, (n + 63) / 64);
-#define NEARK(KK)                                                                                                 \
-  hipLaunchKernelGGL(k_near64<KK>, g, dim3(64), 0, s, ctr, off, offup, qup, coef, npairs, n, M, N, nup, p, L, scale, \
-                     near_part)
+#define NEARK(KK)                                                                                                \
+  hipLaunchKernelGGL(k_near64<KK>, g, dim3(64 * kNearWaves), 0, s, ctr, off, offup, shab, qup, coef, npairs, n, M, \
+                     N, nup, p, L, scale, near_part)
   switch (K) {
     case 1: NEARK(1); break;
     case 2: NEARK(2); break;
@@ -851,7 +968,7 @@ void launch_pack_multi(hipStream_t s, const PackDesc* d, int nd, int total, int 
   if (total > 0) hipLaunchKernelGGL(k_pack_multi, dim3(nblk2(total)), dim3(256), 0, s, d, nd, fp32);
 }
 void launch_near_multi(hipStream_t s, const NearDesc* d, int nd, int nblocks) {
-  if (nblocks > 0) hipLaunchKernelGGL(k_near64_multi, dim3(nblocks), dim3(64), 0, s, d, nd);
+  if (nblocks > 0) hipLaunchKernelGGL(k_near64_multi, dim3(nblocks), dim3(64 * kNearWaves), 0, s, d, nd);
 }
 void launch_moments_multi(hipStream_t s, const MomDesc* d, int nd, int nblocks) {
   if (nblocks > 0) hipLaunchKernelGGL(k_moments_multi, dim3(nblocks), dim3(256), 0, s, d, nd);
