@@ -70,8 +70,10 @@ typedef struct {
   double slip_speed;        /* Janus slip magnitude s [1] */
   int32_t precision;        /* pqn_precision of the far-field pair sums [PQN_FP64] */
   int32_t refine_sweeps;    /* mixed precision: outer refinement sweeps with an FP64 residual [0] */
-  int32_t targets_per_thread; /* far FP32 kernel: 1 or 2 [2] */
+  int32_t targets_per_thread; /* far FP32 kernel: 1 or 2 targets per thread, 256 threads per block [2] */
   int32_t far_chunks;       /* far kernels: source-sphere chunks (grid y); 0 = automatic */
+  int32_t far_split;        /* far FP32 kernel: 1 = 64 targets per block, its four waves split each
+                               chunk's sources and add their sums in LDS (targets_per_thread ignored) */
   int32_t device;           /* HIP device ordinal [0] */
   void* stream;             /* hipStream_t to run on; NULL = the library creates one */
   int32_t profile;          /* 1 = time every far pair-sum launch with HIP events */

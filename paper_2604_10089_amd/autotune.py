@@ -1,11 +1,12 @@
 """Autotuner for the far pair-sum launch shape.
 
 For one workload (sphere count M, grid, precision, densities per pass K) it
-times every candidate (targets per thread, number of source-sphere chunks =
-grid y) with the library's own HIP-event timing of the far kernel over one
-full mobility product, and records the fastest in a JSON cache keyed by the
-device architecture. `Context` consults the cache when its caller does not fix
-the launch shape.
+times every candidate launch shape -- block layout (256 targets per block with
+one or two targets per thread, or 64 targets per block whose four waves split
+the sources) and number of source-sphere chunks (grid y) -- with the library's
+own HIP-event timing of the far kernel over one full mobility product, and
+records the fastest in a JSON cache keyed by the device architecture.
+`Context` consults the cache when its caller does not fix the launch shape.
 
 Usage (on a GPU): python -m paper_2604_10089_amd.autotune [--workload rsa216] [--K 1 6] [--prec mixed fp64]
 """
@@ -47,15 +48,18 @@ def load(arch=None):
 
 
 def lookup(prec, K, M, n, arch='gfx950'):
-    """(tpt, chunks) from the cache, or None."""
+    """(tpt, chunks, split) from the cache, or None."""
     e = load(arch).get(key(prec, K, M, n))
-    return None if e is None else (e['tpt'], e['chunks'])
+    return None if e is None else (e['tpt'], e['chunks'], e.get('split', 0))
 
 
-def candidates(M, K):
+def candidates(M, K, prec):
     tpts = (1, 2) if K <= 2 else (1,)
     chunks = sorted({0} | {c for c in (2, 4, 6, 8, 12, 16, 24, 32, 48, 64) if c <= M})
-    return [(t, c) for t in tpts for c in chunks]
+    out = [(t, c, 0) for t in tpts for c in chunks]
+    if prec == 'mixed':  # the split layout exists for the FP32 pair sum
+        out += [(1, c, 1) for c in chunks]
+    return out
 
 
 def tune(centers, n_theta, n_phi, prec, K, seed=0, verbose=True):
@@ -64,17 +68,17 @@ def tune(centers, n_theta, n_phi, prec, K, seed=0, verbose=True):
     FT = inputs.random_forces(seed, M, k=K)
     best = None
     rows = []
-    for tpt, ch in candidates(M, K):
+    for tpt, ch, sp in candidates(M, K, prec):
         with binding.Context(centers, None, n_theta, n_phi, gmres_tol=1e-8, precision=prec, tpt=tpt,
-                             far_chunks=ch, profile=True) as ctx:
+                             far_chunks=ch, far_split=sp, profile=True) as ctx:
             ctx.mobility_apply_multi(FT)                # warm-up
             _, st = ctx.mobility_apply_multi(FT)
         t = st['t_far_ms'] / max(st['n_far'], 1)
-        rows.append((tpt, ch, t))
+        rows.append((tpt, ch, sp, t))
         if verbose:
-            print(f'  tpt={tpt} chunks={ch or "auto"}: {t:.4f} ms per far launch', flush=True)
-        if best is None or t < best[2]:
-            best = (tpt, ch, t)
+            print(f'  tpt={tpt} split={sp} chunks={ch or "auto"}: {t:.4f} ms per far launch', flush=True)
+        if best is None or t < best[3]:
+            best = (tpt, ch, sp, t)
     return best, rows
 
 
@@ -93,11 +97,12 @@ def main():
         for K in args.K:
             print(f'{args.workload} {prec} K={K}', flush=True)
             t0 = time.time()
-            (tpt, ch, t), rows = tune(c, w['n_theta'], w['n_phi'], prec, K)
+            (tpt, ch, sp, t), rows = tune(c, w['n_theta'], w['n_phi'], prec, K)
             cache[key(prec, K, c.shape[0], w['n_theta'] * w['n_phi'])] = dict(
-                tpt=tpt, chunks=ch, far_ms=round(t, 5), workload=args.workload,
-                sweep=[dict(tpt=a, chunks=b, far_ms=round(x, 5)) for a, b, x in rows])
-            print(f'  best tpt={tpt} chunks={ch or "auto"} {t:.4f} ms ({time.time() - t0:.1f} s)', flush=True)
+                tpt=tpt, chunks=ch, split=sp, far_ms=round(t, 5), workload=args.workload,
+                sweep=[dict(tpt=a, chunks=b, split=z, far_ms=round(x, 5)) for a, b, z, x in rows])
+            print(f'  best tpt={tpt} split={sp} chunks={ch or "auto"} {t:.4f} ms ({time.time() - t0:.1f} s)',
+                  flush=True)
     os.makedirs(CACHE_DIR, exist_ok=True)
     with open(cache_path(arch), 'w') as f:
         json.dump(cache, f, indent=1, sort_keys=True)

@@ -25,7 +25,8 @@ class ConfigDesc(C.Structure):
                 ('gmres_tol', C.c_double), ('gmres_tol_lo', C.c_double), ('gmres_restart', C.c_int32),
                 ('gmres_max_iter', C.c_int32), ('near_gap', C.c_double), ('near_up', C.c_int32),
                 ('slip_speed', C.c_double), ('precision', C.c_int32), ('refine_sweeps', C.c_int32),
-                ('targets_per_thread', C.c_int32), ('far_chunks', C.c_int32), ('device', C.c_int32),
+                ('targets_per_thread', C.c_int32), ('far_chunks', C.c_int32), ('far_split', C.c_int32),
+                ('device', C.c_int32),
                 ('stream', C.c_void_p), ('profile', C.c_int32), ('use_graphs', C.c_int32)]
 
 
@@ -140,7 +141,7 @@ def pqn_host_self_block(n_theta, n_phi, radius=1.0):
 
 def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_tol_lo=None, restart=50,
           max_iter=500, near_gap=0.0, near_up=2, slip=1.0, precision='fp64', refine=0, tpt=2, far_chunks=0,
-          device=0, stream=None, profile=False, graphs=False):
+          far_split=0, device=0, stream=None, profile=False, graphs=False):
     d = ConfigDesc()
     d.n_particles = M
     d.radius, d.mu = radius, mu
@@ -155,6 +156,7 @@ def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_
     d.refine_sweeps = refine
     d.targets_per_thread = tpt
     d.far_chunks = far_chunks
+    d.far_split = 1 if far_split else 0
     d.device = device
     d.stream = stream
     d.profile = 1 if profile else 0
@@ -206,32 +208,35 @@ class BatchContext:
 
 
 def tuned_shape(precision, K, M, n):
-    """(tpt, far_chunks) from the autotuner's cache for this shape, else the library defaults."""
+    """(tpt, far_chunks, far_split) from the autotuner's cache for this shape, else the library defaults."""
     try:
         from paper_2604_10089_amd import autotune
         hit = autotune.lookup(precision, K, M, n)
     except Exception:
         hit = None
-    return hit if hit is not None else (2, 0)
+    return hit if hit is not None else (2, 0, 0)
 
 
 class Context:
     """Owns one pqn_ctx. Methods carry the C ABI names without the prefix.
 
-    tpt / far_chunks = None take the autotuned launch shape for (precision,
-    single density, sphere count, grid) when the cache has one.
+    tpt / far_chunks / far_split = None take the autotuned launch shape for
+    (precision, densities per pass tune_K, sphere count, grid) when the cache
+    has one.
     """
 
     def __init__(self, centers, axes=None, n_theta=8, n_phi=16, lo=None, radius=1.0, mu=1.0,
                  gmres_tol=1e-8, gmres_tol_lo=None, restart=50, max_iter=500, near_gap=0.0, near_up=2,
-                 slip=1.0, precision='fp64', refine=0, tpt=None, far_chunks=None, device=0, stream=None,
-                 profile=False, tune_K=1, graphs=False):
+                 slip=1.0, precision='fp64', refine=0, tpt=None, far_chunks=None, far_split=None, device=0,
+                 stream=None, profile=False, tune_K=1, graphs=False):
         c = _f64(centers).reshape(-1, 3)
         self.M = c.shape[0]
-        if tpt is None or far_chunks is None:
-            t2, c2 = tuned_shape(precision, tune_K, self.M, n_theta * n_phi)
+        if tpt is None or far_chunks is None or far_split is None:
+            t2, c2, s2 = tuned_shape(precision, tune_K, self.M, n_theta * n_phi)
             tpt = t2 if tpt is None else tpt
             far_chunks = c2 if far_chunks is None else far_chunks
+            far_split = s2 if far_split is None else far_split
+        self.far_shape = dict(tpt=tpt, chunks=far_chunks, split=int(bool(far_split)))
         d = ConfigDesc()
         d.n_particles = self.M
         d.radius, d.mu = radius, mu
@@ -246,6 +251,7 @@ class Context:
         d.refine_sweeps = refine
         d.targets_per_thread = tpt
         d.far_chunks = far_chunks
+        d.far_split = 1 if far_split else 0
         d.device = device
         d.stream = stream
         d.profile = 1 if profile else 0

@@ -113,7 +113,8 @@ pqn_status pqn_batch_create(int32_t n_inst, const pqn_config_desc* descs, const 
       if (!bad.empty()) return fail(PQN_ERR_INVALID, "instance " + std::to_string(b) + ": " + bad);
       if (!centers[b]) return fail(PQN_ERR_INVALID, "pqn_batch_create: NULL centres");
       if (c.precision != c0.precision || c.gmres_restart != c0.gmres_restart || c.device != c0.device ||
-          c.targets_per_thread != c0.targets_per_thread || c.refine_sweeps != c0.refine_sweeps)
+          c.targets_per_thread != c0.targets_per_thread || c.far_split != c0.far_split ||
+          c.refine_sweeps != c0.refine_sweeps)
         return fail(PQN_ERR_INVALID, "batched instances must share precision, restart, refinement, device and tiling");
     }
     int ndev = 0;

@@ -101,8 +101,9 @@ void pqn_ctx_impl::setup_level(Level& lv, int nt, int np, double tol) {
     ou[f] = make_double4(t.off_up[3 * f], t.off_up[3 * f + 1], t.off_up[3 * f + 2], t.w_up[f]);
   lv.offup.upload(ou.data(), ou.size(), stream);
   const int N = lv.N;
-  lv.tpt = cfg.targets_per_thread == 1 ? 1 : 2;
-  const int nbt = (N + 256 * lv.tpt - 1) / (256 * lv.tpt);
+  lv.tpt = far_layout(cfg);
+  const int tgt_per_block = lv.tpt == 0 ? 64 : 256 * lv.tpt;
+  const int nbt = (N + tgt_per_block - 1) / tgt_per_block;
   int nch = cfg.far_chunks > 0 ? cfg.far_chunks : std::max(1, (4096 + nbt - 1) / nbt);
   nch = std::min(nch, M);
   lv.spc = (M + nch - 1) / nch;
@@ -322,7 +323,7 @@ void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
       long cost;
     };
     std::vector<Item> items;
-    const int tpt = cfg.targets_per_thread == 1 ? 1 : 2;
+    const int tpt = far_layout(cfg);
     for (MvGroup& gr : groups) {
       Level& lv = *gr.lv;
       FarDesc d{};
@@ -335,7 +336,8 @@ void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
       d.M = lv.M;
       d.N = lv.N;
       d.spc = lv.spc;
-      d.ntb = prec == 1 ? (lv.N + 256 * tpt - 1) / (256 * tpt) : (lv.N + 255) / 256;
+      const int per_block = prec == 1 ? (tpt == 0 ? 64 : 256 * tpt) : 256;
+      d.ntb = (lv.N + per_block - 1) / per_block;
       d.scale = 3.0 / (4.0 * kPi * gr.c->a);
       items.push_back({d, (long)lv.n * lv.n * lv.spc});
     }

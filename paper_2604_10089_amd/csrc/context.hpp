@@ -58,6 +58,13 @@ struct Timer {
 };
 
 // Work buffers of one density (one right-hand side) on one level.
+// Far FP32 launch layout from the configuration: 0 = split (64 targets per
+// block, four waves share the sources), 1 or 2 = targets per thread.
+inline int far_layout(const pqn_config_desc& c) {
+  if (c.far_split) return 0;
+  return c.targets_per_thread == 1 ? 1 : 2;
+}
+
 struct Work {
   DevArray<double> far_part, near_part, coef, qup, selfo, mom;
 };

@@ -65,12 +65,82 @@ __global__ __launch_bounds__(256) void k_pack64(QPtrs q, const double* __restric
 // sphere's contribution (one tile) is summed in the pair precision and added
 // to an FP64 accumulator.
 
+// One source sphere j, nodes [k0, k1), against TPT targets per thread: the
+// tile is summed in FP32 and added to the FP64 accumulators of active targets.
+template <int TPT, int K>
+__device__ __forceinline__ void far32_tile(int j, int k0, int k1, const float* __restrict__ src,
+                                           const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
+                                           int n, int M, const bool (&valid)[TPT], const int (&ti)[TPT],
+                                           const double (&px)[TPT], const double (&py)[TPT], const double (&pz)[TPT],
+                                           const double (&ox)[TPT], const double (&oy)[TPT],
+                                           const double (&oz)[TPT], double (&acc)[TPT][K][3]) {
+  constexpr int S = src32_stride(K);
+  const double cjx = ctr[3 * j], cjy = ctr[3 * j + 1], cjz = ctr[3 * j + 2];
+  bool act[TPT];
+  int any = 0;
+#pragma unroll
+  for (int u = 0; u < TPT; ++u) {
+    act[u] = valid[u] && cls[ti[u] * M + j] == 0;
+    any |= act[u];
+  }
+  if (!__any(any)) return;
+  float Xx[TPT], Xy[TPT], Xz[TPT], sm[TPT][K][3];
+#pragma unroll
+  for (int u = 0; u < TPT; ++u) {
+    Xx[u] = act[u] ? (float)((px[u] - cjx) + ox[u]) : 1.0e4f;
+    Xy[u] = act[u] ? (float)((py[u] - cjy) + oy[u]) : 0.0f;
+    Xz[u] = act[u] ? (float)((pz[u] - cjz) + oz[u]) : 0.0f;
+#pragma unroll
+    for (int r = 0; r < K; ++r) sm[u][r][0] = sm[u][r][1] = sm[u][r][2] = 0.0f;
+  }
+  const float* sp = src + (size_t)j * n * S;
+#pragma unroll 4
+  for (int kk = k0; kk < k1; ++kk) {
+    const float* e = sp + (size_t)kk * S;
+    const float sx = e[0], sy = e[1], sz = e[2];
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+      const float rx = Xx[u] - sx, ry = Xy[u] - sy, rz = Xz[u] - sz;
+      const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+      const float ri = __builtin_amdgcn_rsqf(r2);
+      const float ri2 = ri * ri;
+      const float rn = fmaf(rx, sx, fmaf(ry, sy, rz * sz));
+      const float wgt = rn * ri * ri2 * ri2;
+      if constexpr (K == 1) {
+        const float rq = fmaf(rx, e[3], fmaf(ry, e[4], rz * e[5]));
+        const float c = wgt * rq;
+        sm[u][0][0] = fmaf(c, rx, sm[u][0][0]);
+        sm[u][0][1] = fmaf(c, ry, sm[u][0][1]);
+        sm[u][0][2] = fmaf(c, rz, sm[u][0][2]);
+      } else {
+        // the weight folded into r once: (w r).q costs one multiply per density less
+        const float wx = wgt * rx, wy = wgt * ry, wz = wgt * rz;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+          const float c = fmaf(wx, e[3 + 3 * r], fmaf(wy, e[4 + 3 * r], wz * e[5 + 3 * r]));
+          sm[u][r][0] = fmaf(c, rx, sm[u][r][0]);
+          sm[u][r][1] = fmaf(c, ry, sm[u][r][1]);
+          sm[u][r][2] = fmaf(c, rz, sm[u][r][2]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < TPT; ++u)
+    if (act[u])
+#pragma unroll
+      for (int r = 0; r < K; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[u][r][c] += (double)sm[u][r][c];
+}
+
+// Block = 256 threads owning 256 TPT consecutive targets; every wave streams
+// the whole chunk of source spheres.
 template <int TPT, int K>
 __device__ __forceinline__ void far32_body(int tb, int chunk, const float* __restrict__ src,
                                            const double* __restrict__ off, const double* __restrict__ ctr,
                                            const unsigned char* __restrict__ cls, int n, int M, int N, int spc,
                                            double scale, const OPtrs& part) {
-  constexpr int S = src32_stride(K);
   const int j0 = chunk * spc;
   const int j1 = min(M, j0 + spc);
   int ti[TPT];
@@ -94,56 +164,7 @@ __device__ __forceinline__ void far32_body(int tb, int chunk, const float* __res
 #pragma unroll
     for (int r = 0; r < K; ++r) acc[u][r][0] = acc[u][r][1] = acc[u][r][2] = 0.0;
   }
-  for (int j = j0; j < j1; ++j) {
-    const double cjx = ctr[3 * j], cjy = ctr[3 * j + 1], cjz = ctr[3 * j + 2];
-    bool act[TPT];
-    int any = 0;
-#pragma unroll
-    for (int u = 0; u < TPT; ++u) {
-      act[u] = valid[u] && cls[ti[u] * M + j] == 0;
-      any |= act[u];
-    }
-    if (!__any(any)) continue;
-    float Xx[TPT], Xy[TPT], Xz[TPT], sm[TPT][K][3];
-#pragma unroll
-    for (int u = 0; u < TPT; ++u) {
-      Xx[u] = act[u] ? (float)((px[u] - cjx) + ox[u]) : 1.0e4f;
-      Xy[u] = act[u] ? (float)((py[u] - cjy) + oy[u]) : 0.0f;
-      Xz[u] = act[u] ? (float)((pz[u] - cjz) + oz[u]) : 0.0f;
-#pragma unroll
-      for (int r = 0; r < K; ++r) sm[u][r][0] = sm[u][r][1] = sm[u][r][2] = 0.0f;
-    }
-    const float* sp = src + (size_t)j * n * S;
-#pragma unroll 4
-    for (int kk = 0; kk < n; ++kk) {
-      const float* e = sp + (size_t)kk * S;
-      const float sx = e[0], sy = e[1], sz = e[2];
-#pragma unroll
-      for (int u = 0; u < TPT; ++u) {
-        const float rx = Xx[u] - sx, ry = Xy[u] - sy, rz = Xz[u] - sz;
-        const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
-        const float ri = __builtin_amdgcn_rsqf(r2);
-        const float ri2 = ri * ri;
-        const float rn = fmaf(rx, sx, fmaf(ry, sy, rz * sz));
-        const float wgt = rn * ri * ri2 * ri2;
-#pragma unroll
-        for (int r = 0; r < K; ++r) {
-          const float rq = fmaf(rx, e[3 + 3 * r], fmaf(ry, e[4 + 3 * r], rz * e[5 + 3 * r]));
-          const float c = wgt * rq;
-          sm[u][r][0] = fmaf(c, rx, sm[u][r][0]);
-          sm[u][r][1] = fmaf(c, ry, sm[u][r][1]);
-          sm[u][r][2] = fmaf(c, rz, sm[u][r][2]);
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < TPT; ++u)
-      if (act[u])
-#pragma unroll
-        for (int r = 0; r < K; ++r)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) acc[u][r][c] += (double)sm[u][r][c];
-  }
+  for (int j = j0; j < j1; ++j) far32_tile<TPT, K>(j, 0, n, src, ctr, cls, n, M, valid, ti, px, py, pz, ox, oy, oz, acc);
 #pragma unroll
   for (int u = 0; u < TPT; ++u) {
     const int t = tb * 256 * TPT + u * 256 + threadIdx.x;
@@ -156,6 +177,75 @@ __device__ __forceinline__ void far32_body(int tb, int chunk, const float* __res
         pb[2 * N + t] = scale * acc[u][r][2];
       }
   }
+}
+
+// Split layout: block = 4 waves on the same 64 targets; the chunk's source
+// nodes (spheres j0..j1 flattened) are cut into four equal ranges, one per
+// wave, and the four FP64 partial sums are added in wave order through LDS
+// (one density at a time, so the buffer stays at 9 x 64 doubles). For the same
+// number of chunk partials the grid has four times as many, four times
+// shorter, waves, which evens out the last wave of the launch.
+template <int K>
+__device__ __forceinline__ void far32_split_body(int tb, int chunk, const float* __restrict__ src,
+                                                 const double* __restrict__ off, const double* __restrict__ ctr,
+                                                 const unsigned char* __restrict__ cls, int n, int M, int N, int spc,
+                                                 double scale, const OPtrs& part, double* __restrict__ lds) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j0 = chunk * spc;
+  const int j1 = min(M, j0 + spc);
+  const int t = tb * 64 + lane;
+  int ti[1];
+  bool valid[1];
+  double px[1], py[1], pz[1], ox[1], oy[1], oz[1];
+  double acc[1][K][3];
+  valid[0] = t < N;
+  {
+    const int tt = valid[0] ? t : N - 1;
+    const int i = tt / n;
+    const int k = tt - i * n;
+    ti[0] = i;
+    px[0] = ctr[3 * i];
+    py[0] = ctr[3 * i + 1];
+    pz[0] = ctr[3 * i + 2];
+    ox[0] = off[3 * k];
+    oy[0] = off[3 * k + 1];
+    oz[0] = off[3 * k + 2];
+  }
+#pragma unroll
+  for (int r = 0; r < K; ++r) acc[0][r][0] = acc[0][r][1] = acc[0][r][2] = 0.0;
+  const int len = (j1 - j0) * n;
+  const int s0 = j0 * n + (wv * len) / 4, s1 = j0 * n + ((wv + 1) * len) / 4;
+  for (int s = s0; s < s1;) {
+    const int j = s / n;
+    const int k0 = s - j * n, k1 = min(n, s1 - j * n);
+    far32_tile<1, K>(j, k0, k1, src, ctr, cls, n, M, valid, ti, px, py, pz, ox, oy, oz, acc);
+    s = j * n + k1;
+  }
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    if (wv > 0)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) lds[((wv - 1) * 3 + c) * 64 + lane] = acc[0][r][c];
+    __syncthreads();
+    if (wv == 0 && valid[0]) {
+      double* pb = part.p[r] + (size_t)chunk * 3 * N;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double v = ((acc[0][r][c] + lds[c * 64 + lane]) + lds[(3 + c) * 64 + lane]) + lds[(6 + c) * 64 + lane];
+        pb[(size_t)c * N + t] = scale * v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_far32s(const float* __restrict__ src, const double* __restrict__ off,
+                                                const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
+                                                int n, int M, int N, int spc, double scale, OPtrs part) {
+  __shared__ double lds[9 * 64];
+  far32_split_body<K>(blockIdx.x, blockIdx.y, src, off, ctr, cls, n, M, N, spc, scale, part, lds);
 }
 
 template <int TPT, int K>
@@ -178,7 +268,13 @@ __global__ __launch_bounds__(256) void k_far32_multi(const FarDesc* __restrict__
   const int tb = local % D.ntb, chunk = local / D.ntb;
   OPtrs part;
   part.p[0] = D.part;
-  far32_body<TPT, 1>(tb, chunk, (const float*)D.src, D.off, D.ctr, D.cls, D.n, D.M, D.N, D.spc, D.scale, part);
+  if constexpr (TPT == 0) {
+    __shared__ double lds[9 * 64];
+    far32_split_body<1>(tb, chunk, (const float*)D.src, D.off, D.ctr, D.cls, D.n, D.M, D.N, D.spc, D.scale, part,
+                        lds);
+  } else {
+    far32_body<TPT, 1>(tb, chunk, (const float*)D.src, D.off, D.ctr, D.cls, D.n, D.M, D.N, D.spc, D.scale, part);
+  }
 }
 
 template <int K>
@@ -864,7 +960,10 @@ static void far_k(hipStream_t s, int prec, int tpt, const void* src, const doubl
                   const unsigned char* cls, int n, int M, int N, int spc, int nchunks, double scale,
                   const OPtrs& part) {
   if (prec == 1) {
-    if (tpt == 2)
+    if (tpt == 0)
+      hipLaunchKernelGGL((k_far32s<K>), dim3(nblk(N, 64), nchunks), dim3(256), 0, s, (const float*)src, off, ctr,
+                         cls, n, M, N, spc, scale, part);
+    else if (tpt == 2)
       hipLaunchKernelGGL((k_far32<2, K>), dim3(nblk(N, 512), nchunks), dim3(256), 0, s, (const float*)src, off, ctr,
                          cls, n, M, N, spc, scale, part);
     else
@@ -878,20 +977,23 @@ static void far_k(hipStream_t s, int prec, int tpt, const void* src, const doubl
 
 void launch_far(hipStream_t s, int prec, int K, int tpt, const void* src, const double* off, const double* ctr,
                 const unsigned char* cls, int n, int M, int N, int spc, int nchunks, double scale, const OPtrs& part) {
+  const int t1 = tpt == 0 ? 0 : 1;  // two targets per thread only for K <= 2
   switch (K) {
     case 1: far_k<1>(s, prec, tpt, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
     case 2: far_k<2>(s, prec, tpt, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
-    case 3: far_k<3>(s, prec, 1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
-    case 4: far_k<4>(s, prec, 1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
-    case 5: far_k<5>(s, prec, 1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
-    default: far_k<6>(s, prec, 1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
+    case 3: far_k<3>(s, prec, t1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
+    case 4: far_k<4>(s, prec, t1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
+    case 5: far_k<5>(s, prec, t1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
+    default: far_k<6>(s, prec, t1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
   }
 }
 
 void launch_far_multi(hipStream_t s, int prec, int tpt, const FarDesc* desc, int ndesc, int nitems) {
   if (nitems <= 0) return;
   if (prec == 1) {
-    if (tpt == 2)
+    if (tpt == 0)
+      hipLaunchKernelGGL(k_far32_multi<0>, dim3(nitems), dim3(256), 0, s, desc, ndesc);
+    else if (tpt == 2)
       hipLaunchKernelGGL(k_far32_multi<2>, dim3(nitems), dim3(256), 0, s, desc, ndesc);
     else
       hipLaunchKernelGGL(k_far32_multi<1>, dim3(nitems), dim3(256), 0, s, desc, ndesc);
