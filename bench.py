@@ -27,17 +27,19 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR = 157.3      # TFLOP/s, MI355X FP32 vector (vendor figure, packed issue)
-PEAK_FP32_NONPACKED = 78.6    # TFLOP/s, 256 CU x 64 lanes x 2 flop x 2.4 GHz (no packed FP32)
+PEAK_FP32_VECTOR = 157.3      # TFLOP/s, MI355X FP32 vector FMA (256 CU x 128 lanes/clk x 2 flop x 2.4 GHz)
+PEAK_FP64_VECTOR = 78.6       # TFLOP/s, MI355X FP64 vector FMA
 K_RHS = 6
 PROBE_BYTES = 256 << 20       # reference copy for the HBM byte counters
 
-# HBM bytes of one k_far32<1,6> launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
-# (profiles/k_far32_rsa216_hbm_traffic.md), scaled by what the counters read for a
-# 256 MiB copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0). Valid only for the far-kernel
-# source it was measured on: reported as null once that source changes.
-FAR_TRAFFIC = {'kernel': 'k_far32<1,6>', 'source_sha1': '64873811609cbfcc4edb2a5406ed271fee0fd600',
-               'fetch_kib': 47096.68, 'write_kib': 271188.0, 'fetch_scale': 2.0, 'write_scale': 1.0}
+# HBM bytes of one far FP32 launch with six densities from rocprofv3 --pmc
+# FETCH_SIZE / WRITE_SIZE (profiles/k_far32_rsa216_hbm_traffic.md), scaled by what
+# the counters read for a 256 MiB copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0). Valid
+# only for the far-kernel source and the launch layout it was measured on:
+# reported as null once either changes.
+FAR_TRAFFIC = {'kernel': 'k_far32<1,6>', 'source_sha1': 'a6cf3432f661024da20a19a0db64a4d3d8dff1f6',
+               'layout': {'tpt': 1, 'chunks': 48, 'split': 0},
+               'fetch_kib': 47115.8, 'write_kib': 384912.0, 'fetch_scale': 2.0, 'write_scale': 1.0}
 
 
 def far_source_sha1():
@@ -48,11 +50,18 @@ def far_source_sha1():
     return hashlib.sha1(src[a:b].encode()).hexdigest()
 
 
-def far_traffic_bytes():
+def far_traffic_bytes(layout):
     t = FAR_TRAFFIC
-    if far_source_sha1() != t['source_sha1']:
+    if t['fetch_kib'] is None or far_source_sha1() != t['source_sha1'] or layout != t['layout']:
         return None
     return int(1024 * (t['fetch_kib'] * t['fetch_scale'] + t['write_kib'] * t['write_scale']))
+
+
+def far_kernel_name(layout, K):
+    """Name of the far FP32 kernel a launch layout {tpt, chunks, split} runs for K densities."""
+    if layout['split']:
+        return f'k_far32s<{K}>'
+    return f'k_far32<{layout["tpt"] if K <= 2 else 1},{K}>'
 
 
 def flop_per_pair(K):
@@ -80,6 +89,8 @@ def main():
     ap.add_argument('--no-batch', action='store_true')
     ap.add_argument('--tpt', type=int, default=None, help='targets per thread (default: autotuned)')
     ap.add_argument('--chunks', type=int, default=None, help='far source chunks (default: autotuned)')
+    ap.add_argument('--split', type=int, default=None, choices=(0, 1),
+                    help='far FP32 split layout, 64 targets per block (default: autotuned)')
     ap.add_argument('--counters-probe', action='store_true',
                     help='short run for rocprofv3 --pmc: a 256 MiB device copy (scale reference for FETCH_SIZE/'
                          'WRITE_SIZE) and one six-force-set product on the 216-sphere workload')
@@ -106,9 +117,11 @@ def main():
     K, W = args.steps, args.warmup
     pf = far_pairs(c, n)
 
-    def ctx_for(prec, profile=True):
+    def ctx_for(prec, kr=K_RHS, profile=True):
+        """Context with the launch layout tuned for kr densities per pass (unless fixed on the command line)."""
         return binding.Context(c, None, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision=prec, tpt=args.tpt,
-                               far_chunks=args.chunks, stream=stream.cuda_stream, profile=profile, tune_K=K_RHS)
+                               far_chunks=args.chunks, far_split=args.split, stream=stream.cuda_stream,
+                               profile=profile, tune_K=kr)
 
     FT6 = [inputs.random_forces(100 + k, M, k=K_RHS) for k in range(max(K, 2) + W + 2)]
 
@@ -146,14 +159,19 @@ def main():
     res = {}
     cm = ctx_for('mixed')
     res['mixed6'] = run_multi(cm, K, W, K_RHS)
-    log('mixed K=6', res['mixed6'])
-    res['mixed1'] = run_multi(cm, max(2, K // 2), 1, 1)
-    log('mixed K=1', res['mixed1'])
+    log('mixed K=6', res['mixed6'], cm.far_shape)
+    cm1 = ctx_for('mixed', 1)
+    res['mixed1'] = run_multi(cm1, max(2, K // 2), 1, 1)
+    log('mixed K=1', res['mixed1'], cm1.far_shape)
+    layout1 = cm1.far_shape
+    cm1.close()
     cf = ctx_for('fp64')
     res['fp64_6'] = run_multi(cf, max(1, K // 3), 1, K_RHS)
-    log('fp64 K=6', res['fp64_6'])
-    res['fp64_1'] = run_multi(cf, max(1, K // 3), 1, 1)
-    log('fp64 K=1', res['fp64_1'])
+    log('fp64 K=6', res['fp64_6'], cf.far_shape)
+    cf1 = ctx_for('fp64', 1)
+    res['fp64_1'] = run_multi(cf1, max(1, K // 3), 1, 1)
+    log('fp64 K=1', res['fp64_1'], cf1.far_shape)
+    cf1.close()
 
     # accuracy of mixed vs FP64 on the same six force sets (per velocity block)
     Um, _ = cm.mobility_apply_multi(FT6[0])
@@ -183,6 +201,7 @@ def main():
                                   x_rel_err=float(np.abs(x2 - xs).max() / np.abs(xs).max())),
                         bbpgd=dict(mvp=lb['mvp_hi'], x_rel_err=float(np.abs(x3 - xs).max() / np.abs(xs).max())))
         log('lcp', lcp_info)
+    cm_layout = cm.far_shape
     cm.close()
 
     batch_info = None
@@ -238,12 +257,12 @@ def main():
         'mixed_rel_err_vs_fp64': errs,
         'gmres_iters_per_mvp': {k: round(v['gmres_iters'], 2) for k, v in res.items()},
         'far_kernel_ms': {k: round(v['far_ms'], 4) for k, v in res.items()},
-        'roofline': {'bound': 'alu', 'kernel': 'k_far32<1,6>', 'achieved': round(achieved, 3),
+        'roofline': {'bound': 'alu', 'kernel': far_kernel_name(cm_layout, K_RHS), 'achieved': round(achieved, 3),
                      'peak': PEAK_FP32_VECTOR, 'unit': 'TFLOP/s', 'frac': round(achieved / PEAK_FP32_VECTOR, 4),
-                     'frac_of_nonpacked_peak': round(achieved / PEAK_FP32_NONPACKED, 4),
-                     'flop_per_pair': flop_per_pair(K_RHS), 'traffic': far_traffic_bytes(),
+                     'flop_per_pair': flop_per_pair(K_RHS), 'layout': cm_layout,
+                     'traffic': far_traffic_bytes(cm_layout),
                      'traffic_unit': 'HBM bytes per launch',
-                     'k1': {'kernel': 'k_far32<2,1>', 'achieved': round(achieved1, 3),
+                     'k1': {'kernel': far_kernel_name(layout1, 1), 'layout': layout1, 'achieved': round(achieved1, 3),
                             'frac': round(achieved1 / PEAK_FP32_VECTOR, 4)}},
         'lcp': lcp_info,
         'batch32': batch_info,

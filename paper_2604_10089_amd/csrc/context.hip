@@ -3,6 +3,7 @@
 #include "context.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cstring>
 
 namespace bipqn {
@@ -147,14 +148,20 @@ void pqn_ctx_impl::set_configuration(const double* c, const double* ax) {
     }
     max_slots = std::max(max_slots, h_npart[i]);
   }
-  // ordered near pairs (target sphere, source sphere, partner slot)
+  // ordered near pairs (target sphere, source sphere, partner slot), grouped by
+  // source sphere so that launches reading the same source data run together
   std::vector<int> nl;
-  for (int i = 0; i < M; ++i)
-    for (int s = 0; s < h_npart[i]; ++s) {
-      nl.push_back(i);
-      nl.push_back(h_partners[(size_t)i * kMaxNear + s]);
-      nl.push_back(s);
+  {
+    std::vector<std::array<int, 3>> pr;
+    for (int i = 0; i < M; ++i)
+      for (int s = 0; s < h_npart[i]; ++s) pr.push_back({h_partners[(size_t)i * kMaxNear + s], i, s});
+    std::sort(pr.begin(), pr.end());
+    for (const auto& e : pr) {
+      nl.push_back(e[1]);
+      nl.push_back(e[0]);
+      nl.push_back(e[2]);
     }
+  }
   n_near = (int)nl.size() / 3;
   ctr.upload(centers.data(), centers.size(), stream);
   dax.upload(axes.data(), axes.size(), stream);

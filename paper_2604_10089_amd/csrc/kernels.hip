@@ -65,6 +65,14 @@ __global__ __launch_bounds__(256) void k_pack64(QPtrs q, const double* __restric
 // sphere's contribution (one tile) is summed in the pair precision and added
 // to an FP64 accumulator.
 
+// Workgroups are handed to the eight XCDs in turn (block b to XCD b mod 8).
+// Block b takes work item xcd_item(b) so that each XCD runs one contiguous
+// eighth of the item list: items next to each other in the list read the same
+// sources, which then stay in that XCD's L2. The grid has 8 * per blocks;
+// items past the end exit at once.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_item(int b, int per) { return (b % kXcds) * per + b / kXcds; }
+
 // One source sphere j, nodes [k0, k1), against TPT targets per thread: the
 // tile is summed in FP32 and added to the FP64 accumulators of active targets.
 template <int TPT, int K>
@@ -243,16 +251,23 @@ __device__ __forceinline__ void far32_split_body(int tb, int chunk, const float*
 template <int K>
 __global__ __launch_bounds__(256) void k_far32s(const float* __restrict__ src, const double* __restrict__ off,
                                                 const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
-                                                int n, int M, int N, int spc, double scale, OPtrs part) {
+                                                int n, int M, int N, int spc, double scale, OPtrs part, int ntb,
+                                                int total, int per) {
   __shared__ double lds[9 * 64];
-  far32_split_body<K>(blockIdx.x, blockIdx.y, src, off, ctr, cls, n, M, N, spc, scale, part, lds);
+  const int item = xcd_item(blockIdx.x, per);
+  if (item >= total) return;  // uniform over the block: no barrier is skipped by part of it
+  far32_split_body<K>(item % ntb, item / ntb, src, off, ctr, cls, n, M, N, spc, scale, part, lds);
 }
 
+// Work item = chunk * ntb + target block (chunk-major: an XCD takes whole chunks).
 template <int TPT, int K>
 __global__ __launch_bounds__(256) void k_far32(const float* __restrict__ src, const double* __restrict__ off,
                                                const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
-                                               int n, int M, int N, int spc, double scale, OPtrs part) {
-  far32_body<TPT, K>(blockIdx.x, blockIdx.y, src, off, ctr, cls, n, M, N, spc, scale, part);
+                                               int n, int M, int N, int spc, double scale, OPtrs part, int ntb,
+                                               int total, int per) {
+  const int item = xcd_item(blockIdx.x, per);
+  if (item >= total) return;
+  far32_body<TPT, K>(item % ntb, item / ntb, src, off, ctr, cls, n, M, N, spc, scale, part);
 }
 
 // Many suspensions in one launch: block b takes work item b of a list ordered
@@ -342,8 +357,11 @@ __device__ __forceinline__ void far64_body(int tb, int chunk, const double* __re
 template <int K>
 __global__ __launch_bounds__(256) void k_far64(const double* __restrict__ src, const double* __restrict__ off,
                                                const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
-                                               int n, int M, int N, int spc, double scale, OPtrs part) {
-  far64_body<K>(blockIdx.x, blockIdx.y, src, off, ctr, cls, n, M, N, spc, scale, part);
+                                               int n, int M, int N, int spc, double scale, OPtrs part, int ntb,
+                                               int total, int per) {
+  const int item = xcd_item(blockIdx.x, per);
+  if (item >= total) return;
+  far64_body<K>(item % ntb, item / ntb, src, off, ctr, cls, n, M, N, spc, scale, part);
 }
 
 __global__ __launch_bounds__(256) void k_far64_multi(const FarDesc* __restrict__ desc, int ndesc) {
@@ -542,15 +560,20 @@ __device__ __forceinline__ void near_body(int pair, int chunk, const double* __r
   }
 }
 
+// Work item = pair * nch + target chunk; the pair list is ordered by source
+// sphere, so an XCD's contiguous share re-reads the same upsampled densities.
 template <int K>
 __global__ __launch_bounds__(64 * kNearWaves) void k_near64(const double* __restrict__ ctr,
                                                             const double* __restrict__ off,
                                                             const double4* __restrict__ offup,
                                                             const double* __restrict__ shab, QPtrs qup, QPtrs coef,
                                                             const int* __restrict__ npairs, int n, int M, int N,
-                                                            int nup, int p, int L, double scale, OPtrs near_part) {
+                                                            int nup, int p, int L, double scale, OPtrs near_part,
+                                                            int nch, int total, int per) {
   __shared__ double lds[kNearWaves * 3 * K * 64];
-  near_body<K>(blockIdx.x, blockIdx.y, ctr, off, offup, shab, qup, coef, npairs, n, M, N, nup, p, L, scale, near_part,
+  const int item = xcd_item(blockIdx.x, per);
+  if (item >= total) return;  // uniform over the block
+  near_body<K>(item / nch, item % nch, ctr, off, offup, shab, qup, coef, npairs, n, M, N, nup, p, L, scale, near_part,
                lds);
 }
 
@@ -959,19 +982,23 @@ template <int K>
 static void far_k(hipStream_t s, int prec, int tpt, const void* src, const double* off, const double* ctr,
                   const unsigned char* cls, int n, int M, int N, int spc, int nchunks, double scale,
                   const OPtrs& part) {
+  const int per_block = prec == 1 ? (tpt == 0 ? 64 : 256 * tpt) : 256;
+  const int ntb = (int)nblk(N, per_block);
+  const int total = ntb * nchunks, per = (total + kXcds - 1) / kXcds;
+  const dim3 grid(per * kXcds);
   if (prec == 1) {
     if (tpt == 0)
-      hipLaunchKernelGGL((k_far32s<K>), dim3(nblk(N, 64), nchunks), dim3(256), 0, s, (const float*)src, off, ctr,
-                         cls, n, M, N, spc, scale, part);
+      hipLaunchKernelGGL((k_far32s<K>), grid, dim3(256), 0, s, (const float*)src, off, ctr, cls, n, M, N, spc, scale,
+                         part, ntb, total, per);
     else if (tpt == 2)
-      hipLaunchKernelGGL((k_far32<2, K>), dim3(nblk(N, 512), nchunks), dim3(256), 0, s, (const float*)src, off, ctr,
-                         cls, n, M, N, spc, scale, part);
+      hipLaunchKernelGGL((k_far32<2, K>), grid, dim3(256), 0, s, (const float*)src, off, ctr, cls, n, M, N, spc,
+                         scale, part, ntb, total, per);
     else
-      hipLaunchKernelGGL((k_far32<1, K>), dim3(nblk(N, 256), nchunks), dim3(256), 0, s, (const float*)src, off, ctr,
-                         cls, n, M, N, spc, scale, part);
+      hipLaunchKernelGGL((k_far32<1, K>), grid, dim3(256), 0, s, (const float*)src, off, ctr, cls, n, M, N, spc,
+                         scale, part, ntb, total, per);
   } else {
-    hipLaunchKernelGGL(k_far64<K>, dim3(nblk(N), nchunks), dim3(256), 0, s, (const double*)src, off, ctr, cls, n, M,
-                       N, spc, scale, part);
+    hipLaunchKernelGGL(k_far64<K>, grid, dim3(256), 0, s, (const double*)src, off, ctr, cls, n, M, N, spc, scale,
+                       part, ntb, total, per);
   }
 }
 
@@ -1006,10 +1033,11 @@ void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, cons
                  const double* shab, const QPtrs& qup, const QPtrs& coef, const int* npairs, int n, int M, int N,
                  int nup, int p, int L, double scale, const OPtrs& near_part) {
   if (npairs_count <= 0) return;
-  const dim3 g(npairs_count, (n + 63) / 64);
+  const int nch = (n + 63) / 64, total = npairs_count * nch, per = (total + kXcds - 1) / kXcds;
+  const dim3 g(per * kXcds);
 #define NEARK(KK)                                                                                                \
   hipLaunchKernelGGL(k_near64<KK>, g, dim3(64 * kNearWaves), 0, s, ctr, off, offup, shab, qup, coef, npairs, n, M, \
-                     N, nup, p, L, scale, near_part)
+                     N, nup, p, L, scale, near_part, nch, total, per)
   switch (K) {
     case 1: NEARK(1); break;
     case 2: NEARK(2); break;
