@@ -4,7 +4,8 @@ One timed step = one batched mobility product of K = 6 independent force sets
 U_r = M F_r on 216 spheres of radius 1 at volume fraction 0.3 with 12x24 nodes
 per sphere (62,208 nodes): six GMRES solves (tolerance 1e-8) in lockstep whose
 pair sums share one geometry pass, mixed precision (FP32 far pair sums, FP64
-everything else), forces resident in HBM. value = force sets per second.
+everything else), forces and velocities resident in HBM (the device-pointer
+entry point). value = force sets per second.
 
 The same JSON line reports: the single-force-set rate and the plain FP64 path
 (both K = 1 and K = 6), the mixed-vs-FP64 error of every velocity block, the
@@ -87,6 +88,7 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-lcp', action='store_true')
     ap.add_argument('--no-batch', action='store_true')
+    ap.add_argument('--no-steps', action='store_true')
     ap.add_argument('--tpt', type=int, default=None, help='targets per thread (default: autotuned)')
     ap.add_argument('--chunks', type=int, default=None, help='far source chunks (default: autotuned)')
     ap.add_argument('--split', type=int, default=None, choices=(0, 1),
@@ -124,6 +126,9 @@ def main():
                                profile=profile, tune_K=kr)
 
     FT6 = [inputs.random_forces(100 + k, M, k=K_RHS) for k in range(max(K, 2) + W + 2)]
+    # the timed products read forces from and write velocities to HBM (no host copies)
+    FT6_dev = [torch.as_tensor(np.ascontiguousarray(f), dtype=torch.float64, device=dev) for f in FT6]
+    UO_dev = torch.empty((K_RHS, M, 6), dtype=torch.float64, device=dev)
 
     if args.counters_probe:
         ref = torch.empty(PROBE_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -141,12 +146,12 @@ def main():
 
     def run_multi(ctx, steps, warm, kr):
         for k in range(warm):
-            ctx.mobility_apply_multi(FT6[k][:kr])
+            ctx.mobility_apply_multi_dev(kr, FT6_dev[k].data_ptr(), UO_dev.data_ptr())
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         its = far_ms = nfar = mv = 0
         for k in range(steps):
-            _, st = ctx.mobility_apply_multi(FT6[warm + k][:kr])
+            st = ctx.mobility_apply_multi_dev(kr, FT6_dev[warm + k].data_ptr(), UO_dev.data_ptr())
             its += st['gmres_iters']
             far_ms += st['t_far_ms']
             nfar += st['n_far']
@@ -203,6 +208,43 @@ def main():
         log('lcp', lcp_info)
     cm_layout = cm.far_shape
     cm.close()
+
+    step_info = None
+    if not args.no_steps:
+        # time steps of the Janus suspension (dt 1e-3, contacts below gap 0.1, Bi-PQN): the FP64
+        # trajectory, and the mixed path replayed from each FP64 state
+        axes = inputs.janus_axes(args.seed + 7, M)
+        nsteps, dt = 3, 1e-3
+        states, t64, st64 = [(c, axes)], [], []
+        with ctx_for('fp64', 1, profile=False) as cs:
+            cs.set_state(c, axes)
+            for _ in range(nsteps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = cs.step(dt, 0.1, 'bi')
+                t64.append(time.perf_counter() - t0)
+                st64.append(st)
+                states.append(cs.get_state())
+        tmx, dmax = [], 0.0
+        with ctx_for('mixed', 1, profile=False) as cs:
+            for k in range(nsteps):
+                cs.set_state(*states[k])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                cs.step(dt, 0.1, 'bi')
+                tmx.append(time.perf_counter() - t0)
+                cm_k, _ = cs.get_state()
+                disp = states[k + 1][0] - states[k][0]
+                dmax = max(dmax, float(np.abs(cm_k - states[k + 1][0]).max() / np.abs(disp).max()))
+        step_info = dict(steps=nsteps, dt=dt, contacts=[s_['n_contacts'] for s_ in st64],
+                         active=[s_['n_active'] for s_ in st64],
+                         mvp_hi=[s_['lcp']['mvp_hi'] for s_ in st64], mvp_lo=[s_['lcp']['mvp_lo'] for s_ in st64],
+                         gmres_iters_nc=[s_['gmres_iters_nc'] for s_ in st64],
+                         sec_per_step_fp64=round(float(np.median(t64)), 4),
+                         sec_per_step_mixed=round(float(np.median(tmx)), 4),
+                         speedup=round(float(np.median(t64) / np.median(tmx)), 3),
+                         mixed_displacement_rel_err=dmax)
+        log('steps', step_info)
 
     batch_info = None
     if not args.no_batch:
@@ -266,6 +308,7 @@ def main():
                             'frac': round(achieved1 / PEAK_FP32_VECTOR, 4)}},
         'lcp': lcp_info,
         'batch32': batch_info,
+        'time_steps': step_info,
     }
     if not args.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline(c, nt, nph, res['mixed1'])

@@ -134,14 +134,21 @@ pqn_status pqn_get_state(const pqn_ctx* ctx, double* centers, double* janus_axes
 /* Far pair-sum precision (pqn_precision) for subsequent calls. */
 pqn_status pqn_set_precision(pqn_ctx* ctx, int32_t precision);
 
-/* U = M F (Sec. 2, eq. (mobility); Fig. 1): FT, UO [M][6]. */
+/* U = M F (Sec. 2, eq. (mobility); Fig. 1): FT, UO [M][6] host arrays (row i = F_i, T_i
+ * resp. U_i, Omega_i). Non-finite FT: PQN_ERR_NUMERIC. */
 pqn_status pqn_mobility_apply(pqn_ctx* ctx, const double* FT, double* UO, int32_t fidelity, pqn_mvp_stats* stats);
+/* Same with FT_dev, UO_dev [M][6] in device memory of the context's device (caller-owned);
+ * returns when UO_dev is written. */
 pqn_status pqn_mobility_apply_dev(pqn_ctx* ctx, const double* FT_dev, double* UO_dev, int32_t fidelity,
                                   pqn_mvp_stats* stats);
-/* K <= 6 force sets at once: FT, UO [K][M][6]. The K boundary-integral solves run in
- * lockstep and share every geometry pass of the pair sums (multi-right-hand-side). */
+/* K <= 6 force sets at once: FT, UO [K][M][6] host arrays. The K boundary-integral solves
+ * run in lockstep and share every geometry pass of the pair sums (multi-right-hand-side). */
 pqn_status pqn_mobility_apply_multi(pqn_ctx* ctx, int32_t k_rhs, const double* FT, double* UO, int32_t fidelity,
                                     pqn_mvp_stats* stats);
+/* Same with FT_dev, UO_dev [K][M][6] in device memory (caller-owned); returns when UO_dev is
+ * written. A non-finite force set makes the right-hand-side norm non-finite: PQN_ERR_NUMERIC. */
+pqn_status pqn_mobility_apply_multi_dev(pqn_ctx* ctx, int32_t k_rhs, const double* FT_dev, double* UO_dev,
+                                        int32_t fidelity, pqn_mvp_stats* stats);
 /* Slip-driven rigid velocities U_nc (F = T = 0), UO [M][6]. */
 pqn_status pqn_nc_velocity(pqn_ctx* ctx, double* UO, int32_t fidelity, pqn_mvp_stats* stats);
 

@@ -67,12 +67,23 @@ _I = _P(C.c_int32)
 
 
 def lib():
-    """Load libbipqn.so (raises if it has not been built)."""
+    """Load libbipqn.so (raises if it has not been built).
+
+    PyTorch is imported first when it is installed: its bundled HIP runtime
+    carries the same soname as the system one the library links, so the
+    library then binds to the runtime already in the process and torch's
+    device pointers and streams are valid in library calls. Loading the
+    library first would put a second HIP runtime into the process.
+    """
     global _LIB
     if _LIB is not None:
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f'{LIB_PATH} is missing: build it first (python -m paper_2604_10089_amd.build)')
+    try:
+        import torch  # noqa: F401  (loads the process's HIP runtime; no device is touched)
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     V = C.c_void_p
     sig = {
@@ -83,6 +94,7 @@ def lib():
         'pqn_set_precision': (C.c_int, [V, C.c_int32]),
         'pqn_mobility_apply': (C.c_int, [V, _D, _D, C.c_int32, _P(MvpStats)]),
         'pqn_mobility_apply_dev': (C.c_int, [V, V, V, C.c_int32, _P(MvpStats)]),
+        'pqn_mobility_apply_multi_dev': (C.c_int, [V, C.c_int32, V, V, C.c_int32, _P(MvpStats)]),
         'pqn_nc_velocity': (C.c_int, [V, _D, C.c_int32, _P(MvpStats)]),
         'pqn_find_contacts': (C.c_int, [V, C.c_double, C.c_int32, _I, _I, _D]),
         'pqn_lcp_apply': (C.c_int, [V, C.c_int32, _I, _D, _D, C.c_int32]),
@@ -312,6 +324,13 @@ class Context:
         st = MvpStats()
         status = _check(lib().pqn_mobility_apply_dev(self.h, C.c_void_p(FT_ptr), C.c_void_p(UO_ptr), fidelity,
                                                      C.byref(st)))
+        return dict(_struct_dict(st), status=status)
+
+    def mobility_apply_multi_dev(self, k_rhs, FT_ptr, UO_ptr, fidelity=PQN_HIFI):
+        """K force sets in device memory: FT_ptr, UO_ptr address [K][M][6] FP64 arrays."""
+        st = MvpStats()
+        status = _check(lib().pqn_mobility_apply_multi_dev(self.h, k_rhs, C.c_void_p(FT_ptr), C.c_void_p(UO_ptr),
+                                                           fidelity, C.byref(st)))
         return dict(_struct_dict(st), status=status)
 
     def nc_velocity(self, fidelity=PQN_HIFI):

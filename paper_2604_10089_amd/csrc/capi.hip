@@ -185,6 +185,33 @@ pqn_status pqn_batch_mobility_apply(pqn_ctx* ctx, const double* const* FT, doubl
   });
 }
 
+// K force sets already on the device: FT_dev, UO_dev [K][M][6].
+static pqn_status mobility_multi_common(pqn_ctx* ctx, int32_t k_rhs, const double* FT_dev, double* UO_dev,
+                                        int32_t fidelity, pqn_mvp_stats* stats) {
+  Timer tm;
+  Level& lv = ctx->level(fidelity);
+  const size_t m6 = 6 * (size_t)ctx->M;
+  const double* fp[kMaxRhs];
+  double* up[kMaxRhs];
+  for (int r = 0; r < k_rhs; ++r) {
+    fp[r] = FT_dev + r * m6;
+    up[r] = UO_dev + r * m6;
+  }
+  ctx->n_matvec = 0;
+  ctx->n_graph_launch = 0;
+  ctx->n_far = 0;
+  pqn_mvp_stats st{};
+  ctx->mobility_multi(lv, k_rhs, fp, nullptr, up, &st);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  st.t_far_ms = ctx->end_far_timing();
+  st.matvecs = ctx->n_matvec;
+  st.n_far = ctx->n_far;
+  st.graph_launches = ctx->n_graph_launch;
+  st.t_total_ms = tm.ms();
+  if (stats) *stats = st;
+  return st.converged ? PQN_OK : PQN_WARN_NOT_CONVERGED;
+}
+
 pqn_status pqn_mobility_apply_multi(pqn_ctx* ctx, int32_t k_rhs, const double* FT, double* UO, int32_t fidelity,
                                     pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
@@ -194,30 +221,23 @@ pqn_status pqn_mobility_apply_multi(pqn_ctx* ctx, int32_t k_rhs, const double* F
     for (int k = 0; k < 6 * ctx->M * k_rhs; ++k)
       if (!std::isfinite(FT[k])) return fail(PQN_ERR_NUMERIC, "non-finite force/torque");
     HIPCHK(hipSetDevice(ctx->device));
-    Timer tm;
-    Level& lv = ctx->level(fidelity);
     const size_t m6 = 6 * (size_t)ctx->M;
     HIPCHK(hipMemcpyAsync(ctx->FT.p, FT, k_rhs * m6 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    const double* fp[kMaxRhs];
-    double* up[kMaxRhs];
-    for (int r = 0; r < k_rhs; ++r) {
-      fp[r] = ctx->FT.p + r * m6;
-      up[r] = ctx->UO.p + r * m6;
-    }
-    ctx->n_matvec = 0;
-    ctx->n_graph_launch = 0;
-    ctx->n_far = 0;
-    pqn_mvp_stats st{};
-    ctx->mobility_multi(lv, k_rhs, fp, nullptr, up, &st);
+    const pqn_status s = mobility_multi_common(ctx, k_rhs, ctx->FT.p, ctx->UO.p, fidelity, stats);
     HIPCHK(hipMemcpyAsync(UO, ctx->UO.p, k_rhs * m6 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    st.t_far_ms = ctx->end_far_timing();
-    st.matvecs = ctx->n_matvec;
-    st.n_far = ctx->n_far;
-    st.graph_launches = ctx->n_graph_launch;
-    st.t_total_ms = tm.ms();
-    if (stats) *stats = st;
-    return st.converged ? PQN_OK : PQN_WARN_NOT_CONVERGED;
+    return s;
+  });
+}
+
+pqn_status pqn_mobility_apply_multi_dev(pqn_ctx* ctx, int32_t k_rhs, const double* FT_dev, double* UO_dev,
+                                        int32_t fidelity, pqn_mvp_stats* stats) {
+  return guarded([&]() -> pqn_status {
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_mobility_apply_multi_dev needs a single-suspension context");
+    if (!ctx || !FT_dev || !UO_dev || k_rhs < 1 || k_rhs > kMaxRhs)
+      return fail(PQN_ERR_INVALID, "pqn_mobility_apply_multi_dev: bad argument (1 <= k_rhs <= 6)");
+    HIPCHK(hipSetDevice(ctx->device));
+    return mobility_multi_common(ctx, k_rhs, FT_dev, UO_dev, fidelity, stats);
   });
 }
 

@@ -121,9 +121,11 @@ void pqn_ctx_impl::set_configuration(const double* c, const double* ax) {
   centers.assign(c, c + 3 * (size_t)M);
   for (double v : centers)
     if (!std::isfinite(v)) throw Error(PQN_ERR_NUMERIC, "non-finite centre coordinate");
+  // ax may point into axes itself (re-setting the centres only): copy before overwriting
+  std::vector<double> axn(3 * (size_t)M, 0.0);
+  if (ax) std::copy(ax, ax + 3 * (size_t)M, axn.begin());
   has_axes = ax != nullptr;
-  axes.assign(3 * (size_t)M, 0.0);
-  if (ax) std::copy(ax, ax + 3 * (size_t)M, axes.begin());
+  axes.swap(axn);
   // pair classes: 2 = same sphere, 1 = near (gap < near_gap), 0 = far
   std::vector<unsigned char> hc((size_t)M * M, 0);
   h_partners.assign((size_t)M * kMaxNear, -1);

@@ -47,6 +47,21 @@ def test_multi_rhs_matches_oracle():
         assert rel(U[r], bie.mobility_apply(g, FT[r], dense=A)) < 1e-10
 
 
+def test_multi_rhs_device_pointers_match_host_arrays():
+    import torch
+    w = inputs.workload('tiny', 2)
+    c = w['centers']
+    FT = inputs.random_forces(23, c.shape[0], k=4)
+    with binding.Context(c, None, 8, 16, gmres_tol=1e-12, precision='mixed') as ctx:
+        U, _ = ctx.mobility_apply_multi(FT)
+        FTd = torch.as_tensor(np.ascontiguousarray(FT), dtype=torch.float64, device='cuda:0')
+        UOd = torch.full((4, c.shape[0], 6), float('nan'), dtype=torch.float64, device='cuda:0')
+        st = ctx.mobility_apply_multi_dev(4, FTd.data_ptr(), UOd.data_ptr())
+        Ud = UOd.cpu().numpy()
+    assert st['converged'] == 1
+    assert np.array_equal(U, Ud)
+
+
 def test_multi_rhs_full_size_vs_single():
     w = inputs.workload('rsa216', 0)
     c = w['centers']

@@ -151,3 +151,18 @@ def test_mixed_vs_fp64_mobility_rsa216():
             out[prec], st = ctx.mobility_apply(FT)
     for blk in (slice(0, 3), slice(3, 6)):
         assert rel(out['mixed'][:, blk], out['fp64'][:, blk]) < 1e-6
+
+
+def test_set_state_without_axes_keeps_janus_axes(tiny):
+    """Re-setting only the centres keeps the context's Janus axes (and hence U_nc)."""
+    c, g, A = tiny
+    axes = inputs.janus_axes(9, g.M)
+    c2 = c + 0.01
+    with binding.Context(c, axes, 8, 16, gmres_tol=1e-12) as ctx, \
+            binding.Context(c2, axes, 8, 16, gmres_tol=1e-12) as ref:
+        ctx.set_state(c2)
+        _, ax = ctx.get_state()
+        assert np.array_equal(ax, axes)
+        U, _ = ctx.nc_velocity()
+        Ur, _ = ref.nc_velocity()
+    assert rel(U, Ur) < 1e-12
