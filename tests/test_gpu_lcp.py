@@ -111,3 +111,19 @@ def test_lcp_edge_cases(cases):
             ctx.lcp_solve(np.array([[0, 99]], np.int32), np.array([-1.0]), 'mono')
         with pytest.raises(binding.PqnError):
             ctx.lcp_solve(cs['pairs'], np.full(cs['pairs'].shape[0], np.nan), 'mono')
+
+
+def test_bi_pqn_exact_model_counts_match_oracle(cases):
+    """Low fidelity = high fidelity grid: the device Bi-PQN needs as few high-fidelity
+    products as the oracle's (2-4), fewer than Mono-PQN."""
+    for cs in cases:
+        b = cs['b_pl']
+        Aop = lcp.lcp_operator(lambda F, cs=cs: bie.mobility_apply(cs['g'], F, dense=cs['A']), cs['c'], cs['pairs'])
+        _, _, sb = lcp.bi_pqn(Aop, Aop, b)
+        with binding.Context(cs['c'], None, 8, 16, lo=(8, 16), gmres_tol=1e-13) as ctx:
+            x, gb = ctx.lcp_solve(cs['pairs'], b, 'bi')
+            _, gm = ctx.lcp_solve(cs['pairs'], b, 'mono')
+        say('bi exact model', gb['mvp_hi'], gb['mvp_lo'], 'oracle', sb['mvp_hi'], sb['mvp_lo'], 'mono', gm['mvp_hi'])
+        assert abs(gb['mvp_hi'] - sb['mvp_hi']) <= 1
+        assert gb['mvp_hi'] < gm['mvp_hi']
+        assert np.abs(x - cs['x_pl']).max() < 1e-7 * np.abs(cs['x_pl']).max()

@@ -185,3 +185,14 @@ def test_mvp_counts_in_paper_range(tiny_lcps):
         counts.append((sm['mvp'], sb['mvp']))
     for m, bb in counts:
         assert m <= 3 * soft['mono_pqn_median'] and bb <= 5 * soft['bb_pgd_median']
+
+
+def test_bi_pqn_with_exact_model_needs_few_high_fidelity_products(tiny_lcps):
+    """Alg. 4 with the low-fidelity operator equal to A: each subproblem is the
+    problem itself solved to 1e-2 of the current KKT error, so the high-fidelity
+    products only confirm and polish (2-4 here), fewer than Mono-PQN needs."""
+    for c in tiny_lcps:
+        x, _, sb = lcp.bi_pqn(c['Aop'], c['Aop'], c['b_pl'])
+        _, _, sm = lcp.mono_pqn(c['Aop'], c['b_pl'])
+        assert np.abs(x - c['x_pl']).max() < 1e-7 * np.abs(c['x_pl']).max()
+        assert sb['mvp_hi'] <= 4 and sb['mvp_hi'] < sm['mvp']
