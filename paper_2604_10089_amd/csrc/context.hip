@@ -205,9 +205,41 @@ double pqn_ctx_impl::end_far_timing() {
 }
 
 // y_r = (1/2 I + D + P) q_r for every density of every group.
+void add_to_groups(std::vector<MvGroup>& groups, pqn_ctx_impl* c, Level* lv, int slot, const double* in,
+                   double* out) {
+  MvGroup* g = nullptr;
+  for (MvGroup& gg : groups)
+    if (gg.c == c && gg.lv == lv) g = &gg;
+  if (!g) {
+    groups.push_back(MvGroup{c, lv, 0, {}, {}, {}});
+    g = &groups.back();
+  }
+  if (g->K >= kMaxRhs) throw Error(PQN_ERR_STATE, "more than 6 densities on one level in one pass");
+  g->slot[g->K] = slot;
+  g->in[g->K] = in;
+  g->out[g->K] = out;
+  ++g->K;
+}
+
+// The interleaved upsampled densities of a group: [M][nup][3K] in the work
+// buffer of the group's first slot (grown on first use with more densities).
+static double* group_qup(MvGroup& gr) {
+  Level& lv = *gr.lv;
+  Work& w0 = lv.wk(gr.slot[0]);
+  const size_t need = (size_t)3 * gr.K * lv.M * lv.nup;
+  if (w0.qup.count < need) {
+    HIPCHK(hipDeviceSynchronize());  // the old buffer may still be read by queued work
+    w0.qup.alloc(need);
+  }
+  return w0.qup.p;
+}
+
 void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
   hipStream_t s = stream;
   const int prec = precision == PQN_MIXED ? 1 : 0;
+  for (size_t a = 0; a < groups.size(); ++a)
+    for (size_t b = a + 1; b < groups.size(); ++b)
+      if (groups[a].lv == groups[b].lv) throw Error(PQN_ERR_STATE, "internal: two density groups on one level");
   bool all_single = groups.size() > 1;
   for (MvGroup& gr : groups)
     if (gr.K != 1) all_single = false;
@@ -222,8 +254,10 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
     QPtrs qp{};
     std::vector<GemmDesc> ga, gb;
     int nga = 0, ngb = 0;
+    double* qup = c.n_near > 0 ? group_qup(gr) : nullptr;
+    const int C = 3 * gr.K;
     for (int r = 0; r < gr.K; ++r) {
-      Work& w = lv.wk(gr.slot0 + r);
+      Work& w = lv.wk(gr.slot[r]);
       for (int comp = 0; comp < 3; ++comp) {
         // harmonic coefficients of every sphere's density: coef = T q
         push_gemm(ga, nga, L, M, n, lv.T.p, n, gr.in[r] + (size_t)comp * N, n, w.coef.p + (size_t)comp * M * L, L, 0,
@@ -231,9 +265,9 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
         // singular self interaction on the coefficients, one partial per source component
         push_gemm(gb, ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, w.coef.p + (size_t)comp * M * L, L,
                   w.selfo.p + (size_t)comp * 3 * N, n, N, n);
-        if (c.n_near > 0)  // density on the upsampled grid of every sphere: qup = Yup coef
-          push_gemm(gb, ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L,
-                    w.qup.p + (size_t)comp * M * nup, nup, 0, nup);
+        if (qup)  // density on the upsampled grid of every sphere, interleaved: qup[j][f][3r + comp] = (Yup coef)
+          push_gemm(gb, ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L, qup + 3 * r + comp, 1, C,
+                    nup * C);
       }
       qp.p[r] = gr.in[r];
     }
@@ -249,7 +283,7 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
     for (MvGroup& gr : groups) {
       Level& lv = *gr.lv;
       OPtrs op{};
-      for (int r = 0; r < gr.K; ++r) op.p[r] = lv.wk(gr.slot0 + r).far_part.p;
+      for (int r = 0; r < gr.K; ++r) op.p[r] = lv.wk(gr.slot[r]).far_part.p;
       launch_far(s, prec, gr.K, lv.tpt, lv.src.p, lv.off.p, gr.c->ctr.p, gr.c->cls.p, lv.n, lv.M, lv.N, lv.spc,
                  lv.nchunks, 3.0 / (4.0 * kPi * gr.c->a), op);
     }
@@ -259,18 +293,18 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
   for (MvGroup& gr : groups) {
     Level& lv = *gr.lv;
     pqn_ctx_impl& c = *gr.c;
-    QPtrs qu{}, cf{};
+    QPtrs cf{};
     OPtrs np{};
     for (int r = 0; r < gr.K; ++r) {
-      Work& w = lv.wk(gr.slot0 + r);
-      qu.p[r] = w.qup.p;
+      Work& w = lv.wk(gr.slot[r]);
       cf.p[r] = w.coef.p;
       np.p[r] = w.near_part.p;
     }
-    launch_near(s, gr.K, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, qu, cf, c.near_list.p, lv.n, lv.M, lv.N,
+    const double* qup = lv.wk(gr.slot[0]).qup.p;
+    launch_near(s, gr.K, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, qup, cf, c.near_list.p, lv.n, lv.M, lv.N,
                 lv.nup, lv.p, lv.L, 3.0 / (4.0 * kPi * c.a), np);
     for (int r = 0; r < gr.K; ++r) {
-      Work& w = lv.wk(gr.slot0 + r);
+      Work& w = lv.wk(gr.slot[r]);
       launch_moments(s, gr.in[r], lv.off.p, lv.w.p, lv.n, lv.M, lv.N, w.mom.p);
       launch_combine(s, gr.in[r], w.selfo.p, 3, w.far_part.p, lv.nchunks, w.near_part.p, c.npart.p, w.mom.p,
                      lv.off.p, lv.n, lv.N, c.a, gr.out[r]);
@@ -294,16 +328,16 @@ void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
   for (MvGroup& gr : groups) {
     Level& lv = *gr.lv;
     pqn_ctx_impl& c = *gr.c;
-    Work& w = lv.wk(gr.slot0);
+    Work& w = lv.wk(gr.slot[0]);
     const int n = lv.n, N = lv.N, L = lv.L, nup = lv.nup, M = lv.M;
     for (int comp = 0; comp < 3; ++comp) {
       push_gemm(ga, nga, L, M, n, lv.T.p, n, gr.in[0] + (size_t)comp * N, n, w.coef.p + (size_t)comp * M * L, L, 0,
                 L);
       push_gemm(gb, ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, w.coef.p + (size_t)comp * M * L, L,
                 w.selfo.p + (size_t)comp * 3 * N, n, N, n);
-      if (c.n_near > 0)
-        push_gemm(gb, ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L,
-                  w.qup.p + (size_t)comp * M * nup, nup, 0, nup);
+      if (c.n_near > 0)  // interleaved [M][nup][3]
+        push_gemm(gb, ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup.p + comp, 1, 3,
+                  nup * 3);
     }
     pk.push_back(PackDesc{gr.in[0], lv.off.p, lv.w.p, lv.src.p, n, N, npk});
     npk += N;
@@ -340,7 +374,7 @@ void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
       d.off = lv.off.p;
       d.ctr = gr.c->ctr.p;
       d.cls = gr.c->cls.p;
-      d.part = lv.wk(gr.slot0).far_part.p;
+      d.part = lv.wk(gr.slot[0]).far_part.p;
       d.n = lv.n;
       d.M = lv.M;
       d.N = lv.N;
@@ -371,8 +405,8 @@ void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
 }
 
 void pqn_ctx_impl::apply_operator(Level& lv, int precision, const double* q, double* y) {
-  std::vector<MvGroup> g(1);
-  g[0] = MvGroup{this, &lv, 1, 0, {q}, {y}};
+  std::vector<MvGroup> g;
+  add_to_groups(g, this, &lv, 0, q, y);
   matvec_groups(g, precision);
 }
 
@@ -398,9 +432,8 @@ IterTables pqn_ctx_impl::iteration_tables(pqn_ctx_impl& c, Level& lv, int slot, 
     push_gemm(ga, t.nga, L, M, n, lv.T.p, n, q + (size_t)comp * N, n, w.coef.p + (size_t)comp * M * L, L, 0, L);
     push_gemm(gb, t.ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, w.coef.p + (size_t)comp * M * L, L,
               w.selfo.p + (size_t)comp * 3 * N, n, N, n);
-    if (c.n_near > 0)
-      push_gemm(gb, t.ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L,
-                w.qup.p + (size_t)comp * M * nup, nup, 0, nup);
+    if (c.n_near > 0)  // interleaved [M][nup][3]
+      push_gemm(gb, t.ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup.p + comp, 1, 3, nup * 3);
   }
   DescPack dp;
   t.oa = dp.add(ga);
@@ -432,12 +465,11 @@ void pqn_ctx_impl::iteration_launches(pqn_ctx_impl& c, Level& lv, int slot, int 
   op.p[0] = wk.far_part.p;
   launch_far(s, prec, 1, lv.tpt, lv.src.p, lv.off.p, c.ctr.p, c.cls.p, lv.n, lv.M, lv.N, lv.spc, lv.nchunks, scale,
              op);
-  QPtrs qu{}, cf{};
+  QPtrs cf{};
   OPtrs np{};
-  qu.p[0] = wk.qup.p;
   cf.p[0] = wk.coef.p;
   np.p[0] = wk.near_part.p;
-  launch_near(s, 1, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, qu, cf, c.near_list.p, lv.n, lv.M, lv.N,
+  launch_near(s, 1, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, wk.qup.p, cf, c.near_list.p, lv.n, lv.M, lv.N,
               lv.nup, lv.p, lv.L, scale, np);
   launch_moments(s, q, lv.off.p, lv.w.p, lv.n, lv.M, lv.N, wk.mom.p);
   launch_combine(s, q, wk.selfo.p, 3, wk.far_part.p, lv.nchunks, wk.near_part.p, c.npart.p, wk.mom.p, lv.off.p, lv.n,
@@ -455,13 +487,16 @@ void pqn_ctx_impl::iteration_launches(pqn_ctx_impl& c, Level& lv, int slot, int 
 void pqn_ctx_impl::launch_iteration_graph(pqn_ctx_impl& c, Level& lv, int slot, int prec, int k, double* hp, int m) {
   while ((int)lv.graphs.size() <= slot) lv.graphs.emplace_back(new GraphCache());
   GraphCache& gc = *lv.graphs[slot];
-  if (gc.epoch != c.config_epoch || gc.prec != prec || (int)gc.execs.size() != m || gc.hp != hp) {
+  const double* qup_now = lv.wk(slot).qup.p;  // may move when a wider group grows it
+  if (gc.epoch != c.config_epoch || gc.prec != prec || (int)gc.execs.size() != m || gc.hp != hp ||
+      gc.qup != qup_now) {
     HIPCHK(hipStreamSynchronize(stream));
     gc.clear();
     gc.execs.assign(m, nullptr);
     gc.epoch = c.config_epoch;
     gc.prec = prec;
     gc.hp = hp;
+    gc.qup = qup_now;
   }
   SysBuf& b = lv.sb(slot);
   const long len = 3L * lv.N;
@@ -567,16 +602,7 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
       SysBuf& b = sys[i].lv->sb(sys[i].slot);
       const double* in = use_x ? sys[i].x : b.V.p + (size_t)st[i].k * len_of(i);
       double* out = use_x ? b.r.p : b.V.p + (size_t)(st[i].k + 1) * len_of(i);
-      MvGroup* g = nullptr;
-      for (MvGroup& gg : groups)
-        if (gg.c == sys[i].c && gg.lv == sys[i].lv && gg.K < kMaxRhs && gg.slot0 + gg.K == sys[i].slot) g = &gg;
-      if (!g) {
-        groups.push_back(MvGroup{sys[i].c, sys[i].lv, 0, sys[i].slot, {}, {}});
-        g = &groups.back();
-      }
-      g->in[g->K] = in;
-      g->out[g->K] = out;
-      ++g->K;
+      add_to_groups(groups, sys[i].c, sys[i].lv, sys[i].slot, in, out);
     }
     return groups;
   };
@@ -749,7 +775,7 @@ void pqn_ctx_impl::solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st) {
       std::vector<MvGroup> groups;
       for (int i = 0; i < ns; ++i) {
         SysBuf& b = sys[i].lv->sb(sys[i].slot);
-        groups.push_back(MvGroup{sys[i].c, sys[i].lv, 1, sys[i].slot, {sys[i].x}, {b.tmp.p}});
+        add_to_groups(groups, sys[i].c, sys[i].lv, sys[i].slot, sys[i].x, b.tmp.p);
       }
       matvec_groups(groups, PQN_FP64);
       std::vector<SysRef> corr;

@@ -84,7 +84,8 @@ struct IterTables {
 struct GraphCache {
   int prec = -1;
   unsigned long epoch = 0;
-  const double* hp = nullptr;  // Hessenberg staging the graphs write to
+  const double* hp = nullptr;   // Hessenberg staging the graphs write to
+  const double* qup = nullptr;  // upsampled-density buffer the graphs read
   std::vector<hipGraphExec_t> execs;
   DevArray<char> dtab;  // per-k descriptor tables read by the captured kernels
   size_t stride = 0;
@@ -119,14 +120,21 @@ struct pqn_ctx_impl;
 
 // A group of K densities on one level of one context: K operator applications
 // that share the geometry pass of the pair sums.
+// All densities of one (context, level) form one group: the level's packed
+// source buffer and the group's interleaved upsampled density are shared by
+// the group, so a second group on the same level would overwrite them.
 struct MvGroup {
   pqn_ctx_impl* c;
   Level* lv;
   int K;
-  int slot0;  // work slots slot0 .. slot0+K-1
+  int slot[kMaxRhs];  // work slot of density r
   const double* in[kMaxRhs];
   double* out[kMaxRhs];
 };
+
+// Add density (in -> out, work slot) to the group of its (context, level).
+void add_to_groups(std::vector<MvGroup>& groups, pqn_ctx_impl* c, Level* lv, int slot, const double* in,
+                   double* out);
 
 // One linear system (1/2 + D + P) x = rhs in the lockstep GMRES engine.
 struct SysRef {

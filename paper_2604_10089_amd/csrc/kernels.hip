@@ -390,6 +390,9 @@ __global__ __launch_bounds__(256) void k_far64_multi(const FarDesc* __restrict__
 // orders m = w (mod kNearWaves) of the foot-point expansion; the partial sums
 // meet in LDS and are added in wave order, so results do not depend on timing.
 // Within a wave the source records and coefficients are uniform (scalar loads).
+// The upsampled densities of the K densities are interleaved per node,
+// qup[(j * nup + f) * 3K + 3r + c], so one node's values are one contiguous
+// scalar-load stream.
 
 constexpr int kNearWaves = 4;
 
@@ -444,7 +447,8 @@ __device__ __forceinline__ void foot_part(int p, double ct, double st, double cp
 template <int K>
 __device__ __forceinline__ void near_body(int pair, int chunk, const double* __restrict__ ctr,
                                           const double* __restrict__ off, const double4* __restrict__ offup,
-                                          const double* __restrict__ shab, const QPtrs& qup, const QPtrs& coef,
+                                          const double* __restrict__ shab, const double* __restrict__ qup,
+                                          const QPtrs& coef,
                                           const int* __restrict__ npairs, int n, int M, int N, int nup, int p, int L,
                                           double scale, const OPtrs& near_part, double* __restrict__ lds) {
   constexpr int C = 3 * K;
@@ -458,7 +462,7 @@ __device__ __forceinline__ void near_body(int pair, int chunk, const double* __r
   const double Xx = (ctr[3 * i] + off[3 * kk]) - ctr[3 * j];
   const double Xy = (ctr[3 * i + 1] + off[3 * kk + 1]) - ctr[3 * j + 1];
   const double Xz = (ctr[3 * i + 2] + off[3 * kk + 2]) - ctr[3 * j + 2];
-  const size_t ML = (size_t)M * L, MU = (size_t)M * nup;
+  const size_t ML = (size_t)M * L;
   double f[K][3];
   {
     const double rho = sqrt(Xx * Xx + Xy * Xy);
@@ -498,8 +502,8 @@ __device__ __forceinline__ void near_body(int pair, int chunk, const double* __r
     const double rn = fma(rx, o.x, fma(ry, o.y, rz * o.z));
     const double wgt = o.w * rn * ri * ri2 * ri2;
     if constexpr (K == 1) {
-      const double* qx = qup.p[0] + (size_t)j * nup + fi;
-      const double dqx = qx[0] - f[0][0], dqy = qx[MU] - f[0][1], dqz = qx[2 * MU] - f[0][2];
+      const double* qx = qup + ((size_t)j * nup + fi) * 3;
+      const double dqx = qx[0] - f[0][0], dqy = qx[1] - f[0][1], dqz = qx[2] - f[0][2];
       const double c = wgt * fma(rx, dqx, fma(ry, dqy, rz * dqz));
       a[0][0] = fma(c, rx, a[0][0]);
       a[0][1] = fma(c, ry, a[0][1]);
@@ -514,8 +518,8 @@ __device__ __forceinline__ void near_body(int pair, int chunk, const double* __r
       mzz = fma(wz, rz, mzz);
 #pragma unroll
       for (int r = 0; r < K; ++r) {
-        const double* qx = qup.p[r] + (size_t)j * nup + fi;
-        const double d = fma(wx, qx[0], fma(wy, qx[MU], wz * qx[2 * MU]));
+        const double* qx = qup + ((size_t)j * nup + fi) * C + 3 * r;
+        const double d = fma(wx, qx[0], fma(wy, qx[1], wz * qx[2]));
         a[r][0] = fma(d, rx, a[r][0]);
         a[r][1] = fma(d, ry, a[r][1]);
         a[r][2] = fma(d, rz, a[r][2]);
@@ -566,7 +570,8 @@ template <int K>
 __global__ __launch_bounds__(64 * kNearWaves) void k_near64(const double* __restrict__ ctr,
                                                             const double* __restrict__ off,
                                                             const double4* __restrict__ offup,
-                                                            const double* __restrict__ shab, QPtrs qup, QPtrs coef,
+                                                            const double* __restrict__ shab,
+                                                            const double* __restrict__ qup, QPtrs coef,
                                                             const int* __restrict__ npairs, int n, int M, int N,
                                                             int nup, int p, int L, double scale, OPtrs near_part,
                                                             int nch, int total, int per) {
@@ -888,12 +893,11 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near64_multi(const NearDesc
   const int b = blockIdx.x;
   const NearDesc D = d[find_seg(d, nd, b)];
   const int local = b - D.start;
-  QPtrs qu{}, cf{};
+  QPtrs cf{};
   OPtrs np{};
-  qu.p[0] = D.qup;
   cf.p[0] = D.coef;
   np.p[0] = D.part;
-  near_body<1>(local / D.nch, local % D.nch, D.ctr, D.off, D.offup, D.shab, qu, cf, D.pairs, D.n, D.M, D.N, D.nup,
+  near_body<1>(local / D.nch, local % D.nch, D.ctr, D.off, D.offup, D.shab, D.qup, cf, D.pairs, D.n, D.M, D.N, D.nup,
                D.p, D.L, D.scale, np, lds);
 }
 
@@ -1030,7 +1034,7 @@ void launch_far_multi(hipStream_t s, int prec, int tpt, const FarDesc* desc, int
 }
 
 void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, const double* off, const double4* offup,
-                 const double* shab, const QPtrs& qup, const QPtrs& coef, const int* npairs, int n, int M, int N,
+                 const double* shab, const double* qup, const QPtrs& coef, const int* npairs, int n, int M, int N,
                  int nup, int p, int L, double scale, const OPtrs& near_part) {
   if (npairs_count <= 0) return;
   const int nch = (n + 63) / 64, total = npairs_count * nch, per = (total + kXcds - 1) / kXcds;

@@ -107,7 +107,7 @@ void launch_far(hipStream_t s, int prec, int K, int tpt, const void* src, const 
                 const unsigned char* cls, int n, int M, int N, int spc, int nchunks, double scale, const OPtrs& part);
 void launch_far_multi(hipStream_t s, int prec, int tpt, const FarDesc* desc, int ndesc, int nitems);
 void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, const double* off, const double4* offup,
-                 const double* shab, const QPtrs& qup, const QPtrs& coef, const int* npairs, int n, int M, int N,
+                 const double* shab, const double* qup, const QPtrs& coef, const int* npairs, int n, int M, int N,
                  int nup, int p, int L, double scale, const OPtrs& near_part);
 // C(r, col) = sum_k A[r * lda + k] B[col * ldb + k], stored at C[(r / rb) * rbs + col * ldc + r % rb];
 // grid z = batch with strides Az, Bz, Cz.
