@@ -102,7 +102,7 @@ __device__ __forceinline__ void far32_tile(int j, int k0, int k1, const float* _
     for (int r = 0; r < K; ++r) sm[u][r][0] = sm[u][r][1] = sm[u][r][2] = 0.0f;
   }
   const float* sp = src + (size_t)j * n * S;
-#pragma unroll 4
+#pragma unroll 8
   for (int kk = k0; kk < k1; ++kk) {
     const float* e = sp + (size_t)kk * S;
     const float sx = e[0], sy = e[1], sz = e[2];

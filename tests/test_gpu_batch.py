@@ -120,3 +120,22 @@ def test_batch_context_rejects_single_calls():
     with binding.BatchContext(inst) as bc:
         with pytest.raises(binding.PqnError):
             binding._check(binding.lib().pqn_nc_velocity(bc.h, binding._dptr(np.zeros((8, 6))), 0, None))
+
+
+@pytest.mark.parametrize("prec,refine", [("fp64", 0), ("mixed", 0), ("mixed", 2)])
+def test_multi_rhs_with_gaps_in_the_active_set(prec, refine):
+    """Systems that drop out of the lockstep (a zero force set converges at once, a
+    small one earlier than the rest) leave non-adjacent work slots active; each pass
+    must still see its own density (also in the FP64 refinement sweeps)."""
+    w = inputs.workload('tiny', 2)
+    c = w['centers']
+    FT = inputs.random_forces(24, c.shape[0], k=4)
+    FT[1] = 0.0
+    FT[2] *= 1e-6
+    say('multi gaps', prec, refine)
+    with binding.Context(c, None, 8, 16, gmres_tol=1e-10, precision=prec, refine=refine) as ctx:
+        U, st = ctx.mobility_apply_multi(FT)
+        singles = [ctx.mobility_apply(FT[r])[0] for r in range(4)]
+    assert np.all(U[1] == 0.0)
+    for r in (0, 2, 3):
+        assert rel(U[r], singles[r]) < (1e-11 if prec == 'fp64' else 1e-7), r
