@@ -38,9 +38,9 @@ PROBE_BYTES = 256 << 20       # reference copy for the HBM byte counters
 # the counters read for a 256 MiB copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0). Valid
 # only for the far-kernel source and the launch layout it was measured on:
 # reported as null once either changes.
-FAR_TRAFFIC = {'kernel': 'k_far32<1,6>', 'source_sha1': 'a6cf3432f661024da20a19a0db64a4d3d8dff1f6',
-               'layout': {'tpt': 1, 'chunks': 48, 'split': 0},
-               'fetch_kib': 47115.8, 'write_kib': 384912.0, 'fetch_scale': 2.0, 'write_scale': 1.0}
+FAR_TRAFFIC = {'kernel': 'k_far32<1,6>', 'source_sha1': '89457432d84d81546527ae43239637e47ad97406',
+               'layout': {'tpt': 1, 'chunks': 24, 'split': 0},
+               'fetch_kib': 6455.1, 'write_kib': 209952.0, 'fetch_scale': 2.0, 'write_scale': 1.0}
 
 
 def far_source_sha1():
@@ -268,9 +268,18 @@ def main():
             t0 = time.perf_counter()
             reps = 3
             for _ in range(reps):
-                _, bst = bc.mobility_apply(FTb)
+                Ubm, bst = bc.mobility_apply(FTb)
             torch.cuda.synchronize()
             tb = (time.perf_counter() - t0) / reps
+        with binding.BatchContext(inst, **dict(kw, precision='fp64')) as bc:
+            bc.mobility_apply(FTb)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                Ub64, _ = bc.mobility_apply(FTb)
+            torch.cuda.synchronize()
+            tb64 = (time.perf_counter() - t0) / reps
+        err_b = float(max(np.abs(a - b_).max() / np.abs(b_).max() for a, b_ in zip(Ubm, Ub64)))
         singles = [binding.Context(ci, None, nti, npi, **kw) for ci, nti, npi in inst]
         for ctx_b, F in zip(singles, FTb):
             ctx_b.mobility_apply(F)
@@ -284,6 +293,7 @@ def main():
             ctx_b.close()
         batch_info = dict(instances=len(inst), nodes=int(sum(ci.shape[0] * nti * npi for ci, nti, npi in inst)),
                           batched_sec=round(tb, 4), mvps_batched=round(len(inst) / tb, 2),
+                          mvps_batched_fp64=round(len(inst) / tb64, 2), mixed_rel_err_vs_fp64=err_b,
                           one_by_one_sec=round(ts, 4), mvps_one_by_one=round(len(inst) / ts, 2),
                           speedup=round(ts / tb, 3), lockstep_iterations=bst['n_far'])
         log('batch', batch_info)

@@ -584,70 +584,95 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near64(const double* __rest
 
 // ------------------------------------------------------------------ GEMM
 //
-// C(r, col) = sum_k A[r * lda + k] * B(k, col), FP64, 64x64 tiles, BK = 16.
-// B(k, col) = B[z * Bz + (k / kb) * kbs + col * ldb + k % kb] and
-// C(r, col) is stored at C[z * Cz + (r / rb) * rbs + col * ldc + r % rb]: one
-// kernel covers the per-sphere block products on the SoA field layout.
+// C(r, col) = sum_k A[r * lda + k] * B(k, col), FP64, 32x32 output tiles,
+// B(k, col) = B[col * ldb + k] (k contiguous) and C(r, col) stored at
+// C[(r / rb) * rbs + col * ldc + r % rb]: one kernel covers the per-sphere
+// block products on the SoA field layout (and the interleaved layouts).
 
 constexpr int GBM = 32, GBN = 32, GBK = 16;
+constexpr int kGemmSplitBelow = 2048;  // tiles per launch below which k is split over 4 waves
 
-// One wave per 32x32 output tile, 4x4 outputs per lane (rows ty+8e, cols tx+8f).
-// A is row-major (lda); B(k, col) = B[col * ldb + k] (k contiguous); C(r, col)
-// is stored at C[(r / rb) * rbs + col * ldc + r % rb]. Tile loads run along k,
-// so consecutive lanes read consecutive addresses of A rows and B columns.
+// One workgroup of GW waves per 32x32 output tile: wave w accumulates the
+// k-blocks w, w + GW, ... (4x4 outputs per lane, rows ty+8e, cols tx+8f) and
+// the partial tiles are added in wave order through LDS. GW = 4 gives launches
+// with few tiles (short and wide products, K up to 288) enough waves; GW = 1
+// is used when the tiles alone fill the chip. Tile loads run along k, so
+// consecutive lanes read consecutive addresses.
+template <int GW>
 __device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, const double* __restrict__ A,
                                           int lda, const double* __restrict__ B, int ldb, double* __restrict__ C,
                                           int rb, long rbs, int ldc) {
-  __shared__ double As[GBK][GBM + 1];
-  __shared__ double Bs[GBK][GBN + 1];
-  const int tid = threadIdx.x;
-  const int tx = tid % 8, ty = tid / 8;
+  constexpr int GWAVES = GW;
+  // per wave: A and B slices [GBK][33]; reused for the partial tiles [32][33]
+  __shared__ double sh[GWAVES][2 * GBK * (GBM + 1)];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double* As = sh[wv];
+  double* Bs = sh[wv] + GBK * (GBM + 1);
+  const int tx = lane % 8, ty = lane / 8;
   const int r0 = bx * GBM, c0 = by * GBN;
   double acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += GBK) {
+  const int nkb = (K + GBK - 1) / GBK;
+  const int steps = (nkb + GWAVES - 1) / GWAVES;  // same count for every wave (barriers)
+  for (int st = 0; st < steps; ++st) {
+    const int k0 = (st * GWAVES + wv) * GBK;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int idx = tid + e * 64;          // 0..511: k fastest
+      const int idx = lane + e * 64;          // 0..511: k fastest
       const int kk = idx % GBK, rc = idx / GBK;
       const int gk = k0 + kk;
       const int gr = r0 + rc, gc = c0 + rc;
-      As[kk][rc] = (gr < R && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
-      Bs[kk][rc] = (gc < Cn && gk < K) ? B[(size_t)gc * ldb + gk] : 0.0;
+      As[kk * (GBM + 1) + rc] = (gr < R && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
+      Bs[kk * (GBN + 1) + rc] = (gc < Cn && gk < K) ? B[(size_t)gc * ldb + gk] : 0.0;
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < GBK; ++kk) {
-      double a[4], b[4];
+      double av[4], bv[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        a[e] = As[kk][ty + 8 * e];
-        b[e] = Bs[kk][tx + 8 * e];
+        av[e] = As[kk * (GBM + 1) + ty + 8 * e];
+        bv[e] = Bs[kk * (GBN + 1) + tx + 8 * e];
       }
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int f = 0; f < 4; ++f) acc[e][f] = fma(a[e], b[f], acc[e][f]);
+        for (int f = 0; f < 4; ++f) acc[e][f] = fma(av[e], bv[f], acc[e][f]);
     }
     __syncthreads();
   }
+  // partial tiles of waves 1.. into LDS, wave 0 adds them in order and stores
+  double* part = &sh[0][0];  // (GWAVES - 1) x [32][33] doubles fit in sh
+  if (GWAVES > 1 && wv > 0)
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int gr = r0 + ty + 8 * e;
-    if (gr >= R) continue;
-    const size_t rowbase = (size_t)(gr / rb) * rbs + gr % rb;
+    for (int e = 0; e < 4; ++e)
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const int gc = c0 + tx + 8 * f;
-      if (gc < Cn) C[rowbase + (size_t)gc * ldc] = acc[e][f];
+      for (int f = 0; f < 4; ++f) part[((wv - 1) * GBM + ty + 8 * e) * (GBN + 1) + tx + 8 * f] = acc[e][f];
+  if (GWAVES > 1) __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int gr = r0 + ty + 8 * e;
+      if (gr >= R) continue;
+      const size_t rowbase = (size_t)(gr / rb) * rbs + gr % rb;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const int gc = c0 + tx + 8 * f;
+        double v = acc[e][f];
+#pragma unroll
+        for (int w = 1; w < GWAVES; ++w) v += part[((w - 1) * GBM + ty + 8 * e) * (GBN + 1) + tx + 8 * f];
+        if (gc < Cn) C[rowbase + (size_t)gc * ldc] = v;
+      }
     }
   }
 }
 
-__global__ __launch_bounds__(64) void k_gemm64(int R, int Cn, int K, const double* __restrict__ A, int lda, long Az,
-                                               const double* __restrict__ B, long Bz, int ldb,
-                                               double* __restrict__ C, long Cz, int rb, long rbs, int ldc) {
-  gemm_tile(blockIdx.x, blockIdx.y, R, Cn, K, A + (size_t)blockIdx.z * Az, lda, B + (size_t)blockIdx.z * Bz, ldb,
-            C + (size_t)blockIdx.z * Cz, rb, rbs, ldc);
+template <int GW>
+__global__ __launch_bounds__(64 * GW) void k_gemm64(int R, int Cn, int K, const double* __restrict__ A, int lda,
+                                                    long Az, const double* __restrict__ B, long Bz, int ldb,
+                                                    double* __restrict__ C, long Cz, int rb, long rbs, int ldc) {
+  gemm_tile<GW>(blockIdx.x, blockIdx.y, R, Cn, K, A + (size_t)blockIdx.z * Az, lda, B + (size_t)blockIdx.z * Bz, ldb,
+                C + (size_t)blockIdx.z * Cz, rb, rbs, ldc);
 }
 
 // ------------------------------------------------- completion and slip RHS
@@ -858,11 +883,12 @@ __device__ __forceinline__ int find_seg(const D* __restrict__ d, int nd, int idx
   return lo;
 }
 
-__global__ __launch_bounds__(64) void k_gemm64_multi(const GemmDesc* __restrict__ d, int nd) {
+template <int GW>
+__global__ __launch_bounds__(64 * GW) void k_gemm64_multi(const GemmDesc* __restrict__ d, int nd) {
   const int b = blockIdx.x;
   const GemmDesc D = d[find_seg(d, nd, b)];
   const int local = b - D.start;
-  gemm_tile(local % D.tr, local / D.tr, D.R, D.Cn, D.K, D.A, D.lda, D.B, D.ldb, D.C, D.rb, D.rbs, D.ldc);
+  gemm_tile<GW>(local % D.tr, local / D.tr, D.R, D.Cn, D.K, D.A, D.lda, D.B, D.ldb, D.C, D.rb, D.rbs, D.ldc);
 }
 
 __global__ __launch_bounds__(256) void k_pack_multi(const PackDesc* __restrict__ d, int nd, int fp32) {
@@ -1055,8 +1081,11 @@ void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, cons
 
 void launch_gemm64(hipStream_t s, int R, int Cn, int K, const double* A, int lda, long Az, const double* B, long Bz,
                    int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch) {
-  hipLaunchKernelGGL(k_gemm64, dim3((R + GBM - 1) / GBM, (Cn + GBN - 1) / GBN, batch), dim3(64), 0, s, R, Cn, K, A,
-                     lda, Az, B, Bz, ldb, C, Cz, rb, rbs, ldc);
+  const dim3 g((R + GBM - 1) / GBM, (Cn + GBN - 1) / GBN, batch);
+  if ((long)g.x * g.y * g.z < kGemmSplitBelow)
+    hipLaunchKernelGGL(k_gemm64<4>, g, dim3(256), 0, s, R, Cn, K, A, lda, Az, B, Bz, ldb, C, Cz, rb, rbs, ldc);
+  else
+    hipLaunchKernelGGL(k_gemm64<1>, g, dim3(64), 0, s, R, Cn, K, A, lda, Az, B, Bz, ldb, C, Cz, rb, rbs, ldc);
 }
 void launch_rhs(hipStream_t s, const double* ctr, const double* FT, const double* axes, const double* off, int n,
                 int M, int N, double a, double mu, double slip, double* rhs) {
@@ -1096,7 +1125,11 @@ void launch_axpby(hipStream_t s, double* y, const double* x, double a, double b,
 namespace bipqn {
 static inline unsigned nblk2(long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 void launch_gemm64_multi(hipStream_t s, const GemmDesc* d, int nd, int nblocks) {
-  if (nblocks > 0) hipLaunchKernelGGL(k_gemm64_multi, dim3(nblocks), dim3(64), 0, s, d, nd);
+  if (nblocks <= 0) return;
+  if (nblocks < kGemmSplitBelow)
+    hipLaunchKernelGGL(k_gemm64_multi<4>, dim3(nblocks), dim3(256), 0, s, d, nd);
+  else
+    hipLaunchKernelGGL(k_gemm64_multi<1>, dim3(nblocks), dim3(64), 0, s, d, nd);
 }
 void launch_pack_multi(hipStream_t s, const PackDesc* d, int nd, int total, int fp32) {
   if (total > 0) hipLaunchKernelGGL(k_pack_multi, dim3(nblk2(total)), dim3(256), 0, s, d, nd, fp32);

@@ -166,3 +166,40 @@ def test_set_state_without_axes_keeps_janus_axes(tiny):
         U, _ = ctx.nc_velocity()
         Ur, _ = ref.nc_velocity()
     assert rel(U, Ur) < 1e-12
+
+
+def test_precision_sweep_packing64():
+    """64 spheres compressed to volume fraction 0.35 (16x32 grid): the mixed path against
+    the FP64 path, per velocity block, for random forces and for contact forces D x, and
+    for the solution of a planted LCP on the packing's contact set."""
+    from oracle import lcp
+    w = inputs.workload('packing64', 0)
+    c = w['centers']
+    M = c.shape[0]
+    kw = dict(gmres_tol=1e-10)
+    with binding.Context(c, None, 16, 32, precision='fp64', **kw) as c64, \
+            binding.Context(c, None, 16, 32, precision='mixed', **kw) as cmx:
+        pairs, _ = c64.find_contacts(0.1)
+        say('packing64 contacts', pairs.shape[0])
+        assert pairs.shape[0] >= 10
+        x = np.abs(np.random.default_rng(30).standard_normal(pairs.shape[0]))
+        for name, FT in (('random', inputs.random_forces(31, M)), ('contact', lcp.D_apply(c, pairs, x))):
+            U64, _ = c64.mobility_apply(FT)
+            Umx, _ = cmx.mobility_apply(FT)
+            for blk in (slice(0, 3), slice(3, 6)):
+                e = rel(Umx[:, blk], U64[:, blk])
+                say('  ', name, blk, e)
+                assert e < 1e-6
+        xs, ws = inputs.planted_lcp(3, pairs.shape[0])
+        b = ws - c64.lcp_apply(pairs, xs)
+        x64, s64 = c64.lcp_solve(pairs, b, 'mono', tol_abs=1e-11, tol_rel=1e-14)
+        xmx, smx = cmx.lcp_solve(pairs, b, 'mono', tol_abs=1e-9, tol_rel=1e-9)
+        w64 = c64.lcp_apply(pairs, x64) + b
+    say('  lcp', s64['mvp_hi'], smx['mvp_hi'], np.abs(xmx - x64).max() / np.abs(x64).max())
+    # At gaps down to 0.01 the discrete A of this packing need not be a P-matrix, so the
+    # planted x* need not be the only solution: check that x64 is one (complementarity),
+    # and that the mixed path finds the same one.
+    sw = max(1.0, np.abs(b).max())
+    assert x64.min() >= 0.0 and w64.min() >= -1e-9 * sw
+    assert np.abs(x64 * w64).max() <= 1e-9 * max(1.0, np.abs(x64).max()) * sw
+    assert np.abs(xmx - x64).max() < 1e-6 * np.abs(x64).max()
