@@ -96,6 +96,9 @@ def main():
     ap.add_argument('--counters-probe', action='store_true',
                     help='short run for rocprofv3 --pmc: a 256 MiB device copy (scale reference for FETCH_SIZE/'
                          'WRITE_SIZE) and one six-force-set product on the 216-sphere workload')
+    ap.add_argument('--lcp-table', action='store_true',
+                    help='instead of the benchmark line: BB-PGD, Mono-PQN and Bi-PQN on planted LCPs of the 27-, '
+                         '64- and 216-sphere workloads (three seeds each), one JSON line')
     args = ap.parse_args()
     if args.gpus != 1:
         print(f'bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on one MI355X; '
@@ -129,6 +132,10 @@ def main():
     # the timed products read forces from and write velocities to HBM (no host copies)
     FT6_dev = [torch.as_tensor(np.ascontiguousarray(f), dtype=torch.float64, device=dev) for f in FT6]
     UO_dev = torch.empty((K_RHS, M, 6), dtype=torch.float64, device=dev)
+
+    if args.lcp_table:
+        print(json.dumps(lcp_table(binding, inputs, stream)), flush=True)
+        return
 
     if args.counters_probe:
         ref = torch.empty(PROBE_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -334,6 +341,52 @@ def main():
     if not args.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline(c, nt, nph, res['mixed1'])
     print(json.dumps(out), flush=True)
+
+
+def lcp_table(binding, inputs, stream):
+    """Products per planted LCP (about half the contacts active, KKT 1e-8) for the solvers of
+    the method on the contact sets (gap < 0.1) of three workloads, mixed precision: BB-PGD,
+    Mono-PQN, Bi-PQN with the coarse grid as low fidelity, and Bi-PQN with the same grid at
+    GMRES tolerance 1e-3 as low fidelity. E-MVP = high + low x (low-fidelity product time /
+    high-fidelity product time), both measured."""
+    import torch
+    rows = []
+    for name in ('lattice27_contacts', 'packing64', 'rsa216'):
+        for seed in (0, 1, 2):
+            w = inputs.workload(name, seed)
+            c, nt, nph = w['centers'], w['n_theta'], w['n_phi']
+            row = dict(workload=name, seed=seed)
+            with binding.Context(c, None, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='mixed',
+                                 stream=stream.cuda_stream, tune_K=1) as ctx:
+                pairs, _ = ctx.find_contacts(0.1)
+                if pairs.shape[0] == 0:
+                    continue
+                xs, ws = inputs.planted_lcp(seed, pairs.shape[0])
+                b = ws - ctx.lcp_apply(pairs, xs)
+                row['contacts'] = int(pairs.shape[0])
+                for solver in ('bb', 'mono', 'bi'):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    x, st = ctx.lcp_solve(pairs, b, solver)
+                    row[solver] = dict(hi=st['mvp_hi'], lo=st['mvp_lo'], emvp=round(st['emvp'], 2),
+                                       sec=round(time.perf_counter() - t0, 3), conv=st['converged'],
+                                       x_err=float(np.abs(x - xs).max() / np.abs(xs).max()))
+            with binding.Context(c, None, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3,
+                                 precision='mixed', stream=stream.cuda_stream, tune_K=1) as ctx:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, st = ctx.lcp_solve(pairs, b, 'bi')
+                row['bi_tol'] = dict(hi=st['mvp_hi'], lo=st['mvp_lo'], emvp=round(st['emvp'], 2),
+                                     ratio=round(st['lo_hi_cost_ratio'], 3), sec=round(time.perf_counter() - t0, 3),
+                                     conv=st['converged'], x_err=float(np.abs(x - xs).max() / np.abs(xs).max()))
+            print('[lcp-table]', row, file=sys.stderr, flush=True)
+            rows.append(row)
+    med = {}
+    for name in ('lattice27_contacts', 'packing64', 'rsa216'):
+        rs = [r for r in rows if r['workload'] == name]
+        if rs:
+            med[name] = {k: float(np.median([r[k]['emvp'] for r in rs])) for k in ('bb', 'mono', 'bi', 'bi_tol')}
+    return dict(table='planted LCPs, mixed precision, KKT 1e-8', rows=rows, median_emvp=med)
 
 
 def cpu_baseline(c, nt, nph, mixed):

@@ -203,3 +203,46 @@ def test_precision_sweep_packing64():
     assert x64.min() >= 0.0 and w64.min() >= -1e-9 * sw
     assert np.abs(x64 * w64).max() <= 1e-9 * max(1.0, np.abs(x64).max()) * sw
     assert np.abs(xmx - x64).max() < 1e-6 * np.abs(x64).max()
+
+
+@pytest.mark.parametrize("nt", [6, 12])
+def test_grid_and_self_block_of_device_context(nt):
+    """a1/a2: the context's grid and singular self block are the oracle's."""
+    say('grid/self block', nt)
+    with binding.Context([[0.0, 0.0, 0.0], [3.0, 0.0, 0.0]], None, nt, 2 * nt, radius=1.0) as ctx:
+        off, w = ctx.get_grid()
+        S = ctx.get_self_block()
+    o2, _, w2 = grid.sphere_grid(nt, 2 * nt, 1.0)
+    assert np.abs(off - o2).max() < 1e-14 and np.abs(w - w2).max() < 1e-14
+    So = bie.self_block(nt, 2 * nt, 1.0).reshape(3 * nt * 2 * nt, -1)
+    # both sides sum the rotated-pole rule's ~10^4 terms per entry in FP64, in different orders
+    assert np.abs(S - So).max() <= 5e-12 * np.abs(So).max()
+
+
+@pytest.mark.parametrize("nt", [5, 8, 12])
+def test_single_sphere_operator_matches_oracle(nt):
+    """The self block applied on the device through harmonic coefficients (T q, G coef),
+    plus 1/2 q and the rigid projection, for one sphere (odd and even grids)."""
+    say('single sphere operator', nt)
+    c = [[0.3, -0.2, 0.1]]
+    g = bie.Geometry(c, 1.0, nt, 2 * nt)
+    A = bie.dense_operator(g)
+    q = np.random.default_rng(nt).standard_normal((g.N, 3))
+    with binding.Context(c, None, nt, 2 * nt) as ctx:
+        y = ctx.bie_apply(soa(q))
+    ref = (A @ q.ravel()).reshape(-1, 3).T
+    assert rel(y, ref) < 1e-12
+
+
+def test_mobility_apply_dev_matches_host(tiny):
+    import torch
+    c, g, A = tiny
+    FT = inputs.random_forces(12, g.M)
+    with binding.Context(c, None, 8, 16, gmres_tol=1e-12) as ctx:
+        U, _ = ctx.mobility_apply(FT)
+        FTd = torch.as_tensor(FT, dtype=torch.float64, device='cuda:0').contiguous()
+        UOd = torch.full((g.M, 6), float('nan'), dtype=torch.float64, device='cuda:0')
+        st = ctx.mobility_apply_dev(FTd.data_ptr(), UOd.data_ptr())
+        Ud = UOd.cpu().numpy()
+    assert st['converged'] == 1
+    assert np.array_equal(U, Ud)
