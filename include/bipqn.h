@@ -112,6 +112,8 @@ typedef struct {
   int32_t ssn_steps;        /* semi-smooth Newton steps in total */
   double t_total_ms;
   int32_t gmres_iters;      /* Krylov iterations over all products */
+  int32_t model_rejected;   /* Bi-PQN: 1 if a low-fidelity solve met non-positive curvature or no
+                               descent and the solve finished as Mono-PQN on A */
 } pqn_lcp_stats;
 
 typedef struct {

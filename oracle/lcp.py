@@ -331,6 +331,7 @@ def mono_pqn(Aop, b, x0=None, Ax0=None, k_max=100, tol_abs=1e-8, tol_rel=1e-8,
     conv = False
     hist = []
     ssn_total = 0
+    resets = 0
     for k in range(k_max):
         g = Ax + b
         e = kkt_error(x, g)
@@ -356,6 +357,7 @@ def mono_pqn(Aop, b, x0=None, Ax0=None, k_max=100, tol_abs=1e-8, tol_rel=1e-8,
             qn.sigma = sigma
         eta, reset = step_size(g, x, p, Ap)
         if reset:
+            resets += 1
             qn = QuasiNewton(n, sigma=sigma)
         x = np.maximum(x + eta * p, 0.0)
         Ax = Ax + eta * Ap
@@ -365,7 +367,7 @@ def mono_pqn(Aop, b, x0=None, Ax0=None, k_max=100, tol_abs=1e-8, tol_rel=1e-8,
         hist.append(e)
         conv = _converged(e, e_prev, tol_abs, tol_rel)
     return x, Ax, Stats(iters=len(hist) - 1, mvp=mvp, kkt=hist[-1], converged=conv,
-                        hist=hist, S=list(qn.S), Y=list(qn.Y), ssn=ssn_total, sigma=sigma)
+                        hist=hist, S=list(qn.S), Y=list(qn.Y), ssn=ssn_total, sigma=sigma, resets=resets)
 
 
 def secant_transfer(S, Y, u, v):
@@ -388,6 +390,12 @@ def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_
     eta* by Alg. 2 on the high-fidelity A; BFGS correction of B^(k) with
     B^(k) s = A^ s + (U U^T - V V^T) s, where A^ s = eta (A^ x^ - A^ x)
     (App. E.2) costs no product.
+
+    Model safeguard (not in the paper, which takes B^(k) positive definite):
+    when a low-fidelity solve meets a step with non-positive curvature or no
+    descent (the Alg. 2 edge cases, on the model), the model is rejected and
+    the solve continues as Mono-PQN on A from the current iterate; the
+    products of both phases are counted.
     """
     n = b.size
     x = np.zeros(n)
@@ -395,6 +403,15 @@ def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_
     x, Alox, st0 = mono_pqn(Alo, b, x, np.zeros(n), k_max=k_max_inner,
                             tol_abs=tol0, tol_rel=tol_rel, j_max=j_max)
     mvp_lo = st0['mvp']
+
+    def fallback(x0, Ax0, mvp_hi, mvp_lo, k_done, hist):
+        xm, Axm, sm = mono_pqn(Ahi, b, x0, Ax0, k_max=max(1, k_max - k_done), tol_abs=tol_abs,
+                               tol_rel=tol_rel, j_max=j_max)
+        return xm, Axm, Stats(iters=len(hist) + sm['iters'], mvp_hi=mvp_hi + sm['mvp'], mvp_lo=mvp_lo,
+                              kkt=sm['kkt'], converged=sm['converged'], hist=hist + sm['hist'], fallback=True)
+
+    if st0['resets'] > 0:
+        return fallback(np.zeros(n), np.zeros(n), 0, mvp_lo, 0, [])
     S, Y = st0['S'], st0['Y']
     sigma = st0['sigma']
     if np.any(x != 0.0):
@@ -423,6 +440,8 @@ def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_
                                tol_rel=tol_rel, pairs=list(zip(S, Y)), j_max=j_max, sigma=sigma)
         mvp_lo += st['mvp']
         sigma = st['sigma']
+        if st['resets'] > 0:
+            return fallback(x, Ax, mvp_hi, mvp_lo, k, hist)
         p = xh - x
         if not np.any(p != 0.0):
             conv = True
@@ -454,4 +473,4 @@ def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_
         hist.append(e)
         conv = _converged(e, e_prev, tol_abs, tol_rel)
     return x, Ax, Stats(iters=len(hist) - 1, mvp_hi=mvp_hi, mvp_lo=mvp_lo, kkt=hist[-1],
-                        converged=conv, hist=hist)
+                        converged=conv, hist=hist, fallback=False)

@@ -44,7 +44,8 @@ class LcpOpts(C.Structure):
 class LcpStats(C.Structure):
     _fields_ = [('iters', C.c_int32), ('mvp_hi', C.c_int32), ('mvp_lo', C.c_int32), ('emvp', C.c_double),
                 ('lo_hi_cost_ratio', C.c_double), ('kkt_abs', C.c_double), ('converged', C.c_int32),
-                ('ssn_steps', C.c_int32), ('t_total_ms', C.c_double), ('gmres_iters', C.c_int32)]
+                ('ssn_steps', C.c_int32), ('t_total_ms', C.c_double), ('gmres_iters', C.c_int32),
+                ('model_rejected', C.c_int32)]
 
 
 class StepStats(C.Structure):

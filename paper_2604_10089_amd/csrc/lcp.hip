@@ -16,6 +16,7 @@ constexpr int kT = 256;  // threads of the single-workgroup kernels (4 waves)
 // step then uses H0 = I and sets sigma = p.Ap/p.p from its own product).
 struct PqnScal {
   int r, conv, stationary, reset, ssn_steps, ssn_fail, have_prev, nonzero;
+  int resets;  // steps of this solve that met the Alg. 2 edge cases (non-positive curvature or no descent)
   double e, e_prev, eta, tol_abs, tol_rel, tau, sigma;
 };
 
@@ -501,6 +502,7 @@ __global__ __launch_bounds__(kT) void k_pqn_accept(PqnDev d) {
     d.sc->r = r;
     d.sc->eta = eta;
     d.sc->reset = reset;
+    d.sc->resets += reset;
   }
 }
 
@@ -975,6 +977,7 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
   };
   if (MDx) HIPCHK(hipMemsetAsync(MDx, 0, 6 * (size_t)M * sizeof(double), ctx.stream));
   bool conv = false;
+  bool rejected = false;
   int iters = 0;
   int ssn = 0;
   double kkt = 0.0;
@@ -1027,6 +1030,26 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
     PqnScal sI = read_scal(ctx, I.d.sc);
     ssn += sI.ssn_steps;
     double sigma_in = sI.sigma;   // metric scale carried into every subproblem
+    // Model safeguard: a low-fidelity solve that meets non-positive curvature or no
+    // descent (the Alg. 2 edge cases) shows that the model is not positive definite;
+    // the solve then continues as Mono-PQN on A from the current iterate.
+    auto finish_mono = [&](bool keep_x, int k_done) {
+      rejected = true;
+      hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, O.d, keep_x ? 1 : 0, o.kkt_tol_abs,
+                         o.kkt_tol_rel);
+      if (MDx && !keep_x) HIPCHK(hipMemsetAsync(MDx, 0, 6 * (size_t)M * sizeof(double), ctx.stream));
+      int it = 0;
+      conv = run_mono(ctx, O, std::max(1, o.k_max - k_done), o.j_max, mvp_hi, MDx, M, &it);
+      PqnScal sm = read_scal(ctx, O.d.sc);
+      ssn += sm.ssn_steps;
+      kkt = sm.e;
+      iters = k_done + it;
+    };
+    if (sI.resets > 0) {
+      finish_mono(false, 0);
+      goto done;
+    }
+    {
     // outer state: x = x0, A^ x = inner A x, pairs = inner memory, no corrections
     PqnScal so{};
     so.tol_abs = o.kkt_tol_abs;
@@ -1077,6 +1100,10 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
       PqnScal sI2 = read_scal(ctx, I.d.sc);
       ssn += sI2.ssn_steps;
       sigma_in = sI2.sigma;
+      if (sI2.resets > 0) {
+        finish_mono(true, k);
+        break;
+      }
       hipLaunchKernelGGL(k_bi_direction, dim3(1), dim3(kT), 0, ctx.stream, O.d, I.d);
       PqnScal sd = read_scal(ctx, O.d.sc);
       if (sd.stationary) {
@@ -1090,13 +1117,17 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
                            6 * M);
       HIPCHK(hipGetLastError());
     }
-    if (!conv) {
-      hipLaunchKernelGGL(k_bi_prepare, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
-      PqnScal sf = read_scal(ctx, O.d.sc);
-      conv = sf.conv;
-      kkt = sf.e;
+    if (!rejected) {
+      if (!conv) {
+        hipLaunchKernelGGL(k_bi_prepare, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
+        PqnScal sf = read_scal(ctx, O.d.sc);
+        conv = sf.conv;
+        kkt = sf.e;
+      }
+      iters = k;
     }
-    iters = k;
+    }
+  done:;
   }
   HIPCHK(hipStreamSynchronize(ctx.stream));
   if (stats) {
@@ -1110,6 +1141,7 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
     stats->converged = conv ? 1 : 0;
     stats->ssn_steps = ssn;
     stats->gmres_iters = cnt.gmres;
+    stats->model_rejected = rejected ? 1 : 0;
   }
   return conv;
 }

@@ -127,3 +127,26 @@ def test_bi_pqn_exact_model_counts_match_oracle(cases):
         assert abs(gb['mvp_hi'] - sb['mvp_hi']) <= 1
         assert gb['mvp_hi'] < gm['mvp_hi']
         assert np.abs(x - cs['x_pl']).max() < 1e-7 * np.abs(cs['x_pl']).max()
+
+
+def test_bi_pqn_safe_when_low_fidelity_model_is_poor():
+    """64-sphere packing with gaps down to 0.01 and the coarse 6x12 model: whatever the
+    model's quality, Bi-PQN must return a solution of the LCP (complementarity within
+    tolerance) that agrees with Mono-PQN's; a model that shows non-positive curvature is
+    rejected (model_rejected) and the solve finishes as Mono-PQN on A."""
+    w = inputs.workload('packing64', 1)
+    c = w['centers']
+    kw = dict(tol_abs=1e-10, tol_rel=1e-12, k_max=300)
+    with binding.Context(c, None, 16, 32, lo=(6, 12), gmres_tol=1e-11, gmres_tol_lo=1e-11) as ctx:
+        pairs, _ = ctx.find_contacts(0.1)
+        xs, ws = inputs.planted_lcp(1, pairs.shape[0])
+        b = ws - ctx.lcp_apply(pairs, xs)
+        xb, sb = ctx.lcp_solve(pairs, b, 'bi', **kw)
+        xm, sm = ctx.lcp_solve(pairs, b, 'mono', **kw)
+        wb = ctx.lcp_apply(pairs, xb) + b
+    say('bi on packing64', sb['mvp_hi'], sb['mvp_lo'], 'rejected', sb['model_rejected'], 'mono', sm['mvp_hi'])
+    assert sb['converged'] == 1 and np.all(np.isfinite(xb))
+    sw = max(1.0, np.abs(b).max())
+    assert xb.min() >= 0.0 and wb.min() >= -1e-8 * sw
+    assert np.abs(xb * wb).max() <= 1e-8 * max(1.0, np.abs(xb).max()) * sw
+    assert np.abs(xb - xm).max() <= 1e-6 * np.abs(xm).max()

@@ -196,3 +196,28 @@ def test_bi_pqn_with_exact_model_needs_few_high_fidelity_products(tiny_lcps):
         _, _, sm = lcp.mono_pqn(c['Aop'], c['b_pl'])
         assert np.abs(x - c['x_pl']).max() < 1e-7 * np.abs(c['x_pl']).max()
         assert sb['mvp_hi'] <= 4 and sb['mvp_hi'] < sm['mvp']
+
+
+def test_bi_pqn_rejects_an_indefinite_model():
+    """Model safeguard: with a low-fidelity matrix that has negative curvature, the
+    subproblems of Alg. 4 are unbounded; the solve must notice (Alg. 2 edge case on
+    the model), finish as Mono-PQN on A and still return the brute-force solution.
+    With a positive definite model the safeguard stays silent."""
+    rng = np.random.default_rng(7)
+    n = 8
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.exp(rng.uniform(np.log(1e-2), np.log(1e-1), n))
+    A = (Q * ev) @ Q.T
+    Alo_bad = (Q * (ev * np.r_[1.0, -1.0, np.ones(n - 2)])) @ Q.T  # a direction the iterates explore
+    Alo_good = (Q * (ev * np.exp(rng.uniform(-0.5, 0.5, n)))) @ Q.T
+    xs, ws = inputs.planted_lcp(5, n)
+    b = ws - A @ xs
+    xbf = lcp.brute_force_lcp(A, b)
+    assert np.abs(xbf - xs).max() < 1e-12
+    kw = dict(tol_abs=1e-12, tol_rel=1e-15)
+    x, _, st = lcp.bi_pqn(lambda v: A @ v, lambda v: Alo_bad @ v, b, **kw)
+    assert st['fallback'] and st['converged']
+    assert np.abs(x - xbf).max() < 1e-9 * np.abs(xbf).max()
+    x2, _, st2 = lcp.bi_pqn(lambda v: A @ v, lambda v: Alo_good @ v, b, **kw)
+    assert not st2['fallback'] and st2['converged']
+    assert np.abs(x2 - xbf).max() < 1e-9 * np.abs(xbf).max()
