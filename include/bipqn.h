@@ -79,6 +79,8 @@ typedef struct {
   int32_t profile;          /* 1 = time every far pair-sum launch with HIP events */
   int32_t use_graphs;       /* 1 = replay each GMRES iteration of a single linear system from a
                                captured hipGraph (one per Arnoldi index; ignored when profile = 1) */
+  int32_t warm_start;       /* 1 = the slip-driven solve (U_nc, also inside pqn_step) starts GMRES
+                               from the previous slip solve's density instead of 0 */
 } pqn_config_desc;
 
 typedef struct {

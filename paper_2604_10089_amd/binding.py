@@ -27,7 +27,8 @@ class ConfigDesc(C.Structure):
                 ('slip_speed', C.c_double), ('precision', C.c_int32), ('refine_sweeps', C.c_int32),
                 ('targets_per_thread', C.c_int32), ('far_chunks', C.c_int32), ('far_split', C.c_int32),
                 ('device', C.c_int32),
-                ('stream', C.c_void_p), ('profile', C.c_int32), ('use_graphs', C.c_int32)]
+                ('stream', C.c_void_p), ('profile', C.c_int32), ('use_graphs', C.c_int32),
+                ('warm_start', C.c_int32)]
 
 
 class MvpStats(C.Structure):
@@ -154,7 +155,7 @@ def pqn_host_self_block(n_theta, n_phi, radius=1.0):
 
 def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_tol_lo=None, restart=50,
           max_iter=500, near_gap=0.0, near_up=2, slip=1.0, precision='fp64', refine=0, tpt=2, far_chunks=0,
-          far_split=0, device=0, stream=None, profile=False, graphs=False):
+          far_split=0, device=0, stream=None, profile=False, graphs=False, warm_start=False):
     d = ConfigDesc()
     d.n_particles = M
     d.radius, d.mu = radius, mu
@@ -174,6 +175,7 @@ def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_
     d.stream = stream
     d.profile = 1 if profile else 0
     d.use_graphs = 1 if graphs else 0
+    d.warm_start = 1 if warm_start else 0
     return d
 
 
@@ -241,7 +243,7 @@ class Context:
     def __init__(self, centers, axes=None, n_theta=8, n_phi=16, lo=None, radius=1.0, mu=1.0,
                  gmres_tol=1e-8, gmres_tol_lo=None, restart=50, max_iter=500, near_gap=0.0, near_up=2,
                  slip=1.0, precision='fp64', refine=0, tpt=None, far_chunks=None, far_split=None, device=0,
-                 stream=None, profile=False, tune_K=1, graphs=False):
+                 stream=None, profile=False, tune_K=1, graphs=False, warm_start=False):
         c = _f64(centers).reshape(-1, 3)
         self.M = c.shape[0]
         if tpt is None or far_chunks is None or far_split is None:
@@ -269,6 +271,7 @@ class Context:
         d.stream = stream
         d.profile = 1 if profile else 0
         d.use_graphs = 1 if graphs else 0
+        d.warm_start = 1 if warm_start else 0
         self.n_theta, self.n_phi, self.lo = n_theta, n_phi, lo
         ax = None if axes is None else _f64(axes).reshape(-1, 3)
         h = C.c_void_p()

@@ -583,14 +583,21 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
     g.active = true;
     g.restart = false;
   };
+  std::vector<int> warm;
   for (int i = 0; i < ns; ++i) {
     const double bn = std::sqrt(std::max(0.0, hhost[(size_t)i * hs + 2 * (m + 1)]));
     if (!std::isfinite(bn)) throw Error(PQN_ERR_NUMERIC, "non-finite right-hand side");
     st[i].bnorm = bn;
-    launch_scale_copy(s, sys[i].x, sys[i].rhs, 0.0, len_of(i));  // x = 0 (rhs finite)
     sys[i].its = 0;
     sys[i].relres = 0.0;
     sys[i].conv = true;
+    if (bn > 0.0 && sys[i].x0) {
+      launch_scale_copy(s, sys[i].x, sys[i].x0, 1.0, len_of(i));  // x = x0, residual below
+      sys[i].conv = false;
+      warm.push_back(i);
+      continue;
+    }
+    launch_scale_copy(s, sys[i].x, sys[i].rhs, 0.0, len_of(i));  // x = 0 (rhs finite)
     if (bn > 0.0) {
       sys[i].conv = false;
       start_cycle(i, sys[i].rhs, bn);
@@ -606,6 +613,28 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
     }
     return groups;
   };
+  if (!warm.empty()) {
+    // initial residual r0 = rhs - A x0 of the warm-started systems
+    std::vector<MvGroup> wg = build_groups(warm, true);
+    matvec_groups(wg, precision);
+    for (int i : warm) {
+      SysBuf& b = sys[i].lv->sb(sys[i].slot);
+      launch_axpby(s, b.r.p, sys[i].rhs, 1.0, -1.0, len_of(i));
+      launch_dots(s, b.r.p, len_of(i), 1, b.r.p, len_of(i), sys[i].lv->nb_dots, b.partial.p, nrm_slot(i));
+    }
+    readback();
+    for (int i : warm) {
+      SysBuf& b = sys[i].lv->sb(sys[i].slot);
+      const double beta = std::sqrt(std::max(0.0, hhost[(size_t)i * hs + 2 * (m + 1)]));
+      if (!std::isfinite(beta)) throw Error(PQN_ERR_NUMERIC, "non-finite initial residual");
+      sys[i].relres = beta / st[i].bnorm;
+      if (beta <= sys[i].tol * st[i].bnorm) {
+        sys[i].conv = true;
+      } else {
+        start_cycle(i, b.r.p, beta);
+      }
+    }
+  }
   for (;;) {
     std::vector<int> act;
     for (int i = 0; i < ns; ++i)
@@ -827,7 +856,16 @@ void pqn_ctx_impl::mobility_multi(Level& lv, int K, const double* const* FT_dev,
                cfg.slip_speed, b.rhs.p);
     sys.push_back(SysRef{this, &lv, r, b.rhs.p, b.x.p, lv.tol});
   }
+  // slip-driven solve: the previous one's density is a close initial guess after a small step
+  const bool slip_only = K == 1 && !FT_dev && axes_dev;
+  if (slip_only && cfg.warm_start && lv.has_q_nc) sys[0].x0 = lv.q_nc.p;
   solve_lockstep(sys, st);
+  if (slip_only && cfg.warm_start) {
+    lv.q_nc.alloc(3 * (size_t)lv.N);
+    HIPCHK(hipMemcpyAsync(lv.q_nc.p, lv.sb(0).x.p, 3 * (size_t)lv.N * sizeof(double), hipMemcpyDeviceToDevice,
+                          stream));
+    lv.has_q_nc = true;
+  }
   for (int r = 0; r < K; ++r) {
     Work& w = lv.wk(r);
     launch_moments(stream, lv.sb(r).x.p, lv.off.p, lv.w.p, lv.n, M, lv.N, w.mom.p);

@@ -110,6 +110,8 @@ struct Level {
   std::vector<std::unique_ptr<Work>> work;
   std::vector<std::unique_ptr<SysBuf>> sys;
   std::vector<std::unique_ptr<GraphCache>> graphs;
+  DevArray<double> q_nc;  // density of the last slip-driven solve (warm start of the next one)
+  bool has_q_nc = false;
   Work& wk(int k);
   SysBuf& sb(int k);
 };
@@ -147,6 +149,7 @@ struct SysRef {
   int its = 0;
   double relres = 0.0;
   bool conv = false;
+  const double* x0 = nullptr;  // initial guess (device, [3][N]); nullptr = start from 0
 };
 
 struct pqn_ctx_impl {

@@ -150,3 +150,23 @@ def test_bi_pqn_safe_when_low_fidelity_model_is_poor():
     assert xb.min() >= 0.0 and wb.min() >= -1e-8 * sw
     assert np.abs(xb * wb).max() <= 1e-8 * max(1.0, np.abs(xb).max()) * sw
     assert np.abs(xb - xm).max() <= 1e-6 * np.abs(xm).max()
+
+
+def test_warm_started_slip_solves_match_cold_steps():
+    """Time steps whose slip-driven solve starts from the previous step's density reach
+    the same trajectory (to the GMRES tolerance) in fewer Krylov iterations."""
+    w = inputs.workload('lattice27', 0)
+    c = w['centers']
+    axes = inputs.janus_axes(3, c.shape[0])
+    kw = dict(gmres_tol=1e-10, precision='fp64')
+    its = {}
+    pos = {}
+    for warm in (False, True):
+        with binding.Context(c, axes, 8, 16, lo=(4, 8), warm_start=warm, **kw) as ctx:
+            its[warm] = [ctx.step(1e-3, 0.1, 'mono')['gmres_iters_nc'] for _ in range(3)]
+            pos[warm] = ctx.get_state()[0]
+    say('nc iterations cold', its[False], 'warm', its[True])
+    disp = np.abs(pos[False] - c).max()
+    assert np.abs(pos[True] - pos[False]).max() < 1e-7 * disp
+    assert its[True][0] == its[False][0]
+    assert sum(its[True][1:]) < sum(its[False][1:])
