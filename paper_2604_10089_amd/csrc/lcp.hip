@@ -1045,89 +1045,85 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
       kkt = sm.e;
       iters = k_done + it;
     };
-    if (sI.resets > 0) {
-      finish_mono(false, 0);
-      goto done;
-    }
-    {
-    // outer state: x = x0, A^ x = inner A x, pairs = inner memory, no corrections
-    PqnScal so{};
-    so.tol_abs = o.kkt_tol_abs;
-    so.tol_rel = o.kkt_tol_rel;
-    HIPCHK(hipMemcpyAsync(O.d.sc, &so, sizeof(PqnScal), hipMemcpyHostToDevice, ctx.stream));
-    HIPCHK(hipMemcpyAsync(O.d.x, I.d.x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
-    HIPCHK(hipMemcpyAsync(B.Alox, I.d.Ax, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
-    int nlow = std::min(sI.r, kRmax);
-    if (nlow > 0) {
-      HIPCHK(hipMemcpyAsync(B.Slow, I.d.S, (size_t)nlow * n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
-      HIPCHK(hipMemcpyAsync(B.Ylow, I.d.Y, (size_t)nlow * n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
-    }
-    int hcnt[2] = {0, nlow};
-    HIPCHK(hipMemcpyAsync(B.cnt, hcnt, 2 * sizeof(int), hipMemcpyHostToDevice, ctx.stream));
-    hipLaunchKernelGGL(k_nonzero, dim3(1), dim3(kT), 0, ctx.stream, O.d.x, n, O.d.sc);
-    PqnScal snz = read_scal(ctx, O.d.sc);
-    if (snz.nonzero) {
-      mvp_hi(O.d.x, O.d.Ax, MDx);
-    } else {
-      HIPCHK(hipMemsetAsync(O.d.Ax, 0, (size_t)n * sizeof(double), ctx.stream));
-    }
-    auto mvp_B = [&](const double* v, double* out, double*) {
-      timed(true, [&] { lcp_mvp(ctx, lo, n, st.pairs.p, v, B.tmp, ctx.UO.p, &cnt.gmres); });
-      hipLaunchKernelGGL(k_lowrank, dim3(1), dim3(kT), 0, ctx.stream, B, B.tmp, v, out);
-    };
-    int k = 0;
-    for (k = 0; k < o.k_max; ++k) {
-      hipLaunchKernelGGL(k_bi_prepare, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
-      PqnScal so2 = read_scal(ctx, O.d.sc);
-      if (!std::isfinite(so2.e)) throw Error(PQN_ERR_NUMERIC, "non-finite KKT error in Bi-PQN");
-      kkt = so2.e;
-      if (so2.conv) {
-        conv = true;
-        break;
-      }
-      // subproblem: Mono-PQN on B^(k) from x, warm-started with the stored pairs
-      int hc[2];
-      HIPCHK(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
-      HIPCHK(hipStreamSynchronize(ctx.stream));
-      PqnScal sin{};
-      sin.tol_abs = std::max(1e-12, 1e-2 * so2.e);
-      sin.tol_rel = o.kkt_tol_rel;
-      sin.ssn_steps = 0;
-      sin.sigma = sigma_in;
-      HIPCHK(hipMemcpyAsync(I.d.sc, &sin, sizeof(PqnScal), hipMemcpyHostToDevice, ctx.stream));
-      hipLaunchKernelGGL(k_pqn_replay, dim3(1), dim3(kT), 0, ctx.stream, I.d, B.Slow, B.Ylow, hc[1]);
-      run_mono(ctx, I, o.k_max_inner, o.j_max, mvp_B, nullptr, M, &in_iters);
-      PqnScal sI2 = read_scal(ctx, I.d.sc);
-      ssn += sI2.ssn_steps;
-      sigma_in = sI2.sigma;
-      if (sI2.resets > 0) {
-        finish_mono(true, k);
-        break;
-      }
-      hipLaunchKernelGGL(k_bi_direction, dim3(1), dim3(kT), 0, ctx.stream, O.d, I.d);
-      PqnScal sd = read_scal(ctx, O.d.sc);
-      if (sd.stationary) {
-        conv = true;
-        break;
-      }
-      mvp_hi(O.d.p, O.d.Ap, MDx ? st.MDp.p : nullptr);
-      hipLaunchKernelGGL(k_bi_accept, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
-      if (MDx)
-        hipLaunchKernelGGL(k_axpy_dev, dim3((6 * M + 255) / 256), dim3(256), 0, ctx.stream, MDx, st.MDp.p, O.d.sc,
-                           6 * M);
-      HIPCHK(hipGetLastError());
-    }
+    if (sI.resets > 0) finish_mono(false, 0);
     if (!rejected) {
-      if (!conv) {
-        hipLaunchKernelGGL(k_bi_prepare, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
-        PqnScal sf = read_scal(ctx, O.d.sc);
-        conv = sf.conv;
-        kkt = sf.e;
+      // outer state: x = x0, A^ x = inner A x, pairs = inner memory, no corrections
+      PqnScal so{};
+      so.tol_abs = o.kkt_tol_abs;
+      so.tol_rel = o.kkt_tol_rel;
+      HIPCHK(hipMemcpyAsync(O.d.sc, &so, sizeof(PqnScal), hipMemcpyHostToDevice, ctx.stream));
+      HIPCHK(hipMemcpyAsync(O.d.x, I.d.x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+      HIPCHK(hipMemcpyAsync(B.Alox, I.d.Ax, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+      int nlow = std::min(sI.r, kRmax);
+      if (nlow > 0) {
+        HIPCHK(hipMemcpyAsync(B.Slow, I.d.S, (size_t)nlow * n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+        HIPCHK(hipMemcpyAsync(B.Ylow, I.d.Y, (size_t)nlow * n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
       }
-      iters = k;
-    }
-    }
-  done:;
+      int hcnt[2] = {0, nlow};
+      HIPCHK(hipMemcpyAsync(B.cnt, hcnt, 2 * sizeof(int), hipMemcpyHostToDevice, ctx.stream));
+      hipLaunchKernelGGL(k_nonzero, dim3(1), dim3(kT), 0, ctx.stream, O.d.x, n, O.d.sc);
+      PqnScal snz = read_scal(ctx, O.d.sc);
+      if (snz.nonzero) {
+        mvp_hi(O.d.x, O.d.Ax, MDx);
+      } else {
+        HIPCHK(hipMemsetAsync(O.d.Ax, 0, (size_t)n * sizeof(double), ctx.stream));
+      }
+      auto mvp_B = [&](const double* v, double* out, double*) {
+        timed(true, [&] { lcp_mvp(ctx, lo, n, st.pairs.p, v, B.tmp, ctx.UO.p, &cnt.gmres); });
+        hipLaunchKernelGGL(k_lowrank, dim3(1), dim3(kT), 0, ctx.stream, B, B.tmp, v, out);
+      };
+      int k = 0;
+      for (k = 0; k < o.k_max; ++k) {
+        hipLaunchKernelGGL(k_bi_prepare, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
+        PqnScal so2 = read_scal(ctx, O.d.sc);
+        if (!std::isfinite(so2.e)) throw Error(PQN_ERR_NUMERIC, "non-finite KKT error in Bi-PQN");
+        kkt = so2.e;
+        if (so2.conv) {
+          conv = true;
+          break;
+        }
+        // subproblem: Mono-PQN on B^(k) from x, warm-started with the stored pairs
+        int hc[2];
+        HIPCHK(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+        HIPCHK(hipStreamSynchronize(ctx.stream));
+        PqnScal sin{};
+        sin.tol_abs = std::max(1e-12, 1e-2 * so2.e);
+        sin.tol_rel = o.kkt_tol_rel;
+        sin.ssn_steps = 0;
+        sin.sigma = sigma_in;
+        HIPCHK(hipMemcpyAsync(I.d.sc, &sin, sizeof(PqnScal), hipMemcpyHostToDevice, ctx.stream));
+        hipLaunchKernelGGL(k_pqn_replay, dim3(1), dim3(kT), 0, ctx.stream, I.d, B.Slow, B.Ylow, hc[1]);
+        run_mono(ctx, I, o.k_max_inner, o.j_max, mvp_B, nullptr, M, &in_iters);
+        PqnScal sI2 = read_scal(ctx, I.d.sc);
+        ssn += sI2.ssn_steps;
+        sigma_in = sI2.sigma;
+        if (sI2.resets > 0) {
+          finish_mono(true, k);
+          break;
+        }
+        hipLaunchKernelGGL(k_bi_direction, dim3(1), dim3(kT), 0, ctx.stream, O.d, I.d);
+        PqnScal sd = read_scal(ctx, O.d.sc);
+        if (sd.stationary) {
+          conv = true;
+          break;
+        }
+        mvp_hi(O.d.p, O.d.Ap, MDx ? st.MDp.p : nullptr);
+        hipLaunchKernelGGL(k_bi_accept, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
+        if (MDx)
+          hipLaunchKernelGGL(k_axpy_dev, dim3((6 * M + 255) / 256), dim3(256), 0, ctx.stream, MDx, st.MDp.p, O.d.sc,
+                             6 * M);
+        HIPCHK(hipGetLastError());
+      }
+      if (!rejected) {
+        if (!conv) {
+          hipLaunchKernelGGL(k_bi_prepare, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
+          PqnScal sf = read_scal(ctx, O.d.sc);
+          conv = sf.conv;
+          kkt = sf.e;
+        }
+        iters = k;
+      }
+    }  // !rejected after the initial low-fidelity solve
   }
   HIPCHK(hipStreamSynchronize(ctx.stream));
   if (stats) {
