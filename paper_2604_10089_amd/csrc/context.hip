@@ -857,7 +857,7 @@ void pqn_ctx_impl::mobility_multi(Level& lv, int K, const double* const* FT_dev,
     sys.push_back(SysRef{this, &lv, r, b.rhs.p, b.x.p, lv.tol});
   }
   // slip-driven solve: the previous one's density is a close initial guess after a small step
-  const bool slip_only = K == 1 && !FT_dev && axes_dev;
+  const bool slip_only = K == 1 && (!FT_dev || !FT_dev[0]) && axes_dev;
   if (slip_only && cfg.warm_start && lv.has_q_nc) sys[0].x0 = lv.q_nc.p;
   solve_lockstep(sys, st);
   if (slip_only && cfg.warm_start) {
