@@ -170,3 +170,18 @@ def test_warm_started_slip_solves_match_cold_steps():
     assert np.abs(pos[True] - pos[False]).max() < 1e-7 * disp
     assert its[True][0] == its[False][0]
     assert sum(its[True][1:]) < sum(its[False][1:])
+
+
+def test_warm_started_steps_match_oracle(cases):
+    """Two consecutive time steps with the warm-started slip solve against two oracle steps."""
+    cs = cases[0]
+    c, ax = cs['c'], cs['axes']
+    for _ in range(2):
+        c, ax, _ = dynamics.step(c, ax, 1.0, (8, 16), (4, 8), 0.05, 0.1, 1.0, solver='mono',
+                                 lcp_opts=dict(tol_abs=1e-12, tol_rel=1e-15), tol_gmres=1e-13)
+    with binding.Context(cs['c'], cs['axes'], 8, 16, lo=(4, 8), gmres_tol=1e-13, warm_start=True) as ctx:
+        its = [ctx.step(0.05, 0.1, 'mono', tol_abs=1e-12, tol_rel=1e-15)['gmres_iters_nc'] for _ in range(2)]
+        c2, ax2 = ctx.get_state()
+    say('warm steps vs oracle, nc iterations', its)
+    assert np.abs(c2 - c).max() < 1e-10
+    assert np.abs(ax2 - ax).max() < 1e-10
