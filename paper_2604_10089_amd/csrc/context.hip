@@ -303,11 +303,29 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
     const double* qup = lv.wk(gr.slot[0]).qup.p;
     launch_near(s, gr.K, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, qup, cf, c.near_list.p, lv.n, lv.M, lv.N,
                 lv.nup, lv.p, lv.L, 3.0 / (4.0 * kPi * c.a), np);
-    for (int r = 0; r < gr.K; ++r) {
-      Work& w = lv.wk(gr.slot[r]);
-      launch_moments(s, gr.in[r], lv.off.p, lv.w.p, lv.n, lv.M, lv.N, w.mom.p);
-      launch_combine(s, gr.in[r], w.selfo.p, 3, w.far_part.p, lv.nchunks, w.near_part.p, c.npart.p, w.mom.p,
-                     lv.off.p, lv.n, lv.N, c.a, gr.out[r]);
+    if (gr.K == 1) {
+      Work& w = lv.wk(gr.slot[0]);
+      launch_moments(s, gr.in[0], lv.off.p, lv.w.p, lv.n, lv.M, lv.N, w.mom.p);
+      launch_combine(s, gr.in[0], w.selfo.p, 3, w.far_part.p, lv.nchunks, w.near_part.p, c.npart.p, w.mom.p,
+                     lv.off.p, lv.n, lv.N, c.a, gr.out[0]);
+    } else {
+      // rigid moments and the final combination of all K densities, one launch each
+      std::vector<MomDesc> md;
+      std::vector<CombDesc> cd;
+      int nmd = 0, ncd = 0;
+      for (int r = 0; r < gr.K; ++r) {
+        Work& w = lv.wk(gr.slot[r]);
+        md.push_back(MomDesc{gr.in[r], lv.off.p, lv.w.p, w.mom.p, lv.n, lv.N, nmd});
+        nmd += lv.M;
+        cd.push_back(CombDesc{gr.in[r], w.selfo.p, w.far_part.p, w.near_part.p, c.npart.p, w.mom.p, lv.off.p,
+                              gr.out[r], c.a, lv.nchunks, lv.n, lv.N, ncd});
+        ncd += 3 * lv.N;
+      }
+      DescPack dp;
+      const size_t om = dp.add(md), oc = dp.add(cd);
+      char* base = push_desc_pack(dp.host);
+      launch_moments_multi(s, (const MomDesc*)(base + om), (int)md.size(), nmd);
+      launch_combine_multi(s, (const CombDesc*)(base + oc), (int)cd.size(), ncd);
     }
     n_matvec += gr.K;
   }
