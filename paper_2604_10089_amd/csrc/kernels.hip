@@ -591,79 +591,94 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near64(const double* __rest
 
 constexpr int GBM = 32, GBN = 32, GBK = 16;
 constexpr int kGemmSplitBelow = 2048;  // tiles per launch below which k is split over 4 waves
+constexpr int GLS = GBK + 1;            // padded k stride of the LDS tiles (spreads the banks)
 
-// One workgroup of GW waves per 32x32 output tile: wave w accumulates the
-// k-blocks w, w + GW, ... (4x4 outputs per lane, rows ty+8e, cols tx+8f) and
-// the partial tiles are added in wave order through LDS. GW = 4 gives launches
-// with few tiles (short and wide products, K up to 288) enough waves; GW = 1
-// is used when the tiles alone fill the chip. Tile loads run along k, so
-// consecutive lanes read consecutive addresses.
+typedef double gemm_acc4 __attribute__((ext_vector_type(4)));
+
+// One workgroup of GW waves per 32x32 output tile, on the FP64 matrix cores:
+// each wave holds the tile as 2x2 blocks of 16x16 accumulated by
+// V_MFMA_F64_16X16X4F64 (lane l supplies A(l%16, l/16) and B(l/16, l%16) of a
+// 16x4 by 4x16 step and holds D(l/16 + 4j, l%16), j < 4). Wave w accumulates
+// the k-blocks w, w + GW, ...; with GW = 4 (launches with few tiles: short and
+// wide products, K up to 288) the partial tiles are added in wave order
+// through LDS. Tile loads run along k, so consecutive lanes read consecutive
+// addresses of A rows and B columns.
 template <int GW>
 __device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, const double* __restrict__ A,
                                           int lda, const double* __restrict__ B, int ldb, double* __restrict__ C,
                                           int rb, long rbs, int ldc) {
-  constexpr int GWAVES = GW;
-  // per wave: A and B slices [GBK][33]; reused for the partial tiles [32][33]
-  __shared__ double sh[GWAVES][2 * GBK * (GBM + 1)];
+  // per wave: A and B slices [32][GLS]; reused for the partial tiles [32][33]
+  __shared__ double sh[GW][2 * GBM * GLS];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* As = sh[wv];
-  double* Bs = sh[wv] + GBK * (GBM + 1);
-  const int tx = lane % 8, ty = lane / 8;
+  double* Bs = sh[wv] + GBM * GLS;
   const int r0 = bx * GBM, c0 = by * GBN;
-  double acc[4][4] = {};
+  const int li = lane & 15, lk = lane >> 4;
+  gemm_acc4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = gemm_acc4{0.0, 0.0, 0.0, 0.0};
   const int nkb = (K + GBK - 1) / GBK;
-  const int steps = (nkb + GWAVES - 1) / GWAVES;  // same count for every wave (barriers)
+  const int steps = (nkb + GW - 1) / GW;  // same count for every wave (barriers)
   for (int st = 0; st < steps; ++st) {
-    const int k0 = (st * GWAVES + wv) * GBK;
+    const int k0 = (st * GW + wv) * GBK;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int idx = lane + e * 64;          // 0..511: k fastest
+      const int idx = lane + e * 64;  // 0..511: k fastest
       const int kk = idx % GBK, rc = idx / GBK;
       const int gk = k0 + kk;
       const int gr = r0 + rc, gc = c0 + rc;
-      As[kk * (GBM + 1) + rc] = (gr < R && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
-      Bs[kk * (GBN + 1) + rc] = (gc < Cn && gk < K) ? B[(size_t)gc * ldb + gk] : 0.0;
+      As[rc * GLS + kk] = (gr < R && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
+      Bs[rc * GLS + kk] = (gc < Cn && gk < K) ? B[(size_t)gc * ldb + gk] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < GBK; ++kk) {
-      double av[4], bv[4];
+    for (int k4 = 0; k4 < GBK / 4; ++k4) {
+      double av[2], bv[2];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        av[e] = As[kk * (GBM + 1) + ty + 8 * e];
-        bv[e] = Bs[kk * (GBN + 1) + tx + 8 * e];
+      for (int i = 0; i < 2; ++i) {
+        av[i] = As[(16 * i + li) * GLS + 4 * k4 + lk];
+        bv[i] = Bs[(16 * i + li) * GLS + 4 * k4 + lk];
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int f = 0; f < 4; ++f) acc[e][f] = fma(av[e], bv[f], acc[e][f]);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
-  // partial tiles of waves 1.. into LDS, wave 0 adds them in order and stores
-  double* part = &sh[0][0];  // (GWAVES - 1) x [32][33] doubles fit in sh
-  if (GWAVES > 1 && wv > 0)
+  // element (i, j, q) of the lane: tile row 16 i + lk + 4 q, tile column 16 j + li
+  double* part = &sh[0][0];  // (GW - 1) x [32][33] doubles fit in sh
+  if (GW > 1 && wv > 0)
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int f = 0; f < 4; ++f) part[((wv - 1) * GBM + ty + 8 * e) * (GBN + 1) + tx + 8 * f] = acc[e][f];
-  if (GWAVES > 1) __syncthreads();
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          part[((wv - 1) * GBM + 16 * i + lk + 4 * q) * (GBN + 1) + 16 * j + li] = acc[i][j][q];
+  if (GW > 1) __syncthreads();
   if (wv == 0) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int gr = r0 + ty + 8 * e;
-      if (gr >= R) continue;
-      const size_t rowbase = (size_t)(gr / rb) * rbs + gr % rb;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        const int gc = c0 + tx + 8 * f;
-        double v = acc[e][f];
+      for (int q = 0; q < 4; ++q) {
+        const int tr = 16 * i + lk + 4 * q;
+        const int gr = r0 + tr;
+        if (gr >= R) continue;
+        const size_t rowbase = (size_t)(gr / rb) * rbs + gr % rb;
 #pragma unroll
-        for (int w = 1; w < GWAVES; ++w) v += part[((w - 1) * GBM + ty + 8 * e) * (GBN + 1) + tx + 8 * f];
-        if (gc < Cn) C[rowbase + (size_t)gc * ldc] = v;
+        for (int j = 0; j < 2; ++j) {
+          const int tc = 16 * j + li;
+          const int gc = c0 + tc;
+          double v = acc[i][j][q];
+#pragma unroll
+          for (int w = 1; w < GW; ++w) v += part[((w - 1) * GBM + tr) * (GBN + 1) + tc];
+          if (gc < Cn) C[rowbase + (size_t)gc * ldc] = v;
+        }
       }
-    }
   }
 }
 
