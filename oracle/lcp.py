@@ -474,3 +474,133 @@ def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_
         conv = _converged(e, e_prev, tol_abs, tol_rel)
     return x, Ax, Stats(iters=len(hist) - 1, mvp_hi=mvp_hi, mvp_lo=mvp_lo, kkt=hist[-1],
                         converged=conv, hist=hist, fallback=False)
+
+
+def bi_pqn_rec(ops, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_max=50):
+    """Recursive Bi-PQN over a hierarchy of fidelities (the extension of Sec. 7).
+
+    ops[0] is the high-fidelity product A[.], ops[1], ops[2], ... ever cheaper
+    models. Every subproblem of Bi-PQN is itself a non-negativity constrained
+    quadratic program whose quadratic term is a (corrected) mobility product,
+    so it is solved by Bi-PQN one fidelity down, and by Mono-PQN at the lowest
+    fidelity. With two operators this is bi_pqn step for step.
+
+    Level d minimises 1/2 z.H_d z + c.z over z >= 0, H_d = ops[d] + C_0 + ...
+    + C_{d-1}, the C_e being the BFGS corrections (U U^T - V V^T) of the
+    enclosing levels. A Bi-PQN level d models H_d by L_d + C_d with
+    L_d = ops[d+1] + C_0 + ... + C_{d-1}; it learns C_d from its own steps
+    exactly as bi_pqn (App. E.2: L_d s from L_d x^ - L_d x, no product).
+    Readings (the paper only sketches the variant):
+      * The top level keeps Alg. 4's initial solve from x = 0 (itself solved
+        one level down). A nested level starts at the caller's iterate x with
+        H_d x known and pays one product of ops[d+1] for L_d x (none if x = 0).
+      * Secant pairs warm-start only a Mono-PQN subproblem (the lowest level);
+        a nested Bi-PQN level starts with no correction.
+      * Tolerances: 1e-2 x the level's current KKT error (floor 1e-12), at most
+        k_max_inner outer steps per nested level and products per Mono-PQN.
+      * Model safeguard per level, as in bi_pqn: when the subproblem solve
+        meets the Alg. 2 edge cases on its own operator (its steps, or the
+        Mono-PQN it fell back to), the level finishes as Mono-PQN on H_d from
+        its current iterate. A level reports those edge cases of its own
+        steps and of its fallback to the caller.
+
+    Returns (x, A x, stats) with stats['mvp'] = products per fidelity.
+    """
+    n = b.size
+    nf = len(ops)
+    if nf < 2:
+        raise ValueError('recursive Bi-PQN needs at least two fidelities')
+    cnt = [0] * nf
+
+    def op(d, corrs):
+        def H(v):
+            cnt[d] += 1
+            out = ops[d](v)
+            for c in corrs:
+                out = out + c.lowrank(v)
+            return out
+        return H
+
+    def solve(d, corrs, c, x, Hx, tol, k_lim, pairs, sigma, top=False):
+        H = op(d, corrs)
+        if d == nf - 1:
+            xs, Hxs, st = mono_pqn(H, c, x, Hx, k_max=k_lim, tol_abs=tol, tol_rel=tol_rel,
+                                   pairs=pairs, j_max=j_max, sigma=sigma)
+            return xs, Hxs, dict(resets=st['resets'], S=st['S'], Y=st['Y'], sigma=st['sigma'],
+                                 iters=st['iters'], kkt=st['kkt'], converged=st['converged'],
+                                 hist=st['hist'], fallback=False)
+        last_in = d + 1 == nf - 1
+        L = op(d + 1, corrs)
+        resets = 0
+
+        def fallback(x0, Hx0, k_done, hist):
+            xm, Hxm, sm = mono_pqn(H, c, x0, Hx0, k_max=max(1, k_lim - k_done), tol_abs=tol,
+                                   tol_rel=tol_rel, j_max=j_max)
+            return xm, Hxm, dict(resets=resets + sm['resets'], S=[], Y=[], sigma=sigma,
+                                 iters=len(hist) + sm['iters'], kkt=sm['kkt'],
+                                 converged=sm['converged'], hist=hist + sm['hist'], fallback=True)
+
+        if top:
+            tol0 = max(1e-12, 1e-2 * kkt_error(x, Hx + c))
+            x, Lx, si = solve(d + 1, corrs, c, x, np.zeros(n), tol0, k_max_inner, [], None)
+            if si['resets'] > 0:
+                return fallback(np.zeros(n), np.zeros(n), 0, [])
+            S, Y = (si['S'], si['Y']) if last_in else ([], [])
+            sigma = si['sigma']
+            Hx = H(x) if np.any(x != 0.0) else np.zeros(n)
+        else:
+            Lx = L(x) if np.any(x != 0.0) else np.zeros(n)
+            S, Y = [], []
+        corr = QuasiNewton(n)
+        e_prev = None
+        conv = False
+        hist = []
+        for k in range(k_lim):
+            g = Hx + c
+            e = kkt_error(x, g)
+            hist.append(e)
+            if _converged(e, e_prev, tol, tol_rel):
+                conv = True
+                break
+            e_prev = e
+            Bx = Lx + corr.lowrank(x)
+            tol_in = max(1e-12, 1e-2 * e)
+            xh, Bxh, si = solve(d + 1, corrs + [corr], g - Bx, x, Bx, tol_in, k_max_inner,
+                                list(zip(S, Y)) if last_in else [], sigma)
+            sigma = si['sigma']
+            if si['resets'] > 0:
+                return fallback(x, Hx, k, hist)
+            p = xh - x
+            if not np.any(p != 0.0):
+                conv = True
+                break
+            Hp = H(p)
+            eta, reset = step_size(g, x, p, Hp)
+            Ls = eta * (Bxh - corr.lowrank(xh) - Lx)
+            s, y = eta * p, eta * Hp
+            Bs = Ls + corr.lowrank(s)
+            Shat, Yhat = (si['S'], si['Y']) if last_in else ([], [])
+            if reset:
+                resets += 1
+                corr = QuasiNewton(n)
+                Shat, Yhat = [], []
+                Bs = Ls.copy()
+            nu = len(corr.U)
+            if corr.update(s, y, Bs=Bs):
+                S, Y = secant_transfer(Shat, Yhat, corr.U[nu], corr.V[nu])
+            else:
+                S, Y = list(Shat), list(Yhat)
+            x = np.maximum(x + eta * p, 0.0)
+            Hx = Hx + eta * Hp
+            Lx = Lx + Ls
+        else:
+            e = kkt_error(x, Hx + c)
+            hist.append(e)
+            conv = _converged(e, e_prev, tol, tol_rel)
+        return x, Hx, dict(resets=resets, S=[], Y=[], sigma=sigma, iters=len(hist) - 1, kkt=hist[-1],
+                           converged=conv, hist=hist, fallback=False)
+
+    x, Ax, st = solve(0, [], b, np.zeros(n), np.zeros(n), tol_abs, k_max, [], None, top=True)
+    return x, Ax, Stats(iters=st['iters'], mvp=list(cnt), mvp_hi=cnt[0], mvp_lo=sum(cnt[1:]),
+                        kkt=st['kkt'], converged=st['converged'], hist=st['hist'],
+                        fallback=st['fallback'])

@@ -221,3 +221,92 @@ def test_bi_pqn_rejects_an_indefinite_model():
     x2, _, st2 = lcp.bi_pqn(lambda v: A @ v, lambda v: Alo_good @ v, b, **kw)
     assert not st2['fallback'] and st2['converged']
     assert np.abs(x2 - xbf).max() < 1e-9 * np.abs(xbf).max()
+
+
+def _counted(f, box, k):
+    def g(v):
+        box[k] += 1
+        return f(v)
+    return g
+
+
+def test_bi_pqn_rec_with_two_fidelities_is_bi_pqn(tiny_lcps):
+    """The recursion bottoms out in Alg. 4 itself: with two operators every iterate,
+    KKT error and product count equals bi_pqn's."""
+    for c in tiny_lcps:
+        for b in (c['b_real'], c['b_pl']):
+            x1, Ax1, s1 = lcp.bi_pqn(c['Aop'], c['Alo'], b, tol_abs=1e-12, tol_rel=1e-15)
+            x2, Ax2, s2 = lcp.bi_pqn_rec([c['Aop'], c['Alo']], b, tol_abs=1e-12, tol_rel=1e-15)
+            assert s1['hist'] == s2['hist']
+            assert (s1['mvp_hi'], s1['mvp_lo']) == tuple(s2['mvp'])
+            assert np.array_equal(x1, x2) and np.array_equal(Ax1, Ax2)
+
+
+@pytest.fixture(scope="module")
+def tiny_lcps3(tiny_lcps, tiny_cases):
+    """tiny_lcps plus a middle fidelity (6x12 grid) between the 8x16 and 4x8 ones."""
+    out = []
+    for c, (seed, g, A) in zip(tiny_lcps, tiny_cases):
+        pairs, _ = dynamics.find_contacts(g.c, 1.0, 0.1)
+        gm = bie.Geometry(g.c, 1.0, 6, 12)
+        Am = bie.dense_operator(gm)
+        Amid = lcp.lcp_operator(lambda FT, gm=gm, Am=Am: bie.mobility_apply(gm, FT, dense=Am), g.c, pairs)
+        out.append(dict(c, Amid=Amid))
+    return out
+
+
+def test_bi_pqn_rec_three_fidelities_match_brute_force(tiny_lcps3):
+    """Three fidelities (8x16, 6x12, 4x8 grids): the solution is the LCP's (brute force over
+    active sets), complementarity holds, A x carried by the recurrence equals a fresh
+    product, and every fidelity is used; the counts are the operators' own call counts."""
+    for c in tiny_lcps3:
+        for b in (c['b_real'], c['b_pl']):
+            box = [0, 0, 0]
+            ops = [_counted(c['Aop'], box, 0), _counted(c['Amid'], box, 1), _counted(c['Alo'], box, 2)]
+            x, Ax, st = lcp.bi_pqn_rec(ops, b, tol_abs=1e-12, tol_rel=1e-15)
+            xbf = lcp.brute_force_lcp(c['Ad'], b)
+            assert st['converged'] and not st['fallback']
+            assert np.abs(x - xbf).max() <= 1e-10 * max(np.abs(xbf).max(), 1e-300)
+            _check_complementarity(x, c['Ad'], b)
+            assert np.abs(Ax - c['Ad'] @ x).max() <= 1e-12 * max(1.0, np.abs(c['Ad'] @ x).max())
+            assert st['mvp'] == box
+            if np.any(xbf > 0):
+                assert min(box) >= 1
+
+
+def test_bi_pqn_rec_with_exact_models_needs_few_high_fidelity_products(tiny_lcps):
+    """All three fidelities equal A: the first subproblem is the LCP itself, so as with
+    two exact fidelities the high-fidelity products only confirm and polish."""
+    for c in tiny_lcps:
+        x, _, st = lcp.bi_pqn_rec([c['Aop']] * 3, c['b_pl'], tol_abs=1e-10)
+        assert np.abs(x - c['x_pl']).max() < 1e-8 * np.abs(c['x_pl']).max()
+        assert st['mvp_hi'] <= 4
+
+
+def test_bi_pqn_rec_safeguard_at_each_level():
+    """An indefinite lowest model is caught inside the middle level (which finishes its
+    subproblems as Mono-PQN on its own positive definite operator), so the top level keeps
+    its model; an indefinite middle model makes the top level itself fall back. Both
+    return the brute-force solution."""
+    rng = np.random.default_rng(7)
+    n = 8
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.exp(rng.uniform(np.log(1e-2), np.log(1e-1), n))
+    A = (Q * ev) @ Q.T
+    bad = (Q * (ev * np.r_[1.0, -1.0, np.ones(n - 2)])) @ Q.T
+    good = (Q * (ev * np.exp(rng.uniform(-0.5, 0.5, n)))) @ Q.T
+    good2 = (Q * (ev * np.exp(rng.uniform(-0.7, 0.7, n)))) @ Q.T
+    xs, ws = inputs.planted_lcp(5, n)
+    b = ws - A @ xs
+    xbf = lcp.brute_force_lcp(A, b)
+    kw = dict(tol_abs=1e-12, tol_rel=1e-15)
+    mv = lambda M: (lambda v: M @ v)
+    x, _, st = lcp.bi_pqn_rec([mv(A), mv(good), mv(bad)], b, **kw)
+    assert st['converged'] and not st['fallback']
+    assert np.abs(x - xbf).max() < 1e-9 * np.abs(xbf).max()
+    x, _, st = lcp.bi_pqn_rec([mv(A), mv(bad), mv(good2)], b, **kw)
+    assert st['converged'] and st['fallback']
+    assert np.abs(x - xbf).max() < 1e-9 * np.abs(xbf).max()
+    x, _, st = lcp.bi_pqn_rec([mv(A), mv(good), mv(good2)], b, **kw)
+    assert st['converged'] and not st['fallback']
+    assert np.abs(x - xbf).max() < 1e-9 * np.abs(xbf).max()
