@@ -50,8 +50,12 @@ typedef enum {
 } pqn_status;
 
 typedef enum { PQN_FP64 = 0, PQN_MIXED = 1 } pqn_precision;
-typedef enum { PQN_BBPGD = 0, PQN_MONO = 1, PQN_BI = 2 } pqn_solver;
-typedef enum { PQN_HIFI = 0, PQN_LOFI = 1 } pqn_fidelity;
+/* PQN_BI_REC: recursive Bi-PQN over three fidelities (the generalisation sketched in
+ * Sec. 7): every Bi-PQN subproblem is solved by Bi-PQN one fidelity down, the lowest by
+ * Mono-PQN. Needs both low-fidelity levels of the context. */
+typedef enum { PQN_BBPGD = 0, PQN_MONO = 1, PQN_BI = 2, PQN_BI_REC = 3 } pqn_solver;
+/* PQN_LOFI2: the second, coarsest low fidelity (n_theta_lo2 / gmres_tol_lo2). */
+typedef enum { PQN_HIFI = 0, PQN_LOFI = 1, PQN_LOFI2 = 2 } pqn_fidelity;
 
 /* Context description; copied by pqn_create. Zero fields take the defaults
  * given in brackets. */
@@ -81,6 +85,9 @@ typedef struct {
                                captured hipGraph (one per Arnoldi index; ignored when profile = 1) */
   int32_t warm_start;       /* 1 = the slip-driven solve (U_nc, also inside pqn_step) starts GMRES
                                from the previous slip solve's density instead of 0 */
+  int32_t n_theta_lo2, n_phi_lo2; /* second low-fidelity grid (PQN_LOFI2); 0 = none (PQN_BI_REC
+                               then unavailable). Needs the first low-fidelity grid. */
+  double gmres_tol_lo2;     /* relative residual of each PQN_LOFI2 solve [1e-8] */
 } pqn_config_desc;
 
 typedef struct {
@@ -116,6 +123,8 @@ typedef struct {
   int32_t gmres_iters;      /* Krylov iterations over all products */
   int32_t model_rejected;   /* Bi-PQN: 1 if a low-fidelity solve met non-positive curvature or no
                                descent and the solve finished as Mono-PQN on A */
+  int32_t mvp_lo2;          /* PQN_BI_REC: products at the second low fidelity (each one BIE solve) */
+  double lo2_hi_cost_ratio; /* measured t_lo2/t_hi of this call; emvp adds mvp_lo2 * this ratio */
 } pqn_lcp_stats;
 
 typedef struct {
@@ -165,7 +174,10 @@ pqn_status pqn_find_contacts(pqn_ctx* ctx, double delta, int32_t cap, int32_t* n
 pqn_status pqn_lcp_apply(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const double* x, double* Ax, int32_t fidelity);
 
 /* Solve 0 <= A x + b perp x >= 0 (eq. (LCP)). x: on entry ignored (the solvers start
- * at 0), on exit the solution. opts may be NULL (defaults). */
+ * at 0), on exit the solution. opts may be NULL (defaults). PQN_BI needs the context's
+ * low-fidelity grid, PQN_BI_REC both low-fidelity grids (else PQN_ERR_STATE); for
+ * PQN_BI_REC, k_max_inner bounds the outer steps of the middle level and the products
+ * of each lowest-level solve. */
 pqn_status pqn_lcp_solve(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const double* b, double* x, int32_t solver,
                          const pqn_lcp_opts* opts, pqn_lcp_stats* stats);
 

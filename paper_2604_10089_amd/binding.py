@@ -14,9 +14,9 @@ LIB_PATH = os.path.join(HERE, 'libbipqn.so')
 
 PQN_OK, PQN_WARN_NOT_CONVERGED = 0, 1
 PQN_FP64, PQN_MIXED = 0, 1
-PQN_BBPGD, PQN_MONO, PQN_BI = 0, 1, 2
-PQN_HIFI, PQN_LOFI = 0, 1
-SOLVERS = {'bb': PQN_BBPGD, 'mono': PQN_MONO, 'bi': PQN_BI}
+PQN_BBPGD, PQN_MONO, PQN_BI, PQN_BI_REC = 0, 1, 2, 3
+PQN_HIFI, PQN_LOFI, PQN_LOFI2 = 0, 1, 2
+SOLVERS = {'bb': PQN_BBPGD, 'mono': PQN_MONO, 'bi': PQN_BI, 'birec': PQN_BI_REC}
 
 
 class ConfigDesc(C.Structure):
@@ -28,7 +28,8 @@ class ConfigDesc(C.Structure):
                 ('targets_per_thread', C.c_int32), ('far_chunks', C.c_int32), ('far_split', C.c_int32),
                 ('device', C.c_int32),
                 ('stream', C.c_void_p), ('profile', C.c_int32), ('use_graphs', C.c_int32),
-                ('warm_start', C.c_int32)]
+                ('warm_start', C.c_int32), ('n_theta_lo2', C.c_int32), ('n_phi_lo2', C.c_int32),
+                ('gmres_tol_lo2', C.c_double)]
 
 
 class MvpStats(C.Structure):
@@ -46,7 +47,7 @@ class LcpStats(C.Structure):
     _fields_ = [('iters', C.c_int32), ('mvp_hi', C.c_int32), ('mvp_lo', C.c_int32), ('emvp', C.c_double),
                 ('lo_hi_cost_ratio', C.c_double), ('kkt_abs', C.c_double), ('converged', C.c_int32),
                 ('ssn_steps', C.c_int32), ('t_total_ms', C.c_double), ('gmres_iters', C.c_int32),
-                ('model_rejected', C.c_int32)]
+                ('model_rejected', C.c_int32), ('mvp_lo2', C.c_int32), ('lo2_hi_cost_ratio', C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -155,15 +156,19 @@ def pqn_host_self_block(n_theta, n_phi, radius=1.0):
 
 def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_tol_lo=None, restart=50,
           max_iter=500, near_gap=0.0, near_up=2, slip=1.0, precision='fp64', refine=0, tpt=2, far_chunks=0,
-          far_split=0, device=0, stream=None, profile=False, graphs=False, warm_start=False):
+          far_split=0, device=0, stream=None, profile=False, graphs=False, warm_start=False, lo2=None,
+          gmres_tol_lo2=None):
     d = ConfigDesc()
     d.n_particles = M
     d.radius, d.mu = radius, mu
     d.n_theta, d.n_phi = n_theta, n_phi
     if lo is not None:
         d.n_theta_lo, d.n_phi_lo = lo
+    if lo2 is not None:
+        d.n_theta_lo2, d.n_phi_lo2 = lo2
     d.gmres_tol = gmres_tol
     d.gmres_tol_lo = gmres_tol if gmres_tol_lo is None else gmres_tol_lo
+    d.gmres_tol_lo2 = gmres_tol if gmres_tol_lo2 is None else gmres_tol_lo2
     d.gmres_restart, d.gmres_max_iter = restart, max_iter
     d.near_gap, d.near_up, d.slip_speed = near_gap, near_up, slip
     d.precision = PQN_MIXED if precision == 'mixed' else PQN_FP64
@@ -243,7 +248,8 @@ class Context:
     def __init__(self, centers, axes=None, n_theta=8, n_phi=16, lo=None, radius=1.0, mu=1.0,
                  gmres_tol=1e-8, gmres_tol_lo=None, restart=50, max_iter=500, near_gap=0.0, near_up=2,
                  slip=1.0, precision='fp64', refine=0, tpt=None, far_chunks=None, far_split=None, device=0,
-                 stream=None, profile=False, tune_K=1, graphs=False, warm_start=False):
+                 stream=None, profile=False, tune_K=1, graphs=False, warm_start=False, lo2=None,
+                 gmres_tol_lo2=None):
         c = _f64(centers).reshape(-1, 3)
         self.M = c.shape[0]
         if tpt is None or far_chunks is None or far_split is None:
@@ -252,27 +258,12 @@ class Context:
             far_chunks = c2 if far_chunks is None else far_chunks
             far_split = s2 if far_split is None else far_split
         self.far_shape = dict(tpt=tpt, chunks=far_chunks, split=int(bool(far_split)))
-        d = ConfigDesc()
-        d.n_particles = self.M
-        d.radius, d.mu = radius, mu
-        d.n_theta, d.n_phi = n_theta, n_phi
-        if lo is not None:
-            d.n_theta_lo, d.n_phi_lo = lo
-        d.gmres_tol = gmres_tol
-        d.gmres_tol_lo = gmres_tol if gmres_tol_lo is None else gmres_tol_lo
-        d.gmres_restart, d.gmres_max_iter = restart, max_iter
-        d.near_gap, d.near_up, d.slip_speed = near_gap, near_up, slip
-        d.precision = PQN_MIXED if precision == 'mixed' else PQN_FP64
-        d.refine_sweeps = refine
-        d.targets_per_thread = tpt
-        d.far_chunks = far_chunks
-        d.far_split = 1 if far_split else 0
-        d.device = device
-        d.stream = stream
-        d.profile = 1 if profile else 0
-        d.use_graphs = 1 if graphs else 0
-        d.warm_start = 1 if warm_start else 0
-        self.n_theta, self.n_phi, self.lo = n_theta, n_phi, lo
+        d = _desc(self.M, n_theta, n_phi, lo=lo, radius=radius, mu=mu, gmres_tol=gmres_tol,
+                  gmres_tol_lo=gmres_tol_lo, restart=restart, max_iter=max_iter, near_gap=near_gap,
+                  near_up=near_up, slip=slip, precision=precision, refine=refine, tpt=tpt,
+                  far_chunks=far_chunks, far_split=far_split, device=device, stream=stream, profile=profile,
+                  graphs=graphs, warm_start=warm_start, lo2=lo2, gmres_tol_lo2=gmres_tol_lo2)
+        self.n_theta, self.n_phi, self.lo, self.lo2 = n_theta, n_phi, lo, lo2
         ax = None if axes is None else _f64(axes).reshape(-1, 3)
         h = C.c_void_p()
         _check(lib().pqn_create(C.byref(d), _dptr(c), None if ax is None else _dptr(ax), C.byref(h)))

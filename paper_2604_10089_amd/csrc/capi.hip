@@ -31,6 +31,7 @@ static void fill_defaults(pqn_config_desc& c) {
   if (c.mu <= 0) c.mu = 1.0;
   if (c.gmres_tol <= 0) c.gmres_tol = 1e-8;
   if (c.gmres_tol_lo <= 0) c.gmres_tol_lo = 1e-8;
+  if (c.gmres_tol_lo2 <= 0) c.gmres_tol_lo2 = 1e-8;
   if (c.gmres_restart <= 0) c.gmres_restart = 50;
   if (c.gmres_max_iter <= 0) c.gmres_max_iter = 500;
   if (c.near_gap <= 0) c.near_gap = 0.5 * c.radius;
@@ -40,6 +41,13 @@ static void fill_defaults(pqn_config_desc& c) {
 }
 
 static bool is_batch(const pqn_ctx* ctx) { return ctx && ctx->is_batch; }
+
+// nullptr if the context has the fidelities the (valid) solver needs, else the reason.
+static const char* solver_unavailable(const pqn_ctx_impl& c, int solver) {
+  if (solver == PQN_BI && !c.has_lo) return "Bi-PQN needs a low-fidelity grid";
+  if (solver == PQN_BI_REC && !c.has_lo2) return "recursive Bi-PQN needs two low-fidelity grids";
+  return nullptr;
+}
 
 extern "C" {
 
@@ -51,6 +59,9 @@ static std::string check_desc(const pqn_config_desc& c) {
     return "high-fidelity grid needs n_theta >= 2 and n_phi >= 2 n_theta - 1";
   if (c.n_theta_lo != 0 && (c.n_theta_lo < 2 || c.n_phi_lo < 2 * c.n_theta_lo - 1))
     return "low-fidelity grid needs n_theta >= 2 and n_phi >= 2 n_theta - 1";
+  if (c.n_theta_lo2 != 0 && (c.n_theta_lo2 < 2 || c.n_phi_lo2 < 2 * c.n_theta_lo2 - 1))
+    return "second low-fidelity grid needs n_theta >= 2 and n_phi >= 2 n_theta - 1";
+  if (c.n_theta_lo2 != 0 && c.n_theta_lo == 0) return "a second low-fidelity grid needs the first";
   if (c.precision != PQN_FP64 && c.precision != PQN_MIXED) return "bad precision";
   return "";
 }
@@ -74,6 +85,10 @@ static std::unique_ptr<pqn_ctx_impl> make_context(const pqn_config_desc& c, cons
   if (c.n_theta_lo > 0) {
     ctx->setup_level(ctx->lo, c.n_theta_lo, c.n_phi_lo, c.gmres_tol_lo);
     ctx->has_lo = true;
+  }
+  if (c.n_theta_lo2 > 0) {
+    ctx->setup_level(ctx->lo2, c.n_theta_lo2, c.n_phi_lo2, c.gmres_tol_lo2);
+    ctx->has_lo2 = true;
   }
   ctx->FT.alloc(6 * (size_t)kMaxRhs * ctx->M);
   ctx->UO.alloc(6 * (size_t)kMaxRhs * ctx->M);
@@ -448,8 +463,8 @@ pqn_status pqn_lcp_solve(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const do
   return guarded([&]() -> pqn_status {
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_lcp_solve needs a single-suspension context");
     if (!ctx || n < 0 || (n > 0 && (!pairs || !b || !x))) return fail(PQN_ERR_INVALID, "pqn_lcp_solve: bad argument");
-    if (solver != PQN_BBPGD && solver != PQN_MONO && solver != PQN_BI) return fail(PQN_ERR_INVALID, "bad solver");
-    if (solver == PQN_BI && !ctx->has_lo) return fail(PQN_ERR_STATE, "Bi-PQN needs a low-fidelity grid");
+    if (solver < PQN_BBPGD || solver > PQN_BI_REC) return fail(PQN_ERR_INVALID, "bad solver");
+    if (const char* why = solver_unavailable(*ctx, solver)) return fail(PQN_ERR_STATE, why);
     HIPCHK(hipSetDevice(ctx->device));
     lcp_check_pairs(*ctx, n, pairs);
     return lcp_solve_host(*ctx, n, pairs, b, x, solver, opts, stats);
@@ -461,8 +476,8 @@ pqn_status pqn_step(pqn_ctx* ctx, double dt, double delta, int32_t solver, const
   return guarded([&]() -> pqn_status {
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_step needs a single-suspension context");
     if (!ctx || !(dt > 0.0) || !std::isfinite(delta)) return fail(PQN_ERR_INVALID, "pqn_step: bad argument");
-    if (solver != PQN_BBPGD && solver != PQN_MONO && solver != PQN_BI) return fail(PQN_ERR_INVALID, "bad solver");
-    if (solver == PQN_BI && !ctx->has_lo) return fail(PQN_ERR_STATE, "Bi-PQN needs a low-fidelity grid");
+    if (solver < PQN_BBPGD || solver > PQN_BI_REC) return fail(PQN_ERR_INVALID, "bad solver");
+    if (const char* why = solver_unavailable(*ctx, solver)) return fail(PQN_ERR_STATE, why);
     HIPCHK(hipSetDevice(ctx->device));
     return lcp_step(*ctx, dt, delta, solver, opts, stats);
   });

@@ -161,8 +161,8 @@ struct pqn_ctx_impl {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int device = 0;
-  Level hi, lo;
-  bool has_lo = false;
+  Level hi, lo, lo2;  // fidelities PQN_HIFI, PQN_LOFI, PQN_LOFI2
+  bool has_lo = false, has_lo2 = false;
   // configuration-dependent tables shared by both levels
   DevArray<double> ctr, dax;
   DevArray<unsigned char> cls;
@@ -194,7 +194,11 @@ struct pqn_ctx_impl {
       if (!has_lo) throw Error(PQN_ERR_STATE, "no low-fidelity grid in this context");
       return lo;
     }
-    if (fidelity != PQN_HIFI) throw Error(PQN_ERR_INVALID, "fidelity must be PQN_HIFI or PQN_LOFI");
+    if (fidelity == PQN_LOFI2) {
+      if (!has_lo2) throw Error(PQN_ERR_STATE, "no second low-fidelity grid in this context");
+      return lo2;
+    }
+    if (fidelity != PQN_HIFI) throw Error(PQN_ERR_INVALID, "fidelity must be PQN_HIFI, PQN_LOFI or PQN_LOFI2");
     return hi;
   }
   void setup_level(Level& lv, int nt, int np, double tol);

@@ -708,6 +708,7 @@ __global__ __launch_bounds__(kT) void k_bi_accept(PqnDev o, BiDev B, PqnDev in) 
     B.cnt[1] = nlow;
     o.sc->eta = eta;
     o.sc->reset = reset;
+    o.sc->resets += reset;
   }
 }
 
@@ -797,37 +798,47 @@ struct LcpState {
   int cap = 0;
   DevArray<int> pairs, cpairs, ccount;
   DevArray<double> cgaps;
-  Engine outer, inner;
+  // engines: outer (the solve itself), mid (the middle level of recursive Bi-PQN),
+  // inner (the lowest-fidelity Mono-PQN subproblems)
+  Engine outer, mid, inner;
   DevArray<double> bivec;
   DevArray<int> bicnt;
-  BiDev bi{};
+  BiDev bi{}, bi2{};  // Bi-PQN state of the top level and of the middle level
   DevArray<double> MDx, MDp, Unc;
   void ensure(int n, int M) {
     if (n <= cap && MDx.p) return;
     cap = std::max(n, 1);
     pairs.alloc(2 * (size_t)cap);
     outer.alloc(cap);
+    mid.alloc(cap);
     inner.alloc(cap);
-    bivec.alloc((size_t)(4 * kRmax + 4) * cap);
-    bicnt.alloc(2);
-    double* v = bivec.p;
-    bi.Uc = v;
-    bi.Vc = v + (size_t)kRmax * cap;
-    bi.Slow = v + (size_t)2 * kRmax * cap;
-    bi.Ylow = v + (size_t)3 * kRmax * cap;
-    bi.Alox = v + (size_t)4 * kRmax * cap;
-    bi.Alos = bi.Alox + cap;
-    bi.Bs = bi.Alos + cap;
-    bi.tmp = bi.Bs + cap;
-    bi.cnt = bicnt.p;
+    const size_t per = (size_t)(4 * kRmax + 4) * cap;
+    bivec.alloc(2 * per);
+    bicnt.alloc(4);
+    BiDev* bs[2] = {&bi, &bi2};
+    for (int l = 0; l < 2; ++l) {
+      BiDev& b = *bs[l];
+      double* v = bivec.p + l * per;
+      b.Uc = v;
+      b.Vc = v + (size_t)kRmax * cap;
+      b.Slow = v + (size_t)2 * kRmax * cap;
+      b.Ylow = v + (size_t)3 * kRmax * cap;
+      b.Alox = v + (size_t)4 * kRmax * cap;
+      b.Alos = b.Alox + cap;
+      b.Bs = b.Alos + cap;
+      b.tmp = b.Bs + cap;
+      b.cnt = bicnt.p + 2 * l;
+    }
     MDx.alloc(6 * (size_t)M);
     MDp.alloc(6 * (size_t)M);
     Unc.alloc(6 * (size_t)M);
   }
   void set_n(int n) {
     outer.d.n = n;
+    mid.d.n = n;
     inner.d.n = n;
     bi.n = n;
+    bi2.n = n;
   }
 };
 
@@ -901,8 +912,9 @@ pqn_status lcp_apply_host(pqn_ctx_impl& ctx, int n, const int32_t* pairs, const 
 }
 
 struct SolveCounters {
-  int mvp_hi = 0, mvp_lo = 0, gmres = 0;
-  double t_hi = 0.0, t_lo = 0.0;
+  int mvp[3] = {0, 0, 0};  // LCP products per fidelity (PQN_HIFI, PQN_LOFI, PQN_LOFI2)
+  double t[3] = {0.0, 0.0, 0.0};
+  int gmres = 0;
 };
 
 static PqnScal read_scal(pqn_ctx_impl& ctx, const PqnScal* d) {
@@ -957,6 +969,202 @@ static pqn_lcp_opts opts_or_default(const pqn_lcp_opts* o) {
   return r;
 }
 
+// Bi-PQN (Alg. 4) and its recursive form over up to three fidelities. Level d
+// minimises 1/2 z.H_d z + c.z over z >= 0 from the iterate in its engine, with
+// H_0 = A and, below, H_d = A_d + C_0 + ... + C_{d-1} (A_d the LCP product at
+// fidelity d, C_e the BFGS corrections U U^T - V V^T of the enclosing Bi-PQN
+// levels). A Bi-PQN level models H_d by A_{d+1} + C_0 + ... + C_d and solves
+// each subproblem one level down; the lowest level is Mono-PQN. With two
+// fidelities this is Alg. 4 as written (plus the model safeguard).
+struct BiSolver {
+  pqn_ctx_impl& ctx;
+  LcpState& st;
+  const pqn_lcp_opts& o;
+  SolveCounters& cnt;
+  int n, M, nf;     // nf fidelities: 2 = Bi-PQN, 3 = recursive Bi-PQN
+  double* MDx;      // M D x of the top level (may be null)
+  Level* lv[3];
+  Engine* eng[3];   // engine of each level (eng[nf - 1] runs Mono-PQN)
+  BiDev* bd[2];     // Bi-PQN state of each Bi-PQN level
+  int ssn = 0, in_iters = 0;
+  bool rejected = false;  // the top level finished as Mono-PQN on A
+
+  // out = H_d v; md (top level only) receives M D v.
+  void op(int d, const double* v, double* out, double* md) {
+    Timer t;
+    if (d == 0) {
+      lcp_mvp(ctx, *lv[0], n, st.pairs.p, v, out, md ? md : ctx.UO.p, &cnt.gmres);
+    } else {
+      const double* cur = bd[0]->tmp;
+      lcp_mvp(ctx, *lv[d], n, st.pairs.p, v, bd[0]->tmp, ctx.UO.p, &cnt.gmres);
+      for (int e = 0; e < d; ++e) {
+        double* dst = e == d - 1 ? out : bd[e + 1]->tmp;
+        hipLaunchKernelGGL(k_lowrank, dim3(1), dim3(kT), 0, ctx.stream, *bd[e], cur, v, dst);
+        cur = dst;
+      }
+      HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipStreamSynchronize(ctx.stream));
+    cnt.t[d] += t.ms();
+    cnt.mvp[d] += 1;
+  }
+
+  // (small host-to-device copies from the stack: the stream is synchronised before
+  // the source goes out of scope)
+  void set_counts(BiDev& B, int rc, int nlow) {
+    int h[2] = {rc, nlow};
+    HIPCHK(hipMemcpyAsync(B.cnt, h, 2 * sizeof(int), hipMemcpyHostToDevice, ctx.stream));
+    HIPCHK(hipStreamSynchronize(ctx.stream));
+  }
+
+  void init_scal(Engine& E, double tol_abs, double sigma) {
+    PqnScal z{};
+    z.tol_abs = tol_abs;
+    z.tol_rel = o.kkt_tol_rel;
+    z.sigma = sigma;
+    HIPCHK(hipMemcpyAsync(E.d.sc, &z, sizeof(PqnScal), hipMemcpyHostToDevice, ctx.stream));
+    HIPCHK(hipStreamSynchronize(ctx.stream));
+  }
+
+  struct Result {
+    int resets = 0;  // Alg. 2 edge cases met on H_d (own steps and fallback)
+    bool conv = false;
+    double kkt = 0.0;
+    int iters = 0;
+  };
+
+  // Mono-PQN on H_d from the iterate (x, H_d x) in its engine; level d - 1's stored
+  // secant pairs (npairs of them) warm the memory.
+  Result mono_level(int d, double tol, int k_lim, double& sigma, int npairs) {
+    Engine& E = *eng[d];
+    init_scal(E, tol, sigma);
+    if (npairs > 0)
+      hipLaunchKernelGGL(k_pqn_replay, dim3(1), dim3(kT), 0, ctx.stream, E.d, bd[d - 1]->Slow, bd[d - 1]->Ylow,
+                         npairs);
+    Result r;
+    run_mono(ctx, E, k_lim, o.j_max, [&](const double* v, double* out, double*) { op(d, v, out, nullptr); },
+             nullptr, M, &in_iters);
+    PqnScal s = read_scal(ctx, E.d.sc);
+    ssn += s.ssn_steps;
+    sigma = s.sigma;
+    r.resets = s.resets;
+    r.conv = s.conv || s.stationary;
+    r.kkt = s.e;
+    return r;
+  }
+
+  // Model safeguard: level d continues as Mono-PQN on H_d from its current
+  // iterate (keep_x) or from 0.
+  Result fallback(int d, double tol, int k_lim, bool keep_x, int k_done, int resets_before) {
+    Engine& E = *eng[d];
+    const bool top = d == 0;
+    if (top) rejected = true;
+    hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, E.d, keep_x ? 1 : 0, tol, o.kkt_tol_rel);
+    double* md = top ? MDx : nullptr;
+    if (md && !keep_x) HIPCHK(hipMemsetAsync(md, 0, 6 * (size_t)M * sizeof(double), ctx.stream));
+    int it = 0;
+    Result r;
+    r.conv = run_mono(
+        ctx, E, std::max(1, k_lim - k_done), o.j_max,
+        [&](const double* v, double* out, double* mdv) { op(d, v, out, top ? mdv : nullptr); }, md, M, &it);
+    PqnScal sm = read_scal(ctx, E.d.sc);
+    ssn += sm.ssn_steps;
+    r.kkt = sm.e;
+    r.iters = k_done + it;
+    r.resets = resets_before + sm.resets;
+    return r;
+  }
+
+  // Bi-PQN at level d < nf - 1. Top level: from x = 0 with Alg. 4's initial solve
+  // one level down. Nested: from the iterate the caller left in the engine
+  // (b = c, x, A x = H_d x), with A_{d+1} x paid by one product.
+  Result bi_level(int d, double tol, int k_lim, double& sigma) {
+    const bool top = d == 0;
+    Engine& E = *eng[d];
+    Engine& I = *eng[d + 1];
+    BiDev& B = *bd[d];
+    const bool mono_in = d + 1 == nf - 1;
+    auto solve_in = [&](double tol_in, double& sg, int npairs) {
+      return mono_in ? mono_level(d + 1, tol_in, o.k_max_inner, sg, npairs) : bi_level(d + 1, tol_in, o.k_max_inner, sg);
+    };
+    set_counts(B, 0, 0);
+    if (top) {
+      // initial solve from x^(-1) = 0 with tolerance 1e-2 * KKT(0), KKT(0) = |min(0, b)|
+      HIPCHK(hipMemcpyAsync(I.d.b, E.d.b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+      hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, I.d, 0, 0.0, 0.0);
+      hipLaunchKernelGGL(k_kkt_zero, dim3(1), dim3(kT), 0, ctx.stream, E.d.b, n, E.d.sc);
+      const double e0 = read_scal(ctx, E.d.sc).e;
+      Result r0 = solve_in(std::max(1e-12, 1e-2 * e0), sigma, 0);
+      if (r0.resets > 0) return fallback(d, tol, k_lim, false, 0, 0);
+      // x = x0, A^ x = its model product, stored pairs = its Mono-PQN memory
+      init_scal(E, tol, 0.0);
+      HIPCHK(hipMemcpyAsync(E.d.x, I.d.x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+      HIPCHK(hipMemcpyAsync(B.Alox, I.d.Ax, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+      int nlow = 0;
+      if (mono_in) {
+        nlow = std::min(read_scal(ctx, I.d.sc).r, kRmax);
+        if (nlow > 0) {
+          HIPCHK(hipMemcpyAsync(B.Slow, I.d.S, (size_t)nlow * n * sizeof(double), hipMemcpyDeviceToDevice,
+                                ctx.stream));
+          HIPCHK(hipMemcpyAsync(B.Ylow, I.d.Y, (size_t)nlow * n * sizeof(double), hipMemcpyDeviceToDevice,
+                                ctx.stream));
+        }
+      }
+      set_counts(B, 0, nlow);
+      hipLaunchKernelGGL(k_nonzero, dim3(1), dim3(kT), 0, ctx.stream, E.d.x, n, E.d.sc);
+      if (read_scal(ctx, E.d.sc).nonzero)
+        op(0, E.d.x, E.d.Ax, MDx);
+      else
+        HIPCHK(hipMemsetAsync(E.d.Ax, 0, (size_t)n * sizeof(double), ctx.stream));
+    } else {
+      init_scal(E, tol, 0.0);
+      hipLaunchKernelGGL(k_nonzero, dim3(1), dim3(kT), 0, ctx.stream, E.d.x, n, E.d.sc);
+      if (read_scal(ctx, E.d.sc).nonzero)
+        op(d + 1, E.d.x, B.Alox, nullptr);  // C_d is still empty: A_{d+1} x + C_0 x + ... + C_{d-1} x
+      else
+        HIPCHK(hipMemsetAsync(B.Alox, 0, (size_t)n * sizeof(double), ctx.stream));
+    }
+    Result r;
+    int k = 0;
+    for (k = 0; k < k_lim; ++k) {
+      hipLaunchKernelGGL(k_bi_prepare, dim3(1), dim3(kT), 0, ctx.stream, E.d, B, I.d);
+      PqnScal so = read_scal(ctx, E.d.sc);
+      if (!std::isfinite(so.e)) throw Error(PQN_ERR_NUMERIC, "non-finite KKT error in Bi-PQN");
+      r.kkt = so.e;
+      if (so.conv) {
+        r.conv = true;
+        break;
+      }
+      // subproblem one level down, from x, warm-started with the stored pairs
+      int hc[2];
+      HIPCHK(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+      HIPCHK(hipStreamSynchronize(ctx.stream));
+      Result ri = solve_in(std::max(1e-12, 1e-2 * so.e), sigma, hc[1]);
+      if (ri.resets > 0) return fallback(d, tol, k_lim, true, k, read_scal(ctx, E.d.sc).resets);
+      hipLaunchKernelGGL(k_bi_direction, dim3(1), dim3(kT), 0, ctx.stream, E.d, I.d);
+      if (read_scal(ctx, E.d.sc).stationary) {
+        r.conv = true;
+        break;
+      }
+      op(d, E.d.p, E.d.Ap, top && MDx ? st.MDp.p : nullptr);
+      hipLaunchKernelGGL(k_bi_accept, dim3(1), dim3(kT), 0, ctx.stream, E.d, B, I.d);
+      if (top && MDx)
+        hipLaunchKernelGGL(k_axpy_dev, dim3((6 * M + 255) / 256), dim3(256), 0, ctx.stream, MDx, st.MDp.p, E.d.sc,
+                           6 * M);
+      HIPCHK(hipGetLastError());
+    }
+    if (!r.conv) {
+      hipLaunchKernelGGL(k_bi_prepare, dim3(1), dim3(kT), 0, ctx.stream, E.d, B, I.d);
+      PqnScal sf = read_scal(ctx, E.d.sc);
+      r.conv = sf.conv;
+      r.kkt = sf.e;
+    }
+    r.iters = k;
+    r.resets = read_scal(ctx, E.d.sc).resets;
+    return r;
+  }
+};
+
 // Solve the LCP with b (device, length n) on the stored pairs. x ends in
 // st.outer.d.x; MDx (if non-null) receives M D x.
 static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opts& o, double* MDx,
@@ -965,15 +1173,12 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
   SolveCounters cnt;
   Level& hi = ctx.hi;
   const int M = ctx.M;
-  auto timed = [&](bool lo, auto&& f) {
-    Timer t;
-    f();
-    HIPCHK(hipStreamSynchronize(ctx.stream));
-    (lo ? cnt.t_lo : cnt.t_hi) += t.ms();
-    (lo ? cnt.mvp_lo : cnt.mvp_hi) += 1;
-  };
   auto mvp_hi = [&](const double* v, double* out, double* md) {
-    timed(false, [&] { lcp_mvp(ctx, hi, n, st.pairs.p, v, out, md ? md : ctx.UO.p, &cnt.gmres); });
+    Timer t;
+    lcp_mvp(ctx, hi, n, st.pairs.p, v, out, md ? md : ctx.UO.p, &cnt.gmres);
+    HIPCHK(hipStreamSynchronize(ctx.stream));
+    cnt.t[0] += t.ms();
+    cnt.mvp[0] += 1;
   };
   if (MDx) HIPCHK(hipMemsetAsync(MDx, 0, 6 * (size_t)M * sizeof(double), ctx.stream));
   bool conv = false;
@@ -1009,130 +1214,29 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
     }
     iters = k;
   } else {
-    Level& lo = ctx.lo;
-    Engine& I = st.inner;
-    Engine& O = st.outer;
-    BiDev& B = st.bi;
-    auto mvp_lo_plain = [&](const double* v, double* out, double*) {
-      timed(true, [&] { lcp_mvp(ctx, lo, n, st.pairs.p, v, out, ctx.UO.p, &cnt.gmres); });
-    };
-    // low-fidelity initial solve from x^(-1) = 0 with tolerance 1e-2 * KKT(0), KKT(0) = |min(0, b)|
-    HIPCHK(hipMemcpyAsync(I.d.b, O.d.b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
-    hipLaunchKernelGGL(k_kkt_zero, dim3(1), dim3(kT), 0, ctx.stream, O.d.b, n, O.d.sc);
-    const double e0 = read_scal(ctx, O.d.sc).e;
-    PqnScal si{};
-    si.tol_abs = std::max(1e-12, 1e-2 * e0);
-    si.tol_rel = o.kkt_tol_rel;
-    HIPCHK(hipMemcpyAsync(I.d.sc, &si, sizeof(PqnScal), hipMemcpyHostToDevice, ctx.stream));
-    hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, I.d, 0, si.tol_abs, si.tol_rel);
-    int in_iters = 0;
-    run_mono(ctx, I, o.k_max_inner, o.j_max, mvp_lo_plain, nullptr, M, &in_iters);
-    PqnScal sI = read_scal(ctx, I.d.sc);
-    ssn += sI.ssn_steps;
-    double sigma_in = sI.sigma;   // metric scale carried into every subproblem
-    // Model safeguard: a low-fidelity solve that meets non-positive curvature or no
-    // descent (the Alg. 2 edge cases) shows that the model is not positive definite;
-    // the solve then continues as Mono-PQN on A from the current iterate.
-    auto finish_mono = [&](bool keep_x, int k_done) {
-      rejected = true;
-      hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, O.d, keep_x ? 1 : 0, o.kkt_tol_abs,
-                         o.kkt_tol_rel);
-      if (MDx && !keep_x) HIPCHK(hipMemsetAsync(MDx, 0, 6 * (size_t)M * sizeof(double), ctx.stream));
-      int it = 0;
-      conv = run_mono(ctx, O, std::max(1, o.k_max - k_done), o.j_max, mvp_hi, MDx, M, &it);
-      PqnScal sm = read_scal(ctx, O.d.sc);
-      ssn += sm.ssn_steps;
-      kkt = sm.e;
-      iters = k_done + it;
-    };
-    if (sI.resets > 0) finish_mono(false, 0);
-    if (!rejected) {
-      // outer state: x = x0, A^ x = inner A x, pairs = inner memory, no corrections
-      PqnScal so{};
-      so.tol_abs = o.kkt_tol_abs;
-      so.tol_rel = o.kkt_tol_rel;
-      HIPCHK(hipMemcpyAsync(O.d.sc, &so, sizeof(PqnScal), hipMemcpyHostToDevice, ctx.stream));
-      HIPCHK(hipMemcpyAsync(O.d.x, I.d.x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
-      HIPCHK(hipMemcpyAsync(B.Alox, I.d.Ax, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
-      int nlow = std::min(sI.r, kRmax);
-      if (nlow > 0) {
-        HIPCHK(hipMemcpyAsync(B.Slow, I.d.S, (size_t)nlow * n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
-        HIPCHK(hipMemcpyAsync(B.Ylow, I.d.Y, (size_t)nlow * n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
-      }
-      int hcnt[2] = {0, nlow};
-      HIPCHK(hipMemcpyAsync(B.cnt, hcnt, 2 * sizeof(int), hipMemcpyHostToDevice, ctx.stream));
-      hipLaunchKernelGGL(k_nonzero, dim3(1), dim3(kT), 0, ctx.stream, O.d.x, n, O.d.sc);
-      PqnScal snz = read_scal(ctx, O.d.sc);
-      if (snz.nonzero) {
-        mvp_hi(O.d.x, O.d.Ax, MDx);
-      } else {
-        HIPCHK(hipMemsetAsync(O.d.Ax, 0, (size_t)n * sizeof(double), ctx.stream));
-      }
-      auto mvp_B = [&](const double* v, double* out, double*) {
-        timed(true, [&] { lcp_mvp(ctx, lo, n, st.pairs.p, v, B.tmp, ctx.UO.p, &cnt.gmres); });
-        hipLaunchKernelGGL(k_lowrank, dim3(1), dim3(kT), 0, ctx.stream, B, B.tmp, v, out);
-      };
-      int k = 0;
-      for (k = 0; k < o.k_max; ++k) {
-        hipLaunchKernelGGL(k_bi_prepare, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
-        PqnScal so2 = read_scal(ctx, O.d.sc);
-        if (!std::isfinite(so2.e)) throw Error(PQN_ERR_NUMERIC, "non-finite KKT error in Bi-PQN");
-        kkt = so2.e;
-        if (so2.conv) {
-          conv = true;
-          break;
-        }
-        // subproblem: Mono-PQN on B^(k) from x, warm-started with the stored pairs
-        int hc[2];
-        HIPCHK(hipMemcpyAsync(hc, B.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
-        HIPCHK(hipStreamSynchronize(ctx.stream));
-        PqnScal sin{};
-        sin.tol_abs = std::max(1e-12, 1e-2 * so2.e);
-        sin.tol_rel = o.kkt_tol_rel;
-        sin.ssn_steps = 0;
-        sin.sigma = sigma_in;
-        HIPCHK(hipMemcpyAsync(I.d.sc, &sin, sizeof(PqnScal), hipMemcpyHostToDevice, ctx.stream));
-        hipLaunchKernelGGL(k_pqn_replay, dim3(1), dim3(kT), 0, ctx.stream, I.d, B.Slow, B.Ylow, hc[1]);
-        run_mono(ctx, I, o.k_max_inner, o.j_max, mvp_B, nullptr, M, &in_iters);
-        PqnScal sI2 = read_scal(ctx, I.d.sc);
-        ssn += sI2.ssn_steps;
-        sigma_in = sI2.sigma;
-        if (sI2.resets > 0) {
-          finish_mono(true, k);
-          break;
-        }
-        hipLaunchKernelGGL(k_bi_direction, dim3(1), dim3(kT), 0, ctx.stream, O.d, I.d);
-        PqnScal sd = read_scal(ctx, O.d.sc);
-        if (sd.stationary) {
-          conv = true;
-          break;
-        }
-        mvp_hi(O.d.p, O.d.Ap, MDx ? st.MDp.p : nullptr);
-        hipLaunchKernelGGL(k_bi_accept, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
-        if (MDx)
-          hipLaunchKernelGGL(k_axpy_dev, dim3((6 * M + 255) / 256), dim3(256), 0, ctx.stream, MDx, st.MDp.p, O.d.sc,
-                             6 * M);
-        HIPCHK(hipGetLastError());
-      }
-      if (!rejected) {
-        if (!conv) {
-          hipLaunchKernelGGL(k_bi_prepare, dim3(1), dim3(kT), 0, ctx.stream, O.d, B, I.d);
-          PqnScal sf = read_scal(ctx, O.d.sc);
-          conv = sf.conv;
-          kkt = sf.e;
-        }
-        iters = k;
-      }
-    }  // !rejected after the initial low-fidelity solve
+    const bool rec = solver == PQN_BI_REC;
+    BiSolver bs{ctx, st, o, cnt, n, M, rec ? 3 : 2, MDx, {&ctx.hi, &ctx.lo, rec ? &ctx.lo2 : nullptr},
+                {&st.outer, rec ? &st.mid : &st.inner, rec ? &st.inner : nullptr}, {&st.bi, &st.bi2}};
+    double sigma = 0.0;  // metric scale of the Mono-PQN solves (0 = set by their first step)
+    BiSolver::Result r = bs.bi_level(0, o.kkt_tol_abs, o.k_max, sigma);
+    conv = r.conv;
+    kkt = r.kkt;
+    iters = r.iters;
+    ssn = bs.ssn;
+    rejected = bs.rejected;
   }
   HIPCHK(hipStreamSynchronize(ctx.stream));
   if (stats) {
     stats->iters = iters;
-    stats->mvp_hi = cnt.mvp_hi;
-    stats->mvp_lo = cnt.mvp_lo;
-    const double ratio = (cnt.mvp_lo > 0 && cnt.mvp_hi > 0) ? (cnt.t_lo / cnt.mvp_lo) / (cnt.t_hi / cnt.mvp_hi) : 0.0;
-    stats->lo_hi_cost_ratio = ratio;
-    stats->emvp = cnt.mvp_hi + cnt.mvp_lo * ratio;
+    stats->mvp_hi = cnt.mvp[0];
+    stats->mvp_lo = cnt.mvp[1];
+    stats->mvp_lo2 = cnt.mvp[2];
+    auto ratio = [&](int f) {
+      return (cnt.mvp[f] > 0 && cnt.mvp[0] > 0) ? (cnt.t[f] / cnt.mvp[f]) / (cnt.t[0] / cnt.mvp[0]) : 0.0;
+    };
+    stats->lo_hi_cost_ratio = ratio(1);
+    stats->lo2_hi_cost_ratio = ratio(2);
+    stats->emvp = cnt.mvp[0] + cnt.mvp[1] * ratio(1) + cnt.mvp[2] * ratio(2);
     stats->kkt_abs = kkt;
     stats->converged = conv ? 1 : 0;
     stats->ssn_steps = ssn;

@@ -185,3 +185,84 @@ def test_warm_started_steps_match_oracle(cases):
     say('warm steps vs oracle, nc iterations', its)
     assert np.abs(c2 - c).max() < 1e-10
     assert np.abs(ax2 - ax).max() < 1e-10
+
+
+def _mid_operator(cs):
+    gm = bie.Geometry(cs['c'], 1.0, 6, 12)
+    Am = bie.dense_operator(gm)
+    return gm, Am, lcp.lcp_operator(lambda F: bie.mobility_apply(gm, F, dense=Am), cs['c'], cs['pairs'])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_bi_pqn_rec_matches_oracle(cases, prec):
+    """Recursive Bi-PQN over the 8x16, 6x12 and 4x8 grids: the device solution equals the
+    brute-force LCP solution, the product at the second low fidelity equals the oracle's
+    operator, and in FP64 the products per fidelity match the oracle's recursion (+-1:
+    inner tolerances are decided on rounding-level KKT values)."""
+    tol = 1e-10 if prec == 'fp64' else 1e-6
+    kkt = (1e-12, 1e-15) if prec == 'fp64' else (1e-9, 1e-9)
+    for cs in cases:
+        gm, Am, Amid = _mid_operator(cs)
+        Aop = lcp.lcp_operator(lambda F: bie.mobility_apply(cs['g'], F, dense=cs['A']), cs['c'], cs['pairs'])
+        Alo = lcp.lcp_operator(lambda F: bie.mobility_apply(cs['glo'], F, dense=cs['Alo']), cs['c'], cs['pairs'])
+        with binding.Context(cs['c'], None, 8, 16, lo=(6, 12), lo2=(4, 8), gmres_tol=1e-13,
+                             precision=prec) as ctx:
+            v = np.random.default_rng(3).uniform(0, 1, cs['pairs'].shape[0])
+            y2 = ctx.lcp_apply(cs['pairs'], v, fidelity=binding.PQN_LOFI2)
+            y1 = ctx.lcp_apply(cs['pairs'], v, fidelity=binding.PQN_LOFI)
+            ptol = 1e-10 if prec == 'fp64' else 1e-6
+            assert np.abs(y2 - Alo(v)).max() < ptol * np.abs(Alo(v)).max()
+            assert np.abs(y1 - Amid(v)).max() < ptol * np.abs(Amid(v)).max()
+            for name, b in (('real', cs['b_real']), ('planted', cs['b_pl'])):
+                say('birec', prec, name)
+                xbf = lcp.brute_force_lcp(cs['Ad'], b)
+                x, st = ctx.lcp_solve(cs['pairs'], b, 'birec', tol_abs=kkt[0], tol_rel=kkt[1], k_max=400)
+                assert st['converged'] == 1, st
+                assert x.min() >= 0.0
+                assert np.abs(x - xbf).max() <= tol * max(np.abs(xbf).max(), 1e-300), (x, xbf, st)
+                if prec == 'fp64':
+                    _, _, so = lcp.bi_pqn_rec([Aop, Amid, Alo], b, tol_abs=kkt[0], tol_rel=kkt[1], k_max=400)
+                    say('  device', st['mvp_hi'], st['mvp_lo'], st['mvp_lo2'], 'oracle', so['mvp'])
+                    assert abs(st['mvp_hi'] - so['mvp'][0]) <= 1
+                    assert abs(st['mvp_lo'] - so['mvp'][1]) <= 2
+                    assert abs(st['mvp_lo2'] - so['mvp'][2]) <= 4
+                    assert st['model_rejected'] == int(so['fallback'])
+                if np.any(xbf > 0):
+                    assert st['mvp_lo'] >= 1 and st['mvp_lo2'] >= 1
+
+
+def test_bi_pqn_rec_counts_match_oracle_default_tolerance(cases):
+    """Same recursion at the default KKT tolerance (1e-8): per-fidelity product counts
+    agree with the oracle's."""
+    for cs in cases:
+        gm, Am, Amid = _mid_operator(cs)
+        Aop = lcp.lcp_operator(lambda F: bie.mobility_apply(cs['g'], F, dense=cs['A']), cs['c'], cs['pairs'])
+        Alo = lcp.lcp_operator(lambda F: bie.mobility_apply(cs['glo'], F, dense=cs['Alo']), cs['c'], cs['pairs'])
+        b = cs['b_pl']
+        _, _, so = lcp.bi_pqn_rec([Aop, Amid, Alo], b)
+        with binding.Context(cs['c'], None, 8, 16, lo=(6, 12), lo2=(4, 8), gmres_tol=1e-13) as ctx:
+            _, st = ctx.lcp_solve(cs['pairs'], b, 'birec')
+        say('birec counts', st['mvp_hi'], st['mvp_lo'], st['mvp_lo2'], 'oracle', so['mvp'])
+        assert st['mvp_hi'] == so['mvp'][0]
+        assert abs(st['mvp_lo'] - so['mvp'][1]) <= 1
+        assert abs(st['mvp_lo2'] - so['mvp'][2]) <= 2
+
+
+def test_bi_pqn_rec_step_and_errors(cases):
+    """A time step with recursive Bi-PQN reaches the oracle's configuration (the LCP
+    solution is unique, whichever solver finds it); without a second low-fidelity grid
+    the solver is refused."""
+    cs = cases[0]
+    c1, ax1, info = dynamics.step(cs['c'], cs['axes'], 1.0, (8, 16), (4, 8), 0.1, 0.1, 1.0, solver='mono',
+                                  lcp_opts=dict(tol_abs=1e-12, tol_rel=1e-15), tol_gmres=1e-13)
+    with binding.Context(cs['c'], cs['axes'], 8, 16, lo=(6, 12), lo2=(4, 8), gmres_tol=1e-13) as ctx:
+        st = ctx.step(0.1, 0.1, 'birec', tol_abs=1e-12, tol_rel=1e-15)
+        c2, ax2 = ctx.get_state()
+    assert st['n_contacts'] == info['pairs'].shape[0]
+    assert np.abs(c2 - c1).max() < 1e-10
+    assert np.abs(ax2 - ax1).max() < 1e-10
+    with binding.Context(cs['c'], None, 8, 16, lo=(4, 8)) as ctx:
+        with pytest.raises(binding.PqnError):
+            ctx.lcp_solve(cs['pairs'], cs['b_pl'], 'birec')
+        with pytest.raises(binding.PqnError):
+            ctx.lcp_apply(cs['pairs'], np.ones(cs['pairs'].shape[0]), fidelity=binding.PQN_LOFI2)
