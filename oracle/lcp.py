@@ -494,8 +494,11 @@ def bi_pqn_rec(ops, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_m
       * The top level keeps Alg. 4's initial solve from x = 0 (itself solved
         one level down). A nested level starts at the caller's iterate x with
         H_d x known and pays one product of ops[d+1] for L_d x (none if x = 0).
-      * Secant pairs warm-start only a Mono-PQN subproblem (the lowest level);
-        a nested Bi-PQN level starts with no correction.
+      * Secant pairs warm-start only a Mono-PQN subproblem (the lowest level).
+        A nested Bi-PQN level keeps its correction C_d from one call to the
+        next: H_d - L_d = ops[d] - ops[d+1] does not involve the enclosing
+        corrections, so the secant information C_d holds stays valid when
+        they change (a memory reset at level d clears it).
       * Tolerances: 1e-2 x the level's current KKT error (floor 1e-12), at most
         k_max_inner outer steps per nested level and products per Mono-PQN.
       * Model safeguard per level, as in bi_pqn: when the subproblem solve
@@ -511,6 +514,7 @@ def bi_pqn_rec(ops, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_m
     if nf < 2:
         raise ValueError('recursive Bi-PQN needs at least two fidelities')
     cnt = [0] * nf
+    kept = {}   # correction of each nested Bi-PQN level, kept across its calls
 
     def op(d, corrs):
         def H(v):
@@ -551,7 +555,7 @@ def bi_pqn_rec(ops, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_m
         else:
             Lx = L(x) if np.any(x != 0.0) else np.zeros(n)
             S, Y = [], []
-        corr = QuasiNewton(n)
+        corr = QuasiNewton(n) if top else kept.setdefault(d, QuasiNewton(n))
         e_prev = None
         conv = False
         hist = []
@@ -583,6 +587,8 @@ def bi_pqn_rec(ops, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_m
             if reset:
                 resets += 1
                 corr = QuasiNewton(n)
+                if not top:
+                    kept[d] = corr
                 Shat, Yhat = [], []
                 Bs = Ls.copy()
             nu = len(corr.U)

@@ -989,16 +989,18 @@ struct BiSolver {
   int ssn = 0, in_iters = 0;
   bool rejected = false;  // the top level finished as Mono-PQN on A
 
-  // out = H_d v; md (top level only) receives M D v.
-  void op(int d, const double* v, double* out, double* md) {
+  // out = A_d v + C_0 v + ... + C_{nc-1} v (nc = d: H_d v); md (top level only)
+  // receives M D v.
+  void op(int d, const double* v, double* out, double* md, int nc = -1) {
     Timer t;
-    if (d == 0) {
-      lcp_mvp(ctx, *lv[0], n, st.pairs.p, v, out, md ? md : ctx.UO.p, &cnt.gmres);
+    if (nc < 0) nc = d;
+    if (nc == 0) {
+      lcp_mvp(ctx, *lv[d], n, st.pairs.p, v, out, md ? md : ctx.UO.p, &cnt.gmres);
     } else {
       const double* cur = bd[0]->tmp;
       lcp_mvp(ctx, *lv[d], n, st.pairs.p, v, bd[0]->tmp, ctx.UO.p, &cnt.gmres);
-      for (int e = 0; e < d; ++e) {
-        double* dst = e == d - 1 ? out : bd[e + 1]->tmp;
+      for (int e = 0; e < nc; ++e) {
+        double* dst = e == nc - 1 ? out : bd[e + 1]->tmp;
         hipLaunchKernelGGL(k_lowrank, dim3(1), dim3(kT), 0, ctx.stream, *bd[e], cur, v, dst);
         cur = dst;
       }
@@ -1014,6 +1016,11 @@ struct BiSolver {
   void set_counts(BiDev& B, int rc, int nlow) {
     int h[2] = {rc, nlow};
     HIPCHK(hipMemcpyAsync(B.cnt, h, 2 * sizeof(int), hipMemcpyHostToDevice, ctx.stream));
+    HIPCHK(hipStreamSynchronize(ctx.stream));
+  }
+
+  void set_pair_count(BiDev& B, int nlow) {
+    HIPCHK(hipMemcpyAsync(B.cnt + 1, &nlow, sizeof(int), hipMemcpyHostToDevice, ctx.stream));
     HIPCHK(hipStreamSynchronize(ctx.stream));
   }
 
@@ -1077,7 +1084,10 @@ struct BiSolver {
 
   // Bi-PQN at level d < nf - 1. Top level: from x = 0 with Alg. 4's initial solve
   // one level down. Nested: from the iterate the caller left in the engine
-  // (b = c, x, A x = H_d x), with A_{d+1} x paid by one product.
+  // (b = c, x, A x = H_d x), with A_{d+1} x paid by one product, and with the
+  // correction C_d its previous calls left (H_d - (A_{d+1} + C_0 + ... + C_{d-1})
+  // = A_d - A_{d+1} does not depend on the enclosing corrections, so it stays
+  // valid; the top level clears it once per solve).
   Result bi_level(int d, double tol, int k_lim, double& sigma) {
     const bool top = d == 0;
     Engine& E = *eng[d];
@@ -1087,8 +1097,8 @@ struct BiSolver {
     auto solve_in = [&](double tol_in, double& sg, int npairs) {
       return mono_in ? mono_level(d + 1, tol_in, o.k_max_inner, sg, npairs) : bi_level(d + 1, tol_in, o.k_max_inner, sg);
     };
-    set_counts(B, 0, 0);
     if (top) {
+      for (int l = 0; l < nf - 1; ++l) set_counts(*bd[l], 0, 0);
       // initial solve from x^(-1) = 0 with tolerance 1e-2 * KKT(0), KKT(0) = |min(0, b)|
       HIPCHK(hipMemcpyAsync(I.d.b, E.d.b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
       hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, I.d, 0, 0.0, 0.0);
@@ -1118,9 +1128,10 @@ struct BiSolver {
         HIPCHK(hipMemsetAsync(E.d.Ax, 0, (size_t)n * sizeof(double), ctx.stream));
     } else {
       init_scal(E, tol, 0.0);
+      set_pair_count(B, 0);
       hipLaunchKernelGGL(k_nonzero, dim3(1), dim3(kT), 0, ctx.stream, E.d.x, n, E.d.sc);
       if (read_scal(ctx, E.d.sc).nonzero)
-        op(d + 1, E.d.x, B.Alox, nullptr);  // C_d is still empty: A_{d+1} x + C_0 x + ... + C_{d-1} x
+        op(d + 1, E.d.x, B.Alox, nullptr, d);  // A_{d+1} x + C_0 x + ... + C_{d-1} x
       else
         HIPCHK(hipMemsetAsync(B.Alox, 0, (size_t)n * sizeof(double), ctx.stream));
     }
