@@ -206,12 +206,15 @@ def main():
         t2 = time.perf_counter()
         x3, lb = cm.lcp_solve(pairs, b, 'bb')
         # the other fidelity axis of the method: same grid, GMRES tolerance 1e-3 for the model
-        with binding.Context(c, None, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3, precision='mixed',
-                             tpt=args.tpt, far_chunks=args.chunks, far_split=args.split,
-                             stream=stream.cuda_stream, tune_K=1) as cb:
+        # and recursive Bi-PQN over three fidelities: that model, then the coarse grid at 1e-3
+        with binding.Context(c, None, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3, lo2=w['lo'],
+                             gmres_tol_lo2=1e-3, precision='mixed', tpt=args.tpt, far_chunks=args.chunks,
+                             far_split=args.split, stream=stream.cuda_stream, tune_K=1) as cb:
             t3 = time.perf_counter()
             x4, lt = cb.lcp_solve(pairs, b, 'bi')
             t4 = time.perf_counter()
+            x5, lr = cb.lcp_solve(pairs, b, 'birec')
+            t5 = time.perf_counter()
         lcp_info = dict(n_contacts=int(pairs.shape[0]), planted_active=int((xs > 0).sum()),
                         bi=dict(sec=round(t1 - t0, 3), mvp_hi=ls['mvp_hi'], mvp_lo=ls['mvp_lo'],
                                 emvp=round(ls['emvp'], 2), lo_hi_cost_ratio=round(ls['lo_hi_cost_ratio'], 4),
@@ -222,7 +225,14 @@ def main():
                         bi_tol_fidelity=dict(lo=f'{nt}x{nph} at GMRES 1e-3', sec=round(t4 - t3, 3),
                                              mvp_hi=lt['mvp_hi'], mvp_lo=lt['mvp_lo'], emvp=round(lt['emvp'], 2),
                                              lo_hi_cost_ratio=round(lt['lo_hi_cost_ratio'], 4),
-                                             x_rel_err=float(np.abs(x4 - xs).max() / np.abs(xs).max())))
+                                             x_rel_err=float(np.abs(x4 - xs).max() / np.abs(xs).max())),
+                        bi_recursive=dict(fidelities=f'{nt}x{nph} at 1e-8, {nt}x{nph} at 1e-3, '
+                                                     f'{w["lo"][0]}x{w["lo"][1]} at 1e-3',
+                                          sec=round(t5 - t4, 3), mvp_hi=lr['mvp_hi'], mvp_lo=lr['mvp_lo'],
+                                          mvp_lo2=lr['mvp_lo2'], emvp=round(lr['emvp'], 2),
+                                          cost_ratios=[round(lr['lo_hi_cost_ratio'], 4),
+                                                       round(lr['lo2_hi_cost_ratio'], 4)],
+                                          x_rel_err=float(np.abs(x5 - xs).max() / np.abs(xs).max())))
         log('lcp', lcp_info)
     cm_layout = cm.far_shape
     cm.close()
@@ -347,9 +357,10 @@ def main():
 def lcp_table(binding, inputs, stream):
     """Products per planted LCP (about half the contacts active, KKT 1e-8) for the solvers of
     the method on the contact sets (gap < 0.1) of three workloads, mixed precision: BB-PGD,
-    Mono-PQN, Bi-PQN with the coarse grid as low fidelity, and Bi-PQN with the same grid at
-    GMRES tolerance 1e-3 as low fidelity. E-MVP = high + low x (low-fidelity product time /
-    high-fidelity product time), both measured."""
+    Mono-PQN, Bi-PQN with the coarse grid as low fidelity, Bi-PQN with the same grid at
+    GMRES tolerance 1e-3 as low fidelity, and recursive Bi-PQN over both (same grid at 1e-3,
+    then the coarse grid at 1e-3). E-MVP = high + low x (low-fidelity product time /
+    high-fidelity product time) summed over the fidelities, all measured."""
     import torch
     rows = []
     for name in ('lattice27_contacts', 'packing64', 'rsa216'):
@@ -373,20 +384,24 @@ def lcp_table(binding, inputs, stream):
                                        sec=round(time.perf_counter() - t0, 3), conv=st['converged'],
                                        x_err=float(np.abs(x - xs).max() / np.abs(xs).max()))
             with binding.Context(c, None, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3,
-                                 precision='mixed', stream=stream.cuda_stream, tune_K=1) as ctx:
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                x, st = ctx.lcp_solve(pairs, b, 'bi')
-                row['bi_tol'] = dict(hi=st['mvp_hi'], lo=st['mvp_lo'], emvp=round(st['emvp'], 2),
-                                     ratio=round(st['lo_hi_cost_ratio'], 3), sec=round(time.perf_counter() - t0, 3),
-                                     conv=st['converged'], x_err=float(np.abs(x - xs).max() / np.abs(xs).max()))
+                                 lo2=w['lo'], gmres_tol_lo2=1e-3, precision='mixed', stream=stream.cuda_stream,
+                                 tune_K=1) as ctx:
+                for key, solver in (('bi_tol', 'bi'), ('birec', 'birec')):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    x, st = ctx.lcp_solve(pairs, b, solver)
+                    row[key] = dict(hi=st['mvp_hi'], lo=st['mvp_lo'], lo2=st['mvp_lo2'], emvp=round(st['emvp'], 2),
+                                    ratio=round(st['lo_hi_cost_ratio'], 3), ratio2=round(st['lo2_hi_cost_ratio'], 4),
+                                    sec=round(time.perf_counter() - t0, 3), conv=st['converged'],
+                                    x_err=float(np.abs(x - xs).max() / np.abs(xs).max()))
             print('[lcp-table]', row, file=sys.stderr, flush=True)
             rows.append(row)
     med = {}
     for name in ('lattice27_contacts', 'packing64', 'rsa216'):
         rs = [r for r in rows if r['workload'] == name]
         if rs:
-            med[name] = {k: float(np.median([r[k]['emvp'] for r in rs])) for k in ('bb', 'mono', 'bi', 'bi_tol')}
+            med[name] = {k: float(np.median([r[k]['emvp'] for r in rs]))
+                         for k in ('bb', 'mono', 'bi', 'bi_tol', 'birec')}
     return dict(table='planted LCPs, mixed precision, KKT 1e-8', rows=rows, median_emvp=med)
 
 
