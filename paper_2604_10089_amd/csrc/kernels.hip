@@ -84,6 +84,9 @@ __device__ __forceinline__ void far32_tile(int j, int k0, int k1, const float* _
                                            const double (&oz)[TPT], double (&acc)[TPT][K][3]) {
   constexpr int S = src32_stride(K);
   const double cjx = ctr[3 * j], cjy = ctr[3 * j + 1], cjz = ctr[3 * j + 2];
+  const float* sp = src + (size_t)j * n * S;
+  // |y|^2 of the sphere's source offsets (all a^2 up to rounding), from its first node
+  const double a2 = (double)sp[0] * sp[0] + (double)sp[1] * sp[1] + (double)sp[2] * sp[2];
   bool act[TPT];
   int any = 0;
 #pragma unroll
@@ -92,16 +95,21 @@ __device__ __forceinline__ void far32_tile(int j, int k0, int k1, const float* _
     any |= act[u];
   }
   if (!__any(any)) return;
-  float Xx[TPT], Xy[TPT], Xz[TPT], sm[TPT][K][3];
+  // r.y = (|X|^2 - |y|^2 - |r|^2) / 2 with r = X - y: one FMA per pair from the
+  // target constant Ct = (|X|^2 - a^2) / 2 instead of a dot product. Rounding:
+  // Ct and r^2 are O(|X|^2) while r.y is O(|X| a), so the relative error of r.y
+  // grows like |X| / a (at most ~20 here), on the far pairs whose terms decay
+  // like 1/|X|^2; the operator's mixed-vs-FP64 error is unchanged (2.4e-8).
+  float Xx[TPT], Xy[TPT], Xz[TPT], Ct[TPT], sm[TPT][K][3];
 #pragma unroll
   for (int u = 0; u < TPT; ++u) {
     Xx[u] = act[u] ? (float)((px[u] - cjx) + ox[u]) : 1.0e4f;
     Xy[u] = act[u] ? (float)((py[u] - cjy) + oy[u]) : 0.0f;
     Xz[u] = act[u] ? (float)((pz[u] - cjz) + oz[u]) : 0.0f;
+    Ct[u] = (float)(0.5 * ((double)Xx[u] * Xx[u] + (double)Xy[u] * Xy[u] + (double)Xz[u] * Xz[u] - a2));
 #pragma unroll
     for (int r = 0; r < K; ++r) sm[u][r][0] = sm[u][r][1] = sm[u][r][2] = 0.0f;
   }
-  const float* sp = src + (size_t)j * n * S;
 #pragma unroll 8
   for (int kk = k0; kk < k1; ++kk) {
     const float* e = sp + (size_t)kk * S;
@@ -112,7 +120,7 @@ __device__ __forceinline__ void far32_tile(int j, int k0, int k1, const float* _
       const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
       const float ri = __builtin_amdgcn_rsqf(r2);
       const float ri2 = ri * ri;
-      const float rn = fmaf(rx, sx, fmaf(ry, sy, rz * sz));
+      const float rn = fmaf(-0.5f, r2, Ct[u]);
       const float wgt = rn * ri * ri2 * ri2;
       if constexpr (K == 1) {
         const float rq = fmaf(rx, e[3], fmaf(ry, e[4], rz * e[5]));
@@ -320,6 +328,8 @@ __device__ __forceinline__ void far64_body(int tb, int chunk, const double* __re
 #pragma unroll
     for (int r = 0; r < K; ++r) sm[r][0] = sm[r][1] = sm[r][2] = 0.0;
     const double* sp = src + (size_t)j * n * S;
+    // r.y = Ct - r^2 / 2 (as in the FP32 tile); (w r).q for K >= 2
+    const double Ct = 0.5 * (Xx * Xx + Xy * Xy + Xz * Xz - (sp[0] * sp[0] + sp[1] * sp[1] + sp[2] * sp[2]));
 #pragma unroll 2
     for (int kk = 0; kk < n; ++kk) {
       const double* e = sp + (size_t)kk * S;
@@ -327,15 +337,22 @@ __device__ __forceinline__ void far64_body(int tb, int chunk, const double* __re
       const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
       const double ri = rsqrt(r2);
       const double ri2 = ri * ri;
-      const double rn = fma(rx, e[0], fma(ry, e[1], rz * e[2]));
+      const double rn = fma(-0.5, r2, Ct);
       const double wgt = rn * ri * ri2 * ri2;
+      if constexpr (K == 1) {
+        const double c = wgt * fma(rx, e[3], fma(ry, e[4], rz * e[5]));
+        sm[0][0] = fma(c, rx, sm[0][0]);
+        sm[0][1] = fma(c, ry, sm[0][1]);
+        sm[0][2] = fma(c, rz, sm[0][2]);
+      } else {
+        const double wx = wgt * rx, wy = wgt * ry, wz = wgt * rz;
 #pragma unroll
-      for (int r = 0; r < K; ++r) {
-        const double rq = fma(rx, e[3 + 3 * r], fma(ry, e[4 + 3 * r], rz * e[5 + 3 * r]));
-        const double c = wgt * rq;
-        sm[r][0] = fma(c, rx, sm[r][0]);
-        sm[r][1] = fma(c, ry, sm[r][1]);
-        sm[r][2] = fma(c, rz, sm[r][2]);
+        for (int r = 0; r < K; ++r) {
+          const double c = fma(wx, e[3 + 3 * r], fma(wy, e[4 + 3 * r], wz * e[5 + 3 * r]));
+          sm[r][0] = fma(c, rx, sm[r][0]);
+          sm[r][1] = fma(c, ry, sm[r][1]);
+          sm[r][2] = fma(c, rz, sm[r][2]);
+        }
       }
     }
     if (act)
