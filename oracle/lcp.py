@@ -303,7 +303,7 @@ def bb_pgd(Aop, b, x0=None, tau0=1.0, k_max=200, tol_abs=1e-8, tol_rel=1e-8):
 
 
 def mono_pqn(Aop, b, x0=None, Ax0=None, k_max=100, tol_abs=1e-8, tol_rel=1e-8,
-             pairs=(), j_max=50, sigma=None):
+             pairs=(), j_max=50, sigma=None, ssn_tol=1e-14):
     """Mono-PQN (Alg. 1) with the SSN prox (Alg. 3) and eta* (Alg. 2).
 
     One product A[p] per iteration; A x is carried by the recurrence
@@ -343,7 +343,7 @@ def mono_pqn(Aop, b, x0=None, Ax0=None, k_max=100, tol_abs=1e-8, tol_rel=1e-8,
         xt = x - qn.H_apply(g)
         Um = np.array(qn.U).T if qn.U else None
         Vm = np.array(qn.V).T if qn.V else None
-        xh, nj, _ = prox_ssn(xt, Um, Vm, d=np.full(n, qn.sigma), jmax=j_max)
+        xh, nj, _ = prox_ssn(xt, Um, Vm, d=np.full(n, qn.sigma), jmax=j_max, eps_rel=ssn_tol)
         ssn_total += nj
         p = xh - x
         if not np.any(p != 0.0):
@@ -380,7 +380,8 @@ def secant_transfer(S, Y, u, v):
     return list(S), [yh + u * (u @ sh) - v * (v @ sh) for sh, yh in zip(S, Y)]
 
 
-def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_max=50):
+def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_max=50, x0=None,
+           ssn_tol=1e-14):
     """Bi-PQN (Alg. 4, App. E).
 
     x^(0) from Mono-PQN on the low-fidelity matrix; then per outer step the
@@ -398,20 +399,27 @@ def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_
     products of both phases are counted.
     """
     n = b.size
-    x = np.zeros(n)
-    tol0 = max(1e-12, 1e-2 * kkt_error(x, b))
-    x, Alox, st0 = mono_pqn(Alo, b, x, np.zeros(n), k_max=k_max_inner,
-                            tol_abs=tol0, tol_rel=tol_rel, j_max=j_max)
-    mvp_lo = st0['mvp']
+    # x^(-1): the caller's guess projected on x >= 0 (0 if none); the initial solve's
+    # tolerance is 1e-2 x the low-fidelity KKT error there (|min(0, b)| at 0)
+    xs = np.zeros(n) if x0 is None else np.maximum(np.asarray(x0, dtype=np.float64), 0.0)
+    mvp_lo = 0
+    Alox = np.zeros(n)
+    if np.any(xs != 0.0):
+        Alox = Alo(xs)
+        mvp_lo += 1
+    tol0 = max(1e-12, 1e-2 * kkt_error(xs, Alox + b))
+    x, Alox, st0 = mono_pqn(Alo, b, xs, Alox, k_max=k_max_inner,
+                            tol_abs=tol0, tol_rel=tol_rel, j_max=j_max, ssn_tol=ssn_tol)
+    mvp_lo += st0['mvp']
 
     def fallback(x0, Ax0, mvp_hi, mvp_lo, k_done, hist):
         xm, Axm, sm = mono_pqn(Ahi, b, x0, Ax0, k_max=max(1, k_max - k_done), tol_abs=tol_abs,
-                               tol_rel=tol_rel, j_max=j_max)
+                               tol_rel=tol_rel, j_max=j_max, ssn_tol=ssn_tol)
         return xm, Axm, Stats(iters=len(hist) + sm['iters'], mvp_hi=mvp_hi + sm['mvp'], mvp_lo=mvp_lo,
                               kkt=sm['kkt'], converged=sm['converged'], hist=hist + sm['hist'], fallback=True)
 
     if st0['resets'] > 0:
-        return fallback(np.zeros(n), np.zeros(n), 0, mvp_lo, 0, [])
+        return fallback(xs, None if np.any(xs != 0.0) else np.zeros(n), 0, mvp_lo, 0, [])
     S, Y = st0['S'], st0['Y']
     sigma = st0['sigma']
     if np.any(x != 0.0):
@@ -437,7 +445,8 @@ def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_
         Bop = lambda v: Alo(v) + corr.lowrank(v)
         tol_in = max(1e-12, 1e-2 * e)
         xh, Bxh, st = mono_pqn(Bop, c, x, Bx, k_max=k_max_inner, tol_abs=tol_in,
-                               tol_rel=tol_rel, pairs=list(zip(S, Y)), j_max=j_max, sigma=sigma)
+                               tol_rel=tol_rel, pairs=list(zip(S, Y)), j_max=j_max, sigma=sigma,
+                               ssn_tol=ssn_tol)
         mvp_lo += st['mvp']
         sigma = st['sigma']
         if st['resets'] > 0:
@@ -476,7 +485,8 @@ def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_
                         converged=conv, hist=hist, fallback=False)
 
 
-def bi_pqn_rec(ops, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_max=50):
+def bi_pqn_rec(ops, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_max=50, x0=None,
+               ssn_tol=1e-14):
     """Recursive Bi-PQN over a hierarchy of fidelities (the extension of Sec. 7).
 
     ops[0] is the high-fidelity product A[.], ops[1], ops[2], ... ever cheaper
@@ -529,7 +539,7 @@ def bi_pqn_rec(ops, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_m
         H = op(d, corrs)
         if d == nf - 1:
             xs, Hxs, st = mono_pqn(H, c, x, Hx, k_max=k_lim, tol_abs=tol, tol_rel=tol_rel,
-                                   pairs=pairs, j_max=j_max, sigma=sigma)
+                                   pairs=pairs, j_max=j_max, sigma=sigma, ssn_tol=ssn_tol)
             return xs, Hxs, dict(resets=st['resets'], S=st['S'], Y=st['Y'], sigma=st['sigma'],
                                  iters=st['iters'], kkt=st['kkt'], converged=st['converged'],
                                  hist=st['hist'], fallback=False)
@@ -539,16 +549,19 @@ def bi_pqn_rec(ops, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_m
 
         def fallback(x0, Hx0, k_done, hist):
             xm, Hxm, sm = mono_pqn(H, c, x0, Hx0, k_max=max(1, k_lim - k_done), tol_abs=tol,
-                                   tol_rel=tol_rel, j_max=j_max)
+                                   tol_rel=tol_rel, j_max=j_max, ssn_tol=ssn_tol)
             return xm, Hxm, dict(resets=resets + sm['resets'], S=[], Y=[], sigma=sigma,
                                  iters=len(hist) + sm['iters'], kkt=sm['kkt'],
                                  converged=sm['converged'], hist=hist + sm['hist'], fallback=True)
 
         if top:
-            tol0 = max(1e-12, 1e-2 * kkt_error(x, Hx + c))
-            x, Lx, si = solve(d + 1, corrs, c, x, np.zeros(n), tol0, k_max_inner, [], None)
+            # from x^(-1) (the caller's guess, or 0): tolerance 1e-2 x the model's KKT error there
+            xs = x
+            Lx = L(x) if np.any(x != 0.0) else np.zeros(n)
+            tol0 = max(1e-12, 1e-2 * kkt_error(x, Lx + c))
+            x, Lx, si = solve(d + 1, corrs, c, x, Lx, tol0, k_max_inner, [], None)
             if si['resets'] > 0:
-                return fallback(np.zeros(n), np.zeros(n), 0, [])
+                return fallback(xs, None if np.any(xs != 0.0) else np.zeros(n), 0, [])
             S, Y = (si['S'], si['Y']) if last_in else ([], [])
             sigma = si['sigma']
             Hx = H(x) if np.any(x != 0.0) else np.zeros(n)
@@ -606,7 +619,8 @@ def bi_pqn_rec(ops, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_m
         return x, Hx, dict(resets=resets, S=[], Y=[], sigma=sigma, iters=len(hist) - 1, kkt=hist[-1],
                            converged=conv, hist=hist, fallback=False)
 
-    x, Ax, st = solve(0, [], b, np.zeros(n), np.zeros(n), tol_abs, k_max, [], None, top=True)
+    xs = np.zeros(n) if x0 is None else np.maximum(np.asarray(x0, dtype=np.float64), 0.0)
+    x, Ax, st = solve(0, [], b, xs, None, tol_abs, k_max, [], None, top=True)
     return x, Ax, Stats(iters=st['iters'], mvp=list(cnt), mvp_hi=cnt[0], mvp_lo=sum(cnt[1:]),
                         kkt=st['kkt'], converged=st['converged'], hist=st['hist'],
                         fallback=st['fallback'])

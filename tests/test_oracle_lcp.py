@@ -310,3 +310,35 @@ def test_bi_pqn_rec_safeguard_at_each_level():
     x, _, st = lcp.bi_pqn_rec([mv(A), mv(good), mv(good2)], b, **kw)
     assert st['converged'] and not st['fallback']
     assert np.abs(x - xbf).max() < 1e-9 * np.abs(xbf).max()
+
+
+def test_solvers_from_an_initial_guess(tiny_lcps3):
+    """x^(-1) given: every solver reaches the brute-force solution from a random guess
+    (negative entries projected) and from the solution itself, where Mono-PQN and
+    BB-PGD stop after the one product that evaluates A x^(-1) (Bi-PQN first moves to
+    the low-fidelity solution, Alg. 4's x^(0)). Two-level recursion = bi_pqn also
+    from a guess."""
+    kw = dict(tol_abs=1e-12, tol_rel=1e-15)
+    for c in tiny_lcps3:
+        b = c['b_pl']
+        xbf = lcp.brute_force_lcp(c['Ad'], b)
+        g = np.random.default_rng(c['seed']).uniform(-0.5, 1.5, b.size)
+        ops3 = [c['Aop'], c['Amid'], c['Alo']]
+        runs = {
+            'mono': lambda x0: lcp.mono_pqn(c['Aop'], b, x0=np.maximum(x0, 0.0), **kw),
+            'bb': lambda x0: lcp.bb_pgd(c['Aop'], b, x0=np.maximum(x0, 0.0), tau0=3 * np.pi, k_max=500, **kw),
+            'bi': lambda x0: lcp.bi_pqn(c['Aop'], c['Alo'], b, x0=x0, **kw),
+            'birec': lambda x0: lcp.bi_pqn_rec(ops3, b, x0=x0, **kw),
+        }
+        for name, run in runs.items():
+            x, _, st = run(g)
+            assert st['converged'], name
+            assert np.abs(x - xbf).max() <= 1e-10 * np.abs(xbf).max(), name
+            x, _, st = run(xbf)
+            if name in ('mono', 'bb'):
+                assert st['mvp'] == 1, (name, st)
+            assert st['converged'], name
+            assert np.abs(x - xbf).max() <= 1e-10 * np.abs(xbf).max(), name
+        x1, _, s1 = lcp.bi_pqn(c['Aop'], c['Alo'], b, x0=g, **kw)
+        x2, _, s2 = lcp.bi_pqn_rec([c['Aop'], c['Alo']], b, x0=g, **kw)
+        assert s1['hist'] == s2['hist'] and (s1['mvp_hi'], s1['mvp_lo']) == tuple(s2['mvp'])
