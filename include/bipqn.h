@@ -88,6 +88,16 @@ typedef struct {
   int32_t n_theta_lo2, n_phi_lo2; /* second low-fidelity grid (PQN_LOFI2); 0 = none (PQN_BI_REC
                                then unavailable). Needs the first low-fidelity grid. */
   double gmres_tol_lo2;     /* relative residual of each PQN_LOFI2 solve [1e-8] */
+  /* Device memory provider (e.g. the PyTorch caching allocator), both or neither; NULL =
+   * hipMalloc / hipFree. Every device buffer of the context is obtained through dev_alloc
+   * (bytes, alloc_user), at create and when a call needs larger buffers, and returned
+   * through dev_free(ptr, alloc_user) after the context's stream has been synchronised
+   * (or at pqn_destroy). Blocks must be usable on the context's stream; dev_alloc returns
+   * NULL on failure (the call then fails with PQN_ERR_OOM). The callbacks are invoked on
+   * the calling thread during calls on this context only. */
+  void* (*dev_alloc)(size_t bytes, void* user);
+  void (*dev_free)(void* ptr, void* user);
+  void* alloc_user;
 } pqn_config_desc;
 
 typedef struct {
@@ -108,6 +118,7 @@ typedef struct {
   int32_t j_max;            /* semi-smooth Newton steps per prox (Alg. 3) [50] */
   double kkt_tol_abs;       /* ||min(x, Ax+b)||_2 tolerance, eq. (kkt-error) [1e-8] */
   double kkt_tol_rel;       /* relative change tolerance, eq. (kkt-error) [1e-8] */
+  double ssn_tol;           /* semi-smooth Newton stop: step <= ssn_tol * max(1, |(a, a~)|) [1e-14] */
 } pqn_lcp_opts;
 
 typedef struct {
@@ -125,6 +136,7 @@ typedef struct {
                                descent and the solve finished as Mono-PQN on A */
   int32_t mvp_lo2;          /* PQN_BI_REC: products at the second low fidelity (each one BIE solve) */
   double lo2_hi_cost_ratio; /* measured t_lo2/t_hi of this call; emvp adds mvp_lo2 * this ratio */
+  double kkt_rel;           /* relative change of the last two KKT errors (0 before two iterates) */
 } pqn_lcp_stats;
 
 typedef struct {
@@ -173,13 +185,22 @@ pqn_status pqn_find_contacts(pqn_ctx* ctx, double delta, int32_t cap, int32_t* n
 /* One LCP product Ax = D^T M D x (eq. (defAandb)); pairs [n][2] (i, j), x, Ax [n]. */
 pqn_status pqn_lcp_apply(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const double* x, double* Ax, int32_t fidelity);
 
-/* Solve 0 <= A x + b perp x >= 0 (eq. (LCP)). x: on entry ignored (the solvers start
- * at 0), on exit the solution. opts may be NULL (defaults). PQN_BI needs the context's
+/* Solve 0 <= A x + b perp x >= 0 (eq. (LCP)). x: on entry the initial guess x^(-1) of
+ * Alg. 1/4 (negative entries are projected to 0; all zeros = no guess, no extra product;
+ * a nonzero guess costs one product to evaluate A x^(-1), or A^ x^(-1) for Bi-PQN, whose
+ * initial low-fidelity solve starts there), on exit the solution. opts may be NULL (defaults). PQN_BI needs the context's
  * low-fidelity grid, PQN_BI_REC both low-fidelity grids (else PQN_ERR_STATE); for
  * PQN_BI_REC, k_max_inner bounds the outer steps of the middle level and the products
  * of each lowest-level solve. */
 pqn_status pqn_lcp_solve(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const double* b, double* x, int32_t solver,
                          const pqn_lcp_opts* opts, pqn_lcp_stats* stats);
+
+/* pqn_lcp_solve with pairs [n][2], b [n] and x [n] in device memory (x: guess in,
+ * solution out, as above). Runs on the context's stream and returns after the solve
+ * (the PQN iterations read a few flags back per product); invalid pairs or non-finite
+ * b / x give PQN_ERR_INVALID with x unchanged. */
+pqn_status pqn_lcp_solve_dev(pqn_ctx* ctx, int32_t n, const int32_t* pairs_dev, const double* b_dev, double* x_dev,
+                             int32_t solver, const pqn_lcp_opts* opts, pqn_lcp_stats* stats);
 
 /* One step (eq. (dvi)): contacts(delta) -> U_nc -> b = Phi/dt + D^T U_nc -> LCP ->
  * U = U_nc + M D x -> centres += dt U, Janus axes rotated by Omega dt. */

@@ -19,6 +19,10 @@ PQN_HIFI, PQN_LOFI, PQN_LOFI2 = 0, 1, 2
 SOLVERS = {'bb': PQN_BBPGD, 'mono': PQN_MONO, 'bi': PQN_BI, 'birec': PQN_BI_REC}
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class ConfigDesc(C.Structure):
     _fields_ = [('n_particles', C.c_int32), ('radius', C.c_double), ('mu', C.c_double),
                 ('n_theta', C.c_int32), ('n_phi', C.c_int32), ('n_theta_lo', C.c_int32), ('n_phi_lo', C.c_int32),
@@ -29,7 +33,40 @@ class ConfigDesc(C.Structure):
                 ('device', C.c_int32),
                 ('stream', C.c_void_p), ('profile', C.c_int32), ('use_graphs', C.c_int32),
                 ('warm_start', C.c_int32), ('n_theta_lo2', C.c_int32), ('n_phi_lo2', C.c_int32),
-                ('gmres_tol_lo2', C.c_double)]
+                ('gmres_tol_lo2', C.c_double), ('dev_alloc', _ALLOC_FN), ('dev_free', _FREE_FN),
+                ('alloc_user', C.c_void_p)]
+
+
+class TorchAllocator:
+    """dev_alloc / dev_free of pqn_config_desc through the PyTorch caching allocator.
+
+    Blocks are taken for `stream` (an int hipStream_t handle), the stream the
+    context runs on. The object must outlive the context (pqn_destroy returns
+    its blocks through dev_free).
+    """
+
+    def __init__(self, device, stream):
+        import torch
+        self.device, self.stream = int(device), int(stream)
+        self.live = 0
+
+        def _alloc(nbytes, user):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(max(int(nbytes), 1), self.device, self.stream)
+            except Exception:  # reported to the library as NULL -> PQN_ERR_OOM
+                return None
+            self.live += 1
+            return ptr
+
+        def _free(ptr, user):
+            torch.cuda.caching_allocator_delete(ptr)
+            self.live -= 1
+
+        self.alloc_fn = _ALLOC_FN(_alloc)
+        self.free_fn = _FREE_FN(_free)
+
+    def fill(self, d):
+        d.dev_alloc, d.dev_free, d.alloc_user = self.alloc_fn, self.free_fn, None
 
 
 class MvpStats(C.Structure):
@@ -40,14 +77,15 @@ class MvpStats(C.Structure):
 
 class LcpOpts(C.Structure):
     _fields_ = [('k_max', C.c_int32), ('k_max_inner', C.c_int32), ('j_max', C.c_int32),
-                ('kkt_tol_abs', C.c_double), ('kkt_tol_rel', C.c_double)]
+                ('kkt_tol_abs', C.c_double), ('kkt_tol_rel', C.c_double), ('ssn_tol', C.c_double)]
 
 
 class LcpStats(C.Structure):
     _fields_ = [('iters', C.c_int32), ('mvp_hi', C.c_int32), ('mvp_lo', C.c_int32), ('emvp', C.c_double),
                 ('lo_hi_cost_ratio', C.c_double), ('kkt_abs', C.c_double), ('converged', C.c_int32),
                 ('ssn_steps', C.c_int32), ('t_total_ms', C.c_double), ('gmres_iters', C.c_int32),
-                ('model_rejected', C.c_int32), ('mvp_lo2', C.c_int32), ('lo2_hi_cost_ratio', C.c_double)]
+                ('model_rejected', C.c_int32), ('mvp_lo2', C.c_int32), ('lo2_hi_cost_ratio', C.c_double),
+                ('kkt_rel', C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -102,6 +140,7 @@ def lib():
         'pqn_find_contacts': (C.c_int, [V, C.c_double, C.c_int32, _I, _I, _D]),
         'pqn_lcp_apply': (C.c_int, [V, C.c_int32, _I, _D, _D, C.c_int32]),
         'pqn_lcp_solve': (C.c_int, [V, C.c_int32, _I, _D, _D, C.c_int32, _P(LcpOpts), _P(LcpStats)]),
+        'pqn_lcp_solve_dev': (C.c_int, [V, C.c_int32, V, V, V, C.c_int32, _P(LcpOpts), _P(LcpStats)]),
         'pqn_step': (C.c_int, [V, C.c_double, C.c_double, C.c_int32, _P(LcpOpts), _P(StepStats)]),
         'pqn_bie_apply': (C.c_int, [V, C.c_int32, _D, _D]),
         'pqn_get_self_block': (C.c_int, [V, C.c_int32, _D]),
@@ -157,7 +196,7 @@ def pqn_host_self_block(n_theta, n_phi, radius=1.0):
 def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_tol_lo=None, restart=50,
           max_iter=500, near_gap=0.0, near_up=2, slip=1.0, precision='fp64', refine=0, tpt=2, far_chunks=0,
           far_split=0, device=0, stream=None, profile=False, graphs=False, warm_start=False, lo2=None,
-          gmres_tol_lo2=None):
+          gmres_tol_lo2=None, allocator=None):
     d = ConfigDesc()
     d.n_particles = M
     d.radius, d.mu = radius, mu
@@ -181,20 +220,37 @@ def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_
     d.profile = 1 if profile else 0
     d.use_graphs = 1 if graphs else 0
     d.warm_start = 1 if warm_start else 0
+    if allocator is not None:
+        allocator.fill(d)
     return d
+
+
+def _torch_stream(device, stream):
+    """(handle, owner): the given hipStream_t handle, or a new torch stream kept alive by
+    the caller (a stream the library does not create, so it outlives the context's
+    last dev_free)."""
+    if stream is not None:
+        return int(stream), None
+    import torch
+    st = torch.cuda.Stream(device=device)
+    return int(st.cuda_stream), st
 
 
 class BatchContext:
     """Independent suspensions of uneven size in one batch context (pqn_batch_*)."""
 
-    def __init__(self, instances, **kw):
+    def __init__(self, instances, torch_alloc=False, **kw):
         """instances: list of (centers [M,3], n_theta, n_phi); kw: shared settings as in Context."""
         n = len(instances)
         descs = (ConfigDesc * n)()
         self._centers = [_f64(c).reshape(-1, 3) for c, _, _ in instances]
         self.Ms = [c.shape[0] for c in self._centers]
+        self._alloc = None
+        if torch_alloc:
+            kw['stream'], self._stream_obj = _torch_stream(kw.get('device', 0), kw.get('stream'))
+            self._alloc = TorchAllocator(kw.get('device', 0), kw['stream'])
         for b, (c, nt, nph) in enumerate(instances):
-            descs[b] = _desc(self.Ms[b], nt, nph, **kw)
+            descs[b] = _desc(self.Ms[b], nt, nph, allocator=self._alloc, **kw)
         cp = (_D * n)(*[_dptr(c) for c in self._centers])
         h = C.c_void_p()
         _check(lib().pqn_batch_create(n, descs, cp, None, C.byref(h)))
@@ -249,9 +305,13 @@ class Context:
                  gmres_tol=1e-8, gmres_tol_lo=None, restart=50, max_iter=500, near_gap=0.0, near_up=2,
                  slip=1.0, precision='fp64', refine=0, tpt=None, far_chunks=None, far_split=None, device=0,
                  stream=None, profile=False, tune_K=1, graphs=False, warm_start=False, lo2=None,
-                 gmres_tol_lo2=None):
+                 gmres_tol_lo2=None, torch_alloc=False):
         c = _f64(centers).reshape(-1, 3)
         self.M = c.shape[0]
+        self._alloc = None
+        if torch_alloc:
+            stream, self._stream_obj = _torch_stream(device, stream)
+            self._alloc = TorchAllocator(device, stream)
         if tpt is None or far_chunks is None or far_split is None:
             t2, c2, s2 = tuned_shape(precision, tune_K, self.M, n_theta * n_phi)
             tpt = t2 if tpt is None else tpt
@@ -262,7 +322,8 @@ class Context:
                   gmres_tol_lo=gmres_tol_lo, restart=restart, max_iter=max_iter, near_gap=near_gap,
                   near_up=near_up, slip=slip, precision=precision, refine=refine, tpt=tpt,
                   far_chunks=far_chunks, far_split=far_split, device=device, stream=stream, profile=profile,
-                  graphs=graphs, warm_start=warm_start, lo2=lo2, gmres_tol_lo2=gmres_tol_lo2)
+                  graphs=graphs, warm_start=warm_start, lo2=lo2, gmres_tol_lo2=gmres_tol_lo2,
+                  allocator=self._alloc)
         self.n_theta, self.n_phi, self.lo, self.lo2 = n_theta, n_phi, lo, lo2
         ax = None if axes is None else _f64(axes).reshape(-1, 3)
         h = C.c_void_p()
@@ -354,18 +415,30 @@ class Context:
                                    fidelity))
         return Ax
 
-    def lcp_solve(self, pairs, b, solver='mono', k_max=0, k_max_inner=0, j_max=0, tol_abs=0.0, tol_rel=0.0):
+    def lcp_solve(self, pairs, b, solver='mono', k_max=0, k_max_inner=0, j_max=0, tol_abs=0.0, tol_rel=0.0,
+                  x0=None, ssn_tol=0.0):
         pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
         b = _f64(b)
-        x = np.zeros(pairs.shape[0])
-        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel)
+        x = np.zeros(pairs.shape[0]) if x0 is None else _f64(x0, (pairs.shape[0],)).copy()
+        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol)
         st = LcpStats()
         status = _check(lib().pqn_lcp_solve(self.h, pairs.shape[0], pairs.ctypes.data_as(_I), _dptr(b), _dptr(x),
                                             SOLVERS.get(solver, solver), C.byref(o), C.byref(st)))
         return x, dict(_struct_dict(st), status=status)
 
-    def step(self, dt, delta, solver='mono', k_max=0, k_max_inner=0, j_max=0, tol_abs=0.0, tol_rel=0.0):
-        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel)
+    def lcp_solve_dev(self, n, pairs_ptr, b_ptr, x_ptr, solver='mono', k_max=0, k_max_inner=0, j_max=0,
+                      tol_abs=0.0, tol_rel=0.0, ssn_tol=0.0):
+        """pqn_lcp_solve_dev on device pointers (ints, e.g. torch tensors' data_ptr())."""
+        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol)
+        st = LcpStats()
+        status = _check(lib().pqn_lcp_solve_dev(self.h, n, C.c_void_p(pairs_ptr), C.c_void_p(b_ptr),
+                                                C.c_void_p(x_ptr), SOLVERS.get(solver, solver), C.byref(o),
+                                                C.byref(st)))
+        return dict(_struct_dict(st), status=status)
+
+    def step(self, dt, delta, solver='mono', k_max=0, k_max_inner=0, j_max=0, tol_abs=0.0, tol_rel=0.0,
+             ssn_tol=0.0):
+        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol)
         st = StepStats()
         status = _check(lib().pqn_step(self.h, dt, delta, SOLVERS.get(solver, solver), C.byref(o), C.byref(st)))
         return dict(_struct_dict(st), status=status)

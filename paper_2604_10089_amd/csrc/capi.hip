@@ -63,6 +63,7 @@ static std::string check_desc(const pqn_config_desc& c) {
     return "second low-fidelity grid needs n_theta >= 2 and n_phi >= 2 n_theta - 1";
   if (c.n_theta_lo2 != 0 && c.n_theta_lo == 0) return "a second low-fidelity grid needs the first";
   if (c.precision != PQN_FP64 && c.precision != PQN_MIXED) return "bad precision";
+  if ((c.dev_alloc == nullptr) != (c.dev_free == nullptr)) return "dev_alloc and dev_free go together";
   return "";
 }
 
@@ -81,6 +82,8 @@ static std::unique_ptr<pqn_ctx_impl> make_context(const pqn_config_desc& c, cons
     HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
     ctx->own_stream = true;
   }
+  ctx->dev_alloc = DevAllocator{c.dev_alloc, c.dev_free, c.alloc_user, ctx->stream};
+  AllocScope scope(&ctx->dev_alloc);
   ctx->setup_level(ctx->hi, c.n_theta, c.n_phi, c.gmres_tol);
   if (c.n_theta_lo > 0) {
     ctx->setup_level(ctx->lo, c.n_theta_lo, c.n_phi_lo, c.gmres_tol_lo);
@@ -129,8 +132,10 @@ pqn_status pqn_batch_create(int32_t n_inst, const pqn_config_desc* descs, const 
       if (!centers[b]) return fail(PQN_ERR_INVALID, "pqn_batch_create: NULL centres");
       if (c.precision != c0.precision || c.gmres_restart != c0.gmres_restart || c.device != c0.device ||
           c.targets_per_thread != c0.targets_per_thread || c.far_split != c0.far_split ||
-          c.refine_sweeps != c0.refine_sweeps)
-        return fail(PQN_ERR_INVALID, "batched instances must share precision, restart, refinement, device and tiling");
+          c.refine_sweeps != c0.refine_sweeps || c.dev_alloc != c0.dev_alloc || c.dev_free != c0.dev_free ||
+          c.alloc_user != c0.alloc_user)
+        return fail(PQN_ERR_INVALID,
+                    "batched instances must share precision, restart, refinement, device, tiling and allocator");
     }
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
@@ -146,6 +151,8 @@ pqn_status pqn_batch_create(int32_t n_inst, const pqn_config_desc* descs, const 
       HIPCHK(hipStreamCreateWithFlags(&parent->stream, hipStreamNonBlocking));
       parent->own_stream = true;
     }
+    parent->dev_alloc = DevAllocator{c0.dev_alloc, c0.dev_free, c0.alloc_user, parent->stream};
+    AllocScope scope(&parent->dev_alloc);
     for (int b = 0; b < n_inst; ++b) {
       pqn_config_desc c = descs[b];
       fill_defaults(c);
@@ -158,6 +165,7 @@ pqn_status pqn_batch_create(int32_t n_inst, const pqn_config_desc* descs, const 
 
 pqn_status pqn_batch_mobility_apply(pqn_ctx* ctx, const double* const* FT, double* const* UO, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (!ctx || !FT || !UO) return fail(PQN_ERR_INVALID, "pqn_batch_mobility_apply: NULL argument");
     if (!ctx->is_batch) return fail(PQN_ERR_STATE, "pqn_batch_mobility_apply needs a batch context");
     HIPCHK(hipSetDevice(ctx->device));
@@ -230,6 +238,7 @@ static pqn_status mobility_multi_common(pqn_ctx* ctx, int32_t k_rhs, const doubl
 pqn_status pqn_mobility_apply_multi(pqn_ctx* ctx, int32_t k_rhs, const double* FT, double* UO, int32_t fidelity,
                                     pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_mobility_apply_multi needs a single-suspension context");
     if (!ctx || !FT || !UO || k_rhs < 1 || k_rhs > kMaxRhs)
       return fail(PQN_ERR_INVALID, "pqn_mobility_apply_multi: bad argument (1 <= k_rhs <= 6)");
@@ -248,6 +257,7 @@ pqn_status pqn_mobility_apply_multi(pqn_ctx* ctx, int32_t k_rhs, const double* F
 pqn_status pqn_mobility_apply_multi_dev(pqn_ctx* ctx, int32_t k_rhs, const double* FT_dev, double* UO_dev,
                                         int32_t fidelity, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_mobility_apply_multi_dev needs a single-suspension context");
     if (!ctx || !FT_dev || !UO_dev || k_rhs < 1 || k_rhs > kMaxRhs)
       return fail(PQN_ERR_INVALID, "pqn_mobility_apply_multi_dev: bad argument (1 <= k_rhs <= 6)");
@@ -259,6 +269,7 @@ pqn_status pqn_mobility_apply_multi_dev(pqn_ctx* ctx, int32_t k_rhs, const doubl
 pqn_status pqn_destroy(pqn_ctx* ctx) {
   if (!ctx) return PQN_OK;
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     HIPCHK(hipSetDevice(ctx->device));
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     delete static_cast<pqn_ctx_impl*>(ctx);
@@ -268,6 +279,7 @@ pqn_status pqn_destroy(pqn_ctx* ctx) {
 
 pqn_status pqn_set_state(pqn_ctx* ctx, const double* centers, const double* janus_axes) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_set_state needs a single-suspension context");
     if (!ctx || !centers) return fail(PQN_ERR_INVALID, "pqn_set_state: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
@@ -314,6 +326,7 @@ static pqn_status mobility_common(pqn_ctx* ctx, const double* FT_dev, const doub
 pqn_status pqn_mobility_apply_dev(pqn_ctx* ctx, const double* FT_dev, double* UO_dev, int32_t fidelity,
                                   pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_mobility_apply_dev needs a single-suspension context");
     if (!ctx || !FT_dev || !UO_dev) return fail(PQN_ERR_INVALID, "pqn_mobility_apply_dev: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
@@ -323,6 +336,7 @@ pqn_status pqn_mobility_apply_dev(pqn_ctx* ctx, const double* FT_dev, double* UO
 
 pqn_status pqn_mobility_apply(pqn_ctx* ctx, const double* FT, double* UO, int32_t fidelity, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_mobility_apply needs a single-suspension context");
     if (!ctx || !FT || !UO) return fail(PQN_ERR_INVALID, "pqn_mobility_apply: NULL argument");
     for (int k = 0; k < 6 * ctx->M; ++k)
@@ -338,6 +352,7 @@ pqn_status pqn_mobility_apply(pqn_ctx* ctx, const double* FT, double* UO, int32_
 
 pqn_status pqn_nc_velocity(pqn_ctx* ctx, double* UO, int32_t fidelity, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_nc_velocity needs a single-suspension context");
     if (!ctx || !UO) return fail(PQN_ERR_INVALID, "pqn_nc_velocity: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
@@ -355,6 +370,7 @@ pqn_status pqn_nc_velocity(pqn_ctx* ctx, double* UO, int32_t fidelity, pqn_mvp_s
 
 pqn_status pqn_bie_apply(pqn_ctx* ctx, int32_t fidelity, const double* q, double* y) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_bie_apply needs a single-suspension context");
     if (!ctx || !q || !y) return fail(PQN_ERR_INVALID, "pqn_bie_apply: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
@@ -372,6 +388,7 @@ pqn_status pqn_bie_apply(pqn_ctx* ctx, int32_t fidelity, const double* q, double
 
 pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, double* q, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_bie_solve needs a single-suspension context");
     if (!ctx || !rhs || !q) return fail(PQN_ERR_INVALID, "pqn_bie_solve: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
@@ -400,6 +417,7 @@ pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, doub
 
 pqn_status pqn_get_self_block(pqn_ctx* ctx, int32_t fidelity, double* S) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_get_self_block needs a single-suspension context");
     if (!ctx || !S) return fail(PQN_ERR_INVALID, "pqn_get_self_block: NULL argument");
     Level& lv = ctx->level(fidelity);
@@ -410,6 +428,7 @@ pqn_status pqn_get_self_block(pqn_ctx* ctx, int32_t fidelity, double* S) {
 
 pqn_status pqn_get_grid(pqn_ctx* ctx, int32_t fidelity, int32_t* n_nodes, double* offsets, double* weights) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_get_grid needs a single-suspension context");
     if (!ctx) return fail(PQN_ERR_INVALID, "pqn_get_grid: NULL context");
     Level& lv = ctx->level(fidelity);
@@ -435,6 +454,7 @@ pqn_status pqn_host_self_block(int32_t n_theta, int32_t n_phi, double radius, do
 
 pqn_status pqn_find_contacts(pqn_ctx* ctx, double delta, int32_t cap, int32_t* n_out, int32_t* pairs, double* gaps) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_find_contacts needs a single-suspension context");
     if (!ctx || !n_out || (cap > 0 && (!pairs || !gaps)) || cap < 0)
       return fail(PQN_ERR_INVALID, "pqn_find_contacts: bad argument");
@@ -450,6 +470,7 @@ pqn_status pqn_find_contacts(pqn_ctx* ctx, double delta, int32_t cap, int32_t* n
 pqn_status pqn_lcp_apply(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const double* x, double* Ax,
                          int32_t fidelity) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_lcp_apply needs a single-suspension context");
     if (!ctx || n < 0 || (n > 0 && (!pairs || !x || !Ax))) return fail(PQN_ERR_INVALID, "pqn_lcp_apply: bad argument");
     HIPCHK(hipSetDevice(ctx->device));
@@ -461,6 +482,7 @@ pqn_status pqn_lcp_apply(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const do
 pqn_status pqn_lcp_solve(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const double* b, double* x, int32_t solver,
                          const pqn_lcp_opts* opts, pqn_lcp_stats* stats) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_lcp_solve needs a single-suspension context");
     if (!ctx || n < 0 || (n > 0 && (!pairs || !b || !x))) return fail(PQN_ERR_INVALID, "pqn_lcp_solve: bad argument");
     if (solver < PQN_BBPGD || solver > PQN_BI_REC) return fail(PQN_ERR_INVALID, "bad solver");
@@ -471,9 +493,24 @@ pqn_status pqn_lcp_solve(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const do
   });
 }
 
+pqn_status pqn_lcp_solve_dev(pqn_ctx* ctx, int32_t n, const int32_t* pairs_dev, const double* b_dev, double* x_dev,
+                             int32_t solver, const pqn_lcp_opts* opts, pqn_lcp_stats* stats) {
+  return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_lcp_solve_dev needs a single-suspension context");
+    if (!ctx || n < 0 || (n > 0 && (!pairs_dev || !b_dev || !x_dev)))
+      return fail(PQN_ERR_INVALID, "pqn_lcp_solve_dev: bad argument");
+    if (solver < PQN_BBPGD || solver > PQN_BI_REC) return fail(PQN_ERR_INVALID, "bad solver");
+    if (const char* why = solver_unavailable(*ctx, solver)) return fail(PQN_ERR_STATE, why);
+    HIPCHK(hipSetDevice(ctx->device));
+    return lcp_solve_dev(*ctx, n, pairs_dev, b_dev, x_dev, solver, opts, stats);
+  });
+}
+
 pqn_status pqn_step(pqn_ctx* ctx, double dt, double delta, int32_t solver, const pqn_lcp_opts* opts,
                     pqn_step_stats* stats) {
   return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_step needs a single-suspension context");
     if (!ctx || !(dt > 0.0) || !std::isfinite(delta)) return fail(PQN_ERR_INVALID, "pqn_step: bad argument");
     if (solver < PQN_BBPGD || solver > PQN_BI_REC) return fail(PQN_ERR_INVALID, "bad solver");

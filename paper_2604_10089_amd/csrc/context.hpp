@@ -24,24 +24,62 @@ struct Error : std::runtime_error {
                            std::string(#x) + ": " + hipGetErrorString(e_));                          \
   } while (0)
 
+// Device memory provider of a context (pqn_config_desc.dev_alloc / dev_free);
+// null functions = hipMalloc / hipFree. `stream` is the context's stream: a
+// buffer replaced by a larger one is returned only after it has drained.
+struct DevAllocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free)(void*, void*) = nullptr;
+  void* user = nullptr;
+  hipStream_t stream = nullptr;
+};
+
+// Provider used by DevArray::alloc on this thread: set for the duration of each
+// call on a context (AllocScope), null outside calls.
+inline thread_local const DevAllocator* g_dev_allocator = nullptr;
+
+struct AllocScope {
+  const DevAllocator* prev;
+  explicit AllocScope(const DevAllocator* a) : prev(g_dev_allocator) { g_dev_allocator = a; }
+  ~AllocScope() { g_dev_allocator = prev; }
+  AllocScope(const AllocScope&) = delete;
+  AllocScope& operator=(const AllocScope&) = delete;
+};
+
 template <class T>
 struct DevArray {
   T* p = nullptr;
   size_t count = 0;
+  DevAllocator al{};  // provider that returned p
   DevArray() = default;
   DevArray(const DevArray&) = delete;
   DevArray& operator=(const DevArray&) = delete;
   ~DevArray() { release(); }
+  // (the owner has synchronised the stream: pqn_destroy does before deleting a context)
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (al.free)
+        al.free(p, al.user);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
     count = 0;
   }
   void alloc(size_t n) {
     if (n <= count && p) return;
+    if (p && al.free) HIPCHK(hipStreamSynchronize(al.stream));  // kernels may still read the old block
     release();
     if (n == 0) return;
-    HIPCHK(hipMalloc((void**)&p, n * sizeof(T)));
+    const DevAllocator* cur = g_dev_allocator;
+    if (cur && cur->alloc) {
+      al = *cur;
+      p = static_cast<T*>(al.alloc(n * sizeof(T), al.user));
+      if (!p) throw Error(PQN_ERR_OOM, "dev_alloc returned NULL");
+    } else {
+      al = DevAllocator{};
+      HIPCHK(hipMalloc((void**)&p, n * sizeof(T)));
+    }
     count = n;
   }
   void upload(const T* h, size_t n, hipStream_t s) {
@@ -161,6 +199,7 @@ struct pqn_ctx_impl {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int device = 0;
+  DevAllocator dev_alloc;  // device memory provider (every DevArray of the context)
   Level hi, lo, lo2;  // fidelities PQN_HIFI, PQN_LOFI, PQN_LOFI2
   bool has_lo = false, has_lo2 = false;
   // configuration-dependent tables shared by both levels

@@ -17,6 +17,7 @@ constexpr int kT = 256;  // threads of the single-workgroup kernels (4 waves)
 struct PqnScal {
   int r, conv, stationary, reset, ssn_steps, ssn_fail, have_prev, nonzero;
   int resets;  // steps of this solve that met the Alg. 2 edge cases (non-positive curvature or no descent)
+  int bad;     // k_check_lcp_inputs: an invalid pair or a non-finite entry of b or x
   double e, e_prev, eta, tol_abs, tol_rel, tau, sigma;
 };
 
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(kT) void k_pqn_replay(PqnDev d, const double* __res
 
 // KKT check, x~ = x - H g (two-loop recursion, H0 = I), prox by semi-smooth
 // Newton (Prop. 1, Alg. 3), p = x^ - x.
-__global__ __launch_bounds__(kT) void k_pqn_prepare(PqnDev d, int jmax) {
+__global__ __launch_bounds__(kT) void k_pqn_prepare(PqnDev d, int jmax, double ssn_tol) {
   __shared__ double red[4];
   __shared__ double Jm[2 * kRmax * 2 * kRmax];
   __shared__ double Lv[2 * kRmax];
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(kT) void k_pqn_prepare(PqnDev d, int jmax) {
             dn += Lv[k] * Lv[k];
             zn += z[k] * z[k];
           }
-        stop = !ok || sqrt(dn) <= 1e-14 * fmax(1.0, sqrt(zn));
+        stop = !ok || sqrt(dn) <= ssn_tol * fmax(1.0, sqrt(zn));
         if (!ok) d.sc->ssn_fail += 1;
       }
       __syncthreads();
@@ -740,6 +741,40 @@ __global__ __launch_bounds__(kT) void k_kkt_zero(const double* __restrict__ b, i
   if (threadIdx.x == 0) sc->e = sqrt(s);
 }
 
+// Inputs handed over in device memory: pairs in range with i != j, b and x finite
+// (else sc->bad); x projected on x >= 0 in place; sc->nonzero = x has a positive entry.
+__global__ __launch_bounds__(kT) void k_check_lcp_inputs(const int* __restrict__ pairs, const double* __restrict__ b,
+                                                         double* __restrict__ x, int n, int M, PqnScal* sc) {
+  __shared__ double red[4];
+  double bad = 0.0, nz = 0.0;
+  for (int e = threadIdx.x; e < n; e += kT) {
+    const int i = pairs[2 * e], j = pairs[2 * e + 1];
+    if (i < 0 || j < 0 || i >= M || j >= M || i == j || !isfinite(b[e]) || !isfinite(x[e])) bad += 1.0;
+    const double v = fmax(x[e], 0.0);
+    x[e] = v;
+    nz += v > 0.0 ? 1.0 : 0.0;
+  }
+  bad = block_sum(bad, red);
+  nz = block_sum(nz, red);
+  if (threadIdx.x == 0) {
+    sc->bad = bad > 0.0;
+    sc->nonzero = nz > 0.0;
+  }
+}
+
+// KKT error |min(x, A x + b)|_2 (into sc->e).
+__global__ __launch_bounds__(kT) void k_kkt(const double* __restrict__ x, const double* __restrict__ Ax,
+                                            const double* __restrict__ b, int n, PqnScal* sc) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int e = threadIdx.x; e < n; e += kT) {
+    const double m = fmin(x[e], Ax[e] + b[e]);
+    s = fma(m, m, s);
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) sc->e = sqrt(s);
+}
+
 // Forward Euler of centres and Rodrigues rotation of the Janus axes.
 __global__ void k_euler(double* __restrict__ ctr, double* __restrict__ axes, const double* __restrict__ Unc,
                         const double* __restrict__ MDx, int M, double dt, int has_axes) {
@@ -927,12 +962,12 @@ static PqnScal read_scal(pqn_ctx_impl& ctx, const PqnScal* d) {
 // Mono-PQN (Alg. 1) on an engine; mvp(v, out, md) computes out = A v (md: M D v or null).
 // Returns whether it converged; the engine holds x, A x and the memory.
 template <class Mvp>
-static bool run_mono(pqn_ctx_impl& ctx, Engine& E, int k_max, int j_max, Mvp&& mvp, double* MDx, int M,
+static bool run_mono(pqn_ctx_impl& ctx, Engine& E, int k_max, const pqn_lcp_opts& o, Mvp&& mvp, double* MDx, int M,
                      int* iters) {
   bool conv = false;
   int k = 0;
   for (k = 0; k < k_max; ++k) {
-    hipLaunchKernelGGL(k_pqn_prepare, dim3(1), dim3(kT), 0, ctx.stream, E.d, j_max);
+    hipLaunchKernelGGL(k_pqn_prepare, dim3(1), dim3(kT), 0, ctx.stream, E.d, o.j_max, o.ssn_tol);
     HIPCHK(hipGetLastError());
     PqnScal s = read_scal(ctx, E.d.sc);
     if (!std::isfinite(s.e)) throw Error(PQN_ERR_NUMERIC, "non-finite KKT error in PQN");
@@ -949,7 +984,7 @@ static bool run_mono(pqn_ctx_impl& ctx, Engine& E, int k_max, int j_max, Mvp&& m
   }
   if (!conv) {
     // final KKT evaluation (no product needed: A x is carried by the recurrence)
-    hipLaunchKernelGGL(k_pqn_prepare, dim3(1), dim3(kT), 0, ctx.stream, E.d, j_max);
+    hipLaunchKernelGGL(k_pqn_prepare, dim3(1), dim3(kT), 0, ctx.stream, E.d, o.j_max, o.ssn_tol);
     PqnScal s = read_scal(ctx, E.d.sc);
     conv = s.conv;
   }
@@ -958,13 +993,14 @@ static bool run_mono(pqn_ctx_impl& ctx, Engine& E, int k_max, int j_max, Mvp&& m
 }
 
 static pqn_lcp_opts opts_or_default(const pqn_lcp_opts* o) {
-  pqn_lcp_opts r{100, 50, 50, 1e-8, 1e-8};
+  pqn_lcp_opts r{100, 50, 50, 1e-8, 1e-8, 1e-14};
   if (o) {
     if (o->k_max > 0) r.k_max = o->k_max;
     if (o->k_max_inner > 0) r.k_max_inner = o->k_max_inner;
     if (o->j_max > 0) r.j_max = o->j_max;
     if (o->kkt_tol_abs > 0) r.kkt_tol_abs = o->kkt_tol_abs;
     if (o->kkt_tol_rel > 0) r.kkt_tol_rel = o->kkt_tol_rel;
+    if (o->ssn_tol > 0) r.ssn_tol = o->ssn_tol;
   }
   return r;
 }
@@ -983,6 +1019,7 @@ struct BiSolver {
   SolveCounters& cnt;
   int n, M, nf;     // nf fidelities: 2 = Bi-PQN, 3 = recursive Bi-PQN
   double* MDx;      // M D x of the top level (may be null)
+  bool x0;          // the top level starts from the caller's x^(-1) (in its engine's x), not 0
   Level* lv[3];
   Engine* eng[3];   // engine of each level (eng[nf - 1] runs Mono-PQN)
   BiDev* bd[2];     // Bi-PQN state of each Bi-PQN level
@@ -1049,7 +1086,7 @@ struct BiSolver {
       hipLaunchKernelGGL(k_pqn_replay, dim3(1), dim3(kT), 0, ctx.stream, E.d, bd[d - 1]->Slow, bd[d - 1]->Ylow,
                          npairs);
     Result r;
-    run_mono(ctx, E, k_lim, o.j_max, [&](const double* v, double* out, double*) { op(d, v, out, nullptr); },
+    run_mono(ctx, E, k_lim, o, [&](const double* v, double* out, double*) { op(d, v, out, nullptr); },
              nullptr, M, &in_iters);
     PqnScal s = read_scal(ctx, E.d.sc);
     ssn += s.ssn_steps;
@@ -1061,18 +1098,23 @@ struct BiSolver {
   }
 
   // Model safeguard: level d continues as Mono-PQN on H_d from its current
-  // iterate (keep_x) or from 0.
-  Result fallback(int d, double tol, int k_lim, bool keep_x, int k_done, int resets_before) {
+  // iterate (keep_x), from the top level's x^(-1) (restart: x is still in the
+  // engine, A x is evaluated again) or from 0.
+  Result fallback(int d, double tol, int k_lim, bool keep_x, int k_done, int resets_before, bool restart = false) {
     Engine& E = *eng[d];
     const bool top = d == 0;
     if (top) rejected = true;
-    hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, E.d, keep_x ? 1 : 0, tol, o.kkt_tol_rel);
+    hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, E.d, keep_x || restart ? 1 : 0, tol,
+                       o.kkt_tol_rel);
     double* md = top ? MDx : nullptr;
-    if (md && !keep_x) HIPCHK(hipMemsetAsync(md, 0, 6 * (size_t)M * sizeof(double), ctx.stream));
+    if (restart)
+      op(d, E.d.x, E.d.Ax, md);  // md (if any) receives M D x^(-1)
+    else if (md && !keep_x)
+      HIPCHK(hipMemsetAsync(md, 0, 6 * (size_t)M * sizeof(double), ctx.stream));
     int it = 0;
     Result r;
     r.conv = run_mono(
-        ctx, E, std::max(1, k_lim - k_done), o.j_max,
+        ctx, E, std::max(1, k_lim - k_done), o,
         [&](const double* v, double* out, double* mdv) { op(d, v, out, top ? mdv : nullptr); }, md, M, &it);
     PqnScal sm = read_scal(ctx, E.d.sc);
     ssn += sm.ssn_steps;
@@ -1099,13 +1141,20 @@ struct BiSolver {
     };
     if (top) {
       for (int l = 0; l < nf - 1; ++l) set_counts(*bd[l], 0, 0);
-      // initial solve from x^(-1) = 0 with tolerance 1e-2 * KKT(0), KKT(0) = |min(0, b)|
+      // initial solve one level down from x^(-1) with tolerance 1e-2 x the model's KKT
+      // error there (|min(0, b)| at x^(-1) = 0, where the model product is free)
       HIPCHK(hipMemcpyAsync(I.d.b, E.d.b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
-      hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, I.d, 0, 0.0, 0.0);
-      hipLaunchKernelGGL(k_kkt_zero, dim3(1), dim3(kT), 0, ctx.stream, E.d.b, n, E.d.sc);
+      if (x0) {
+        HIPCHK(hipMemcpyAsync(I.d.x, E.d.x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+        op(1, I.d.x, I.d.Ax, nullptr);  // no correction yet: A_1 x^(-1)
+        hipLaunchKernelGGL(k_kkt, dim3(1), dim3(kT), 0, ctx.stream, I.d.x, I.d.Ax, I.d.b, n, E.d.sc);
+      } else {
+        hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, I.d, 0, 0.0, 0.0);
+        hipLaunchKernelGGL(k_kkt_zero, dim3(1), dim3(kT), 0, ctx.stream, E.d.b, n, E.d.sc);
+      }
       const double e0 = read_scal(ctx, E.d.sc).e;
       Result r0 = solve_in(std::max(1e-12, 1e-2 * e0), sigma, 0);
-      if (r0.resets > 0) return fallback(d, tol, k_lim, false, 0, 0);
+      if (r0.resets > 0) return fallback(d, tol, k_lim, false, 0, 0, x0);
       // x = x0, A^ x = its model product, stored pairs = its Mono-PQN memory
       init_scal(E, tol, 0.0);
       HIPCHK(hipMemcpyAsync(E.d.x, I.d.x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
@@ -1179,7 +1228,7 @@ struct BiSolver {
 // Solve the LCP with b (device, length n) on the stored pairs. x ends in
 // st.outer.d.x; MDx (if non-null) receives M D x.
 static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opts& o, double* MDx,
-                         pqn_lcp_stats* stats) {
+                         pqn_lcp_stats* stats, bool x0) {
   LcpState& st = *ctx.lcp;
   SolveCounters cnt;
   Level& hi = ctx.hi;
@@ -1197,9 +1246,12 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
   int iters = 0;
   int ssn = 0;
   double kkt = 0.0;
-  hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, st.outer.d, 0, o.kkt_tol_abs, o.kkt_tol_rel);
+  hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, st.outer.d, x0 ? 1 : 0, o.kkt_tol_abs,
+                     o.kkt_tol_rel);
+  // Mono-PQN and BB-PGD from x^(-1): A x^(-1) (and M D x^(-1)) by one product
+  if (x0 && solver != PQN_BI && solver != PQN_BI_REC) mvp_hi(st.outer.d.x, st.outer.d.Ax, MDx);
   if (solver == PQN_MONO) {
-    conv = run_mono(ctx, st.outer, o.k_max, o.j_max, mvp_hi, MDx, M, &iters);
+    conv = run_mono(ctx, st.outer, o.k_max, o, mvp_hi, MDx, M, &iters);
     PqnScal s = read_scal(ctx, st.outer.d.sc);
     ssn = s.ssn_steps;
     kkt = s.e;
@@ -1226,7 +1278,7 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
     iters = k;
   } else {
     const bool rec = solver == PQN_BI_REC;
-    BiSolver bs{ctx, st, o, cnt, n, M, rec ? 3 : 2, MDx, {&ctx.hi, &ctx.lo, rec ? &ctx.lo2 : nullptr},
+    BiSolver bs{ctx, st, o, cnt, n, M, rec ? 3 : 2, MDx, x0, {&ctx.hi, &ctx.lo, rec ? &ctx.lo2 : nullptr},
                 {&st.outer, rec ? &st.mid : &st.inner, rec ? &st.inner : nullptr}, {&st.bi, &st.bi2}};
     double sigma = 0.0;  // metric scale of the Mono-PQN solves (0 = set by their first step)
     BiSolver::Result r = bs.bi_level(0, o.kkt_tol_abs, o.k_max, sigma);
@@ -1236,8 +1288,10 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
     ssn = bs.ssn;
     rejected = bs.rejected;
   }
-  HIPCHK(hipStreamSynchronize(ctx.stream));
+  const PqnScal fin = read_scal(ctx, st.outer.d.sc);
   if (stats) {
+    const double mx = std::max(fin.e, fin.e_prev);
+    stats->kkt_rel = fin.have_prev && mx > 0.0 ? std::fabs(fin.e - fin.e_prev) / mx : 0.0;
     stats->iters = iters;
     stats->mvp_hi = cnt.mvp[0];
     stats->mvp_lo = cnt.mvp[1];
@@ -1271,10 +1325,48 @@ pqn_status lcp_solve_host(pqn_ctx_impl& ctx, int n, const int32_t* pairs, const 
   st.ensure(n, ctx.M);
   st.set_n(n);
   const pqn_lcp_opts o = opts_or_default(opts);
+  // x^(-1): the caller's x projected on x >= 0
+  std::vector<double> xg(x, x + n);
+  bool x0 = false;
+  for (double& v : xg) {
+    if (!std::isfinite(v)) throw Error(PQN_ERR_NUMERIC, "non-finite initial guess x");
+    v = std::max(v, 0.0);
+    x0 = x0 || v > 0.0;
+  }
   HIPCHK(hipMemcpyAsync(st.pairs.p, pairs, 2 * (size_t)n * sizeof(int), hipMemcpyHostToDevice, ctx.stream));
   HIPCHK(hipMemcpyAsync(st.outer.d.b, b, (size_t)n * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
-  const bool conv = solve_device(ctx, n, solver, o, nullptr, &st_local);
+  if (x0) HIPCHK(hipMemcpyAsync(st.outer.d.x, xg.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
+  HIPCHK(hipStreamSynchronize(ctx.stream));  // xg leaves scope only after the copy
+  const bool conv = solve_device(ctx, n, solver, o, nullptr, &st_local, x0);
   HIPCHK(hipMemcpyAsync(x, st.outer.d.x, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  HIPCHK(hipStreamSynchronize(ctx.stream));
+  ctx.end_far_timing();
+  st_local.t_total_ms = tm.ms();
+  if (stats) *stats = st_local;
+  return conv ? PQN_OK : PQN_WARN_NOT_CONVERGED;
+}
+
+pqn_status lcp_solve_dev(pqn_ctx_impl& ctx, int n, const int32_t* pairs, const double* b, double* x, int solver,
+                         const pqn_lcp_opts* opts, pqn_lcp_stats* stats) {
+  Timer tm;
+  pqn_lcp_stats st_local{};
+  if (n == 0) {
+    if (stats) *stats = st_local;
+    return PQN_OK;
+  }
+  LcpState& st = state(ctx);
+  st.ensure(n, ctx.M);
+  st.set_n(n);
+  const pqn_lcp_opts o = opts_or_default(opts);
+  HIPCHK(hipMemcpyAsync(st.pairs.p, pairs, 2 * (size_t)n * sizeof(int), hipMemcpyDeviceToDevice, ctx.stream));
+  HIPCHK(hipMemcpyAsync(st.outer.d.b, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+  HIPCHK(hipMemcpyAsync(st.outer.d.x, x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+  hipLaunchKernelGGL(k_check_lcp_inputs, dim3(1), dim3(kT), 0, ctx.stream, st.pairs.p, st.outer.d.b, st.outer.d.x, n,
+                     ctx.M, st.outer.d.sc);
+  const PqnScal chk = read_scal(ctx, st.outer.d.sc);
+  if (chk.bad) throw Error(PQN_ERR_INVALID, "invalid contact pair or non-finite b / x");
+  const bool conv = solve_device(ctx, n, solver, o, nullptr, &st_local, chk.nonzero != 0);
+  HIPCHK(hipMemcpyAsync(x, st.outer.d.x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
   HIPCHK(hipStreamSynchronize(ctx.stream));
   ctx.end_far_timing();
   st_local.t_total_ms = tm.ms();
@@ -1317,7 +1409,7 @@ pqn_status lcp_step(pqn_ctx_impl& ctx, double dt, double delta, int solver, cons
     hipLaunchKernelGGL(k_make_b, dim3((n + 255) / 256), dim3(256), 0, ctx.stream, st.cgaps.p, st.outer.d.t1, dt, n,
                        st.outer.d.b);
     const pqn_lcp_opts o = opts_or_default(opts);
-    conv = solve_device(ctx, n, solver, o, st.MDx.p, &ss.lcp);
+    conv = solve_device(ctx, n, solver, o, st.MDx.p, &ss.lcp, false);
     MDx = st.MDx.p;
     std::vector<double> hx(n);
     HIPCHK(hipMemcpyAsync(hx.data(), st.outer.d.x, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));

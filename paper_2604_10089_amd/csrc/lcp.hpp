@@ -12,6 +12,8 @@ void lcp_check_pairs(pqn_ctx_impl& ctx, int n, const int32_t* pairs);
 pqn_status lcp_apply_host(pqn_ctx_impl& ctx, int n, const int32_t* pairs, const double* x, double* Ax, int fidelity);
 pqn_status lcp_solve_host(pqn_ctx_impl& ctx, int n, const int32_t* pairs, const double* b, double* x, int solver,
                           const pqn_lcp_opts* opts, pqn_lcp_stats* stats);
+pqn_status lcp_solve_dev(pqn_ctx_impl& ctx, int n, const int32_t* pairs, const double* b, double* x, int solver,
+                         const pqn_lcp_opts* opts, pqn_lcp_stats* stats);
 pqn_status lcp_step(pqn_ctx_impl& ctx, double dt, double delta, int solver, const pqn_lcp_opts* opts,
                     pqn_step_stats* stats);
 

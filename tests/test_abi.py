@@ -56,3 +56,53 @@ def test_host_self_block_rejects_bad_grid():
         binding.pqn_host_self_block(1, 2, 1.0)
     with pytest.raises(binding.PqnError):
         binding.pqn_host_self_block(6, 12, -1.0)
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes structure of the binding has the header's size and field offsets
+    (a C program built with the host compiler prints offsetof / sizeof)."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which('gcc') or shutil.which('cc')
+    if cc is None:
+        pytest.skip('no host C compiler')
+    structs = {'pqn_config_desc': binding.ConfigDesc, 'pqn_mvp_stats': binding.MvpStats,
+               'pqn_lcp_opts': binding.LcpOpts, 'pqn_lcp_stats': binding.LcpStats,
+               'pqn_step_stats': binding.StepStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bipqn.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / 'layout.c'
+    src.write_text('\n'.join(lines))
+    exe = tmp_path / 'layout'
+    subprocess.run([cc, '-I', os.path.dirname(HEADER), str(src), '-o', str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, f, v = ln.split()
+        got[(cname, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, 'size')] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+    # and no header field is missing from the binding
+    text = open(HEADER).read()
+    for cname, py in structs.items():
+        body = re.search(r'typedef struct \{([^{}]*)\}\s*' + cname + r';', text).group(1)
+        body = re.sub(r'/\*.*?\*/', '', body, flags=re.S)
+        names = []
+        for decl in body.split(';'):
+            decl = ' '.join(decl.split())
+            if not decl:
+                continue
+            m = re.match(r'.*\(\s*\*\s*(\w+)\s*\)', decl)
+            if m:  # function pointer
+                names.append(m.group(1))
+                continue
+            parts = decl.split(',')
+            names.append(re.findall(r'\w+', parts[0])[-1])
+            names += [re.findall(r'\w+', q)[-1] for q in parts[1:]]
+        assert names == [f for f, _ in py._fields_], (cname, names)

@@ -266,3 +266,64 @@ def test_bi_pqn_rec_step_and_errors(cases):
             ctx.lcp_solve(cs['pairs'], cs['b_pl'], 'birec')
         with pytest.raises(binding.PqnError):
             ctx.lcp_apply(cs['pairs'], np.ones(cs['pairs'].shape[0]), fidelity=binding.PQN_LOFI2)
+
+
+@pytest.mark.parametrize("solver", ["mono", "bb", "bi", "birec"])
+def test_lcp_solve_from_an_initial_guess_matches_oracle(cases, solver):
+    """x^(-1) given (a random guess with negative entries, projected on x >= 0): the device
+    reaches the brute-force solution, with the products of the oracle's solver started
+    from the same guess (within 1 high, 2 low)."""
+    kw = dict(tol_abs=1e-12, tol_rel=1e-15)
+    for cs in cases:
+        b = cs['b_pl']
+        g = np.random.default_rng(5).uniform(-0.5, 1.5, b.size)
+        xbf = lcp.brute_force_lcp(cs['Ad'], b)
+        Aop = lcp.lcp_operator(lambda F: bie.mobility_apply(cs['g'], F, dense=cs['A']), cs['c'], cs['pairs'])
+        Alo = lcp.lcp_operator(lambda F: bie.mobility_apply(cs['glo'], F, dense=cs['Alo']), cs['c'], cs['pairs'])
+        if solver == 'mono':
+            _, _, so = lcp.mono_pqn(Aop, b, x0=np.maximum(g, 0.0), **kw)
+            ref = (so['mvp'], 0)
+        elif solver == 'bb':
+            _, _, so = lcp.bb_pgd(Aop, b, x0=np.maximum(g, 0.0), tau0=3 * np.pi, k_max=500, **kw)
+            ref = (so['mvp'], 0)
+        elif solver == 'bi':
+            _, _, so = lcp.bi_pqn(Aop, Alo, b, x0=g, **kw)
+            ref = (so['mvp_hi'], so['mvp_lo'])
+        else:
+            Amid = _mid_operator(cs)[2]
+            _, _, so = lcp.bi_pqn_rec([Aop, Amid, Alo], b, x0=g, **kw)
+            ref = (so['mvp'][0], so['mvp'][1])
+        lo = dict(lo=(6, 12), lo2=(4, 8)) if solver == 'birec' else dict(lo=(4, 8))
+        with binding.Context(cs['c'], None, 8, 16, gmres_tol=1e-13, **lo) as ctx:
+            x, st = ctx.lcp_solve(cs['pairs'], b, solver, x0=g, k_max=500, **kw)
+        say('guess', solver, st['mvp_hi'], st['mvp_lo'], 'oracle', ref)
+        assert st['converged'] == 1
+        assert np.abs(x - xbf).max() <= 1e-10 * np.abs(xbf).max()
+        assert abs(st['mvp_hi'] - ref[0]) <= 1 and abs(st['mvp_lo'] - ref[1]) <= 2
+        assert 0.0 <= st['kkt_rel'] < 1.0
+
+
+def test_lcp_solve_dev_matches_host_arrays(cases):
+    """pqn_lcp_solve_dev on device pointers: the same solution and counts as the host-array
+    entry point, guess included; an invalid pair is rejected and x is left as it was."""
+    import torch
+    cs = cases[0]
+    b = cs['b_pl']
+    n = b.size
+    g = np.random.default_rng(6).uniform(-0.5, 1.5, n)
+    with binding.Context(cs['c'], None, 8, 16, lo=(4, 8), gmres_tol=1e-12) as ctx:
+        xh, sh = ctx.lcp_solve(cs['pairs'], b, 'bi', x0=g)
+        P = torch.as_tensor(np.ascontiguousarray(cs['pairs'], dtype=np.int32), device='cuda')
+        B = torch.as_tensor(b, dtype=torch.float64, device='cuda')
+        X = torch.as_tensor(g, dtype=torch.float64, device='cuda')
+        torch.cuda.synchronize()
+        sd = ctx.lcp_solve_dev(n, P.data_ptr(), B.data_ptr(), X.data_ptr(), 'bi')
+        assert np.array_equal(X.cpu().numpy(), xh)
+        assert (sd['mvp_hi'], sd['mvp_lo'], sd['iters']) == (sh['mvp_hi'], sh['mvp_lo'], sh['iters'])
+        Pbad = P.clone()
+        Pbad[0, 1] = 99
+        X2 = X.clone()
+        torch.cuda.synchronize()
+        with pytest.raises(binding.PqnError):
+            ctx.lcp_solve_dev(n, Pbad.data_ptr(), B.data_ptr(), X2.data_ptr(), 'mono')
+        assert torch.equal(X2, X)
