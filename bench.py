@@ -93,6 +93,9 @@ def main():
     ap.add_argument('--chunks', type=int, default=None, help='far source chunks (default: autotuned)')
     ap.add_argument('--split', type=int, default=None, choices=(0, 1),
                     help='far FP32 split layout, 64 targets per block (default: autotuned)')
+    ap.add_argument('--serial', action='store_true',
+                    help='one stream everywhere (no side stream beside the far pair sum): every kernel runs '
+                         'alone, as in the profiles of individual kernels')
     ap.add_argument('--counters-probe', action='store_true',
                     help='short run for rocprofv3 --pmc: a 256 MiB device copy (scale reference for FETCH_SIZE/'
                          'WRITE_SIZE) and one six-force-set product on the 216-sphere workload')
@@ -122,11 +125,16 @@ def main():
     K, W = args.steps, args.warmup
     pf = far_pairs(c, n)
 
-    def ctx_for(prec, kr=K_RHS, profile=True, warm_start=False):
-        """Context with the launch layout tuned for kr densities per pass (unless fixed on the command line)."""
+    def ctx_for(prec, kr=K_RHS, profile=True, warm_start=False, side=None):
+        """Context with the launch layout tuned for kr densities per pass (unless fixed on the command line).
+        side: run the GEMM / near / moment work on a second stream beside the far pair sum (default: for the
+        mixed path, where it measured 5-7% faster; the FP64 K = 6 pass was 2.5% slower with it). Profiled
+        contexts time the far kernel alone and keep one stream."""
+        if side is None:
+            side = prec == 'mixed' and not profile and not args.serial
         return binding.Context(c, None, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision=prec, tpt=args.tpt,
                                far_chunks=args.chunks, far_split=args.split, stream=stream.cuda_stream,
-                               profile=profile, tune_K=kr, warm_start=warm_start)
+                               profile=profile, tune_K=kr, warm_start=warm_start, side_stream=side)
 
     FT6 = [inputs.random_forces(100 + k, M, k=K_RHS) for k in range(max(K, 2) + W + 2)]
     # the timed products read forces from and write velocities to HBM (no host copies)
@@ -143,7 +151,7 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(ref)                      # reads and writes PROBE_BYTES once each
         torch.cuda.synchronize()
-        cm = ctx_for('mixed', profile=False)
+        cm = ctx_for('mixed', profile=False, side=False)  # per-dispatch counters: one kernel at a time
         _, st = cm.mobility_apply_multi(FT6[0])
         torch.cuda.synchronize()
         cm.close()
@@ -169,14 +177,23 @@ def main():
                     far_ms=far_ms / max(nfar, 1), matvecs_per_mvp=mv / (steps * kr), far_launches=nfar)
 
     res = {}
-    cm = ctx_for('mixed')
+    # headline: the library's fastest configuration (side stream on the mixed path), no event timing
+    cm = ctx_for('mixed', profile=False)
     res['mixed6'] = run_multi(cm, K, W, K_RHS)
     log('mixed K=6', res['mixed6'], cm.far_shape)
-    cm1 = ctx_for('mixed', 1)
+    # far-kernel timing (roofline): the same launches on one stream with HIP events around each far launch
+    with ctx_for('mixed', profile=True) as cp:
+        prof6 = run_multi(cp, K, W, K_RHS)
+    log('mixed K=6 far kernel alone', prof6)
+    cm1 = ctx_for('mixed', 1, profile=False)
     res['mixed1'] = run_multi(cm1, max(2, K // 2), 1, 1)
     log('mixed K=1', res['mixed1'], cm1.far_shape)
     layout1 = cm1.far_shape
     cm1.close()
+    with ctx_for('mixed', 1, profile=True) as cp1:
+        prof1 = run_multi(cp1, max(2, K // 2), 1, 1)
+    log('mixed K=1 far kernel alone', prof1)
+    res['mixed6']['far_ms'], res['mixed1']['far_ms'] = prof6['far_ms'], prof1['far_ms']
     cf = ctx_for('fp64')
     res['fp64_6'] = run_multi(cf, max(1, K // 3), 1, K_RHS)
     log('fp64 K=6', res['fp64_6'], cf.far_shape)

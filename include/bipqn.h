@@ -98,6 +98,9 @@ typedef struct {
   void* (*dev_alloc)(size_t bytes, void* user);
   void (*dev_free)(void* ptr, void* user);
   void* alloc_user;
+  int32_t side_stream;      /* 1 = the coefficient / self-interaction GEMMs, near tiles and rigid
+                               moments of an operator application run on a second stream of the
+                               library, concurrently with the far pair sum (same results) */
 } pqn_config_desc;
 
 typedef struct {

@@ -30,14 +30,25 @@ static void push_gemm(std::vector<GemmDesc>& v, int& blocks, int R, int Cn, int 
   v.push_back(d);
 }
 
-char* pqn_ctx_impl::push_desc_pack(const std::vector<char>& pack) {
-  if (pack.size() > ddesc.count) {
+char* pqn_ctx_impl::push_desc_pack(const std::vector<char>& pack) { return push_desc_pack(pack, stream, ddesc); }
+
+char* pqn_ctx_impl::push_desc_pack(const std::vector<char>& pack, hipStream_t st, DevArray<char>& table) {
+  if (pack.size() > table.count) {
     // growing the table: wait for kernels still reading the old one
-    HIPCHK(hipStreamSynchronize(stream));
-    ddesc.alloc(std::max<size_t>(pack.size() * 2, 1 << 16));
+    HIPCHK(hipStreamSynchronize(st));
+    table.alloc(std::max<size_t>(pack.size() * 2, 1 << 16));
   }
-  HIPCHK(hipMemcpyAsync(ddesc.p, pack.data(), pack.size(), hipMemcpyHostToDevice, stream));
-  return ddesc.p;
+  HIPCHK(hipMemcpyAsync(table.p, pack.data(), pack.size(), hipMemcpyHostToDevice, st));
+  return table.p;
+}
+
+hipStream_t pqn_ctx_impl::side_stream() {
+  if (!side) {
+    HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_side, hipEventDisableTiming));
+  }
+  return side;
 }
 
 Work& Level::wk(int k) {
@@ -78,6 +89,12 @@ pqn_ctx_impl::~pqn_ctx_impl() {
   for (auto& e : ev_pool) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
+  }
+  if (side) {
+    (void)hipStreamSynchronize(side);
+    (void)hipStreamDestroy(side);
+    (void)hipEventDestroy(ev_in);
+    (void)hipEventDestroy(ev_side);
   }
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
@@ -247,6 +264,19 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
     matvec_batched(groups, prec);
     return;
   }
+  // One group, side_stream on: the coefficient and self-interaction GEMMs, the
+  // near tiles and the rigid moments (none of which the far pair sum reads) run
+  // on a second stream, concurrently with the packing and far pair sum; the
+  // final combination waits for both.
+  const bool ov = cfg.side_stream && groups.size() == 1;
+  hipStream_t sa = s;
+  DevArray<char>* dtab = &ddesc;
+  if (ov) {
+    sa = side_stream();
+    dtab = &ddesc_side;
+    HIPCHK(hipEventRecord(ev_in, s));
+    HIPCHK(hipStreamWaitEvent(sa, ev_in, 0));
+  }
   for (MvGroup& gr : groups) {
     Level& lv = *gr.lv;
     pqn_ctx_impl& c = *gr.c;
@@ -273,9 +303,10 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
     }
     DescPack dp;
     const size_t oa = dp.add(ga), ob = dp.add(gb);
-    char* base = push_desc_pack(dp.host);
-    launch_gemm64_multi(s, (const GemmDesc*)(base + oa), (int)ga.size(), nga);
-    launch_gemm64_multi(s, (const GemmDesc*)(base + ob), (int)gb.size(), ngb);
+    char* base = push_desc_pack(dp.host, sa, *dtab);
+    launch_gemm64_multi(sa, (const GemmDesc*)(base + oa), (int)ga.size(), nga);
+    launch_gemm64_multi(sa, (const GemmDesc*)(base + ob), (int)gb.size(), ngb);
+    if (ov) side_work(gr, sa);
     launch_pack(s, prec, gr.K, qp, lv.off.p, lv.w.p, n, N, lv.src.p);
   }
   begin_far_timing();
@@ -290,46 +321,69 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
   }
   end_far_launch();
   ++n_far;
+  if (ov) {
+    HIPCHK(hipEventRecord(ev_side, sa));
+    HIPCHK(hipStreamWaitEvent(s, ev_side, 0));
+  }
   for (MvGroup& gr : groups) {
     Level& lv = *gr.lv;
     pqn_ctx_impl& c = *gr.c;
-    QPtrs cf{};
-    OPtrs np{};
-    for (int r = 0; r < gr.K; ++r) {
-      Work& w = lv.wk(gr.slot[r]);
-      cf.p[r] = w.coef.p;
-      np.p[r] = w.near_part.p;
-    }
-    const double* qup = lv.wk(gr.slot[0]).qup.p;
-    launch_near(s, gr.K, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, qup, cf, c.near_list.p, lv.n, lv.M, lv.N,
-                lv.nup, lv.p, lv.L, 3.0 / (4.0 * kPi * c.a), np);
+    if (!ov) side_work(gr, s);
     if (gr.K == 1) {
       Work& w = lv.wk(gr.slot[0]);
-      launch_moments(s, gr.in[0], lv.off.p, lv.w.p, lv.n, lv.M, lv.N, w.mom.p);
       launch_combine(s, gr.in[0], w.selfo.p, 3, w.far_part.p, lv.nchunks, w.near_part.p, c.npart.p, w.mom.p,
                      lv.off.p, lv.n, lv.N, c.a, gr.out[0]);
     } else {
-      // rigid moments and the final combination of all K densities, one launch each
-      std::vector<MomDesc> md;
+      // the final combination of all K densities, one launch
       std::vector<CombDesc> cd;
-      int nmd = 0, ncd = 0;
+      int ncd = 0;
       for (int r = 0; r < gr.K; ++r) {
         Work& w = lv.wk(gr.slot[r]);
-        md.push_back(MomDesc{gr.in[r], lv.off.p, lv.w.p, w.mom.p, lv.n, lv.N, nmd});
-        nmd += lv.M;
         cd.push_back(CombDesc{gr.in[r], w.selfo.p, w.far_part.p, w.near_part.p, c.npart.p, w.mom.p, lv.off.p,
                               gr.out[r], c.a, lv.nchunks, lv.n, lv.N, ncd});
         ncd += 3 * lv.N;
       }
       DescPack dp;
-      const size_t om = dp.add(md), oc = dp.add(cd);
+      const size_t oc = dp.add(cd);
       char* base = push_desc_pack(dp.host);
-      launch_moments_multi(s, (const MomDesc*)(base + om), (int)md.size(), nmd);
       launch_combine_multi(s, (const CombDesc*)(base + oc), (int)cd.size(), ncd);
     }
     n_matvec += gr.K;
   }
   HIPCHK(hipGetLastError());
+}
+
+// Near tiles and rigid moments of one group on stream st (after its GEMMs on st).
+void pqn_ctx_impl::side_work(MvGroup& gr, hipStream_t st) {
+  Level& lv = *gr.lv;
+  pqn_ctx_impl& c = *gr.c;
+  QPtrs cf{};
+  OPtrs np{};
+  for (int r = 0; r < gr.K; ++r) {
+    Work& w = lv.wk(gr.slot[r]);
+    cf.p[r] = w.coef.p;
+    np.p[r] = w.near_part.p;
+  }
+  const double* qup = lv.wk(gr.slot[0]).qup.p;
+  launch_near(st, gr.K, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, qup, cf, c.near_list.p, lv.n, lv.M, lv.N,
+              lv.nup, lv.p, lv.L, 3.0 / (4.0 * kPi * c.a), np);
+  if (gr.K == 1) {
+    Work& w = lv.wk(gr.slot[0]);
+    launch_moments(st, gr.in[0], lv.off.p, lv.w.p, lv.n, lv.M, lv.N, w.mom.p);
+  } else {
+    std::vector<MomDesc> md;
+    int nmd = 0;
+    for (int r = 0; r < gr.K; ++r) {
+      Work& w = lv.wk(gr.slot[r]);
+      md.push_back(MomDesc{gr.in[r], lv.off.p, lv.w.p, w.mom.p, lv.n, lv.N, nmd});
+      nmd += lv.M;
+    }
+    // own descriptor table per stream; on the main stream it follows the GEMMs' use of it
+    DescPack dp;
+    const size_t om = dp.add(md);
+    char* base = st == stream ? push_desc_pack(dp.host) : push_desc_pack(dp.host, st, ddesc_side);
+    launch_moments_multi(st, (const MomDesc*)(base + om), (int)md.size(), nmd);
+  }
 }
 
 // Many suspensions (one density each): every phase of the operator is one

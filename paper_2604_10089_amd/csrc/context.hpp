@@ -215,6 +215,13 @@ struct pqn_ctx_impl {
   DevArray<FarDesc> fdesc;
   DevArray<char> ddesc;  // segment descriptors of the multi-suspension kernels
   char* push_desc_pack(const std::vector<char>& pack);
+  char* push_desc_pack(const std::vector<char>& pack, hipStream_t st, DevArray<char>& table);
+  // second stream for work that overlaps the far pair sum (config side_stream)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_in = nullptr, ev_side = nullptr;
+  DevArray<char> ddesc_side;  // descriptor table of the side stream's segmented launches
+  hipStream_t side_stream();
+  void side_work(MvGroup& gr, hipStream_t st);
   // profiling of far launches
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   size_t ev_used = 0;
