@@ -73,7 +73,9 @@ typedef struct {
   int32_t near_up;          /* upsampling factor of the near rule [2] */
   double slip_speed;        /* Janus slip magnitude s [1] */
   int32_t precision;        /* pqn_precision of the far-field pair sums [PQN_FP64] */
-  int32_t refine_sweeps;    /* mixed precision: outer refinement sweeps with an FP64 residual [0] */
+  int32_t refine_sweeps;    /* mixed precision: outer refinement sweeps with an FP64 residual [0];
+                               a system still above tolerance after them gets one FP64 correction
+                               solve (counted in pqn_mvp_stats.fp64_fallback) */
   int32_t targets_per_thread; /* far FP32 kernel: 1 or 2 targets per thread, 256 threads per block [2] */
   int32_t far_chunks;       /* far kernels: source-sphere chunks (grid y); 0 = automatic */
   int32_t far_split;        /* far FP32 kernel: 1 = 64 targets per block, its four waves split each
@@ -113,6 +115,9 @@ typedef struct {
   double t_far_ms;          /* summed far pair-sum kernel time (profile = 1) */
   int32_t n_far;            /* far pair-sum launches */
   int32_t graph_launches;   /* GMRES iterations replayed from captured graphs (use_graphs = 1) */
+  int32_t fp64_fallback;    /* mixed precision with refine_sweeps > 0: systems whose FP64 residual was
+                               still above tolerance after the sweeps and were finished by an FP64
+                               correction solve */
 } pqn_mvp_stats;
 
 typedef struct {

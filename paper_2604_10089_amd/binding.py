@@ -72,7 +72,8 @@ class TorchAllocator:
 class MvpStats(C.Structure):
     _fields_ = [('gmres_iters', C.c_int32), ('matvecs', C.c_int32), ('refine_sweeps', C.c_int32),
                 ('converged', C.c_int32), ('rel_residual', C.c_double), ('t_total_ms', C.c_double),
-                ('t_far_ms', C.c_double), ('n_far', C.c_int32), ('graph_launches', C.c_int32)]
+                ('t_far_ms', C.c_double), ('n_far', C.c_int32), ('graph_launches', C.c_int32),
+                ('fp64_fallback', C.c_int32)]
 
 
 class LcpOpts(C.Structure):

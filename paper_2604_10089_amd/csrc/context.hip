@@ -864,7 +864,7 @@ void pqn_ctx_impl::solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st) {
   gmres_lockstep(sys, prec);
   int its = 0;
   for (SysRef& r : sys) its += r.its;
-  int sweeps = 0;
+  int sweeps = 0, fallback = 0;
   if (prec == PQN_MIXED && cfg.refine_sweeps > 0) {
     const int ns = (int)sys.size();
     std::vector<double> bn(ns);
@@ -872,7 +872,9 @@ void pqn_ctx_impl::solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st) {
       const long len = 3L * sys[i].lv->N;
       bn[i] = std::sqrt(dot_host(sys[i].rhs, sys[i].rhs, len, *sys[i].lv));
     }
-    for (int sw = 0; sw < cfg.refine_sweeps; ++sw) {
+    // checks 0..R (R = refine_sweeps) are each followed by a correction solve: mixed after
+    // checks 0..R-1 (the sweeps), FP64 after check R (the fallback); check R+1 only measures
+    for (int sw = 0; sw <= cfg.refine_sweeps + 1; ++sw) {
       std::vector<MvGroup> groups;
       for (int i = 0; i < ns; ++i) {
         SysBuf& b = sys[i].lv->sb(sys[i].slot);
@@ -894,19 +896,25 @@ void pqn_ctx_impl::solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st) {
           owner.push_back(i);
         }
       }
-      if (corr.empty()) break;
-      ++sweeps;
-      gmres_lockstep(corr, prec);  // corrections d for A_mixed d = rhs - A64 x
+      if (corr.empty() || sw == cfg.refine_sweeps + 1) break;
+      // after the last sweep's residual check, a system still above tolerance is finished in
+      // FP64: the correction solve then runs with the FP64 operator
+      const bool fb = sw == cfg.refine_sweeps;
+      if (fb)
+        fallback += (int)corr.size();
+      else
+        ++sweeps;
+      gmres_lockstep(corr, fb ? PQN_FP64 : prec);  // corrections d for A d = rhs - A64 x
       for (size_t j = 0; j < corr.size(); ++j) {
         its += corr[j].its;
-        const int i = owner[j];
-        launch_axpby(stream, sys[i].x, corr[j].x, 1.0, 1.0, 3L * sys[i].lv->N);
+        launch_axpby(stream, sys[owner[j]].x, corr[j].x, 1.0, 1.0, 3L * sys[owner[j]].lv->N);
       }
     }
   }
   if (st) {
     st->gmres_iters += its;
     st->refine_sweeps += sweeps;
+    st->fp64_fallback += fallback;
     double rr = 0.0;
     bool conv = true;
     for (SysRef& r : sys) {

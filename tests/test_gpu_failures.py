@@ -1,0 +1,72 @@
+"""Failure handling forced from the host: iteration caps, non-finite inputs, and the
+mixed-precision monitor that finishes a stalled solve in FP64. Every kernel exits
+normally; only statuses and statistics are checked."""
+import numpy as np
+import pytest
+
+from oracle import bie
+from paper_2604_10089_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+PQN_ERR_NUMERIC = -4
+
+
+def _tiny():
+    return inputs.workload('tiny', 0)['centers']
+
+
+def test_gmres_iteration_cap_warns_and_returns_the_iterate():
+    c = _tiny()
+    F = inputs.random_forces(4, c.shape[0])
+    with binding.Context(c, None, 8, 16, max_iter=3, gmres_tol=1e-12) as ctx:
+        U, st = ctx.mobility_apply(F)
+    assert st['status'] == binding.PQN_WARN_NOT_CONVERGED
+    assert st['converged'] == 0 and st['gmres_iters'] == 3
+    assert np.all(np.isfinite(U)) and st['rel_residual'] > 1e-12
+
+
+def test_non_finite_inputs_are_rejected():
+    c = _tiny()
+    F = inputs.random_forces(4, c.shape[0])
+    F[3, 2] = np.nan
+    with binding.Context(c, None, 8, 16) as ctx:
+        with pytest.raises(binding.PqnError) as e:
+            ctx.mobility_apply(F)
+        assert e.value.status == PQN_ERR_NUMERIC
+        bad = c.copy()
+        bad[1, 0] = np.inf
+        with pytest.raises(binding.PqnError) as e:
+            ctx.set_state(bad)
+        assert e.value.status == PQN_ERR_NUMERIC
+
+
+def test_lcp_iteration_cap_warns():
+    c = _tiny()
+    with binding.Context(c, None, 8, 16, lo=(4, 8)) as ctx:
+        pairs, _ = ctx.find_contacts(0.1)
+        xs, ws = inputs.planted_lcp(0, pairs.shape[0])
+        b = ws - ctx.lcp_apply(pairs, xs)
+        for solver in ('mono', 'bb', 'bi'):
+            x, st = ctx.lcp_solve(pairs, b, solver, k_max=1, tol_abs=1e-14, tol_rel=1e-16)
+            assert st['status'] == binding.PQN_WARN_NOT_CONVERGED and st['converged'] == 0, solver
+            assert np.all(np.isfinite(x)) and x.min() >= 0.0
+
+
+def test_mixed_solve_finished_in_fp64_when_refinement_stalls():
+    """A tolerance no arithmetic reaches (1e-17) with one refinement sweep: the FP64
+    residual is still above it after the sweep, so the monitor runs the FP64
+    correction solve (fp64_fallback = 1), the call warns, and the result is the FP64
+    solution to FP64 accuracy."""
+    c = _tiny()
+    F = inputs.random_forces(5, c.shape[0])
+    with binding.Context(c, None, 8, 16, precision='mixed', refine=1, gmres_tol=1e-17, max_iter=80) as ctx:
+        U, st = ctx.mobility_apply(F)
+    with binding.Context(c, None, 8, 16, precision='fp64', gmres_tol=1e-13) as cf:
+        Uf, _ = cf.mobility_apply(F)
+    assert st['fp64_fallback'] == 1 and st['refine_sweeps'] == 1
+    assert st['status'] == binding.PQN_WARN_NOT_CONVERGED
+    assert np.abs(U - Uf).max() < 1e-11 * np.abs(Uf).max()
+    g = bie.Geometry(c, 1.0, 8, 16)
+    Uo = bie.mobility_apply(g, F, dense=bie.dense_operator(g))
+    assert np.abs(U - Uo).max() < 1e-11 * np.abs(Uo).max()
