@@ -222,6 +222,7 @@ def main():
         x2, lm = cm.lcp_solve(pairs, b, 'mono')
         t2 = time.perf_counter()
         x3, lb = cm.lcp_solve(pairs, b, 'bb')
+        t2b = time.perf_counter()
         # the other fidelity axis of the method: same grid, GMRES tolerance 1e-3 for the model
         # and recursive Bi-PQN over three fidelities: that model, then the coarse grid at 1e-3
         with binding.Context(c, None, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3, lo2=w['lo'],
@@ -238,7 +239,8 @@ def main():
                                 x_rel_err=float(np.abs(x - xs).max() / np.abs(xs).max())),
                         mono=dict(sec=round(t2 - t1, 3), mvp=lm['mvp_hi'],
                                   x_rel_err=float(np.abs(x2 - xs).max() / np.abs(xs).max())),
-                        bbpgd=dict(mvp=lb['mvp_hi'], x_rel_err=float(np.abs(x3 - xs).max() / np.abs(xs).max())),
+                        bbpgd=dict(sec=round(t2b - t2, 3), mvp=lb['mvp_hi'],
+                                   x_rel_err=float(np.abs(x3 - xs).max() / np.abs(xs).max())),
                         bi_tol_fidelity=dict(lo=f'{nt}x{nph} at GMRES 1e-3', sec=round(t4 - t3, 3),
                                              mvp_hi=lt['mvp_hi'], mvp_lo=lt['mvp_lo'], emvp=round(lt['emvp'], 2),
                                              lo_hi_cost_ratio=round(lt['lo_hi_cost_ratio'], 4),
@@ -250,6 +252,9 @@ def main():
                                           cost_ratios=[round(lr['lo_hi_cost_ratio'], 4),
                                                        round(lr['lo2_hi_cost_ratio'], 4)],
                                           x_rel_err=float(np.abs(x5 - xs).max() / np.abs(xs).max())))
+        for v in lcp_info.values():
+            if isinstance(v, dict) and v.get('sec'):
+                v['solves_per_s'] = round(1.0 / v['sec'], 3)
         log('lcp', lcp_info)
     cm_layout = cm.far_shape
     cm.close()
@@ -336,6 +341,7 @@ def main():
     m6 = res['mixed6']
     achieved = flop_per_pair(K_RHS) * pf / (m6['far_ms'] * 1e-3) / 1e12
     achieved1 = flop_per_pair(1) * pf / (res['mixed1']['far_ms'] * 1e-3) / 1e12
+    achieved64 = flop_per_pair(K_RHS) * pf / (res['fp64_6']['far_ms'] * 1e-3) / 1e12
     out = {
         'metric': 'batched mobility MVPs/s (216 spheres, 6 force sets per pass, mixed FP32/FP64, GMRES 1e-8)',
         'value': round(m6['mvps'], 4),
@@ -348,6 +354,13 @@ def main():
                                '6 random force sets per step, GMRES tol 1e-8', 'n_nodes': M * n,
                    'force_sets_per_step': K_RHS, 'far_pairs_per_matvec': int(pf)},
         'gpair_evals_per_s': round(m6['matvecs_per_mvp'] * pf * m6['mvps'] / 1e9, 2),
+        # far (target, source) node-pair evaluations per second: pair-density products for the
+        # six-force-set passes (geometry shared by the six), pairs for the single force set
+        'gpair_evals_per_s_detail': {
+            'mixed_K6_pair_density': round(m6['matvecs_per_mvp'] * pf * m6['mvps'] / 1e9, 2),
+            'mixed_K1': round(res['mixed1']['matvecs_per_mvp'] * pf * res['mixed1']['mvps'] / 1e9, 2),
+            'fp64_K6_pair_density': round(res['fp64_6']['matvecs_per_mvp'] * pf * res['fp64_6']['mvps'] / 1e9, 2),
+            'fp64_K1': round(res['fp64_1']['matvecs_per_mvp'] * pf * res['fp64_1']['mvps'] / 1e9, 2)},
         'single_mvps_per_s': {'mixed': round(res['mixed1']['mvps'], 4), 'fp64': round(res['fp64_1']['mvps'], 4)},
         'batched_mvps_per_s': {'mixed': round(m6['mvps'], 4), 'fp64': round(res['fp64_6']['mvps'], 4)},
         'speedup_mixed_vs_fp64': {'K6': round(m6['mvps'] / res['fp64_6']['mvps'], 3),
@@ -361,7 +374,9 @@ def main():
                      'traffic': far_traffic_bytes(cm_layout),
                      'traffic_unit': 'HBM bytes per launch',
                      'k1': {'kernel': far_kernel_name(layout1, 1), 'layout': layout1, 'achieved': round(achieved1, 3),
-                            'frac': round(achieved1 / PEAK_FP32_VECTOR, 4)}},
+                            'frac': round(achieved1 / PEAK_FP32_VECTOR, 4)},
+                     'fp64': {'kernel': f'k_far64<{K_RHS}>', 'achieved': round(achieved64, 3),
+                              'peak': PEAK_FP64_VECTOR, 'frac': round(achieved64 / PEAK_FP64_VECTOR, 4)}},
         'lcp': lcp_info,
         'batch32': batch_info,
         'time_steps': step_info,
