@@ -265,7 +265,7 @@ def main():
         # warm-started from the previous step): the FP64 trajectory, and the mixed path replayed
         # from each FP64 state
         axes = inputs.janus_axes(args.seed + 7, M)
-        nsteps, dt = 3, 1e-3
+        nsteps, dt = 10, 1e-3
         states, t64, st64 = [(c, axes)], [], []
         with ctx_for('fp64', 1, profile=False, warm_start=True) as cs:
             cs.set_state(c, axes)
@@ -276,17 +276,24 @@ def main():
                 t64.append(time.perf_counter() - t0)
                 st64.append(st)
                 states.append(cs.get_state())
-        tmx, dmax = [], 0.0
-        with ctx_for('mixed', 1, profile=False, warm_start=True) as cs:
-            for k in range(nsteps):
-                cs.set_state(*states[k])
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                cs.step(dt, 0.1, 'bi')
-                tmx.append(time.perf_counter() - t0)
-                cm_k, _ = cs.get_state()
-                disp = states[k + 1][0] - states[k][0]
-                dmax = max(dmax, float(np.abs(cm_k - states[k + 1][0]).max() / np.abs(disp).max()))
+        mixed = {}
+        for name, refine in (('mixed', 0), ('mixed_refined', 1)):
+            tmx, dmax = [], 0.0
+            with binding.Context(c, None, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='mixed', refine=refine,
+                                 tpt=args.tpt, far_chunks=args.chunks, far_split=args.split,
+                                 stream=stream.cuda_stream, tune_K=1, warm_start=True,
+                                 side_stream=not args.serial) as cs:
+                for k in range(nsteps):
+                    cs.set_state(*states[k])
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    cs.step(dt, 0.1, 'bi')
+                    tmx.append(time.perf_counter() - t0)
+                    cm_k, _ = cs.get_state()
+                    disp = states[k + 1][0] - states[k][0]
+                    dmax = max(dmax, float(np.abs(cm_k - states[k + 1][0]).max() / np.abs(disp).max()))
+            mixed[name] = (tmx, dmax)
+        tmx, dmax = mixed['mixed']
         step_info = dict(steps=nsteps, dt=dt, contacts=[s_['n_contacts'] for s_ in st64],
                          active=[s_['n_active'] for s_ in st64],
                          mvp_hi=[s_['lcp']['mvp_hi'] for s_ in st64], mvp_lo=[s_['lcp']['mvp_lo'] for s_ in st64],
@@ -294,7 +301,9 @@ def main():
                          sec_per_step_fp64=round(float(np.median(t64)), 4),
                          sec_per_step_mixed=round(float(np.median(tmx)), 4),
                          speedup=round(float(np.median(t64) / np.median(tmx)), 3),
-                         mixed_displacement_rel_err=dmax)
+                         mixed_displacement_rel_err=dmax,
+                         sec_per_step_mixed_refined=round(float(np.median(mixed['mixed_refined'][0])), 4),
+                         mixed_refined_displacement_rel_err=mixed['mixed_refined'][1])
         log('steps', step_info)
 
     batch_info = None
