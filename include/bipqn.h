@@ -82,7 +82,8 @@ typedef struct {
                                chunk's sources and add their sums in LDS (targets_per_thread ignored) */
   int32_t device;           /* HIP device ordinal [0] */
   void* stream;             /* hipStream_t to run on; NULL = the library creates one */
-  int32_t profile;          /* 1 = time every far pair-sum launch with HIP events */
+  int32_t profile;          /* 1 = time every far pair-sum launch (and the other operator stages) with
+                               HIP events; work then stays on one stream (side_stream ignored) */
   int32_t use_graphs;       /* 1 = replay each GMRES iteration of a single linear system from a
                                captured hipGraph (one per Arnoldi index; ignored when profile = 1) */
   int32_t warm_start;       /* 1 = the slip-driven solve (U_nc, also inside pqn_step) starts GMRES
@@ -118,6 +119,11 @@ typedef struct {
   int32_t fp64_fallback;    /* mixed precision with refine_sweeps > 0: systems whose FP64 residual was
                                still above tolerance after the sweeps and were finished by an FP64
                                correction solve */
+  /* profile = 1: summed HIP-event times of the other operator stages (one stream) */
+  double t_near_ms;         /* near tiles */
+  double t_gemm_ms;         /* harmonic coefficients, self interaction and upsampling GEMMs */
+  double t_local_ms;        /* packing, rigid moments and the final combination */
+  double t_arnoldi_ms;      /* CGS2 dot products and vector updates of GMRES */
 } pqn_mvp_stats;
 
 typedef struct {

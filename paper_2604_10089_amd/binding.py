@@ -73,7 +73,8 @@ class MvpStats(C.Structure):
     _fields_ = [('gmres_iters', C.c_int32), ('matvecs', C.c_int32), ('refine_sweeps', C.c_int32),
                 ('converged', C.c_int32), ('rel_residual', C.c_double), ('t_total_ms', C.c_double),
                 ('t_far_ms', C.c_double), ('n_far', C.c_int32), ('graph_launches', C.c_int32),
-                ('fp64_fallback', C.c_int32)]
+                ('fp64_fallback', C.c_int32), ('t_near_ms', C.c_double), ('t_gemm_ms', C.c_double),
+                ('t_local_ms', C.c_double), ('t_arnoldi_ms', C.c_double)]
 
 
 class LcpOpts(C.Structure):

@@ -44,7 +44,9 @@ def build(verbose=False, jobs=None):
         if verbose and text.strip():
             print(text)
     tmp = LIB + '.tmp'
-    cmd = [cc, '-shared', '-fPIC', f'--offload-arch={ARCH}', '-o', tmp] + objs
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(cc))), 'lib')
+    cmd = [cc, '-shared', '-fPIC', f'--offload-arch={ARCH}', '-o', tmp] + objs + [
+        f'-L{rocm_lib}', f'-Wl,-rpath,{rocm_lib}', '-lrocprofiler-sdk-roctx']
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
     if r.returncode != 0:
         raise RuntimeError('link failed:\n' + r.stdout.decode(errors='replace'))

@@ -42,6 +42,14 @@ static void fill_defaults(pqn_config_desc& c) {
 
 static bool is_batch(const pqn_ctx* ctx) { return ctx && ctx->is_batch; }
 
+// Stage times of the last call (profile = 1), after end_far_timing.
+static void stage_stats(const pqn_ctx_impl& c, pqn_mvp_stats& st) {
+  st.t_near_ms = c.stage_ms[pqn_ctx_impl::kStageNear];
+  st.t_gemm_ms = c.stage_ms[pqn_ctx_impl::kStageGemm];
+  st.t_local_ms = c.stage_ms[pqn_ctx_impl::kStageLocal];
+  st.t_arnoldi_ms = c.stage_ms[pqn_ctx_impl::kStageArnoldi];
+}
+
 // nullptr if the context has the fidelities the (valid) solver needs, else the reason.
 static const char* solver_unavailable(const pqn_ctx_impl& c, int solver) {
   if (solver == PQN_BI && !c.has_lo) return "Bi-PQN needs a low-fidelity grid";
@@ -166,6 +174,7 @@ pqn_status pqn_batch_create(int32_t n_inst, const pqn_config_desc* descs, const 
 pqn_status pqn_batch_mobility_apply(pqn_ctx* ctx, const double* const* FT, double* const* UO, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_batch_mobility_apply");
     if (!ctx || !FT || !UO) return fail(PQN_ERR_INVALID, "pqn_batch_mobility_apply: NULL argument");
     if (!ctx->is_batch) return fail(PQN_ERR_STATE, "pqn_batch_mobility_apply needs a batch context");
     HIPCHK(hipSetDevice(ctx->device));
@@ -199,6 +208,7 @@ pqn_status pqn_batch_mobility_apply(pqn_ctx* ctx, const double* const* FT, doubl
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     st.t_far_ms = ctx->end_far_timing();
+    stage_stats(*ctx, st);
     st.matvecs = ctx->n_matvec;
     st.n_far = ctx->n_far;
     st.graph_launches = ctx->n_graph_launch;
@@ -227,6 +237,7 @@ static pqn_status mobility_multi_common(pqn_ctx* ctx, int32_t k_rhs, const doubl
   ctx->mobility_multi(lv, k_rhs, fp, nullptr, up, &st);
   HIPCHK(hipStreamSynchronize(ctx->stream));
   st.t_far_ms = ctx->end_far_timing();
+    stage_stats(*ctx, st);
   st.matvecs = ctx->n_matvec;
   st.n_far = ctx->n_far;
   st.graph_launches = ctx->n_graph_launch;
@@ -239,6 +250,7 @@ pqn_status pqn_mobility_apply_multi(pqn_ctx* ctx, int32_t k_rhs, const double* F
                                     pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_mobility_apply_multi");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_mobility_apply_multi needs a single-suspension context");
     if (!ctx || !FT || !UO || k_rhs < 1 || k_rhs > kMaxRhs)
       return fail(PQN_ERR_INVALID, "pqn_mobility_apply_multi: bad argument (1 <= k_rhs <= 6)");
@@ -258,6 +270,7 @@ pqn_status pqn_mobility_apply_multi_dev(pqn_ctx* ctx, int32_t k_rhs, const doubl
                                         int32_t fidelity, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_mobility_apply_multi_dev");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_mobility_apply_multi_dev needs a single-suspension context");
     if (!ctx || !FT_dev || !UO_dev || k_rhs < 1 || k_rhs > kMaxRhs)
       return fail(PQN_ERR_INVALID, "pqn_mobility_apply_multi_dev: bad argument (1 <= k_rhs <= 6)");
@@ -270,6 +283,7 @@ pqn_status pqn_destroy(pqn_ctx* ctx) {
   if (!ctx) return PQN_OK;
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_destroy");
     HIPCHK(hipSetDevice(ctx->device));
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     delete static_cast<pqn_ctx_impl*>(ctx);
@@ -280,6 +294,7 @@ pqn_status pqn_destroy(pqn_ctx* ctx) {
 pqn_status pqn_set_state(pqn_ctx* ctx, const double* centers, const double* janus_axes) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_set_state");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_set_state needs a single-suspension context");
     if (!ctx || !centers) return fail(PQN_ERR_INVALID, "pqn_set_state: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
@@ -315,6 +330,7 @@ static pqn_status mobility_common(pqn_ctx* ctx, const double* FT_dev, const doub
   ctx->mobility(lv, FT_dev, axes_dev, UO_dev, &st);
   HIPCHK(hipStreamSynchronize(ctx->stream));
   st.t_far_ms = ctx->end_far_timing();
+    stage_stats(*ctx, st);
   st.matvecs = ctx->n_matvec;
   st.n_far = ctx->n_far;
   st.graph_launches = ctx->n_graph_launch;
@@ -327,6 +343,7 @@ pqn_status pqn_mobility_apply_dev(pqn_ctx* ctx, const double* FT_dev, double* UO
                                   pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_mobility_apply_dev");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_mobility_apply_dev needs a single-suspension context");
     if (!ctx || !FT_dev || !UO_dev) return fail(PQN_ERR_INVALID, "pqn_mobility_apply_dev: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
@@ -337,6 +354,7 @@ pqn_status pqn_mobility_apply_dev(pqn_ctx* ctx, const double* FT_dev, double* UO
 pqn_status pqn_mobility_apply(pqn_ctx* ctx, const double* FT, double* UO, int32_t fidelity, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_mobility_apply");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_mobility_apply needs a single-suspension context");
     if (!ctx || !FT || !UO) return fail(PQN_ERR_INVALID, "pqn_mobility_apply: NULL argument");
     for (int k = 0; k < 6 * ctx->M; ++k)
@@ -353,6 +371,7 @@ pqn_status pqn_mobility_apply(pqn_ctx* ctx, const double* FT, double* UO, int32_
 pqn_status pqn_nc_velocity(pqn_ctx* ctx, double* UO, int32_t fidelity, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_nc_velocity");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_nc_velocity needs a single-suspension context");
     if (!ctx || !UO) return fail(PQN_ERR_INVALID, "pqn_nc_velocity: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
@@ -371,6 +390,7 @@ pqn_status pqn_nc_velocity(pqn_ctx* ctx, double* UO, int32_t fidelity, pqn_mvp_s
 pqn_status pqn_bie_apply(pqn_ctx* ctx, int32_t fidelity, const double* q, double* y) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_bie_apply");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_bie_apply needs a single-suspension context");
     if (!ctx || !q || !y) return fail(PQN_ERR_INVALID, "pqn_bie_apply: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
@@ -389,6 +409,7 @@ pqn_status pqn_bie_apply(pqn_ctx* ctx, int32_t fidelity, const double* q, double
 pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, double* q, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_bie_solve");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_bie_solve needs a single-suspension context");
     if (!ctx || !rhs || !q) return fail(PQN_ERR_INVALID, "pqn_bie_solve: NULL argument");
     HIPCHK(hipSetDevice(ctx->device));
@@ -406,6 +427,7 @@ pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, doub
     HIPCHK(hipMemcpyAsync(q, b.x.p, len * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     st.t_far_ms = ctx->end_far_timing();
+    stage_stats(*ctx, st);
     st.matvecs = ctx->n_matvec;
     st.n_far = ctx->n_far;
     st.graph_launches = ctx->n_graph_launch;
@@ -418,6 +440,7 @@ pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, doub
 pqn_status pqn_get_self_block(pqn_ctx* ctx, int32_t fidelity, double* S) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_get_self_block");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_get_self_block needs a single-suspension context");
     if (!ctx || !S) return fail(PQN_ERR_INVALID, "pqn_get_self_block: NULL argument");
     Level& lv = ctx->level(fidelity);
@@ -429,6 +452,7 @@ pqn_status pqn_get_self_block(pqn_ctx* ctx, int32_t fidelity, double* S) {
 pqn_status pqn_get_grid(pqn_ctx* ctx, int32_t fidelity, int32_t* n_nodes, double* offsets, double* weights) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_get_grid");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_get_grid needs a single-suspension context");
     if (!ctx) return fail(PQN_ERR_INVALID, "pqn_get_grid: NULL context");
     Level& lv = ctx->level(fidelity);
@@ -455,6 +479,7 @@ pqn_status pqn_host_self_block(int32_t n_theta, int32_t n_phi, double radius, do
 pqn_status pqn_find_contacts(pqn_ctx* ctx, double delta, int32_t cap, int32_t* n_out, int32_t* pairs, double* gaps) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_find_contacts");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_find_contacts needs a single-suspension context");
     if (!ctx || !n_out || (cap > 0 && (!pairs || !gaps)) || cap < 0)
       return fail(PQN_ERR_INVALID, "pqn_find_contacts: bad argument");
@@ -471,6 +496,7 @@ pqn_status pqn_lcp_apply(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const do
                          int32_t fidelity) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_lcp_apply");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_lcp_apply needs a single-suspension context");
     if (!ctx || n < 0 || (n > 0 && (!pairs || !x || !Ax))) return fail(PQN_ERR_INVALID, "pqn_lcp_apply: bad argument");
     HIPCHK(hipSetDevice(ctx->device));
@@ -483,6 +509,7 @@ pqn_status pqn_lcp_solve(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const do
                          const pqn_lcp_opts* opts, pqn_lcp_stats* stats) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_lcp_solve");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_lcp_solve needs a single-suspension context");
     if (!ctx || n < 0 || (n > 0 && (!pairs || !b || !x))) return fail(PQN_ERR_INVALID, "pqn_lcp_solve: bad argument");
     if (solver < PQN_BBPGD || solver > PQN_BI_REC) return fail(PQN_ERR_INVALID, "bad solver");
@@ -497,6 +524,7 @@ pqn_status pqn_lcp_solve_dev(pqn_ctx* ctx, int32_t n, const int32_t* pairs_dev, 
                              int32_t solver, const pqn_lcp_opts* opts, pqn_lcp_stats* stats) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_lcp_solve_dev");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_lcp_solve_dev needs a single-suspension context");
     if (!ctx || n < 0 || (n > 0 && (!pairs_dev || !b_dev || !x_dev)))
       return fail(PQN_ERR_INVALID, "pqn_lcp_solve_dev: bad argument");
@@ -511,6 +539,7 @@ pqn_status pqn_step(pqn_ctx* ctx, double dt, double delta, int32_t solver, const
                     pqn_step_stats* stats) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_step");
     if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_step needs a single-suspension context");
     if (!ctx || !(dt > 0.0) || !std::isfinite(delta)) return fail(PQN_ERR_INVALID, "pqn_step: bad argument");
     if (solver < PQN_BBPGD || solver > PQN_BI_REC) return fail(PQN_ERR_INVALID, "bad solver");

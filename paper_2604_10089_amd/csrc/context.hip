@@ -86,10 +86,11 @@ pqn_ctx_impl::~pqn_ctx_impl() {
   lcp_release(lcp);
   lcp = nullptr;
   children.clear();
-  for (auto& e : ev_pool) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
-  }
+  for (auto& pool : ev_pool)
+    for (auto& e : pool) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
   if (side) {
     (void)hipStreamSynchronize(side);
     (void)hipStreamDestroy(side);
@@ -192,33 +193,41 @@ void pqn_ctx_impl::set_configuration(const double* c, const double* ax) {
   ++config_epoch;
 }
 
-void pqn_ctx_impl::begin_far_timing() {
+void pqn_ctx_impl::stage_begin(int st) {
   if (!cfg.profile) return;
-  if (ev_used == ev_pool.size()) {
+  auto& pool = ev_pool[st];
+  if (ev_used[st] == pool.size()) {
     hipEvent_t a0, b0;
     HIPCHK(hipEventCreate(&a0));
     HIPCHK(hipEventCreate(&b0));
-    ev_pool.emplace_back(a0, b0);
+    pool.emplace_back(a0, b0);
   }
-  HIPCHK(hipEventRecord(ev_pool[ev_used].first, stream));
+  HIPCHK(hipEventRecord(pool[ev_used[st]].first, stream));
 }
 
-void pqn_ctx_impl::end_far_launch() {
+void pqn_ctx_impl::stage_end(int st) {
   if (!cfg.profile) return;
-  HIPCHK(hipEventRecord(ev_pool[ev_used].second, stream));
-  ++ev_used;
+  HIPCHK(hipEventRecord(ev_pool[st][ev_used[st]].second, stream));
+  ++ev_used[st];
 }
+
+void pqn_ctx_impl::begin_far_timing() { stage_begin(kStageFar); }
+
+void pqn_ctx_impl::end_far_launch() { stage_end(kStageFar); }
 
 double pqn_ctx_impl::end_far_timing() {
-  // called after the stream has been synchronised: sums and recycles the events
-  double t = 0.0;
-  for (size_t k = 0; k < ev_used; ++k) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, ev_pool[k].first, ev_pool[k].second));
-    t += ms;
+  // called after the stream has been synchronised: sums and recycles the events of every stage
+  for (int st = 0; st < kNumStages; ++st) {
+    double t = 0.0;
+    for (size_t k = 0; k < ev_used[st]; ++k) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev_pool[st][k].first, ev_pool[st][k].second));
+      t += ms;
+    }
+    ev_used[st] = 0;
+    stage_ms[st] = t;
   }
-  ev_used = 0;
-  return t;
+  return stage_ms[kStageFar];
 }
 
 // y_r = (1/2 I + D + P) q_r for every density of every group.
@@ -268,7 +277,7 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
   // near tiles and the rigid moments (none of which the far pair sum reads) run
   // on a second stream, concurrently with the packing and far pair sum; the
   // final combination waits for both.
-  const bool ov = cfg.side_stream && groups.size() == 1;
+  const bool ov = cfg.side_stream && !cfg.profile && groups.size() == 1;
   hipStream_t sa = s;
   DevArray<char>* dtab = &ddesc;
   if (ov) {
@@ -304,10 +313,14 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
     DescPack dp;
     const size_t oa = dp.add(ga), ob = dp.add(gb);
     char* base = push_desc_pack(dp.host, sa, *dtab);
+    stage_begin(kStageGemm);
     launch_gemm64_multi(sa, (const GemmDesc*)(base + oa), (int)ga.size(), nga);
     launch_gemm64_multi(sa, (const GemmDesc*)(base + ob), (int)gb.size(), ngb);
+    stage_end(kStageGemm);
     if (ov) side_work(gr, sa);
+    stage_begin(kStageLocal);
     launch_pack(s, prec, gr.K, qp, lv.off.p, lv.w.p, n, N, lv.src.p);
+    stage_end(kStageLocal);
   }
   begin_far_timing();
   {
@@ -329,6 +342,7 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
     Level& lv = *gr.lv;
     pqn_ctx_impl& c = *gr.c;
     if (!ov) side_work(gr, s);
+    stage_begin(kStageLocal);
     if (gr.K == 1) {
       Work& w = lv.wk(gr.slot[0]);
       launch_combine(s, gr.in[0], w.selfo.p, 3, w.far_part.p, lv.nchunks, w.near_part.p, c.npart.p, w.mom.p,
@@ -348,6 +362,7 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
       char* base = push_desc_pack(dp.host);
       launch_combine_multi(s, (const CombDesc*)(base + oc), (int)cd.size(), ncd);
     }
+    stage_end(kStageLocal);
     n_matvec += gr.K;
   }
   HIPCHK(hipGetLastError());
@@ -365,8 +380,12 @@ void pqn_ctx_impl::side_work(MvGroup& gr, hipStream_t st) {
     np.p[r] = w.near_part.p;
   }
   const double* qup = lv.wk(gr.slot[0]).qup.p;
+  // (stage events are recorded only while profiling, when st is the main stream)
+  stage_begin(kStageNear);
   launch_near(st, gr.K, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, qup, cf, c.near_list.p, lv.n, lv.M, lv.N,
               lv.nup, lv.p, lv.L, 3.0 / (4.0 * kPi * c.a), np);
+  stage_end(kStageNear);
+  stage_begin(kStageLocal);
   if (gr.K == 1) {
     Work& w = lv.wk(gr.slot[0]);
     launch_moments(st, gr.in[0], lv.off.p, lv.w.p, lv.n, lv.M, lv.N, w.mom.p);
@@ -384,6 +403,7 @@ void pqn_ctx_impl::side_work(MvGroup& gr, hipStream_t st) {
     char* base = st == stream ? push_desc_pack(dp.host) : push_desc_pack(dp.host, st, ddesc_side);
     launch_moments_multi(st, (const MomDesc*)(base + om), (int)md.size(), nmd);
   }
+  stage_end(kStageLocal);
 }
 
 // Many suspensions (one density each): every phase of the operator is one
@@ -708,6 +728,7 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
     }
   }
   for (;;) {
+    TraceRange trace_iter("gmres_iteration");
     std::vector<int> act;
     for (int i = 0; i < ns; ++i)
       if (st[i].active) act.push_back(i);
@@ -724,6 +745,7 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
     if (graph_iter) {
       // operator and CGS2 already in the replayed graph
     } else if (act.size() == 1) {
+      stage_begin(kStageArnoldi);
       for (int i : act) {
         SysBuf& b = sys[i].lv->sb(sys[i].slot);
         const long len = len_of(i);
@@ -736,6 +758,7 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
         }
         launch_dots(s, w, len, 1, w, len, sys[i].lv->nb_dots, b.partial.p, hp + 2 * (m + 1));
       }
+      stage_end(kStageArnoldi);
     } else {
       // CGS2 of every active system with segmented launches
       std::vector<DotDesc> dd[2], dn;
@@ -759,11 +782,13 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
       DescPack dp;
       const size_t o0 = dp.add(dd[0]), o1 = dp.add(cd[0]), o2 = dp.add(dd[1]), o3 = dp.add(cd[1]), o4 = dp.add(dn);
       char* base = push_desc_pack(dp.host);
+      stage_begin(kStageArnoldi);
       launch_dots_multi(s, (const DotDesc*)(base + o0), (int)dd[0].size(), nv[0], kMultiDotBlocks);
       launch_combo_multi(s, (const ComboDesc*)(base + o1), (int)cd[0].size(), ne[0]);
       launch_dots_multi(s, (const DotDesc*)(base + o2), (int)dd[1].size(), nv[1], kMultiDotBlocks);
       launch_combo_multi(s, (const ComboDesc*)(base + o3), (int)cd[1].size(), ne[1]);
       launch_dots_multi(s, (const DotDesc*)(base + o4), (int)dn.size(), nn, kMultiDotBlocks);
+      stage_end(kStageArnoldi);
     }
     readback();
     std::vector<int> need_restart;

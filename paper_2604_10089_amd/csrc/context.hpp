@@ -6,6 +6,8 @@
 #include <stdexcept>
 #include <utility>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/bipqn.h"
 #include "kernels.hpp"
 
@@ -86,6 +88,15 @@ struct DevArray {
     alloc(n);
     if (n) HIPCHK(hipMemcpyAsync(p, h, n * sizeof(T), hipMemcpyHostToDevice, s));
   }
+};
+
+// Named range on the calling thread's roctx stack (seen by rocprofv3 --marker-trace;
+// a push and a pop when no tool is attached).
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
 };
 
 struct Timer {
@@ -223,8 +234,14 @@ struct pqn_ctx_impl {
   hipStream_t side_stream();
   void side_work(MvGroup& gr, hipStream_t st);
   // profiling of far launches
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
-  size_t ev_used = 0;
+  // profile = 1: HIP events around every launch of each stage of the operator, on the
+  // main stream (the side stream is not used while profiling)
+  enum { kStageFar = 0, kStageNear, kStageGemm, kStageLocal, kStageArnoldi, kNumStages };
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[kNumStages];
+  size_t ev_used[kNumStages] = {};
+  double stage_ms[kNumStages] = {};  // totals of the last end_far_timing()
+  void stage_begin(int st);
+  void stage_end(int st);
   int n_matvec = 0, n_far = 0;
   unsigned long config_epoch = 1;  // bumped by every configuration change (invalidates graphs)
   int n_graph_launch = 0;

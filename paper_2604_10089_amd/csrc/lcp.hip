@@ -967,6 +967,7 @@ static bool run_mono(pqn_ctx_impl& ctx, Engine& E, int k_max, const pqn_lcp_opts
   bool conv = false;
   int k = 0;
   for (k = 0; k < k_max; ++k) {
+    TraceRange trace_iter("pqn_iteration");
     hipLaunchKernelGGL(k_pqn_prepare, dim3(1), dim3(kT), 0, ctx.stream, E.d, o.j_max, o.ssn_tol);
     HIPCHK(hipGetLastError());
     PqnScal s = read_scal(ctx, E.d.sc);
@@ -1187,6 +1188,7 @@ struct BiSolver {
     Result r;
     int k = 0;
     for (k = 0; k < k_lim; ++k) {
+      TraceRange trace_iter(top ? "bi_pqn_outer_iteration" : "bi_pqn_nested_iteration");
       hipLaunchKernelGGL(k_bi_prepare, dim3(1), dim3(kT), 0, ctx.stream, E.d, B, I.d);
       PqnScal so = read_scal(ctx, E.d.sc);
       if (!std::isfinite(so.e)) throw Error(PQN_ERR_NUMERIC, "non-finite KKT error in Bi-PQN");

@@ -246,3 +246,18 @@ def test_mobility_apply_dev_matches_host(tiny):
         Ud = UOd.cpu().numpy()
     assert st['converged'] == 1
     assert np.array_equal(U, Ud)
+
+
+def test_profile_stage_times(tiny):
+    """profile = 1: every operator stage is timed with HIP events on one stream; the
+    stage times are positive and add up to less than the call's wall time."""
+    c, g, A = tiny
+    F = inputs.random_forces(7, g.M, k=2)
+    with binding.Context(c, None, 8, 16, gmres_tol=1e-10, profile=True, side_stream=True) as ctx:
+        U, st = ctx.mobility_apply_multi(F)
+        U1, _ = ctx.mobility_apply(F[0])
+    stages = [st[k] for k in ('t_far_ms', 't_near_ms', 't_gemm_ms', 't_local_ms', 't_arnoldi_ms')]
+    say('stage ms', stages, 'total', st['t_total_ms'])
+    assert min(stages) > 0.0
+    assert sum(stages) < st['t_total_ms']
+    assert rel(U[0], U1) < 1e-9

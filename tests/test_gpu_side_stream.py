@@ -34,3 +34,28 @@ def test_side_stream_is_bit_identical(prec):
             out[side] = r
     for a, b in zip(out[False], out[True]):
         assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+def test_bench_configuration_full_size():
+    """The timed configuration itself: 216 spheres, six force sets per pass through
+    device pointers, mixed precision, tuned layout, side stream on, GMRES 1e-8. Bit-equal
+    to the one-stream run, and within 1e-6 per velocity block of the FP64 path."""
+    import torch
+    w = inputs.workload('rsa216', 0)
+    c = w['centers']
+    FT = inputs.random_forces(100, c.shape[0], k=6)
+    FTd = torch.as_tensor(FT, dtype=torch.float64, device='cuda')
+    out = {}
+    for name, prec, side in (('side', 'mixed', True), ('serial', 'mixed', False), ('fp64', 'fp64', False)):
+        UOd = torch.full((6, c.shape[0], 6), float('nan'), dtype=torch.float64, device='cuda')
+        torch.cuda.synchronize()
+        with binding.Context(c, None, w['n_theta'], w['n_phi'], lo=w['lo'], gmres_tol=1e-8, precision=prec,
+                             tune_K=6, side_stream=side) as ctx:
+            st = ctx.mobility_apply_multi_dev(6, FTd.data_ptr(), UOd.data_ptr())
+        assert st['converged'] == 1
+        out[name] = UOd.cpu().numpy()
+    assert np.array_equal(out['side'], out['serial'])
+    for blk in (slice(0, 3), slice(3, 6)):
+        for r in range(6):
+            ref = out['fp64'][r][:, blk]
+            assert np.abs(out['side'][r][:, blk] - ref).max() < 1e-6 * np.abs(ref).max()
