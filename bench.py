@@ -310,7 +310,8 @@ def main():
     if not args.no_batch:
         inst = inputs.batched_suspensions(args.seed)
         FTb = [inputs.random_forces(500 + b, ci.shape[0]) for b, (ci, _, _) in enumerate(inst)]
-        kw = dict(gmres_tol=1e-8, precision='mixed', tpt=args.tpt or 2, stream=stream.cuda_stream)
+        kw = dict(gmres_tol=1e-8, precision='mixed', tpt=args.tpt or 2, stream=stream.cuda_stream,
+                  side_stream=not args.serial)
         with binding.BatchContext(inst, **kw) as bc:
             bc.mobility_apply(FTb)
             torch.cuda.synchronize()

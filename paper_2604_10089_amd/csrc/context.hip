@@ -448,9 +448,28 @@ void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
   DescPack dp;
   const size_t oa = dp.add(ga), ob = dp.add(gb), op = dp.add(pk), on = dp.add(nd), om = dp.add(md), oc = dp.add(cd);
   char* base = push_desc_pack(dp.host);
-  launch_gemm64_multi(s, (const GemmDesc*)(base + oa), (int)ga.size(), nga);   // coef = T q
-  launch_gemm64_multi(s, (const GemmDesc*)(base + ob), (int)gb.size(), ngb);   // self, qup
+  // side_stream: GEMMs, near tiles and moments of every suspension on the second stream,
+  // beside the packing and far pair sums (the table above is read by both streams and
+  // rewritten only after the join)
+  const bool ov = cfg.side_stream && !cfg.profile;
+  hipStream_t sa = s;
+  if (ov) {
+    sa = side_stream();
+    HIPCHK(hipEventRecord(ev_in, s));
+    HIPCHK(hipStreamWaitEvent(sa, ev_in, 0));
+  }
+  stage_begin(kStageGemm);
+  launch_gemm64_multi(sa, (const GemmDesc*)(base + oa), (int)ga.size(), nga);  // coef = T q
+  launch_gemm64_multi(sa, (const GemmDesc*)(base + ob), (int)gb.size(), ngb);  // self, qup
+  stage_end(kStageGemm);
+  if (ov) {
+    if (!nd.empty()) launch_near_multi(sa, (const NearDesc*)(base + on), (int)nd.size(), nnd);
+    launch_moments_multi(sa, (const MomDesc*)(base + om), (int)md.size(), nmd);
+    HIPCHK(hipEventRecord(ev_side, sa));
+  }
+  stage_begin(kStageLocal);
   launch_pack_multi(s, (const PackDesc*)(base + op), (int)pk.size(), npk, prec);
+  stage_end(kStageLocal);
   begin_far_timing();
   {
     struct Item {
@@ -489,9 +508,19 @@ void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
   }
   end_far_launch();
   ++n_far;
-  if (!nd.empty()) launch_near_multi(s, (const NearDesc*)(base + on), (int)nd.size(), nnd);
-  launch_moments_multi(s, (const MomDesc*)(base + om), (int)md.size(), nmd);
+  if (ov) {
+    HIPCHK(hipStreamWaitEvent(s, ev_side, 0));
+  } else {
+    stage_begin(kStageNear);
+    if (!nd.empty()) launch_near_multi(s, (const NearDesc*)(base + on), (int)nd.size(), nnd);
+    stage_end(kStageNear);
+    stage_begin(kStageLocal);
+    launch_moments_multi(s, (const MomDesc*)(base + om), (int)md.size(), nmd);
+    stage_end(kStageLocal);
+  }
+  stage_begin(kStageLocal);
   launch_combine_multi(s, (const CombDesc*)(base + oc), (int)cd.size(), ncd);
+  stage_end(kStageLocal);
   n_matvec += (int)groups.size();
   HIPCHK(hipGetLastError());
 }
