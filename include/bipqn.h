@@ -46,7 +46,9 @@ typedef enum {
   PQN_ERR_DEVICE = -2,  /* HIP runtime error */
   PQN_ERR_OOM = -3,     /* device allocation failed */
   PQN_ERR_NUMERIC = -4, /* NaN/Inf encountered */
-  PQN_ERR_STATE = -5    /* call not valid in the context's state */
+  PQN_ERR_STATE = -5,   /* call not valid in the context's state */
+  PQN_ERR_INDEFINITE = -6 /* pqn_step: the contact LCP met p.Ap <= 0 (A = D^T M D not positive
+                             definite) and did not converge; the configuration is unchanged */
 } pqn_status;
 
 typedef enum { PQN_FP64 = 0, PQN_MIXED = 1 } pqn_precision;
@@ -151,6 +153,11 @@ typedef struct {
   int32_t mvp_lo2;          /* PQN_BI_REC: products at the second low fidelity (each one BIE solve) */
   double lo2_hi_cost_ratio; /* measured t_lo2/t_hi of this call; emvp adds mvp_lo2 * this ratio */
   double kkt_rel;           /* relative change of the last two KKT errors (0 before two iterates) */
+  int32_t nonpos_curvature; /* steps on A (the final phase of the solve) whose direction p had
+                               p.Ap <= 0, i.e. A is not positive definite along p; the step then
+                               takes eta = 1 and resets the quasi-Newton memory (Alg. 2 edge case).
+                               Positive definiteness of A is the method's assumption (Sec. 3); a
+                               near-contact pair below the surface grid's resolution can break it */
 } pqn_lcp_stats;
 
 typedef struct {
@@ -217,7 +224,10 @@ pqn_status pqn_lcp_solve_dev(pqn_ctx* ctx, int32_t n, const int32_t* pairs_dev, 
                              int32_t solver, const pqn_lcp_opts* opts, pqn_lcp_stats* stats);
 
 /* One step (eq. (dvi)): contacts(delta) -> U_nc -> b = Phi/dt + D^T U_nc -> LCP ->
- * U = U_nc + M D x -> centres += dt U, Janus axes rotated by Omega dt. */
+ * U = U_nc + M D x -> centres += dt U, Janus axes rotated by Omega dt. An LCP that
+ * hits its cap after meeting p.Ap <= 0 (A not positive definite) gives
+ * PQN_ERR_INDEFINITE and leaves the configuration unchanged; any other cap gives
+ * PQN_WARN_NOT_CONVERGED and the step is taken with the last iterate. */
 pqn_status pqn_step(pqn_ctx* ctx, double dt, double delta, int32_t solver, const pqn_lcp_opts* opts,
                     pqn_step_stats* stats);
 

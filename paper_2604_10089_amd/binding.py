@@ -87,7 +87,7 @@ class LcpStats(C.Structure):
                 ('lo_hi_cost_ratio', C.c_double), ('kkt_abs', C.c_double), ('converged', C.c_int32),
                 ('ssn_steps', C.c_int32), ('t_total_ms', C.c_double), ('gmres_iters', C.c_int32),
                 ('model_rejected', C.c_int32), ('mvp_lo2', C.c_int32), ('lo2_hi_cost_ratio', C.c_double),
-                ('kkt_rel', C.c_double)]
+                ('kkt_rel', C.c_double), ('nonpos_curvature', C.c_int32)]
 
 
 class StepStats(C.Structure):

@@ -17,6 +17,7 @@ constexpr int kT = 256;  // threads of the single-workgroup kernels (4 waves)
 struct PqnScal {
   int r, conv, stationary, reset, ssn_steps, ssn_fail, have_prev, nonzero;
   int resets;  // steps of this solve that met the Alg. 2 edge cases (non-positive curvature or no descent)
+  int nonpos;  // of those, steps with p.Ap <= 0: the operator is not positive definite along p
   int bad;     // k_check_lcp_inputs: an invalid pair or a non-finite entry of b or x
   double e, e_prev, eta, tol_abs, tol_rel, tau, sigma;
 };
@@ -465,7 +466,7 @@ __device__ double step_size_block(const double* g, const double* x, const double
     if (p[e] < 0.0) lim = fmin(lim, -x[e] / p[e]);
   lim = block_min(lim, red);
   if (!(pAp > 0.0)) {
-    *reset = 1;
+    *reset = 2;
     return 1.0;
   }
   const double eta1 = -gp / pAp;
@@ -503,7 +504,8 @@ __global__ __launch_bounds__(kT) void k_pqn_accept(PqnDev d) {
     d.sc->r = r;
     d.sc->eta = eta;
     d.sc->reset = reset;
-    d.sc->resets += reset;
+    d.sc->resets += reset != 0;
+    d.sc->nonpos += reset == 2;
   }
 }
 
@@ -709,7 +711,8 @@ __global__ __launch_bounds__(kT) void k_bi_accept(PqnDev o, BiDev B, PqnDev in) 
     B.cnt[1] = nlow;
     o.sc->eta = eta;
     o.sc->reset = reset;
-    o.sc->resets += reset;
+    o.sc->resets += reset != 0;
+    o.sc->nonpos += reset == 2;
   }
 }
 
@@ -1309,6 +1312,7 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
     stats->ssn_steps = ssn;
     stats->gmres_iters = cnt.gmres;
     stats->model_rejected = rejected ? 1 : 0;
+    stats->nonpos_curvature = fin.nonpos;
   }
   return conv;
 }
@@ -1412,6 +1416,14 @@ pqn_status lcp_step(pqn_ctx_impl& ctx, double dt, double delta, int solver, cons
                        st.outer.d.b);
     const pqn_lcp_opts o = opts_or_default(opts);
     conv = solve_device(ctx, n, solver, o, st.MDx.p, &ss.lcp, false);
+    if (!conv && ss.lcp.nonpos_curvature > 0) {
+      // the iterate of a solve that met p.Ap <= 0 on A and did not converge can be
+      // arbitrarily large: moving the spheres with it would scatter them
+      throw Error(PQN_ERR_INDEFINITE,
+                  "pqn_step: the contact LCP matrix A = D^T M D is not positive definite (p.Ap <= 0 along a "
+                  "search direction; typically a near-contact pair the surface grid does not resolve) and the "
+                  "solve did not converge; configuration unchanged");
+    }
     MDx = st.MDx.p;
     std::vector<double> hx(n);
     HIPCHK(hipMemcpyAsync(hx.data(), st.outer.d.x, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));

@@ -10,6 +10,7 @@ from paper_2604_10089_amd import binding, inputs
 pytestmark = pytest.mark.gpu
 
 PQN_ERR_NUMERIC = -4
+PQN_ERR_INDEFINITE = -6
 
 
 def _tiny():
@@ -70,3 +71,39 @@ def test_mixed_solve_finished_in_fp64_when_refinement_stalls():
     g = bie.Geometry(c, 1.0, 8, 16)
     Uo = bie.mobility_apply(g, F, dense=bie.dense_operator(g))
     assert np.abs(U - Uo).max() < 1e-11 * np.abs(Uo).max()
+
+
+def _pair(gap):
+    d = np.ones(3) / np.sqrt(3.0)  # line of centres oblique to the grid's pole
+    c = np.array([np.zeros(3), (2.0 + gap) * d])
+    axes = np.array([d, -d])  # each sphere swims towards the other
+    return c, axes
+
+
+def test_unresolved_contact_makes_lcp_indefinite_and_step_refuses():
+    """Two spheres swimming head on at gap 3e-4 on the 8x16 grid: the grid does not
+    resolve the gap, the discrete relative mobility of the pair (the 1x1 LCP matrix) is
+    negative, PQN meets p.Ap <= 0 (counted in nonpos_curvature), and pqn_step refuses
+    the step with PQN_ERR_INDEFINITE, leaving the configuration as it was. At gap 5e-2
+    the same pair is resolved: A > 0 and the step is taken."""
+    c, axes = _pair(3e-4)
+    with binding.Context(c, axes, 8, 16, gmres_tol=1e-10) as ctx:
+        pairs, gaps = ctx.find_contacts(0.1)
+        assert pairs.shape[0] == 1
+        A = ctx.lcp_apply(pairs, np.ones(1))[0]
+        print('A at gap 3e-4', A, flush=True)
+        assert A < 0.0
+        x, st = ctx.lcp_solve(pairs, np.array([-1.0]), 'mono', k_max=5)
+        assert st['status'] == binding.PQN_WARN_NOT_CONVERGED and st['nonpos_curvature'] > 0
+        c0, a0 = ctx.get_state()
+        with pytest.raises(binding.PqnError) as e:
+            ctx.step(0.1, 0.1, 'mono', k_max=5)
+        assert e.value.status == PQN_ERR_INDEFINITE
+        c1, a1 = ctx.get_state()
+        assert np.array_equal(c0, c1) and np.array_equal(a0, a1)
+    c, axes = _pair(5e-2)
+    with binding.Context(c, axes, 8, 16, gmres_tol=1e-10) as ctx:
+        pairs, _ = ctx.find_contacts(0.1)
+        assert ctx.lcp_apply(pairs, np.ones(1))[0] > 0.0
+        st = ctx.step(0.1, 0.1, 'mono')
+        assert st['status'] == binding.PQN_OK and st['lcp']['nonpos_curvature'] == 0
