@@ -306,6 +306,52 @@ def main():
                          mixed_refined_displacement_rel_err=mixed['mixed_refined'][1])
         log('steps', step_info)
 
+    inward_info = None
+    if not args.no_steps:
+        # time steps with active contacts: Janus axes towards the centroid (the paper's online runs start
+        # with the amphiphilic sides facing the origin), dt 0.1, so approaching pairs enter the LCP; the
+        # near rule upsampled 3x per direction keeps A positive definite once gaps close below ~5e-3
+        ax_in = c.mean(axis=0) - c
+        ax_in /= np.linalg.norm(ax_in, axis=1, keepdims=True)
+        nin, dt_in = 5, 0.1
+        try:
+            states_in, rows = [(c, ax_in)], []
+            with binding.Context(c, ax_in, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='fp64', tune_K=1,
+                                 warm_start=True, near_up=3, stream=stream.cuda_stream) as cs:
+                for _ in range(nin):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st = cs.step(dt_in, 0.1, 'bi')
+                    rows.append((time.perf_counter() - t0, st))
+                    states_in.append(cs.get_state())
+            tmi, dmi = [], 0.0
+            with binding.Context(c, ax_in, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='mixed', tune_K=1,
+                                 warm_start=True, near_up=3, stream=stream.cuda_stream,
+                                 side_stream=not args.serial) as cs:
+                for k in range(nin):
+                    cs.set_state(*states_in[k])
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    cs.step(dt_in, 0.1, 'bi')
+                    tmi.append(time.perf_counter() - t0)
+                    cm_k, _ = cs.get_state()
+                    disp = states_in[k + 1][0] - states_in[k][0]
+                    dmi = max(dmi, float(np.abs(cm_k - states_in[k + 1][0]).max() / np.abs(disp).max()))
+            inward_info = dict(steps=nin, dt=dt_in, near_up=3, axes='towards the centroid',
+                               contacts=[r[1]['n_contacts'] for r in rows], active=[r[1]['n_active'] for r in rows],
+                               mvp_hi=[r[1]['lcp']['mvp_hi'] for r in rows],
+                               mvp_lo=[r[1]['lcp']['mvp_lo'] for r in rows],
+                               emvp=[round(r[1]['lcp']['emvp'], 2) for r in rows],
+                               lcp_converged=[r[1]['lcp']['converged'] for r in rows if r[1]['n_contacts'] > 0],
+                               sec_per_step_fp64=[round(r[0], 3) for r in rows],
+                               sec_per_step_mixed=[round(t_, 3) for t_ in tmi],
+                               speedup=round(sum(r[0] for r in rows) / sum(tmi), 3),
+                               mixed_displacement_rel_err=dmi,
+                               min_gap_after=round(float(inputs.min_gap(states_in[-1][0])), 6))
+        except binding.PqnError as e:
+            inward_info = dict(error=str(e))
+        log('steps with contacts', inward_info)
+
     batch_info = None
     if not args.no_batch:
         inst = inputs.batched_suspensions(args.seed)
@@ -390,6 +436,7 @@ def main():
         'lcp': lcp_info,
         'batch32': batch_info,
         'time_steps': step_info,
+        'time_steps_with_contacts': inward_info,
     }
     if not args.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline(c, nt, nph, res['mixed1'])
