@@ -261,3 +261,31 @@ def test_profile_stage_times(tiny):
     assert min(stages) > 0.0
     assert sum(stages) < st['t_total_ms']
     assert rel(U[0], U1) < 1e-9
+
+
+def test_near_upsampling_factor_matches_oracle():
+    """The near rule upsampled 3x per direction (used for time steps whose gaps close
+    below the 2x rule's reach): the operator equals the oracle's matrix-free operator
+    with the same upsampling, and the 1x1 LCP matrix of a pair at gap 3e-4 on the 8x16
+    grid, negative with 2x upsampling, is positive and equals the oracle's."""
+    up = 3
+    w = inputs.workload('tiny', 0)
+    c = w['centers']
+    g = bie.Geometry(c, 1.0, 8, 16, near_up=up)
+    q = np.random.default_rng(5).standard_normal((g.N, 3))
+    with binding.Context(c, None, 8, 16, near_up=up) as ctx:
+        y = ctx.bie_apply(soa(q))
+    assert rel(y, bie.operator_apply(g, q).reshape(-1, 3).T) < 1e-12
+    d = np.ones(3) / np.sqrt(3.0)
+    cp = np.array([np.zeros(3), (2.0 + 3e-4) * d])
+    gp = bie.Geometry(cp, 1.0, 8, 16, near_up=up)
+    Ap = bie.dense_operator(gp)
+    F = np.zeros((2, 6))
+    F[0, :3], F[1, :3] = -d, d  # unit push apart along the line of centres
+    U = bie.mobility_apply(gp, F, dense=Ap)
+    a_ref = float(d @ (U[1, :3] - U[0, :3]))
+    with binding.Context(cp, None, 8, 16, gmres_tol=1e-13, near_up=up) as ctx:
+        pairs, _ = ctx.find_contacts(0.1)
+        a = ctx.lcp_apply(pairs, np.ones(1))[0]
+    say('near_up', up, 'pair A', a, 'oracle', a_ref)
+    assert a > 0.0 and abs(a - a_ref) < 1e-9 * abs(a_ref)
