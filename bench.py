@@ -99,6 +99,9 @@ def main():
     ap.add_argument('--counters-probe', action='store_true',
                     help='short run for rocprofv3 --pmc: a 256 MiB device copy (scale reference for FETCH_SIZE/'
                          'WRITE_SIZE) and one six-force-set product on the 216-sphere workload')
+    ap.add_argument('--batch-probe', action='store_true',
+                    help='short run for rocprofv3 --kernel-trace: only the 32-suspension batch, mixed precision '
+                         '(one warm-up product and three timed ones), one JSON line')
     ap.add_argument('--lcp-table', action='store_true',
                     help='instead of the benchmark line: BB-PGD, Mono-PQN and Bi-PQN on planted LCPs of the 27-, '
                          '64- and 216-sphere workloads (three seeds each), one JSON line')
@@ -143,6 +146,23 @@ def main():
 
     if args.lcp_table:
         print(json.dumps(lcp_table(binding, inputs, stream)), flush=True)
+        return
+
+    if args.batch_probe:
+        inst = inputs.batched_suspensions(args.seed)
+        FTb = [inputs.random_forces(500 + b, ci.shape[0]) for b, (ci, _, _) in enumerate(inst)]
+        with binding.BatchContext(inst, gmres_tol=1e-8, precision='mixed', tpt=args.tpt or 2,
+                                  stream=stream.cuda_stream, side_stream=not args.serial) as bc:
+            bc.mobility_apply(FTb)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                _, bst = bc.mobility_apply(FTb)
+            torch.cuda.synchronize()
+            tb = (time.perf_counter() - t0) / 3
+        print(json.dumps({'instances': len(inst), 'ms_per_product': round(tb * 1e3, 3),
+                          'mvps_batched': round(len(inst) / tb, 2), 'lockstep_iterations': bst['n_far'],
+                          'side_stream': not args.serial}), flush=True)
         return
 
     if args.counters_probe:
