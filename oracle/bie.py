@@ -35,6 +35,8 @@ discrete operator):
     degree-p expansion of the density there. The subtraction uses
     D_j[const](x) = 0 outside sphere j. This stands in for the paper's
     near-singular evaluation, which the paper names by cost only (Sec. 5.1);
+    optionally, pairs closer than near_close_gap use the finer factor
+    near_close_up instead (a gap the near_up grid does not resolve);
   * the weakly singular self interaction by a rotated-pole rule: for each target
     node x0 the sphere is re-gridded with x0 at the pole (Gauss-Legendre in the
     polar angle theta' on [0, pi] with 3 n_theta points, trapezoid in phi' with
@@ -58,7 +60,7 @@ class Geometry:
     """Centres plus the per-sphere grid of one suspension (plain container)."""
 
     def __init__(self, centers, radius=1.0, n_theta=8, n_phi=16, mu=1.0,
-                 near_gap=None, near_up=2):
+                 near_gap=None, near_up=2, near_close_gap=0.0, near_close_up=3):
         self.c = np.array(centers, dtype=np.float64).reshape(-1, 3)
         self.M = self.c.shape[0]
         self.a = float(radius)
@@ -69,6 +71,8 @@ class Geometry:
         self.N = self.M * self.n
         self.near_gap = 0.5 * self.a if near_gap is None else float(near_gap)
         self.near_up = int(near_up)
+        self.near_close_gap = float(near_close_gap)
+        self.near_close_up = int(near_close_up)
         self.x = (self.c[:, None, :] + self.o[None, :, :]).reshape(-1, 3)
         self.normals = np.tile(self.nrm, (self.M, 1))
         self.weights = np.tile(self.w, self.M)
@@ -76,6 +80,11 @@ class Geometry:
     def nodes(self, i):
         s = slice(i * self.n, (i + 1) * self.n)
         return s
+
+    def pair_up(self, i, j):
+        """Upsampling factor of the near pair (i, j): near_close_up below near_close_gap."""
+        gap = np.linalg.norm(self.c[i] - self.c[j]) - 2.0 * self.a
+        return self.near_close_up if gap < self.near_close_gap else self.near_up
 
     def pair_class(self):
         """(M, M) int array: 2 on the diagonal, 1 for near pairs, 0 otherwise."""
@@ -265,9 +274,9 @@ def upsample_matrix(n_theta, n_phi, up):
     return _UP_CACHE[key]
 
 
-def near_sources(geom, j):
-    """Upsampled nodes, normals and weights of sphere j used for near pairs."""
-    of, nf, wf = _grid.sphere_grid(geom.near_up * geom.n_theta, geom.near_up * geom.n_phi, geom.a)
+def near_sources(geom, j, up):
+    """Nodes, normals and weights of sphere j on the up-times finer grid of near pairs."""
+    of, nf, wf = _grid.sphere_grid(up * geom.n_theta, up * geom.n_phi, geom.a)
     return geom.c[j] + of, nf, wf
 
 
@@ -277,8 +286,9 @@ def near_block(geom, i, j):
     if (i, j) in cache:
         return cache[(i, j)]
     X = geom.x[geom.nodes(i)]
-    yf, nf, wf = near_sources(geom, j)
-    I = upsample_matrix(geom.n_theta, geom.n_phi, geom.near_up)
+    up = geom.pair_up(i, j)
+    yf, nf, wf = near_sources(geom, j, up)
+    I = upsample_matrix(geom.n_theta, geom.n_phi, up)
     K = dl_kernel(X, yf, nf) * wf[None, :, None, None]          # (n, nf, 3, 3)
     u = X - geom.c[j]
     u /= np.linalg.norm(u, axis=1)[:, None]
@@ -293,8 +303,9 @@ def near_block(geom, i, j):
 def near_row(geom, i, j, k):
     """Row (3, n, 3) of the near block for the single target node k of sphere i."""
     X = geom.x[geom.nodes(i)][k:k + 1]
-    yf, nf, wf = near_sources(geom, j)
-    I = upsample_matrix(geom.n_theta, geom.n_phi, geom.near_up)
+    up = geom.pair_up(i, j)
+    yf, nf, wf = near_sources(geom, j, up)
+    I = upsample_matrix(geom.n_theta, geom.n_phi, up)
     K = dl_kernel(X, yf, nf)[0] * wf[:, None, None]              # (nf, 3, 3)
     u = (X[0] - geom.c[j]) / np.linalg.norm(X[0] - geom.c[j])
     Ifoot = _grid.projection_to_points(geom.n_theta, geom.n_phi, np.array([np.arccos(np.clip(u[2], -1.0, 1.0))]),

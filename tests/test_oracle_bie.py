@@ -164,3 +164,37 @@ def test_operator_rows_equal_full_apply(tiny_cases):
     full = (A @ q.ravel()).reshape(-1, 3)
     tg = [0, 5, 127, 128, 700, g.N - 1]
     assert np.abs(bie.operator_rows(g, q, tg) - full[tg]).max() < 1e-12 * np.abs(full).max()
+
+
+def test_close_pairs_take_the_finer_near_rule():
+    """Near pairs closer than near_close_gap use the near_close_up grid, the others
+    near_up: each block equals the block of a geometry that uses that one factor for
+    every near pair, and the close class moves only the close pair's block."""
+    d = np.array([1.0, 1.0, 1.0]) / np.sqrt(3.0)
+    e = np.array([1.0, -1.0, 0.0]) / np.sqrt(2.0)
+    c = np.array([np.zeros(3), (2.0 + 3e-4) * d, (2.0 + 0.1) * e])   # one close, one near pair
+    g = bie.Geometry(c, 1.0, 8, 16, near_close_gap=0.01, near_close_up=3)
+    g2 = bie.Geometry(c, 1.0, 8, 16, near_up=2)
+    g3 = bie.Geometry(c, 1.0, 8, 16, near_up=3)
+    assert g.pair_up(0, 1) == g.pair_up(1, 0) == 3 and g.pair_up(0, 2) == 2
+    assert np.array_equal(bie.near_block(g, 0, 1), bie.near_block(g3, 0, 1))
+    assert np.array_equal(bie.near_block(g, 1, 0), bie.near_block(g3, 1, 0))
+    assert np.array_equal(bie.near_block(g, 0, 2), bie.near_block(g2, 0, 2))
+    assert np.abs(bie.near_block(g3, 0, 1) - bie.near_block(g2, 0, 1)).max() > 1e-3
+    assert np.array_equal(bie.near_row(g, 0, 1, 5), bie.near_block(g3, 0, 1)[5])
+
+
+def test_close_class_restores_a_positive_pair_mobility():
+    """Two spheres at gap 3e-4 on the 8x16 grid, line of centres oblique to the pole:
+    with the 2x near rule the relative mobility along the line of centres (the 1x1
+    contact matrix) is negative; with the 3x rule for the close pair it is positive."""
+    d = np.array([1.0, 1.0, 1.0]) / np.sqrt(3.0)
+    c = np.array([np.zeros(3), (2.0 + 3e-4) * d])
+    F = np.zeros((2, 6))
+    F[0, :3], F[1, :3] = -d, d
+    vals = {}
+    for name, kw in (('2x', {}), ('close 3x', dict(near_close_gap=0.01, near_close_up=3))):
+        g = bie.Geometry(c, 1.0, 8, 16, **kw)
+        U = bie.mobility_apply(g, F, dense=bie.dense_operator(g))
+        vals[name] = float(d @ (U[1, :3] - U[0, :3]))
+    assert vals['2x'] < 0.0 < vals['close 3x']
