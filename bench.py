@@ -329,15 +329,17 @@ def main():
     inward_info = None
     if not args.no_steps:
         # time steps with active contacts: Janus axes towards the centroid (the paper's online runs start
-        # with the amphiphilic sides facing the origin), dt 0.1, so approaching pairs enter the LCP; the
-        # near rule upsampled 3x per direction keeps A positive definite once gaps close below ~5e-3
+        # with the amphiphilic sides facing the origin), dt 0.1, so approaching pairs enter the LCP; near
+        # pairs closer than 0.02 take the 3x grid, which keeps A positive definite once gaps close below
+        # ~5e-3
         ax_in = c.mean(axis=0) - c
         ax_in /= np.linalg.norm(ax_in, axis=1, keepdims=True)
         nin, dt_in = 5, 0.1
         try:
             states_in, rows = [(c, ax_in)], []
             with binding.Context(c, ax_in, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='fp64', tune_K=1,
-                                 warm_start=True, near_up=3, stream=stream.cuda_stream) as cs:
+                                 warm_start=True, near_close_gap=0.02, near_close_up=3,
+                                 stream=stream.cuda_stream) as cs:
                 for _ in range(nin):
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
@@ -346,8 +348,8 @@ def main():
                     states_in.append(cs.get_state())
             tmi, dmi = [], 0.0
             with binding.Context(c, ax_in, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='mixed', tune_K=1,
-                                 warm_start=True, near_up=3, stream=stream.cuda_stream,
-                                 side_stream=not args.serial) as cs:
+                                 warm_start=True, near_close_gap=0.02, near_close_up=3,
+                                 stream=stream.cuda_stream, side_stream=not args.serial) as cs:
                 for k in range(nin):
                     cs.set_state(*states_in[k])
                     torch.cuda.synchronize()
@@ -357,7 +359,8 @@ def main():
                     cm_k, _ = cs.get_state()
                     disp = states_in[k + 1][0] - states_in[k][0]
                     dmi = max(dmi, float(np.abs(cm_k - states_in[k + 1][0]).max() / np.abs(disp).max()))
-            inward_info = dict(steps=nin, dt=dt_in, near_up=3, axes='towards the centroid',
+            inward_info = dict(steps=nin, dt=dt_in, near_close_gap=0.02, near_close_up=3,
+                               axes='towards the centroid',
                                contacts=[r[1]['n_contacts'] for r in rows], active=[r[1]['n_active'] for r in rows],
                                mvp_hi=[r[1]['lcp']['mvp_hi'] for r in rows],
                                mvp_lo=[r[1]['lcp']['mvp_lo'] for r in rows],

@@ -106,6 +106,11 @@ typedef struct {
   int32_t side_stream;      /* 1 = the coefficient / self-interaction GEMMs, near tiles and rigid
                                moments of an operator application run on a second stream of the
                                library, concurrently with the far pair sum (same results) */
+  double near_close_gap;    /* near pairs with gap < near_close_gap use the finer factor
+                               near_close_up [0 = none]: a gap the near_up grid does not resolve
+                               can make the pair's discrete mobility, and the contact LCP
+                               matrix, indefinite */
+  int32_t near_close_up;    /* upsampling factor of those close pairs [3] */
 } pqn_config_desc;
 
 typedef struct {

@@ -36,6 +36,8 @@ static void fill_defaults(pqn_config_desc& c) {
   if (c.gmres_max_iter <= 0) c.gmres_max_iter = 500;
   if (c.near_gap <= 0) c.near_gap = 0.5 * c.radius;
   if (c.near_up <= 0) c.near_up = 2;
+  if (c.near_close_gap < 0) c.near_close_gap = 0;
+  if (c.near_close_up <= 0) c.near_close_up = 3;
   if (c.slip_speed == 0) c.slip_speed = 1.0;
   if (c.targets_per_thread <= 0) c.targets_per_thread = 2;
 }
@@ -72,6 +74,7 @@ static std::string check_desc(const pqn_config_desc& c) {
   if (c.n_theta_lo2 != 0 && c.n_theta_lo == 0) return "a second low-fidelity grid needs the first";
   if (c.precision != PQN_FP64 && c.precision != PQN_MIXED) return "bad precision";
   if ((c.dev_alloc == nullptr) != (c.dev_free == nullptr)) return "dev_alloc and dev_free go together";
+  if (c.near_up > 8 || c.near_close_up > 8) return "near upsampling factors above 8 are not supported";
   return "";
 }
 

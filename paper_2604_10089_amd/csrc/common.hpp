@@ -76,6 +76,9 @@ struct SphereTables {
   std::vector<double> off_up;   // [n_up][3] upsampled grid offsets
   std::vector<double> w_up;     // [n_up]
   std::vector<double> Y_up;     // [n_up][L] synthesis on the upsampled grid
+  // finer grid of the close near pairs (gap < near_close_gap); n_up2 = 0 when unused
+  int up2 = 0, n_up2 = 0;
+  std::vector<double> off_up2, w_up2, Y_up2;
   std::vector<double> shab;     // [L][2] Legendre recurrence factors (sh_recurrence_table)
 };
 
@@ -86,6 +89,7 @@ struct SphereTables {
 std::vector<double> sh_recurrence_table(int p);
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
-void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, SphereTables& t);
+// close_up > 0: also the close-pair grid, close_up times finer per direction
+void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, SphereTables& t, int close_up = 0);
 
 }  // namespace bipqn

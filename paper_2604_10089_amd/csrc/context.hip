@@ -59,6 +59,7 @@ Work& Level::wk(int k) {
     w.near_part.alloc((size_t)kMaxNear * 3 * N);
     w.coef.alloc((size_t)3 * M * L);
     w.qup.alloc((size_t)3 * M * nup);
+    if (nup2 > 0) w.qup2.alloc((size_t)3 * M * nup2);
     w.selfo.alloc((size_t)9 * N);
     w.mom.alloc((size_t)6 * M);
   }
@@ -101,7 +102,7 @@ pqn_ctx_impl::~pqn_ctx_impl() {
 }
 
 void pqn_ctx_impl::setup_level(Level& lv, int nt, int np, double tol) {
-  build_sphere_tables(nt, np, a, cfg.near_up, lv.tab);
+  build_sphere_tables(nt, np, a, cfg.near_up, lv.tab, cfg.near_close_gap > 0.0 ? cfg.near_close_up : 0);
   SphereTables& t = lv.tab;
   lv.M = M;
   lv.n = t.n;
@@ -119,6 +120,14 @@ void pqn_ctx_impl::setup_level(Level& lv, int nt, int np, double tol) {
   for (int f = 0; f < t.n_up; ++f)
     ou[f] = make_double4(t.off_up[3 * f], t.off_up[3 * f + 1], t.off_up[3 * f + 2], t.w_up[f]);
   lv.offup.upload(ou.data(), ou.size(), stream);
+  lv.nup2 = t.n_up2;
+  if (lv.nup2 > 0) {
+    std::vector<double4> ou2(t.n_up2);
+    for (int f = 0; f < t.n_up2; ++f)
+      ou2[f] = make_double4(t.off_up2[3 * f], t.off_up2[3 * f + 1], t.off_up2[3 * f + 2], t.w_up2[f]);
+    lv.offup2.upload(ou2.data(), ou2.size(), stream);
+    lv.Yup2.upload(t.Y_up2.data(), t.Y_up2.size(), stream);
+  }
   const int N = lv.N;
   lv.tpt = far_layout(cfg);
   const int tgt_per_block = lv.tpt == 0 ? 64 : 256 * lv.tpt;
@@ -148,6 +157,7 @@ void pqn_ctx_impl::set_configuration(const double* c, const double* ax) {
   std::vector<unsigned char> hc((size_t)M * M, 0);
   h_partners.assign((size_t)M * kMaxNear, -1);
   h_npart.assign(M, 0);
+  std::vector<char> h_close((size_t)M * kMaxNear, 0);
   max_slots = 0;
   for (int i = 0; i < M; ++i) {
     for (int j = 0; j < M; ++j) {
@@ -163,6 +173,7 @@ void pqn_ctx_impl::set_configuration(const double* c, const double* ax) {
         int& k = h_npart[i];
         if (k >= kMaxNear) throw Error(PQN_ERR_INVALID, "more than 16 near neighbours of one sphere");
         h_partners[(size_t)i * kMaxNear + k] = j;
+        h_close[(size_t)i * kMaxNear + k] = gap < cfg.near_close_gap;
         ++k;
       }
     }
@@ -170,25 +181,29 @@ void pqn_ctx_impl::set_configuration(const double* c, const double* ax) {
   }
   // ordered near pairs (target sphere, source sphere, partner slot), grouped by
   // source sphere so that launches reading the same source data run together
-  std::vector<int> nl;
+  // (close pairs, gap < near_close_gap, in a list of their own for the finer grid)
+  std::vector<int> nl, nl2;
   {
     std::vector<std::array<int, 3>> pr;
     for (int i = 0; i < M; ++i)
       for (int s = 0; s < h_npart[i]; ++s) pr.push_back({h_partners[(size_t)i * kMaxNear + s], i, s});
     std::sort(pr.begin(), pr.end());
     for (const auto& e : pr) {
-      nl.push_back(e[1]);
-      nl.push_back(e[0]);
-      nl.push_back(e[2]);
+      std::vector<int>& l = h_close[(size_t)e[1] * kMaxNear + e[2]] ? nl2 : nl;
+      l.push_back(e[1]);
+      l.push_back(e[0]);
+      l.push_back(e[2]);
     }
   }
   n_near = (int)nl.size() / 3;
+  n_near2 = (int)nl2.size() / 3;
   ctr.upload(centers.data(), centers.size(), stream);
   dax.upload(axes.data(), axes.size(), stream);
   cls.upload(hc.data(), hc.size(), stream);
   partners.upload(h_partners.data(), h_partners.size(), stream);
   npart.upload(h_npart.data(), h_npart.size(), stream);
   near_list.upload(nl.data(), nl.size(), stream);
+  near_list2.upload(nl2.data(), nl2.size(), stream);
   HIPCHK(hipStreamSynchronize(stream));
   ++config_epoch;
 }
@@ -249,15 +264,16 @@ void add_to_groups(std::vector<MvGroup>& groups, pqn_ctx_impl* c, Level* lv, int
 
 // The interleaved upsampled densities of a group: [M][nup][3K] in the work
 // buffer of the group's first slot (grown on first use with more densities).
-static double* group_qup(MvGroup& gr) {
+static double* group_qup(MvGroup& gr, bool close = false) {
   Level& lv = *gr.lv;
   Work& w0 = lv.wk(gr.slot[0]);
-  const size_t need = (size_t)3 * gr.K * lv.M * lv.nup;
-  if (w0.qup.count < need) {
+  DevArray<double>& buf = close ? w0.qup2 : w0.qup;
+  const size_t need = (size_t)3 * gr.K * lv.M * (close ? lv.nup2 : lv.nup);
+  if (buf.count < need) {
     HIPCHK(hipDeviceSynchronize());  // the old buffer may still be read by queued work
-    w0.qup.alloc(need);
+    buf.alloc(need);
   }
-  return w0.qup.p;
+  return buf.p;
 }
 
 void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
@@ -294,6 +310,7 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
     std::vector<GemmDesc> ga, gb;
     int nga = 0, ngb = 0;
     double* qup = c.n_near > 0 ? group_qup(gr) : nullptr;
+    double* qup2 = c.n_near2 > 0 ? group_qup(gr, true) : nullptr;
     const int C = 3 * gr.K;
     for (int r = 0; r < gr.K; ++r) {
       Work& w = lv.wk(gr.slot[r]);
@@ -307,6 +324,9 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
         if (qup)  // density on the upsampled grid of every sphere, interleaved: qup[j][f][3r + comp] = (Yup coef)
           push_gemm(gb, ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L, qup + 3 * r + comp, 1, C,
                     nup * C);
+        if (qup2)  // the same on the close-pair grid
+          push_gemm(gb, ngb, lv.nup2, M, L, lv.Yup2.p, L, w.coef.p + (size_t)comp * M * L, L, qup2 + 3 * r + comp,
+                    1, C, lv.nup2 * C);
       }
       qp.p[r] = gr.in[r];
     }
@@ -384,6 +404,8 @@ void pqn_ctx_impl::side_work(MvGroup& gr, hipStream_t st) {
   stage_begin(kStageNear);
   launch_near(st, gr.K, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, qup, cf, c.near_list.p, lv.n, lv.M, lv.N,
               lv.nup, lv.p, lv.L, 3.0 / (4.0 * kPi * c.a), np);
+  launch_near(st, gr.K, c.n_near2, c.ctr.p, lv.off.p, lv.offup2.p, lv.shab.p, lv.wk(gr.slot[0]).qup2.p, cf,
+              c.near_list2.p, lv.n, lv.M, lv.N, lv.nup2, lv.p, lv.L, 3.0 / (4.0 * kPi * c.a), np);
   stage_end(kStageNear);
   stage_begin(kStageLocal);
   if (gr.K == 1) {
@@ -430,6 +452,9 @@ void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
       if (c.n_near > 0)  // interleaved [M][nup][3]
         push_gemm(gb, ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup.p + comp, 1, 3,
                   nup * 3);
+      if (c.n_near2 > 0)
+        push_gemm(gb, ngb, lv.nup2, M, L, lv.Yup2.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup2.p + comp, 1, 3,
+                  lv.nup2 * 3);
     }
     pk.push_back(PackDesc{gr.in[0], lv.off.p, lv.w.p, lv.src.p, n, N, npk});
     npk += N;
@@ -438,6 +463,12 @@ void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
       nd.push_back(NearDesc{c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, w.qup.p, w.coef.p, c.near_list.p, w.near_part.p,
                             3.0 / (4.0 * kPi * c.a), n, M, N, nup, lv.p, L, nch, nnd});
       nnd += c.n_near * nch;
+    }
+    if (c.n_near2 > 0) {
+      const int nch = (n + 63) / 64;
+      nd.push_back(NearDesc{c.ctr.p, lv.off.p, lv.offup2.p, lv.shab.p, w.qup2.p, w.coef.p, c.near_list2.p,
+                            w.near_part.p, 3.0 / (4.0 * kPi * c.a), n, M, N, lv.nup2, lv.p, L, nch, nnd});
+      nnd += c.n_near2 * nch;
     }
     md.push_back(MomDesc{gr.in[0], lv.off.p, lv.w.p, w.mom.p, n, N, nmd});
     nmd += M;
@@ -555,6 +586,9 @@ IterTables pqn_ctx_impl::iteration_tables(pqn_ctx_impl& c, Level& lv, int slot, 
               w.selfo.p + (size_t)comp * 3 * N, n, N, n);
     if (c.n_near > 0)  // interleaved [M][nup][3]
       push_gemm(gb, t.ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup.p + comp, 1, 3, nup * 3);
+    if (c.n_near2 > 0)
+      push_gemm(gb, t.ngb, lv.nup2, M, L, lv.Yup2.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup2.p + comp, 1, 3,
+                lv.nup2 * 3);
   }
   DescPack dp;
   t.oa = dp.add(ga);
@@ -592,6 +626,8 @@ void pqn_ctx_impl::iteration_launches(pqn_ctx_impl& c, Level& lv, int slot, int 
   np.p[0] = wk.near_part.p;
   launch_near(s, 1, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, wk.qup.p, cf, c.near_list.p, lv.n, lv.M, lv.N,
               lv.nup, lv.p, lv.L, scale, np);
+  launch_near(s, 1, c.n_near2, c.ctr.p, lv.off.p, lv.offup2.p, lv.shab.p, wk.qup2.p, cf, c.near_list2.p, lv.n, lv.M,
+              lv.N, lv.nup2, lv.p, lv.L, scale, np);
   launch_moments(s, q, lv.off.p, lv.w.p, lv.n, lv.M, lv.N, wk.mom.p);
   launch_combine(s, q, wk.selfo.p, 3, wk.far_part.p, lv.nchunks, wk.near_part.p, c.npart.p, wk.mom.p, lv.off.p, lv.n,
                  lv.N, c.a, w);
@@ -609,8 +645,9 @@ void pqn_ctx_impl::launch_iteration_graph(pqn_ctx_impl& c, Level& lv, int slot, 
   while ((int)lv.graphs.size() <= slot) lv.graphs.emplace_back(new GraphCache());
   GraphCache& gc = *lv.graphs[slot];
   const double* qup_now = lv.wk(slot).qup.p;  // may move when a wider group grows it
+  const double* qup2_now = lv.wk(slot).qup2.p;
   if (gc.epoch != c.config_epoch || gc.prec != prec || (int)gc.execs.size() != m || gc.hp != hp ||
-      gc.qup != qup_now) {
+      gc.qup != qup_now || gc.qup2 != qup2_now) {
     HIPCHK(hipStreamSynchronize(stream));
     gc.clear();
     gc.execs.assign(m, nullptr);
@@ -618,6 +655,7 @@ void pqn_ctx_impl::launch_iteration_graph(pqn_ctx_impl& c, Level& lv, int slot, 
     gc.prec = prec;
     gc.hp = hp;
     gc.qup = qup_now;
+    gc.qup2 = qup2_now;
   }
   SysBuf& b = lv.sb(slot);
   const long len = 3L * lv.N;

@@ -116,6 +116,7 @@ inline int far_layout(const pqn_config_desc& c) {
 
 struct Work {
   DevArray<double> far_part, near_part, coef, qup, selfo, mom;
+  DevArray<double> qup2;  // densities on the close-pair grid, same interleaving as qup
 };
 
 // Krylov storage of one linear system on one level.
@@ -134,7 +135,8 @@ struct GraphCache {
   int prec = -1;
   unsigned long epoch = 0;
   const double* hp = nullptr;   // Hessenberg staging the graphs write to
-  const double* qup = nullptr;  // upsampled-density buffer the graphs read
+  const double* qup = nullptr;  // upsampled-density buffers the graphs read
+  const double* qup2 = nullptr;
   std::vector<hipGraphExec_t> execs;
   DevArray<char> dtab;  // per-k descriptor tables read by the captured kernels
   size_t stride = 0;
@@ -151,6 +153,9 @@ struct Level {
   int M = 0, n = 0, N = 0, L = 0, nup = 0, p = 0;
   DevArray<double> off, w, G, T, Yup, shab;
   DevArray<double4> offup;
+  int nup2 = 0;  // close-pair grid (0 = none)
+  DevArray<double> Yup2;
+  DevArray<double4> offup2;
   DevArray<double> src;  // packed far sources, up to kMaxRhs densities (FP64 record is the larger)
   int nchunks = 1, spc = 1, tpt = 2;
   int restart = 50, max_iter = 500;
@@ -218,6 +223,8 @@ struct pqn_ctx_impl {
   DevArray<unsigned char> cls;
   DevArray<int> partners, npart, near_list;
   int max_slots = 0, n_near = 0;
+  DevArray<int> near_list2;  // close near pairs (gap < near_close_gap), same format as near_list
+  int n_near2 = 0;
   std::vector<int> h_partners, h_npart;
   DevArray<double> FT, UO;
   // lockstep GMRES scratch: per-system Hessenberg columns, read back in one copy

@@ -184,7 +184,21 @@ std::vector<double> sh_recurrence_table(int p) {
   return t;
 }
 
-void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, SphereTables& t) {
+// Grid up times finer per direction and the degree-p synthesis on it.
+static void upsampled_grid(const SphereTables& t, int up, std::vector<double>& off, std::vector<double>& w,
+                           std::vector<double>& Y, int& n_up) {
+  const int nt = up * t.n_theta, np = up * t.n_phi;
+  n_up = nt * np;
+  std::vector<double> ctu, phu;
+  sphere_grid(nt, np, t.radius, off, w, &ctu, &phu);
+  Y.assign((size_t)n_up * t.L, 0.0);
+  for (int f = 0; f < n_up; ++f) {
+    double st = std::sqrt(1.0 - ctu[f] * ctu[f]);
+    sh_row(t.p, ctu[f], st, std::cos(phu[f]), std::sin(phu[f]), &Y[(size_t)f * t.L]);
+  }
+}
+
+void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, SphereTables& t, int close_up) {
   if (n_theta < 2 || n_phi < 2 * n_theta - 1 || n_theta - 1 > kMaxDegree)
     throw std::runtime_error("grid must have n_theta >= 2, n_phi >= 2 n_theta - 1, degree <= 40");
   t.n_theta = n_theta;
@@ -230,14 +244,10 @@ void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, Sph
   t.up = near_up;
   t.nt_up = near_up * n_theta;
   t.np_up = near_up * n_phi;
-  t.n_up = t.nt_up * t.np_up;
-  std::vector<double> ctu, phu;
-  sphere_grid(t.nt_up, t.np_up, radius, t.off_up, t.w_up, &ctu, &phu);
-  t.Y_up.assign((size_t)t.n_up * t.L, 0.0);
-  for (int f = 0; f < t.n_up; ++f) {
-    double st = std::sqrt(1.0 - ctu[f] * ctu[f]);
-    sh_row(t.p, ctu[f], st, std::cos(phu[f]), std::sin(phu[f]), &t.Y_up[(size_t)f * t.L]);
-  }
+  upsampled_grid(t, near_up, t.off_up, t.w_up, t.Y_up, t.n_up);
+  t.up2 = close_up > 0 ? close_up : 0;
+  t.n_up2 = 0;
+  if (t.up2 > 0) upsampled_grid(t, t.up2, t.off_up2, t.w_up2, t.Y_up2, t.n_up2);
   t.shab = sh_recurrence_table(t.p);
 }
 

@@ -84,8 +84,9 @@ def test_unresolved_contact_makes_lcp_indefinite_and_step_refuses():
     """Two spheres swimming head on at gap 3e-4 on the 8x16 grid: the grid does not
     resolve the gap, the discrete relative mobility of the pair (the 1x1 LCP matrix) is
     negative, PQN meets p.Ap <= 0 (counted in nonpos_curvature), and pqn_step refuses
-    the step with PQN_ERR_INDEFINITE, leaving the configuration as it was. At gap 5e-2
-    the same pair is resolved: A > 0 and the step is taken."""
+    the step with PQN_ERR_INDEFINITE, leaving the configuration as it was. The close-pair
+    class (3x grid below gap 1e-2) resolves it, and so does the plain rule at gap 5e-2:
+    A > 0 and the step is taken."""
     c, axes = _pair(3e-4)
     with binding.Context(c, axes, 8, 16, gmres_tol=1e-10) as ctx:
         pairs, gaps = ctx.find_contacts(0.1)
@@ -101,6 +102,12 @@ def test_unresolved_contact_makes_lcp_indefinite_and_step_refuses():
         assert e.value.status == PQN_ERR_INDEFINITE
         c1, a1 = ctx.get_state()
         assert np.array_equal(c0, c1) and np.array_equal(a0, a1)
+    # the close-pair class (finer near grid below gap 1e-2) resolves the pair: A > 0, the step is taken
+    with binding.Context(c, axes, 8, 16, gmres_tol=1e-10, near_close_gap=1e-2, near_close_up=3) as ctx:
+        pairs, _ = ctx.find_contacts(0.1)
+        assert ctx.lcp_apply(pairs, np.ones(1))[0] > 0.0
+        st = ctx.step(0.1, 0.1, 'mono')
+        assert st['status'] == binding.PQN_OK and st['lcp']['nonpos_curvature'] == 0
     c, axes = _pair(5e-2)
     with binding.Context(c, axes, 8, 16, gmres_tol=1e-10) as ctx:
         pairs, _ = ctx.find_contacts(0.1)

@@ -289,3 +289,44 @@ def test_near_upsampling_factor_matches_oracle():
         a = ctx.lcp_apply(pairs, np.ones(1))[0]
     say('near_up', up, 'pair A', a, 'oracle', a_ref)
     assert a > 0.0 and abs(a - a_ref) < 1e-9 * abs(a_ref)
+
+
+CLOSE = dict(near_close_gap=0.05, near_close_up=3)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_close_pair_class_matches_oracle(prec, tol):
+    """Near pairs closer than near_close_gap on the finer grid: on the 8-sphere cluster
+    (gaps 0.01-0.1) some pairs fall below 0.05; the operator equals the oracle's with the
+    same two classes, and differs from the single-class operator."""
+    w = inputs.workload('tiny', 0)
+    c = w['centers']
+    g = bie.Geometry(c, 1.0, 8, 16, **CLOSE)
+    nclose = sum(1 for i in range(g.M) for j in range(g.M)
+                 if i != j and np.linalg.norm(c[i] - c[j]) - 2.0 < 0.05)
+    assert nclose > 0
+    q = np.random.default_rng(6).standard_normal((g.N, 3))
+    with binding.Context(c, None, 8, 16, precision=prec, **CLOSE) as ctx:
+        y = ctx.bie_apply(soa(q))
+    ref = bie.operator_apply(g, q).reshape(-1, 3).T
+    say('close class', prec, nclose, 'ordered close pairs, rel err', rel(y, ref))
+    assert rel(y, ref) < tol
+    assert rel(bie.operator_apply(bie.Geometry(c, 1.0, 8, 16), q).reshape(-1, 3).T, ref) > 1e-6
+
+
+def test_close_pair_class_in_batch_and_graph_paths():
+    """The batch context's segmented launches and the graph-replayed single-system
+    iterations run the close pairs too: same velocities as the eager single context."""
+    w = inputs.workload('tiny', 0)
+    c = w['centers']
+    F = inputs.random_forces(9, c.shape[0])
+    kw = dict(gmres_tol=1e-12, **CLOSE)
+    with binding.Context(c, None, 8, 16, **kw) as ctx:
+        U, _ = ctx.mobility_apply(F)
+    with binding.Context(c, None, 8, 16, graphs=True, **kw) as ctx:
+        Ug, _ = ctx.mobility_apply(F)
+    c2 = c + np.array([0.3, -0.2, 0.1])
+    with binding.BatchContext([(c, 8, 16), (c2, 8, 16)], **kw) as bc:
+        Ub, _ = bc.mobility_apply([F, F])
+    assert rel(Ug, U) < 1e-12
+    assert rel(Ub[0], U) < 1e-11 and rel(Ub[1], U) < 1e-11   # a translated copy moves the same way
