@@ -347,6 +347,23 @@ def main():
                     rows.append((time.perf_counter() - t0, st))
                     states_in.append(cs.get_state())
             tmi, dmi = [], 0.0
+            active_k = [k for k in range(nin) if rows[k][1]['n_active'] > 0]
+            per_solver = {}
+
+            def replay(cs, solver, name, ks):
+                """Steps from the FP64 states ks with one solver: products and time per step."""
+                out = dict(mvp_hi=[], mvp_lo=[], emvp=[], converged=[], sec=[])
+                for k in ks:
+                    cs.set_state(*states_in[k])
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st_ = cs.step(dt_in, 0.1, solver)
+                    out['sec'].append(round(time.perf_counter() - t0, 3))
+                    for key in ('mvp_hi', 'mvp_lo', 'converged'):
+                        out[key].append(st_['lcp'][key])
+                    out['emvp'].append(round(st_['lcp']['emvp'], 2))
+                per_solver[name] = out
+
             with binding.Context(c, ax_in, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='mixed', tune_K=1,
                                  warm_start=True, near_close_gap=0.02, near_close_up=3,
                                  stream=stream.cuda_stream, side_stream=not args.serial) as cs:
@@ -359,6 +376,15 @@ def main():
                     cm_k, _ = cs.get_state()
                     disp = states_in[k + 1][0] - states_in[k][0]
                     dmi = max(dmi, float(np.abs(cm_k - states_in[k + 1][0]).max() / np.abs(disp).max()))
+                # the other solvers on the same LCPs (the steps with active contacts), mixed precision
+                replay(cs, 'bi', 'bi_pqn', active_k)
+                replay(cs, 'mono', 'mono_pqn', active_k)
+                replay(cs, 'bb', 'bb_pgd', active_k)
+            # Bi-PQN whose low fidelity is the same grid solved to GMRES 1e-3
+            with binding.Context(c, ax_in, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3,
+                                 precision='mixed', tune_K=1, warm_start=True, near_close_gap=0.02,
+                                 near_close_up=3, stream=stream.cuda_stream, side_stream=not args.serial) as cs:
+                replay(cs, 'bi', 'bi_pqn_tol_fidelity', active_k)
             inward_info = dict(steps=nin, dt=dt_in, near_close_gap=0.02, near_close_up=3,
                                axes='towards the centroid',
                                contacts=[r[1]['n_contacts'] for r in rows], active=[r[1]['n_active'] for r in rows],
@@ -370,7 +396,8 @@ def main():
                                sec_per_step_mixed=[round(t_, 3) for t_ in tmi],
                                speedup=round(sum(r[0] for r in rows) / sum(tmi), 3),
                                mixed_displacement_rel_err=dmi,
-                               min_gap_after=round(float(inputs.min_gap(states_in[-1][0])), 6))
+                               min_gap_after=round(float(inputs.min_gap(states_in[-1][0])), 6),
+                               solvers_mixed=dict(steps=active_k, **per_solver))
         except binding.PqnError as e:
             inward_info = dict(error=str(e))
         log('steps with contacts', inward_info)
