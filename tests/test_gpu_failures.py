@@ -11,6 +11,7 @@ pytestmark = pytest.mark.gpu
 
 PQN_ERR_NUMERIC = -4
 PQN_ERR_INDEFINITE = -6
+PQN_ERR_INVALID = -1
 
 
 def _tiny():
@@ -114,3 +115,27 @@ def test_unresolved_contact_makes_lcp_indefinite_and_step_refuses():
         assert ctx.lcp_apply(pairs, np.ones(1))[0] > 0.0
         st = ctx.step(0.1, 0.1, 'mono')
         assert st['status'] == binding.PQN_OK and st['lcp']['nonpos_curvature'] == 0
+
+
+def test_documented_limits_are_rejected_at_create():
+    """Limits stated in the header give PQN_ERR_INVALID at context creation: more than 16
+    near partners of one sphere, harmonic degree above 40, a grid with n_phi < 2 n_theta
+    - 1, near upsampling factors above 8."""
+    # 17 spheres around a central one at centre distance 3.5 (gap 1.5 < near gap 2.0)
+    k = np.arange(17) + 0.5
+    th, ph = np.arccos(1.0 - 2.0 * k / 17), np.pi * (1.0 + 5.0 ** 0.5) * k
+    ring = 3.5 * np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=1)
+    c = np.vstack([np.zeros(3), ring])
+    d = np.linalg.norm(c[:, None] - c[None], axis=2) + 10.0 * np.eye(c.shape[0])
+    assert d.min() > 2.0  # no overlaps
+    with pytest.raises(binding.PqnError) as e:
+        binding.Context(c, None, 4, 8, near_gap=2.0)
+    assert e.value.status == PQN_ERR_INVALID and '16' in str(e.value)
+    with binding.Context(c[:17], None, 4, 8, near_gap=2.0):
+        pass  # 16 partners are accepted
+    one = np.zeros((1, 3))
+    for kw in (dict(n_theta=42, n_phi=84), dict(n_theta=8, n_phi=12), dict(n_theta=4, n_phi=8, near_up=9),
+               dict(n_theta=4, n_phi=8, near_close_gap=0.1, near_close_up=9)):
+        with pytest.raises(binding.PqnError) as e:
+            binding.Context(one, None, **kw)
+        assert e.value.status == PQN_ERR_INVALID, kw
