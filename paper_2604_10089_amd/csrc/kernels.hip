@@ -262,6 +262,8 @@ __global__ __launch_bounds__(256) void k_far32s(const float* __restrict__ src, c
                                                 int n, int M, int N, int spc, double scale, OPtrs part, int ntb,
                                                 int total, int per) {
   __shared__ double lds[9 * 64];
+  // issue priority over waves of kernels running beside it (near tiles, GEMMs on the side stream)
+  __builtin_amdgcn_s_setprio(3);
   const int item = xcd_item(blockIdx.x, per);
   if (item >= total) return;  // uniform over the block: no barrier is skipped by part of it
   far32_split_body<K>(item % ntb, item / ntb, src, off, ctr, cls, n, M, N, spc, scale, part, lds);
@@ -273,6 +275,7 @@ __global__ __launch_bounds__(256) void k_far32(const float* __restrict__ src, co
                                                const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
                                                int n, int M, int N, int spc, double scale, OPtrs part, int ntb,
                                                int total, int per) {
+  __builtin_amdgcn_s_setprio(3);  // as in k_far32s
   const int item = xcd_item(blockIdx.x, per);
   if (item >= total) return;
   far32_body<TPT, K>(item % ntb, item / ntb, src, off, ctr, cls, n, M, N, spc, scale, part);
