@@ -42,16 +42,18 @@ def rotate_axes(axes, omega, dt):
 
 
 def step(centers, axes, radius, grid_hi, grid_lo, dt, delta, slip, solver='mono',
-         tol_gmres=1e-13, lcp_opts=None, mu=1.0):
+         tol_gmres=1e-13, lcp_opts=None, mu=1.0, near=None):
     """One step C <- C + dt (G U_nc + G M D x) with the LCP of eq. (LCP) (eq. (dvi)).
 
     Contacts at the current configuration, U_nc from the slip-driven solve,
     b = Phi/dt + D^T U_nc, x from the chosen solver, then the Euler update of
     centres and Janus axes. Dense operators are used (small suspensions).
-    Returns (centers, axes, info).
+    Returns (centers, axes, info). near: keyword arguments of the geometries'
+    near rule (near_gap, near_up, near_close_gap, near_close_up).
     """
     lcp_opts = {} if lcp_opts is None else dict(lcp_opts)
-    g_hi = bie.Geometry(centers, radius, grid_hi[0], grid_hi[1], mu)
+    near = {} if near is None else dict(near)
+    g_hi = bie.Geometry(centers, radius, grid_hi[0], grid_hi[1], mu, **near)
     A_hi = bie.dense_operator(g_hi)
     mob_hi = lambda FT: bie.mobility_apply(g_hi, FT, dense=A_hi)
     pairs, gaps = find_contacts(centers, radius, delta)
@@ -61,7 +63,7 @@ def step(centers, axes, radius, grid_hi, grid_lo, dt, delta, slip, solver='mono'
         b = lcp.lcp_b(gaps, dt, centers, pairs, U_nc)
         Aop = lcp.lcp_operator(mob_hi, centers, pairs)
         if solver == 'bi':
-            g_lo = bie.Geometry(centers, radius, grid_lo[0], grid_lo[1], mu)
+            g_lo = bie.Geometry(centers, radius, grid_lo[0], grid_lo[1], mu, **near)
             A_lo = bie.dense_operator(g_lo)
             Alo = lcp.lcp_operator(lambda FT: bie.mobility_apply(g_lo, FT, dense=A_lo), centers, pairs)
             x, _, st = lcp.bi_pqn(Aop, Alo, b, **lcp_opts)

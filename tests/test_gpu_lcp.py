@@ -327,3 +327,24 @@ def test_lcp_solve_dev_matches_host_arrays(cases):
         with pytest.raises(binding.PqnError):
             ctx.lcp_solve_dev(n, Pbad.data_ptr(), B.data_ptr(), X2.data_ptr(), 'mono')
         assert torch.equal(X2, X)
+
+
+def test_step_with_close_pairs_matches_oracle():
+    """A time step of the 8-sphere cluster swimming towards its centroid (dt 0.1) with the
+    close-pair class (gap < 0.05 on the 3x grid): contacts, active set and the new
+    configuration equal the oracle's step with the same near rule."""
+    w = inputs.workload('tiny', 0)
+    c = w['centers']
+    ax = c.mean(axis=0) - c
+    ax /= np.linalg.norm(ax, axis=1, keepdims=True)
+    near = dict(near_close_gap=0.05, near_close_up=3)
+    c1, ax1, info = dynamics.step(c, ax, 1.0, (8, 16), (4, 8), 0.1, 0.1, 1.0, solver='mono',
+                                  lcp_opts=dict(tol_abs=1e-12, tol_rel=1e-15), tol_gmres=1e-13, near=near)
+    with binding.Context(c, ax, 8, 16, lo=(4, 8), gmres_tol=1e-13, **near) as ctx:
+        st = ctx.step(0.1, 0.1, 'mono', tol_abs=1e-12, tol_rel=1e-15)
+        c2, ax2 = ctx.get_state()
+    say('close-pair step: contacts', st['n_contacts'], 'active', st['n_active'])
+    assert st['n_contacts'] == info['pairs'].shape[0]
+    assert st['n_active'] == int((info['x'] > 0).sum()) and st['n_active'] > 0
+    assert np.abs(c2 - c1).max() < 1e-10
+    assert np.abs(ax2 - ax1).max() < 1e-10
