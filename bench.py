@@ -102,6 +102,9 @@ def main():
     ap.add_argument('--batch-probe', action='store_true',
                     help='short run for rocprofv3 --kernel-trace: only the 32-suspension batch, mixed precision '
                          '(one warm-up product and three timed ones), one JSON line')
+    ap.add_argument('--contact-probe', action='store_true',
+                    help='short run for rocprofv3 --kernel-trace: only the five time steps with active contacts '
+                         '(FP64, then the mixed replay), one JSON line')
     ap.add_argument('--lcp-table', action='store_true',
                     help='instead of the benchmark line: BB-PGD, Mono-PQN and Bi-PQN on planted LCPs of the 27-, '
                          '64- and 216-sphere workloads (three seeds each), one JSON line')
@@ -146,6 +149,10 @@ def main():
 
     if args.lcp_table:
         print(json.dumps(lcp_table(binding, inputs, stream)), flush=True)
+        return
+
+    if args.contact_probe:
+        print(json.dumps(contact_steps(binding, inputs, torch, stream, w, args, replay_solvers=False)), flush=True)
         return
 
     if args.batch_probe:
@@ -328,78 +335,7 @@ def main():
 
     inward_info = None
     if not args.no_steps:
-        # time steps with active contacts: Janus axes towards the centroid (the paper's online runs start
-        # with the amphiphilic sides facing the origin), dt 0.1, so approaching pairs enter the LCP; near
-        # pairs closer than 0.02 take the 3x grid, which keeps A positive definite once gaps close below
-        # ~5e-3
-        ax_in = c.mean(axis=0) - c
-        ax_in /= np.linalg.norm(ax_in, axis=1, keepdims=True)
-        nin, dt_in = 5, 0.1
-        try:
-            states_in, rows = [(c, ax_in)], []
-            with binding.Context(c, ax_in, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='fp64', tune_K=1,
-                                 warm_start=True, near_close_gap=0.02, near_close_up=3,
-                                 stream=stream.cuda_stream) as cs:
-                for _ in range(nin):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    st = cs.step(dt_in, 0.1, 'bi')
-                    rows.append((time.perf_counter() - t0, st))
-                    states_in.append(cs.get_state())
-            tmi, dmi = [], 0.0
-            active_k = [k for k in range(nin) if rows[k][1]['n_active'] > 0]
-            per_solver = {}
-
-            def replay(cs, solver, name, ks):
-                """Steps from the FP64 states ks with one solver: products and time per step."""
-                out = dict(mvp_hi=[], mvp_lo=[], emvp=[], converged=[], sec=[])
-                for k in ks:
-                    cs.set_state(*states_in[k])
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    st_ = cs.step(dt_in, 0.1, solver)
-                    out['sec'].append(round(time.perf_counter() - t0, 3))
-                    for key in ('mvp_hi', 'mvp_lo', 'converged'):
-                        out[key].append(st_['lcp'][key])
-                    out['emvp'].append(round(st_['lcp']['emvp'], 2))
-                per_solver[name] = out
-
-            with binding.Context(c, ax_in, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='mixed', tune_K=1,
-                                 warm_start=True, near_close_gap=0.02, near_close_up=3,
-                                 stream=stream.cuda_stream, side_stream=not args.serial) as cs:
-                for k in range(nin):
-                    cs.set_state(*states_in[k])
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    cs.step(dt_in, 0.1, 'bi')
-                    tmi.append(time.perf_counter() - t0)
-                    cm_k, _ = cs.get_state()
-                    disp = states_in[k + 1][0] - states_in[k][0]
-                    dmi = max(dmi, float(np.abs(cm_k - states_in[k + 1][0]).max() / np.abs(disp).max()))
-                # the other solvers on the same LCPs (the steps with active contacts), mixed precision
-                replay(cs, 'bi', 'bi_pqn', active_k)
-                replay(cs, 'mono', 'mono_pqn', active_k)
-                replay(cs, 'bb', 'bb_pgd', active_k)
-            # Bi-PQN whose low fidelity is the same grid solved to GMRES 1e-3
-            with binding.Context(c, ax_in, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3,
-                                 precision='mixed', tune_K=1, warm_start=True, near_close_gap=0.02,
-                                 near_close_up=3, stream=stream.cuda_stream, side_stream=not args.serial) as cs:
-                replay(cs, 'bi', 'bi_pqn_tol_fidelity', active_k)
-            inward_info = dict(steps=nin, dt=dt_in, near_close_gap=0.02, near_close_up=3,
-                               axes='towards the centroid',
-                               contacts=[r[1]['n_contacts'] for r in rows], active=[r[1]['n_active'] for r in rows],
-                               mvp_hi=[r[1]['lcp']['mvp_hi'] for r in rows],
-                               mvp_lo=[r[1]['lcp']['mvp_lo'] for r in rows],
-                               emvp=[round(r[1]['lcp']['emvp'], 2) for r in rows],
-                               lcp_converged=[r[1]['lcp']['converged'] for r in rows if r[1]['n_contacts'] > 0],
-                               sec_per_step_fp64=[round(r[0], 3) for r in rows],
-                               sec_per_step_mixed=[round(t_, 3) for t_ in tmi],
-                               speedup=round(sum(r[0] for r in rows) / sum(tmi), 3),
-                               mixed_displacement_rel_err=dmi,
-                               min_gap_after=round(float(inputs.min_gap(states_in[-1][0])), 6),
-                               solvers_mixed=dict(steps=active_k, **per_solver))
-        except binding.PqnError as e:
-            inward_info = dict(error=str(e))
+        inward_info = contact_steps(binding, inputs, torch, stream, w, args)
         log('steps with contacts', inward_info)
 
     batch_info = None
@@ -493,6 +429,87 @@ def main():
     if not args.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline(c, nt, nph, res['mixed1'])
     print(json.dumps(out), flush=True)
+
+
+def contact_steps(binding, inputs, torch, stream, w, args, replay_solvers=True):
+    """Five time steps with active contacts on the 216-sphere workload (FP64 trajectory, the mixed
+    path replayed from each state, and optionally every solver on the same LCPs)."""
+    c, nt, nph = w['centers'], w['n_theta'], w['n_phi']
+    # time steps with active contacts: Janus axes towards the centroid (the paper's online runs start
+    # with the amphiphilic sides facing the origin), dt 0.1, so approaching pairs enter the LCP; near
+    # pairs closer than 0.02 take the 3x grid, which keeps A positive definite once gaps close below
+    # ~5e-3
+    ax_in = c.mean(axis=0) - c
+    ax_in /= np.linalg.norm(ax_in, axis=1, keepdims=True)
+    nin, dt_in = 5, 0.1
+    try:
+        states_in, rows = [(c, ax_in)], []
+        with binding.Context(c, ax_in, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='fp64', tune_K=1,
+                             warm_start=True, near_close_gap=0.02, near_close_up=3,
+                             stream=stream.cuda_stream) as cs:
+            for _ in range(nin):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = cs.step(dt_in, 0.1, 'bi')
+                rows.append((time.perf_counter() - t0, st))
+                states_in.append(cs.get_state())
+        tmi, dmi = [], 0.0
+        active_k = [k for k in range(nin) if rows[k][1]['n_active'] > 0]
+        per_solver = {}
+
+        def replay(cs, solver, name, ks):
+            """Steps from the FP64 states ks with one solver: products and time per step."""
+            out = dict(mvp_hi=[], mvp_lo=[], emvp=[], converged=[], sec=[])
+            for k in ks:
+                cs.set_state(*states_in[k])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st_ = cs.step(dt_in, 0.1, solver)
+                out['sec'].append(round(time.perf_counter() - t0, 3))
+                for key in ('mvp_hi', 'mvp_lo', 'converged'):
+                    out[key].append(st_['lcp'][key])
+                out['emvp'].append(round(st_['lcp']['emvp'], 2))
+            per_solver[name] = out
+
+        with binding.Context(c, ax_in, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='mixed', tune_K=1,
+                             warm_start=True, near_close_gap=0.02, near_close_up=3,
+                             stream=stream.cuda_stream, side_stream=not args.serial) as cs:
+            for k in range(nin):
+                cs.set_state(*states_in[k])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                cs.step(dt_in, 0.1, 'bi')
+                tmi.append(time.perf_counter() - t0)
+                cm_k, _ = cs.get_state()
+                disp = states_in[k + 1][0] - states_in[k][0]
+                dmi = max(dmi, float(np.abs(cm_k - states_in[k + 1][0]).max() / np.abs(disp).max()))
+            # the other solvers on the same LCPs (the steps with active contacts), mixed precision
+            if replay_solvers:
+                replay(cs, 'bi', 'bi_pqn', active_k)
+                replay(cs, 'mono', 'mono_pqn', active_k)
+                replay(cs, 'bb', 'bb_pgd', active_k)
+        if replay_solvers:
+            # Bi-PQN whose low fidelity is the same grid solved to GMRES 1e-3
+            with binding.Context(c, ax_in, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3,
+                                 precision='mixed', tune_K=1, warm_start=True, near_close_gap=0.02,
+                                 near_close_up=3, stream=stream.cuda_stream, side_stream=not args.serial) as cs:
+                replay(cs, 'bi', 'bi_pqn_tol_fidelity', active_k)
+        inward_info = dict(steps=nin, dt=dt_in, near_close_gap=0.02, near_close_up=3,
+                           axes='towards the centroid',
+                           contacts=[r[1]['n_contacts'] for r in rows], active=[r[1]['n_active'] for r in rows],
+                           mvp_hi=[r[1]['lcp']['mvp_hi'] for r in rows],
+                           mvp_lo=[r[1]['lcp']['mvp_lo'] for r in rows],
+                           emvp=[round(r[1]['lcp']['emvp'], 2) for r in rows],
+                           lcp_converged=[r[1]['lcp']['converged'] for r in rows if r[1]['n_contacts'] > 0],
+                           sec_per_step_fp64=[round(r[0], 3) for r in rows],
+                           sec_per_step_mixed=[round(t_, 3) for t_ in tmi],
+                           speedup=round(sum(r[0] for r in rows) / sum(tmi), 3),
+                           mixed_displacement_rel_err=dmi,
+                           min_gap_after=round(float(inputs.min_gap(states_in[-1][0])), 6),
+                           solvers_mixed=dict(steps=active_k, **per_solver))
+    except binding.PqnError as e:
+        inward_info = dict(error=str(e))
+    return inward_info
 
 
 def lcp_table(binding, inputs, stream):
