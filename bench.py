@@ -507,8 +507,8 @@ def contact_steps(binding, inputs, torch, stream, w, args, replay_solvers=True):
                            mixed_displacement_rel_err=dmi,
                            min_gap_after=round(float(inputs.min_gap(states_in[-1][0])), 6),
                            solvers_mixed=dict(steps=active_k, **per_solver))
-    except binding.PqnError as e:
-        inward_info = dict(error=str(e))
+    except Exception as e:  # a failed step is reported in the line, not a lost line
+        inward_info = dict(error=f'{type(e).__name__}: {e}')
     return inward_info
 
 
