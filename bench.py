@@ -11,11 +11,16 @@ The same JSON line reports: the single-force-set rate and the plain FP64 path
 (both K = 1 and K = 6), the mixed-vs-FP64 error of every velocity block, the
 far pair-sum kernel against the FP32 vector roofline (HIP events on the
 library's stream), the 32-suspension uneven batch (one far launch per GMRES
-iteration) against the same suspensions one by one, one Bi-PQN and one
-Mono-PQN solve of a planted LCP on the suspension's contact set (low fidelity
-6x12), and the CPU oracle's rate on a bounded sample of the same operator.
+iteration) against the same suspensions one by one, the LCP solvers on a
+planted LCP of the suspension's contact set (low fidelity 6x12), ten Janus
+time steps at dt 1e-3, five time steps with active contacts (axes towards the
+centroid, dt 0.1) with every solver replayed on their LCPs, and the CPU
+oracle's rate on a bounded sample of the same operator (one core and all
+cores).
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline] [--no-lcp] [--no-batch]
+       [--no-steps] [--serial]; short runs for profilers: --counters-probe, --batch-probe, --contact-probe;
+       --lcp-table for the solver comparison on three workloads.
 """
 import argparse
 import json
