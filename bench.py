@@ -163,8 +163,9 @@ def main():
     if args.batch_probe:
         inst = inputs.batched_suspensions(args.seed)
         FTb = [inputs.random_forces(500 + b, ci.shape[0]) for b, (ci, _, _) in enumerate(inst)]
-        with binding.BatchContext(inst, gmres_tol=1e-8, precision='mixed', tpt=args.tpt or 2,
-                                  stream=stream.cuda_stream, side_stream=not args.serial) as bc:
+        kwp = dict(tpt=args.tpt) if args.tpt else {}
+        with binding.BatchContext(inst, gmres_tol=1e-8, precision='mixed', stream=stream.cuda_stream,
+                                  side_stream=not args.serial, **kwp) as bc:
             bc.mobility_apply(FTb)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -347,9 +348,12 @@ def main():
     if not args.no_batch:
         inst = inputs.batched_suspensions(args.seed)
         FTb = [inputs.random_forces(500 + b, ci.shape[0]) for b, (ci, _, _) in enumerate(inst)]
-        kw = dict(gmres_tol=1e-8, precision='mixed', tpt=args.tpt or 2, stream=stream.cuda_stream,
-                  side_stream=not args.serial)
+        # launch shape from the autotuner's batch entry unless fixed on the command line
+        kw = dict(gmres_tol=1e-8, precision='mixed', stream=stream.cuda_stream, side_stream=not args.serial)
+        if args.tpt:
+            kw['tpt'] = args.tpt
         with binding.BatchContext(inst, **kw) as bc:
+            batch_shape = bc.far_shape
             bc.mobility_apply(FTb)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -382,7 +386,7 @@ def main():
                           batched_sec=round(tb, 4), mvps_batched=round(len(inst) / tb, 2),
                           mvps_batched_fp64=round(len(inst) / tb64, 2), mixed_rel_err_vs_fp64=err_b,
                           one_by_one_sec=round(ts, 4), mvps_one_by_one=round(len(inst) / ts, 2),
-                          speedup=round(ts / tb, 3), lockstep_iterations=bst['n_far'])
+                          speedup=round(ts / tb, 3), lockstep_iterations=bst['n_far'], far_layout=batch_shape)
         log('batch', batch_info)
 
     m6 = res['mixed6']

@@ -245,8 +245,22 @@ class BatchContext:
     """Independent suspensions of uneven size in one batch context (pqn_batch_*)."""
 
     def __init__(self, instances, torch_alloc=False, **kw):
-        """instances: list of (centers [M,3], n_theta, n_phi); kw: shared settings as in Context."""
+        """instances: list of (centers [M,3], n_theta, n_phi); kw: shared settings as in Context.
+        Without tpt / far_chunks / far_split the far launch shape comes from the autotuner's
+        cache for this batch (else 2 targets per thread, automatic chunks)."""
         n = len(instances)
+        if not any(k in kw for k in ('tpt', 'far_chunks', 'far_split')):
+            hit = None
+            try:
+                from paper_2604_10089_amd import autotune
+                hit = autotune.lookup_batch(kw.get('precision', 'fp64'),
+                                            [(_f64(c).reshape(-1, 3), nt, nph) for c, nt, nph in instances])
+            except Exception:
+                hit = None
+            if hit is not None:
+                kw['tpt'], kw['far_chunks'], kw['far_split'] = hit
+        self.far_shape = dict(tpt=kw.get('tpt', 2), chunks=kw.get('far_chunks', 0),
+                              split=int(bool(kw.get('far_split', 0))))
         descs = (ConfigDesc * n)()
         self._centers = [_f64(c).reshape(-1, 3) for c, _, _ in instances]
         self.Ms = [c.shape[0] for c in self._centers]
