@@ -281,7 +281,14 @@ def near_sources(geom, j, up):
 
 
 def near_block(geom, i, j):
-    """Dense (n, 3, n, 3) near-pair block: upsampled plain rule with subtraction."""
+    """Dense (n, 3, n, 3) near-pair block: upsampled plain rule with subtraction.
+
+    Pinned by: the exterior double layer of sphere j's six rigid motions vanishes at
+    every target (gaps 0.4 to 0.01); on band-limited densities the rule converges, as
+    the upsampling grows, to a graded rotated-pole reference quadrature with the
+    density in closed form; the subtracted value is the density at the foot point
+    (tests/test_oracle_bie.py).
+    """
     cache = geom.__dict__.setdefault('_near_cache', {})
     if (i, j) in cache:
         return cache[(i, j)]
@@ -301,7 +308,10 @@ def near_block(geom, i, j):
 
 
 def near_row(geom, i, j, k):
-    """Row (3, n, 3) of the near block for the single target node k of sphere i."""
+    """Row (3, n, 3) of the near block for the single target node k of sphere i.
+
+    Pinned as near_block (the reference-quadrature and foot-point pins use rows).
+    """
     X = geom.x[geom.nodes(i)][k:k + 1]
     up = geom.pair_up(i, j)
     yf, nf, wf = near_sources(geom, j, up)

@@ -28,6 +28,9 @@ def rotate_axes(axes, omega, dt):
 
     The paper tracks orientation (with a quaternion, Sec. 3 footnote); for the
     axisymmetric Janus sphere only the axis matters.
+    Pinned by: closed-form rotations about the coordinate axes (right-hand rule),
+    Omega = 0 and Omega along the axis, composition and inversion, scipy's rotation
+    by the vector Omega dt (tests/test_oracle_step.py).
     """
     out = np.array(axes, dtype=np.float64)
     for i in range(out.shape[0]):
