@@ -140,6 +140,10 @@ typedef struct {
   double kkt_tol_abs;       /* ||min(x, Ax+b)||_2 tolerance, eq. (kkt-error) [1e-8] */
   double kkt_tol_rel;       /* relative change tolerance, eq. (kkt-error) [1e-8] */
   double ssn_tol;           /* semi-smooth Newton stop: step <= ssn_tol * max(1, |(a, a~)|) [1e-14] */
+  int32_t printed_metric;   /* initial quasi-Newton metric of the Mono-PQN solves (Alg. 1, and Alg. 4's
+                               subproblems): 0 = H0 = I for the first step, then B0 = sigma I with
+                               sigma = p.Ap/p.p of that step (invariant to the units of A) [0];
+                               1 = H0 = I throughout, Alg. 1 as printed */
 } pqn_lcp_opts;
 
 typedef struct {
@@ -232,7 +236,11 @@ pqn_status pqn_lcp_solve_dev(pqn_ctx* ctx, int32_t n, const int32_t* pairs_dev, 
  * U = U_nc + M D x -> centres += dt U, Janus axes rotated by Omega dt. An LCP that
  * hits its cap after meeting p.Ap <= 0 (A not positive definite) gives
  * PQN_ERR_INDEFINITE and leaves the configuration unchanged; any other cap gives
- * PQN_WARN_NOT_CONVERGED and the step is taken with the last iterate. */
+ * PQN_WARN_NOT_CONVERGED and the step is taken with the last iterate. A moved
+ * configuration the context cannot hold (a sphere with more than 16 near partners:
+ * PQN_ERR_INVALID; a non-finite centre: PQN_ERR_NUMERIC) is rejected and the context
+ * keeps the configuration it had before the step. pqn_set_state rejects such a
+ * configuration in the same way. */
 pqn_status pqn_step(pqn_ctx* ctx, double dt, double delta, int32_t solver, const pqn_lcp_opts* opts,
                     pqn_step_stats* stats);
 
@@ -253,6 +261,10 @@ pqn_status pqn_batch_mobility_apply(pqn_ctx* ctx, const double* const* FT, doubl
  * pqn_get_self_block: S [3n][3n] rows (c*n+i), columns (d*n+k).
  * pqn_get_grid: node offsets [n][3] and weights [n] of one sphere. */
 pqn_status pqn_bie_apply(pqn_ctx* ctx, int32_t fidelity, const double* q, double* y);
+/* pqn_bie_apply_multi: the same for k <= 6 densities in one pass (q, y [k][3][N] host
+ * arrays): the k applications share every geometry pass of the pair sums, through the
+ * kernels and launch layout of the context's k-density mobility products. */
+pqn_status pqn_bie_apply_multi(pqn_ctx* ctx, int32_t fidelity, int32_t k, const double* q, double* y);
 pqn_status pqn_get_self_block(pqn_ctx* ctx, int32_t fidelity, double* S);
 /* pqn_bie_solve: q solving (1/2 I + D + P) q = rhs by GMRES (plus refinement in mixed
  * precision), rhs, q [3][N] host arrays. */

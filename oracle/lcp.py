@@ -15,6 +15,8 @@ Readings of the paper taken here (each also listed in the design notes):
     uses H^(0) = I and, once its product A p is known, the quasi-Newton matrix
     starts from B0 = sigma I with sigma = p.Ap/p.p (no extra product). sigma is
     kept for the rest of one LCP solve (all Bi-PQN subproblems included).
+    printed_metric=True keeps Alg. 1 as printed instead: H^(0) = I at every
+    (re)start, sigma = 1 throughout.
   * Stopping rule: the KKT errors of eq. (kkt-error), 2-norm, absolute OR
     relative change below tolerance.
   * Prop. 1 root function: L~(a, a~) = [a; a~] + L(a, a~) with L as printed;
@@ -303,8 +305,12 @@ def bb_pgd(Aop, b, x0=None, tau0=1.0, k_max=200, tol_abs=1e-8, tol_rel=1e-8):
 
 
 def mono_pqn(Aop, b, x0=None, Ax0=None, k_max=100, tol_abs=1e-8, tol_rel=1e-8,
-             pairs=(), j_max=50, sigma=None, ssn_tol=1e-14):
+             pairs=(), j_max=50, sigma=None, ssn_tol=1e-14, printed_metric=False):
     """Mono-PQN (Alg. 1) with the SSN prox (Alg. 3) and eta* (Alg. 2).
+
+    sigma: scale of the initial metric B0 = sigma I; None = set from the first
+    step's curvature p.Ap/p.p. printed_metric=True is Alg. 1 as printed,
+    H^(0) = I (sigma = 1) at the start and after every memory reset.
 
     One product A[p] per iteration; A x is carried by the recurrence
     A x+ = A x + eta A p (Remark after Alg. 2). `pairs` are secant pairs
@@ -312,6 +318,8 @@ def mono_pqn(Aop, b, x0=None, Ax0=None, k_max=100, tol_abs=1e-8, tol_rel=1e-8,
     Returns (x, A x, stats) with stats['S'], stats['Y'] the accepted pairs.
     """
     n = b.size
+    if printed_metric:
+        sigma = 1.0
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
     mvp = 0
     if Ax0 is not None:
@@ -381,7 +389,7 @@ def secant_transfer(S, Y, u, v):
 
 
 def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_max=50, x0=None,
-           ssn_tol=1e-14):
+           ssn_tol=1e-14, printed_metric=False):
     """Bi-PQN (Alg. 4, App. E).
 
     x^(0) from Mono-PQN on the low-fidelity matrix; then per outer step the
@@ -409,12 +417,14 @@ def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_
         mvp_lo += 1
     tol0 = max(1e-12, 1e-2 * kkt_error(xs, Alox + b))
     x, Alox, st0 = mono_pqn(Alo, b, xs, Alox, k_max=k_max_inner,
-                            tol_abs=tol0, tol_rel=tol_rel, j_max=j_max, ssn_tol=ssn_tol)
+                            tol_abs=tol0, tol_rel=tol_rel, j_max=j_max, ssn_tol=ssn_tol,
+                            printed_metric=printed_metric)
     mvp_lo += st0['mvp']
 
     def fallback(x0, Ax0, mvp_hi, mvp_lo, k_done, hist):
         xm, Axm, sm = mono_pqn(Ahi, b, x0, Ax0, k_max=max(1, k_max - k_done), tol_abs=tol_abs,
-                               tol_rel=tol_rel, j_max=j_max, ssn_tol=ssn_tol)
+                               tol_rel=tol_rel, j_max=j_max, ssn_tol=ssn_tol,
+                               printed_metric=printed_metric)
         return xm, Axm, Stats(iters=len(hist) + sm['iters'], mvp_hi=mvp_hi + sm['mvp'], mvp_lo=mvp_lo,
                               kkt=sm['kkt'], converged=sm['converged'], hist=hist + sm['hist'], fallback=True)
 
@@ -486,7 +496,7 @@ def bi_pqn(Ahi, Alo, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_
 
 
 def bi_pqn_rec(ops, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_max=50, x0=None,
-               ssn_tol=1e-14):
+               ssn_tol=1e-14, printed_metric=False):
     """Recursive Bi-PQN over a hierarchy of fidelities (the extension of Sec. 7).
 
     ops[0] is the high-fidelity product A[.], ops[1], ops[2], ... ever cheaper
@@ -539,7 +549,8 @@ def bi_pqn_rec(ops, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_m
         H = op(d, corrs)
         if d == nf - 1:
             xs, Hxs, st = mono_pqn(H, c, x, Hx, k_max=k_lim, tol_abs=tol, tol_rel=tol_rel,
-                                   pairs=pairs, j_max=j_max, sigma=sigma, ssn_tol=ssn_tol)
+                                   pairs=pairs, j_max=j_max, sigma=sigma, ssn_tol=ssn_tol,
+                                   printed_metric=printed_metric)
             return xs, Hxs, dict(resets=st['resets'], S=st['S'], Y=st['Y'], sigma=st['sigma'],
                                  iters=st['iters'], kkt=st['kkt'], converged=st['converged'],
                                  hist=st['hist'], fallback=False)
@@ -549,7 +560,8 @@ def bi_pqn_rec(ops, b, k_max=50, k_max_inner=50, tol_abs=1e-8, tol_rel=1e-8, j_m
 
         def fallback(x0, Hx0, k_done, hist):
             xm, Hxm, sm = mono_pqn(H, c, x0, Hx0, k_max=max(1, k_lim - k_done), tol_abs=tol,
-                                   tol_rel=tol_rel, j_max=j_max, ssn_tol=ssn_tol)
+                                   tol_rel=tol_rel, j_max=j_max, ssn_tol=ssn_tol,
+                                   printed_metric=printed_metric)
             return xm, Hxm, dict(resets=resets + sm['resets'], S=[], Y=[], sigma=sigma,
                                  iters=len(hist) + sm['iters'], kkt=sm['kkt'],
                                  converged=sm['converged'], hist=hist + sm['hist'], fallback=True)

@@ -80,7 +80,8 @@ class MvpStats(C.Structure):
 
 class LcpOpts(C.Structure):
     _fields_ = [('k_max', C.c_int32), ('k_max_inner', C.c_int32), ('j_max', C.c_int32),
-                ('kkt_tol_abs', C.c_double), ('kkt_tol_rel', C.c_double), ('ssn_tol', C.c_double)]
+                ('kkt_tol_abs', C.c_double), ('kkt_tol_rel', C.c_double), ('ssn_tol', C.c_double),
+                ('printed_metric', C.c_int32)]
 
 
 class LcpStats(C.Structure):
@@ -146,6 +147,7 @@ def lib():
         'pqn_lcp_solve_dev': (C.c_int, [V, C.c_int32, V, V, V, C.c_int32, _P(LcpOpts), _P(LcpStats)]),
         'pqn_step': (C.c_int, [V, C.c_double, C.c_double, C.c_int32, _P(LcpOpts), _P(StepStats)]),
         'pqn_bie_apply': (C.c_int, [V, C.c_int32, _D, _D]),
+        'pqn_bie_apply_multi': (C.c_int, [V, C.c_int32, C.c_int32, _D, _D]),
         'pqn_get_self_block': (C.c_int, [V, C.c_int32, _D]),
         'pqn_bie_solve': (C.c_int, [V, C.c_int32, _D, _D, _P(MvpStats)]),
         'pqn_get_grid': (C.c_int, [V, C.c_int32, _I, _D, _D]),
@@ -436,20 +438,20 @@ class Context:
         return Ax
 
     def lcp_solve(self, pairs, b, solver='mono', k_max=0, k_max_inner=0, j_max=0, tol_abs=0.0, tol_rel=0.0,
-                  x0=None, ssn_tol=0.0):
+                  x0=None, ssn_tol=0.0, printed_metric=False):
         pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
         b = _f64(b)
         x = np.zeros(pairs.shape[0]) if x0 is None else _f64(x0, (pairs.shape[0],)).copy()
-        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol)
+        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol, int(printed_metric))
         st = LcpStats()
         status = _check(lib().pqn_lcp_solve(self.h, pairs.shape[0], pairs.ctypes.data_as(_I), _dptr(b), _dptr(x),
                                             SOLVERS.get(solver, solver), C.byref(o), C.byref(st)))
         return x, dict(_struct_dict(st), status=status)
 
     def lcp_solve_dev(self, n, pairs_ptr, b_ptr, x_ptr, solver='mono', k_max=0, k_max_inner=0, j_max=0,
-                      tol_abs=0.0, tol_rel=0.0, ssn_tol=0.0):
+                      tol_abs=0.0, tol_rel=0.0, ssn_tol=0.0, printed_metric=False):
         """pqn_lcp_solve_dev on device pointers (ints, e.g. torch tensors' data_ptr())."""
-        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol)
+        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol, int(printed_metric))
         st = LcpStats()
         status = _check(lib().pqn_lcp_solve_dev(self.h, n, C.c_void_p(pairs_ptr), C.c_void_p(b_ptr),
                                                 C.c_void_p(x_ptr), SOLVERS.get(solver, solver), C.byref(o),
@@ -457,8 +459,8 @@ class Context:
         return dict(_struct_dict(st), status=status)
 
     def step(self, dt, delta, solver='mono', k_max=0, k_max_inner=0, j_max=0, tol_abs=0.0, tol_rel=0.0,
-             ssn_tol=0.0):
-        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol)
+             ssn_tol=0.0, printed_metric=False):
+        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol, int(printed_metric))
         st = StepStats()
         status = _check(lib().pqn_step(self.h, dt, delta, SOLVERS.get(solver, solver), C.byref(o), C.byref(st)))
         return dict(_struct_dict(st), status=status)
@@ -468,6 +470,14 @@ class Context:
         y = np.zeros_like(q)
         _check(lib().pqn_bie_apply(self.h, fidelity, _dptr(q), _dptr(y)))
         return y.reshape(3, -1)
+
+    def bie_apply_multi(self, q_soa, fidelity=PQN_HIFI):
+        """q_soa [k][3][N] -> y [k][3][N], the k densities in one pass."""
+        q = _f64(q_soa)
+        k = q.shape[0]
+        y = np.zeros_like(q)
+        _check(lib().pqn_bie_apply_multi(self.h, fidelity, k, _dptr(q), _dptr(y)))
+        return y
 
     def bie_solve(self, rhs_soa, fidelity=PQN_HIFI):
         r = _f64(rhs_soa).ravel()

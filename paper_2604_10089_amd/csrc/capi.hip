@@ -409,6 +409,31 @@ pqn_status pqn_bie_apply(pqn_ctx* ctx, int32_t fidelity, const double* q, double
   });
 }
 
+pqn_status pqn_bie_apply_multi(pqn_ctx* ctx, int32_t fidelity, int32_t k, const double* q, double* y) {
+  return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_bie_apply_multi");
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_bie_apply_multi needs a single-suspension context");
+    if (!ctx || !q || !y) return fail(PQN_ERR_INVALID, "pqn_bie_apply_multi: NULL argument");
+    if (k < 1 || k > kMaxRhs) return fail(PQN_ERR_INVALID, "pqn_bie_apply_multi: k must be 1..6");
+    HIPCHK(hipSetDevice(ctx->device));
+    Level& lv = ctx->level(fidelity);
+    const size_t len = 3 * (size_t)lv.N;
+    std::vector<MvGroup> groups;
+    for (int r = 0; r < k; ++r) {
+      SysBuf& b = lv.sb(r);
+      HIPCHK(hipMemcpyAsync(b.rhs.p, q + r * len, len * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+      add_to_groups(groups, ctx, &lv, r, b.rhs.p, b.tmp.p);
+    }
+    ctx->matvec_groups(groups, ctx->cfg.precision);
+    for (int r = 0; r < k; ++r)
+      HIPCHK(hipMemcpyAsync(y + r * len, lv.sb(r).tmp.p, len * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->end_far_timing();
+    return PQN_OK;
+  });
+}
+
 pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, double* q, pqn_mvp_stats* stats) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);

@@ -145,39 +145,37 @@ void pqn_ctx_impl::setup_level(Level& lv, int nt, int np, double tol) {
 }
 
 void pqn_ctx_impl::set_configuration(const double* c, const double* ax) {
-  centers.assign(c, c + 3 * (size_t)M);
-  for (double v : centers)
+  // Everything is derived into locals and validated first; the context's state
+  // changes only once no check can fail (a rejected configuration leaves it as it was).
+  std::vector<double> cn(c, c + 3 * (size_t)M);
+  for (double v : cn)
     if (!std::isfinite(v)) throw Error(PQN_ERR_NUMERIC, "non-finite centre coordinate");
   // ax may point into axes itself (re-setting the centres only): copy before overwriting
   std::vector<double> axn(3 * (size_t)M, 0.0);
   if (ax) std::copy(ax, ax + 3 * (size_t)M, axn.begin());
-  has_axes = ax != nullptr;
-  axes.swap(axn);
   // pair classes: 2 = same sphere, 1 = near (gap < near_gap), 0 = far
   std::vector<unsigned char> hc((size_t)M * M, 0);
-  h_partners.assign((size_t)M * kMaxNear, -1);
-  h_npart.assign(M, 0);
+  std::vector<int> hp((size_t)M * kMaxNear, -1), hn(M, 0);
   std::vector<char> h_close((size_t)M * kMaxNear, 0);
-  max_slots = 0;
+  int slots = 0;
   for (int i = 0; i < M; ++i) {
     for (int j = 0; j < M; ++j) {
       if (i == j) {
         hc[(size_t)i * M + j] = 2;
         continue;
       }
-      double dx = centers[3 * i] - centers[3 * j], dy = centers[3 * i + 1] - centers[3 * j + 1],
-             dz = centers[3 * i + 2] - centers[3 * j + 2];
+      double dx = cn[3 * i] - cn[3 * j], dy = cn[3 * i + 1] - cn[3 * j + 1], dz = cn[3 * i + 2] - cn[3 * j + 2];
       double gap = std::sqrt(dx * dx + dy * dy + dz * dz) - 2.0 * a;
       if (gap < cfg.near_gap) {
         hc[(size_t)i * M + j] = 1;
-        int& k = h_npart[i];
+        int& k = hn[i];
         if (k >= kMaxNear) throw Error(PQN_ERR_INVALID, "more than 16 near neighbours of one sphere");
-        h_partners[(size_t)i * kMaxNear + k] = j;
+        hp[(size_t)i * kMaxNear + k] = j;
         h_close[(size_t)i * kMaxNear + k] = gap < cfg.near_close_gap;
         ++k;
       }
     }
-    max_slots = std::max(max_slots, h_npart[i]);
+    slots = std::max(slots, hn[i]);
   }
   // ordered near pairs (target sphere, source sphere, partner slot), grouped by
   // source sphere so that launches reading the same source data run together
@@ -186,7 +184,7 @@ void pqn_ctx_impl::set_configuration(const double* c, const double* ax) {
   {
     std::vector<std::array<int, 3>> pr;
     for (int i = 0; i < M; ++i)
-      for (int s = 0; s < h_npart[i]; ++s) pr.push_back({h_partners[(size_t)i * kMaxNear + s], i, s});
+      for (int s = 0; s < hn[i]; ++s) pr.push_back({hp[(size_t)i * kMaxNear + s], i, s});
     std::sort(pr.begin(), pr.end());
     for (const auto& e : pr) {
       std::vector<int>& l = h_close[(size_t)e[1] * kMaxNear + e[2]] ? nl2 : nl;
@@ -195,6 +193,12 @@ void pqn_ctx_impl::set_configuration(const double* c, const double* ax) {
       l.push_back(e[2]);
     }
   }
+  centers.swap(cn);
+  has_axes = ax != nullptr;
+  axes.swap(axn);
+  h_partners.swap(hp);
+  h_npart.swap(hn);
+  max_slots = slots;
   n_near = (int)nl.size() / 3;
   n_near2 = (int)nl2.size() / 3;
   ctr.upload(centers.data(), centers.size(), stream);

@@ -259,14 +259,17 @@ __global__ __launch_bounds__(kT) void k_DT_gather(const double* __restrict__ ctr
 
 // ------------------------------------------------------------ PQN engine
 
-// Reset an engine: memory cleared; x, Ax either zero or kept (warm start).
-__global__ __launch_bounds__(kT) void k_pqn_init(PqnDev d, int keep_x, double tol_abs, double tol_rel) {
+// Reset an engine: memory cleared; x, Ax either zero or kept (warm start);
+// sigma0 = initial metric scale (0 = set by the first step).
+__global__ __launch_bounds__(kT) void k_pqn_init(PqnDev d, int keep_x, double tol_abs, double tol_rel,
+                                                 double sigma0) {
   for (int e = threadIdx.x; e < d.n; e += kT)
     if (!keep_x) d.x[e] = d.Ax[e] = 0.0;
   if (threadIdx.x == 0) {
     PqnScal z{};
     z.tol_abs = tol_abs;
     z.tol_rel = tol_rel;
+    z.sigma = sigma0;
     *d.sc = z;
   }
 }
@@ -997,7 +1000,7 @@ static bool run_mono(pqn_ctx_impl& ctx, Engine& E, int k_max, const pqn_lcp_opts
 }
 
 static pqn_lcp_opts opts_or_default(const pqn_lcp_opts* o) {
-  pqn_lcp_opts r{100, 50, 50, 1e-8, 1e-8, 1e-14};
+  pqn_lcp_opts r{100, 50, 50, 1e-8, 1e-8, 1e-14, 0};
   if (o) {
     if (o->k_max > 0) r.k_max = o->k_max;
     if (o->k_max_inner > 0) r.k_max_inner = o->k_max_inner;
@@ -1005,6 +1008,8 @@ static pqn_lcp_opts opts_or_default(const pqn_lcp_opts* o) {
     if (o->kkt_tol_abs > 0) r.kkt_tol_abs = o->kkt_tol_abs;
     if (o->kkt_tol_rel > 0) r.kkt_tol_rel = o->kkt_tol_rel;
     if (o->ssn_tol > 0) r.ssn_tol = o->ssn_tol;
+    if (o->printed_metric < 0 || o->printed_metric > 1) throw Error(PQN_ERR_INVALID, "printed_metric must be 0 or 1");
+    r.printed_metric = o->printed_metric;
   }
   return r;
 }
@@ -1065,6 +1070,9 @@ struct BiSolver {
     HIPCHK(hipStreamSynchronize(ctx.stream));
   }
 
+  // initial metric scale of a Mono-PQN solve: 1 = H0 = I as printed, 0 = set by its first step
+  double sigma0() const { return o.printed_metric ? 1.0 : 0.0; }
+
   void init_scal(Engine& E, double tol_abs, double sigma) {
     PqnScal z{};
     z.tol_abs = tol_abs;
@@ -1109,7 +1117,7 @@ struct BiSolver {
     const bool top = d == 0;
     if (top) rejected = true;
     hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, E.d, keep_x || restart ? 1 : 0, tol,
-                       o.kkt_tol_rel);
+                       o.kkt_tol_rel, sigma0());
     double* md = top ? MDx : nullptr;
     if (restart)
       op(d, E.d.x, E.d.Ax, md);  // md (if any) receives M D x^(-1)
@@ -1153,7 +1161,7 @@ struct BiSolver {
         op(1, I.d.x, I.d.Ax, nullptr);  // no correction yet: A_1 x^(-1)
         hipLaunchKernelGGL(k_kkt, dim3(1), dim3(kT), 0, ctx.stream, I.d.x, I.d.Ax, I.d.b, n, E.d.sc);
       } else {
-        hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, I.d, 0, 0.0, 0.0);
+        hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, I.d, 0, 0.0, 0.0, sigma0());
         hipLaunchKernelGGL(k_kkt_zero, dim3(1), dim3(kT), 0, ctx.stream, E.d.b, n, E.d.sc);
       }
       const double e0 = read_scal(ctx, E.d.sc).e;
@@ -1252,7 +1260,7 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
   int ssn = 0;
   double kkt = 0.0;
   hipLaunchKernelGGL(k_pqn_init, dim3(1), dim3(kT), 0, ctx.stream, st.outer.d, x0 ? 1 : 0, o.kkt_tol_abs,
-                     o.kkt_tol_rel);
+                     o.kkt_tol_rel, o.printed_metric ? 1.0 : 0.0);
   // Mono-PQN and BB-PGD from x^(-1): A x^(-1) (and M D x^(-1)) by one product
   if (x0 && solver != PQN_BI && solver != PQN_BI_REC) mvp_hi(st.outer.d.x, st.outer.d.Ax, MDx);
   if (solver == PQN_MONO) {
@@ -1285,7 +1293,7 @@ static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opt
     const bool rec = solver == PQN_BI_REC;
     BiSolver bs{ctx, st, o, cnt, n, M, rec ? 3 : 2, MDx, x0, {&ctx.hi, &ctx.lo, rec ? &ctx.lo2 : nullptr},
                 {&st.outer, rec ? &st.mid : &st.inner, rec ? &st.inner : nullptr}, {&st.bi, &st.bi2}};
-    double sigma = 0.0;  // metric scale of the Mono-PQN solves (0 = set by their first step)
+    double sigma = bs.sigma0();  // metric scale of the Mono-PQN solves (0 = set by their first step)
     BiSolver::Result r = bs.bi_level(0, o.kkt_tol_abs, o.k_max, sigma);
     conv = r.conv;
     kkt = r.kkt;
@@ -1438,7 +1446,18 @@ pqn_status lcp_step(pqn_ctx_impl& ctx, double dt, double delta, int solver, cons
   HIPCHK(hipMemcpyAsync(ax.data(), ctx.dax.p, ax.size() * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
   HIPCHK(hipStreamSynchronize(ctx.stream));
   ctx.end_far_timing();
-  ctx.set_configuration(c.data(), ctx.has_axes ? ax.data() : nullptr);
+  try {
+    ctx.set_configuration(c.data(), ctx.has_axes ? ax.data() : nullptr);
+  } catch (...) {
+    // the new configuration was rejected (e.g. a sphere with more near partners than
+    // the near tables hold): the context keeps the old one, device copies included
+    HIPCHK(hipMemcpyAsync(ctx.ctr.p, ctx.centers.data(), ctx.centers.size() * sizeof(double),
+                          hipMemcpyHostToDevice, ctx.stream));
+    HIPCHK(hipMemcpyAsync(ctx.dax.p, ctx.axes.data(), ctx.axes.size() * sizeof(double), hipMemcpyHostToDevice,
+                          ctx.stream));
+    HIPCHK(hipStreamSynchronize(ctx.stream));
+    throw;
+  }
   ss.t_total_ms = tm.ms();
   if (stats) *stats = ss;
   return conv ? PQN_OK : PQN_WARN_NOT_CONVERGED;

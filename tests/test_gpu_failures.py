@@ -139,3 +139,38 @@ def test_documented_limits_are_rejected_at_create():
         with pytest.raises(binding.PqnError) as e:
             binding.Context(one, None, **kw)
         assert e.value.status == PQN_ERR_INVALID, kw
+
+
+def _shell(n, seed=0, iters=3000):
+    """n unit vectors spread by point repulsion (deterministic)."""
+    rng = np.random.default_rng(seed)
+    p = rng.standard_normal((n, 3))
+    p /= np.linalg.norm(p, axis=1, keepdims=True)
+    for _ in range(iters):
+        d = p[:, None] - p[None]
+        r = np.linalg.norm(d, axis=2) + np.eye(n)
+        p += 0.01 * (d / r[..., None] ** 4).sum(1)
+        p /= np.linalg.norm(p, axis=1, keepdims=True)
+    return p
+
+
+def test_rejected_configuration_leaves_the_context_unchanged():
+    """A configuration the context cannot hold (a sphere with 17 near partners) is rejected
+    with PQN_ERR_INVALID, and the context keeps the previous configuration whole: state,
+    pair classes and near lists (the next product equals the one before)."""
+    shell = _shell(17)
+    inner = np.vstack([np.zeros(3), 2.45 * shell])            # 17 partners at gap 0.45 < 0.5
+    d = np.linalg.norm(inner[:, None] - inner[None], axis=2) + np.eye(18) * 9
+    assert d.min() > 2.0                                       # no overlaps (checked on the host)
+    ok = np.vstack([np.zeros(3), 2.45 * shell[:16], 2.9 * shell[16:]])   # the 17th outside the near gap
+    axes = inputs.janus_axes(3, 18)
+    FT = inputs.random_forces(4, 18)
+    with binding.Context(ok, axes, 6, 12, gmres_tol=1e-12) as ctx:
+        U0, _ = ctx.mobility_apply(FT)
+        with pytest.raises(binding.PqnError) as e:
+            ctx.set_state(inner, axes)
+        assert e.value.status == -1
+        c1, a1 = ctx.get_state()
+        assert np.array_equal(c1, ok) and np.array_equal(a1, axes)
+        U1, _ = ctx.mobility_apply(FT)
+    assert np.array_equal(U0, U1)

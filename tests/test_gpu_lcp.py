@@ -348,3 +348,33 @@ def test_step_with_close_pairs_matches_oracle():
     assert st['n_active'] == int((info['x'] > 0).sum()) and st['n_active'] > 0
     assert np.abs(c2 - c1).max() < 1e-10
     assert np.abs(ax2 - ax1).max() < 1e-10
+
+
+@pytest.mark.parametrize("solver", ["mono", "bi"])
+def test_printed_metric_matches_oracle(cases, solver):
+    """Alg. 1 as printed (H^(0) = I throughout, printed_metric = 1): the device solvers
+    reach the brute-force solution and need the oracle's product counts in that mode."""
+    for cs in cases:
+        b = cs['b_pl']
+        Aop = lcp.lcp_operator(lambda F, cs=cs: bie.mobility_apply(cs['g'], F, dense=cs['A']), cs['c'], cs['pairs'])
+        Alo = lcp.lcp_operator(lambda F, cs=cs: bie.mobility_apply(cs['glo'], F, dense=cs['Alo']), cs['c'],
+                               cs['pairs'])
+        kw = dict(tol_abs=1e-12, tol_rel=1e-15)
+        if solver == 'mono':
+            _, _, so = lcp.mono_pqn(Aop, b, k_max=300, printed_metric=True, **kw)
+            hi_o, lo_o = so['mvp'], 0
+        else:
+            _, _, so = lcp.bi_pqn(Aop, Alo, b, k_max=100, printed_metric=True, **kw)
+            hi_o, lo_o = so['mvp_hi'], so['mvp_lo']
+        xbf = lcp.brute_force_lcp(cs['Ad'], b)
+        with binding.Context(cs['c'], None, 8, 16, lo=(4, 8), gmres_tol=1e-13) as ctx:
+            x, st = ctx.lcp_solve(cs['pairs'], b, solver, k_max=300, printed_metric=True, **kw)
+            _, st_s = ctx.lcp_solve(cs['pairs'], b, solver, k_max=300, **kw)
+        say('printed metric', solver, 'device', st['mvp_hi'], st['mvp_lo'], 'oracle', hi_o, lo_o,
+            'scaled metric', st_s['mvp_hi'], st_s['mvp_lo'])
+        assert st['converged'] == 1
+        assert np.abs(x - xbf).max() <= 1e-10 * np.abs(xbf).max()
+        assert abs(st['mvp_hi'] - hi_o) <= 1
+        assert abs(st['mvp_lo'] - lo_o) <= 2
+    with binding.Context(cases[0]['c'], None, 8, 16) as ctx, pytest.raises(binding.PqnError):
+        ctx.lcp_solve(cases[0]['pairs'], cases[0]['b_pl'], 'mono', printed_metric=2)

@@ -342,3 +342,64 @@ def test_solvers_from_an_initial_guess(tiny_lcps3):
         x1, _, s1 = lcp.bi_pqn(c['Aop'], c['Alo'], b, x0=g, **kw)
         x2, _, s2 = lcp.bi_pqn_rec([c['Aop'], c['Alo']], b, x0=g, **kw)
         assert s1['hist'] == s2['hist'] and (s1['mvp_hi'], s1['mvp_lo']) == tuple(s2['mvp'])
+
+
+@pytest.mark.parametrize("solver", ["mono", "bi", "birec"])
+def test_printed_metric_matches_brute_force(tiny_lcps, solver):
+    """Alg. 1 as printed (H^(0) = I at every start, no metric scale): the solvers still
+    reach the brute-force solution, and the metric scale stays 1."""
+    for c in tiny_lcps:
+        b = c['b_pl']
+        xbf = lcp.brute_force_lcp(c['Ad'], b)
+        kw = dict(tol_abs=1e-12, tol_rel=1e-15, printed_metric=True)
+        if solver == 'mono':
+            x, _, st = lcp.mono_pqn(c['Aop'], b, k_max=300, **kw)
+            assert st['sigma'] == 1.0
+        elif solver == 'bi':
+            x, _, st = lcp.bi_pqn(c['Aop'], c['Alo'], b, k_max=100, **kw)
+        else:
+            x, _, st = lcp.bi_pqn_rec([c['Aop'], c['Alo'], c['Alo']], b, k_max=100, **kw)
+        assert st['converged']
+        assert np.abs(x - xbf).max() <= 1e-10 * np.abs(xbf).max()
+        _check_complementarity(x, c['Ad'], b)
+
+
+def test_metric_scale_invariance():
+    """The reading's metric (B0 = sigma I, sigma from the first step's curvature) makes
+    Mono-PQN's iterates invariant to the units of A: under (A, b) -> (c A, c b) the
+    solution is unchanged, H scales by 1/c and the gradient by c, so every search
+    direction p (the vectors A is applied to) is the same for any c. Alg. 1 as printed
+    (H^(0) = I) is not: from the second step on its BFGS matrix mixes I with c A. (The
+    first direction is the projected gradient step in both forms, c times longer for c A;
+    directions are compared after normalisation.)"""
+    A = _spd(30, 7, kappa=20.0)
+    xs, ws = inputs.planted_lcp(2, 30)
+    b = ws - A @ xs
+    dirs = {}
+    for printed in (False, True):
+        for c in (1.0, 1e-2, 1e2):
+            seen = []
+
+            def Aop(v, c=c, seen=seen):
+                seen.append(np.array(v))
+                return c * (A @ v)
+            x, _, st = lcp.mono_pqn(Aop, c * b, tol_abs=1e-12 * c, tol_rel=1e-15, k_max=60,
+                                    printed_metric=printed)
+            if not printed:
+                assert st['converged'] and np.abs(x - xs).max() < 1e-9
+                assert np.isclose(st['sigma'], c * dirs.get((False, 1.0), (None, st['sigma'] / c))[1], rtol=1e-10)
+            else:
+                assert st['sigma'] == 1.0
+            dirs[(printed, c)] = (seen, st['sigma'] / c)
+    for printed in (False, True):
+        ref = dirs[(printed, 1.0)][0]
+        for c in (1e-2, 1e2):
+            other = dirs[(printed, c)][0]
+            k = min(len(ref), len(other), 8)
+            unit = lambda v: v / np.linalg.norm(v)
+            same = [np.abs(unit(ref[i]) - unit(other[i])).max() < 1e-9 for i in range(k)]
+            assert same[0]                      # the first step uses H = I in both forms
+            if printed:
+                assert not all(same)
+            else:
+                assert all(same)
