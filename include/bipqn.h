@@ -144,6 +144,12 @@ typedef struct {
                                subproblems): 0 = H0 = I for the first step, then B0 = sigma I with
                                sigma = p.Ap/p.p of that step (invariant to the units of A) [0];
                                1 = H0 = I throughout, Alg. 1 as printed */
+  int32_t recycle;          /* 1 = every mobility solve of an LCP product starts GMRES from the best
+                               combination of the earlier products' solutions of the same call (per
+                               fidelity, at most 32 kept; the Krylov reuse Sec. 7 names as future
+                               work): x0 = Q (W^T r) with W = A Q orthonormal, so the initial
+                               residual costs no operator application. Same stopping rule as a cold
+                               solve. Ignored in mixed precision with refine_sweeps > 0 [0] */
 } pqn_lcp_opts;
 
 typedef struct {

@@ -423,14 +423,15 @@ def operator_apply(geom, q):
 
 # ------------------------------------------------------------------- GMRES
 
-def gmres(apply, rhs, tol=1e-13, restart=50, maxiter=1000):
+def gmres(apply, rhs, tol=1e-13, restart=50, maxiter=1000, x0=None):
     """Restarted GMRES (modified Gram-Schmidt Arnoldi, Givens rotations).
 
-    Textbook GMRES(m): stops when the residual norm falls below tol * ||rhs||.
+    Textbook GMRES(m) from the initial guess x0 (default 0): stops when the
+    residual norm falls below tol * ||rhs||.
     Returns (x, iterations, final relative residual estimate).
     """
     b = rhs.ravel().astype(np.float64)
-    x = np.zeros_like(b)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64).ravel()
     bnorm = np.linalg.norm(b)
     if bnorm == 0.0:
         return x, 0, 0.0
@@ -506,3 +507,48 @@ def nc_velocity(geom, axes, speed, dense=None, tol=1e-13):
     rhs = janus_slip(geom, axes, speed)
     q = solve_density(geom, rhs, dense, tol)
     return rigid_velocity(geom, q)
+
+
+class RecyclingMobility:
+    """U = M F with every GMRES solve started from the earlier solutions (Sec. 7
+    names the reuse of Krylov information across the MVPs of one solve as future
+    work; this is its simplest form).
+
+    The densities q_k of the earlier solves and their operator images
+    w_k = A q_k are kept (at most `keep`, oldest dropped). A new right-hand side
+    r starts GMRES from x0 = sum_k c_k q_k with c = argmin |r - sum_k c_k w_k|_2,
+    whose residual r - A x0 = r - W c is never larger than |r|. The stopping rule
+    is the cold solve's (|residual| <= tol |r|), so the result equals the cold
+    solution to the GMRES tolerance. A product whose force lies in the span of
+    earlier forces has a right-hand side in the span of earlier right-hand sides,
+    so its initial residual is zero up to the earlier solves' tolerance.
+    Here w_k is evaluated by one more operator application (plain, not fast);
+    `iters` records the GMRES iterations of each call.
+    """
+
+    def __init__(self, geom, tol=1e-13, keep=32, restart=50):
+        self.geom, self.tol, self.keep, self.restart = geom, tol, keep, restart
+        self.Q, self.W, self.iters, self.r0 = [], [], [], []
+
+    def _apply(self, v):
+        return operator_apply(self.geom, v.reshape(-1, 3)).ravel()
+
+    def __call__(self, FT):
+        rhs = -completion(self.geom, FT).ravel()
+        x0 = None
+        if self.Q:
+            W = np.stack(self.W, axis=1)
+            c = np.linalg.lstsq(W, rhs, rcond=None)[0]
+            x0 = np.stack(self.Q, axis=1) @ c
+            self.r0.append(np.linalg.norm(rhs - W @ c) / max(np.linalg.norm(rhs), 1e-300))
+        else:
+            self.r0.append(1.0)
+        q, its, _ = gmres(lambda v: self._apply(v), rhs, tol=self.tol, restart=self.restart, x0=x0)
+        self.iters.append(its)
+        if np.linalg.norm(rhs) > 0.0:
+            self.Q.append(q.copy())
+            self.W.append(self._apply(q))
+            if len(self.Q) > self.keep:
+                self.Q.pop(0)
+                self.W.pop(0)
+        return rigid_velocity(self.geom, q.reshape(-1, 3))

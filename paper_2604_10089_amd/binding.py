@@ -81,7 +81,7 @@ class MvpStats(C.Structure):
 class LcpOpts(C.Structure):
     _fields_ = [('k_max', C.c_int32), ('k_max_inner', C.c_int32), ('j_max', C.c_int32),
                 ('kkt_tol_abs', C.c_double), ('kkt_tol_rel', C.c_double), ('ssn_tol', C.c_double),
-                ('printed_metric', C.c_int32)]
+                ('printed_metric', C.c_int32), ('recycle', C.c_int32)]
 
 
 class LcpStats(C.Structure):
@@ -438,20 +438,20 @@ class Context:
         return Ax
 
     def lcp_solve(self, pairs, b, solver='mono', k_max=0, k_max_inner=0, j_max=0, tol_abs=0.0, tol_rel=0.0,
-                  x0=None, ssn_tol=0.0, printed_metric=False):
+                  x0=None, ssn_tol=0.0, printed_metric=False, recycle=False):
         pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
         b = _f64(b)
         x = np.zeros(pairs.shape[0]) if x0 is None else _f64(x0, (pairs.shape[0],)).copy()
-        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol, int(printed_metric))
+        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol, int(printed_metric), int(recycle))
         st = LcpStats()
         status = _check(lib().pqn_lcp_solve(self.h, pairs.shape[0], pairs.ctypes.data_as(_I), _dptr(b), _dptr(x),
                                             SOLVERS.get(solver, solver), C.byref(o), C.byref(st)))
         return x, dict(_struct_dict(st), status=status)
 
     def lcp_solve_dev(self, n, pairs_ptr, b_ptr, x_ptr, solver='mono', k_max=0, k_max_inner=0, j_max=0,
-                      tol_abs=0.0, tol_rel=0.0, ssn_tol=0.0, printed_metric=False):
+                      tol_abs=0.0, tol_rel=0.0, ssn_tol=0.0, printed_metric=False, recycle=False):
         """pqn_lcp_solve_dev on device pointers (ints, e.g. torch tensors' data_ptr())."""
-        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol, int(printed_metric))
+        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol, int(printed_metric), int(recycle))
         st = LcpStats()
         status = _check(lib().pqn_lcp_solve_dev(self.h, n, C.c_void_p(pairs_ptr), C.c_void_p(b_ptr),
                                                 C.c_void_p(x_ptr), SOLVERS.get(solver, solver), C.byref(o),
@@ -459,8 +459,8 @@ class Context:
         return dict(_struct_dict(st), status=status)
 
     def step(self, dt, delta, solver='mono', k_max=0, k_max_inner=0, j_max=0, tol_abs=0.0, tol_rel=0.0,
-             ssn_tol=0.0, printed_metric=False):
-        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol, int(printed_metric))
+             ssn_tol=0.0, printed_metric=False, recycle=False):
+        o = LcpOpts(k_max, k_max_inner, j_max, tol_abs, tol_rel, ssn_tol, int(printed_metric), int(recycle))
         st = StepStats()
         status = _check(lib().pqn_step(self.h, dt, delta, SOLVERS.get(solver, solver), C.byref(o), C.byref(st)))
         return dict(_struct_dict(st), status=status)

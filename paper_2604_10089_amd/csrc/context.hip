@@ -79,6 +79,7 @@ SysBuf& Level::sb(int k) {
     b.d.alloc(len);
     b.partial.alloc((size_t)std::max(nb_dots, kMultiDotBlocks) * (restart + 1));
     b.ycoef.alloc((size_t)restart + 1);
+    b.rcoef.alloc((size_t)restart + 2);
   }
   return b;
 }
@@ -746,7 +747,11 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
     g.active = true;
     g.restart = false;
   };
-  std::vector<int> warm;
+  // the final residual vector of a system that ends with its residual in v (res_out)
+  auto residual_out = [&](int i, const double* v) {
+    if (sys[i].res_out) launch_scale_copy(s, sys[i].res_out, v, 1.0, len_of(i));
+  };
+  std::vector<int> warm, given;  // initial guesses whose residual needs a product / is given
   for (int i = 0; i < ns; ++i) {
     const double bn = std::sqrt(std::max(0.0, hhost[(size_t)i * hs + 2 * (m + 1)]));
     if (!std::isfinite(bn)) throw Error(PQN_ERR_NUMERIC, "non-finite right-hand side");
@@ -757,13 +762,21 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
     if (bn > 0.0 && sys[i].x0) {
       launch_scale_copy(s, sys[i].x, sys[i].x0, 1.0, len_of(i));  // x = x0, residual below
       sys[i].conv = false;
-      warm.push_back(i);
+      if (sys[i].r0) {
+        SysBuf& b = sys[i].lv->sb(sys[i].slot);
+        launch_scale_copy(s, b.r.p, sys[i].r0, 1.0, len_of(i));
+        given.push_back(i);
+      } else {
+        warm.push_back(i);
+      }
       continue;
     }
     launch_scale_copy(s, sys[i].x, sys[i].rhs, 0.0, len_of(i));  // x = 0 (rhs finite)
     if (bn > 0.0) {
       sys[i].conv = false;
       start_cycle(i, sys[i].rhs, bn);
+    } else {
+      residual_out(i, sys[i].rhs);  // zero
     }
   }
   auto build_groups = [&](const std::vector<int>& idx, bool use_x) {
@@ -776,13 +789,19 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
     }
     return groups;
   };
-  if (!warm.empty()) {
-    // initial residual r0 = rhs - A x0 of the warm-started systems
-    std::vector<MvGroup> wg = build_groups(warm, true);
-    matvec_groups(wg, precision);
+  if (!warm.empty() || !given.empty()) {
+    // initial residual r0 = rhs - A x0 of the warm-started systems (given, or by one product)
+    if (!warm.empty()) {
+      std::vector<MvGroup> wg = build_groups(warm, true);
+      matvec_groups(wg, precision);
+      for (int i : warm) {
+        SysBuf& b = sys[i].lv->sb(sys[i].slot);
+        launch_axpby(s, b.r.p, sys[i].rhs, 1.0, -1.0, len_of(i));
+      }
+    }
+    warm.insert(warm.end(), given.begin(), given.end());
     for (int i : warm) {
       SysBuf& b = sys[i].lv->sb(sys[i].slot);
-      launch_axpby(s, b.r.p, sys[i].rhs, 1.0, -1.0, len_of(i));
       launch_dots(s, b.r.p, len_of(i), 1, b.r.p, len_of(i), sys[i].lv->nb_dots, b.partial.p, nrm_slot(i));
     }
     readback();
@@ -793,6 +812,7 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
       sys[i].relres = beta / st[i].bnorm;
       if (beta <= sys[i].tol * st[i].bnorm) {
         sys[i].conv = true;
+        residual_out(i, b.r.p);
       } else {
         start_cycle(i, b.r.p, beta);
       }
@@ -911,6 +931,21 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
       HIPCHK(hipMemcpyAsync(b.ycoef.p, y.data(), dk * sizeof(double), hipMemcpyHostToDevice, s));
       launch_combo(s, sr.x, 1.0, b.V.p, len, dk, b.ycoef.p, 1.0, len);
       g.active = false;
+      const bool final_cycle = conv || sr.its >= sr.lv->max_iter;
+      if (final_cycle && sr.res_out) {
+        // final residual from the Arnoldi relation: r = V_{k+2} (beta e1 - Hbar y) =
+        // V_{k+2} G_0^T ... G_k^T (0, ..., 0, g_{k+1}); V[k+1] still holds w unnormalised
+        std::vector<double> e(dk + 1, 0.0);
+        e[dk] = g.g[dk];
+        for (int r = dk - 1; r >= 0; --r) {
+          const double a0 = e[r], a1 = e[r + 1];
+          e[r] = g.cs[r] * a0 - g.sn[r] * a1;
+          e[r + 1] = g.sn[r] * a0 + g.cs[r] * a1;
+        }
+        e[dk] = hn > 0.0 ? e[dk] / hn : 0.0;
+        HIPCHK(hipMemcpyAsync(b.rcoef.p, e.data(), (dk + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_combo(s, sr.res_out, 0.0, b.V.p, len, dk + 1, b.rcoef.p, 1.0, len);
+      }
       if (conv) {
         sr.conv = true;
       } else if (sr.its >= sr.lv->max_iter) {
@@ -944,6 +979,7 @@ void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
         sys[i].relres = beta / st[i].bnorm;
         if (beta <= sys[i].tol * st[i].bnorm) {
           sys[i].conv = true;
+          residual_out(i, b.r.p);
         } else {
           start_cycle(i, b.r.p, beta);
         }
@@ -1022,6 +1058,67 @@ void pqn_ctx_impl::solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st) {
   }
 }
 
+// x0 = Q c and r0 = rhs - W c with c = W^T rhs (W orthonormal: the minimal residual over
+// span(W), no operator application); the final residual goes to sb(0).tmp.
+void pqn_ctx_impl::recycle_start(Level& lv, SysRef& sr) {
+  Recycle& rc = lv.rc;
+  const long len = 3L * lv.N;
+  if (!rc.Q.p) {
+    rc.kmax = std::min(32, lv.restart + 1);  // (dot partials hold restart + 1 vectors)
+    rc.Q.alloc((size_t)rc.kmax * len);
+    rc.W.alloc((size_t)rc.kmax * len);
+    rc.c.alloc((size_t)rc.kmax);
+    rc.nrm.alloc(2);
+  }
+  if (rc.epoch != config_epoch) {
+    rc.k = 0;
+    rc.epoch = config_epoch;
+  }
+  SysBuf& b = lv.sb(sr.slot);
+  if (rc.k > 0) {
+    launch_dots(stream, rc.W.p, len, rc.k, sr.rhs, len, lv.nb_dots, b.partial.p, rc.c.p);
+    launch_combo(stream, b.d.p, 0.0, rc.Q.p, len, rc.k, rc.c.p, 1.0, len);
+    launch_scale_copy(stream, b.tmp.p, sr.rhs, 1.0, len);
+    launch_combo(stream, b.tmp.p, 1.0, rc.W.p, len, rc.k, rc.c.p, -1.0, len);
+    sr.x0 = b.d.p;
+    sr.r0 = b.tmp.p;
+  }
+  sr.res_out = b.tmp.p;
+}
+
+// Append the solution x (sb(0).x) and its image w = rhs - res to the store: both are
+// projected against the stored pairs (two passes) and scaled so that the new w has unit
+// norm (A q_new = w_new by linearity). An image within 1e-6 of the stored span adds
+// nothing and is dropped; so is any once the store is full.
+void pqn_ctx_impl::recycle_add(Level& lv, const double* res) {
+  Recycle& rc = lv.rc;
+  if (rc.k >= rc.kmax) return;
+  const long len = 3L * lv.N;
+  SysBuf& b = lv.sb(0);
+  double* qn = rc.Q.p + (size_t)rc.k * len;
+  double* wn = rc.W.p + (size_t)rc.k * len;
+  launch_scale_copy(stream, qn, b.x.p, 1.0, len);
+  launch_scale_copy(stream, wn, b.rhs.p, 1.0, len);
+  launch_axpby(stream, wn, res, -1.0, 1.0, len);  // w = rhs - res
+  launch_dots(stream, wn, len, 1, wn, len, lv.nb_dots, b.partial.p, rc.nrm.p);
+  for (int pass = 0; pass < 2 && rc.k > 0; ++pass) {
+    launch_dots(stream, rc.W.p, len, rc.k, wn, len, lv.nb_dots, b.partial.p, rc.c.p);
+    launch_combo(stream, wn, 1.0, rc.W.p, len, rc.k, rc.c.p, -1.0, len);
+    launch_combo(stream, qn, 1.0, rc.Q.p, len, rc.k, rc.c.p, -1.0, len);
+  }
+  launch_dots(stream, wn, len, 1, wn, len, lv.nb_dots, b.partial.p, rc.nrm.p + 1);
+  double h[2] = {0.0, 0.0};
+  HIPCHK(hipMemcpyAsync(h, rc.nrm.p, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (!(std::isfinite(h[0]) && std::isfinite(h[1]))) throw Error(PQN_ERR_NUMERIC, "non-finite recycled image");
+  if (h[1] > 1e-12 * h[0] && h[1] > 0.0) {
+    const double sc = 1.0 / std::sqrt(h[1]);
+    launch_scale_copy(stream, qn, qn, sc, len);
+    launch_scale_copy(stream, wn, wn, sc, len);
+    ++rc.k;
+  }
+}
+
 void pqn_ctx_impl::mobility_multi(Level& lv, int K, const double* const* FT_dev, const double* axes_dev,
                                   double* const* UO_dev, pqn_mvp_stats* st) {
   if (K < 1 || K > kMaxRhs) throw Error(PQN_ERR_INVALID, "between 1 and 6 force sets per call");
@@ -1035,7 +1132,11 @@ void pqn_ctx_impl::mobility_multi(Level& lv, int K, const double* const* FT_dev,
   // slip-driven solve: the previous one's density is a close initial guess after a small step
   const bool slip_only = K == 1 && (!FT_dev || !FT_dev[0]) && axes_dev;
   if (slip_only && cfg.warm_start && lv.has_q_nc) sys[0].x0 = lv.q_nc.p;
+  // force-driven solve inside an LCP solve that reuses earlier solutions
+  const bool recycle = K == 1 && FT_dev && FT_dev[0] && lv.rc.active;
+  if (recycle) recycle_start(lv, sys[0]);
   solve_lockstep(sys, st);
+  if (recycle) recycle_add(lv, sys[0].res_out);
   if (slip_only && cfg.warm_start) {
     lv.q_nc.alloc(3 * (size_t)lv.N);
     HIPCHK(hipMemcpyAsync(lv.q_nc.p, lv.sb(0).x.p, 3 * (size_t)lv.N * sizeof(double), hipMemcpyDeviceToDevice,

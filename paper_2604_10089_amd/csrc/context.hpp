@@ -121,7 +121,22 @@ struct Work {
 
 // Krylov storage of one linear system on one level.
 struct SysBuf {
-  DevArray<double> V, x, r, rhs, tmp, d, partial, ycoef;
+  DevArray<double> V, x, r, rhs, tmp, d, partial, ycoef, rcoef;
+};
+
+// Reuse of earlier solutions across the mobility products of one LCP solve (the
+// Krylov reuse Sec. 7 names as future work): densities Q of earlier solves and
+// their operator images W = A Q, kept with W orthonormal. A new right-hand side r
+// starts GMRES from x0 = Q (W^T r), whose residual r - W (W^T r) is known without
+// an operator application. Active only inside pqn_lcp_solve / pqn_step calls that
+// ask for it.
+struct Recycle {
+  DevArray<double> Q, W;  // [kmax][3N] each
+  DevArray<double> c;     // coefficients W^T r [kmax]
+  DevArray<double> nrm;   // squared norms of a new image before / after projection
+  int k = 0, kmax = 0;
+  bool active = false;
+  unsigned long epoch = 0;  // configuration the stored pairs belong to
 };
 
 // Offsets and sizes of the segmented GEMM descriptor tables of one iteration.
@@ -166,6 +181,7 @@ struct Level {
   std::vector<std::unique_ptr<GraphCache>> graphs;
   DevArray<double> q_nc;  // density of the last slip-driven solve (warm start of the next one)
   bool has_q_nc = false;
+  Recycle rc;
   Work& wk(int k);
   SysBuf& sb(int k);
 };
@@ -204,6 +220,8 @@ struct SysRef {
   double relres = 0.0;
   bool conv = false;
   const double* x0 = nullptr;  // initial guess (device, [3][N]); nullptr = start from 0
+  const double* r0 = nullptr;  // its residual rhs - A x0 when known (no operator application then)
+  double* res_out = nullptr;   // receives the final residual vector rhs - A x (from the Arnoldi relation)
 };
 
 struct pqn_ctx_impl {
@@ -289,6 +307,10 @@ struct pqn_ctx_impl {
   // mobility products of K force sets on one level (K <= kMaxRhs)
   void mobility_multi(Level& lv, int K, const double* const* FT_dev, const double* axes_dev,
                       double* const* UO_dev, pqn_mvp_stats* st);
+  // Recycle: warm start of a single force-driven solve from the stored pairs, and the
+  // addition of its solution (rhs in sb(0).rhs, solution in sb(0).x, final residual in res)
+  void recycle_start(Level& lv, SysRef& sr);
+  void recycle_add(Level& lv, const double* res);
   void mobility(Level& lv, const double* FT_dev, const double* axes_dev, double* UO_dev, pqn_mvp_stats* st) {
     mobility_multi(lv, 1, &FT_dev, axes_dev, &UO_dev, st);
   }

@@ -1000,7 +1000,7 @@ static bool run_mono(pqn_ctx_impl& ctx, Engine& E, int k_max, const pqn_lcp_opts
 }
 
 static pqn_lcp_opts opts_or_default(const pqn_lcp_opts* o) {
-  pqn_lcp_opts r{100, 50, 50, 1e-8, 1e-8, 1e-14, 0};
+  pqn_lcp_opts r{100, 50, 50, 1e-8, 1e-8, 1e-14, 0, 0};
   if (o) {
     if (o->k_max > 0) r.k_max = o->k_max;
     if (o->k_max_inner > 0) r.k_max_inner = o->k_max_inner;
@@ -1010,6 +1010,8 @@ static pqn_lcp_opts opts_or_default(const pqn_lcp_opts* o) {
     if (o->ssn_tol > 0) r.ssn_tol = o->ssn_tol;
     if (o->printed_metric < 0 || o->printed_metric > 1) throw Error(PQN_ERR_INVALID, "printed_metric must be 0 or 1");
     r.printed_metric = o->printed_metric;
+    if (o->recycle < 0 || o->recycle > 1) throw Error(PQN_ERR_INVALID, "recycle must be 0 or 1");
+    r.recycle = o->recycle;
   }
   return r;
 }
@@ -1238,11 +1240,36 @@ struct BiSolver {
   }
 };
 
+// Reuse of earlier solutions across the products of one solve (pqn_lcp_opts.recycle) on
+// every level of the context, for the duration of the solve; the stores start empty.
+struct RecycleScope {
+  std::vector<Level*> lv;
+  RecycleScope(pqn_ctx_impl& ctx, bool on) {
+    if (!on || (ctx.cfg.precision == PQN_MIXED && ctx.cfg.refine_sweeps > 0)) return;
+    lv.push_back(&ctx.hi);
+    if (ctx.has_lo) lv.push_back(&ctx.lo);
+    if (ctx.has_lo2) lv.push_back(&ctx.lo2);
+    for (Level* l : lv) {
+      l->rc.active = true;
+      l->rc.k = 0;
+    }
+  }
+  ~RecycleScope() {
+    for (Level* l : lv) {
+      l->rc.active = false;
+      l->rc.k = 0;
+    }
+  }
+  RecycleScope(const RecycleScope&) = delete;
+  RecycleScope& operator=(const RecycleScope&) = delete;
+};
+
 // Solve the LCP with b (device, length n) on the stored pairs. x ends in
 // st.outer.d.x; MDx (if non-null) receives M D x.
 static bool solve_device(pqn_ctx_impl& ctx, int n, int solver, const pqn_lcp_opts& o, double* MDx,
                          pqn_lcp_stats* stats, bool x0) {
   LcpState& st = *ctx.lcp;
+  RecycleScope recycle_scope(ctx, o.recycle != 0);
   SolveCounters cnt;
   Level& hi = ctx.hi;
   const int M = ctx.M;

@@ -378,3 +378,34 @@ def test_printed_metric_matches_oracle(cases, solver):
         assert abs(st['mvp_lo'] - lo_o) <= 2
     with binding.Context(cases[0]['c'], None, 8, 16) as ctx, pytest.raises(binding.PqnError):
         ctx.lcp_solve(cases[0]['pairs'], cases[0]['b_pl'], 'mono', printed_metric=2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_recycled_products_match_oracle(cases, prec):
+    """Krylov reuse across the products of one LCP solve (recycle = 1): the solutions equal
+    brute force and the cold solves, and the GMRES iterations fall as the oracle's
+    RecyclingMobility predicts (device CGS2 vs oracle MGS: counts within 2 per product)."""
+    tol = 1e-10 if prec == 'fp64' else 1e-6
+    kkt = (1e-12, 1e-15) if prec == 'fp64' else (1e-9, 1e-9)
+    for cs in cases:
+        b = cs['b_pl']
+        xbf = lcp.brute_force_lcp(cs['Ad'], b)
+        rec = bie.RecyclingMobility(cs['g'], tol=1e-13)
+        Aop = lcp.lcp_operator(rec, cs['c'], cs['pairs'])
+        xo, _, so = lcp.mono_pqn(Aop, b, tol_abs=kkt[0], tol_rel=kkt[1])
+        with binding.Context(cs['c'], None, 8, 16, lo=(4, 8), gmres_tol=1e-13, precision=prec) as ctx:
+            xc, sc = ctx.lcp_solve(cs['pairs'], b, 'mono', tol_abs=kkt[0], tol_rel=kkt[1])
+            xr, sr = ctx.lcp_solve(cs['pairs'], b, 'mono', tol_abs=kkt[0], tol_rel=kkt[1], recycle=True)
+            xb, sb = ctx.lcp_solve(cs['pairs'], b, 'bi', tol_abs=kkt[0], tol_rel=kkt[1], recycle=True)
+            xcold, _ = ctx.lcp_solve(cs['pairs'], b, 'mono', tol_abs=kkt[0], tol_rel=kkt[1])
+        say('recycle', prec, 'gmres cold', sc['gmres_iters'], 'recycled', sr['gmres_iters'], 'oracle',
+            sum(rec.iters), 'products', sr['mvp_hi'], so['mvp'], 'bi', sb['mvp_hi'], sb['mvp_lo'], sb['gmres_iters'])
+        for x, st in ((xc, sc), (xr, sr), (xb, sb)):
+            assert st['converged'] == 1
+            assert np.abs(x - xbf).max() <= tol * np.abs(xbf).max()
+        assert np.abs(xo - xbf).max() <= 1e-10 * np.abs(xbf).max()
+        assert np.array_equal(xc, xcold)          # the store does not outlive its call
+        assert sr['gmres_iters'] < sc['gmres_iters']
+        if prec == 'fp64':
+            assert abs(sr['mvp_hi'] - so['mvp']) <= 1
+            assert abs(sr['gmres_iters'] - sum(rec.iters)) <= 2 * sr['mvp_hi']

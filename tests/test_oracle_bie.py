@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import bie, grid
+from paper_2604_10089_amd import inputs
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), 'golden', 'closed_forms.json')))
 
@@ -345,3 +346,41 @@ def test_near_rule_subtracts_the_density_at_the_foot_point():
             u = (X[k] - g.c[1]) / np.linalg.norm(X[k] - g.c[1])
             foot = qf(u[None, :])[0]
             assert np.abs(near - (plain - Ksum @ foot)).max() < 1e-12 * max(1.0, np.abs(plain).max())
+
+
+def test_gmres_from_an_initial_guess(tiny_cases):
+    """GMRES from x0 solves the same system: the exact solution as x0 needs no iteration,
+    a perturbed one converges to the dense solve."""
+    _, g, A = tiny_cases[0]
+    rhs = -bie.completion(g, inputs.random_forces(12, g.M))
+    q = np.linalg.solve(A, rhs.ravel())
+    x, its, rr = bie.gmres(lambda v: A @ v.ravel(), rhs, tol=1e-12, x0=q)
+    assert its == 0 and rr <= 1e-12
+    x0 = q + 1e-3 * np.random.default_rng(1).standard_normal(q.size)
+    x, its, _ = bie.gmres(lambda v: A @ v.ravel(), rhs, tol=1e-13, x0=x0)
+    assert its > 0 and np.abs(x - q).max() < 1e-11 * np.abs(q).max()
+
+
+def test_recycling_mobility_equals_cold_solves(tiny_cases):
+    """Krylov reuse across products (the future work of Sec. 7): each solve starts from the
+    least-squares combination of earlier solutions, and
+      * its result equals the cold solve to the GMRES tolerance;
+      * the initial residual is never larger than the right-hand side;
+      * a force that is a combination of earlier forces has a right-hand side in the span
+        of earlier ones: initial residual ~0 and no iteration at all;
+      * a new, independent force still needs iterations."""
+    _, g, A = tiny_cases[0]
+    rec = bie.RecyclingMobility(g, tol=1e-12)
+    F = [inputs.random_forces(20 + k, g.M) for k in range(3)]
+    for f in F:
+        U = rec(f)
+        Uc = bie.mobility_apply(g, f, dense=A)
+        assert np.abs(U - Uc).max() < 1e-10 * np.abs(Uc).max()
+    assert rec.iters[0] > 0 and all(r <= 1.0 + 1e-12 for r in rec.r0)
+    comb = 0.7 * F[0] - 1.3 * F[2] + 0.2 * F[1]
+    U = rec(comb)
+    assert rec.r0[-1] < 1e-10 and rec.iters[-1] == 0
+    Uc = bie.mobility_apply(g, comb, dense=A)
+    assert np.abs(U - Uc).max() < 1e-10 * np.abs(Uc).max()
+    U = rec(inputs.random_forces(40, g.M))
+    assert rec.iters[-1] > 0 and rec.r0[-1] > 1e-3
