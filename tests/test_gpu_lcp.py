@@ -392,7 +392,7 @@ def test_recycled_products_match_oracle(cases, prec):
         xbf = lcp.brute_force_lcp(cs['Ad'], b)
         rec = bie.RecyclingMobility(cs['g'], tol=1e-13)
         Aop = lcp.lcp_operator(rec, cs['c'], cs['pairs'])
-        xo, _, so = lcp.mono_pqn(Aop, b, tol_abs=kkt[0], tol_rel=kkt[1])
+        xo, _, so = lcp.mono_pqn(Aop, b, tol_abs=1e-12, tol_rel=1e-15)
         with binding.Context(cs['c'], None, 8, 16, lo=(4, 8), gmres_tol=1e-13, precision=prec) as ctx:
             xc, sc = ctx.lcp_solve(cs['pairs'], b, 'mono', tol_abs=kkt[0], tol_rel=kkt[1])
             xr, sr = ctx.lcp_solve(cs['pairs'], b, 'mono', tol_abs=kkt[0], tol_rel=kkt[1], recycle=True)
