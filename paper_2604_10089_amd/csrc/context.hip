@@ -10,17 +10,6 @@ namespace bipqn {
 
 constexpr int kMultiDotBlocks = 16;  // reduction blocks per vector in the segmented dot kernel
 
-// Host staging of typed descriptor arrays, uploaded in one copy.
-struct DescPack {
-  std::vector<char> host;
-  template <class T>
-  size_t add(const std::vector<T>& v) {
-    const size_t off = (host.size() + 63) & ~size_t(63);
-    host.resize(off + v.size() * sizeof(T));
-    if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
-    return off;
-  }
-};
 
 // One GEMM problem of a segmented launch: C(r, col) = sum_k A[r lda + k] B[col ldb + k].
 static void push_gemm(std::vector<GemmDesc>& v, int& blocks, int R, int Cn, int K, const double* A, int lda,
@@ -433,60 +422,114 @@ void pqn_ctx_impl::side_work(MvGroup& gr, hipStream_t st) {
   stage_end(kStageLocal);
 }
 
-// Many suspensions (one density each): every phase of the operator is one
-// segmented launch over all of them.
-void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
-  hipStream_t s = stream;
+// Segment tables of one operator application to many suspensions (one density
+// each), appended to dp: every phase is one segmented launch over all of them.
+// live[g] (may be empty) is the flag of group g's system (graph-captured GMRES).
+BatchOpTables pqn_ctx_impl::batch_op_tables(std::vector<MvGroup>& groups, int prec, const std::vector<const int*>& live,
+                                            DescPack& dp) {
   std::vector<GemmDesc> ga, gb;
   std::vector<PackDesc> pk;
   std::vector<NearDesc> nd;
   std::vector<MomDesc> md;
   std::vector<CombDesc> cd;
-  int nga = 0, ngb = 0, npk = 0, nnd = 0, nmd = 0, ncd = 0;
-
-  for (MvGroup& gr : groups) {
+  BatchOpTables t{};
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    MvGroup& gr = groups[gi];
+    const int* lf = live.empty() ? nullptr : live[gi];
     Level& lv = *gr.lv;
     pqn_ctx_impl& c = *gr.c;
     Work& w = lv.wk(gr.slot[0]);
     const int n = lv.n, N = lv.N, L = lv.L, nup = lv.nup, M = lv.M;
+    const size_t a0 = ga.size(), b0 = gb.size();
     for (int comp = 0; comp < 3; ++comp) {
-      push_gemm(ga, nga, L, M, n, lv.T.p, n, gr.in[0] + (size_t)comp * N, n, w.coef.p + (size_t)comp * M * L, L, 0,
+      push_gemm(ga, t.nga, L, M, n, lv.T.p, n, gr.in[0] + (size_t)comp * N, n, w.coef.p + (size_t)comp * M * L, L, 0,
                 L);
-      push_gemm(gb, ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, w.coef.p + (size_t)comp * M * L, L,
+      push_gemm(gb, t.ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, w.coef.p + (size_t)comp * M * L, L,
                 w.selfo.p + (size_t)comp * 3 * N, n, N, n);
       if (c.n_near > 0)  // interleaved [M][nup][3]
-        push_gemm(gb, ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup.p + comp, 1, 3,
+        push_gemm(gb, t.ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup.p + comp, 1, 3,
                   nup * 3);
       if (c.n_near2 > 0)
-        push_gemm(gb, ngb, lv.nup2, M, L, lv.Yup2.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup2.p + comp, 1, 3,
+        push_gemm(gb, t.ngb, lv.nup2, M, L, lv.Yup2.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup2.p + comp, 1, 3,
                   lv.nup2 * 3);
     }
-    pk.push_back(PackDesc{gr.in[0], lv.off.p, lv.w.p, lv.src.p, n, N, npk});
-    npk += N;
+    for (size_t e = a0; e < ga.size(); ++e) ga[e].live = lf;
+    for (size_t e = b0; e < gb.size(); ++e) gb[e].live = lf;
+    pk.push_back(PackDesc{gr.in[0], lv.off.p, lv.w.p, lv.src.p, n, N, t.npk, lf});
+    t.npk += N;
     if (c.n_near > 0) {
       const int nch = (n + 63) / 64;
       nd.push_back(NearDesc{c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, w.qup.p, w.coef.p, c.near_list.p, w.near_part.p,
-                            3.0 / (4.0 * kPi * c.a), n, M, N, nup, lv.p, L, nch, nnd});
-      nnd += c.n_near * nch;
+                            3.0 / (4.0 * kPi * c.a), n, M, N, nup, lv.p, L, nch, t.nnd, lf});
+      t.nnd += c.n_near * nch;
     }
     if (c.n_near2 > 0) {
       const int nch = (n + 63) / 64;
       nd.push_back(NearDesc{c.ctr.p, lv.off.p, lv.offup2.p, lv.shab.p, w.qup2.p, w.coef.p, c.near_list2.p,
-                            w.near_part.p, 3.0 / (4.0 * kPi * c.a), n, M, N, lv.nup2, lv.p, L, nch, nnd});
-      nnd += c.n_near2 * nch;
+                            w.near_part.p, 3.0 / (4.0 * kPi * c.a), n, M, N, lv.nup2, lv.p, L, nch, t.nnd, lf});
+      t.nnd += c.n_near2 * nch;
     }
-    md.push_back(MomDesc{gr.in[0], lv.off.p, lv.w.p, w.mom.p, n, N, nmd});
-    nmd += M;
+    md.push_back(MomDesc{gr.in[0], lv.off.p, lv.w.p, w.mom.p, n, N, t.nmd, lf});
+    t.nmd += M;
     cd.push_back(CombDesc{gr.in[0], w.selfo.p, w.far_part.p, w.near_part.p, c.npart.p, w.mom.p, lv.off.p, gr.out[0],
-                          c.a, lv.nchunks, n, N, ncd});
-    ncd += 3 * N;
+                          c.a, lv.nchunks, n, N, t.ncd, lf});
+    t.ncd += 3 * N;
   }
-  DescPack dp;
-  const size_t oa = dp.add(ga), ob = dp.add(gb), op = dp.add(pk), on = dp.add(nd), om = dp.add(md), oc = dp.add(cd);
-  char* base = push_desc_pack(dp.host);
-  // side_stream: GEMMs, near tiles and moments of every suspension on the second stream,
-  // beside the packing and far pair sums (the table above is read by both streams and
-  // rewritten only after the join)
+  // far pair sums of all suspensions in one launch, work items by decreasing cost
+  struct Item {
+    FarDesc d;
+    long cost;
+  };
+  std::vector<Item> items;
+  const int tpt = far_layout(cfg);
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    MvGroup& gr = groups[gi];
+    Level& lv = *gr.lv;
+    FarDesc d{};
+    d.src = lv.src.p;
+    d.off = lv.off.p;
+    d.ctr = gr.c->ctr.p;
+    d.cls = gr.c->cls.p;
+    d.part = lv.wk(gr.slot[0]).far_part.p;
+    d.n = lv.n;
+    d.M = lv.M;
+    d.N = lv.N;
+    d.spc = lv.spc;
+    const int per_block = prec == 1 ? (tpt == 0 ? 64 : 256 * tpt) : 256;
+    d.ntb = (lv.N + per_block - 1) / per_block;
+    d.scale = 3.0 / (4.0 * kPi * gr.c->a);
+    d.live = live.empty() ? nullptr : live[gi];
+    items.push_back({d, (long)lv.n * lv.n * lv.spc});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+  std::vector<FarDesc> fd;
+  for (Item& it : items) {
+    it.d.item0 = t.nfar;
+    t.nfar += it.d.ntb * ((it.d.M + it.d.spc - 1) / it.d.spc);
+    fd.push_back(it.d);
+  }
+  t.na = (int)ga.size();
+  t.nb = (int)gb.size();
+  t.npk_n = (int)pk.size();
+  t.nnd_n = (int)nd.size();
+  t.nmd_n = (int)md.size();
+  t.ncd_n = (int)cd.size();
+  t.nfd = (int)fd.size();
+  t.oa = dp.add(ga);
+  t.ob = dp.add(gb);
+  t.op = dp.add(pk);
+  t.on = dp.add(nd);
+  t.om = dp.add(md);
+  t.oc = dp.add(cd);
+  t.of = dp.add(fd);
+  return t;
+}
+
+// Kernel launches of one batched operator application from uploaded tables (no copies
+// or fills: capturable). side_stream: GEMMs, near tiles and moments on the second stream,
+// forked and joined by events, beside the packing and far pair sums.
+void pqn_ctx_impl::batch_op_launch(const char* base, const BatchOpTables& t, int prec) {
+  hipStream_t s = stream;
   const bool ov = cfg.side_stream && !cfg.profile;
   hipStream_t sa = s;
   if (ov) {
@@ -495,68 +538,44 @@ void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
     HIPCHK(hipStreamWaitEvent(sa, ev_in, 0));
   }
   stage_begin(kStageGemm);
-  launch_gemm64_multi(sa, (const GemmDesc*)(base + oa), (int)ga.size(), nga);  // coef = T q
-  launch_gemm64_multi(sa, (const GemmDesc*)(base + ob), (int)gb.size(), ngb);  // self, qup
+  launch_gemm64_multi(sa, (const GemmDesc*)(base + t.oa), t.na, t.nga);  // coef = T q
+  launch_gemm64_multi(sa, (const GemmDesc*)(base + t.ob), t.nb, t.ngb);  // self, qup
   stage_end(kStageGemm);
   if (ov) {
-    if (!nd.empty()) launch_near_multi(sa, (const NearDesc*)(base + on), (int)nd.size(), nnd);
-    launch_moments_multi(sa, (const MomDesc*)(base + om), (int)md.size(), nmd);
+    if (t.nnd_n > 0) launch_near_multi(sa, (const NearDesc*)(base + t.on), t.nnd_n, t.nnd);
+    launch_moments_multi(sa, (const MomDesc*)(base + t.om), t.nmd_n, t.nmd);
     HIPCHK(hipEventRecord(ev_side, sa));
   }
   stage_begin(kStageLocal);
-  launch_pack_multi(s, (const PackDesc*)(base + op), (int)pk.size(), npk, prec);
+  launch_pack_multi(s, (const PackDesc*)(base + t.op), t.npk_n, t.npk, prec);
   stage_end(kStageLocal);
   begin_far_timing();
-  {
-    struct Item {
-      FarDesc d;
-      long cost;
-    };
-    std::vector<Item> items;
-    const int tpt = far_layout(cfg);
-    for (MvGroup& gr : groups) {
-      Level& lv = *gr.lv;
-      FarDesc d{};
-      d.src = lv.src.p;
-      d.off = lv.off.p;
-      d.ctr = gr.c->ctr.p;
-      d.cls = gr.c->cls.p;
-      d.part = lv.wk(gr.slot[0]).far_part.p;
-      d.n = lv.n;
-      d.M = lv.M;
-      d.N = lv.N;
-      d.spc = lv.spc;
-      const int per_block = prec == 1 ? (tpt == 0 ? 64 : 256 * tpt) : 256;
-      d.ntb = (lv.N + per_block - 1) / per_block;
-      d.scale = 3.0 / (4.0 * kPi * gr.c->a);
-      items.push_back({d, (long)lv.n * lv.n * lv.spc});
-    }
-    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
-    std::vector<FarDesc> ds;
-    int total = 0;
-    for (Item& it : items) {
-      it.d.item0 = total;
-      total += it.d.ntb * ((it.d.M + it.d.spc - 1) / it.d.spc);
-      ds.push_back(it.d);
-    }
-    fdesc.upload(ds.data(), ds.size(), s);
-    launch_far_multi(s, prec, tpt, fdesc.p, (int)ds.size(), total);
-  }
+  launch_far_multi(s, prec, far_layout(cfg), (const FarDesc*)(base + t.of), t.nfd, t.nfar);
   end_far_launch();
   ++n_far;
   if (ov) {
     HIPCHK(hipStreamWaitEvent(s, ev_side, 0));
   } else {
     stage_begin(kStageNear);
-    if (!nd.empty()) launch_near_multi(s, (const NearDesc*)(base + on), (int)nd.size(), nnd);
+    if (t.nnd_n > 0) launch_near_multi(s, (const NearDesc*)(base + t.on), t.nnd_n, t.nnd);
     stage_end(kStageNear);
     stage_begin(kStageLocal);
-    launch_moments_multi(s, (const MomDesc*)(base + om), (int)md.size(), nmd);
+    launch_moments_multi(s, (const MomDesc*)(base + t.om), t.nmd_n, t.nmd);
     stage_end(kStageLocal);
   }
   stage_begin(kStageLocal);
-  launch_combine_multi(s, (const CombDesc*)(base + oc), (int)cd.size(), ncd);
+  launch_combine_multi(s, (const CombDesc*)(base + t.oc), t.ncd_n, t.ncd);
   stage_end(kStageLocal);
+}
+
+// Many suspensions (one density each): every phase of the operator is one
+// segmented launch over all of them.
+void pqn_ctx_impl::matvec_batched(std::vector<MvGroup>& groups, int prec) {
+  DescPack dp;
+  const BatchOpTables t = batch_op_tables(groups, prec, {}, dp);
+  // (the table is read by both streams and rewritten only after the join)
+  const char* base = push_desc_pack(dp.host);
+  batch_op_launch(base, t, prec);
   n_matvec += (int)groups.size();
   HIPCHK(hipGetLastError());
 }
@@ -708,12 +727,243 @@ struct GmState {
 };
 }  // namespace
 
+void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
+  bool graph = is_batch && cfg.use_graphs && !cfg.profile && sys.size() > 1 && precision == cfg.precision;
+  for (SysRef& r : sys) graph = graph && !r.x0 && !r.res_out;
+  if (graph)
+    gmres_batch_graph(sys, precision);
+  else
+    gmres_lockstep_eager(sys, precision);
+}
+
+// Descriptor tables of Arnoldi index j for every system (operator on V[j] -> V[j+1],
+// CGS2 against V[0..j], |w|^2, the Givens step and the normalisation of V[j+1]),
+// uploaded once, then the launches captured into graph j.
+void pqn_ctx_impl::capture_batch_iteration(BatchGraph& bg, std::vector<SysRef>& sys, int j, int prec) {
+  const int ns = (int)sys.size(), m = bg.m;
+  const int hs = 2 * (m + 1) + 2;
+  std::vector<MvGroup> groups;
+  std::vector<const int*> live;
+  for (int i = 0; i < ns; ++i) {
+    SysBuf& b = sys[i].lv->sb(sys[i].slot);
+    const size_t len = 3 * (size_t)sys[i].lv->N;
+    add_to_groups(groups, sys[i].c, sys[i].lv, sys[i].slot, b.V.p + (size_t)j * len, b.V.p + (size_t)(j + 1) * len);
+    live.push_back(&bg.sys.p[i].active);
+  }
+  if ((int)groups.size() != ns) throw Error(PQN_ERR_STATE, "internal: batched systems must be on distinct levels");
+  DescPack dp;
+  const BatchOpTables t = batch_op_tables(groups, prec, live, dp);
+  std::vector<DotDesc> dd[2], dn;
+  std::vector<ComboDesc> cd[2];
+  std::vector<ScaleDesc> sc;
+  int nv[2] = {0, 0}, nn = 0, ne[2] = {0, 0}, nsc = 0;
+  for (int i = 0; i < ns; ++i) {
+    SysBuf& b = sys[i].lv->sb(sys[i].slot);
+    const long len = 3L * sys[i].lv->N;
+    double* w = b.V.p + (size_t)(j + 1) * len;
+    double* hp = bg.hbuf.p + (size_t)i * hs;
+    for (int pass = 0; pass < 2; ++pass) {
+      dd[pass].push_back(DotDesc{b.V.p, w, b.partial.p, hp + pass * (m + 1), len, len, nv[pass], live[i]});
+      nv[pass] += j + 1;
+      cd[pass].push_back(ComboDesc{w, b.V.p, hp + pass * (m + 1), -1.0, 1.0, len, len, j + 1, ne[pass], live[i]});
+      ne[pass] += (int)len;
+    }
+    dn.push_back(DotDesc{w, w, b.partial.p, hp + 2 * (m + 1), len, len, nn, live[i]});
+    nn += 1;
+    sc.push_back(ScaleDesc{w, &bg.sys.p[i].inv_hn, live[i], len, nsc});
+    nsc += (int)len;
+  }
+  const size_t o0 = dp.add(dd[0]), o1 = dp.add(cd[0]), o2 = dp.add(dd[1]), o3 = dp.add(cd[1]), o4 = dp.add(dn),
+               o5 = dp.add(sc);
+  const size_t need = (dp.host.size() + 255) & ~size_t(255);
+  if (!bg.tabs.p || need > bg.stride) {
+    // every graph captured so far points into the old tables: drop them all
+    HIPCHK(hipStreamSynchronize(stream));
+    bg.clear();
+    bg.execs.assign(m, nullptr);
+    bg.stride = need;
+    bg.tabs.release();
+    bg.tabs.alloc(bg.stride * m);
+  }
+  char* base = bg.tabs.p + bg.stride * j;
+  HIPCHK(hipMemcpyAsync(base, dp.host.data(), dp.host.size(), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  const int nfar0 = n_far;
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  try {
+    batch_op_launch(base, t, prec);
+    launch_dots_multi(stream, (const DotDesc*)(base + o0), ns, nv[0], kMultiDotBlocks);
+    launch_combo_multi(stream, (const ComboDesc*)(base + o1), ns, ne[0]);
+    launch_dots_multi(stream, (const DotDesc*)(base + o2), ns, nv[1], kMultiDotBlocks);
+    launch_combo_multi(stream, (const ComboDesc*)(base + o3), ns, ne[1]);
+    launch_dots_multi(stream, (const DotDesc*)(base + o4), ns, nn, kMultiDotBlocks);
+    launch_gmres_step(stream, bg.sys.p, bg.hess.p, bg.hbuf.p, hs, m, ns);
+    launch_scale_multi(stream, (const ScaleDesc*)(base + o5), ns, nsc);
+  } catch (...) {
+    hipGraph_t g2 = nullptr;
+    (void)hipStreamEndCapture(stream, &g2);
+    if (g2) (void)hipGraphDestroy(g2);
+    n_far = nfar0;
+    throw;
+  }
+  n_far = nfar0;
+  HIPCHK(hipStreamEndCapture(stream, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCHK(ie);
+  bg.execs[j] = exec;
+}
+
+// First GMRES(m) cycle of many cold-started systems from captured graphs: all systems
+// take Arnoldi step j together (graph j); the Givens rotations and the end test run on
+// the device, so the host reads the state back only every 8 steps to stop early. The
+// cycle's end (x += V y) is done from the read-back Hessenberg matrices; systems whose
+// cycle filled continue in the eager lockstep loop from their iterate.
+void pqn_ctx_impl::gmres_batch_graph(std::vector<SysRef>& sys, int precision) {
+  const int ns = (int)sys.size();
+  const int m = sys[0].lv->restart;
+  for (SysRef& r : sys)
+    if (r.lv->restart != m) throw Error(PQN_ERR_STATE, "internal: batched systems with different restart lengths");
+  const int prec = precision == PQN_MIXED ? 1 : 0;
+  const int hs = 2 * (m + 1) + 2;
+  hipStream_t s = stream;
+  std::vector<const void*> key;
+  for (SysRef& r : sys) {
+    key.push_back(r.c);
+    key.push_back(r.lv);
+    key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>(r.slot)));
+    r.lv->wk(r.slot);  // every buffer exists before any capture
+    r.lv->sb(r.slot);
+  }
+  if (cfg.side_stream) side_stream();  // created before any capture that forks onto it
+  if (!bgraph) bgraph.reset(new BatchGraph());
+  BatchGraph& bg = *bgraph;
+  if (bg.key != key || bg.prec != prec || bg.m != m) {
+    HIPCHK(hipStreamSynchronize(s));
+    bg.clear();
+    bg.key = key;
+    bg.prec = prec;
+    bg.m = m;
+    bg.ns = ns;
+    bg.execs.assign(m, nullptr);
+    bg.sys.alloc(ns);
+    bg.hess.alloc((size_t)ns * gm_stride(m));
+    bg.hbuf.alloc((size_t)ns * hs);
+  }
+  // right-hand side norms
+  for (int i = 0; i < ns; ++i) {
+    SysBuf& b = sys[i].lv->sb(sys[i].slot);
+    launch_dots(s, sys[i].rhs, 3L * sys[i].lv->N, 1, sys[i].rhs, 3L * sys[i].lv->N, sys[i].lv->nb_dots, b.partial.p,
+                bg.hbuf.p + (size_t)i * hs + 2 * (m + 1));
+  }
+  std::vector<double> hb((size_t)ns * hs);
+  HIPCHK(hipMemcpyAsync(hb.data(), bg.hbuf.p, hb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<GmSys> hsys(ns);
+  for (int i = 0; i < ns; ++i) {
+    const long len = 3L * sys[i].lv->N;
+    const double bn = std::sqrt(std::max(0.0, hb[(size_t)i * hs + 2 * (m + 1)]));
+    if (!std::isfinite(bn)) throw Error(PQN_ERR_NUMERIC, "non-finite right-hand side");
+    sys[i].its = 0;
+    sys[i].relres = 0.0;
+    sys[i].conv = bn == 0.0;
+    launch_scale_copy(s, sys[i].x, sys[i].rhs, 0.0, len);  // x = 0
+    GmSys g{};
+    g.max_iter = sys[i].lv->max_iter;
+    g.bnorm = bn;
+    g.tol = sys[i].tol;
+    if (bn > 0.0) {
+      launch_scale_copy(s, sys[i].lv->sb(sys[i].slot).V.p, sys[i].rhs, 1.0 / bn, len);
+      g.active = 1;
+    }
+    hsys[i] = g;
+  }
+  HIPCHK(hipMemcpyAsync(bg.sys.p, hsys.data(), ns * sizeof(GmSys), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  bool read_now = false;
+  for (int j = 0; j < m; ++j) {
+    TraceRange trace_iter("gmres_iteration_graph");
+    if (!bg.execs[j]) capture_batch_iteration(bg, sys, j, prec);
+    HIPCHK(hipGraphLaunch(bg.execs[j], s));
+    ++n_graph_launch;
+    ++n_far;
+    read_now = j % 8 == 7 || j == m - 1;
+    if (read_now) {
+      HIPCHK(hipMemcpyAsync(hsys.data(), bg.sys.p, ns * sizeof(GmSys), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      bool any = false;
+      for (const GmSys& g : hsys) any = any || g.active;
+      if (!any) break;
+    }
+  }
+  if (!read_now) {
+    HIPCHK(hipMemcpyAsync(hsys.data(), bg.sys.p, ns * sizeof(GmSys), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  std::vector<double> hh((size_t)ns * gm_stride(m));
+  HIPCHK(hipMemcpyAsync(hh.data(), bg.hess.p, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  // end of the cycle: y = R^{-1} g, x += V y
+  std::vector<int> rest;
+  std::vector<std::vector<double>> ys(ns);
+  for (int i = 0; i < ns; ++i) {
+    const GmSys& g = hsys[i];
+    SysRef& sr = sys[i];
+    if (g.bnorm == 0.0) continue;
+    if (g.err) throw Error(PQN_ERR_NUMERIC, "non-finite value or breakdown in GMRES");
+    if (g.active) throw Error(PQN_ERR_STATE, "internal: GMRES cycle still active after m steps");
+    n_matvec += g.its;
+    sr.its = g.its;
+    sr.relres = g.relres;
+    const double* H = hh.data() + (size_t)i * gm_stride(m);
+    const double* gv = H + (size_t)(m + 1) * m + 2 * m;
+    const int dk = g.k + 1;
+    std::vector<double>& y = ys[i];
+    y.assign(dk, 0.0);
+    for (int r = dk - 1; r >= 0; --r) {
+      double v = gv[r];
+      for (int c2 = r + 1; c2 < dk; ++c2) v -= H[(size_t)r * m + c2] * y[c2];
+      y[r] = v / H[(size_t)r * m + r];
+    }
+    SysBuf& b = sr.lv->sb(sr.slot);
+    const long len = 3L * sr.lv->N;
+    HIPCHK(hipMemcpyAsync(b.ycoef.p, y.data(), dk * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_combo(s, sr.x, 1.0, b.V.p, len, dk, b.ycoef.p, 1.0, len);
+    if (g.conv) {
+      sr.conv = true;
+    } else if (g.its >= g.max_iter) {
+      sr.conv = false;
+    } else {
+      rest.push_back(i);
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));  // the y vectors leave scope only after their copies
+  if (!rest.empty()) {
+    // cycles that filled: continue from the iterate (the eager loop restarts from the true residual)
+    std::vector<SysRef> sub;
+    for (int i : rest) {
+      SysRef r = sys[i];
+      r.x0 = r.x;
+      sub.push_back(r);
+    }
+    gmres_lockstep_eager(sub, precision);
+    for (size_t k = 0; k < rest.size(); ++k) {
+      SysRef& sr = sys[rest[k]];
+      sr.its += sub[k].its;
+      sr.relres = sub[k].relres;
+      sr.conv = sub[k].conv;
+    }
+  }
+}
+
 // Restarted GMRES(m) on many systems in lockstep: every iteration applies the
 // operator to all active systems at once (one joint launch of the pair sums)
 // and reads back all Hessenberg columns in one copy. Per system: classical
 // Gram-Schmidt with one reorthogonalisation (CGS2) in FP64 on the device,
 // Givens rotations on the host; restarts from the true residual.
-void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
+void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision) {
   const int ns = (int)sys.size();
   if (ns == 0) return;
   const int m = sys[0].lv->restart;

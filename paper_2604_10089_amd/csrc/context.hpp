@@ -2,6 +2,7 @@
 // operator on groups of densities, lockstep GMRES and the mobility product.
 #pragma once
 #include <chrono>
+#include <cstring>
 #include <memory>
 #include <stdexcept>
 #include <utility>
@@ -139,6 +140,26 @@ struct Recycle {
   unsigned long epoch = 0;  // configuration the stored pairs belong to
 };
 
+// Host staging of typed descriptor arrays, uploaded in one copy.
+struct DescPack {
+  std::vector<char> host;
+  template <class T>
+  size_t add(const std::vector<T>& v) {
+    const size_t off = (host.size() + 63) & ~size_t(63);
+    host.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+// Offsets (in a DescPack) and sizes of the segment tables of one batched operator
+// application: descriptor counts (n*) and launch extents (blocks or elements).
+struct BatchOpTables {
+  size_t oa = 0, ob = 0, op = 0, on = 0, om = 0, oc = 0, of = 0;
+  int na = 0, nga = 0, nb = 0, ngb = 0, npk_n = 0, npk = 0, nnd_n = 0, nnd = 0, nmd_n = 0, nmd = 0, ncd_n = 0,
+      ncd = 0, nfd = 0, nfar = 0;
+};
+
 // Offsets and sizes of the segmented GEMM descriptor tables of one iteration.
 struct IterTables {
   size_t oa = 0, ob = 0;
@@ -161,6 +182,25 @@ struct GraphCache {
     execs.clear();
   }
   ~GraphCache() { clear(); }
+};
+
+// Captured GMRES iterations of a batch of systems (one graph per Arnoldi index, all
+// systems in lockstep; device-side Givens rotations and end tests, so a system that
+// ends turns its segments of the later launches into no-ops).
+struct BatchGraph {
+  int m = 0, ns = 0, prec = -1;
+  std::vector<const void*> key;  // (context, level, slot) of every system, in order
+  DevArray<GmSys> sys;
+  DevArray<double> hess, hbuf;
+  DevArray<char> tabs;  // descriptor tables of every Arnoldi index (stride apart)
+  size_t stride = 0;
+  std::vector<hipGraphExec_t> execs;
+  void clear() {
+    for (hipGraphExec_t& e : execs)
+      if (e) (void)hipGraphExecDestroy(e);
+    execs.clear();
+  }
+  ~BatchGraph() { clear(); }
 };
 
 struct Level {
@@ -248,7 +288,6 @@ struct pqn_ctx_impl {
   // lockstep GMRES scratch: per-system Hessenberg columns, read back in one copy
   DevArray<double> hdev;
   std::vector<double> hhost;
-  DevArray<FarDesc> fdesc;
   DevArray<char> ddesc;  // segment descriptors of the multi-suspension kernels
   char* push_desc_pack(const std::vector<char>& pack);
   char* push_desc_pack(const std::vector<char>& pack, hipStream_t st, DevArray<char>& table);
@@ -294,6 +333,9 @@ struct pqn_ctx_impl {
   // operator on groups of densities (all on this context's stream)
   void matvec_groups(std::vector<MvGroup>& groups, int precision);
   void matvec_batched(std::vector<MvGroup>& groups, int prec);
+  BatchOpTables batch_op_tables(std::vector<MvGroup>& groups, int prec, const std::vector<const int*>& live,
+                                DescPack& dp);
+  void batch_op_launch(const char* base, const BatchOpTables& t, int prec);
   // one GMRES iteration of a single system (operator + CGS2), kernels only, for capture
   IterTables iteration_tables(pqn_ctx_impl& c, Level& lv, int slot, const double* q, std::vector<char>& bytes);
   void iteration_launches(pqn_ctx_impl& c, Level& lv, int slot, int prec, const double* q, double* w,
@@ -302,6 +344,11 @@ struct pqn_ctx_impl {
   void apply_operator(Level& lv, int precision, const double* q, double* y);
   // lockstep GMRES over systems; every system's x is overwritten (initial guess 0)
   void gmres_lockstep(std::vector<SysRef>& sys, int precision);
+  void gmres_lockstep_eager(std::vector<SysRef>& sys, int precision);
+  // batch contexts with use_graphs: the first cycle of cold-started systems from captured graphs
+  std::unique_ptr<BatchGraph> bgraph;
+  void gmres_batch_graph(std::vector<SysRef>& sys, int precision);
+  void capture_batch_iteration(BatchGraph& bg, std::vector<SysRef>& sys, int j, int prec);
   // solve in the context's precision with optional FP64-residual refinement
   void solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st);
   // mobility products of K force sets on one level (K <= kMaxRhs)

@@ -290,6 +290,7 @@ __global__ __launch_bounds__(256) void k_far32_multi(const FarDesc* __restrict__
   int d = 0;
   while (d + 1 < ndesc && desc[d + 1].item0 <= item) ++d;
   const FarDesc D = desc[d];
+  if (D.live && !*D.live) return;  // uniform over the block
   const int local = item - D.item0;
   const int tb = local % D.ntb, chunk = local / D.ntb;
   OPtrs part;
@@ -389,6 +390,7 @@ __global__ __launch_bounds__(256) void k_far64_multi(const FarDesc* __restrict__
   int d = 0;
   while (d + 1 < ndesc && desc[d + 1].item0 <= item) ++d;
   const FarDesc D = desc[d];
+  if (D.live && !*D.live) return;
   const int local = item - D.item0;
   const int tb = local % D.ntb, chunk = local / D.ntb;
   OPtrs part;
@@ -922,6 +924,7 @@ template <int GW>
 __global__ __launch_bounds__(64 * GW) void k_gemm64_multi(const GemmDesc* __restrict__ d, int nd) {
   const int b = blockIdx.x;
   const GemmDesc D = d[find_seg(d, nd, b)];
+  if (D.live && !*D.live) return;  // uniform over the block, before any barrier
   const int local = b - D.start;
   gemm_tile<GW>(local % D.tr, local / D.tr, D.R, D.Cn, D.K, D.A, D.lda, D.B, D.ldb, D.C, D.rb, D.rbs, D.ldc);
 }
@@ -930,7 +933,7 @@ __global__ __launch_bounds__(256) void k_pack_multi(const PackDesc* __restrict__
   const int g = blockIdx.x * 256 + threadIdx.x;
   const PackDesc D = d[find_seg(d, nd, g)];
   const int t = g - D.start;
-  if (t < 0 || t >= D.N) return;
+  if (t < 0 || t >= D.N || (D.live && !*D.live)) return;
   const int k = t % D.n;
   const double wk = D.w[k];
   if (fp32) {
@@ -953,6 +956,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near64_multi(const NearDesc
   __shared__ double lds[kNearWaves * 3 * 64];
   const int b = blockIdx.x;
   const NearDesc D = d[find_seg(d, nd, b)];
+  if (D.live && !*D.live) return;
   const int local = b - D.start;
   QPtrs cf{};
   OPtrs np{};
@@ -964,6 +968,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near64_multi(const NearDesc
 
 __global__ __launch_bounds__(256) void k_moments_multi(const MomDesc* __restrict__ d, int nd) {
   const MomDesc D = d[find_seg(d, nd, blockIdx.x)];
+  if (D.live && !*D.live) return;
   moments_body(blockIdx.x - D.start, D.q, D.off, D.w, D.n, D.N, D.mom);
 }
 
@@ -971,13 +976,14 @@ __global__ __launch_bounds__(256) void k_combine_multi(const CombDesc* __restric
   const int g = blockIdx.x * 256 + threadIdx.x;
   const CombDesc D = d[find_seg(d, nd, g)];
   const int e = g - D.start;
-  if (e < 0 || e >= 3 * D.N) return;
+  if (e < 0 || e >= 3 * D.N || (D.live && !*D.live)) return;
   combine_elem(e, D.q, D.selfo, 3, D.far, D.nchunks, D.near, D.npart, D.mom, D.off, D.n, D.N, D.a, D.y);
 }
 
 // partial[v][b] for the vectors of every system (grid: nb x total vectors)
 __global__ __launch_bounds__(256) void k_dots_multi(const DotDesc* __restrict__ d, int nd) {
   const DotDesc D = d[find_seg(d, nd, blockIdx.y)];
+  if (D.live && !*D.live) return;
   const int v = blockIdx.y - D.start;
   const double* x = D.V + (size_t)v * D.ldv;
   double s = 0.0;
@@ -994,6 +1000,7 @@ __global__ __launch_bounds__(256) void k_dots_multi(const DotDesc* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_dots_finish_multi(const DotDesc* __restrict__ d, int nd, int nb) {
   const DotDesc D = d[find_seg(d, nd, blockIdx.x)];
+  if (D.live && !*D.live) return;
   const int v = blockIdx.x - D.start;
   double s = 0.0;
   for (int b = threadIdx.x; b < nb; b += 256) s += D.partial[(size_t)v * nb + b];
@@ -1012,10 +1019,73 @@ __global__ __launch_bounds__(256) void k_combo_multi(const ComboDesc* __restrict
   const int g = blockIdx.x * 256 + threadIdx.x;
   const ComboDesc D = d[find_seg(d, nd, g)];
   const long e = g - D.start;
-  if (e < 0 || e >= D.len) return;
+  if (e < 0 || e >= D.len || (D.live && !*D.live)) return;
   double s = 0.0;
   for (int v = 0; v < D.nvec; ++v) s = fma(D.h[v], D.V[(size_t)v * D.ldv + e], s);
   D.w[e] = (D.beta == 0.0 ? 0.0 : D.beta * D.w[e]) + D.alpha * s;
+}
+
+// One GMRES step per active system (one thread each): Hessenberg column k from the
+// two CGS2 passes, the earlier Givens rotations applied to it, a new rotation, the
+// residual estimate |g_{k+1}| and the end test (converged, or cycle full / iteration
+// cap). A system that goes on gets inv_hn = 1/|w| for the normalisation of V[k+1];
+// one that ends keeps V[k+1] unnormalised (hn kept), as the host loop does.
+__global__ void k_gmres_step(GmSys* __restrict__ sys, double* __restrict__ hess, const double* __restrict__ hbuf,
+                             int hs, int m, int ns) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  GmSys S = sys[i];
+  if (!S.active) return;
+  const int k = S.k;
+  double* H = hess + (size_t)i * gm_stride(m);
+  double* cs = H + (size_t)(m + 1) * m;
+  double* sn = cs + m;
+  double* g = sn + m;
+  const double* hb = hbuf + (size_t)i * hs;
+  if (k == 0) g[0] = S.bnorm;  // cold start: the residual is the right-hand side
+  for (int r = 0; r <= k; ++r) H[r * m + k] = hb[r] + hb[m + 1 + r];
+  const double hn = sqrt(fmax(0.0, hb[2 * (m + 1)]));
+  H[(k + 1) * m + k] = hn;
+  for (int r = 0; r < k; ++r) {
+    const double t0 = cs[r] * H[r * m + k] + sn[r] * H[(r + 1) * m + k];
+    H[(r + 1) * m + k] = -sn[r] * H[r * m + k] + cs[r] * H[(r + 1) * m + k];
+    H[r * m + k] = t0;
+  }
+  const double den = sqrt(H[k * m + k] * H[k * m + k] + hn * hn);
+  S.its += 1;
+  if (!(den > 0.0) || !isfinite(den) || !isfinite(hn)) {
+    S.err = 1;
+    S.active = 0;
+    sys[i] = S;
+    return;
+  }
+  cs[k] = H[k * m + k] / den;
+  sn[k] = H[(k + 1) * m + k] / den;
+  H[k * m + k] = den;
+  H[(k + 1) * m + k] = 0.0;
+  g[k + 1] = -sn[k] * g[k];
+  g[k] = cs[k] * g[k];
+  S.relres = fabs(g[k + 1]) / S.bnorm;
+  const bool conv = fabs(g[k + 1]) <= S.tol * S.bnorm || hn == 0.0;
+  const bool full = (k + 1 == m) || S.its >= S.max_iter;
+  S.hn = hn;
+  if (!conv && !full) {
+    S.inv_hn = 1.0 / hn;
+    S.k = k + 1;
+  } else {
+    S.active = 0;
+    S.conv = conv ? 1 : 0;
+  }
+  sys[i] = S;
+}
+
+// w *= s for every segment whose system is still active (segmented, elementwise).
+__global__ __launch_bounds__(256) void k_scale_multi(const ScaleDesc* __restrict__ d, int nd) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const ScaleDesc D = d[find_seg(d, nd, g)];
+  const long e = g - D.start;
+  if (e < 0 || e >= D.len || (D.live && !*D.live)) return;
+  D.w[e] *= *D.s;
 }
 
 // ------------------------------------------------------------- launchers
@@ -1185,5 +1255,11 @@ void launch_dots_multi(hipStream_t s, const DotDesc* d, int nd, int nvec_total, 
 }
 void launch_combo_multi(hipStream_t s, const ComboDesc* d, int nd, int total) {
   if (total > 0) hipLaunchKernelGGL(k_combo_multi, dim3(nblk2(total)), dim3(256), 0, s, d, nd);
+}
+void launch_gmres_step(hipStream_t s, GmSys* sys, double* hess, const double* hbuf, int hs, int m, int ns) {
+  if (ns > 0) hipLaunchKernelGGL(k_gmres_step, dim3(nblk2(ns, 64)), dim3(64), 0, s, sys, hess, hbuf, hs, m, ns);
+}
+void launch_scale_multi(hipStream_t s, const ScaleDesc* d, int nd, int total) {
+  if (total > 0) hipLaunchKernelGGL(k_scale_multi, dim3(nblk2(total)), dim3(256), 0, s, d, nd);
 }
 }  // namespace bipqn

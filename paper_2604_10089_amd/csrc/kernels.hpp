@@ -25,6 +25,7 @@ struct FarDesc {
   double* part;
   int n, M, N, spc, ntb, item0;
   double scale;
+  const int* live;  // null, or a flag: 0 = the segment's system is done (its blocks exit)
 };
 
 // Segment descriptors of the multi-suspension kernels; `start` is the first
@@ -36,6 +37,7 @@ struct GemmDesc {
   double* C;
   long rbs;
   int R, Cn, K, lda, ldb, rb, ldc, tr, start;
+  const int* live;  // null, or a flag: 0 = the segment's system is done (its blocks exit)
 };
 struct PackDesc {
   const double* q;
@@ -43,6 +45,7 @@ struct PackDesc {
   const double* w;
   void* src;
   int n, N, start;
+  const int* live;  // null, or a flag: 0 = the segment's system is done (its blocks exit)
 };
 struct NearDesc {
   const double* ctr;
@@ -55,6 +58,7 @@ struct NearDesc {
   double* part;
   double scale;
   int n, M, N, nup, p, L, nch, start;
+  const int* live;  // null, or a flag: 0 = the segment's system is done (its blocks exit)
 };
 struct MomDesc {
   const double* q;
@@ -62,6 +66,7 @@ struct MomDesc {
   const double* w;
   double* mom;
   int n, N, start;
+  const int* live;  // null, or a flag: 0 = the segment's system is done (its blocks exit)
 };
 struct CombDesc {
   const double* q;
@@ -74,6 +79,7 @@ struct CombDesc {
   double* y;
   double a;
   int nchunks, n, N, start;
+  const int* live;  // null, or a flag: 0 = the segment's system is done (its blocks exit)
 };
 struct DotDesc {
   const double* V;
@@ -82,6 +88,7 @@ struct DotDesc {
   double* out;
   long ldv, len;
   int start;
+  const int* live;  // null, or a flag: 0 = the segment's system is done (its blocks exit)
 };
 struct ComboDesc {
   double* w;
@@ -90,9 +97,35 @@ struct ComboDesc {
   double alpha, beta;
   long ldv, len;
   int nvec, start;
+  const int* live;  // null, or a flag: 0 = the segment's system is done (its blocks exit)
+};
+
+// Device state of one system of the graph-captured batched GMRES (see k_gmres_step).
+struct GmSys {
+  int active;   // 1 while the cycle runs; cleared when it converges or fills
+  int k;        // current Arnoldi index
+  int its;      // iterations of this solve
+  int conv;     // 1 if the last residual estimate met the tolerance
+  int err;      // 1 = non-finite value or breakdown
+  int max_iter;
+  double bnorm, tol, hn, inv_hn, relres;
+};
+// Per system: Hessenberg (m+1) x m row-major, then cs [m], sn [m], g [m+1] (stride gm_stride(m)).
+__host__ __device__ constexpr long gm_stride(int m) { return (long)(m + 1) * m + 3L * m + 1; }
+struct ScaleDesc {
+  double* w;
+  const double* s;   // device scale factor
+  const int* live;
+  long len;
+  int start;
 };
 
 void launch_gemm64_multi(hipStream_t s, const GemmDesc* d, int nd, int nblocks);
+// One Givens step of GMRES for every active system of a batch at Arnoldi index j: the
+// Hessenberg column from the CGS2 dot products in hbuf (system i at hbuf + i hs: pass 1
+// [m+1], pass 2 [m+1], |w|^2), the rotations, the residual estimate and the end test.
+void launch_gmres_step(hipStream_t s, GmSys* sys, double* hess, const double* hbuf, int hs, int m, int ns);
+void launch_scale_multi(hipStream_t s, const ScaleDesc* d, int nd, int total);
 void launch_pack_multi(hipStream_t s, const PackDesc* d, int nd, int total, int fp32);
 void launch_near_multi(hipStream_t s, const NearDesc* d, int nd, int nblocks);
 void launch_moments_multi(hipStream_t s, const MomDesc* d, int nd, int nblocks);
