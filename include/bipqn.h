@@ -218,6 +218,17 @@ pqn_status pqn_nc_velocity(pqn_ctx* ctx, double* UO, int32_t fidelity, pqn_mvp_s
  * PQN_ERR_INVALID with *n_out set to the number needed. */
 pqn_status pqn_find_contacts(pqn_ctx* ctx, double delta, int32_t cap, int32_t* n_out, int32_t* pairs, double* gaps);
 
+/* pqn_find_contacts for callers that cannot allocate device memory during the call
+ * (serving loops, harnesses that forbid allocation): same arguments, results and errors,
+ * but the kernel's count and list are staged in a fixed device array of the library
+ * (one per device, about 0.5 MB, held until the process ends) instead of context buffers;
+ * no device memory is allocated or freed. At most 32768 contacts: a configuration with
+ * more gives PQN_ERR_INVALID with *n_out set to the count. Every call on one device
+ * shares that device's array: calls that overlap on one device (several host threads,
+ * or contexts on different streams) race and must be serialised by the caller. */
+pqn_status pqn_find_contacts_noalloc(pqn_ctx* ctx, double delta, int32_t cap, int32_t* n_out, int32_t* pairs,
+                                     double* gaps);
+
 /* One LCP product Ax = D^T M D x (eq. (defAandb)); pairs [n][2] (i, j), x, Ax [n]. */
 pqn_status pqn_lcp_apply(pqn_ctx* ctx, int32_t n, const int32_t* pairs, const double* x, double* Ax, int32_t fidelity);
 

@@ -142,6 +142,7 @@ def lib():
         'pqn_mobility_apply_multi_dev': (C.c_int, [V, C.c_int32, V, V, C.c_int32, _P(MvpStats)]),
         'pqn_nc_velocity': (C.c_int, [V, _D, C.c_int32, _P(MvpStats)]),
         'pqn_find_contacts': (C.c_int, [V, C.c_double, C.c_int32, _I, _I, _D]),
+        'pqn_find_contacts_noalloc': (C.c_int, [V, C.c_double, C.c_int32, _I, _I, _D]),
         'pqn_lcp_apply': (C.c_int, [V, C.c_int32, _I, _D, _D, C.c_int32]),
         'pqn_lcp_solve': (C.c_int, [V, C.c_int32, _I, _D, _D, C.c_int32, _P(LcpOpts), _P(LcpStats)]),
         'pqn_lcp_solve_dev': (C.c_int, [V, C.c_int32, V, V, V, C.c_int32, _P(LcpOpts), _P(LcpStats)]),

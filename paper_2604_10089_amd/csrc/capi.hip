@@ -122,6 +122,7 @@ pqn_status pqn_create(const pqn_config_desc* desc, const double* centers, const 
     HIPCHK(hipGetDeviceCount(&ndev));
     if (c.device < 0 || c.device >= ndev) return fail(PQN_ERR_DEVICE, "no such HIP device");
     HIPCHK(hipSetDevice(c.device));
+    contact_scratch_setup(c.device);  // device address of pqn_find_contacts_noalloc's staging
     std::unique_ptr<pqn_ctx_impl> ctx = make_context(c, centers, janus_axes, (hipStream_t)c.stream);
     *out = static_cast<pqn_ctx*>(ctx.release());
     return PQN_OK;
@@ -517,6 +518,18 @@ pqn_status pqn_find_contacts(pqn_ctx* ctx, double delta, int32_t cap, int32_t* n
     if (n > cap) return fail(PQN_ERR_INVALID, "pqn_find_contacts: cap too small");
     lcp_copy_contacts(*ctx, n, pairs, gaps);
     return PQN_OK;
+  });
+}
+
+pqn_status pqn_find_contacts_noalloc(pqn_ctx* ctx, double delta, int32_t cap, int32_t* n_out, int32_t* pairs,
+                                     double* gaps) {
+  return guarded([&]() -> pqn_status {
+    TraceRange trace_range("pqn_find_contacts_noalloc");
+    if (is_batch(ctx)) return fail(PQN_ERR_STATE, "pqn_find_contacts_noalloc needs a single-suspension context");
+    if (!ctx || !n_out || (cap > 0 && (!pairs || !gaps)) || cap < 0)
+      return fail(PQN_ERR_INVALID, "pqn_find_contacts_noalloc: bad argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    return lcp_find_contacts_noalloc(*ctx, delta, cap, n_out, pairs, gaps);
   });
 }
 

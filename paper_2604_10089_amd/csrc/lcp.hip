@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 namespace bipqn {
 
@@ -218,6 +220,66 @@ __global__ __launch_bounds__(kT) void k_contacts(const double* __restrict__ ctr,
     __syncthreads();
   }
   if (threadIdx.x == 0) *count = base;
+}
+
+// --------------------------------------------- contacts without allocation
+//
+// pqn_find_contacts_noalloc stages the contact kernel's count and list in this
+// file-scope device array instead of buffers of the context (one copy per device,
+// held until the process ends). Layout: the count at byte 0; gaps (double) from
+// byte 256; pairs (two int) after the gaps. Host code never passes the array's name
+// to a kernel or a copy: it uses the per-device address resolved at set-up.
+constexpr int kNoAllocContacts = 32768;
+constexpr size_t kScratchGaps = 256;
+constexpr size_t kScratchPairs = kScratchGaps + sizeof(double) * kNoAllocContacts;
+constexpr size_t kScratchBytes = kScratchPairs + 2 * sizeof(int) * kNoAllocContacts;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Resolve the array's address on `device` (current on the calling thread), once.
+void contact_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) throw Error(PQN_ERR_DEVICE, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Error(PQN_ERR_DEVICE, "hipGetSymbolAddress returned a null address for the contact staging");
+  g_scratch_ptr[device] = p;
+}
+
+pqn_status lcp_find_contacts_noalloc(pqn_ctx_impl& ctx, double delta, int cap, int* n_out, int* pairs,
+                                     double* gaps) {
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (ctx.device >= 0 && ctx.device < kMaxDevices) base = g_scratch_ptr[ctx.device];
+  }
+  if (!base) throw Error(PQN_ERR_STATE, "contact staging not set up on this device");
+  unsigned char* b = static_cast<unsigned char*>(base);
+  int* count = reinterpret_cast<int*>(b);
+  double* sgaps = reinterpret_cast<double*>(b + kScratchGaps);
+  int* spairs = reinterpret_cast<int*>(b + kScratchPairs);
+  // the kernel writes the count unconditionally and at most kNoAllocContacts entries
+  hipLaunchKernelGGL(k_contacts, dim3(1), dim3(kT), 0, ctx.stream, ctx.ctr.p, ctx.M, ctx.a, delta, kNoAllocContacts,
+                     spairs, sgaps, count);
+  HIPCHK(hipGetLastError());
+  int n = 0;
+  HIPCHK(hipMemcpyAsync(&n, count, sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+  HIPCHK(hipStreamSynchronize(ctx.stream));
+  *n_out = n;
+  if (n > kNoAllocContacts)
+    throw Error(PQN_ERR_INVALID, "pqn_find_contacts_noalloc: " + std::to_string(n) +
+                                     " contacts, more than its staging holds (32768)");
+  if (n > cap) throw Error(PQN_ERR_INVALID, "pqn_find_contacts_noalloc: cap too small");
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(pairs, spairs, 2 * (size_t)n * sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+    HIPCHK(hipMemcpyAsync(gaps, sgaps, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+    HIPCHK(hipStreamSynchronize(ctx.stream));
+  }
+  return PQN_OK;
 }
 
 // FT = D x: force -x_l n_l on i, +x_l n_l on j (n_l = unit c_j - c_i), no torque.
