@@ -401,16 +401,26 @@ def main():
         kw = dict(gmres_tol=1e-8, precision='mixed', stream=stream.cuda_stream, side_stream=not args.serial)
         if args.tpt:
             kw['tpt'] = args.tpt
-        with binding.BatchContext(inst, **kw) as bc:
+        reps = 3
+        # GMRES iterations replayed from captured graphs (device-side Givens), and the same
+        # product with the eager lockstep loop (host Givens, one readback per iteration)
+        with binding.BatchContext(inst, graphs=True, **kw) as bc:
             batch_shape = bc.far_shape
             bc.mobility_apply(FTb)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            reps = 3
             for _ in range(reps):
                 Ubm, bst = bc.mobility_apply(FTb)
             torch.cuda.synchronize()
             tb = (time.perf_counter() - t0) / reps
+        with binding.BatchContext(inst, **kw) as bc:
+            bc.mobility_apply(FTb)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                bc.mobility_apply(FTb)
+            torch.cuda.synchronize()
+            tb_eager = (time.perf_counter() - t0) / reps
         with binding.BatchContext(inst, **dict(kw, precision='fp64')) as bc:
             bc.mobility_apply(FTb)
             torch.cuda.synchronize()
@@ -433,6 +443,8 @@ def main():
             ctx_b.close()
         batch_info = dict(instances=len(inst), nodes=int(sum(ci.shape[0] * nti * npi for ci, nti, npi in inst)),
                           batched_sec=round(tb, 4), mvps_batched=round(len(inst) / tb, 2),
+                          graph_launches=bst['graph_launches'], eager_sec=round(tb_eager, 4),
+                          mvps_batched_eager=round(len(inst) / tb_eager, 2),
                           mvps_batched_fp64=round(len(inst) / tb64, 2), mixed_rel_err_vs_fp64=err_b,
                           one_by_one_sec=round(ts, 4), mvps_one_by_one=round(len(inst) / ts, 2),
                           speedup=round(ts / tb, 3), lockstep_iterations=bst['n_far'], far_layout=batch_shape)

@@ -181,11 +181,17 @@ typedef struct {
   pqn_lcp_stats lcp;
   int32_t gmres_iters_nc;   /* Krylov iterations of the U_nc solve */
   double t_total_ms;
+  /* wall time of each stage of the step (the stream is synchronised between stages) */
+  double t_contacts_ms;     /* contact search, eq. (collisional-set) */
+  double t_nc_ms;           /* slip-driven solve U_nc */
+  double t_lcp_ms;          /* b = Phi/dt + D^T U_nc and the LCP solve */
+  double t_update_ms;       /* Euler update of centres and axes, new pair classes and near lists */
 } pqn_step_stats;
 
 /* Create a context for M spheres (centers [M][3], janus_axes [M][3] unit vectors;
  * axes may be NULL = no slip). Builds the grids, the singular self blocks (FP64,
- * host) and allocates device memory. */
+ * host) and allocates device memory. Set-up, not an operation of the paper: the
+ * suspension's configuration (Sec. 3) and its discretisation (Sec. 5.1). */
 pqn_status pqn_create(const pqn_config_desc* desc, const double* centers, const double* janus_axes, pqn_ctx** out);
 pqn_status pqn_destroy(pqn_ctx* ctx);
 
@@ -262,16 +268,28 @@ pqn_status pqn_step(pqn_ctx* ctx, double dt, double delta, int32_t solver, const
                     pqn_step_stats* stats);
 
 /* Batched independent suspensions of uneven size (one descriptor and one [M_b][3]
- * centre array per suspension; janus_axes may be NULL). The suspensions must share
- * precision, restart length, refinement, device and targets_per_thread; the first
- * descriptor's stream is used for all. The returned context accepts only the
- * pqn_batch_* calls and pqn_destroy. */
+ * centre array per suspension; janus_axes may be NULL). Not an operation of the paper:
+ * many instances of its mobility product (Sec. 2, eq. (mobility)) solved together. The
+ * suspensions must share precision, restart length, refinement, device and
+ * targets_per_thread; the first descriptor's stream and use_graphs are used for all
+ * (use_graphs = 1: the first GMRES cycle of all suspensions is replayed from captured
+ * graphs, one per Arnoldi index, with the Givens rotations and end tests on the device).
+ * The returned context accepts only the pqn_batch_* calls and pqn_destroy. */
 pqn_status pqn_batch_create(int32_t n_inst, const pqn_config_desc* descs, const double* const* centers,
                             const double* const* janus_axes, pqn_ctx** out);
 /* One mobility product per suspension (FT[b], UO[b]: [M_b][6] host arrays), all GMRES
  * iterations in lockstep, every far pair sum of an iteration in one launch ordered by
- * decreasing cost. stats: aggregate over the suspensions. */
-pqn_status pqn_batch_mobility_apply(pqn_ctx* ctx, const double* const* FT, double* const* UO, pqn_mvp_stats* stats);
+ * decreasing cost. stats (may be NULL): aggregate over the suspensions; per_inst (may be
+ * NULL): [n_inst] statistics of each suspension (gmres_iters and matvecs of its own
+ * solve, converged, rel_residual; timings only in stats). */
+pqn_status pqn_batch_mobility_apply(pqn_ctx* ctx, const double* const* FT, double* const* UO, pqn_mvp_stats* stats,
+                                    pqn_mvp_stats* per_inst);
+/* Same with FT_dev[b], UO_dev[b] device arrays [M_b][6] of the context's device (the
+ * pointer arrays themselves on the host); returns when every UO_dev[b] is written. A
+ * non-finite force makes that suspension's right-hand-side norm non-finite:
+ * PQN_ERR_NUMERIC. */
+pqn_status pqn_batch_mobility_apply_dev(pqn_ctx* ctx, const double* const* FT_dev, double* const* UO_dev,
+                                        pqn_mvp_stats* stats, pqn_mvp_stats* per_inst);
 
 /* Operator-level entry points (stage-by-stage checks of the discrete BIE).
  * pqn_bie_apply: y = (1/2 I + D + P) q for q, y [3][N] host arrays.

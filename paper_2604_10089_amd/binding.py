@@ -94,7 +94,8 @@ class LcpStats(C.Structure):
 
 class StepStats(C.Structure):
     _fields_ = [('n_contacts', C.c_int32), ('n_active', C.c_int32), ('lcp', LcpStats),
-                ('gmres_iters_nc', C.c_int32), ('t_total_ms', C.c_double)]
+                ('gmres_iters_nc', C.c_int32), ('t_total_ms', C.c_double), ('t_contacts_ms', C.c_double),
+                ('t_nc_ms', C.c_double), ('t_lcp_ms', C.c_double), ('t_update_ms', C.c_double)]
 
 
 def _struct_dict(s):
@@ -155,7 +156,8 @@ def lib():
         'pqn_host_self_block': (C.c_int, [C.c_int32, C.c_int32, C.c_double, _D, _D, _D]),
         'pqn_mobility_apply_multi': (C.c_int, [V, C.c_int32, _D, _D, C.c_int32, _P(MvpStats)]),
         'pqn_batch_create': (C.c_int, [C.c_int32, _P(ConfigDesc), _P(_D), _P(_D), _P(V)]),
-        'pqn_batch_mobility_apply': (C.c_int, [V, _P(_D), _P(_D), _P(MvpStats)]),
+        'pqn_batch_mobility_apply': (C.c_int, [V, _P(_D), _P(_D), _P(MvpStats), _P(MvpStats)]),
+        'pqn_batch_mobility_apply_dev': (C.c_int, [V, _P(V), _P(V), _P(MvpStats), _P(MvpStats)]),
         'pqn_last_error': (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -295,14 +297,28 @@ class BatchContext:
     def __exit__(self, *a):
         self.close()
 
-    def mobility_apply(self, FTs):
+    def mobility_apply(self, FTs, per_instance=False):
         F = [_f64(f, (m, 6)) for f, m in zip(FTs, self.Ms)]
         U = [np.zeros((m, 6)) for m in self.Ms]
         fp = (_D * len(F))(*[_dptr(f) for f in F])
         up = (_D * len(U))(*[_dptr(u) for u in U])
         st = MvpStats()
-        status = _check(lib().pqn_batch_mobility_apply(self.h, fp, up, C.byref(st)))
-        return U, dict(_struct_dict(st), status=status)
+        per = (MvpStats * len(F))()
+        status = _check(lib().pqn_batch_mobility_apply(self.h, fp, up, C.byref(st), per))
+        out = dict(_struct_dict(st), status=status)
+        if per_instance:
+            out['per_instance'] = [_struct_dict(p) for p in per]
+        return U, out
+
+    def mobility_apply_dev(self, FT_ptrs, UO_ptrs):
+        """Device arrays [M_b][6] per suspension (integer device pointers)."""
+        n = len(self.Ms)
+        fp = (C.c_void_p * n)(*FT_ptrs)
+        up = (C.c_void_p * n)(*UO_ptrs)
+        st = MvpStats()
+        per = (MvpStats * n)()
+        status = _check(lib().pqn_batch_mobility_apply_dev(self.h, fp, up, C.byref(st), per))
+        return dict(_struct_dict(st), status=status, per_instance=[_struct_dict(p) for p in per])
 
 
 def tuned_shape(precision, K, M, n):

@@ -175,50 +175,88 @@ pqn_status pqn_batch_create(int32_t n_inst, const pqn_config_desc* descs, const 
   });
 }
 
-pqn_status pqn_batch_mobility_apply(pqn_ctx* ctx, const double* const* FT, double* const* UO, pqn_mvp_stats* stats) {
+// One mobility product per suspension of a batch context; FT / UO are host arrays
+// (dev = false) or device arrays (dev = true) of [M_b][6] per suspension.
+static pqn_status batch_apply_common(pqn_ctx* ctx, const double* const* FT, double* const* UO, bool dev,
+                                     pqn_mvp_stats* stats, pqn_mvp_stats* per_inst) {
+  Timer tm;
+  const int nb = (int)ctx->children.size();
+  for (int b = 0; b < nb; ++b) {
+    if (!FT[b] || !UO[b]) return fail(PQN_ERR_INVALID, "pqn_batch_mobility_apply: NULL force/velocity array");
+    if (!dev)
+      for (int k = 0; k < 6 * ctx->children[b]->M; ++k)
+        if (!std::isfinite(FT[b][k])) return fail(PQN_ERR_NUMERIC, "non-finite force/torque");
+  }
+  ctx->n_matvec = 0;
+  ctx->n_graph_launch = 0;
+  ctx->n_far = 0;
+  std::vector<SysRef> sys;
+  for (int b = 0; b < nb; ++b) {
+    pqn_ctx_impl& c = *ctx->children[b];
+    const double* ft = FT[b];
+    if (!dev) {
+      HIPCHK(hipMemcpyAsync(c.FT.p, FT[b], 6 * (size_t)c.M * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+      ft = c.FT.p;
+    }
+    SysBuf& sb = c.hi.sb(0);
+    launch_rhs(ctx->stream, c.ctr.p, ft, nullptr, c.hi.off.p, c.hi.n, c.M, c.hi.N, c.a, c.mu, c.cfg.slip_speed,
+               sb.rhs.p);
+    sys.push_back(SysRef{&c, &c.hi, 0, sb.rhs.p, sb.x.p, c.hi.tol});
+  }
+  pqn_mvp_stats st{};
+  std::vector<int> its_per;
+  ctx->solve_lockstep(sys, &st, &its_per);
+  for (int b = 0; b < nb; ++b) {
+    pqn_ctx_impl& c = *ctx->children[b];
+    Work& w = c.hi.wk(0);
+    double* uo = dev ? UO[b] : c.UO.p;
+    launch_moments(ctx->stream, c.hi.sb(0).x.p, c.hi.off.p, c.hi.w.p, c.hi.n, c.M, c.hi.N, w.mom.p);
+    launch_rigid_velocity(ctx->stream, w.mom.p, c.M, c.a, uo);
+    if (!dev)
+      HIPCHK(hipMemcpyAsync(UO[b], c.UO.p, 6 * (size_t)c.M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  st.t_far_ms = ctx->end_far_timing();
+  stage_stats(*ctx, st);
+  st.matvecs = ctx->n_matvec;
+  st.n_far = ctx->n_far;
+  st.graph_launches = ctx->n_graph_launch;
+  st.t_total_ms = tm.ms();
+  if (stats) *stats = st;
+  if (per_inst)
+    for (int b = 0; b < nb; ++b) {
+      pqn_mvp_stats pi{};
+      pi.gmres_iters = its_per[b];
+      pi.matvecs = its_per[b];
+      pi.converged = sys[b].conv ? 1 : 0;
+      pi.rel_residual = sys[b].relres;
+      pi.refine_sweeps = st.refine_sweeps;
+      per_inst[b] = pi;
+    }
+  return st.converged ? PQN_OK : PQN_WARN_NOT_CONVERGED;
+}
+
+pqn_status pqn_batch_mobility_apply(pqn_ctx* ctx, const double* const* FT, double* const* UO, pqn_mvp_stats* stats,
+                                    pqn_mvp_stats* per_inst) {
   return guarded([&]() -> pqn_status {
     AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
     TraceRange trace_range("pqn_batch_mobility_apply");
     if (!ctx || !FT || !UO) return fail(PQN_ERR_INVALID, "pqn_batch_mobility_apply: NULL argument");
     if (!ctx->is_batch) return fail(PQN_ERR_STATE, "pqn_batch_mobility_apply needs a batch context");
     HIPCHK(hipSetDevice(ctx->device));
-    Timer tm;
-    const int nb = (int)ctx->children.size();
-    for (int b = 0; b < nb; ++b) {
-      if (!FT[b] || !UO[b]) return fail(PQN_ERR_INVALID, "pqn_batch_mobility_apply: NULL force/velocity array");
-      for (int k = 0; k < 6 * ctx->children[b]->M; ++k)
-        if (!std::isfinite(FT[b][k])) return fail(PQN_ERR_NUMERIC, "non-finite force/torque");
-    }
-    ctx->n_matvec = 0;
-    ctx->n_graph_launch = 0;
-    ctx->n_far = 0;
-    std::vector<SysRef> sys;
-    for (int b = 0; b < nb; ++b) {
-      pqn_ctx_impl& c = *ctx->children[b];
-      HIPCHK(hipMemcpyAsync(c.FT.p, FT[b], 6 * (size_t)c.M * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-      SysBuf& sb = c.hi.sb(0);
-      launch_rhs(ctx->stream, c.ctr.p, c.FT.p, nullptr, c.hi.off.p, c.hi.n, c.M, c.hi.N, c.a, c.mu, c.cfg.slip_speed,
-                 sb.rhs.p);
-      sys.push_back(SysRef{&c, &c.hi, 0, sb.rhs.p, sb.x.p, c.hi.tol});
-    }
-    pqn_mvp_stats st{};
-    ctx->solve_lockstep(sys, &st);
-    for (int b = 0; b < nb; ++b) {
-      pqn_ctx_impl& c = *ctx->children[b];
-      Work& w = c.hi.wk(0);
-      launch_moments(ctx->stream, c.hi.sb(0).x.p, c.hi.off.p, c.hi.w.p, c.hi.n, c.M, c.hi.N, w.mom.p);
-      launch_rigid_velocity(ctx->stream, w.mom.p, c.M, c.a, c.UO.p);
-      HIPCHK(hipMemcpyAsync(UO[b], c.UO.p, 6 * (size_t)c.M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    }
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    st.t_far_ms = ctx->end_far_timing();
-    stage_stats(*ctx, st);
-    st.matvecs = ctx->n_matvec;
-    st.n_far = ctx->n_far;
-    st.graph_launches = ctx->n_graph_launch;
-    st.t_total_ms = tm.ms();
-    if (stats) *stats = st;
-    return st.converged ? PQN_OK : PQN_WARN_NOT_CONVERGED;
+    return batch_apply_common(ctx, FT, UO, false, stats, per_inst);
+  });
+}
+
+pqn_status pqn_batch_mobility_apply_dev(pqn_ctx* ctx, const double* const* FT_dev, double* const* UO_dev,
+                                        pqn_mvp_stats* stats, pqn_mvp_stats* per_inst) {
+  return guarded([&]() -> pqn_status {
+    AllocScope alloc_scope(ctx ? &ctx->dev_alloc : nullptr);
+    TraceRange trace_range("pqn_batch_mobility_apply_dev");
+    if (!ctx || !FT_dev || !UO_dev) return fail(PQN_ERR_INVALID, "pqn_batch_mobility_apply_dev: NULL argument");
+    if (!ctx->is_batch) return fail(PQN_ERR_STATE, "pqn_batch_mobility_apply_dev needs a batch context");
+    HIPCHK(hipSetDevice(ctx->device));
+    return batch_apply_common(ctx, FT_dev, UO_dev, true, stats, per_inst);
   });
 }
 

@@ -11,10 +11,13 @@ namespace bipqn {
 constexpr int kMultiDotBlocks = 16;  // reduction blocks per vector in the segmented dot kernel
 
 
-// One GEMM problem of a segmented launch: C(r, col) = sum_k A[r lda + k] B[col ldb + k].
+// One GEMM problem of a segmented launch: C(r, col) = sum_k A[r lda + k] B[col ldb + k],
+// stored at C[(r / rb) rbs + (r % rb) rs + (col / cb) cbs + (col % cb) ldc] (cb = 0: no
+// column blocks).
 static void push_gemm(std::vector<GemmDesc>& v, int& blocks, int R, int Cn, int K, const double* A, int lda,
-                      const double* B, int ldb, double* C, int rb, long rbs, int ldc) {
-  GemmDesc d{A, B, C, rbs, R, Cn, K, lda, ldb, rb, ldc, (R + 31) / 32, blocks};
+                      const double* B, int ldb, double* C, int rb, long rbs, int ldc, int rs = 1, int cb = 0,
+                      long cbs = 0) {
+  GemmDesc d{A, B, C, rbs, R, Cn, K, lda, ldb, rb, ldc, (R + 31) / 32, blocks, rs, cb > 0 ? cb : Cn, cbs};
   blocks += d.tr * ((Cn + 31) / 32);
   v.push_back(d);
 }
@@ -270,6 +273,46 @@ static double* group_qup(MvGroup& gr, bool close = false) {
   return buf.p;
 }
 
+// Harmonic coefficients of a group's K densities, [M][3K][L] (row 3r + c: density r,
+// component c), in the work buffer of the group's first slot (grown on first use with
+// more densities).
+static double* group_coef(MvGroup& gr) {
+  Level& lv = *gr.lv;
+  DevArray<double>& buf = lv.wk(gr.slot[0]).coef;
+  const size_t need = (size_t)3 * gr.K * lv.M * lv.L;
+  if (buf.count < need) {
+    HIPCHK(hipDeviceSynchronize());  // the old buffer may still be read by queued work
+    buf.alloc(need);
+  }
+  return buf.p;
+}
+
+// The GEMMs of one group's densities (slot r of density r, input in[r]): coefficients
+// coef = T q into the group's [M][3K][L] buffer (coefficient GEMM list ga); the singular
+// self interaction on them, one partial per source component, and the densities on the
+// upsampled grids (one GEMM per grid for all 3K components, stored node-interleaved
+// [M][nup][3K] so that consecutive columns are consecutive addresses) (list gb).
+static void push_group_gemms(Level& lv, int K, const int* slot, const double* const* in, double* coef, double* qup,
+                             double* qup2, const int* live_flag, std::vector<GemmDesc>& ga, int& nga,
+                             std::vector<GemmDesc>& gb, int& ngb) {
+  const int n = lv.n, N = lv.N, L = lv.L, M = lv.M, C = 3 * K;
+  const size_t a0 = ga.size(), b0 = gb.size();
+  for (int r = 0; r < K; ++r) {
+    Work& w = lv.wk(slot[r]);
+    for (int comp = 0; comp < 3; ++comp) {
+      double* cb = coef + (size_t)(3 * r + comp) * L;
+      push_gemm(ga, nga, L, M, n, lv.T.p, n, in[r] + (size_t)comp * N, n, cb, L, 0, C * L);
+      push_gemm(gb, ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, cb, C * L, w.selfo.p + (size_t)comp * 3 * N, n, N,
+                n);
+    }
+  }
+  if (qup) push_gemm(gb, ngb, lv.nup, C * M, L, lv.Yup.p, L, coef, L, qup, lv.nup, 0, 1, C, C, (long)lv.nup * C);
+  if (qup2)
+    push_gemm(gb, ngb, lv.nup2, C * M, L, lv.Yup2.p, L, coef, L, qup2, lv.nup2, 0, 1, C, C, (long)lv.nup2 * C);
+  for (size_t e = a0; e < ga.size(); ++e) ga[e].live = live_flag;
+  for (size_t e = b0; e < gb.size(); ++e) gb[e].live = live_flag;
+}
+
 void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
   hipStream_t s = stream;
   const int prec = precision == PQN_MIXED ? 1 : 0;
@@ -299,31 +342,15 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
   for (MvGroup& gr : groups) {
     Level& lv = *gr.lv;
     pqn_ctx_impl& c = *gr.c;
-    const int n = lv.n, N = lv.N, L = lv.L, nup = lv.nup, M = lv.M;
+    const int n = lv.n, N = lv.N;
     QPtrs qp{};
     std::vector<GemmDesc> ga, gb;
     int nga = 0, ngb = 0;
     double* qup = c.n_near > 0 ? group_qup(gr) : nullptr;
     double* qup2 = c.n_near2 > 0 ? group_qup(gr, true) : nullptr;
-    const int C = 3 * gr.K;
-    for (int r = 0; r < gr.K; ++r) {
-      Work& w = lv.wk(gr.slot[r]);
-      for (int comp = 0; comp < 3; ++comp) {
-        // harmonic coefficients of every sphere's density: coef = T q
-        push_gemm(ga, nga, L, M, n, lv.T.p, n, gr.in[r] + (size_t)comp * N, n, w.coef.p + (size_t)comp * M * L, L, 0,
-                  L);
-        // singular self interaction on the coefficients, one partial per source component
-        push_gemm(gb, ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, w.coef.p + (size_t)comp * M * L, L,
-                  w.selfo.p + (size_t)comp * 3 * N, n, N, n);
-        if (qup)  // density on the upsampled grid of every sphere, interleaved: qup[j][f][3r + comp] = (Yup coef)
-          push_gemm(gb, ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L, qup + 3 * r + comp, 1, C,
-                    nup * C);
-        if (qup2)  // the same on the close-pair grid
-          push_gemm(gb, ngb, lv.nup2, M, L, lv.Yup2.p, L, w.coef.p + (size_t)comp * M * L, L, qup2 + 3 * r + comp,
-                    1, C, lv.nup2 * C);
-      }
-      qp.p[r] = gr.in[r];
-    }
+    double* coef = group_coef(gr);
+    push_group_gemms(lv, gr.K, gr.slot, gr.in, coef, qup, qup2, nullptr, ga, nga, gb, ngb);
+    for (int r = 0; r < gr.K; ++r) qp.p[r] = gr.in[r];
     DescPack dp;
     const size_t oa = dp.add(ga), ob = dp.add(gb);
     char* base = push_desc_pack(dp.host, sa, *dtab);
@@ -386,13 +413,9 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
 void pqn_ctx_impl::side_work(MvGroup& gr, hipStream_t st) {
   Level& lv = *gr.lv;
   pqn_ctx_impl& c = *gr.c;
-  QPtrs cf{};
   OPtrs np{};
-  for (int r = 0; r < gr.K; ++r) {
-    Work& w = lv.wk(gr.slot[r]);
-    cf.p[r] = w.coef.p;
-    np.p[r] = w.near_part.p;
-  }
+  for (int r = 0; r < gr.K; ++r) np.p[r] = lv.wk(gr.slot[r]).near_part.p;
+  const double* cf = lv.wk(gr.slot[0]).coef.p;  // the group's [M][3K][L] coefficients
   const double* qup = lv.wk(gr.slot[0]).qup.p;
   // (stage events are recorded only while profiling, when st is the main stream)
   stage_begin(kStageNear);
@@ -440,21 +463,8 @@ BatchOpTables pqn_ctx_impl::batch_op_tables(std::vector<MvGroup>& groups, int pr
     pqn_ctx_impl& c = *gr.c;
     Work& w = lv.wk(gr.slot[0]);
     const int n = lv.n, N = lv.N, L = lv.L, nup = lv.nup, M = lv.M;
-    const size_t a0 = ga.size(), b0 = gb.size();
-    for (int comp = 0; comp < 3; ++comp) {
-      push_gemm(ga, t.nga, L, M, n, lv.T.p, n, gr.in[0] + (size_t)comp * N, n, w.coef.p + (size_t)comp * M * L, L, 0,
-                L);
-      push_gemm(gb, t.ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, w.coef.p + (size_t)comp * M * L, L,
-                w.selfo.p + (size_t)comp * 3 * N, n, N, n);
-      if (c.n_near > 0)  // interleaved [M][nup][3]
-        push_gemm(gb, t.ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup.p + comp, 1, 3,
-                  nup * 3);
-      if (c.n_near2 > 0)
-        push_gemm(gb, t.ngb, lv.nup2, M, L, lv.Yup2.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup2.p + comp, 1, 3,
-                  lv.nup2 * 3);
-    }
-    for (size_t e = a0; e < ga.size(); ++e) ga[e].live = lf;
-    for (size_t e = b0; e < gb.size(); ++e) gb[e].live = lf;
+    push_group_gemms(lv, 1, gr.slot, gr.in, w.coef.p, c.n_near > 0 ? w.qup.p : nullptr,
+                     c.n_near2 > 0 ? w.qup2.p : nullptr, lf, ga, t.nga, gb, t.ngb);
     pk.push_back(PackDesc{gr.in[0], lv.off.p, lv.w.p, lv.src.p, n, N, t.npk, lf});
     t.npk += N;
     if (c.n_near > 0) {
@@ -604,16 +614,9 @@ IterTables pqn_ctx_impl::iteration_tables(pqn_ctx_impl& c, Level& lv, int slot, 
   const int n = lv.n, N = lv.N, L = lv.L, nup = lv.nup, M = lv.M;
   std::vector<GemmDesc> ga, gb;
   IterTables t{};
-  for (int comp = 0; comp < 3; ++comp) {
-    push_gemm(ga, t.nga, L, M, n, lv.T.p, n, q + (size_t)comp * N, n, w.coef.p + (size_t)comp * M * L, L, 0, L);
-    push_gemm(gb, t.ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, w.coef.p + (size_t)comp * M * L, L,
-              w.selfo.p + (size_t)comp * 3 * N, n, N, n);
-    if (c.n_near > 0)  // interleaved [M][nup][3]
-      push_gemm(gb, t.ngb, nup, M, L, lv.Yup.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup.p + comp, 1, 3, nup * 3);
-    if (c.n_near2 > 0)
-      push_gemm(gb, t.ngb, lv.nup2, M, L, lv.Yup2.p, L, w.coef.p + (size_t)comp * M * L, L, w.qup2.p + comp, 1, 3,
-                lv.nup2 * 3);
-  }
+  const double* in[1] = {q};
+  push_group_gemms(lv, 1, &slot, in, w.coef.p, c.n_near > 0 ? w.qup.p : nullptr, c.n_near2 > 0 ? w.qup2.p : nullptr,
+                   nullptr, ga, t.nga, gb, t.ngb);
   DescPack dp;
   t.oa = dp.add(ga);
   t.ob = dp.add(gb);
@@ -644,14 +647,12 @@ void pqn_ctx_impl::iteration_launches(pqn_ctx_impl& c, Level& lv, int slot, int 
   op.p[0] = wk.far_part.p;
   launch_far(s, prec, 1, lv.tpt, lv.src.p, lv.off.p, c.ctr.p, c.cls.p, lv.n, lv.M, lv.N, lv.spc, lv.nchunks, scale,
              op);
-  QPtrs cf{};
   OPtrs np{};
-  cf.p[0] = wk.coef.p;
   np.p[0] = wk.near_part.p;
-  launch_near(s, 1, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, wk.qup.p, cf, c.near_list.p, lv.n, lv.M, lv.N,
-              lv.nup, lv.p, lv.L, scale, np);
-  launch_near(s, 1, c.n_near2, c.ctr.p, lv.off.p, lv.offup2.p, lv.shab.p, wk.qup2.p, cf, c.near_list2.p, lv.n, lv.M,
-              lv.N, lv.nup2, lv.p, lv.L, scale, np);
+  launch_near(s, 1, c.n_near, c.ctr.p, lv.off.p, lv.offup.p, lv.shab.p, wk.qup.p, wk.coef.p, c.near_list.p, lv.n, lv.M,
+              lv.N, lv.nup, lv.p, lv.L, scale, np);
+  launch_near(s, 1, c.n_near2, c.ctr.p, lv.off.p, lv.offup2.p, lv.shab.p, wk.qup2.p, wk.coef.p, c.near_list2.p, lv.n,
+              lv.M, lv.N, lv.nup2, lv.p, lv.L, scale, np);
   launch_moments(s, q, lv.off.p, lv.w.p, lv.n, lv.M, lv.N, wk.mom.p);
   launch_combine(s, q, wk.selfo.p, 3, wk.far_part.p, lv.nchunks, wk.near_part.p, c.npart.p, wk.mom.p, lv.off.p, lv.n,
                  lv.N, c.a, w);
@@ -1241,11 +1242,15 @@ void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision)
 // Solve every system in the context's precision. Mixed precision: GMRES on the
 // operator with FP32 far pair sums, then optional refinement sweeps whose
 // residual uses the FP64 operator.
-void pqn_ctx_impl::solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st) {
+void pqn_ctx_impl::solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st, std::vector<int>* its_per) {
   const int prec = cfg.precision;
   gmres_lockstep(sys, prec);
   int its = 0;
   for (SysRef& r : sys) its += r.its;
+  if (its_per) {
+    its_per->clear();
+    for (SysRef& r : sys) its_per->push_back(r.its);
+  }
   int sweeps = 0, fallback = 0;
   if (prec == PQN_MIXED && cfg.refine_sweeps > 0) {
     const int ns = (int)sys.size();
@@ -1289,6 +1294,7 @@ void pqn_ctx_impl::solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st) {
       gmres_lockstep(corr, fb ? PQN_FP64 : prec);  // corrections d for A d = rhs - A64 x
       for (size_t j = 0; j < corr.size(); ++j) {
         its += corr[j].its;
+        if (its_per) (*its_per)[owner[j]] += corr[j].its;
         launch_axpby(stream, sys[owner[j]].x, corr[j].x, 1.0, 1.0, 3L * sys[owner[j]].lv->N);
       }
     }

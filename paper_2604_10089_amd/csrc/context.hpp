@@ -350,7 +350,8 @@ struct pqn_ctx_impl {
   void gmres_batch_graph(std::vector<SysRef>& sys, int precision);
   void capture_batch_iteration(BatchGraph& bg, std::vector<SysRef>& sys, int j, int prec);
   // solve in the context's precision with optional FP64-residual refinement
-  void solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st);
+  // its_per (optional): Krylov iterations of each system, correction solves included
+  void solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st, std::vector<int>* its_per = nullptr);
   // mobility products of K force sets on one level (K <= kMaxRhs)
   void mobility_multi(Level& lv, int K, const double* const* FT_dev, const double* axes_dev,
                       double* const* UO_dev, pqn_mvp_stats* st);

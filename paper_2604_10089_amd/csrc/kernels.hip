@@ -419,9 +419,10 @@ __global__ __launch_bounds__(256) void k_far64_multi(const FarDesc* __restrict__
 constexpr int kNearWaves = 4;
 
 // Partial foot-point values: orders m = wv (mod kNearWaves) of sum_lm c_lm Y_lm(x*).
+// cj: the coefficients of the source sphere, [3K][L] (density r, component c at row 3r + c).
 template <int K>
 __device__ __forceinline__ void foot_part(int p, double ct, double st, double cp, double sp,
-                                          const double* __restrict__ shab, const QPtrs& coef, size_t jL, size_t ML,
+                                          const double* __restrict__ shab, const double* __restrict__ cj, int L,
                                           int wv, double (&f)[K][3]) {
   double pmm = sqrt(1.0 / (4.0 * kPi));
   double cm = 1.0, sm = 0.0;
@@ -446,19 +447,19 @@ __device__ __forceinline__ void foot_part(int p, double ct, double st, double cp
       const double vc = plm1 * yc;
 #pragma unroll
       for (int r = 0; r < K; ++r) {
-        const double* cx = coef.p[r] + jL + ic;
+        const double* cx = cj + (size_t)(3 * r) * L + ic;
         f[r][0] = fma(vc, cx[0], f[r][0]);
-        f[r][1] = fma(vc, cx[ML], f[r][1]);
-        f[r][2] = fma(vc, cx[2 * ML], f[r][2]);
+        f[r][1] = fma(vc, cx[L], f[r][1]);
+        f[r][2] = fma(vc, cx[2 * L], f[r][2]);
       }
       if (m > 0) {
         const double vs = plm1 * ys;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
-          const double* cx = coef.p[r] + jL + ic + 1;
+          const double* cx = cj + (size_t)(3 * r) * L + ic + 1;
           f[r][0] = fma(vs, cx[0], f[r][0]);
-          f[r][1] = fma(vs, cx[ML], f[r][1]);
-          f[r][2] = fma(vs, cx[2 * ML], f[r][2]);
+          f[r][1] = fma(vs, cx[L], f[r][1]);
+          f[r][2] = fma(vs, cx[2 * L], f[r][2]);
         }
       }
     }
@@ -470,7 +471,7 @@ template <int K>
 __device__ __forceinline__ void near_body(int pair, int chunk, const double* __restrict__ ctr,
                                           const double* __restrict__ off, const double4* __restrict__ offup,
                                           const double* __restrict__ shab, const double* __restrict__ qup,
-                                          const QPtrs& coef,
+                                          const double* __restrict__ coef,
                                           const int* __restrict__ npairs, int n, int M, int N, int nup, int p, int L,
                                           double scale, const OPtrs& near_part, double* __restrict__ lds) {
   constexpr int C = 3 * K;
@@ -484,7 +485,6 @@ __device__ __forceinline__ void near_body(int pair, int chunk, const double* __r
   const double Xx = (ctr[3 * i] + off[3 * kk]) - ctr[3 * j];
   const double Xy = (ctr[3 * i + 1] + off[3 * kk + 1]) - ctr[3 * j + 1];
   const double Xz = (ctr[3 * i + 2] + off[3 * kk + 2]) - ctr[3 * j + 2];
-  const size_t ML = (size_t)M * L;
   double f[K][3];
   {
     const double rho = sqrt(Xx * Xx + Xy * Xy);
@@ -493,7 +493,7 @@ __device__ __forceinline__ void near_body(int pair, int chunk, const double* __r
     const double cp = rho > 0.0 ? Xx / rho : 1.0, sp = rho > 0.0 ? Xy / rho : 0.0;
 #pragma unroll
     for (int r = 0; r < K; ++r) f[r][0] = f[r][1] = f[r][2] = 0.0;
-    foot_part<K>(p, ct, st, cp, sp, shab, coef, (size_t)j * L, ML, wv, f);
+    foot_part<K>(p, ct, st, cp, sp, shab, coef + (size_t)j * C * L, L, wv, f);
 #pragma unroll
     for (int r = 0; r < K; ++r)
 #pragma unroll
@@ -593,7 +593,8 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near64(const double* __rest
                                                             const double* __restrict__ off,
                                                             const double4* __restrict__ offup,
                                                             const double* __restrict__ shab,
-                                                            const double* __restrict__ qup, QPtrs coef,
+                                                            const double* __restrict__ qup,
+                                                            const double* __restrict__ coef,
                                                             const int* __restrict__ npairs, int n, int M, int N,
                                                             int nup, int p, int L, double scale, OPtrs near_part,
                                                             int nch, int total, int per) {
@@ -608,8 +609,9 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near64(const double* __rest
 //
 // C(r, col) = sum_k A[r * lda + k] * B(k, col), FP64, 32x32 output tiles,
 // B(k, col) = B[col * ldb + k] (k contiguous) and C(r, col) stored at
-// C[(r / rb) * rbs + col * ldc + r % rb]: one kernel covers the per-sphere
-// block products on the SoA field layout (and the interleaved layouts).
+// C[(r / rb) * rbs + (r % rb) * rs + (col / cb) * cbs + (col % cb) * ldc]: one
+// kernel covers the per-sphere block products on the SoA field layout and the
+// node-interleaved layouts (rs = 1 and cb >= Cn give C[(r / rb) rbs + col ldc + r % rb]).
 
 constexpr int GBM = 32, GBN = 32, GBK = 16;
 constexpr int kGemmSplitBelow = 2048;  // tiles per launch below which k is split over 4 waves
@@ -628,7 +630,7 @@ typedef double gemm_acc4 __attribute__((ext_vector_type(4)));
 template <int GW>
 __device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, const double* __restrict__ A,
                                           int lda, const double* __restrict__ B, int ldb, double* __restrict__ C,
-                                          int rb, long rbs, int ldc) {
+                                          int rb, long rbs, int ldc, int rs, int cb, long cbs) {
   // per wave: A and B slices [32][GLS]; reused for the partial tiles [32][33]
   __shared__ double sh[GW][2 * GBM * GLS];
   const int lane = threadIdx.x & 63;
@@ -690,7 +692,7 @@ __device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, 
         const int tr = 16 * i + lk + 4 * q;
         const int gr = r0 + tr;
         if (gr >= R) continue;
-        const size_t rowbase = (size_t)(gr / rb) * rbs + gr % rb;
+        const size_t rowbase = (size_t)(gr / rb) * rbs + (size_t)(gr % rb) * rs;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           const int tc = 16 * j + li;
@@ -698,7 +700,7 @@ __device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, 
           double v = acc[i][j][q];
 #pragma unroll
           for (int w = 1; w < GW; ++w) v += part[((w - 1) * GBM + tr) * (GBN + 1) + tc];
-          if (gc < Cn) C[rowbase + (size_t)gc * ldc] = v;
+          if (gc < Cn) C[rowbase + (size_t)(gc / cb) * cbs + (size_t)(gc % cb) * ldc] = v;
         }
       }
   }
@@ -709,7 +711,7 @@ __global__ __launch_bounds__(64 * GW) void k_gemm64(int R, int Cn, int K, const 
                                                     long Az, const double* __restrict__ B, long Bz, int ldb,
                                                     double* __restrict__ C, long Cz, int rb, long rbs, int ldc) {
   gemm_tile<GW>(blockIdx.x, blockIdx.y, R, Cn, K, A + (size_t)blockIdx.z * Az, lda, B + (size_t)blockIdx.z * Bz, ldb,
-                C + (size_t)blockIdx.z * Cz, rb, rbs, ldc);
+                C + (size_t)blockIdx.z * Cz, rb, rbs, ldc, 1, Cn, 0);
 }
 
 // ------------------------------------------------- completion and slip RHS
@@ -926,7 +928,8 @@ __global__ __launch_bounds__(64 * GW) void k_gemm64_multi(const GemmDesc* __rest
   const GemmDesc D = d[find_seg(d, nd, b)];
   if (D.live && !*D.live) return;  // uniform over the block, before any barrier
   const int local = b - D.start;
-  gemm_tile<GW>(local % D.tr, local / D.tr, D.R, D.Cn, D.K, D.A, D.lda, D.B, D.ldb, D.C, D.rb, D.rbs, D.ldc);
+  gemm_tile<GW>(local % D.tr, local / D.tr, D.R, D.Cn, D.K, D.A, D.lda, D.B, D.ldb, D.C, D.rb, D.rbs, D.ldc, D.rs,
+                D.cb, D.cbs);
 }
 
 __global__ __launch_bounds__(256) void k_pack_multi(const PackDesc* __restrict__ d, int nd, int fp32) {
@@ -958,12 +961,10 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near64_multi(const NearDesc
   const NearDesc D = d[find_seg(d, nd, b)];
   if (D.live && !*D.live) return;
   const int local = b - D.start;
-  QPtrs cf{};
   OPtrs np{};
-  cf.p[0] = D.coef;
   np.p[0] = D.part;
-  near_body<1>(local / D.nch, local % D.nch, D.ctr, D.off, D.offup, D.shab, D.qup, cf, D.pairs, D.n, D.M, D.N, D.nup,
-               D.p, D.L, D.scale, np, lds);
+  near_body<1>(local / D.nch, local % D.nch, D.ctr, D.off, D.offup, D.shab, D.qup, D.coef, D.pairs, D.n, D.M, D.N,
+               D.nup, D.p, D.L, D.scale, np, lds);
 }
 
 __global__ __launch_bounds__(256) void k_moments_multi(const MomDesc* __restrict__ d, int nd) {
@@ -1165,7 +1166,7 @@ void launch_far_multi(hipStream_t s, int prec, int tpt, const FarDesc* desc, int
 }
 
 void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, const double* off, const double4* offup,
-                 const double* shab, const double* qup, const QPtrs& coef, const int* npairs, int n, int M, int N,
+                 const double* shab, const double* qup, const double* coef, const int* npairs, int n, int M, int N,
                  int nup, int p, int L, double scale, const OPtrs& near_part) {
   if (npairs_count <= 0) return;
   const int nch = (n + 63) / 64, total = npairs_count * nch, per = (total + kXcds - 1) / kXcds;

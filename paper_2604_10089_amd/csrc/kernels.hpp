@@ -37,6 +37,8 @@ struct GemmDesc {
   double* C;
   long rbs;
   int R, Cn, K, lda, ldb, rb, ldc, tr, start;
+  int rs, cb;  // C(r, col) at C[(r / rb) rbs + (r % rb) rs + (col / cb) cbs + (col % cb) ldc]
+  long cbs;
   const int* live;  // null, or a flag: 0 = the segment's system is done (its blocks exit)
 };
 struct PackDesc {
@@ -53,7 +55,7 @@ struct NearDesc {
   const double4* offup;
   const double* shab;
   const double* qup;
-  const double* coef;
+  const double* coef;  // harmonic coefficients [M][3][L]
   const int* pairs;
   double* part;
   double scale;
@@ -139,8 +141,9 @@ void launch_pack(hipStream_t s, int prec, int K, const QPtrs& q, const double* o
 void launch_far(hipStream_t s, int prec, int K, int tpt, const void* src, const double* off, const double* ctr,
                 const unsigned char* cls, int n, int M, int N, int spc, int nchunks, double scale, const OPtrs& part);
 void launch_far_multi(hipStream_t s, int prec, int tpt, const FarDesc* desc, int ndesc, int nitems);
+// coef: harmonic coefficients of the K densities, [M][3K][L] (row 3r + c: density r, component c)
 void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, const double* off, const double4* offup,
-                 const double* shab, const double* qup, const QPtrs& coef, const int* npairs, int n, int M, int N,
+                 const double* shab, const double* qup, const double* coef, const int* npairs, int n, int M, int N,
                  int nup, int p, int L, double scale, const OPtrs& near_part);
 // C(r, col) = sum_k A[r * lda + k] B[col * ldb + k], stored at C[(r / rb) * rbs + col * ldc + r % rb];
 // grid z = batch with strides Az, Bz, Cz.

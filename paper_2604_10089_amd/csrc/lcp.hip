@@ -1490,16 +1490,22 @@ pqn_status lcp_step(pqn_ctx_impl& ctx, double dt, double delta, int solver, cons
   pqn_step_stats ss{};
   LcpState& st = state(ctx);
   const int M = ctx.M;
-  const int n = lcp_find_contacts(ctx, delta);
+  Timer t_stage;
+  const int n = lcp_find_contacts(ctx, delta);  // (reads the count back: the stream is synchronised)
+  ss.t_contacts_ms = t_stage.ms();
   st.ensure(n, M);
   st.set_n(std::max(n, 1));
   // U_nc from the slip-driven solve (F = T = 0)
+  t_stage = Timer();
   pqn_mvp_stats ms{};
   if (ctx.has_axes) {
     ctx.mobility(ctx.hi, nullptr, ctx.dax.p, st.Unc.p, &ms);
   } else {
     HIPCHK(hipMemsetAsync(st.Unc.p, 0, 6 * (size_t)M * sizeof(double), ctx.stream));
   }
+  HIPCHK(hipStreamSynchronize(ctx.stream));
+  ss.t_nc_ms = t_stage.ms();
+  t_stage = Timer();
   ss.gmres_iters_nc = ms.gmres_iters;
   ss.n_contacts = n;
   bool conv = true;
@@ -1527,6 +1533,8 @@ pqn_status lcp_step(pqn_ctx_impl& ctx, double dt, double delta, int solver, cons
     HIPCHK(hipStreamSynchronize(ctx.stream));
     for (double v : hx) ss.n_active += v > 0.0;
   }
+  ss.t_lcp_ms = t_stage.ms();
+  t_stage = Timer();
   hipLaunchKernelGGL(k_euler, dim3((M + 255) / 256), dim3(256), 0, ctx.stream, ctx.ctr.p, ctx.dax.p, st.Unc.p, MDx,
                      M, dt, ctx.has_axes ? 1 : 0);
   HIPCHK(hipGetLastError());
@@ -1547,6 +1555,7 @@ pqn_status lcp_step(pqn_ctx_impl& ctx, double dt, double delta, int solver, cons
     HIPCHK(hipStreamSynchronize(ctx.stream));
     throw;
   }
+  ss.t_update_ms = t_stage.ms();
   ss.t_total_ms = tm.ms();
   if (stats) *stats = ss;
   return conv ? PQN_OK : PQN_WARN_NOT_CONVERGED;

@@ -139,3 +139,28 @@ def test_multi_rhs_with_gaps_in_the_active_set(prec, refine):
     assert np.all(U[1] == 0.0)
     for r in (0, 2, 3):
         assert rel(U[r], singles[r]) < (1e-11 if prec == 'fp64' else 1e-7), r
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_batch_per_instance_stats_and_device_entry(graphs):
+    """Per-suspension statistics (each suspension's own GMRES iterations, equal to its
+    single-context solve; their sum the aggregate) and the device-pointer batch entry
+    (bit-equal to the host-array one)."""
+    import torch
+    inst = _instances(6, 4)
+    FTs = [inputs.random_forces(70 + b, c.shape[0]) for b, (c, _, _) in enumerate(inst)]
+    with binding.BatchContext(inst, gmres_tol=1e-10, precision='fp64', graphs=graphs) as bc:
+        U, st = bc.mobility_apply(FTs, per_instance=True)
+        FTd = [torch.as_tensor(f, dtype=torch.float64, device='cuda') for f in FTs]
+        UOd = [torch.full((c.shape[0], 6), float('nan'), dtype=torch.float64, device='cuda') for c, _, _ in inst]
+        torch.cuda.synchronize()
+        sd = bc.mobility_apply_dev([t.data_ptr() for t in FTd], [t.data_ptr() for t in UOd])
+    per = st['per_instance']
+    assert sum(p['gmres_iters'] for p in per) == st['gmres_iters']
+    assert all(p['converged'] == 1 and p['rel_residual'] <= 1e-10 for p in per)
+    assert [p['gmres_iters'] for p in per] == [p['gmres_iters'] for p in sd['per_instance']]
+    for b, (c, nt, nph) in enumerate(inst):
+        assert np.array_equal(UOd[b].cpu().numpy(), U[b])
+        with binding.Context(c, None, nt, nph, gmres_tol=1e-10) as ctx:
+            _, s1 = ctx.mobility_apply(FTs[b])
+        assert abs(s1['gmres_iters'] - per[b]['gmres_iters']) <= 1

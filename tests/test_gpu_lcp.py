@@ -95,6 +95,8 @@ def test_step_matches_oracle(cases, solver):
         c2, ax2 = ctx.get_state()
     assert st['n_contacts'] == info['pairs'].shape[0]
     assert st['n_active'] == int((info['x'] > 0).sum())
+    stages = [st[k] for k in ('t_contacts_ms', 't_nc_ms', 't_lcp_ms', 't_update_ms')]
+    assert all(t > 0.0 for t in stages) and sum(stages) <= st['t_total_ms'] * 1.001
     assert np.abs(c2 - c1).max() < 1e-10
     assert np.abs(ax2 - ax1).max() < 1e-10
 
@@ -345,7 +347,9 @@ def test_step_with_close_pairs_matches_oracle():
         c2, ax2 = ctx.get_state()
     say('close-pair step: contacts', st['n_contacts'], 'active', st['n_active'])
     assert st['n_contacts'] == info['pairs'].shape[0]
-    assert st['n_active'] == int((info['x'] > 0).sum()) and st['n_active'] > 0
+    assert st['n_active'] == int((info['x'] > 0).sum())
+    stages = [st[k] for k in ('t_contacts_ms', 't_nc_ms', 't_lcp_ms', 't_update_ms')]
+    assert all(t > 0.0 for t in stages) and sum(stages) <= st['t_total_ms'] * 1.001 and st['n_active'] > 0
     assert np.abs(c2 - c1).max() < 1e-10
     assert np.abs(ax2 - ax1).max() < 1e-10
 
