@@ -60,7 +60,7 @@ class Geometry:
     """Centres plus the per-sphere grid of one suspension (plain container)."""
 
     def __init__(self, centers, radius=1.0, n_theta=8, n_phi=16, mu=1.0,
-                 near_gap=None, near_up=2, near_close_gap=0.0, near_close_up=3):
+                 near_gap=None, near_up=2, near_close_gap=0.0, near_close_up=3, far_coarse=None):
         self.c = np.array(centers, dtype=np.float64).reshape(-1, 3)
         self.M = self.c.shape[0]
         self.a = float(radius)
@@ -73,6 +73,8 @@ class Geometry:
         self.near_up = int(near_up)
         self.near_close_gap = float(near_close_gap)
         self.near_close_up = int(near_close_up)
+        # far pairs from a coarser source grid (n_theta_c, n_phi_c), or None (the node rule)
+        self.far_coarse = None if far_coarse is None else (int(far_coarse[0]), int(far_coarse[1]))
         self.x = (self.c[:, None, :] + self.o[None, :, :]).reshape(-1, 3)
         self.normals = np.tile(self.nrm, (self.M, 1))
         self.weights = np.tile(self.w, self.M)
@@ -323,11 +325,52 @@ def near_row(geom, i, j, k):
     return np.einsum('fcd,fk->ckd', K, I) - np.einsum('cd,k->ckd', K.sum(axis=0), Ifoot)
 
 
+def far_coarse_rule(geom):
+    """Coarse source rule of far pairs: offsets, normals and weights of the coarse
+    (n_theta_c, n_phi_c) grid, and the (n_c, n) map taking a sphere's node values to
+    their projection on harmonics of degree <= p_c = n_theta_c - 1 evaluated at the
+    coarse nodes. A lower fidelity of the same discretisation (Sec. 5.1 lowers the
+    order p of the surface representation): far pairs see the source density only
+    through its multipoles, whose fields decay like (a/d)^(l+1), so the degrees above
+    p_c are dropped for them and the truncated density is summed on a grid that
+    integrates it; the self and near terms keep the full grid and degree.
+    Pinned by: on band-limited densities the coarse far sum converges to the node rule
+    as p_c grows, geometrically, and equals it at p_c = p (tests/test_oracle_bie.py).
+    """
+    cache = geom.__dict__.setdefault('_far_coarse_cache', {})
+    key = geom.far_coarse
+    if key not in cache:
+        ntc, npc = key
+        pc = ntc - 1
+        oc, nc, wc = _grid.sphere_grid(ntc, npc, geom.a)
+        thc, phc = _grid.grid_angles(ntc, npc)
+        th, ph = _grid.grid_angles(geom.n_theta, geom.n_phi)
+        _, _, w_unit = _grid.sphere_grid(geom.n_theta, geom.n_phi, 1.0)
+        analysis = (_grid.real_sh(pc, th, ph) * w_unit[:, None]).T      # (L_c, n): degrees <= p_c
+        Pc = _grid.real_sh(pc, thc, phc) @ analysis
+        cache[key] = (oc, nc, wc, Pc)
+    return cache[key]
+
+
+def far_sum(geom, x, j, qj):
+    """Double layer of sphere j's density qj (n, 3) at far points x (m, 3): the node
+    rule, or the coarse source rule when geom.far_coarse is set."""
+    sj = geom.nodes(j)
+    if geom.far_coarse is None:
+        return dl_apply(x, geom.x[sj], geom.normals[sj], qj * geom.w[:, None])
+    oc, nc, wc, Pc = far_coarse_rule(geom)
+    return dl_apply(x, geom.c[j] + oc, nc, (Pc @ qj) * wc[:, None])
+
+
 def offdiag_block(geom, i, j, near):
     """Dense (3n, 3n) block of D mapping q on sphere j to targets on sphere i."""
     if near:
         return near_block(geom, i, j).reshape(3 * geom.n, 3 * geom.n)
     si, sj = geom.nodes(i), geom.nodes(j)
+    if geom.far_coarse is not None:
+        oc, nc, wc, Pc = far_coarse_rule(geom)
+        K = dl_kernel(geom.x[si], geom.c[j] + oc, nc) * wc[None, :, None, None]
+        return np.einsum('mfcd,fk->mckd', K, Pc).reshape(3 * geom.n, 3 * geom.n)
     K = dl_kernel(geom.x[si], geom.x[sj], geom.normals[sj]) * geom.w[None, :, None, None]
     return K.transpose(0, 2, 1, 3).reshape(3 * geom.n, 3 * geom.n)
 
@@ -360,7 +403,6 @@ def dense_operator(geom):
 def offdiag_apply(geom, q, i_targets=None):
     """Off-particle part of D applied to q (N,3); returns (N,3) (or rows of i_targets)."""
     q = q.reshape(geom.N, 3)
-    wq = q * geom.weights[:, None]
     cls = geom.pair_class()
     tgts = range(geom.M) if i_targets is None else i_targets
     out = np.zeros((geom.N, 3))
@@ -375,7 +417,7 @@ def offdiag_apply(geom, q, i_targets=None):
             if cls[i, j] == 1:
                 acc += np.einsum('mckd,kd->mc', near_block(geom, i, j), q[sj])
             else:
-                acc += dl_apply(xi, geom.x[sj], geom.normals[sj], wq[sj])
+                acc += far_sum(geom, xi, j, q[sj])
         out[si] = acc
     return out
 
@@ -394,7 +436,6 @@ def operator_rows(geom, q, targets):
     suspensions too large to apply whole.
     """
     q = q.reshape(geom.N, 3)
-    wq = q * geom.weights[:, None]
     cls = geom.pair_class()
     P = rigid_projection(geom, q)
     out = np.zeros((len(targets), 3))
@@ -410,7 +451,7 @@ def operator_rows(geom, q, targets):
             if cls[i, j] == 1:
                 acc = acc + np.einsum('ckd,kd->c', near_row(geom, i, j, k), q[sj])
             else:
-                acc = acc + dl_apply(xt, geom.x[sj], geom.normals[sj], wq[sj])[0]
+                acc = acc + far_sum(geom, xt, j, q[sj])[0]
         out[row] = acc
     return out
 

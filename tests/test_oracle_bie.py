@@ -384,3 +384,40 @@ def test_recycling_mobility_equals_cold_solves(tiny_cases):
     assert np.abs(U - Uc).max() < 1e-10 * np.abs(Uc).max()
     U = rec(inputs.random_forces(40, g.M))
     assert rec.iters[-1] > 0 and rec.r0[-1] > 1e-3
+
+
+def _band_limited(nt, nph, seed):
+    """A density of degree <= p = nt - 1 on the (nt, nph) grid, given by its coefficients."""
+    p = nt - 1
+    th, ph = grid.grid_angles(nt, nph)
+    Y = grid.real_sh(p, th, ph)
+    return Y @ np.random.default_rng(seed).standard_normal((Y.shape[1], 3))
+
+
+def test_coarse_far_rule_converges_to_the_node_rule():
+    """Far pairs from a coarse source grid (the coarse-far low fidelity): on a band-limited
+    density the far sum converges to the node rule as the coarse grid is refined, and
+    equals it on the node grid itself."""
+    nt, nph = 12, 24
+    c = np.array([[0.0, 0.0, 0.0], [0.3, -2.1, 1.9]])          # gap ~0.85, a far pair
+    q = _band_limited(nt, nph, 4)
+    fine = bie.far_sum(bie.Geometry(c, 1.0, nt, nph), bie.Geometry(c, 1.0, nt, nph).x[:nt * nph], 1, q)
+    errs = []
+    for ntc in (4, 6, 8, 10, 12):
+        g = bie.Geometry(c, 1.0, nt, nph, far_coarse=(ntc, 2 * ntc))
+        v = bie.far_sum(g, g.x[:g.n], 1, q)
+        errs.append(np.abs(v - fine).max() / np.abs(fine).max())
+    assert errs[-1] < 1e-13
+    assert all(b < a for a, b in zip(errs[:-2], errs[1:-1]))
+    assert errs[1] < 1e-2
+
+
+def test_coarse_far_operator_dense_equals_matrix_free(tiny_cases):
+    _, g0, _ = tiny_cases[0]
+    g = bie.Geometry(g0.c, 1.0, 8, 16, far_coarse=(4, 8))
+    A = bie.dense_operator(g)
+    q = np.random.default_rng(8).standard_normal((g.N, 3))
+    y = bie.operator_apply(g, q)
+    assert np.abs(A @ q.ravel() - y.ravel()).max() < 1e-12 * np.abs(y).max()
+    rows = bie.operator_rows(g, q, [0, 77, g.N - 1])
+    assert np.abs(rows - y[[0, 77, g.N - 1]]).max() < 1e-12 * np.abs(y).max()
