@@ -111,6 +111,13 @@ typedef struct {
                                can make the pair's discrete mobility, and the contact LCP
                                matrix, indefinite */
   int32_t near_close_up;    /* upsampling factor of those close pairs [3] */
+  int32_t far_coarse_lo;    /* first low fidelity: far sphere pairs summed from a coarse source grid of
+                               far_coarse_lo x 2 far_coarse_lo nodes carrying the density truncated to
+                               degree far_coarse_lo - 1 (its multipoles to that degree); self and near
+                               terms keep the level's grid. Sec. 5.1 lowers the order of the surface
+                               representation for its low fidelity; with n_theta_lo = n_theta this lowers
+                               it for the far field only. 0 = the node rule; else 2..n_theta_lo */
+  int32_t far_coarse_lo2;   /* the same for the second low fidelity (2..n_theta_lo2) */
 } pqn_config_desc;
 
 typedef struct {

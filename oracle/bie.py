@@ -37,6 +37,9 @@ discrete operator):
     near-singular evaluation, which the paper names by cost only (Sec. 5.1);
     optionally, pairs closer than near_close_gap use the finer factor
     near_close_up instead (a gap the near_up grid does not resolve);
+  * optionally (Geometry(far_coarse=(nt_c, np_c)), a lower fidelity of the same
+    discretisation) far pairs take their sources from a coarse grid carrying the
+    density truncated to degree nt_c - 1 (far_coarse_rule);
   * the weakly singular self interaction by a rotated-pole rule: for each target
     node x0 the sphere is re-gridded with x0 at the pole (Gauss-Legendre in the
     polar angle theta' on [0, pi] with 3 n_theta points, trapezoid in phi' with

@@ -35,7 +35,7 @@ class ConfigDesc(C.Structure):
                 ('warm_start', C.c_int32), ('n_theta_lo2', C.c_int32), ('n_phi_lo2', C.c_int32),
                 ('gmres_tol_lo2', C.c_double), ('dev_alloc', _ALLOC_FN), ('dev_free', _FREE_FN),
                 ('alloc_user', C.c_void_p), ('side_stream', C.c_int32), ('near_close_gap', C.c_double),
-                ('near_close_up', C.c_int32)]
+                ('near_close_up', C.c_int32), ('far_coarse_lo', C.c_int32), ('far_coarse_lo2', C.c_int32)]
 
 
 class TorchAllocator:
@@ -204,7 +204,8 @@ def pqn_host_self_block(n_theta, n_phi, radius=1.0):
 def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_tol_lo=None, restart=50,
           max_iter=500, near_gap=0.0, near_up=2, slip=1.0, precision='fp64', refine=0, tpt=2, far_chunks=0,
           far_split=0, device=0, stream=None, profile=False, graphs=False, warm_start=False, lo2=None,
-          gmres_tol_lo2=None, allocator=None, side_stream=False, near_close_gap=0.0, near_close_up=3):
+          gmres_tol_lo2=None, allocator=None, side_stream=False, near_close_gap=0.0, near_close_up=3,
+          far_coarse_lo=0, far_coarse_lo2=0):
     d = ConfigDesc()
     d.n_particles = M
     d.radius, d.mu = radius, mu
@@ -232,6 +233,7 @@ def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_
         allocator.fill(d)
     d.side_stream = 1 if side_stream else 0
     d.near_close_gap, d.near_close_up = near_close_gap, near_close_up
+    d.far_coarse_lo, d.far_coarse_lo2 = far_coarse_lo, far_coarse_lo2
     return d
 
 
@@ -343,7 +345,8 @@ class Context:
                  gmres_tol=1e-8, gmres_tol_lo=None, restart=50, max_iter=500, near_gap=0.0, near_up=2,
                  slip=1.0, precision='fp64', refine=0, tpt=None, far_chunks=None, far_split=None, device=0,
                  stream=None, profile=False, tune_K=1, graphs=False, warm_start=False, lo2=None,
-                 gmres_tol_lo2=None, torch_alloc=False, side_stream=False, near_close_gap=0.0, near_close_up=3):
+                 gmres_tol_lo2=None, torch_alloc=False, side_stream=False, near_close_gap=0.0, near_close_up=3,
+                 far_coarse_lo=0, far_coarse_lo2=0):
         c = _f64(centers).reshape(-1, 3)
         self.M = c.shape[0]
         self._alloc = None
@@ -362,7 +365,7 @@ class Context:
                   far_chunks=far_chunks, far_split=far_split, device=device, stream=stream, profile=profile,
                   graphs=graphs, warm_start=warm_start, lo2=lo2, gmres_tol_lo2=gmres_tol_lo2,
                   allocator=self._alloc, side_stream=side_stream, near_close_gap=near_close_gap,
-                  near_close_up=near_close_up)
+                  near_close_up=near_close_up, far_coarse_lo=far_coarse_lo, far_coarse_lo2=far_coarse_lo2)
         self.n_theta, self.n_phi, self.lo, self.lo2 = n_theta, n_phi, lo, lo2
         ax = None if axes is None else _f64(axes).reshape(-1, 3)
         h = C.c_void_p()

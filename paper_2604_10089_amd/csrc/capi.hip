@@ -75,6 +75,10 @@ static std::string check_desc(const pqn_config_desc& c) {
   if (c.precision != PQN_FP64 && c.precision != PQN_MIXED) return "bad precision";
   if ((c.dev_alloc == nullptr) != (c.dev_free == nullptr)) return "dev_alloc and dev_free go together";
   if (c.near_up > 8 || c.near_close_up > 8) return "near upsampling factors above 8 are not supported";
+  if (c.far_coarse_lo != 0 && (c.n_theta_lo == 0 || c.far_coarse_lo < 2 || c.far_coarse_lo > c.n_theta_lo))
+    return "far_coarse_lo needs a low-fidelity grid and 2 <= far_coarse_lo <= n_theta_lo";
+  if (c.far_coarse_lo2 != 0 && (c.n_theta_lo2 == 0 || c.far_coarse_lo2 < 2 || c.far_coarse_lo2 > c.n_theta_lo2))
+    return "far_coarse_lo2 needs a second low-fidelity grid and 2 <= far_coarse_lo2 <= n_theta_lo2";
   return "";
 }
 
@@ -97,11 +101,11 @@ static std::unique_ptr<pqn_ctx_impl> make_context(const pqn_config_desc& c, cons
   AllocScope scope(&ctx->dev_alloc);
   ctx->setup_level(ctx->hi, c.n_theta, c.n_phi, c.gmres_tol);
   if (c.n_theta_lo > 0) {
-    ctx->setup_level(ctx->lo, c.n_theta_lo, c.n_phi_lo, c.gmres_tol_lo);
+    ctx->setup_level(ctx->lo, c.n_theta_lo, c.n_phi_lo, c.gmres_tol_lo, c.far_coarse_lo);
     ctx->has_lo = true;
   }
   if (c.n_theta_lo2 > 0) {
-    ctx->setup_level(ctx->lo2, c.n_theta_lo2, c.n_phi_lo2, c.gmres_tol_lo2);
+    ctx->setup_level(ctx->lo2, c.n_theta_lo2, c.n_phi_lo2, c.gmres_tol_lo2, c.far_coarse_lo2);
     ctx->has_lo2 = true;
   }
   ctx->FT.alloc(6 * (size_t)kMaxRhs * ctx->M);

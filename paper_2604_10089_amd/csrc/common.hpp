@@ -79,6 +79,11 @@ struct SphereTables {
   // finer grid of the close near pairs (gap < near_close_gap); n_up2 = 0 when unused
   int up2 = 0, n_up2 = 0;
   std::vector<double> off_up2, w_up2, Y_up2;
+  // coarse far-source grid (far_theta x 2 far_theta nodes, nc of them; nc = 0 when unused):
+  // the density truncated to degree Lc = far_theta^2 harmonics, synthesised there
+  int nc = 0, Lc = 0;
+  std::vector<double> off_c, w_c;  // [nc][3], [nc]
+  std::vector<double> Y_c;         // [nc][Lc]
   std::vector<double> shab;     // [L][2] Legendre recurrence factors (sh_recurrence_table)
 };
 
@@ -90,6 +95,7 @@ std::vector<double> sh_recurrence_table(int p);
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 // close_up > 0: also the close-pair grid, close_up times finer per direction
-void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, SphereTables& t, int close_up = 0);
+void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, SphereTables& t, int close_up = 0,
+                         int far_theta = 0);
 
 }  // namespace bipqn

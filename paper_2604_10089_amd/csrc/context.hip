@@ -94,8 +94,8 @@ pqn_ctx_impl::~pqn_ctx_impl() {
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
-void pqn_ctx_impl::setup_level(Level& lv, int nt, int np, double tol) {
-  build_sphere_tables(nt, np, a, cfg.near_up, lv.tab, cfg.near_close_gap > 0.0 ? cfg.near_close_up : 0);
+void pqn_ctx_impl::setup_level(Level& lv, int nt, int np, double tol, int far_theta) {
+  build_sphere_tables(nt, np, a, cfg.near_up, lv.tab, cfg.near_close_gap > 0.0 ? cfg.near_close_up : 0, far_theta);
   SphereTables& t = lv.tab;
   lv.M = M;
   lv.n = t.n;
@@ -120,6 +120,13 @@ void pqn_ctx_impl::setup_level(Level& lv, int nt, int np, double tol) {
       ou2[f] = make_double4(t.off_up2[3 * f], t.off_up2[3 * f + 1], t.off_up2[3 * f + 2], t.w_up2[f]);
     lv.offup2.upload(ou2.data(), ou2.size(), stream);
     lv.Yup2.upload(t.Y_up2.data(), t.Y_up2.size(), stream);
+  }
+  lv.nc = t.nc;
+  lv.Lc = t.Lc;
+  if (lv.nc > 0) {
+    lv.offc.upload(t.off_c.data(), t.off_c.size(), stream);
+    lv.wc.upload(t.w_c.data(), t.w_c.size(), stream);
+    lv.Yc.upload(t.Y_c.data(), t.Y_c.size(), stream);
   }
   const int N = lv.N;
   lv.tpt = far_layout(cfg);
@@ -276,6 +283,18 @@ static double* group_qup(MvGroup& gr, bool close = false) {
 // Harmonic coefficients of a group's K densities, [M][3K][L] (row 3r + c: density r,
 // component c), in the work buffer of the group's first slot (grown on first use with
 // more densities).
+// Degree-truncated densities of a group on the coarse far-source grid, [M][nc][3K].
+static double* group_qc(MvGroup& gr) {
+  Level& lv = *gr.lv;
+  DevArray<double>& buf = lv.wk(gr.slot[0]).qc;
+  const size_t need = (size_t)3 * gr.K * lv.M * lv.nc;
+  if (buf.count < need) {
+    HIPCHK(hipDeviceSynchronize());  // the old buffer may still be read by queued work
+    buf.alloc(need);
+  }
+  return buf.p;
+}
+
 static double* group_coef(MvGroup& gr) {
   Level& lv = *gr.lv;
   DevArray<double>& buf = lv.wk(gr.slot[0]).coef;
@@ -330,37 +349,55 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
   // near tiles and the rigid moments (none of which the far pair sum reads) run
   // on a second stream, concurrently with the packing and far pair sum; the
   // final combination waits for both.
+  // With a coarse far-source grid the far sources come from the coefficients: the
+  // coefficient and coarse-synthesis GEMMs then run on the main stream before the fork.
   const bool ov = cfg.side_stream && !cfg.profile && groups.size() == 1;
-  hipStream_t sa = s;
-  DevArray<char>* dtab = &ddesc;
-  if (ov) {
-    sa = side_stream();
-    dtab = &ddesc_side;
-    HIPCHK(hipEventRecord(ev_in, s));
-    HIPCHK(hipStreamWaitEvent(sa, ev_in, 0));
-  }
+  hipStream_t sa = ov ? side_stream() : s;
+  bool forked = false;
+  auto fork = [&]() {
+    if (ov && !forked) {
+      HIPCHK(hipEventRecord(ev_in, s));
+      HIPCHK(hipStreamWaitEvent(sa, ev_in, 0));
+      forked = true;
+    }
+  };
   for (MvGroup& gr : groups) {
     Level& lv = *gr.lv;
     pqn_ctx_impl& c = *gr.c;
-    const int n = lv.n, N = lv.N;
+    const int n = lv.n, N = lv.N, C = 3 * gr.K;
     QPtrs qp{};
-    std::vector<GemmDesc> ga, gb;
-    int nga = 0, ngb = 0;
+    std::vector<GemmDesc> ga, gb, gc;
+    int nga = 0, ngb = 0, ngc = 0;
     double* qup = c.n_near > 0 ? group_qup(gr) : nullptr;
     double* qup2 = c.n_near2 > 0 ? group_qup(gr, true) : nullptr;
     double* coef = group_coef(gr);
+    double* qc = lv.nc > 0 ? group_qc(gr) : nullptr;
     push_group_gemms(lv, gr.K, gr.slot, gr.in, coef, qup, qup2, nullptr, ga, nga, gb, ngb);
+    if (qc)  // densities truncated to the coarse grid's degree, synthesised on it: [M][nc][3K]
+      push_gemm(gc, ngc, lv.nc, C * lv.M, lv.Lc, lv.Yc.p, lv.Lc, coef, lv.L, qc, lv.nc, 0, 1, C, C, (long)lv.nc * C);
     for (int r = 0; r < gr.K; ++r) qp.p[r] = gr.in[r];
     DescPack dp;
-    const size_t oa = dp.add(ga), ob = dp.add(gb);
-    char* base = push_desc_pack(dp.host, sa, *dtab);
+    const size_t oa = dp.add(ga), ob = dp.add(gb), oc = dp.add(gc);
     stage_begin(kStageGemm);
-    launch_gemm64_multi(sa, (const GemmDesc*)(base + oa), (int)ga.size(), nga);
-    launch_gemm64_multi(sa, (const GemmDesc*)(base + ob), (int)gb.size(), ngb);
+    if (qc) {
+      char* base = push_desc_pack(dp.host);  // main stream (read by the side stream after the fork)
+      launch_gemm64_multi(s, (const GemmDesc*)(base + oa), (int)ga.size(), nga);
+      launch_gemm64_multi(s, (const GemmDesc*)(base + oc), (int)gc.size(), ngc);
+      fork();
+      launch_gemm64_multi(sa, (const GemmDesc*)(base + ob), (int)gb.size(), ngb);
+    } else {
+      fork();
+      char* base = ov ? push_desc_pack(dp.host, sa, ddesc_side) : push_desc_pack(dp.host);
+      launch_gemm64_multi(sa, (const GemmDesc*)(base + oa), (int)ga.size(), nga);
+      launch_gemm64_multi(sa, (const GemmDesc*)(base + ob), (int)gb.size(), ngb);
+    }
     stage_end(kStageGemm);
     if (ov) side_work(gr, sa);
     stage_begin(kStageLocal);
-    launch_pack(s, prec, gr.K, qp, lv.off.p, lv.w.p, n, N, lv.src.p);
+    if (qc)
+      launch_pack_coarse(s, prec, gr.K, qc, lv.offc.p, lv.wc.p, lv.nc, lv.M * lv.nc, lv.src.p);
+    else
+      launch_pack(s, prec, gr.K, qp, lv.off.p, lv.w.p, n, N, lv.src.p);
     stage_end(kStageLocal);
   }
   begin_far_timing();
@@ -369,8 +406,8 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
       Level& lv = *gr.lv;
       OPtrs op{};
       for (int r = 0; r < gr.K; ++r) op.p[r] = lv.wk(gr.slot[r]).far_part.p;
-      launch_far(s, prec, gr.K, lv.tpt, lv.src.p, lv.off.p, gr.c->ctr.p, gr.c->cls.p, lv.n, lv.M, lv.N, lv.spc,
-                 lv.nchunks, 3.0 / (4.0 * kPi * gr.c->a), op);
+      launch_far(s, prec, gr.K, lv.tpt, lv.src.p, lv.off.p, gr.c->ctr.p, gr.c->cls.p, lv.n, lv.nc > 0 ? lv.nc : lv.n,
+                 lv.M, lv.N, lv.spc, lv.nchunks, 3.0 / (4.0 * kPi * gr.c->a), op);
     }
   }
   end_far_launch();
@@ -645,7 +682,7 @@ void pqn_ctx_impl::iteration_launches(pqn_ctx_impl& c, Level& lv, int slot, int 
   launch_pack(s, prec, 1, qp, lv.off.p, lv.w.p, lv.n, lv.N, lv.src.p);
   OPtrs op{};
   op.p[0] = wk.far_part.p;
-  launch_far(s, prec, 1, lv.tpt, lv.src.p, lv.off.p, c.ctr.p, c.cls.p, lv.n, lv.M, lv.N, lv.spc, lv.nchunks, scale,
+  launch_far(s, prec, 1, lv.tpt, lv.src.p, lv.off.p, c.ctr.p, c.cls.p, lv.n, lv.n, lv.M, lv.N, lv.spc, lv.nchunks, scale,
              op);
   OPtrs np{};
   np.p[0] = wk.near_part.p;
@@ -1075,7 +1112,7 @@ void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision)
     for (int i = 0; i < ns; ++i)
       if (st[i].active) act.push_back(i);
     if (act.empty()) break;
-    const bool graph_iter = ns == 1 && cfg.use_graphs && !cfg.profile;
+    const bool graph_iter = ns == 1 && cfg.use_graphs && !cfg.profile && sys[0].lv->nc == 0;
     if (graph_iter) {
       const int i = act[0];
       launch_iteration_graph(*sys[i].c, *sys[i].lv, sys[i].slot, precision == PQN_MIXED ? 1 : 0, st[i].k,

@@ -118,6 +118,7 @@ inline int far_layout(const pqn_config_desc& c) {
 struct Work {
   DevArray<double> far_part, near_part, coef, qup, selfo, mom;
   DevArray<double> qup2;  // densities on the close-pair grid, same interleaving as qup
+  DevArray<double> qc;    // degree-truncated densities on the coarse far-source grid [M][nc][3K]
 };
 
 // Krylov storage of one linear system on one level.
@@ -211,6 +212,8 @@ struct Level {
   int nup2 = 0;  // close-pair grid (0 = none)
   DevArray<double> Yup2;
   DevArray<double4> offup2;
+  int nc = 0, Lc = 0;  // coarse far-source grid (0 = far pairs by the node rule) and its truncation
+  DevArray<double> offc, wc, Yc;
   DevArray<double> src;  // packed far sources, up to kMaxRhs densities (FP64 record is the larger)
   int nchunks = 1, spc = 1, tpt = 2;
   int restart = 50, max_iter = 500;
@@ -328,7 +331,7 @@ struct pqn_ctx_impl {
     if (fidelity != PQN_HIFI) throw Error(PQN_ERR_INVALID, "fidelity must be PQN_HIFI, PQN_LOFI or PQN_LOFI2");
     return hi;
   }
-  void setup_level(Level& lv, int nt, int np, double tol);
+  void setup_level(Level& lv, int nt, int np, double tol, int far_theta = 0);
   void set_configuration(const double* c, const double* ax);
   // operator on groups of densities (all on this context's stream)
   void matvec_groups(std::vector<MvGroup>& groups, int precision);

@@ -198,7 +198,8 @@ static void upsampled_grid(const SphereTables& t, int up, std::vector<double>& o
   }
 }
 
-void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, SphereTables& t, int close_up) {
+void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, SphereTables& t, int close_up,
+                         int far_theta) {
   if (n_theta < 2 || n_phi < 2 * n_theta - 1 || n_theta - 1 > kMaxDegree)
     throw std::runtime_error("grid must have n_theta >= 2, n_phi >= 2 n_theta - 1, degree <= 40");
   t.n_theta = n_theta;
@@ -248,6 +249,21 @@ void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, Sph
   t.up2 = close_up > 0 ? close_up : 0;
   t.n_up2 = 0;
   if (t.up2 > 0) upsampled_grid(t, t.up2, t.off_up2, t.w_up2, t.Y_up2, t.n_up2);
+  // coarse far-source grid: degree far_theta - 1 synthesis at its Gauss-Legendre x trapezoid nodes
+  t.nc = t.Lc = 0;
+  if (far_theta > 0) {
+    if (far_theta > n_theta) throw std::runtime_error("the coarse far-source grid must not be finer than the grid");
+    const int ntc = far_theta, npc = 2 * far_theta, pc = far_theta - 1;
+    t.nc = ntc * npc;
+    t.Lc = ntc * ntc;
+    std::vector<double> ctc, phc;
+    sphere_grid(ntc, npc, radius, t.off_c, t.w_c, &ctc, &phc);
+    t.Y_c.assign((size_t)t.nc * t.Lc, 0.0);
+    for (int f = 0; f < t.nc; ++f) {
+      const double st = std::sqrt(1.0 - ctc[f] * ctc[f]);
+      sh_row(pc, ctc[f], st, std::cos(phc[f]), std::sin(phc[f]), &t.Y_c[(size_t)f * t.Lc]);
+    }
+  }
   t.shab = sh_recurrence_table(t.p);
 }
 

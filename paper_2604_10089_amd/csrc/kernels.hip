@@ -52,6 +52,42 @@ __global__ __launch_bounds__(256) void k_pack64(QPtrs q, const double* __restric
   for (int e = 3 + 3 * K; e < S; ++e) d[e] = 0.0;
 }
 
+// Far sources on the coarse far-source grid: record of coarse node k of sphere j
+// from the synthesised coarse densities qc[(j * nc + k) * 3K + 3r + c] (the
+// degree-truncated densities at the coarse nodes) with the coarse weights.
+template <int K>
+__global__ __launch_bounds__(256) void k_pack_coarse(const double* __restrict__ qc, const double* __restrict__ off,
+                                                     const double* __restrict__ w, int nc, int Nc, int fp32,
+                                                     void* __restrict__ src) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Nc) return;
+  constexpr int C = 3 * K;
+  const int k = t % nc;
+  const double wk = w[k];
+  const double* q = qc + (size_t)t * C;
+  if (fp32) {
+    constexpr int S = src32_stride(K);
+    float* d = (float*)src + (size_t)t * S;
+    d[0] = (float)off[3 * k];
+    d[1] = (float)off[3 * k + 1];
+    d[2] = (float)off[3 * k + 2];
+#pragma unroll
+    for (int e = 0; e < C; ++e) d[3 + e] = (float)(wk * q[e]);
+#pragma unroll
+    for (int e = 3 + C; e < S; ++e) d[e] = 0.f;
+  } else {
+    constexpr int S = src64_stride(K);
+    double* d = (double*)src + (size_t)t * S;
+    d[0] = off[3 * k];
+    d[1] = off[3 * k + 1];
+    d[2] = off[3 * k + 2];
+#pragma unroll
+    for (int e = 0; e < C; ++e) d[3 + e] = wk * q[e];
+#pragma unroll
+    for (int e = 3 + C; e < S; ++e) d[e] = 0.0;
+  }
+}
+
 // ----------------------------------------------------------- far pair sum
 //
 // u_r(x) += 3/(4 pi a) sum_y r (r.wq_r,y)(r.o_y)/|r|^5, r = x - y, for every
@@ -73,18 +109,19 @@ __global__ __launch_bounds__(256) void k_pack64(QPtrs q, const double* __restric
 constexpr int kXcds = 8;
 __device__ __forceinline__ int xcd_item(int b, int per) { return (b % kXcds) * per + b / kXcds; }
 
-// One source sphere j, nodes [k0, k1), against TPT targets per thread: the
-// tile is summed in FP32 and added to the FP64 accumulators of active targets.
+// One source sphere j (ns source nodes per sphere), nodes [k0, k1), against TPT
+// targets per thread: the tile is summed in FP32 and added to the FP64
+// accumulators of active targets.
 template <int TPT, int K>
 __device__ __forceinline__ void far32_tile(int j, int k0, int k1, const float* __restrict__ src,
                                            const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
-                                           int n, int M, const bool (&valid)[TPT], const int (&ti)[TPT],
+                                           int ns, int M, const bool (&valid)[TPT], const int (&ti)[TPT],
                                            const double (&px)[TPT], const double (&py)[TPT], const double (&pz)[TPT],
                                            const double (&ox)[TPT], const double (&oy)[TPT],
                                            const double (&oz)[TPT], double (&acc)[TPT][K][3]) {
   constexpr int S = src32_stride(K);
   const double cjx = ctr[3 * j], cjy = ctr[3 * j + 1], cjz = ctr[3 * j + 2];
-  const float* sp = src + (size_t)j * n * S;
+  const float* sp = src + (size_t)j * ns * S;
   // |y|^2 of the sphere's source offsets (all a^2 up to rounding), from its first node
   const double a2 = (double)sp[0] * sp[0] + (double)sp[1] * sp[1] + (double)sp[2] * sp[2];
   bool act[TPT];
@@ -155,8 +192,8 @@ __device__ __forceinline__ void far32_tile(int j, int k0, int k1, const float* _
 template <int TPT, int K>
 __device__ __forceinline__ void far32_body(int tb, int chunk, const float* __restrict__ src,
                                            const double* __restrict__ off, const double* __restrict__ ctr,
-                                           const unsigned char* __restrict__ cls, int n, int M, int N, int spc,
-                                           double scale, const OPtrs& part) {
+                                           const unsigned char* __restrict__ cls, int n, int ns, int M, int N,
+                                           int spc, double scale, const OPtrs& part) {
   const int j0 = chunk * spc;
   const int j1 = min(M, j0 + spc);
   int ti[TPT];
@@ -180,7 +217,8 @@ __device__ __forceinline__ void far32_body(int tb, int chunk, const float* __res
 #pragma unroll
     for (int r = 0; r < K; ++r) acc[u][r][0] = acc[u][r][1] = acc[u][r][2] = 0.0;
   }
-  for (int j = j0; j < j1; ++j) far32_tile<TPT, K>(j, 0, n, src, ctr, cls, n, M, valid, ti, px, py, pz, ox, oy, oz, acc);
+  for (int j = j0; j < j1; ++j)
+    far32_tile<TPT, K>(j, 0, ns, src, ctr, cls, ns, M, valid, ti, px, py, pz, ox, oy, oz, acc);
 #pragma unroll
   for (int u = 0; u < TPT; ++u) {
     const int t = tb * 256 * TPT + u * 256 + threadIdx.x;
@@ -204,8 +242,8 @@ __device__ __forceinline__ void far32_body(int tb, int chunk, const float* __res
 template <int K>
 __device__ __forceinline__ void far32_split_body(int tb, int chunk, const float* __restrict__ src,
                                                  const double* __restrict__ off, const double* __restrict__ ctr,
-                                                 const unsigned char* __restrict__ cls, int n, int M, int N, int spc,
-                                                 double scale, const OPtrs& part, double* __restrict__ lds) {
+                                                 const unsigned char* __restrict__ cls, int n, int ns, int M, int N,
+                                                 int spc, double scale, const OPtrs& part, double* __restrict__ lds) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j0 = chunk * spc;
@@ -230,13 +268,13 @@ __device__ __forceinline__ void far32_split_body(int tb, int chunk, const float*
   }
 #pragma unroll
   for (int r = 0; r < K; ++r) acc[0][r][0] = acc[0][r][1] = acc[0][r][2] = 0.0;
-  const int len = (j1 - j0) * n;
-  const int s0 = j0 * n + (wv * len) / 4, s1 = j0 * n + ((wv + 1) * len) / 4;
+  const int len = (j1 - j0) * ns;
+  const int s0 = j0 * ns + (wv * len) / 4, s1 = j0 * ns + ((wv + 1) * len) / 4;
   for (int s = s0; s < s1;) {
-    const int j = s / n;
-    const int k0 = s - j * n, k1 = min(n, s1 - j * n);
-    far32_tile<1, K>(j, k0, k1, src, ctr, cls, n, M, valid, ti, px, py, pz, ox, oy, oz, acc);
-    s = j * n + k1;
+    const int j = s / ns;
+    const int k0 = s - j * ns, k1 = min(ns, s1 - j * ns);
+    far32_tile<1, K>(j, k0, k1, src, ctr, cls, ns, M, valid, ti, px, py, pz, ox, oy, oz, acc);
+    s = j * ns + k1;
   }
 #pragma unroll
   for (int r = 0; r < K; ++r) {
@@ -259,26 +297,26 @@ __device__ __forceinline__ void far32_split_body(int tb, int chunk, const float*
 template <int K>
 __global__ __launch_bounds__(256) void k_far32s(const float* __restrict__ src, const double* __restrict__ off,
                                                 const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
-                                                int n, int M, int N, int spc, double scale, OPtrs part, int ntb,
-                                                int total, int per) {
+                                                int n, int ns, int M, int N, int spc, double scale, OPtrs part,
+                                                int ntb, int total, int per) {
   __shared__ double lds[9 * 64];
   // issue priority over waves of kernels running beside it (near tiles, GEMMs on the side stream)
   __builtin_amdgcn_s_setprio(3);
   const int item = xcd_item(blockIdx.x, per);
   if (item >= total) return;  // uniform over the block: no barrier is skipped by part of it
-  far32_split_body<K>(item % ntb, item / ntb, src, off, ctr, cls, n, M, N, spc, scale, part, lds);
+  far32_split_body<K>(item % ntb, item / ntb, src, off, ctr, cls, n, ns, M, N, spc, scale, part, lds);
 }
 
 // Work item = chunk * ntb + target block (chunk-major: an XCD takes whole chunks).
 template <int TPT, int K>
 __global__ __launch_bounds__(256) void k_far32(const float* __restrict__ src, const double* __restrict__ off,
                                                const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
-                                               int n, int M, int N, int spc, double scale, OPtrs part, int ntb,
-                                               int total, int per) {
+                                               int n, int ns, int M, int N, int spc, double scale, OPtrs part,
+                                               int ntb, int total, int per) {
   __builtin_amdgcn_s_setprio(3);  // as in k_far32s
   const int item = xcd_item(blockIdx.x, per);
   if (item >= total) return;
-  far32_body<TPT, K>(item % ntb, item / ntb, src, off, ctr, cls, n, M, N, spc, scale, part);
+  far32_body<TPT, K>(item % ntb, item / ntb, src, off, ctr, cls, n, ns, M, N, spc, scale, part);
 }
 
 // Many suspensions in one launch: block b takes work item b of a list ordered
@@ -297,18 +335,19 @@ __global__ __launch_bounds__(256) void k_far32_multi(const FarDesc* __restrict__
   part.p[0] = D.part;
   if constexpr (TPT == 0) {
     __shared__ double lds[9 * 64];
-    far32_split_body<1>(tb, chunk, (const float*)D.src, D.off, D.ctr, D.cls, D.n, D.M, D.N, D.spc, D.scale, part,
-                        lds);
+    far32_split_body<1>(tb, chunk, (const float*)D.src, D.off, D.ctr, D.cls, D.n, D.n, D.M, D.N, D.spc, D.scale,
+                        part, lds);
   } else {
-    far32_body<TPT, 1>(tb, chunk, (const float*)D.src, D.off, D.ctr, D.cls, D.n, D.M, D.N, D.spc, D.scale, part);
+    far32_body<TPT, 1>(tb, chunk, (const float*)D.src, D.off, D.ctr, D.cls, D.n, D.n, D.M, D.N, D.spc, D.scale,
+                       part);
   }
 }
 
 template <int K>
 __device__ __forceinline__ void far64_body(int tb, int chunk, const double* __restrict__ src,
                                            const double* __restrict__ off, const double* __restrict__ ctr,
-                                           const unsigned char* __restrict__ cls, int n, int M, int N, int spc,
-                                           double scale, const OPtrs& part) {
+                                           const unsigned char* __restrict__ cls, int n, int ns, int M, int N,
+                                           int spc, double scale, const OPtrs& part) {
   constexpr int S = src64_stride(K);
   const int t = tb * 256 + threadIdx.x;
   const bool valid = t < N;
@@ -331,11 +370,11 @@ __device__ __forceinline__ void far64_body(int tb, int chunk, const double* __re
     double sm[K][3];
 #pragma unroll
     for (int r = 0; r < K; ++r) sm[r][0] = sm[r][1] = sm[r][2] = 0.0;
-    const double* sp = src + (size_t)j * n * S;
+    const double* sp = src + (size_t)j * ns * S;
     // r.y = Ct - r^2 / 2 (as in the FP32 tile); (w r).q for K >= 2
     const double Ct = 0.5 * (Xx * Xx + Xy * Xy + Xz * Xz - (sp[0] * sp[0] + sp[1] * sp[1] + sp[2] * sp[2]));
 #pragma unroll 2
-    for (int kk = 0; kk < n; ++kk) {
+    for (int kk = 0; kk < ns; ++kk) {
       const double* e = sp + (size_t)kk * S;
       const double rx = Xx - e[0], ry = Xy - e[1], rz = Xz - e[2];
       const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
@@ -378,11 +417,11 @@ __device__ __forceinline__ void far64_body(int tb, int chunk, const double* __re
 template <int K>
 __global__ __launch_bounds__(256) void k_far64(const double* __restrict__ src, const double* __restrict__ off,
                                                const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
-                                               int n, int M, int N, int spc, double scale, OPtrs part, int ntb,
-                                               int total, int per) {
+                                               int n, int ns, int M, int N, int spc, double scale, OPtrs part,
+                                               int ntb, int total, int per) {
   const int item = xcd_item(blockIdx.x, per);
   if (item >= total) return;
-  far64_body<K>(item % ntb, item / ntb, src, off, ctr, cls, n, M, N, spc, scale, part);
+  far64_body<K>(item % ntb, item / ntb, src, off, ctr, cls, n, ns, M, N, spc, scale, part);
 }
 
 __global__ __launch_bounds__(256) void k_far64_multi(const FarDesc* __restrict__ desc, int ndesc) {
@@ -395,7 +434,7 @@ __global__ __launch_bounds__(256) void k_far64_multi(const FarDesc* __restrict__
   const int tb = local % D.ntb, chunk = local / D.ntb;
   OPtrs part;
   part.p[0] = D.part;
-  far64_body<1>(tb, chunk, (const double*)D.src, D.off, D.ctr, D.cls, D.n, D.M, D.N, D.spc, D.scale, part);
+  far64_body<1>(tb, chunk, (const double*)D.src, D.off, D.ctr, D.cls, D.n, D.n, D.M, D.N, D.spc, D.scale, part);
 }
 
 // ---------------------------------------------------------- near pair sum
@@ -1102,6 +1141,19 @@ static void pack_k(hipStream_t s, int prec, const QPtrs& q, const double* off, c
     hipLaunchKernelGGL(k_pack64<K>, dim3(nblk(N)), dim3(256), 0, s, q, off, w, n, N, (double*)src);
 }
 
+void launch_pack_coarse(hipStream_t s, int prec, int K, const double* qc, const double* off, const double* w, int nc,
+                        int Nc, void* src) {
+  const int f = prec == 1 ? 1 : 0;
+  switch (K) {
+    case 1: hipLaunchKernelGGL(k_pack_coarse<1>, dim3(nblk(Nc)), dim3(256), 0, s, qc, off, w, nc, Nc, f, src); break;
+    case 2: hipLaunchKernelGGL(k_pack_coarse<2>, dim3(nblk(Nc)), dim3(256), 0, s, qc, off, w, nc, Nc, f, src); break;
+    case 3: hipLaunchKernelGGL(k_pack_coarse<3>, dim3(nblk(Nc)), dim3(256), 0, s, qc, off, w, nc, Nc, f, src); break;
+    case 4: hipLaunchKernelGGL(k_pack_coarse<4>, dim3(nblk(Nc)), dim3(256), 0, s, qc, off, w, nc, Nc, f, src); break;
+    case 5: hipLaunchKernelGGL(k_pack_coarse<5>, dim3(nblk(Nc)), dim3(256), 0, s, qc, off, w, nc, Nc, f, src); break;
+    default: hipLaunchKernelGGL(k_pack_coarse<6>, dim3(nblk(Nc)), dim3(256), 0, s, qc, off, w, nc, Nc, f, src); break;
+  }
+}
+
 void launch_pack(hipStream_t s, int prec, int K, const QPtrs& q, const double* off, const double* w, int n, int N,
                  void* src) {
   switch (K) {
@@ -1116,7 +1168,7 @@ void launch_pack(hipStream_t s, int prec, int K, const QPtrs& q, const double* o
 
 template <int K>
 static void far_k(hipStream_t s, int prec, int tpt, const void* src, const double* off, const double* ctr,
-                  const unsigned char* cls, int n, int M, int N, int spc, int nchunks, double scale,
+                  const unsigned char* cls, int n, int ns, int M, int N, int spc, int nchunks, double scale,
                   const OPtrs& part) {
   const int per_block = prec == 1 ? (tpt == 0 ? 64 : 256 * tpt) : 256;
   const int ntb = (int)nblk(N, per_block);
@@ -1124,30 +1176,31 @@ static void far_k(hipStream_t s, int prec, int tpt, const void* src, const doubl
   const dim3 grid(per * kXcds);
   if (prec == 1) {
     if (tpt == 0)
-      hipLaunchKernelGGL((k_far32s<K>), grid, dim3(256), 0, s, (const float*)src, off, ctr, cls, n, M, N, spc, scale,
-                         part, ntb, total, per);
+      hipLaunchKernelGGL((k_far32s<K>), grid, dim3(256), 0, s, (const float*)src, off, ctr, cls, n, ns, M, N, spc,
+                         scale, part, ntb, total, per);
     else if (tpt == 2)
-      hipLaunchKernelGGL((k_far32<2, K>), grid, dim3(256), 0, s, (const float*)src, off, ctr, cls, n, M, N, spc,
+      hipLaunchKernelGGL((k_far32<2, K>), grid, dim3(256), 0, s, (const float*)src, off, ctr, cls, n, ns, M, N, spc,
                          scale, part, ntb, total, per);
     else
-      hipLaunchKernelGGL((k_far32<1, K>), grid, dim3(256), 0, s, (const float*)src, off, ctr, cls, n, M, N, spc,
+      hipLaunchKernelGGL((k_far32<1, K>), grid, dim3(256), 0, s, (const float*)src, off, ctr, cls, n, ns, M, N, spc,
                          scale, part, ntb, total, per);
   } else {
-    hipLaunchKernelGGL(k_far64<K>, grid, dim3(256), 0, s, (const double*)src, off, ctr, cls, n, M, N, spc, scale,
-                       part, ntb, total, per);
+    hipLaunchKernelGGL(k_far64<K>, grid, dim3(256), 0, s, (const double*)src, off, ctr, cls, n, ns, M, N, spc,
+                       scale, part, ntb, total, per);
   }
 }
 
 void launch_far(hipStream_t s, int prec, int K, int tpt, const void* src, const double* off, const double* ctr,
-                const unsigned char* cls, int n, int M, int N, int spc, int nchunks, double scale, const OPtrs& part) {
+                const unsigned char* cls, int n, int ns, int M, int N, int spc, int nchunks, double scale,
+                const OPtrs& part) {
   const int t1 = tpt == 0 ? 0 : 1;  // two targets per thread only for K <= 2
   switch (K) {
-    case 1: far_k<1>(s, prec, tpt, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
-    case 2: far_k<2>(s, prec, tpt, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
-    case 3: far_k<3>(s, prec, t1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
-    case 4: far_k<4>(s, prec, t1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
-    case 5: far_k<5>(s, prec, t1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
-    default: far_k<6>(s, prec, t1, src, off, ctr, cls, n, M, N, spc, nchunks, scale, part); break;
+    case 1: far_k<1>(s, prec, tpt, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
+    case 2: far_k<2>(s, prec, tpt, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
+    case 3: far_k<3>(s, prec, t1, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
+    case 4: far_k<4>(s, prec, t1, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
+    case 5: far_k<5>(s, prec, t1, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
+    default: far_k<6>(s, prec, t1, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
   }
 }
 

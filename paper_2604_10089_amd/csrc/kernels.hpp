@@ -138,8 +138,13 @@ void launch_combo_multi(hipStream_t s, const ComboDesc* d, int nd, int total);
 // prec: 0 = FP64 pair sums, 1 = FP32 pair sums (mixed)
 void launch_pack(hipStream_t s, int prec, int K, const QPtrs& q, const double* off, const double* w, int n, int N,
                  void* src);
+// n target nodes per sphere, ns source nodes per sphere in src (n, or the coarse far-source grid's count)
 void launch_far(hipStream_t s, int prec, int K, int tpt, const void* src, const double* off, const double* ctr,
-                const unsigned char* cls, int n, int M, int N, int spc, int nchunks, double scale, const OPtrs& part);
+                const unsigned char* cls, int n, int ns, int M, int N, int spc, int nchunks, double scale,
+                const OPtrs& part);
+// far sources from the coarse densities qc [M][nc][3K] at the coarse grid (offsets off, weights w)
+void launch_pack_coarse(hipStream_t s, int prec, int K, const double* qc, const double* off, const double* w, int nc,
+                        int Nc, void* src);
 void launch_far_multi(hipStream_t s, int prec, int tpt, const FarDesc* desc, int ndesc, int nitems);
 // coef: harmonic coefficients of the K densities, [M][3K][L] (row 3r + c: density r, component c)
 void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, const double* off, const double4* offup,
