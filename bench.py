@@ -110,6 +110,10 @@ def main():
     ap.add_argument('--contact-probe', action='store_true',
                     help='short run for rocprofv3 --kernel-trace: only the five time steps with active contacts '
                          '(FP64, then the mixed replay), one JSON line')
+    ap.add_argument('--cpu-table', action='store_true',
+                    help='instead of the benchmark line: the CPU oracle timed on the host cores on the 8-sphere '
+                         '(full MVP and Mono-PQN LCP with the assembled operator), 27-, 64- and 216-sphere '
+                         'workloads (one matvec over all cores), beside the GPU path on the same inputs')
     ap.add_argument('--lcp-table', action='store_true',
                     help='instead of the benchmark line: BB-PGD, Mono-PQN and Bi-PQN on planted LCPs of the 27-, '
                          '64- and 216-sphere workloads (three seeds each), one JSON line')
@@ -154,6 +158,10 @@ def main():
 
     if args.lcp_table:
         print(json.dumps(lcp_table(binding, inputs, stream)), flush=True)
+        return
+
+    if args.cpu_table:
+        print(json.dumps(cpu_table(binding, inputs, stream)), flush=True)
         return
 
     if args.contact_probe:
@@ -578,11 +586,14 @@ def contact_steps(binding, inputs, torch, stream, w, args, replay_solvers=True):
                 replay(cs, 'mono', 'mono_pqn', active_k)
                 replay(cs, 'bb', 'bb_pgd', active_k)
         if replay_solvers:
-            # Bi-PQN whose low fidelity is the same grid solved to GMRES 1e-3
-            with binding.Context(c, ax_in, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3,
-                                 precision='mixed', tune_K=1, warm_start=True, near_close_gap=0.02,
-                                 near_close_up=3, stream=stream.cuda_stream, side_stream=not args.serial) as cs:
-                replay(cs, 'bi', 'bi_pqn_tol_fidelity', active_k)
+            # Bi-PQN whose low fidelity is the same grid solved to GMRES 1e-3, and the same grid
+            # with far pairs from a 6x12 source grid (degree 5) at GMRES 1e-3
+            for name, kw_lo in (('bi_pqn_tol_fidelity', {}), ('bi_pqn_coarse_far', dict(far_coarse_lo=6))):
+                with binding.Context(c, ax_in, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3,
+                                     precision='mixed', tune_K=1, warm_start=True, near_close_gap=0.02,
+                                     near_close_up=3, stream=stream.cuda_stream, side_stream=not args.serial,
+                                     **kw_lo) as cs:
+                    replay(cs, 'bi', name, active_k)
         inward_info = dict(steps=nin, dt=dt_in, near_close_gap=0.02, near_close_up=3,
                            axes='towards the centroid',
                            contacts=[r[1]['n_contacts'] for r in rows], active=[r[1]['n_active'] for r in rows],
@@ -608,7 +619,10 @@ def lcp_table(binding, inputs, stream):
     initial metric and with Alg. 1's printed H^(0) = I), Bi-PQN with the same grid at
     GMRES tolerance 1e-3 as low fidelity, and recursive Bi-PQN over both (same grid at 1e-3,
     then the coarse grid at 1e-3). E-MVP = high + low x (low-fidelity product time /
-    high-fidelity product time) summed over the fidelities, all measured."""
+    high-fidelity product time) summed over the fidelities, all measured. The coarse-far
+    variants take the same grid with far pairs from a 6x12 source grid (density truncated to
+    degree 5) as the low fidelity, at GMRES 1e-8 (bi_cf) and 1e-3 (bi_cf_tol), and recursive
+    Bi-PQN over that model and the coarse grid at 1e-3 (birec_cf)."""
     import torch
     rows = []
     for name in ('lattice27_contacts', 'packing64', 'rsa216'):
@@ -632,10 +646,17 @@ def lcp_table(binding, inputs, stream):
                     row[key] = dict(hi=st['mvp_hi'], lo=st['mvp_lo'], emvp=round(st['emvp'], 2),
                                        sec=round(time.perf_counter() - t0, 3), conv=st['converged'],
                                        x_err=float(np.abs(x - xs).max() / np.abs(xs).max()))
-            with binding.Context(c, None, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3,
-                                 lo2=w['lo'], gmres_tol_lo2=1e-3, precision='mixed', stream=stream.cuda_stream,
-                                 tune_K=1) as ctx:
-                for key, solver in (('bi_tol', 'bi'), ('birec', 'birec')):
+            variants = (('bi_tol', 'bi', dict(gmres_tol_lo=1e-3, lo2=w['lo'], gmres_tol_lo2=1e-3)),
+                        ('birec', 'birec', dict(gmres_tol_lo=1e-3, lo2=w['lo'], gmres_tol_lo2=1e-3)),
+                        ('bi_cf', 'bi', dict(gmres_tol_lo=1e-8, far_coarse_lo=6)),
+                        ('bi_cf_tol', 'bi', dict(gmres_tol_lo=1e-3, far_coarse_lo=6)),
+                        ('birec_cf', 'birec', dict(gmres_tol_lo=1e-3, far_coarse_lo=6, lo2=w['lo'],
+                                                   gmres_tol_lo2=1e-3)))
+            for key, solver, kw_lo in variants:
+                with binding.Context(c, None, nt, nph, lo=(nt, nph), gmres_tol=1e-8, precision='mixed',
+                                     stream=stream.cuda_stream, tune_K=1, **kw_lo) as ctx:
+                    if key.startswith('bi_cf'):
+                        ctx.lcp_solve(pairs, b, solver)     # warm the coarse-grid buffers
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
                     x, st = ctx.lcp_solve(pairs, b, solver)
@@ -650,8 +671,71 @@ def lcp_table(binding, inputs, stream):
         rs = [r for r in rows if r['workload'] == name]
         if rs:
             med[name] = {k: float(np.median([r[k]['emvp'] for r in rs]))
-                         for k in ('bb', 'mono', 'bi', 'bi_tol', 'birec', 'mono_printed', 'bi_printed')}
+                         for k in ('bb', 'mono', 'bi', 'bi_tol', 'birec', 'bi_cf', 'bi_cf_tol', 'birec_cf',
+                                   'mono_printed', 'bi_printed')}
+            med[name + '_sec'] = {k: float(np.median([r[k]['sec'] for r in rs]))
+                                  for k in ('bb', 'mono', 'bi', 'bi_tol', 'birec', 'bi_cf', 'bi_cf_tol', 'birec_cf')}
     return dict(table='planted LCPs, mixed precision, KKT 1e-8', rows=rows, median_emvp=med)
+
+
+def cpu_table(binding, inputs, stream):
+    """The CPU oracle on the host cores against the GPU path, per workload: the 8-sphere
+    workload end to end on one core (assembled operator, LU factorisation as set-up, one
+    MVP and one Mono-PQN LCP on its contact set), and one matvec of the 27-, 64- and
+    216-sphere operators over all cores (cpu_baseline), with the GPU path's GMRES iterations
+    per MVP (mixed, 1e-8) to turn matvecs into MVPs."""
+    import torch
+    from oracle import bie, dynamics, lcp
+    out = {}
+    # 8 spheres: everything by the assembled operator, one core
+    w = inputs.workload('tiny', 0)
+    c = w['centers']
+    g = bie.Geometry(c, 1.0, w['n_theta'], w['n_phi'])
+    t0 = time.perf_counter()
+    A = bie.dense_operator(g)
+    FT = inputs.random_forces(1, g.M)
+    bie.mobility_apply(g, FT, dense=A)        # LU factorisation (set-up)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bie.mobility_apply(g, inputs.random_forces(2, g.M), dense=A)
+    t_mvp = time.perf_counter() - t0
+    pairs, _ = dynamics.find_contacts(c, 1.0, 0.1)
+    Aop = lcp.lcp_operator(lambda F: bie.mobility_apply(g, F, dense=A), c, pairs)
+    xs, ws = inputs.planted_lcp(0, pairs.shape[0])
+    b = ws - Aop(xs)
+    t0 = time.perf_counter()
+    _, _, st = lcp.mono_pqn(Aop, b)
+    t_lcp = time.perf_counter() - t0
+    with binding.Context(c, None, w['n_theta'], w['n_phi'], gmres_tol=1e-8, precision='mixed',
+                         stream=stream.cuda_stream) as ctx:
+        ctx.mobility_apply(FT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.mobility_apply(FT)
+        t_gpu_mvp = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, sg = ctx.lcp_solve(pairs, b, 'mono')
+        t_gpu_lcp = time.perf_counter() - t0
+    out['tiny'] = dict(nodes=g.N, cores=1, setup_sec=round(t_setup, 3), mvp_sec=round(t_mvp, 5),
+                       lcp_sec=round(t_lcp, 4), lcp_mvps=st['mvp'], gpu_mvp_sec=round(t_gpu_mvp, 5),
+                       gpu_lcp_sec=round(t_gpu_lcp, 4), gpu_lcp_mvps=sg['mvp_hi'])
+    print('[cpu-table]', 'tiny', out['tiny'], file=sys.stderr, flush=True)
+    for name in ('lattice27', 'packing64', 'rsa216'):
+        w = inputs.workload(name, 0)
+        c, nt, nph = w['centers'], w['n_theta'], w['n_phi']
+        FT = inputs.random_forces(3, c.shape[0])
+        with binding.Context(c, None, nt, nph, gmres_tol=1e-8, precision='mixed', stream=stream.cuda_stream,
+                             tune_K=1) as ctx:
+            ctx.mobility_apply(FT)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, sg = ctx.mobility_apply(FT)
+            t_gpu = time.perf_counter() - t0
+        cb = cpu_baseline(c, nt, nph, {'matvecs_per_mvp': float(sg['matvecs'])})
+        out[name] = dict(nodes=int(c.shape[0] * nt * nph), gmres_matvecs_per_mvp=sg['matvecs'],
+                         gpu_mvp_sec=round(t_gpu, 4), gpu_mvps_per_s=round(1.0 / t_gpu, 3), cpu=cb)
+        print('[cpu-table]', name, out[name], file=sys.stderr, flush=True)
+    return out
 
 
 def cpu_model():
@@ -742,7 +826,8 @@ def cpu_baseline(c, nt, nph, mixed):
     t1 = sum(r[0] for r in res) + t_near_all + t_self
     tall = max(r[0] for r in res) + t_near_all / cores + t_self
     mpm = mixed['matvecs_per_mvp']
-    detail = (f'one matvec of the 216-sphere operator: all {far_pairs_done:,} far pairs by the oracle\'s '
+    detail = (f'one matvec of the {g.M}-sphere operator ({nt}x{nph}): all {far_pairs_done:,} far pairs by the '
+              f'oracle\'s '
               f'double-layer sums in {cores} single-threaded processes (target spheres dealt round-robin), '
               f'self block and rigid projection of all spheres, near-pair blocks applied on {len(sample)} '
               f'of {len(near)} (built before the timed region) and scaled; x {mpm:.1f} matvecs per MVP')
