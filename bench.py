@@ -105,8 +105,9 @@ def main():
                     help='short run for rocprofv3 --pmc: a 256 MiB device copy (scale reference for FETCH_SIZE/'
                          'WRITE_SIZE) and one six-force-set product on the 216-sphere workload')
     ap.add_argument('--batch-probe', action='store_true',
-                    help='short run for rocprofv3 --kernel-trace: only the 32-suspension batch, mixed precision '
-                         '(one warm-up product and three timed ones), one JSON line')
+                    help='short run for rocprofv3 --kernel-trace: only the 32-suspension batch, mixed precision, '
+                         'GMRES iterations from captured graphs (one warm-up product and three timed ones), one '
+                         'JSON line')
     ap.add_argument('--contact-probe', action='store_true',
                     help='short run for rocprofv3 --kernel-trace: only the five time steps with active contacts '
                          '(FP64, then the mixed replay), one JSON line')
@@ -173,7 +174,7 @@ def main():
         FTb = [inputs.random_forces(500 + b, ci.shape[0]) for b, (ci, _, _) in enumerate(inst)]
         kwp = dict(tpt=args.tpt) if args.tpt else {}
         with binding.BatchContext(inst, gmres_tol=1e-8, precision='mixed', stream=stream.cuda_stream,
-                                  side_stream=not args.serial, **kwp) as bc:
+                                  side_stream=not args.serial, graphs=True, **kwp) as bc:
             bc.mobility_apply(FTb)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
