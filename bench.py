@@ -523,7 +523,7 @@ def main():
         'time_steps_with_contacts': inward_info,
     }
     out['host'] = {'gpu': torch.cuda.get_device_name(0), 'cpu_model': cpu_model(),
-                   'cpu_threads_available': len(os.sched_getaffinity(0))}
+                   'cpu_threads_available': len(os.sched_getaffinity(0)), 'gpu_sclk_mhz': gpu_sclk()}
     if not args.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline(c, nt, nph, res['mixed1'])
     print(json.dumps(out), flush=True)
@@ -737,6 +737,28 @@ def cpu_table(binding, inputs, stream):
                          gpu_mvp_sec=round(t_gpu, 4), gpu_mvps_per_s=round(1.0 / t_gpu, 3), cpu=cb)
         print('[cpu-table]', name, out[name], file=sys.stderr, flush=True)
     return out
+
+
+def gpu_sclk():
+    """Engine clock levels of the GPU from sysfs after the timed region: {'levels': [MHz...], 'current': MHz},
+    or None where the driver does not expose them."""
+    import glob
+    for path in sorted(glob.glob('/sys/class/drm/card*/device/pp_dpm_sclk')):
+        try:
+            levels, cur = [], None
+            with open(path) as f:
+                for line in f:
+                    parts = line.split()
+                    if len(parts) >= 2 and parts[1].lower().endswith('mhz'):
+                        mhz = int(parts[1][:-3])
+                        levels.append(mhz)
+                        if '*' in line:
+                            cur = mhz
+            if levels:
+                return {'levels': levels, 'current': cur}
+        except (OSError, ValueError):
+            continue
+    return None
 
 
 def cpu_model():

@@ -88,6 +88,17 @@ __global__ __launch_bounds__(256) void k_pack_coarse(const double* __restrict__ 
   }
 }
 
+// 1/sqrt(x) in FP64 for finite x > 0 (squared distances of distinct points):
+// the hardware estimate y0 refined once by the second-order expansion of
+// (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., e = 1 - x y0^2. Six VALU
+// instructions; the library rsqrt adds a class test and two selects for zero,
+// infinite and denormal arguments, which cannot occur here.
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 // ----------------------------------------------------------- far pair sum
 //
 // u_r(x) += 3/(4 pi a) sum_y r (r.wq_r,y)(r.o_y)/|r|^5, r = x - y, for every
@@ -378,7 +389,7 @@ __device__ __forceinline__ void far64_body(int tb, int chunk, const double* __re
       const double* e = sp + (size_t)kk * S;
       const double rx = Xx - e[0], ry = Xy - e[1], rz = Xz - e[2];
       const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-      const double ri = rsqrt(r2);
+      const double ri = rsqrt_pos(r2);
       const double ri2 = ri * ri;
       const double rn = fma(-0.5, r2, Ct);
       const double wgt = rn * ri * ri2 * ri2;
@@ -549,6 +560,12 @@ __device__ __forceinline__ void near_body(int pair, int chunk, const double* __r
     }
   }
   const int f0 = (wv * nup) / kNearWaves, f1 = ((wv + 1) * nup) / kNearWaves;
+  // r.o = Ct - r^2 / 2 with Ct = (|X|^2 - |o|^2) / 2 (all upsampled nodes lie
+  // on the sphere): one FMA per pair instead of a dot product. Ct and r^2 are
+  // O(|X|^2) while r.o is O(|X| a), so the rounding grows like |X| / a: below
+  // 3 for near targets at the default near gap (0.5 a).
+  const double4 o0 = offup[0];
+  const double Ct = 0.5 * (Xx * Xx + Xy * Xy + Xz * Xz - (o0.x * o0.x + o0.y * o0.y + o0.z * o0.z));
   double a[K][3];
 #pragma unroll
   for (int r = 0; r < K; ++r) a[r][0] = a[r][1] = a[r][2] = 0.0;
@@ -558,9 +575,9 @@ __device__ __forceinline__ void near_body(int pair, int chunk, const double* __r
     const double4 o = offup[fi];
     const double rx = Xx - o.x, ry = Xy - o.y, rz = Xz - o.z;
     const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-    const double ri = rsqrt(r2);
+    const double ri = rsqrt_pos(r2);
     const double ri2 = ri * ri;
-    const double rn = fma(rx, o.x, fma(ry, o.y, rz * o.z));
+    const double rn = fma(-0.5, r2, Ct);
     const double wgt = o.w * rn * ri * ri2 * ri2;
     if constexpr (K == 1) {
       const double* qx = qup + ((size_t)j * nup + fi) * 3;
