@@ -118,6 +118,14 @@ typedef struct {
                                representation for its low fidelity; with n_theta_lo = n_theta this lowers
                                it for the far field only. 0 = the node rule; else 2..n_theta_lo */
   int32_t far_coarse_lo2;   /* the same for the second low fidelity (2..n_theta_lo2) */
+  int32_t precond;          /* 1 = every GMRES solve is right-preconditioned (Sec. 2 calls for
+                               preconditioned Krylov solves without fixing one): for sphere i with
+                               near partners j, (P v)_i = inv(S_i) (v_i - sum_j A_ij inv(D) v_j),
+                               S_i = D - sum_j A_ij inv(D) A_ji, D the single-sphere block and A_ij
+                               the near blocks. Same solution and stopping rule (true residual);
+                               fewer iterations. Built at the first solve after each configuration
+                               change (pqn_mvp_stats.t_precond_ms); device memory about
+                               (2 n_near + 4 M) (3n)^2 doubles. Not for batch contexts [0] */
 } pqn_config_desc;
 
 typedef struct {
@@ -138,6 +146,9 @@ typedef struct {
   double t_gemm_ms;         /* harmonic coefficients, self interaction and upsampling GEMMs */
   double t_local_ms;        /* packing, rigid moments and the final combination */
   double t_arnoldi_ms;      /* CGS2 dot products and vector updates of GMRES */
+  double t_precond_ms;      /* precond = 1: wall time of preconditioner set-ups in this call */
+  int32_t precond_fallback; /* precond = 1: spheres whose Schur complement inverse did not converge
+                               in those set-ups (they use inv(D)) */
 } pqn_mvp_stats;
 
 typedef struct {
@@ -318,6 +329,13 @@ pqn_status pqn_get_grid(pqn_ctx* ctx, int32_t fidelity, int32_t* n_nodes, double
  * n = n_theta * n_phi. */
 pqn_status pqn_host_self_block(int32_t n_theta, int32_t n_phi, double radius, double* offsets, double* weights,
                                double* S);
+
+/* Host-only (no device needed): the single-sphere block D = 1/2 I + S + P_rigid (self
+ * interaction and rigid projection of one sphere, the diagonal block of the discrete
+ * operator) and its inverse, as the precond = 1 set-up builds them. D, Dinv [3n][3n]
+ * row-major in the SoA order of one sphere (row c n + node); either may be NULL.
+ * PQN_ERR_NUMERIC if D is singular. */
+pqn_status pqn_host_sphere_block(int32_t n_theta, int32_t n_phi, double radius, double* D, double* Dinv);
 
 const char* pqn_last_error(void);
 

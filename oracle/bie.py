@@ -467,13 +467,19 @@ def operator_apply(geom, q):
 
 # ------------------------------------------------------------------- GMRES
 
-def gmres(apply, rhs, tol=1e-13, restart=50, maxiter=1000, x0=None):
+def gmres(apply, rhs, tol=1e-13, restart=50, maxiter=1000, x0=None, right=None):
     """Restarted GMRES (modified Gram-Schmidt Arnoldi, Givens rotations).
 
     Textbook GMRES(m) from the initial guess x0 (default 0): stops when the
-    residual norm falls below tol * ||rhs||.
+    residual norm falls below tol * ||rhs||. With a right preconditioner
+    `right` (a linear map P), the Krylov space is built for the operator A P
+    and every cycle ends with x += P (V y): the residual, and so the stopping
+    rule, is that of x itself.
     Returns (x, iterations, final relative residual estimate).
     """
+    if right is not None:
+        a0 = apply
+        apply = lambda v: a0(right(v.ravel()).reshape(v.shape))  # noqa: E731
     b = rhs.ravel().astype(np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64).ravel()
     bnorm = np.linalg.norm(b)
@@ -481,7 +487,7 @@ def gmres(apply, rhs, tol=1e-13, restart=50, maxiter=1000, x0=None):
         return x, 0, 0.0
     its = 0
     while True:
-        r = b - apply(x.reshape(rhs.shape)).ravel()
+        r = b - (apply(x.reshape(rhs.shape)) if right is None else a0(x.reshape(rhs.shape))).ravel()
         beta = np.linalg.norm(r)
         if beta <= tol * bnorm or its >= maxiter:
             return x, its, beta / bnorm
@@ -515,7 +521,49 @@ def gmres(apply, rhs, tol=1e-13, restart=50, maxiter=1000, x0=None):
                 break
         m = k + 1
         y = np.linalg.solve(np.triu(H[:m, :m]), g[:m])
-        x += V[:m].T @ y
+        x += V[:m].T @ y if right is None else right(V[:m].T @ y)
+
+
+# --------------------------------------------------------- preconditioner
+
+def near_patch_preconditioner(geom, A):
+    """Right preconditioner of the BIE's GMRES from its assembled matrix A (node-major).
+
+    Sec. 2 calls for preconditioned Krylov solves of the mobility problem
+    without naming a preconditioner; this is the one the GPU path uses. With D
+    the diagonal block of one sphere (the same for every sphere) and A_ij the
+    block of a near pair (gap < near_gap), sphere i's part of P v is
+        S_i^{-1} (v_i - sum_j A_ij D^{-1} v_j),   S_i = D - sum_j A_ij D^{-1} A_ji:
+    the row of sphere i of the inverse of its near patch, partner-partner
+    coupling dropped (a Schur complement). Returns P as a function of a flat
+    node-major vector. Pinned by: one sphere gives P = D^{-1} = A^{-1}; two
+    spheres that are each other's only near partner give P = A^{-1}
+    (block inverse by Schur complements) (tests/test_oracle_bie.py).
+    """
+    n3, M = 3 * geom.n, geom.M
+    blk = lambda i, j: A[i * n3:(i + 1) * n3, j * n3:(j + 1) * n3]  # noqa: E731
+    D = blk(0, 0)
+    Di = np.linalg.inv(D)
+    cls = geom.pair_class()
+    nbr = [[j for j in range(M) if j != i and cls[i, j] == 1] for i in range(M)]
+    Sinv = []
+    for i in range(M):
+        S = D.copy()
+        for j in nbr[i]:
+            S -= blk(i, j) @ Di @ blk(j, i)
+        Sinv.append(np.linalg.inv(S))
+
+    def apply(v):
+        v = np.asarray(v, dtype=np.float64).reshape(M, n3)
+        y = v @ Di.T
+        out = np.empty_like(v)
+        for i in range(M):
+            r = v[i].copy()
+            for j in nbr[i]:
+                r -= blk(i, j) @ y[j]
+            out[i] = Sinv[i] @ r
+        return out.ravel()
+    return apply
 
 
 # --------------------------------------------------------------- mobility

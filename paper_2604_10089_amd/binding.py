@@ -35,7 +35,8 @@ class ConfigDesc(C.Structure):
                 ('warm_start', C.c_int32), ('n_theta_lo2', C.c_int32), ('n_phi_lo2', C.c_int32),
                 ('gmres_tol_lo2', C.c_double), ('dev_alloc', _ALLOC_FN), ('dev_free', _FREE_FN),
                 ('alloc_user', C.c_void_p), ('side_stream', C.c_int32), ('near_close_gap', C.c_double),
-                ('near_close_up', C.c_int32), ('far_coarse_lo', C.c_int32), ('far_coarse_lo2', C.c_int32)]
+                ('near_close_up', C.c_int32), ('far_coarse_lo', C.c_int32), ('far_coarse_lo2', C.c_int32),
+                ('precond', C.c_int32)]
 
 
 class TorchAllocator:
@@ -75,7 +76,8 @@ class MvpStats(C.Structure):
                 ('converged', C.c_int32), ('rel_residual', C.c_double), ('t_total_ms', C.c_double),
                 ('t_far_ms', C.c_double), ('n_far', C.c_int32), ('graph_launches', C.c_int32),
                 ('fp64_fallback', C.c_int32), ('t_near_ms', C.c_double), ('t_gemm_ms', C.c_double),
-                ('t_local_ms', C.c_double), ('t_arnoldi_ms', C.c_double)]
+                ('t_local_ms', C.c_double), ('t_arnoldi_ms', C.c_double), ('t_precond_ms', C.c_double),
+                ('precond_fallback', C.c_int32)]
 
 
 class LcpOpts(C.Structure):
@@ -154,6 +156,7 @@ def lib():
         'pqn_bie_solve': (C.c_int, [V, C.c_int32, _D, _D, _P(MvpStats)]),
         'pqn_get_grid': (C.c_int, [V, C.c_int32, _I, _D, _D]),
         'pqn_host_self_block': (C.c_int, [C.c_int32, C.c_int32, C.c_double, _D, _D, _D]),
+        'pqn_host_sphere_block': (C.c_int, [C.c_int32, C.c_int32, C.c_double, _D, _D]),
         'pqn_mobility_apply_multi': (C.c_int, [V, C.c_int32, _D, _D, C.c_int32, _P(MvpStats)]),
         'pqn_batch_create': (C.c_int, [C.c_int32, _P(ConfigDesc), _P(_D), _P(_D), _P(V)]),
         'pqn_batch_mobility_apply': (C.c_int, [V, _P(_D), _P(_D), _P(MvpStats), _P(MvpStats)]),
@@ -201,11 +204,21 @@ def pqn_host_self_block(n_theta, n_phi, radius=1.0):
     return off, w, S
 
 
+def pqn_host_sphere_block(n_theta, n_phi, radius=1.0):
+    """(D, D^{-1}), the single-sphere block 1/2 I + S + P_rigid [3n,3n] (SoA order) and its
+    inverse, built on the host without a device."""
+    n3 = 3 * n_theta * n_phi
+    D = np.zeros((n3, n3))
+    Di = np.zeros((n3, n3))
+    _check(lib().pqn_host_sphere_block(n_theta, n_phi, radius, _dptr(D), _dptr(Di)))
+    return D, Di
+
+
 def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_tol_lo=None, restart=50,
           max_iter=500, near_gap=0.0, near_up=2, slip=1.0, precision='fp64', refine=0, tpt=2, far_chunks=0,
           far_split=0, device=0, stream=None, profile=False, graphs=False, warm_start=False, lo2=None,
           gmres_tol_lo2=None, allocator=None, side_stream=False, near_close_gap=0.0, near_close_up=3,
-          far_coarse_lo=0, far_coarse_lo2=0):
+          far_coarse_lo=0, far_coarse_lo2=0, precond=False):
     d = ConfigDesc()
     d.n_particles = M
     d.radius, d.mu = radius, mu
@@ -234,6 +247,7 @@ def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_
     d.side_stream = 1 if side_stream else 0
     d.near_close_gap, d.near_close_up = near_close_gap, near_close_up
     d.far_coarse_lo, d.far_coarse_lo2 = far_coarse_lo, far_coarse_lo2
+    d.precond = 1 if precond else 0
     return d
 
 
@@ -346,7 +360,7 @@ class Context:
                  slip=1.0, precision='fp64', refine=0, tpt=None, far_chunks=None, far_split=None, device=0,
                  stream=None, profile=False, tune_K=1, graphs=False, warm_start=False, lo2=None,
                  gmres_tol_lo2=None, torch_alloc=False, side_stream=False, near_close_gap=0.0, near_close_up=3,
-                 far_coarse_lo=0, far_coarse_lo2=0):
+                 far_coarse_lo=0, far_coarse_lo2=0, precond=False):
         c = _f64(centers).reshape(-1, 3)
         self.M = c.shape[0]
         self._alloc = None
@@ -365,7 +379,8 @@ class Context:
                   far_chunks=far_chunks, far_split=far_split, device=device, stream=stream, profile=profile,
                   graphs=graphs, warm_start=warm_start, lo2=lo2, gmres_tol_lo2=gmres_tol_lo2,
                   allocator=self._alloc, side_stream=side_stream, near_close_gap=near_close_gap,
-                  near_close_up=near_close_up, far_coarse_lo=far_coarse_lo, far_coarse_lo2=far_coarse_lo2)
+                  near_close_up=near_close_up, far_coarse_lo=far_coarse_lo, far_coarse_lo2=far_coarse_lo2,
+                  precond=precond)
         self.n_theta, self.n_phi, self.lo, self.lo2 = n_theta, n_phi, lo, lo2
         ax = None if axes is None else _f64(axes).reshape(-1, 3)
         h = C.c_void_p()

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, 'csrc')
 LIB = os.path.join(HERE, 'libbipqn.so')
-SOURCES = ['host_math.cpp', 'kernels.hip', 'context.hip', 'lcp.hip', 'capi.hip']
+SOURCES = ['host_math.cpp', 'kernels.hip', 'context.hip', 'precond.hip', 'lcp.hip', 'capi.hip']
 ARCH = os.environ.get('BIPQN_ARCH', 'gfx950')
 
 

@@ -50,6 +50,8 @@ static void stage_stats(const pqn_ctx_impl& c, pqn_mvp_stats& st) {
   st.t_gemm_ms = c.stage_ms[pqn_ctx_impl::kStageGemm];
   st.t_local_ms = c.stage_ms[pqn_ctx_impl::kStageLocal];
   st.t_arnoldi_ms = c.stage_ms[pqn_ctx_impl::kStageArnoldi];
+  st.t_precond_ms = c.pc_setup_ms;
+  st.precond_fallback = c.pc_fallback;
 }
 
 // nullptr if the context has the fidelities the (valid) solver needs, else the reason.
@@ -79,6 +81,7 @@ static std::string check_desc(const pqn_config_desc& c) {
     return "far_coarse_lo needs a low-fidelity grid and 2 <= far_coarse_lo <= n_theta_lo";
   if (c.far_coarse_lo2 != 0 && (c.n_theta_lo2 == 0 || c.far_coarse_lo2 < 2 || c.far_coarse_lo2 > c.n_theta_lo2))
     return "far_coarse_lo2 needs a second low-fidelity grid and 2 <= far_coarse_lo2 <= n_theta_lo2";
+  if (c.precond != 0 && c.precond != 1) return "precond must be 0 or 1";
   return "";
 }
 
@@ -145,6 +148,8 @@ pqn_status pqn_batch_create(int32_t n_inst, const pqn_config_desc* descs, const 
       fill_defaults(c);
       const std::string bad = check_desc(c);
       if (!bad.empty()) return fail(PQN_ERR_INVALID, "instance " + std::to_string(b) + ": " + bad);
+      if (c.precond) return fail(PQN_ERR_INVALID, "instance " + std::to_string(b) + ": precond is not available "
+                                                 "for batch contexts");
       if (!centers[b]) return fail(PQN_ERR_INVALID, "pqn_batch_create: NULL centres");
       if (c.precision != c0.precision || c.gmres_restart != c0.gmres_restart || c.device != c0.device ||
           c.targets_per_thread != c0.targets_per_thread || c.far_split != c0.far_split ||
@@ -193,6 +198,8 @@ static pqn_status batch_apply_common(pqn_ctx* ctx, const double* const* FT, doub
   }
   ctx->n_matvec = 0;
   ctx->n_graph_launch = 0;
+  ctx->pc_setup_ms = 0.0;
+  ctx->pc_fallback = 0;
   ctx->n_far = 0;
   std::vector<SysRef> sys;
   for (int b = 0; b < nb; ++b) {
@@ -278,6 +285,8 @@ static pqn_status mobility_multi_common(pqn_ctx* ctx, int32_t k_rhs, const doubl
   }
   ctx->n_matvec = 0;
   ctx->n_graph_launch = 0;
+  ctx->pc_setup_ms = 0.0;
+  ctx->pc_fallback = 0;
   ctx->n_far = 0;
   pqn_mvp_stats st{};
   ctx->mobility_multi(lv, k_rhs, fp, nullptr, up, &st);
@@ -372,6 +381,8 @@ static pqn_status mobility_common(pqn_ctx* ctx, const double* FT_dev, const doub
   pqn_mvp_stats st{};
   ctx->n_matvec = 0;
   ctx->n_graph_launch = 0;
+  ctx->pc_setup_ms = 0.0;
+  ctx->pc_fallback = 0;
   ctx->n_far = 0;
   ctx->mobility(lv, FT_dev, axes_dev, UO_dev, &st);
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -489,6 +500,8 @@ pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, doub
     const size_t len = 3 * (size_t)lv.N;
     ctx->n_matvec = 0;
     ctx->n_graph_launch = 0;
+    ctx->pc_setup_ms = 0.0;
+    ctx->pc_fallback = 0;
     ctx->n_far = 0;
     SysBuf& b = lv.sb(0);
     HIPCHK(hipMemcpyAsync(b.rhs.p, rhs, len * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
@@ -543,6 +556,24 @@ pqn_status pqn_host_self_block(int32_t n_theta, int32_t n_phi, double radius, do
     if (offsets) std::memcpy(offsets, t.off.data(), t.off.size() * sizeof(double));
     if (weights) std::memcpy(weights, t.w.data(), t.w.size() * sizeof(double));
     if (S) std::memcpy(S, t.S.data(), t.S.size() * sizeof(double));
+    return PQN_OK;
+  });
+}
+
+pqn_status pqn_host_sphere_block(int32_t n_theta, int32_t n_phi, double radius, double* D, double* Dinv) {
+  return guarded([&]() -> pqn_status {
+    if (!(radius > 0.0)) return fail(PQN_ERR_INVALID, "radius must be > 0");
+    if (n_theta < 2 || n_phi < 2 * n_theta - 1 || n_theta > kMaxDegree + 1)
+      return fail(PQN_ERR_INVALID, "grid needs 2 <= n_theta <= 41 and n_phi >= 2 n_theta - 1");
+    SphereTables t;
+    build_sphere_tables(n_theta, n_phi, radius, 1, t);
+    std::vector<double> d;
+    single_sphere_block(t, d);
+    if (D) std::memcpy(D, d.data(), d.size() * sizeof(double));
+    if (Dinv) {
+      invert_gauss_jordan(d, 3 * t.n);
+      std::memcpy(Dinv, d.data(), d.size() * sizeof(double));
+    }
     return PQN_OK;
   });
 }

@@ -14,10 +14,10 @@ constexpr int kMultiDotBlocks = 16;  // reduction blocks per vector in the segme
 // One GEMM problem of a segmented launch: C(r, col) = sum_k A[r lda + k] B[col ldb + k],
 // stored at C[(r / rb) rbs + (r % rb) rs + (col / cb) cbs + (col % cb) ldc] (cb = 0: no
 // column blocks).
-static void push_gemm(std::vector<GemmDesc>& v, int& blocks, int R, int Cn, int K, const double* A, int lda,
-                      const double* B, int ldb, double* C, int rb, long rbs, int ldc, int rs = 1, int cb = 0,
-                      long cbs = 0) {
-  GemmDesc d{A, B, C, rbs, R, Cn, K, lda, ldb, rb, ldc, (R + 31) / 32, blocks, rs, cb > 0 ? cb : Cn, cbs};
+void push_gemm(std::vector<GemmDesc>& v, int& blocks, int R, int Cn, int K, const double* A, int lda,
+               const double* B, int ldb, double* C, int rb, long rbs, int ldc, int rs, int cb, long cbs, int at) {
+  GemmDesc d{A, B, C, rbs, R, Cn, K, lda, ldb, rb, ldc, (R + 31) / 32, blocks, rs, cb > 0 ? cb : Cn, cbs, nullptr,
+             at};
   blocks += d.tr * ((Cn + 31) / 32);
   v.push_back(d);
 }
@@ -268,7 +268,7 @@ void add_to_groups(std::vector<MvGroup>& groups, pqn_ctx_impl* c, Level* lv, int
 
 // The interleaved upsampled densities of a group: [M][nup][3K] in the work
 // buffer of the group's first slot (grown on first use with more densities).
-static double* group_qup(MvGroup& gr, bool close = false) {
+double* group_qup(MvGroup& gr, bool close) {
   Level& lv = *gr.lv;
   Work& w0 = lv.wk(gr.slot[0]);
   DevArray<double>& buf = close ? w0.qup2 : w0.qup;
@@ -295,7 +295,7 @@ static double* group_qc(MvGroup& gr) {
   return buf.p;
 }
 
-static double* group_coef(MvGroup& gr) {
+double* group_coef(MvGroup& gr) {
   Level& lv = *gr.lv;
   DevArray<double>& buf = lv.wk(gr.slot[0]).coef;
   const size_t need = (size_t)3 * gr.K * lv.M * lv.L;
@@ -311,9 +311,9 @@ static double* group_coef(MvGroup& gr) {
 // self interaction on them, one partial per source component, and the densities on the
 // upsampled grids (one GEMM per grid for all 3K components, stored node-interleaved
 // [M][nup][3K] so that consecutive columns are consecutive addresses) (list gb).
-static void push_group_gemms(Level& lv, int K, const int* slot, const double* const* in, double* coef, double* qup,
-                             double* qup2, const int* live_flag, std::vector<GemmDesc>& ga, int& nga,
-                             std::vector<GemmDesc>& gb, int& ngb) {
+void push_group_gemms(Level& lv, int K, const int* slot, const double* const* in, double* coef, double* qup,
+                      double* qup2, const int* live_flag, std::vector<GemmDesc>& ga, int& nga,
+                      std::vector<GemmDesc>& gb, int& ngb, bool with_self) {
   const int n = lv.n, N = lv.N, L = lv.L, M = lv.M, C = 3 * K;
   const size_t a0 = ga.size(), b0 = gb.size();
   for (int r = 0; r < K; ++r) {
@@ -321,8 +321,9 @@ static void push_group_gemms(Level& lv, int K, const int* slot, const double* co
     for (int comp = 0; comp < 3; ++comp) {
       double* cb = coef + (size_t)(3 * r + comp) * L;
       push_gemm(ga, nga, L, M, n, lv.T.p, n, in[r] + (size_t)comp * N, n, cb, L, 0, C * L);
-      push_gemm(gb, ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, cb, C * L, w.selfo.p + (size_t)comp * 3 * N, n, N,
-                n);
+      if (with_self)
+        push_gemm(gb, ngb, 3 * n, M, L, lv.G.p + comp * L, 3 * L, cb, C * L, w.selfo.p + (size_t)comp * 3 * N, n,
+                  N, n);
     }
   }
   if (qup) push_gemm(gb, ngb, lv.nup, C * M, L, lv.Yup.p, L, coef, L, qup, lv.nup, 0, 1, C, C, (long)lv.nup * C);
@@ -1016,6 +1017,17 @@ void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision)
     HIPCHK(hipStreamSynchronize(s));
   };
   auto nrm_slot = [&](int i) { return hdev.p + (size_t)i * hs + 2 * (m + 1); };
+  // right preconditioning (config precond): the Arnoldi vectors enter the operator as
+  // z = P V[k] and a cycle ends with x += P (V y); set up for the current configuration
+  std::vector<char> pcs(ns, 0);
+  bool any_pc = false;
+  for (int i = 0; i < ns; ++i)
+    if (sys[i].c->cfg.precond) {
+      sys[i].c->precond_setup(*sys[i].lv);
+      sys[i].lv->sb(sys[i].slot).z.alloc((size_t)len_of(i));
+      pcs[i] = 1;
+      any_pc = true;
+    }
   // right-hand side norms
   for (int i = 0; i < ns; ++i) {
     SysBuf& b = sys[i].lv->sb(sys[i].slot);
@@ -1071,7 +1083,7 @@ void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision)
     std::vector<MvGroup> groups;
     for (int i : idx) {
       SysBuf& b = sys[i].lv->sb(sys[i].slot);
-      const double* in = use_x ? sys[i].x : b.V.p + (size_t)st[i].k * len_of(i);
+      const double* in = use_x ? sys[i].x : pcs[i] ? b.z.p : b.V.p + (size_t)st[i].k * len_of(i);
       double* out = use_x ? b.r.p : b.V.p + (size_t)(st[i].k + 1) * len_of(i);
       add_to_groups(groups, sys[i].c, sys[i].lv, sys[i].slot, in, out);
     }
@@ -1112,12 +1124,21 @@ void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision)
     for (int i = 0; i < ns; ++i)
       if (st[i].active) act.push_back(i);
     if (act.empty()) break;
-    const bool graph_iter = ns == 1 && cfg.use_graphs && !cfg.profile && sys[0].lv->nc == 0;
+    const bool graph_iter = ns == 1 && cfg.use_graphs && !cfg.profile && sys[0].lv->nc == 0 && !any_pc;
     if (graph_iter) {
       const int i = act[0];
       launch_iteration_graph(*sys[i].c, *sys[i].lv, sys[i].slot, precision == PQN_MIXED ? 1 : 0, st[i].k,
                              hdev.p + (size_t)i * hs, m);
     } else {
+      if (any_pc) {
+        std::vector<MvGroup> pg;  // z = P V[k]
+        for (int i : act)
+          if (pcs[i]) {
+            SysBuf& b = sys[i].lv->sb(sys[i].slot);
+            add_to_groups(pg, sys[i].c, sys[i].lv, sys[i].slot, b.V.p + (size_t)st[i].k * len_of(i), b.z.p);
+          }
+        for (MvGroup& gr : pg) gr.c->precond_apply(gr);
+      }
       std::vector<MvGroup> groups = build_groups(act, false);
       matvec_groups(groups, precision);
     }
@@ -1217,7 +1238,15 @@ void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision)
         y[r] = v / g.H[(size_t)r * m + r];
       }
       HIPCHK(hipMemcpyAsync(b.ycoef.p, y.data(), dk * sizeof(double), hipMemcpyHostToDevice, s));
-      launch_combo(s, sr.x, 1.0, b.V.p, len, dk, b.ycoef.p, 1.0, len);
+      if (pcs[i]) {
+        // x += P (V y) (in place in z; tmp may hold this system's right-hand side)
+        launch_combo(s, b.z.p, 0.0, b.V.p, len, dk, b.ycoef.p, 1.0, len);
+        MvGroup g1{sr.c, sr.lv, 1, {sr.slot}, {b.z.p}, {b.z.p}};
+        sr.c->precond_apply(g1);
+        launch_axpby(s, sr.x, b.z.p, 1.0, 1.0, len);
+      } else {
+        launch_combo(s, sr.x, 1.0, b.V.p, len, dk, b.ycoef.p, 1.0, len);
+      }
       g.active = false;
       const bool final_cycle = conv || sr.its >= sr.lv->max_iter;
       if (final_cycle && sr.res_out) {

@@ -124,6 +124,26 @@ struct Work {
 // Krylov storage of one linear system on one level.
 struct SysBuf {
   DevArray<double> V, x, r, rhs, tmp, d, partial, ycoef, rcoef;
+  DevArray<double> z;  // preconditioned Arnoldi vector (config precond)
+};
+
+// Right preconditioner of the level's GMRES (config precond; precond.hip): the
+// single-sphere block D, its inverse, the near blocks A_ij, the Schur complements
+// S_i = D - sum_j A_ij D^{-1} A_ji and their inverses, rebuilt at the first solve
+// after a configuration change.
+struct Precond {
+  bool has_d = false;
+  unsigned long epoch = 0;       // configuration of the tables below (0 = none yet)
+  DevArray<double> D, Dinv;      // [3n][3n] row-major
+  DevArray<double> DinvT;        // D^{-1} by columns ([3n][3n] row-major of its transpose)
+  DevArray<double> NB, TB;       // per sphere [3n][npart_i 3n] row-major, at nbo[i] doubles
+  std::vector<long> nbo;
+  DevArray<double> S, X, X2, W;  // [M][3n][3n]; S row-major, X (= S^{-1}), X2, W by columns
+  DevArray<double> res;          // [M] Newton-Schulz residuals
+  DevArray<double> vl, yl, ug;   // local vectors [M][K][3n] and K global fields [3][N]
+  int fallback = 0;              // spheres left on D^{-1} (Newton-Schulz did not converge)
+  int ns_iters = 0;              // Newton-Schulz steps of the last set-up
+  double setup_ms = 0.0;         // wall time of the last set-up
 };
 
 // Reuse of earlier solutions across the mobility products of one LCP solve (the
@@ -225,6 +245,7 @@ struct Level {
   DevArray<double> q_nc;  // density of the last slip-driven solve (warm start of the next one)
   bool has_q_nc = false;
   Recycle rc;
+  Precond pc;
   Work& wk(int k);
   SysBuf& sb(int k);
 };
@@ -247,9 +268,28 @@ struct MvGroup {
   double* out[kMaxRhs];
 };
 
+// The single-sphere block D = 1/2 I + S + P_rigid ([3n][3n] row-major, local order c n + x)
+// and the in-place inverse of a row-major n x n matrix (Gauss-Jordan, partial pivoting).
+void single_sphere_block(const SphereTables& t, std::vector<double>& D);
+void invert_gauss_jordan(std::vector<double>& A, int n);
+
 // Add density (in -> out, work slot) to the group of its (context, level).
 void add_to_groups(std::vector<MvGroup>& groups, pqn_ctx_impl* c, Level* lv, int slot, const double* in,
                    double* out);
+
+// Work buffers of a group (grown on first use with more densities): the interleaved
+// upsampled densities [M][nup][3K] and the harmonic coefficients [M][3K][L].
+double* group_qup(MvGroup& gr, bool close = false);
+double* group_coef(MvGroup& gr);
+// One GEMM problem of a segmented launch (see kernels.hpp, GemmDesc).
+void push_gemm(std::vector<GemmDesc>& v, int& blocks, int R, int Cn, int K, const double* A, int lda,
+               const double* B, int ldb, double* C, int rb, long rbs, int ldc, int rs = 1, int cb = 0, long cbs = 0,
+               int at = 0);
+// The coefficient GEMMs of a group (list ga) and its self-interaction (with_self) and
+// upsampling GEMMs (list gb).
+void push_group_gemms(Level& lv, int K, const int* slot, const double* const* in, double* coef, double* qup,
+                      double* qup2, const int* live_flag, std::vector<GemmDesc>& ga, int& nga,
+                      std::vector<GemmDesc>& gb, int& ngb, bool with_self = true);
 
 // One linear system (1/2 + D + P) x = rhs in the lockstep GMRES engine.
 struct SysRef {
@@ -362,6 +402,16 @@ struct pqn_ctx_impl {
   // addition of its solution (rhs in sb(0).rhs, solution in sb(0).x, final residual in res)
   void recycle_start(Level& lv, SysRef& sr);
   void recycle_add(Level& lv, const double* res);
+  // right preconditioner (precond.hip): set-up of a level for the current configuration
+  // (no-op when up to date), and out_r = P in_r for the densities of a group (out_r may
+  // be in_r: every read of the input precedes the write of the output)
+  void precond_setup(Level& lv);
+  void precond_apply(MvGroup& gr);
+  // near tiles only: near_part of the group's slots from its densities (with their
+  // coefficient and upsampling GEMMs), on the main stream
+  void near_stage(MvGroup& gr);
+  double pc_setup_ms = 0.0;  // preconditioner set-up time and fallbacks since the last reset
+  int pc_fallback = 0;
   void mobility(Level& lv, const double* FT_dev, const double* axes_dev, double* UO_dev, pqn_mvp_stats* st) {
     mobility_multi(lv, 1, &FT_dev, axes_dev, &UO_dev, st);
   }

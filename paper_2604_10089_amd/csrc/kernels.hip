@@ -663,7 +663,8 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near64(const double* __rest
 
 // ------------------------------------------------------------------ GEMM
 //
-// C(r, col) = sum_k A[r * lda + k] * B(k, col), FP64, 32x32 output tiles,
+// C(r, col) = sum_k A(r, k) * B(k, col), FP64, 32x32 output tiles,
+// A(r, k) = A[r * lda + k] (at = 0) or A[k * lda + r] (at = 1),
 // B(k, col) = B[col * ldb + k] (k contiguous) and C(r, col) stored at
 // C[(r / rb) * rbs + (r % rb) * rs + (col / cb) * cbs + (col % cb) * ldc]: one
 // kernel covers the per-sphere block products on the SoA field layout and the
@@ -686,7 +687,7 @@ typedef double gemm_acc4 __attribute__((ext_vector_type(4)));
 template <int GW>
 __device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, const double* __restrict__ A,
                                           int lda, const double* __restrict__ B, int ldb, double* __restrict__ C,
-                                          int rb, long rbs, int ldc, int rs, int cb, long cbs) {
+                                          int rb, long rbs, int ldc, int rs, int cb, long cbs, int at) {
   // per wave: A and B slices [32][GLS]; reused for the partial tiles [32][33]
   __shared__ double sh[GW][2 * GBM * GLS];
   const int lane = threadIdx.x & 63;
@@ -709,9 +710,22 @@ __device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, 
       const int idx = lane + e * 64;  // 0..511: k fastest
       const int kk = idx % GBK, rc = idx / GBK;
       const int gk = k0 + kk;
-      const int gr = r0 + rc, gc = c0 + rc;
-      As[rc * GLS + kk] = (gr < R && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
+      const int gc = c0 + rc;
+      if (!at) {
+        const int gr = r0 + rc;
+        As[rc * GLS + kk] = (gr < R && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
+      }
       Bs[rc * GLS + kk] = (gc < Cn && gk < K) ? B[(size_t)gc * ldb + gk] : 0.0;
+    }
+    if (at) {
+      // A stored by columns: rows fastest, so consecutive lanes read consecutive addresses
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int idx = lane + e * 64;
+        const int rc = idx % GBM, kk = idx / GBM;
+        const int gr = r0 + rc, gk = k0 + kk;
+        As[rc * GLS + kk] = (gr < R && gk < K) ? A[(size_t)gk * lda + gr] : 0.0;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -765,9 +779,10 @@ __device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, 
 template <int GW>
 __global__ __launch_bounds__(64 * GW) void k_gemm64(int R, int Cn, int K, const double* __restrict__ A, int lda,
                                                     long Az, const double* __restrict__ B, long Bz, int ldb,
-                                                    double* __restrict__ C, long Cz, int rb, long rbs, int ldc) {
+                                                    double* __restrict__ C, long Cz, int rb, long rbs, int ldc,
+                                                    int at) {
   gemm_tile<GW>(blockIdx.x, blockIdx.y, R, Cn, K, A + (size_t)blockIdx.z * Az, lda, B + (size_t)blockIdx.z * Bz, ldb,
-                C + (size_t)blockIdx.z * Cz, rb, rbs, ldc, 1, Cn, 0);
+                C + (size_t)blockIdx.z * Cz, rb, rbs, ldc, 1, Cn, 0, at);
 }
 
 // ------------------------------------------------- completion and slip RHS
@@ -985,7 +1000,7 @@ __global__ __launch_bounds__(64 * GW) void k_gemm64_multi(const GemmDesc* __rest
   if (D.live && !*D.live) return;  // uniform over the block, before any barrier
   const int local = b - D.start;
   gemm_tile<GW>(local % D.tr, local / D.tr, D.R, D.Cn, D.K, D.A, D.lda, D.B, D.ldb, D.C, D.rb, D.rbs, D.ldc, D.rs,
-                D.cb, D.cbs);
+                D.cb, D.cbs, D.at);
 }
 
 __global__ __launch_bounds__(256) void k_pack_multi(const PackDesc* __restrict__ d, int nd, int fp32) {
@@ -1256,12 +1271,12 @@ void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, cons
 }
 
 void launch_gemm64(hipStream_t s, int R, int Cn, int K, const double* A, int lda, long Az, const double* B, long Bz,
-                   int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch) {
+                   int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch, int at) {
   const dim3 g((R + GBM - 1) / GBM, (Cn + GBN - 1) / GBN, batch);
   if ((long)g.x * g.y * g.z < kGemmSplitBelow)
-    hipLaunchKernelGGL(k_gemm64<4>, g, dim3(256), 0, s, R, Cn, K, A, lda, Az, B, Bz, ldb, C, Cz, rb, rbs, ldc);
+    hipLaunchKernelGGL(k_gemm64<4>, g, dim3(256), 0, s, R, Cn, K, A, lda, Az, B, Bz, ldb, C, Cz, rb, rbs, ldc, at);
   else
-    hipLaunchKernelGGL(k_gemm64<1>, g, dim3(64), 0, s, R, Cn, K, A, lda, Az, B, Bz, ldb, C, Cz, rb, rbs, ldc);
+    hipLaunchKernelGGL(k_gemm64<1>, g, dim3(64), 0, s, R, Cn, K, A, lda, Az, B, Bz, ldb, C, Cz, rb, rbs, ldc, at);
 }
 void launch_rhs(hipStream_t s, const double* ctr, const double* FT, const double* axes, const double* off, int n,
                 int M, int N, double a, double mu, double slip, double* rhs) {

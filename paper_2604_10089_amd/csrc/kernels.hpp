@@ -40,6 +40,7 @@ struct GemmDesc {
   int rs, cb;  // C(r, col) at C[(r / rb) rbs + (r % rb) rs + (col / cb) cbs + (col % cb) ldc]
   long cbs;
   const int* live;  // null, or a flag: 0 = the segment's system is done (its blocks exit)
+  int at;           // 1: A(r, k) = A[k * lda + r] (A stored by columns), else A[r * lda + k]
 };
 struct PackDesc {
   const double* q;
@@ -153,7 +154,7 @@ void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, cons
 // C(r, col) = sum_k A[r * lda + k] B[col * ldb + k], stored at C[(r / rb) * rbs + col * ldc + r % rb];
 // grid z = batch with strides Az, Bz, Cz.
 void launch_gemm64(hipStream_t s, int R, int Cn, int K, const double* A, int lda, long Az, const double* B, long Bz,
-                   int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch);
+                   int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch, int at = 0);
 
 void launch_rhs(hipStream_t s, const double* ctr, const double* FT, const double* axes, const double* off, int n,
                 int M, int N, double a, double mu, double slip, double* rhs);

@@ -1,0 +1,416 @@
+// Right preconditioner of the BIE's GMRES (config precond).
+//
+// Sec. 2 notes that practical mobility solves need preconditioned Krylov
+// methods without fixing a preconditioner; this is the one used here. GMRES
+// solves (1/2 I + D + P) P_r y = rhs and returns q = P_r y, so the solution and
+// the stopping rule (true residual of q) are those of the unpreconditioned
+// solve. For sphere i with near partners j (gap < near_gap):
+//
+//   (P_r v)_i = S_i^{-1} (v_i - sum_j A_ij D^{-1} v_j),  S_i = D - sum_j A_ij D^{-1} A_ji,
+//
+// where D is the single-sphere block (1/2 I + self interaction + rigid
+// projection: one matrix for every sphere, the spheres being identical and
+// their grids globally aligned) and A_ij the near block of the pair (the near
+// rule's map from sphere j's density to sphere i's nodes). This is the row of
+// sphere i of the inverse of its near patch [[D, A_ij], [A_ji, D], ...] with
+// the coupling between its partners dropped: a restricted additive Schwarz
+// preconditioner over near-pair patches with the patch solves reduced to Schur
+// complements. For a lone near pair it is the pair's exact inverse; far
+// interactions stay out (smooth, few GMRES iterations).
+//
+// Set-up, once per configuration and level (at the first solve after a change):
+//   - D on the host from the self block and the rigid projection, D^{-1} by
+//     Gauss-Jordan elimination with partial pivoting (once per level);
+//   - the near blocks, six columns at a time, from the near stage of the
+//     operator applied to unit densities (the same kernels as every product);
+//   - S_i by FP64 matrix-core GEMMs, S_i^{-1} by the Newton-Schulz iteration
+//     X <- X (2I - S_i X) from X = D^{-1} until every sphere's residual
+//     ||I - S_i X||_F / sqrt(3n) is below kNsTol. A sphere whose iteration does
+//     not get below kNsKeep keeps X = D^{-1} (block Jacobi for that sphere).
+//
+// Layouts (3n = per-sphere unknowns, local index c n + x: component c, node x):
+//   D, D^{-1}: [3n][3n] row-major; near blocks of sphere i: [3n][npart_i 3n]
+//   row-major (slot s in columns s 3n ..); S_i row-major; X_i by columns.
+#include "context.hpp"
+
+#include <algorithm>
+
+namespace bipqn {
+
+constexpr double kNsTol = 1e-10;   // Newton-Schulz stop: residual of every sphere below this
+constexpr double kNsKeep = 1e-3;   // spheres above this after the last step fall back to D^{-1}
+constexpr int kNsMaxSteps = 14;
+
+// ---------------------------------------------------------------- host set-up
+
+// D = 1/2 I + S + P_rigid in local order (rows c n + x, columns d n + m). P_rigid
+// is the rigid projection of the completed operator: the translation
+// w_m delta_cd / (4 pi a^2) and the rotation -(3 / (8 pi a^4)) w_m [o_x]x [o_m]x,
+// with ([a]x [b]x)_cd = b_c a_d - (a.b) delta_cd.
+void single_sphere_block(const SphereTables& t, std::vector<double>& D) {
+  const int n = t.n, n3 = 3 * n;
+  const double a = t.radius;
+  D = t.S;
+  for (int r = 0; r < n3; ++r) D[(size_t)r * n3 + r] += 0.5;
+  const double ctr = 1.0 / (4.0 * kPi * a * a), crot = 3.0 / (8.0 * kPi * a * a * a * a);
+  for (int x = 0; x < n; ++x) {
+    const double* ox = &t.off[3 * x];
+    for (int m = 0; m < n; ++m) {
+      const double* om = &t.off[3 * m];
+      const double wm = t.w[m];
+      const double dot = ox[0] * om[0] + ox[1] * om[1] + ox[2] * om[2];
+      for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) {
+          const double cross2 = om[c] * ox[d] - (c == d ? dot : 0.0);
+          D[(size_t)(c * n + x) * n3 + d * n + m] += (c == d ? ctr * wm : 0.0) - crot * wm * cross2;
+        }
+    }
+  }
+}
+
+// In-place inverse of the row-major n x n matrix A (Gauss-Jordan, partial pivoting).
+void invert_gauss_jordan(std::vector<double>& A, int n) {
+  std::vector<int> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  std::vector<double> rowk(n);
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    double best = std::fabs(A[(size_t)k * n + k]);
+    for (int r = k + 1; r < n; ++r)
+      if (std::fabs(A[(size_t)r * n + k]) > best) {
+        best = std::fabs(A[(size_t)r * n + k]);
+        piv = r;
+      }
+    if (!(best > 0.0) || !std::isfinite(best)) throw Error(PQN_ERR_NUMERIC, "singular single-sphere block");
+    if (piv != k) {
+      std::swap_ranges(A.begin() + (size_t)k * n, A.begin() + (size_t)(k + 1) * n, A.begin() + (size_t)piv * n);
+      std::swap(perm[k], perm[piv]);
+    }
+    double* ak = &A[(size_t)k * n];
+    const double inv = 1.0 / ak[k];
+    ak[k] = 1.0;
+    for (int c = 0; c < n; ++c) ak[c] *= inv;
+    std::copy(ak, ak + n, rowk.begin());
+    for (int r = 0; r < n; ++r) {
+      if (r == k) continue;
+      double* ar = &A[(size_t)r * n];
+      const double f = ar[k];
+      if (f == 0.0) continue;
+      ar[k] = 0.0;
+      for (int c = 0; c < n; ++c) ar[c] -= f * rowk[c];
+    }
+  }
+  // the row swaps act as a column permutation of the inverse: undo it
+  std::vector<double> tmp(n);
+  for (int r = 0; r < n; ++r) {
+    double* ar = &A[(size_t)r * n];
+    for (int c = 0; c < n; ++c) tmp[perm[c]] = ar[c];
+    std::copy(tmp.begin(), tmp.end(), ar);
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+
+// K densities holding unit vectors: u_r = e_{k0 + r} on every sphere (local index).
+__global__ __launch_bounds__(256) void k_unit_cols(double* __restrict__ u, int K, int k0, int n, int N) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  const long len = 3L * N;
+  if (e >= (long)K * len) return;
+  const int r = (int)(e / len);
+  const long g = e - (long)r * len;
+  const int c = (int)(g / N), t = (int)(g - (long)c * N);
+  const int x = t % n;
+  u[e] = (c * n + x == k0 + r) ? 1.0 : 0.0;
+}
+
+// Columns k0 .. k0 + K - 1 of the near blocks from the near partials of unit densities:
+// NB_i(row, s 3n + k0 + r) = near_part_r[s 3N + c N + i n + x], row = c n + x.
+// Thread per (sphere, slot, row), writing its K consecutive columns.
+__global__ __launch_bounds__(256) void k_nb_scatter(OPtrs np, int K, int k0, const int* __restrict__ npart,
+                                                    const long* __restrict__ nbo, int n, int M, int N,
+                                                    double* __restrict__ NB) {
+  const int n3 = 3 * n;
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)M * kMaxNear * n3) return;
+  const int row = (int)(e % n3);
+  const int s = (int)((e / n3) % kMaxNear);
+  const int i = (int)(e / ((long)n3 * kMaxNear));
+  const int ns = npart[i];
+  if (s >= ns) return;
+  const int c = row / n, x = row - c * n;
+  double* dst = NB + nbo[i] + (size_t)row * ns * n3 + (size_t)s * n3 + k0;
+  const size_t src = (size_t)s * 3 * N + (size_t)c * N + (size_t)i * n + x;
+  for (int r = 0; r < K; ++r) dst[r] = np.p[r][src];
+}
+
+// S_i = D - C_i (row-major, in place over C), for every sphere.
+__global__ __launch_bounds__(256) void k_schur_finish(const double* __restrict__ D, int n3, int M,
+                                                      double* __restrict__ S) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  const long nn = (long)n3 * n3;
+  if (e >= (long)M * nn) return;
+  S[e] = D[e % nn] - S[e];
+}
+
+// W <- 2I - W for every sphere (by columns; the diagonal is the same either way).
+__global__ __launch_bounds__(256) void k_two_minus(double* __restrict__ W, int n3, int M) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  const long nn = (long)n3 * n3;
+  if (e >= (long)M * nn) return;
+  const long l = e % nn;
+  const int r = (int)(l % n3), c = (int)(l / n3);
+  W[e] = (r == c ? 2.0 : 0.0) - W[e];
+}
+
+// res_i = ||I - W_i||_F^2 / 3n, one block per sphere (fixed-order reduction).
+__global__ __launch_bounds__(256) void k_ns_residual(const double* __restrict__ W, int n3, double* __restrict__ res) {
+  __shared__ double sh[256];
+  const int i = blockIdx.x;
+  const long nn = (long)n3 * n3;
+  const double* Wi = W + (size_t)i * nn;
+  double acc = 0.0;
+  for (long l = threadIdx.x; l < nn; l += 256) {
+    const int r = (int)(l % n3), c = (int)(l / n3);
+    const double d = (r == c ? 1.0 : 0.0) - Wi[l];
+    acc = fma(d, d, acc);
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) res[i] = sh[0] / n3;
+}
+
+// vl[(i K + r) 3n + c n + x] = sign * v_r[c N + i n + x] + (near: - sum_{s < npart_i} near_r[s 3N + ...]).
+__global__ __launch_bounds__(256) void k_pc_gather(QPtrs v, OPtrs np, const int* __restrict__ npart, int K, int n,
+                                                   int M, int N, double* __restrict__ vl) {
+  const int n3 = 3 * n;
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)M * K * n3) return;
+  const int row = (int)(e % n3);
+  const int r = (int)((e / n3) % K);
+  const int i = (int)(e / ((long)n3 * K));
+  const int c = row / n, x = row - c * n;
+  const size_t g = (size_t)c * N + (size_t)i * n + x;
+  double val = v.p[r][g];
+  if (np.p[0]) {
+    const int ns = npart[i];
+    for (int s = 0; s < ns; ++s) val -= np.p[r][(size_t)s * 3 * N + g];
+  }
+  vl[e] = val;
+}
+
+// out_r[c N + i n + x] = yl[(i K + r) 3n + c n + x]
+__global__ __launch_bounds__(256) void k_pc_scatter(const double* __restrict__ yl, OPtrs out, int K, int n, int M,
+                                                    int N) {
+  const int n3 = 3 * n;
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)M * K * n3) return;
+  const int row = (int)(e % n3);
+  const int r = (int)((e / n3) % K);
+  const int i = (int)(e / ((long)n3 * K));
+  const int c = row / n, x = row - c * n;
+  out.p[r][(size_t)c * N + (size_t)i * n + x] = yl[e];
+}
+
+static unsigned nblocks(long count) { return (unsigned)((count + 255) / 256); }
+
+// ------------------------------------------------------------ near stage only
+
+void pqn_ctx_impl::near_stage(MvGroup& gr) {
+  Level& lv = *gr.lv;
+  hipStream_t s = stream;
+  if (n_near + n_near2 == 0) return;
+  double* qup = n_near > 0 ? group_qup(gr) : nullptr;
+  double* qup2 = n_near2 > 0 ? group_qup(gr, true) : nullptr;
+  double* coef = group_coef(gr);
+  std::vector<GemmDesc> ga, gb;
+  int nga = 0, ngb = 0;
+  push_group_gemms(lv, gr.K, gr.slot, gr.in, coef, qup, qup2, nullptr, ga, nga, gb, ngb, false);
+  DescPack dp;
+  const size_t oa = dp.add(ga), ob = dp.add(gb);
+  char* base = push_desc_pack(dp.host);
+  launch_gemm64_multi(s, (const GemmDesc*)(base + oa), (int)ga.size(), nga);
+  launch_gemm64_multi(s, (const GemmDesc*)(base + ob), (int)gb.size(), ngb);
+  OPtrs np{};
+  for (int r = 0; r < gr.K; ++r) np.p[r] = lv.wk(gr.slot[r]).near_part.p;
+  const double scale = 3.0 / (4.0 * kPi * a);
+  launch_near(s, gr.K, n_near, ctr.p, lv.off.p, lv.offup.p, lv.shab.p, qup, coef, near_list.p, lv.n, lv.M, lv.N,
+              lv.nup, lv.p, lv.L, scale, np);
+  launch_near(s, gr.K, n_near2, ctr.p, lv.off.p, lv.offup2.p, lv.shab.p, qup2, coef, near_list2.p, lv.n, lv.M,
+              lv.N, lv.nup2, lv.p, lv.L, scale, np);
+}
+
+// ----------------------------------------------------------------- set-up
+
+void pqn_ctx_impl::precond_setup(Level& lv) {
+  Precond& pc = lv.pc;
+  if (!cfg.precond || pc.epoch == config_epoch) return;
+  TraceRange trace("precond_setup");
+  HIPCHK(hipStreamSynchronize(stream));
+  Timer tm;
+  hipStream_t s = stream;
+  const int n = lv.n, n3 = 3 * n, M = lv.M, N = lv.N;
+  const size_t nn = (size_t)n3 * n3;
+  if (!pc.has_d) {
+    std::vector<double> D;
+    single_sphere_block(lv.tab, D);
+    std::vector<double> Di = D;
+    invert_gauss_jordan(Di, n3);
+    std::vector<double> DiT(nn);
+    for (int r = 0; r < n3; ++r)
+      for (int c = 0; c < n3; ++c) DiT[(size_t)c * n3 + r] = Di[(size_t)r * n3 + c];
+    pc.D.upload(D.data(), nn, s);
+    pc.Dinv.upload(Di.data(), nn, s);
+    pc.DinvT.upload(DiT.data(), nn, s);
+    HIPCHK(hipStreamSynchronize(s));
+    pc.has_d = true;
+  }
+  pc.X.alloc((size_t)M * nn);
+  pc.res.alloc((size_t)M);
+  long total = 0;
+  pc.nbo.assign(M, 0);
+  for (int i = 0; i < M; ++i) {
+    pc.nbo[i] = total;
+    total += (long)h_npart[i] * nn;
+  }
+  pc.fallback = 0;
+  pc.ns_iters = 0;
+  if (total == 0) {
+    // no near pairs: block Jacobi
+    for (int i = 0; i < M; ++i)
+      HIPCHK(hipMemcpyAsync(pc.X.p + (size_t)i * nn, pc.DinvT.p, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    pc.NB.alloc((size_t)total);
+    pc.TB.alloc((size_t)total);
+    DevArray<long> dnbo;
+    dnbo.upload(pc.nbo.data(), pc.nbo.size(), s);
+    // near blocks, kMaxRhs columns per pass, from unit densities through the near stage
+    pc.ug.alloc((size_t)kMaxRhs * 3 * N);
+    for (int k0 = 0; k0 < n3; k0 += kMaxRhs) {
+      const int K = std::min(kMaxRhs, n3 - k0);
+      hipLaunchKernelGGL(k_unit_cols, dim3(nblocks((long)K * 3 * N)), dim3(256), 0, s, pc.ug.p, K, k0, n, N);
+      MvGroup g{this, &lv, K, {}, {}, {}};
+      OPtrs np{};
+      for (int r = 0; r < K; ++r) {
+        g.slot[r] = r;
+        g.in[r] = pc.ug.p + (size_t)r * 3 * N;
+        np.p[r] = lv.wk(r).near_part.p;
+      }
+      near_stage(g);
+      hipLaunchKernelGGL(k_nb_scatter, dim3(nblocks((long)M * kMaxNear * n3)), dim3(256), 0, s, np, K, k0, npart.p,
+                         dnbo.p, n, M, N, pc.NB.p);
+    }
+    // T_(i,s) = D^{-1} A_(j,s'), j the partner in slot s of i and s' the slot of i in j's list,
+    // stored as TB_i(c, s 3n + m) = T_(i,s)(m, c): computed as C(c, m) = sum_k A_(j,s')(k, c) D^{-1}(m, k)
+    pc.S.alloc((size_t)M * nn);
+    std::vector<GemmDesc> gt, gs;
+    int ngt = 0, ngs = 0;
+    for (int i = 0; i < M; ++i) {
+      const int ns = h_npart[i];
+      if (ns == 0) {  // C_i = 0: a product with no terms writes zeros
+        push_gemm(gs, ngs, n3, n3, 0, pc.Dinv.p, n3, pc.Dinv.p, n3, pc.S.p + (size_t)i * nn, n3, 0, 1, n3, n3, 0, 0);
+        continue;
+      }
+      const int ldi = ns * n3;
+      for (int sl = 0; sl < ns; ++sl) {
+        const int j = h_partners[(size_t)i * kMaxNear + sl];
+        int sj = -1;
+        for (int q = 0; q < h_npart[j]; ++q)
+          if (h_partners[(size_t)j * kMaxNear + q] == i) sj = q;
+        if (sj < 0) throw Error(PQN_ERR_STATE, "internal: near pair list is not symmetric");
+        const int ldj = h_npart[j] * n3;
+        push_gemm(gt, ngt, n3, n3, n3, pc.NB.p + pc.nbo[j] + (size_t)sj * n3, ldj, pc.Dinv.p, n3,
+                  pc.TB.p + pc.nbo[i] + (size_t)sl * n3, n3, 0, 1, ldi, n3, 0, 1);
+      }
+      // C_i = sum_s A_(i,s) T_(i,s): one product over the concatenated slots, row-major into S_i
+      push_gemm(gs, ngs, n3, n3, ldi, pc.NB.p + pc.nbo[i], ldi, pc.TB.p + pc.nbo[i], ldi, pc.S.p + (size_t)i * nn,
+                n3, 0, 1, n3, n3, 0, 0);
+    }
+    DescPack dp;
+    const size_t ot = dp.add(gt), os = dp.add(gs);
+    char* base = push_desc_pack(dp.host);
+    launch_gemm64_multi(s, (const GemmDesc*)(base + ot), (int)gt.size(), ngt);
+    launch_gemm64_multi(s, (const GemmDesc*)(base + os), (int)gs.size(), ngs);
+    hipLaunchKernelGGL(k_schur_finish, dim3(nblocks((long)M * nn)), dim3(256), 0, s, pc.D.p, n3, M, pc.S.p);
+    // Newton-Schulz from X = D^{-1}
+    pc.X2.alloc((size_t)M * nn);
+    pc.W.alloc((size_t)M * nn);
+    for (int i = 0; i < M; ++i)
+      HIPCHK(hipMemcpyAsync(pc.X.p + (size_t)i * nn, pc.DinvT.p, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    std::vector<double> res(M);
+    for (int step = 0;; ++step) {
+      // W = S X (by columns): C(r, c) = sum_k S(r, k) X(k, c)
+      launch_gemm64(s, n3, n3, n3, pc.S.p, n3, (long)nn, pc.X.p, (long)nn, n3, pc.W.p, (long)nn, n3, 0, n3, M, 0);
+      hipLaunchKernelGGL(k_ns_residual, dim3(M), dim3(256), 0, s, pc.W.p, n3, pc.res.p);
+      HIPCHK(hipMemcpyAsync(res.data(), pc.res.p, M * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      double worst = 0.0;
+      for (double v : res) worst = std::isfinite(v) ? std::max(worst, std::sqrt(v)) : 1e300;
+      if (worst <= kNsTol || step == kNsMaxSteps) break;
+      // X <- X (2I - W): C(r, c) = sum_k X(r, k) F(k, c), X read by columns
+      hipLaunchKernelGGL(k_two_minus, dim3(nblocks((long)M * nn)), dim3(256), 0, s, pc.W.p, n3, M);
+      launch_gemm64(s, n3, n3, n3, pc.X.p, n3, (long)nn, pc.W.p, (long)nn, n3, pc.X2.p, (long)nn, n3, 0, n3, M, 1);
+      std::swap(pc.X.p, pc.X2.p);
+      ++pc.ns_iters;
+    }
+    for (int i = 0; i < M; ++i)
+      if (!(std::sqrt(res[i]) <= kNsKeep)) {
+        HIPCHK(hipMemcpyAsync(pc.X.p + (size_t)i * nn, pc.DinvT.p, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+        ++pc.fallback;
+      }
+    HIPCHK(hipStreamSynchronize(s));  // dnbo and the descriptor tables are released/reused after this
+  }
+  HIPCHK(hipGetLastError());
+  pc.epoch = config_epoch;
+  pc.setup_ms = tm.ms();
+  pc_setup_ms += pc.setup_ms;
+  pc_fallback += pc.fallback;
+}
+
+// ------------------------------------------------------------ application
+
+void pqn_ctx_impl::precond_apply(MvGroup& gr) {
+  Level& lv = *gr.lv;
+  Precond& pc = lv.pc;
+  if (pc.epoch != config_epoch) throw Error(PQN_ERR_STATE, "internal: preconditioner not set up");
+  hipStream_t s = stream;
+  const int n = lv.n, n3 = 3 * n, M = lv.M, N = lv.N, K = gr.K;
+  const size_t nn = (size_t)n3 * n3;
+  const long loc = (long)M * K * n3;
+  pc.vl.alloc((size_t)M * kMaxRhs * n3);
+  pc.yl.alloc((size_t)M * kMaxRhs * n3);
+  QPtrs vin{};
+  for (int r = 0; r < K; ++r) vin.p[r] = gr.in[r];
+  OPtrs none{};
+  OPtrs out{};
+  for (int r = 0; r < K; ++r) out.p[r] = gr.out[r];
+  // y = D^{-1} v per sphere (columns (i, r) of the local layout)
+  hipLaunchKernelGGL(k_pc_gather, dim3(nblocks(loc)), dim3(256), 0, s, vin, none, npart.p, K, n, M, N, pc.vl.p);
+  launch_gemm64(s, n3, M * K, n3, pc.Dinv.p, n3, 0, pc.vl.p, 0, n3, pc.yl.p, 0, n3, 0, n3, 1, 0);
+  if (n_near + n_near2 == 0) {
+    hipLaunchKernelGGL(k_pc_scatter, dim3(nblocks(loc)), dim3(256), 0, s, pc.yl.p, out, K, n, M, N);
+    return;
+  }
+  // near tiles of y: sum_j A_ij y_j in the near partials of the group's slots
+  pc.ug.alloc((size_t)kMaxRhs * 3 * N);
+  OPtrs yg{};
+  MvGroup ny = gr;
+  for (int r = 0; r < K; ++r) {
+    yg.p[r] = pc.ug.p + (size_t)r * 3 * N;
+    ny.in[r] = yg.p[r];
+  }
+  hipLaunchKernelGGL(k_pc_scatter, dim3(nblocks(loc)), dim3(256), 0, s, pc.yl.p, yg, K, n, M, N);
+  near_stage(ny);
+  // r_i = v_i - sum_j A_ij y_j, then out_i = S_i^{-1} r_i (X_i read by columns)
+  OPtrs np{};
+  for (int r = 0; r < K; ++r) np.p[r] = lv.wk(gr.slot[r]).near_part.p;
+  hipLaunchKernelGGL(k_pc_gather, dim3(nblocks(loc)), dim3(256), 0, s, vin, np, npart.p, K, n, M, N, pc.vl.p);
+  launch_gemm64(s, n3, K, n3, pc.X.p, n3, (long)nn, pc.vl.p, (long)K * n3, n3, pc.yl.p, (long)K * n3, n3, 0, n3, M,
+                1);
+  hipLaunchKernelGGL(k_pc_scatter, dim3(nblocks(loc)), dim3(256), 0, s, pc.yl.p, out, K, n, M, N);
+}
+
+}  // namespace bipqn

@@ -51,6 +51,21 @@ def test_host_self_block_matches_oracle(nt):
     assert np.abs(S - So).max() <= 1e-12 * np.abs(So).max()
 
 
+@pytest.mark.parametrize("nt", [4, 6])
+def test_host_sphere_block_matches_oracle(nt):
+    """The diagonal block of the preconditioner (1/2 I + self interaction + rigid projection of
+    one sphere) is the oracle's one-sphere operator, reordered from node-major to SoA."""
+    from oracle import bie
+    D, Di = binding.pqn_host_sphere_block(nt, 2 * nt, 1.3)
+    g = bie.Geometry([[0.4, -1.0, 2.0]], 1.3, nt, 2 * nt)
+    A = bie.dense_operator(g)
+    n = g.n
+    perm = np.array([x * 3 + c for c in range(3) for x in range(n)])  # SoA row c n + x <- node-major 3 x + c
+    Ao = A[np.ix_(perm, perm)]
+    assert np.abs(D - Ao).max() <= 1e-12 * np.abs(Ao).max()
+    assert np.abs(Di @ D - np.eye(3 * n)).max() < 1e-12
+
+
 def test_host_self_block_rejects_bad_grid():
     with pytest.raises(binding.PqnError):
         binding.pqn_host_self_block(1, 2, 1.0)

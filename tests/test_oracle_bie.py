@@ -424,3 +424,40 @@ def test_coarse_far_operator_dense_equals_matrix_free(tiny_cases):
     assert np.abs(A @ q.ravel() - y.ravel()).max() < 1e-12 * np.abs(y).max()
     rows = bie.operator_rows(g, q, [0, 77, g.N - 1])
     assert np.abs(rows - y[[0, 77, g.N - 1]]).max() < 1e-12 * np.abs(y).max()
+
+
+def test_near_patch_preconditioner_inverts_one_sphere_and_a_lone_pair():
+    """The preconditioner of the GMRES solves (Sec. 2 asks for preconditioned Krylov
+    solves without naming one) is exact where its construction is: one sphere gives
+    D^{-1} = A^{-1}; two spheres that are each other's only near partner give the
+    block inverse of A by Schur complements, so A P = I in both cases."""
+    rng = np.random.default_rng(3)
+    for centers in ([[0.2, -0.1, 0.4]], [[0.0, 0.0, 0.0], [2.05, 0.3, -0.1]]):
+        g = bie.Geometry(centers, 1.0, 6, 12)
+        A = bie.dense_operator(g)
+        P = bie.near_patch_preconditioner(g, A)
+        V = rng.standard_normal((A.shape[0], 4))
+        AP = np.stack([A @ P(V[:, c]) for c in range(4)], axis=1)
+        assert np.abs(AP - V).max() < 1e-11 * np.abs(V).max()
+    # a sphere far from the pair is outside every patch: P then differs from A^{-1}
+    g = bie.Geometry([[0.0, 0.0, 0.0], [2.05, 0.3, -0.1], [9.0, 0.0, 0.0]], 1.0, 6, 12)
+    A = bie.dense_operator(g)
+    P = bie.near_patch_preconditioner(g, A)
+    v = rng.standard_normal(A.shape[0])
+    err = np.abs(A @ P(v) - v).max() / np.abs(v).max()
+    assert 1e-8 < err < 0.1
+
+
+def test_right_preconditioned_gmres_solves_the_same_system(tiny_cases):
+    """Right preconditioning changes the Krylov space, not the solution or its stopping
+    rule: the same density as the dense solve, in fewer iterations."""
+    _, g, A = tiny_cases[0]
+    rhs = -bie.completion(g, inputs.random_forces(21, g.M))
+    q = np.linalg.solve(A, rhs.ravel())
+    x0, i0, _ = bie.gmres(lambda v: A @ v.ravel(), rhs, tol=1e-11)
+    P = bie.near_patch_preconditioner(g, A)
+    x1, i1, rr = bie.gmres(lambda v: A @ v.ravel(), rhs, tol=1e-11, right=P)
+    assert rr <= 1e-11
+    assert np.linalg.norm(A @ x1 - rhs.ravel()) <= 1.01e-11 * np.linalg.norm(rhs)
+    assert np.abs(x1 - q).max() < 1e-9 * np.abs(q).max()
+    assert i1 < 0.6 * i0
