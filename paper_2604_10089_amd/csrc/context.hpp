@@ -140,7 +140,12 @@ struct Precond {
   std::vector<long> nbo;
   DevArray<double> S, X, X2, W;  // [M][3n][3n]; S row-major, X (= S^{-1}), X2, W by columns
   DevArray<double> res;          // [M] Newton-Schulz residuals
-  DevArray<double> vl, yl, ug;   // local vectors [M][K][3n] and K global fields [3][N]
+  DevArray<double> ug;           // kMaxRhs unit densities [3][N] (near-block assembly)
+  DevArray<float> B32;           // the preconditioner's blocks in FP32, by columns, row of sphere i
+  DevArray<int> bptr, bcol;      // first block of sphere i's row [M + 1]; column sphere of each block
+  DevArray<double> vI;           // input densities interleaved per node [M][3n][K]
+  DevArray<double> part;         // per-block partial products [nblk][K][3n]
+  int nblk = 0;                  // blocks: M + the ordered near pairs
   int fallback = 0;              // spheres left on D^{-1} (Newton-Schulz did not converge)
   int ns_iters = 0;              // Newton-Schulz steps of the last set-up
   double setup_ms = 0.0;         // wall time of the last set-up

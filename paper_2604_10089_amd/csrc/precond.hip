@@ -28,16 +28,25 @@
 //     ||I - S_i X||_F / sqrt(3n) is below kNsTol. A sphere whose iteration does
 //     not get below kNsKeep keeps X = D^{-1} (block Jacobi for that sphere).
 //
+//   - G_ij = S_i^{-1} A_ij D^{-1} for every near pair, so that
+//     (P_r v)_i = S_i^{-1} v_i - sum_j G_ij v_j: one block-sparse product whose
+//     blocks (S_i^{-1} and the G_ij, 3n x 3n each) are stored in FP32. P_r is a
+//     fixed linear map either way, so GMRES keeps its convergence theory and the
+//     solution its accuracy; the rounding only perturbs the preconditioner.
+// Each application streams the blocks once from HBM ((M + n_near) (3n)^2 4 bytes:
+// 2.2 GB at 216 spheres and 12x24 nodes), whatever the number of densities K.
+//
 // Layouts (3n = per-sphere unknowns, local index c n + x: component c, node x):
 //   D, D^{-1}: [3n][3n] row-major; near blocks of sphere i: [3n][npart_i 3n]
-//   row-major (slot s in columns s 3n ..); S_i row-major; X_i by columns.
+//   row-major (slot s in columns s 3n ..); S_i row-major; X_i by columns; the
+//   FP32 blocks by columns, sphere i's row of blocks contiguous (S_i^{-1} first).
 #include "context.hpp"
 
 #include <algorithm>
 
 namespace bipqn {
 
-constexpr double kNsTol = 1e-10;   // Newton-Schulz stop: residual of every sphere below this
+constexpr double kNsTol = 1e-8;    // Newton-Schulz stop: residual of every sphere below this
 constexpr double kNsKeep = 1e-3;   // spheres above this after the last step fall back to D^{-1}
 constexpr int kNsMaxSteps = 14;
 
@@ -183,36 +192,73 @@ __global__ __launch_bounds__(256) void k_ns_residual(const double* __restrict__ 
   if (threadIdx.x == 0) res[i] = sh[0] / n3;
 }
 
-// vl[(i K + r) 3n + c n + x] = sign * v_r[c N + i n + x] + (near: - sum_{s < npart_i} near_r[s 3N + ...]).
-__global__ __launch_bounds__(256) void k_pc_gather(QPtrs v, OPtrs np, const int* __restrict__ npart, int K, int n,
-                                                   int M, int N, double* __restrict__ vl) {
+// vI[(j 3n + m) K + r] = v_r[c N + j n + x], m = c n + x: the K densities of a node
+// next to each other, one scalar-load stream per block column.
+__global__ __launch_bounds__(256) void k_pc_interleave(QPtrs v, int K, int n, int M, int N,
+                                                       double* __restrict__ vI) {
   const int n3 = 3 * n;
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (long)M * K * n3) return;
-  const int row = (int)(e % n3);
-  const int r = (int)((e / n3) % K);
-  const int i = (int)(e / ((long)n3 * K));
-  const int c = row / n, x = row - c * n;
-  const size_t g = (size_t)c * N + (size_t)i * n + x;
-  double val = v.p[r][g];
-  if (np.p[0]) {
-    const int ns = npart[i];
-    for (int s = 0; s < ns; ++s) val -= np.p[r][(size_t)s * 3 * N + g];
-  }
-  vl[e] = val;
+  if (e >= (long)M * n3 * K) return;
+  const int r = (int)(e % K);
+  const long jm = e / K;
+  const int m = (int)(jm % n3), j = (int)(jm / n3);
+  const int c = m / n, x = m - c * n;
+  vI[e] = v.p[r][(size_t)c * N + (size_t)j * n + x];
 }
 
-// out_r[c N + i n + x] = yl[(i K + r) 3n + c n + x]
-__global__ __launch_bounds__(256) void k_pc_scatter(const double* __restrict__ yl, OPtrs out, int K, int n, int M,
-                                                    int N) {
+// FP32 copies of FP64 blocks stored by columns: block b of the list is sgn[b] src[b].
+__global__ __launch_bounds__(256) void k_blocks_f32(const double* const* __restrict__ src,
+                                                    const double* __restrict__ sgn, long nn, long nb,
+                                                    float* __restrict__ dst) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nb * nn) return;
+  const long b = e / nn;
+  dst[e] = (float)(sgn[b] * src[b][e - b * nn]);
+}
+
+// part[(b K + r) 3n + row] = sum_m B_b(row, m) vI[(j 3n + m) K + r], j the column sphere of
+// block b. Thread per (block, row): the block's columns are read by consecutive rows
+// (coalesced), the densities of node m of sphere j are wave-uniform (scalar loads). A
+// workgroup per (block, 256 rows), rather than per (sphere, rows), gives the launch
+// enough waves to keep the loads in flight that stream the blocks from HBM.
+// FP32 blocks, FP64 products and sums.
+template <int K>
+__global__ __launch_bounds__(256) void k_bsr_block(const float* __restrict__ B, const int* __restrict__ bcol,
+                                                   const double* __restrict__ vI, int n3, int rchunks,
+                                                   double* __restrict__ part) {
+  const int b = blockIdx.x / rchunks;
+  const int row = (blockIdx.x - b * rchunks) * 256 + threadIdx.x;
+  const bool valid = row < n3;
+  const int rr = valid ? row : n3 - 1;
+  const float* Bb = B + (size_t)b * n3 * n3 + rr;
+  const double* v = vI + (size_t)bcol[b] * n3 * K;
+  double acc[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) acc[r] = 0.0;
+#pragma unroll 8
+  for (int m = 0; m < n3; ++m) {
+    const double a = (double)Bb[(size_t)m * n3];
+#pragma unroll
+    for (int r = 0; r < K; ++r) acc[r] = fma(a, v[m * K + r], acc[r]);
+  }
+  if (valid)
+#pragma unroll
+    for (int r = 0; r < K; ++r) part[((size_t)b * K + r) * n3 + row] = acc[r];
+}
+
+// out_r[c N + i n + x] = sum of the partials of sphere i's blocks (in block order), row = c n + x.
+__global__ __launch_bounds__(256) void k_bsr_sum(const double* __restrict__ part, const int* __restrict__ bptr,
+                                                 int K, int n, int M, int N, OPtrs out) {
   const int n3 = 3 * n;
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= (long)M * K * n3) return;
   const int row = (int)(e % n3);
   const int r = (int)((e / n3) % K);
   const int i = (int)(e / ((long)n3 * K));
+  double v = 0.0;
+  for (int b = bptr[i]; b < bptr[i + 1]; ++b) v += part[((size_t)b * K + r) * n3 + row];
   const int c = row / n, x = row - c * n;
-  out.p[r][(size_t)c * N + (size_t)i * n + x] = yl[e];
+  out.p[r][(size_t)c * N + (size_t)i * n + x] = v;
 }
 
 static unsigned nblocks(long count) { return (unsigned)((count + 255) / 256); }
@@ -361,7 +407,56 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
         HIPCHK(hipMemcpyAsync(pc.X.p + (size_t)i * nn, pc.DinvT.p, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
         ++pc.fallback;
       }
+    // G_(i,s) = X_i A_(i,s) D^{-1}: H = A_(i,s) D^{-1} by columns into TB (slot s at s (3n)^2),
+    // then G = X_i H by columns into NB (the near blocks are no longer needed)
+    std::vector<GemmDesc> gh, gg;
+    int ngh = 0, ngg = 0;
+    for (int i = 0; i < M; ++i) {
+      const int ns = h_npart[i];
+      const int ldi = ns * n3;
+      for (int sl = 0; sl < ns; ++sl) {
+        push_gemm(gh, ngh, n3, n3, n3, pc.NB.p + pc.nbo[i] + (size_t)sl * n3, ldi, pc.DinvT.p, n3,
+                  pc.TB.p + pc.nbo[i] + (size_t)sl * nn, n3, 0, n3, 1, n3, 0, 0);
+        push_gemm(gg, ngg, n3, n3, n3, pc.X.p + (size_t)i * nn, n3, pc.TB.p + pc.nbo[i] + (size_t)sl * nn, n3,
+                  pc.NB.p + pc.nbo[i] + (size_t)sl * nn, n3, 0, n3, 1, n3, 0, 1);
+      }
+    }
+    DescPack dq;
+    const size_t oh = dq.add(gh), og = dq.add(gg);
+    char* qb = push_desc_pack(dq.host);
+    launch_gemm64_multi(s, (const GemmDesc*)(qb + oh), (int)gh.size(), ngh);
+    launch_gemm64_multi(s, (const GemmDesc*)(qb + og), (int)gg.size(), ngg);
     HIPCHK(hipStreamSynchronize(s));  // dnbo and the descriptor tables are released/reused after this
+  }
+  // block rows in FP32: sphere i holds S_i^{-1} (or D^{-1}) then G_(i,s) for its slots
+  {
+    std::vector<int> bp(M + 1, 0), bc;
+    std::vector<const double*> src;
+    std::vector<double> sg;
+    for (int i = 0; i < M; ++i) {
+      bp[i] = (int)bc.size();
+      bc.push_back(i);
+      src.push_back(pc.X.p + (size_t)i * nn);
+      sg.push_back(1.0);
+      for (int sl = 0; sl < h_npart[i]; ++sl) {
+        bc.push_back(h_partners[(size_t)i * kMaxNear + sl]);
+        src.push_back(pc.NB.p + pc.nbo[i] + (size_t)sl * nn);
+        sg.push_back(-1.0);
+      }
+    }
+    bp[M] = (int)bc.size();
+    const long nb = (long)bc.size();
+    pc.nblk = (int)nb;
+    pc.B32.alloc((size_t)nb * nn);
+    pc.bptr.upload(bp.data(), bp.size(), s);
+    pc.bcol.upload(bc.data(), bc.size(), s);
+    DevArray<const double*> dsrc;
+    DevArray<double> dsg;
+    dsrc.upload(src.data(), src.size(), s);
+    dsg.upload(sg.data(), sg.size(), s);
+    hipLaunchKernelGGL(k_blocks_f32, dim3(nblocks(nb * (long)nn)), dim3(256), 0, s, dsrc.p, dsg.p, (long)nn, nb,
+                       pc.B32.p);
+    HIPCHK(hipStreamSynchronize(s));  // dsrc is released after this
   }
   HIPCHK(hipGetLastError());
   pc.epoch = config_epoch;
@@ -378,39 +473,30 @@ void pqn_ctx_impl::precond_apply(MvGroup& gr) {
   if (pc.epoch != config_epoch) throw Error(PQN_ERR_STATE, "internal: preconditioner not set up");
   hipStream_t s = stream;
   const int n = lv.n, n3 = 3 * n, M = lv.M, N = lv.N, K = gr.K;
-  const size_t nn = (size_t)n3 * n3;
-  const long loc = (long)M * K * n3;
-  pc.vl.alloc((size_t)M * kMaxRhs * n3);
-  pc.yl.alloc((size_t)M * kMaxRhs * n3);
+  pc.vI.alloc((size_t)M * n3 * kMaxRhs);
   QPtrs vin{};
-  for (int r = 0; r < K; ++r) vin.p[r] = gr.in[r];
-  OPtrs none{};
   OPtrs out{};
-  for (int r = 0; r < K; ++r) out.p[r] = gr.out[r];
-  // y = D^{-1} v per sphere (columns (i, r) of the local layout)
-  hipLaunchKernelGGL(k_pc_gather, dim3(nblocks(loc)), dim3(256), 0, s, vin, none, npart.p, K, n, M, N, pc.vl.p);
-  launch_gemm64(s, n3, M * K, n3, pc.Dinv.p, n3, 0, pc.vl.p, 0, n3, pc.yl.p, 0, n3, 0, n3, 1, 0);
-  if (n_near + n_near2 == 0) {
-    hipLaunchKernelGGL(k_pc_scatter, dim3(nblocks(loc)), dim3(256), 0, s, pc.yl.p, out, K, n, M, N);
-    return;
-  }
-  // near tiles of y: sum_j A_ij y_j in the near partials of the group's slots
-  pc.ug.alloc((size_t)kMaxRhs * 3 * N);
-  OPtrs yg{};
-  MvGroup ny = gr;
   for (int r = 0; r < K; ++r) {
-    yg.p[r] = pc.ug.p + (size_t)r * 3 * N;
-    ny.in[r] = yg.p[r];
+    vin.p[r] = gr.in[r];
+    out.p[r] = gr.out[r];
   }
-  hipLaunchKernelGGL(k_pc_scatter, dim3(nblocks(loc)), dim3(256), 0, s, pc.yl.p, yg, K, n, M, N);
-  near_stage(ny);
-  // r_i = v_i - sum_j A_ij y_j, then out_i = S_i^{-1} r_i (X_i read by columns)
-  OPtrs np{};
-  for (int r = 0; r < K; ++r) np.p[r] = lv.wk(gr.slot[r]).near_part.p;
-  hipLaunchKernelGGL(k_pc_gather, dim3(nblocks(loc)), dim3(256), 0, s, vin, np, npart.p, K, n, M, N, pc.vl.p);
-  launch_gemm64(s, n3, K, n3, pc.X.p, n3, (long)nn, pc.vl.p, (long)K * n3, n3, pc.yl.p, (long)K * n3, n3, 0, n3, M,
-                1);
-  hipLaunchKernelGGL(k_pc_scatter, dim3(nblocks(loc)), dim3(256), 0, s, pc.yl.p, out, K, n, M, N);
+  hipLaunchKernelGGL(k_pc_interleave, dim3(nblocks((long)M * n3 * K)), dim3(256), 0, s, vin, K, n, M, N, pc.vI.p);
+  const int rchunks = (n3 + 255) / 256;
+  const dim3 g(pc.nblk * rchunks);
+  pc.part.alloc((size_t)pc.nblk * kMaxRhs * n3);
+#define BSRK(KK) \
+  hipLaunchKernelGGL(k_bsr_block<KK>, g, dim3(256), 0, s, pc.B32.p, pc.bcol.p, pc.vI.p, n3, rchunks, pc.part.p)
+  switch (K) {
+    case 1: BSRK(1); break;
+    case 2: BSRK(2); break;
+    case 3: BSRK(3); break;
+    case 4: BSRK(4); break;
+    case 5: BSRK(5); break;
+    default: BSRK(6); break;
+  }
+#undef BSRK
+  hipLaunchKernelGGL(k_bsr_sum, dim3(nblocks((long)M * K * n3)), dim3(256), 0, s, pc.part.p, pc.bptr.p, K, n, M, N,
+                     out);
 }
 
 }  // namespace bipqn
