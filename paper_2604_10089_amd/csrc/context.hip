@@ -15,10 +15,12 @@ constexpr int kMultiDotBlocks = 16;  // reduction blocks per vector in the segme
 // stored at C[(r / rb) rbs + (r % rb) rs + (col / cb) cbs + (col % cb) ldc] (cb = 0: no
 // column blocks).
 void push_gemm(std::vector<GemmDesc>& v, int& blocks, int R, int Cn, int K, const double* A, int lda,
-               const double* B, int ldb, double* C, int rb, long rbs, int ldc, int rs, int cb, long cbs, int at) {
-  GemmDesc d{A, B, C, rbs, R, Cn, K, lda, ldb, rb, ldc, (R + 31) / 32, blocks, rs, cb > 0 ? cb : Cn, cbs, nullptr,
-             at};
-  blocks += d.tr * ((Cn + 31) / 32);
+               const double* B, int ldb, double* C, int rb, long rbs, int ldc, int rs, int cb, long cbs, int at,
+               int big) {
+  const int tile = big ? 64 : 32;
+  GemmDesc d{A, B, C, rbs, R, Cn, K, lda, ldb, rb, ldc, (R + tile - 1) / tile, blocks, rs, cb > 0 ? cb : Cn, cbs,
+             nullptr, at};
+  blocks += d.tr * ((Cn + tile - 1) / tile);
   v.push_back(d);
 }
 

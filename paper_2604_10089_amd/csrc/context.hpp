@@ -286,10 +286,11 @@ void add_to_groups(std::vector<MvGroup>& groups, pqn_ctx_impl* c, Level* lv, int
 // upsampled densities [M][nup][3K] and the harmonic coefficients [M][3K][L].
 double* group_qup(MvGroup& gr, bool close = false);
 double* group_coef(MvGroup& gr);
-// One GEMM problem of a segmented launch (see kernels.hpp, GemmDesc).
+// One GEMM problem of a segmented launch (see kernels.hpp, GemmDesc); big = 1 counts
+// 64x64 tiles (launch_gemm64_multi_big), else 32x32 (launch_gemm64_multi).
 void push_gemm(std::vector<GemmDesc>& v, int& blocks, int R, int Cn, int K, const double* A, int lda,
                const double* B, int ldb, double* C, int rb, long rbs, int ldc, int rs = 1, int cb = 0, long cbs = 0,
-               int at = 0);
+               int at = 0, int big = 0);
 // The coefficient GEMMs of a group (list ga) and its self-interaction (with_self) and
 // upsampling GEMMs (list gb).
 void push_group_gemms(Level& lv, int K, const int* slot, const double* const* in, double* coef, double* qup,

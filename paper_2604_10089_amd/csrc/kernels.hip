@@ -776,6 +776,100 @@ __device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, 
   }
 }
 
+// 64x64 output tiles for large products (R and Cn in the hundreds or more, as in the
+// preconditioner set-up): four waves, each a 32x32 quadrant of 2x2 16x16 MFMA blocks as
+// above, share the LDS slices of A (64 x 16) and B (64 x 16), which halves the loads per
+// flop of the 32x32 tiles; the next slices are loaded into registers while the MFMAs run
+// on the current ones.
+__device__ __forceinline__ void gemm_tile_big(int bx, int by, int R, int Cn, int K, const double* __restrict__ A,
+                                              int lda, const double* __restrict__ B, int ldb, double* __restrict__ C,
+                                              int rb, long rbs, int ldc, int rs, int cb, long cbs, int at) {
+  __shared__ double As[2 * GBM * GLS], Bs[2 * GBN * GLS];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int r0 = bx * 2 * GBM, c0 = by * 2 * GBN;
+  const int qr = (wv >> 1) * GBM, qc = (wv & 1) * GBN;
+  const int li = lane & 15, lk = lane >> 4;
+  gemm_acc4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = gemm_acc4{0.0, 0.0, 0.0, 0.0};
+  double ra[4], rbv[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = t + e * 256;  // 0..1023
+      {
+        const int kk = at ? idx / (2 * GBM) : idx % GBK, rc = at ? idx % (2 * GBM) : idx / GBK;
+        const int gr = r0 + rc, gk = k0 + kk;
+        ra[e] = (gr < R && gk < K) ? (at ? A[(size_t)gk * lda + gr] : A[(size_t)gr * lda + gk]) : 0.0;
+      }
+      const int kk = idx % GBK, rc = idx / GBK;
+      const int gc = c0 + rc, gk = k0 + kk;
+      rbv[e] = (gc < Cn && gk < K) ? B[(size_t)gc * ldb + gk] : 0.0;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = t + e * 256;
+      {
+        const int kk = at ? idx / (2 * GBM) : idx % GBK, rc = at ? idx % (2 * GBM) : idx / GBK;
+        As[rc * GLS + kk] = ra[e];
+      }
+      Bs[(idx / GBK) * GLS + idx % GBK] = rbv[e];
+    }
+  };
+  const int nkb = (K + GBK - 1) / GBK;
+  if (nkb > 0) {
+    load(0);
+    store();
+  }
+  __syncthreads();
+  for (int kb = 0; kb < nkb; ++kb) {
+    if (kb + 1 < nkb) load((kb + 1) * GBK);  // in flight during the MFMAs below
+#pragma unroll
+    for (int k4 = 0; k4 < GBK / 4; ++k4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        av[i] = As[(qr + 16 * i + li) * GLS + 4 * k4 + lk];
+        bv[i] = Bs[(qc + 16 * i + li) * GLS + 4 * k4 + lk];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+    if (kb + 1 < nkb) store();
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gr = r0 + qr + 16 * i + lk + 4 * q;
+      if (gr >= R) continue;
+      const size_t rowbase = (size_t)(gr / rb) * rbs + (size_t)(gr % rb) * rs;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int gc = c0 + qc + 16 * j + li;
+        if (gc < Cn) C[rowbase + (size_t)(gc / cb) * cbs + (size_t)(gc % cb) * ldc] = acc[i][j][q];
+      }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gemm64_big(int R, int Cn, int K, const double* __restrict__ A, int lda,
+                                                    long Az, const double* __restrict__ B, long Bz, int ldb,
+                                                    double* __restrict__ C, long Cz, int rb, long rbs, int ldc,
+                                                    int at) {
+  gemm_tile_big(blockIdx.x, blockIdx.y, R, Cn, K, A + (size_t)blockIdx.z * Az, lda, B + (size_t)blockIdx.z * Bz,
+                ldb, C + (size_t)blockIdx.z * Cz, rb, rbs, ldc, 1, Cn, 0, at);
+}
+
 template <int GW>
 __global__ __launch_bounds__(64 * GW) void k_gemm64(int R, int Cn, int K, const double* __restrict__ A, int lda,
                                                     long Az, const double* __restrict__ B, long Bz, int ldb,
@@ -1000,6 +1094,16 @@ __global__ __launch_bounds__(64 * GW) void k_gemm64_multi(const GemmDesc* __rest
   if (D.live && !*D.live) return;  // uniform over the block, before any barrier
   const int local = b - D.start;
   gemm_tile<GW>(local % D.tr, local / D.tr, D.R, D.Cn, D.K, D.A, D.lda, D.B, D.ldb, D.C, D.rb, D.rbs, D.ldc, D.rs,
+                D.cb, D.cbs, D.at);
+}
+
+// Segmented launch of 64x64 tiles (descriptors built with 64-row tiles: tr = ceil(R / 64)).
+__global__ __launch_bounds__(256) void k_gemm64_multi_big(const GemmDesc* __restrict__ d, int nd) {
+  const int b = blockIdx.x;
+  const GemmDesc D = d[find_seg(d, nd, b)];
+  if (D.live && !*D.live) return;  // uniform over the block, before any barrier
+  const int local = b - D.start;
+  gemm_tile_big(local % D.tr, local / D.tr, D.R, D.Cn, D.K, D.A, D.lda, D.B, D.ldb, D.C, D.rb, D.rbs, D.ldc, D.rs,
                 D.cb, D.cbs, D.at);
 }
 
@@ -1277,6 +1381,14 @@ void launch_gemm64(hipStream_t s, int R, int Cn, int K, const double* A, int lda
     hipLaunchKernelGGL(k_gemm64<4>, g, dim3(256), 0, s, R, Cn, K, A, lda, Az, B, Bz, ldb, C, Cz, rb, rbs, ldc, at);
   else
     hipLaunchKernelGGL(k_gemm64<1>, g, dim3(64), 0, s, R, Cn, K, A, lda, Az, B, Bz, ldb, C, Cz, rb, rbs, ldc, at);
+}
+void launch_gemm64_big(hipStream_t s, int R, int Cn, int K, const double* A, int lda, long Az, const double* B,
+                       long Bz, int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch, int at) {
+  const dim3 g((R + 2 * GBM - 1) / (2 * GBM), (Cn + 2 * GBN - 1) / (2 * GBN), batch);
+  hipLaunchKernelGGL(k_gemm64_big, g, dim3(256), 0, s, R, Cn, K, A, lda, Az, B, Bz, ldb, C, Cz, rb, rbs, ldc, at);
+}
+void launch_gemm64_multi_big(hipStream_t s, const GemmDesc* d, int nd, int nblocks) {
+  if (nblocks > 0) hipLaunchKernelGGL(k_gemm64_multi_big, dim3(nblocks), dim3(256), 0, s, d, nd);
 }
 void launch_rhs(hipStream_t s, const double* ctr, const double* FT, const double* axes, const double* off, int n,
                 int M, int N, double a, double mu, double slip, double* rhs) {

@@ -155,6 +155,11 @@ void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, cons
 // grid z = batch with strides Az, Bz, Cz.
 void launch_gemm64(hipStream_t s, int R, int Cn, int K, const double* A, int lda, long Az, const double* B, long Bz,
                    int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch, int at = 0);
+// The same with 64x64 tiles (large products); the segmented form takes descriptors whose
+// tr and start count 64x64 tiles.
+void launch_gemm64_big(hipStream_t s, int R, int Cn, int K, const double* A, int lda, long Az, const double* B,
+                       long Bz, int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch, int at = 0);
+void launch_gemm64_multi_big(hipStream_t s, const GemmDesc* d, int nd, int nblocks);
 
 void launch_rhs(hipStream_t s, const double* ctr, const double* FT, const double* axes, const double* off, int n,
                 int M, int N, double a, double mu, double slip, double* rhs);

@@ -357,7 +357,7 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
     for (int i = 0; i < M; ++i) {
       const int ns = h_npart[i];
       if (ns == 0) {  // C_i = 0: a product with no terms writes zeros
-        push_gemm(gs, ngs, n3, n3, 0, pc.Dinv.p, n3, pc.Dinv.p, n3, pc.S.p + (size_t)i * nn, n3, 0, 1, n3, n3, 0, 0);
+        push_gemm(gs, ngs, n3, n3, 0, pc.Dinv.p, n3, pc.Dinv.p, n3, pc.S.p + (size_t)i * nn, n3, 0, 1, n3, n3, 0, 0, 1);
         continue;
       }
       const int ldi = ns * n3;
@@ -369,17 +369,17 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
         if (sj < 0) throw Error(PQN_ERR_STATE, "internal: near pair list is not symmetric");
         const int ldj = h_npart[j] * n3;
         push_gemm(gt, ngt, n3, n3, n3, pc.NB.p + pc.nbo[j] + (size_t)sj * n3, ldj, pc.Dinv.p, n3,
-                  pc.TB.p + pc.nbo[i] + (size_t)sl * n3, n3, 0, 1, ldi, n3, 0, 1);
+                  pc.TB.p + pc.nbo[i] + (size_t)sl * n3, n3, 0, 1, ldi, n3, 0, 1, 1);
       }
       // C_i = sum_s A_(i,s) T_(i,s): one product over the concatenated slots, row-major into S_i
       push_gemm(gs, ngs, n3, n3, ldi, pc.NB.p + pc.nbo[i], ldi, pc.TB.p + pc.nbo[i], ldi, pc.S.p + (size_t)i * nn,
-                n3, 0, 1, n3, n3, 0, 0);
+                n3, 0, 1, n3, n3, 0, 0, 1);
     }
     DescPack dp;
     const size_t ot = dp.add(gt), os = dp.add(gs);
     char* base = push_desc_pack(dp.host);
-    launch_gemm64_multi(s, (const GemmDesc*)(base + ot), (int)gt.size(), ngt);
-    launch_gemm64_multi(s, (const GemmDesc*)(base + os), (int)gs.size(), ngs);
+    launch_gemm64_multi_big(s, (const GemmDesc*)(base + ot), (int)gt.size(), ngt);
+    launch_gemm64_multi_big(s, (const GemmDesc*)(base + os), (int)gs.size(), ngs);
     hipLaunchKernelGGL(k_schur_finish, dim3(nblocks((long)M * nn)), dim3(256), 0, s, pc.D.p, n3, M, pc.S.p);
     // Newton-Schulz from X = D^{-1}
     pc.X2.alloc((size_t)M * nn);
@@ -389,7 +389,7 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
     std::vector<double> res(M);
     for (int step = 0;; ++step) {
       // W = S X (by columns): C(r, c) = sum_k S(r, k) X(k, c)
-      launch_gemm64(s, n3, n3, n3, pc.S.p, n3, (long)nn, pc.X.p, (long)nn, n3, pc.W.p, (long)nn, n3, 0, n3, M, 0);
+      launch_gemm64_big(s, n3, n3, n3, pc.S.p, n3, (long)nn, pc.X.p, (long)nn, n3, pc.W.p, (long)nn, n3, 0, n3, M, 0);
       hipLaunchKernelGGL(k_ns_residual, dim3(M), dim3(256), 0, s, pc.W.p, n3, pc.res.p);
       HIPCHK(hipMemcpyAsync(res.data(), pc.res.p, M * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -398,7 +398,7 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
       if (worst <= kNsTol || step == kNsMaxSteps) break;
       // X <- X (2I - W): C(r, c) = sum_k X(r, k) F(k, c), X read by columns
       hipLaunchKernelGGL(k_two_minus, dim3(nblocks((long)M * nn)), dim3(256), 0, s, pc.W.p, n3, M);
-      launch_gemm64(s, n3, n3, n3, pc.X.p, n3, (long)nn, pc.W.p, (long)nn, n3, pc.X2.p, (long)nn, n3, 0, n3, M, 1);
+      launch_gemm64_big(s, n3, n3, n3, pc.X.p, n3, (long)nn, pc.W.p, (long)nn, n3, pc.X2.p, (long)nn, n3, 0, n3, M, 1);
       std::swap(pc.X.p, pc.X2.p);
       ++pc.ns_iters;
     }
@@ -416,16 +416,16 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
       const int ldi = ns * n3;
       for (int sl = 0; sl < ns; ++sl) {
         push_gemm(gh, ngh, n3, n3, n3, pc.NB.p + pc.nbo[i] + (size_t)sl * n3, ldi, pc.DinvT.p, n3,
-                  pc.TB.p + pc.nbo[i] + (size_t)sl * nn, n3, 0, n3, 1, n3, 0, 0);
+                  pc.TB.p + pc.nbo[i] + (size_t)sl * nn, n3, 0, n3, 1, n3, 0, 0, 1);
         push_gemm(gg, ngg, n3, n3, n3, pc.X.p + (size_t)i * nn, n3, pc.TB.p + pc.nbo[i] + (size_t)sl * nn, n3,
-                  pc.NB.p + pc.nbo[i] + (size_t)sl * nn, n3, 0, n3, 1, n3, 0, 1);
+                  pc.NB.p + pc.nbo[i] + (size_t)sl * nn, n3, 0, n3, 1, n3, 0, 1, 1);
       }
     }
     DescPack dq;
     const size_t oh = dq.add(gh), og = dq.add(gg);
     char* qb = push_desc_pack(dq.host);
-    launch_gemm64_multi(s, (const GemmDesc*)(qb + oh), (int)gh.size(), ngh);
-    launch_gemm64_multi(s, (const GemmDesc*)(qb + og), (int)gg.size(), ngg);
+    launch_gemm64_multi_big(s, (const GemmDesc*)(qb + oh), (int)gh.size(), ngh);
+    launch_gemm64_multi_big(s, (const GemmDesc*)(qb + og), (int)gg.size(), ngg);
     HIPCHK(hipStreamSynchronize(s));  // dnbo and the descriptor tables are released/reused after this
   }
   // block rows in FP32: sphere i holds S_i^{-1} (or D^{-1}) then G_(i,s) for its slots
