@@ -70,6 +70,18 @@ def far_kernel_name(layout, K):
     return f'k_far32<{layout["tpt"] if K <= 2 else 1},{K}>'
 
 
+def pc_blocks(c, near_gap=0.5, radius=1.0):
+    """Blocks of the preconditioner: one per sphere and one per ordered near pair (gap < near_gap)."""
+    d = np.linalg.norm(c[:, None, :] - c[None, :, :], axis=2) - 2 * radius
+    np.fill_diagonal(d, np.inf)
+    return int(c.shape[0] + (d < near_gap).sum())
+
+
+def precond_bytes(M, n, nblocks):
+    """HBM bytes of one preconditioner application: the FP32 blocks (3n)^2 each, streamed once."""
+    return int(nblocks * (3 * n) ** 2 * 4)
+
+
 def flop_per_pair(K):
     """Algorithmic flops of one far pair with K densities (FMA = 2, rsqrt = 1): 18 shared + 12 per density."""
     return 18 + 12 * K
@@ -98,6 +110,9 @@ def main():
     ap.add_argument('--chunks', type=int, default=None, help='far source chunks (default: autotuned)')
     ap.add_argument('--split', type=int, default=None, choices=(0, 1),
                     help='far FP32 split layout, 64 targets per block (default: autotuned)')
+    ap.add_argument('--no-precond', action='store_true',
+                    help='plain GMRES everywhere (default: the near-patch preconditioner on every '
+                         'single-suspension context; the headline is also measured without it)')
     ap.add_argument('--serial', action='store_true',
                     help='one stream everywhere (no side stream beside the far pair sum): every kernel runs '
                          'alone, as in the profiles of individual kernels')
@@ -141,16 +156,24 @@ def main():
     K, W = args.steps, args.warmup
     pf = far_pairs(c, n)
 
-    def ctx_for(prec, kr=K_RHS, profile=True, warm_start=False, side=None):
+    PC = not args.no_precond
+    # the preconditioner: built at the first solve where a configuration serves many products
+    # (the MVP passes and LCP solves), when a configuration is solved a second time in the
+    # time steps (a step without contacts solves once and never pays for the set-up)
+    PC_FIXED = 'eager' if PC else False
+
+    def ctx_for(prec, kr=K_RHS, profile=True, warm_start=False, side=None, precond=None):
         """Context with the launch layout tuned for kr densities per pass (unless fixed on the command line).
         side: run the GEMM / near / moment work on a second stream beside the far pair sum (default: for the
         mixed path, where it measured 5-7% faster; the FP64 K = 6 pass was 2.5% slower with it). Profiled
-        contexts time the far kernel alone and keep one stream."""
+        contexts time the far kernel alone and keep one stream. precond: right-preconditioned GMRES
+        (default: on unless --no-precond)."""
         if side is None:
             side = prec == 'mixed' and not profile and not args.serial
         return binding.Context(c, None, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision=prec, tpt=args.tpt,
                                far_chunks=args.chunks, far_split=args.split, stream=stream.cuda_stream,
-                               profile=profile, tune_K=kr, warm_start=warm_start, side_stream=side)
+                               profile=profile, tune_K=kr, warm_start=warm_start, side_stream=side,
+                               precond=PC_FIXED if precond is None else precond)
 
     FT6 = [inputs.random_forces(100 + k, M, k=K_RHS) for k in range(max(K, 2) + W + 2)]
     # the timed products read forces from and write velocities to HBM (no host copies)
@@ -202,21 +225,29 @@ def main():
         return
 
     def run_multi(ctx, steps, warm, kr):
+        # the preconditioner is built in the first product after a configuration change (warm-up)
+        setup_ms = 0.0
         for k in range(warm):
-            ctx.mobility_apply_multi_dev(kr, FT6_dev[k].data_ptr(), UO_dev.data_ptr())
+            st = ctx.mobility_apply_multi_dev(kr, FT6_dev[k].data_ptr(), UO_dev.data_ptr())
+            setup_ms += st['t_precond_ms']
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        its = far_ms = nfar = mv = 0
+        its = far_ms = nfar = mv = pc_ms = pc_n = pc_setup_timed = 0
         for k in range(steps):
             st = ctx.mobility_apply_multi_dev(kr, FT6_dev[warm + k].data_ptr(), UO_dev.data_ptr())
             its += st['gmres_iters']
             far_ms += st['t_far_ms']
             nfar += st['n_far']
             mv += st['matvecs']
+            pc_ms += st['t_precond_apply_ms']
+            pc_n += st['precond_applies']
+            pc_setup_timed += st['t_precond_ms']
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         return dict(steps=steps, sec=sec, mvps=steps * kr / sec, gmres_iters=its / (steps * kr),
-                    far_ms=far_ms / max(nfar, 1), matvecs_per_mvp=mv / (steps * kr), far_launches=nfar)
+                    far_ms=far_ms / max(nfar, 1), matvecs_per_mvp=mv / (steps * kr), far_launches=nfar,
+                    precond_setup_ms=setup_ms, precond_setup_in_timed_ms=pc_setup_timed,
+                    precond_apply_ms=pc_ms / max(pc_n, 1), precond_applies=pc_n)
 
     res = {}
     # headline: the library's fastest configuration (side stream on the mixed path), no event timing
@@ -236,6 +267,11 @@ def main():
         prof1 = run_multi(cp1, max(2, K // 2), 1, 1)
     log('mixed K=1 far kernel alone', prof1)
     res['mixed6']['far_ms'], res['mixed1']['far_ms'] = prof6['far_ms'], prof1['far_ms']
+    # the headline product with plain GMRES (no preconditioner), for comparison and for the
+    # oracle's matvec count (its GMRES is unpreconditioned)
+    with ctx_for('mixed', profile=False, precond=False) as cpl:
+        plain6 = run_multi(cpl, K, W, K_RHS)
+    log('mixed K=6 plain GMRES', plain6)
     cf = ctx_for('fp64')
     res['fp64_6'] = run_multi(cf, max(1, K // 3), 1, K_RHS)
     log('fp64 K=6', res['fp64_6'], cf.far_shape)
@@ -270,7 +306,7 @@ def main():
         # and recursive Bi-PQN over three fidelities: that model, then the coarse grid at 1e-3
         with binding.Context(c, None, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3, lo2=w['lo'],
                              gmres_tol_lo2=1e-3, precision='mixed', tpt=args.tpt, far_chunks=args.chunks,
-                             far_split=args.split, stream=stream.cuda_stream, tune_K=1) as cb:
+                             far_split=args.split, stream=stream.cuda_stream, tune_K=1, precond=PC_FIXED) as cb:
             t3 = time.perf_counter()
             x4, lt = cb.lcp_solve(pairs, b, 'bi')
             t4 = time.perf_counter()
@@ -283,7 +319,7 @@ def main():
             with binding.Context(c, None, nt, nph, lo=(nt, nph), far_coarse_lo=6, gmres_tol=1e-8,
                                  gmres_tol_lo=tol_lo, precision='mixed', tpt=args.tpt, far_chunks=args.chunks,
                                  far_split=args.split, stream=stream.cuda_stream, tune_K=1,
-                                 side_stream=not args.serial) as ccf:
+                                 side_stream=not args.serial, precond=PC_FIXED) as ccf:
                 ccf.lcp_solve(pairs, b, 'bi')       # the coarse-grid tables and buffers warm
                 torch.cuda.synchronize()
                 t0c = time.perf_counter()
@@ -325,7 +361,7 @@ def main():
         tight = dict(kkt_tol_abs=1e-10, gmres_tol=1e-10, b_from='FP64 product at GMRES 1e-12')
         xe = lambda x_: float(np.abs(x_ - xs).max() / np.abs(xs).max())
         kw_t = dict(lo=w['lo'], tpt=args.tpt, far_chunks=args.chunks, far_split=args.split,
-                    stream=stream.cuda_stream, tune_K=1)
+                    stream=stream.cuda_stream, tune_K=1, precond=PC_FIXED)
         with binding.Context(c, None, nt, nph, precision='fp64', gmres_tol=1e-12, **kw_t) as cref:
             b_t = ws - cref.lcp_apply(pairs, xs)
         with binding.Context(c, None, nt, nph, precision='fp64', gmres_tol=1e-10, **kw_t) as cf64, \
@@ -377,7 +413,7 @@ def main():
         axes = inputs.janus_axes(args.seed + 7, M)
         nsteps, dt = 10, 1e-3
         states, t64, st64 = [(c, axes)], [], []
-        with ctx_for('fp64', 1, profile=False, warm_start=True) as cs:
+        with ctx_for('fp64', 1, profile=False, warm_start=True, precond=PC) as cs:
             cs.set_state(c, axes)
             for _ in range(nsteps):
                 torch.cuda.synchronize()
@@ -392,7 +428,7 @@ def main():
             with binding.Context(c, None, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='mixed', refine=refine,
                                  tpt=args.tpt, far_chunks=args.chunks, far_split=args.split,
                                  stream=stream.cuda_stream, tune_K=1, warm_start=True,
-                                 side_stream=not args.serial) as cs:
+                                 side_stream=not args.serial, precond=PC) as cs:
                 for k in range(nsteps):
                     cs.set_state(*states[k])
                     torch.cuda.synchronize()
@@ -404,7 +440,7 @@ def main():
                     dmax = max(dmax, float(np.abs(cm_k - states[k + 1][0]).max() / np.abs(disp).max()))
             mixed[name] = (tmx, dmax)
         tmx, dmax = mixed['mixed']
-        step_info = dict(steps=nsteps, dt=dt, contacts=[s_['n_contacts'] for s_ in st64],
+        step_info = dict(steps=nsteps, dt=dt, precond='on reuse' if PC else 'off', contacts=[s_['n_contacts'] for s_ in st64],
                          active=[s_['n_active'] for s_ in st64],
                          mvp_hi=[s_['lcp']['mvp_hi'] for s_ in st64], mvp_lo=[s_['lcp']['mvp_lo'] for s_ in st64],
                          gmres_iters_nc=[s_['gmres_iters_nc'] for s_ in st64],
@@ -508,6 +544,17 @@ def main():
         'mixed_rel_err_vs_fp64': errs,
         'gmres_iters_per_mvp': {k: round(v['gmres_iters'], 2) for k, v in res.items()},
         'far_kernel_ms': {k: round(v['far_ms'], 4) for k, v in res.items()},
+        'precond': None if not PC else {
+            'kind': 'near-patch Schur complements, right preconditioning (config precond)',
+            'setup_ms': round(m6['precond_setup_ms'], 1),
+            'setup_ms_in_timed_region': round(m6['precond_setup_in_timed_ms'], 1),
+            'apply_ms_k6': round(prof6['precond_apply_ms'], 4),
+            'apply_hbm_gbs_k6': round(precond_bytes(M, n, pc_blocks(c)) / (prof6['precond_apply_ms'] * 1e-3) / 1e9, 1)
+            if prof6['precond_apply_ms'] > 0 else None,
+            'block_bytes': precond_bytes(M, n, pc_blocks(c)),
+            'plain_gmres': {'mvps': round(plain6['mvps'], 4), 'gmres_iters_per_mvp': round(plain6['gmres_iters'], 2),
+                            'ms_per_step': round(1e3 * plain6['sec'] / plain6['steps'], 3)},
+            'speedup_vs_plain': round(m6['mvps'] / plain6['mvps'], 3)},
         'roofline': {'bound': 'alu', 'kernel': far_kernel_name(cm_layout, K_RHS), 'achieved': round(achieved, 3),
                      'peak': PEAK_FP32_VECTOR, 'unit': 'TFLOP/s', 'frac': round(achieved / PEAK_FP32_VECTOR, 4),
                      'flop_per_pair': flop_per_pair(K_RHS), 'layout': cm_layout,
@@ -525,7 +572,7 @@ def main():
     out['host'] = {'gpu': torch.cuda.get_device_name(0), 'cpu_model': cpu_model(),
                    'cpu_threads_available': len(os.sched_getaffinity(0)), 'gpu_sclk_mhz': gpu_sclk()}
     if not args.no_cpu_baseline:
-        out['cpu_baseline'] = cpu_baseline(c, nt, nph, res['mixed1'])
+        out['cpu_baseline'] = cpu_baseline(c, nt, nph, plain6)
     print(json.dumps(out), flush=True)
 
 
@@ -542,9 +589,10 @@ def contact_steps(binding, inputs, torch, stream, w, args, replay_solvers=True):
     nin, dt_in = 5, 0.1
     try:
         states_in, rows = [(c, ax_in)], []
+        pc = not getattr(args, 'no_precond', False)
         with binding.Context(c, ax_in, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='fp64', tune_K=1,
                              warm_start=True, near_close_gap=0.02, near_close_up=3,
-                             stream=stream.cuda_stream) as cs:
+                             stream=stream.cuda_stream, precond=pc) as cs:
             for _ in range(nin):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -571,7 +619,7 @@ def contact_steps(binding, inputs, torch, stream, w, args, replay_solvers=True):
 
         with binding.Context(c, ax_in, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='mixed', tune_K=1,
                              warm_start=True, near_close_gap=0.02, near_close_up=3,
-                             stream=stream.cuda_stream, side_stream=not args.serial) as cs:
+                             stream=stream.cuda_stream, side_stream=not args.serial, precond=pc) as cs:
             for k in range(nin):
                 cs.set_state(*states_in[k])
                 torch.cuda.synchronize()
@@ -593,9 +641,10 @@ def contact_steps(binding, inputs, torch, stream, w, args, replay_solvers=True):
                 with binding.Context(c, ax_in, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3,
                                      precision='mixed', tune_K=1, warm_start=True, near_close_gap=0.02,
                                      near_close_up=3, stream=stream.cuda_stream, side_stream=not args.serial,
-                                     **kw_lo) as cs:
+                                     precond=pc, **kw_lo) as cs:
                     replay(cs, 'bi', name, active_k)
         inward_info = dict(steps=nin, dt=dt_in, near_close_gap=0.02, near_close_up=3,
+                           precond='on reuse' if pc else 'off',
                            axes='towards the centroid',
                            contacts=[r[1]['n_contacts'] for r in rows], active=[r[1]['n_active'] for r in rows],
                            mvp_hi=[r[1]['lcp']['mvp_hi'] for r in rows],
@@ -853,7 +902,8 @@ def cpu_baseline(c, nt, nph, mixed):
               f'oracle\'s '
               f'double-layer sums in {cores} single-threaded processes (target spheres dealt round-robin), '
               f'self block and rigid projection of all spheres, near-pair blocks applied on {len(sample)} '
-              f'of {len(near)} (built before the timed region) and scaled; x {mpm:.1f} matvecs per MVP')
+              f'of {len(near)} (built before the timed region) and scaled; x {mpm:.1f} matvecs per MVP '
+              f'(the oracle\'s GMRES is unpreconditioned: the GPU path\'s plain-GMRES count)')
     return {'value': round(1.0 / (tall * mpm), 8), 'unit': 'MVP/s', 'cores': cores, 'kind': 'oracle',
             'sample': detail, 'matvec_sec': round(tall, 3),
             'single_core': {'value': round(1.0 / (t1 * mpm), 8), 'unit': 'MVP/s', 'cores': 1,

@@ -118,14 +118,17 @@ typedef struct {
                                representation for its low fidelity; with n_theta_lo = n_theta this lowers
                                it for the far field only. 0 = the node rule; else 2..n_theta_lo */
   int32_t far_coarse_lo2;   /* the same for the second low fidelity (2..n_theta_lo2) */
-  int32_t precond;          /* 1 = every GMRES solve is right-preconditioned (Sec. 2 calls for
-                               preconditioned Krylov solves without fixing one): for sphere i with
-                               near partners j, (P v)_i = inv(S_i) (v_i - sum_j A_ij inv(D) v_j),
+  int32_t precond;          /* right-preconditioned GMRES (Sec. 2 calls for preconditioned Krylov
+                               solves without fixing one): for sphere i with near partners j,
+                               (P v)_i = inv(S_i) (v_i - sum_j A_ij inv(D) v_j),
                                S_i = D - sum_j A_ij inv(D) A_ji, D the single-sphere block and A_ij
-                               the near blocks. Same solution and stopping rule (true residual);
-                               fewer iterations. Built at the first solve after each configuration
-                               change (pqn_mvp_stats.t_precond_ms); device memory about
-                               (2 n_near + 4 M) (3n)^2 doubles. Not for batch contexts [0] */
+                               the near blocks; applied as one block-sparse product with FP32
+                               blocks. Same solution and stopping rule (true residual), fewer
+                               iterations. The set-up (pqn_mvp_stats.t_precond_ms) is per
+                               configuration and fidelity: 1 = built when a configuration is solved
+                               a second time (its first solve is plain), 2 = built at the first
+                               solve; 0 = plain GMRES. Device memory about (2 n_near + 4 M) (3n)^2
+                               doubles. Not for batch contexts [0] */
 } pqn_config_desc;
 
 typedef struct {
@@ -149,6 +152,9 @@ typedef struct {
   double t_precond_ms;      /* precond = 1: wall time of preconditioner set-ups in this call */
   int32_t precond_fallback; /* precond = 1: spheres whose Schur complement inverse did not converge
                                in those set-ups (they use inv(D)) */
+  int32_t precond_applies;  /* precond = 1: applications of the preconditioner (one per group of
+                               densities per GMRES iteration, one per system per cycle end) */
+  double t_precond_apply_ms; /* profile = 1: summed HIP-event time of those applications */
 } pqn_mvp_stats;
 
 typedef struct {

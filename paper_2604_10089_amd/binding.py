@@ -77,7 +77,8 @@ class MvpStats(C.Structure):
                 ('t_far_ms', C.c_double), ('n_far', C.c_int32), ('graph_launches', C.c_int32),
                 ('fp64_fallback', C.c_int32), ('t_near_ms', C.c_double), ('t_gemm_ms', C.c_double),
                 ('t_local_ms', C.c_double), ('t_arnoldi_ms', C.c_double), ('t_precond_ms', C.c_double),
-                ('precond_fallback', C.c_int32)]
+                ('precond_fallback', C.c_int32), ('precond_applies', C.c_int32),
+                ('t_precond_apply_ms', C.c_double)]
 
 
 class LcpOpts(C.Structure):
@@ -247,7 +248,9 @@ def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_
     d.side_stream = 1 if side_stream else 0
     d.near_close_gap, d.near_close_up = near_close_gap, near_close_up
     d.far_coarse_lo, d.far_coarse_lo2 = far_coarse_lo, far_coarse_lo2
-    d.precond = 1 if precond else 0
+    # precond: False / 0 = plain GMRES, True / 1 = built when a configuration is solved a second
+    # time, 'eager' / 2 = built at its first solve
+    d.precond = 2 if precond in ('eager', 2) else (1 if precond else 0)
     return d
 
 

@@ -52,6 +52,8 @@ static void stage_stats(const pqn_ctx_impl& c, pqn_mvp_stats& st) {
   st.t_arnoldi_ms = c.stage_ms[pqn_ctx_impl::kStageArnoldi];
   st.t_precond_ms = c.pc_setup_ms;
   st.precond_fallback = c.pc_fallback;
+  st.precond_applies = c.pc_applies;
+  st.t_precond_apply_ms = c.stage_ms[pqn_ctx_impl::kStagePrecond];
 }
 
 // nullptr if the context has the fidelities the (valid) solver needs, else the reason.
@@ -81,7 +83,7 @@ static std::string check_desc(const pqn_config_desc& c) {
     return "far_coarse_lo needs a low-fidelity grid and 2 <= far_coarse_lo <= n_theta_lo";
   if (c.far_coarse_lo2 != 0 && (c.n_theta_lo2 == 0 || c.far_coarse_lo2 < 2 || c.far_coarse_lo2 > c.n_theta_lo2))
     return "far_coarse_lo2 needs a second low-fidelity grid and 2 <= far_coarse_lo2 <= n_theta_lo2";
-  if (c.precond != 0 && c.precond != 1) return "precond must be 0 or 1";
+  if (c.precond < 0 || c.precond > 2) return "precond must be 0, 1 or 2";
   return "";
 }
 
@@ -200,6 +202,7 @@ static pqn_status batch_apply_common(pqn_ctx* ctx, const double* const* FT, doub
   ctx->n_graph_launch = 0;
   ctx->pc_setup_ms = 0.0;
   ctx->pc_fallback = 0;
+  ctx->pc_applies = 0;
   ctx->n_far = 0;
   std::vector<SysRef> sys;
   for (int b = 0; b < nb; ++b) {
@@ -287,6 +290,7 @@ static pqn_status mobility_multi_common(pqn_ctx* ctx, int32_t k_rhs, const doubl
   ctx->n_graph_launch = 0;
   ctx->pc_setup_ms = 0.0;
   ctx->pc_fallback = 0;
+  ctx->pc_applies = 0;
   ctx->n_far = 0;
   pqn_mvp_stats st{};
   ctx->mobility_multi(lv, k_rhs, fp, nullptr, up, &st);
@@ -383,6 +387,7 @@ static pqn_status mobility_common(pqn_ctx* ctx, const double* FT_dev, const doub
   ctx->n_graph_launch = 0;
   ctx->pc_setup_ms = 0.0;
   ctx->pc_fallback = 0;
+  ctx->pc_applies = 0;
   ctx->n_far = 0;
   ctx->mobility(lv, FT_dev, axes_dev, UO_dev, &st);
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -502,6 +507,7 @@ pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, doub
     ctx->n_graph_launch = 0;
     ctx->pc_setup_ms = 0.0;
     ctx->pc_fallback = 0;
+  ctx->pc_applies = 0;
     ctx->n_far = 0;
     SysBuf& b = lv.sb(0);
     HIPCHK(hipMemcpyAsync(b.rhs.p, rhs, len * sizeof(double), hipMemcpyHostToDevice, ctx->stream));

@@ -1020,16 +1020,39 @@ void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision)
   };
   auto nrm_slot = [&](int i) { return hdev.p + (size_t)i * hs + 2 * (m + 1); };
   // right preconditioning (config precond): the Arnoldi vectors enter the operator as
-  // z = P V[k] and a cycle ends with x += P (V y); set up for the current configuration
+  // z = P V[k] and a cycle ends with x += P (V y). The preconditioner of a level is built
+  // for the current configuration at its first solve (precond = 2) or when the
+  // configuration is solved a second time (precond = 1: a configuration solved once, such
+  // as a time step without contacts, never pays for the set-up); decided once per level.
   std::vector<char> pcs(ns, 0);
   bool any_pc = false;
-  for (int i = 0; i < ns; ++i)
-    if (sys[i].c->cfg.precond) {
-      sys[i].c->precond_setup(*sys[i].lv);
-      sys[i].lv->sb(sys[i].slot).z.alloc((size_t)len_of(i));
-      pcs[i] = 1;
-      any_pc = true;
+  {
+    std::vector<std::pair<Level*, bool>> decided;
+    for (int i = 0; i < ns; ++i) {
+      pqn_ctx_impl& c = *sys[i].c;
+      Level& lv = *sys[i].lv;
+      if (!c.cfg.precond) continue;
+      int use = -1;
+      for (auto& d : decided)
+        if (d.first == &lv) use = d.second;
+      if (use < 0) {
+        bool u = lv.pc.epoch == c.config_epoch;
+        if (!u && (c.cfg.precond == 2 || lv.pc.seen == c.config_epoch)) {
+          c.precond_setup(lv);
+          u = true;
+        } else if (!u) {
+          lv.pc.seen = c.config_epoch;
+        }
+        decided.emplace_back(&lv, u);
+        use = u;
+      }
+      if (use) {
+        lv.sb(sys[i].slot).z.alloc((size_t)len_of(i));
+        pcs[i] = 1;
+        any_pc = true;
+      }
     }
+  }
   // right-hand side norms
   for (int i = 0; i < ns; ++i) {
     SysBuf& b = sys[i].lv->sb(sys[i].slot);

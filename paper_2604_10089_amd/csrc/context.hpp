@@ -134,6 +134,7 @@ struct SysBuf {
 struct Precond {
   bool has_d = false;
   unsigned long epoch = 0;       // configuration of the tables below (0 = none yet)
+  unsigned long seen = 0;        // configuration last solved without them (precond = 1)
   DevArray<double> D, Dinv;      // [3n][3n] row-major
   DevArray<double> DinvT;        // D^{-1} by columns ([3n][3n] row-major of its transpose)
   DevArray<double> NB, TB;       // per sphere [3n][npart_i 3n] row-major, at nbo[i] doubles
@@ -349,7 +350,7 @@ struct pqn_ctx_impl {
   // profiling of far launches
   // profile = 1: HIP events around every launch of each stage of the operator, on the
   // main stream (the side stream is not used while profiling)
-  enum { kStageFar = 0, kStageNear, kStageGemm, kStageLocal, kStageArnoldi, kNumStages };
+  enum { kStageFar = 0, kStageNear, kStageGemm, kStageLocal, kStageArnoldi, kStagePrecond, kNumStages };
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[kNumStages];
   size_t ev_used[kNumStages] = {};
   double stage_ms[kNumStages] = {};  // totals of the last end_far_timing()
@@ -416,8 +417,9 @@ struct pqn_ctx_impl {
   // near tiles only: near_part of the group's slots from its densities (with their
   // coefficient and upsampling GEMMs), on the main stream
   void near_stage(MvGroup& gr);
-  double pc_setup_ms = 0.0;  // preconditioner set-up time and fallbacks since the last reset
+  double pc_setup_ms = 0.0;  // preconditioner set-up time, fallbacks and applications since the last reset
   int pc_fallback = 0;
+  int pc_applies = 0;
   void mobility(Level& lv, const double* FT_dev, const double* axes_dev, double* UO_dev, pqn_mvp_stats* st) {
     mobility_multi(lv, 1, &FT_dev, axes_dev, &UO_dev, st);
   }

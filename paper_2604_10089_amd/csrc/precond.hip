@@ -480,6 +480,7 @@ void pqn_ctx_impl::precond_apply(MvGroup& gr) {
     vin.p[r] = gr.in[r];
     out.p[r] = gr.out[r];
   }
+  stage_begin(kStagePrecond);
   hipLaunchKernelGGL(k_pc_interleave, dim3(nblocks((long)M * n3 * K)), dim3(256), 0, s, vin, K, n, M, N, pc.vI.p);
   const int rchunks = (n3 + 255) / 256;
   const dim3 g(pc.nblk * rchunks);
@@ -497,6 +498,8 @@ void pqn_ctx_impl::precond_apply(MvGroup& gr) {
 #undef BSRK
   hipLaunchKernelGGL(k_bsr_sum, dim3(nblocks((long)M * K * n3)), dim3(256), 0, s, pc.part.p, pc.bptr.p, K, n, M, N,
                      out);
+  stage_end(kStagePrecond);
+  ++pc_applies;
 }
 
 }  // namespace bipqn

@@ -35,7 +35,7 @@ def test_preconditioned_bie_solve_matches_oracle_and_its_iteration_count(tiny_ca
         _, its_o, _ = bie.gmres(lambda v: A @ v.ravel(), rhs, tol=1e-10, right=P)
         _, its_plain, _ = bie.gmres(lambda v: A @ v.ravel(), rhs, tol=1e-10)
         c = g.c
-        with binding.Context(c, None, 8, 16, gmres_tol=1e-10, precond=True) as ctx:
+        with binding.Context(c, None, 8, 16, gmres_tol=1e-10, precond='eager') as ctx:
             qd, st = ctx.bie_solve(soa(rhs))
         say('precond tiny seed', seed, 'gpu its', st['gmres_iters'], 'oracle', its_o, 'plain', its_plain,
             'setup ms', round(st['t_precond_ms'], 2), 'fallback', st['precond_fallback'])
@@ -50,7 +50,7 @@ def test_preconditioned_mobility_matches_oracle(tiny_cases, prec, tol):
     _, g, A = tiny_cases[0]
     FT = inputs.random_forces(7, g.M)
     Uo = bie.mobility_apply(g, FT, dense=A)
-    with binding.Context(g.c, None, 8, 16, gmres_tol=1e-11, precision=prec, precond=True) as ctx:
+    with binding.Context(g.c, None, 8, 16, gmres_tol=1e-11, precision=prec, precond='eager') as ctx:
         U, st = ctx.mobility_apply(FT)
     say('precond mobility tiny', prec, st['gmres_iters'], rel(U, Uo))
     assert st['converged'] == 1
@@ -62,7 +62,7 @@ def test_lone_near_pair_is_solved_in_one_iteration():
     (Schur complement), so GMRES ends after one iteration."""
     c = np.array([[0.0, 0.0, 0.0], [2.04, 0.2, -0.1]])
     rhs = np.random.default_rng(5).standard_normal((3, 2 * 128))
-    with binding.Context(c, None, 8, 16, gmres_tol=1e-10, precond=True) as ctx:
+    with binding.Context(c, None, 8, 16, gmres_tol=1e-10, precond='eager') as ctx:
         q, st = ctx.bie_solve(rhs)
         y = ctx.bie_apply(q)
     say('lone pair its', st['gmres_iters'])
@@ -73,7 +73,7 @@ def test_lone_near_pair_is_solved_in_one_iteration():
 def test_configuration_change_rebuilds_the_preconditioner(tiny_cases):
     (_, g0, A0), (_, g1, A1) = tiny_cases
     FT = inputs.random_forces(11, g0.M)
-    with binding.Context(g0.c, None, 8, 16, gmres_tol=1e-11, precond=True) as ctx:
+    with binding.Context(g0.c, None, 8, 16, gmres_tol=1e-11, precond='eager') as ctx:
         U0, s0 = ctx.mobility_apply(FT)
         U0b, s0b = ctx.mobility_apply(FT)
         ctx.set_state(g1.c)
@@ -95,7 +95,7 @@ def test_packing64_preconditioned_equals_plain(close):
     FT = inputs.random_forces(17, c.shape[0])
     out = {}
     for pc in (False, True):
-        with binding.Context(c, None, 12, 24, gmres_tol=1e-10, precond=pc, **kw) as ctx:
+        with binding.Context(c, None, 12, 24, gmres_tol=1e-10, precond='eager' if pc else False, **kw) as ctx:
             out[pc] = ctx.mobility_apply(FT)
     (U0, s0), (U1, s1) = out[False], out[True]
     say('packing64 close', close, 'its', s0['gmres_iters'], s1['gmres_iters'], 'setup ms',
@@ -116,7 +116,7 @@ def test_rsa216_six_force_sets_mixed():
     out = {}
     for pc in (False, True):
         with binding.Context(c, None, 12, 24, gmres_tol=1e-8, precision='mixed', tune_K=6, side_stream=True,
-                             precond=pc) as ctx:
+                             precond='eager' if pc else False) as ctx:
             out[pc] = ctx.mobility_apply_multi(FT)
     (U0, s0), (U1, s1) = out[False], out[True]
     say('rsa216 K=6 its', s0['gmres_iters'], s1['gmres_iters'], 'setup ms', round(s1['t_precond_ms'], 1),
@@ -133,7 +133,7 @@ def test_preconditioned_lcp_and_step_equal_plain(tiny_cases):
     res = {}
     b = None
     for pc in (False, True):
-        with binding.Context(g.c, ax, 8, 16, lo=(4, 8), gmres_tol=1e-11, precond=pc) as ctx:
+        with binding.Context(g.c, ax, 8, 16, lo=(4, 8), gmres_tol=1e-11, precond=pc) as ctx:  # on reuse
             pairs, gaps = ctx.find_contacts(0.1)
             assert len(pairs) > 0
             if b is None:
@@ -150,5 +150,31 @@ def test_preconditioned_lcp_and_step_equal_plain(tiny_cases):
 def test_batch_contexts_reject_precond():
     inst = inputs.batched_suspensions(0, n_inst=2)
     with pytest.raises(binding.PqnError) as e:
-        binding.BatchContext(inst, precond=True)
+        binding.BatchContext(inst, precond='eager')
     assert e.value.status == -1  # PQN_ERR_INVALID
+
+
+def test_precond_on_reuse_builds_at_the_second_solve_of_a_configuration(tiny_cases):
+    """precond = 1: the first solve of a configuration is plain GMRES (no set-up), the second
+    builds the preconditioner and uses it, later ones reuse it; a new configuration starts over."""
+    (_, g0, A0), (_, g1, _) = tiny_cases
+    FT = inputs.random_forces(13, g0.M)
+    with binding.Context(g0.c, None, 8, 16, gmres_tol=1e-11) as plain:
+        U_ref, s_ref = plain.mobility_apply(FT)
+    with binding.Context(g0.c, None, 8, 16, gmres_tol=1e-11, precond=True) as ctx:
+        U1, s1 = ctx.mobility_apply(FT)
+        U2, s2 = ctx.mobility_apply(FT)
+        U3, s3 = ctx.mobility_apply(FT)
+        ctx.set_state(g1.c)
+        _, s4 = ctx.mobility_apply(FT)
+        _, s5 = ctx.mobility_apply(FT)
+    say('on reuse: its', s1['gmres_iters'], s2['gmres_iters'], s3['gmres_iters'], s4['gmres_iters'],
+        s5['gmres_iters'], 'set-up', s1['t_precond_ms'], s2['t_precond_ms'], s3['t_precond_ms'],
+        s4['t_precond_ms'], s5['t_precond_ms'])
+    assert s1['t_precond_ms'] == 0 and s1['precond_applies'] == 0 and s1['gmres_iters'] == s_ref['gmres_iters']
+    assert np.array_equal(U1, U_ref)
+    assert s2['t_precond_ms'] > 0 and s2['precond_applies'] > 0 and s2['gmres_iters'] < 0.6 * s1['gmres_iters']
+    assert s3['t_precond_ms'] == 0 and s3['gmres_iters'] == s2['gmres_iters'] and np.array_equal(U3, U2)
+    assert rel(U2, U1) < 1e-9
+    assert s4['t_precond_ms'] == 0 and s4['precond_applies'] == 0
+    assert s5['t_precond_ms'] > 0
