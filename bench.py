@@ -78,8 +78,8 @@ def pc_blocks(c, near_gap=0.5, radius=1.0):
 
 
 def precond_bytes(M, n, nblocks):
-    """HBM bytes of one preconditioner application: the FP32 blocks (3n)^2 each, streamed once."""
-    return int(nblocks * (3 * n) ** 2 * 4)
+    """HBM bytes of one preconditioner application: the FP16 blocks (3n)^2 each, streamed once."""
+    return int(nblocks * (3 * n) ** 2 * 2)
 
 
 def flop_per_pair(K):

@@ -122,8 +122,9 @@ typedef struct {
                                solves without fixing one): for sphere i with near partners j,
                                (P v)_i = inv(S_i) (v_i - sum_j A_ij inv(D) v_j),
                                S_i = D - sum_j A_ij inv(D) A_ji, D the single-sphere block and A_ij
-                               the near blocks; applied as one block-sparse product with FP32
-                               blocks. Same solution and stopping rule (true residual), fewer
+                               the near blocks; applied as one block-sparse product with FP16
+                               blocks (each scaled by its largest magnitude). Same solution and
+                               stopping rule (true residual), fewer
                                iterations. The set-up (pqn_mvp_stats.t_precond_ms) is per
                                configuration and fidelity: 1 = built when a configuration is solved
                                a second time (its first solve is plain), 2 = built at the first

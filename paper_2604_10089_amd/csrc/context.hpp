@@ -142,7 +142,8 @@ struct Precond {
   DevArray<double> S, X, X2, W;  // [M][3n][3n]; S row-major, X (= S^{-1}), X2, W by columns
   DevArray<double> res;          // [M] Newton-Schulz residuals
   DevArray<double> ug;           // kMaxRhs unit densities [3][N] (near-block assembly)
-  DevArray<float> B32;           // the preconditioner's blocks in FP32, by columns, row of sphere i
+  DevArray<_Float16> B16;        // the preconditioner's blocks in FP16, by columns, row of sphere i
+  DevArray<float> bscale;        // each block's largest magnitude (its FP16 copy is divided by it)
   DevArray<int> bptr, bcol;      // first block of sphere i's row [M + 1]; column sphere of each block
   DevArray<double> vI;           // input densities interleaved per node [M][3n][K]
   DevArray<double> part;         // per-block partial products [nblk][K][3n]

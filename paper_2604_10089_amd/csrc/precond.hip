@@ -30,16 +30,18 @@
 //
 //   - G_ij = S_i^{-1} A_ij D^{-1} for every near pair, so that
 //     (P_r v)_i = S_i^{-1} v_i - sum_j G_ij v_j: one block-sparse product whose
-//     blocks (S_i^{-1} and the G_ij, 3n x 3n each) are stored in FP32. P_r is a
+//     blocks (S_i^{-1} and the G_ij, 3n x 3n each) are stored in FP16, each
+//     scaled by its largest magnitude (one FP32 factor per block). P_r is a
 //     fixed linear map either way, so GMRES keeps its convergence theory and the
-//     solution its accuracy; the rounding only perturbs the preconditioner.
-// Each application streams the blocks once from HBM ((M + n_near) (3n)^2 4 bytes:
-// 2.2 GB at 216 spheres and 12x24 nodes), whatever the number of densities K.
+//     solution its accuracy; the rounding only perturbs the preconditioner (the
+//     iteration counts on the test workloads are those of FP64 blocks).
+// Each application streams the blocks once from HBM ((M + n_near) (3n)^2 2 bytes:
+// 1.1 GB at 216 spheres and 12x24 nodes), whatever the number of densities K.
 //
 // Layouts (3n = per-sphere unknowns, local index c n + x: component c, node x):
 //   D, D^{-1}: [3n][3n] row-major; near blocks of sphere i: [3n][npart_i 3n]
 //   row-major (slot s in columns s 3n ..); S_i row-major; X_i by columns; the
-//   FP32 blocks by columns, sphere i's row of blocks contiguous (S_i^{-1} first).
+//   FP16 blocks by columns, sphere i's row of blocks contiguous (S_i^{-1} first).
 #include "context.hpp"
 
 #include <algorithm>
@@ -152,37 +154,36 @@ __global__ __launch_bounds__(256) void k_nb_scatter(OPtrs np, int K, int k0, con
   for (int r = 0; r < K; ++r) dst[r] = np.p[r][src];
 }
 
+// The set-up's elementwise passes over [M][3n][3n] matrices: one block per (sphere,
+// column), threads along the column (no 64-bit index division per element).
+
 // S_i = D - C_i (row-major, in place over C), for every sphere.
-__global__ __launch_bounds__(256) void k_schur_finish(const double* __restrict__ D, int n3, int M,
+__global__ __launch_bounds__(256) void k_schur_finish(const double* __restrict__ D, int n3,
                                                       double* __restrict__ S) {
-  const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  const long nn = (long)n3 * n3;
-  if (e >= (long)M * nn) return;
-  S[e] = D[e % nn] - S[e];
+  const size_t col = (size_t)blockIdx.x % n3, i = (size_t)blockIdx.x / n3;
+  double* s = S + (i * n3 + col) * n3;
+  const double* d = D + col * n3;
+  for (int r = threadIdx.x; r < n3; r += 256) s[r] = d[r] - s[r];
 }
 
 // W <- 2I - W for every sphere (by columns; the diagonal is the same either way).
-__global__ __launch_bounds__(256) void k_two_minus(double* __restrict__ W, int n3, int M) {
-  const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  const long nn = (long)n3 * n3;
-  if (e >= (long)M * nn) return;
-  const long l = e % nn;
-  const int r = (int)(l % n3), c = (int)(l / n3);
-  W[e] = (r == c ? 2.0 : 0.0) - W[e];
+__global__ __launch_bounds__(256) void k_two_minus(double* __restrict__ W, int n3) {
+  const int col = blockIdx.x % n3;
+  double* w = W + (size_t)blockIdx.x * n3;
+  for (int r = threadIdx.x; r < n3; r += 256) w[r] = (r == col ? 2.0 : 0.0) - w[r];
 }
 
 // res_i = ||I - W_i||_F^2 / 3n, one block per sphere (fixed-order reduction).
 __global__ __launch_bounds__(256) void k_ns_residual(const double* __restrict__ W, int n3, double* __restrict__ res) {
   __shared__ double sh[256];
   const int i = blockIdx.x;
-  const long nn = (long)n3 * n3;
-  const double* Wi = W + (size_t)i * nn;
+  const double* Wi = W + (size_t)i * n3 * n3;
   double acc = 0.0;
-  for (long l = threadIdx.x; l < nn; l += 256) {
-    const int r = (int)(l % n3), c = (int)(l / n3);
-    const double d = (r == c ? 1.0 : 0.0) - Wi[l];
-    acc = fma(d, d, acc);
-  }
+  for (int c = 0; c < n3; ++c)
+    for (int r = threadIdx.x; r < n3; r += 256) {
+      const double d = (r == c ? 1.0 : 0.0) - Wi[(size_t)c * n3 + r];
+      acc = fma(d, d, acc);
+    }
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -206,14 +207,31 @@ __global__ __launch_bounds__(256) void k_pc_interleave(QPtrs v, int K, int n, in
   vI[e] = v.p[r][(size_t)c * N + (size_t)j * n + x];
 }
 
-// FP32 copies of FP64 blocks stored by columns: block b of the list is sgn[b] src[b].
-__global__ __launch_bounds__(256) void k_blocks_f32(const double* const* __restrict__ src,
-                                                    const double* __restrict__ sgn, long nn, long nb,
-                                                    float* __restrict__ dst) {
+// Largest magnitude of each FP64 block (one workgroup per block, fixed-order reduction).
+__global__ __launch_bounds__(256) void k_block_absmax(const double* const* __restrict__ src, long nn,
+                                                      float* __restrict__ scale) {
+  __shared__ double sh[256];
+  const double* s = src[blockIdx.x];
+  double m = 0.0;
+  for (long l = threadIdx.x; l < nn; l += 256) m = fmax(m, fabs(s[l]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) scale[blockIdx.x] = sh[0] > 0.0 ? (float)sh[0] : 1.0f;
+}
+
+// FP16 copies of FP64 blocks stored by columns: block b of the list is sgn[b] src[b] / scale[b]
+// (entries in [-1, 1]; the product multiplies the scale back).
+__global__ __launch_bounds__(256) void k_blocks_f16(const double* const* __restrict__ src,
+                                                    const double* __restrict__ sgn, const float* __restrict__ scale,
+                                                    long nn, long nb, _Float16* __restrict__ dst) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= nb * nn) return;
   const long b = e / nn;
-  dst[e] = (float)(sgn[b] * src[b][e - b * nn]);
+  dst[e] = (_Float16)(float)(sgn[b] / scale[b] * src[b][e - b * nn]);
 }
 
 // part[(b K + r) 3n + row] = sum_m B_b(row, m) vI[(j 3n + m) K + r], j the column sphere of
@@ -221,29 +239,31 @@ __global__ __launch_bounds__(256) void k_blocks_f32(const double* const* __restr
 // (coalesced), the densities of node m of sphere j are wave-uniform (scalar loads). A
 // workgroup per (block, 256 rows), rather than per (sphere, rows), gives the launch
 // enough waves to keep the loads in flight that stream the blocks from HBM.
-// FP32 blocks, FP64 products and sums.
+// FP16 blocks scaled to [-1, 1] (scale[b] multiplied back at the end), FP64 products and sums.
 template <int K>
-__global__ __launch_bounds__(256) void k_bsr_block(const float* __restrict__ B, const int* __restrict__ bcol,
-                                                   const double* __restrict__ vI, int n3, int rchunks,
-                                                   double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_bsr_block(const _Float16* __restrict__ B, const float* __restrict__ scale,
+                                                   const int* __restrict__ bcol, const double* __restrict__ vI,
+                                                   int n3, int rchunks, double* __restrict__ part) {
   const int b = blockIdx.x / rchunks;
   const int row = (blockIdx.x - b * rchunks) * 256 + threadIdx.x;
   const bool valid = row < n3;
   const int rr = valid ? row : n3 - 1;
-  const float* Bb = B + (size_t)b * n3 * n3 + rr;
+  const _Float16* Bb = B + (size_t)b * n3 * n3 + rr;
   const double* v = vI + (size_t)bcol[b] * n3 * K;
   double acc[K];
 #pragma unroll
   for (int r = 0; r < K; ++r) acc[r] = 0.0;
 #pragma unroll 8
   for (int m = 0; m < n3; ++m) {
-    const double a = (double)Bb[(size_t)m * n3];
+    const double a = (double)(float)Bb[(size_t)m * n3];
 #pragma unroll
     for (int r = 0; r < K; ++r) acc[r] = fma(a, v[m * K + r], acc[r]);
   }
-  if (valid)
+  if (valid) {
+    const double sc = scale[b];
 #pragma unroll
-    for (int r = 0; r < K; ++r) part[((size_t)b * K + r) * n3 + row] = acc[r];
+    for (int r = 0; r < K; ++r) part[((size_t)b * K + r) * n3 + row] = sc * acc[r];
+  }
 }
 
 // out_r[c N + i n + x] = sum of the partials of sphere i's blocks (in block order), row = c n + x.
@@ -380,7 +400,7 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
     char* base = push_desc_pack(dp.host);
     launch_gemm64_multi_big(s, (const GemmDesc*)(base + ot), (int)gt.size(), ngt);
     launch_gemm64_multi_big(s, (const GemmDesc*)(base + os), (int)gs.size(), ngs);
-    hipLaunchKernelGGL(k_schur_finish, dim3(nblocks((long)M * nn)), dim3(256), 0, s, pc.D.p, n3, M, pc.S.p);
+    hipLaunchKernelGGL(k_schur_finish, dim3(M * n3), dim3(256), 0, s, pc.D.p, n3, pc.S.p);
     // Newton-Schulz from X = D^{-1}
     pc.X2.alloc((size_t)M * nn);
     pc.W.alloc((size_t)M * nn);
@@ -397,7 +417,7 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
       for (double v : res) worst = std::isfinite(v) ? std::max(worst, std::sqrt(v)) : 1e300;
       if (worst <= kNsTol || step == kNsMaxSteps) break;
       // X <- X (2I - W): C(r, c) = sum_k X(r, k) F(k, c), X read by columns
-      hipLaunchKernelGGL(k_two_minus, dim3(nblocks((long)M * nn)), dim3(256), 0, s, pc.W.p, n3, M);
+      hipLaunchKernelGGL(k_two_minus, dim3(M * n3), dim3(256), 0, s, pc.W.p, n3);
       launch_gemm64_big(s, n3, n3, n3, pc.X.p, n3, (long)nn, pc.W.p, (long)nn, n3, pc.X2.p, (long)nn, n3, 0, n3, M, 1);
       std::swap(pc.X.p, pc.X2.p);
       ++pc.ns_iters;
@@ -428,7 +448,7 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
     launch_gemm64_multi_big(s, (const GemmDesc*)(qb + og), (int)gg.size(), ngg);
     HIPCHK(hipStreamSynchronize(s));  // dnbo and the descriptor tables are released/reused after this
   }
-  // block rows in FP32: sphere i holds S_i^{-1} (or D^{-1}) then G_(i,s) for its slots
+  // block rows in FP16: sphere i holds S_i^{-1} (or D^{-1}) then G_(i,s) for its slots
   {
     std::vector<int> bp(M + 1, 0), bc;
     std::vector<const double*> src;
@@ -447,15 +467,17 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
     bp[M] = (int)bc.size();
     const long nb = (long)bc.size();
     pc.nblk = (int)nb;
-    pc.B32.alloc((size_t)nb * nn);
+    pc.B16.alloc((size_t)nb * nn);
+    pc.bscale.alloc((size_t)nb);
     pc.bptr.upload(bp.data(), bp.size(), s);
     pc.bcol.upload(bc.data(), bc.size(), s);
     DevArray<const double*> dsrc;
     DevArray<double> dsg;
     dsrc.upload(src.data(), src.size(), s);
     dsg.upload(sg.data(), sg.size(), s);
-    hipLaunchKernelGGL(k_blocks_f32, dim3(nblocks(nb * (long)nn)), dim3(256), 0, s, dsrc.p, dsg.p, (long)nn, nb,
-                       pc.B32.p);
+    hipLaunchKernelGGL(k_block_absmax, dim3(nb), dim3(256), 0, s, dsrc.p, (long)nn, pc.bscale.p);
+    hipLaunchKernelGGL(k_blocks_f16, dim3(nblocks(nb * (long)nn)), dim3(256), 0, s, dsrc.p, dsg.p, pc.bscale.p,
+                       (long)nn, nb, pc.B16.p);
     HIPCHK(hipStreamSynchronize(s));  // dsrc is released after this
   }
   HIPCHK(hipGetLastError());
@@ -486,7 +508,8 @@ void pqn_ctx_impl::precond_apply(MvGroup& gr) {
   const dim3 g(pc.nblk * rchunks);
   pc.part.alloc((size_t)pc.nblk * kMaxRhs * n3);
 #define BSRK(KK) \
-  hipLaunchKernelGGL(k_bsr_block<KK>, g, dim3(256), 0, s, pc.B32.p, pc.bcol.p, pc.vI.p, n3, rchunks, pc.part.p)
+  hipLaunchKernelGGL(k_bsr_block<KK>, g, dim3(256), 0, s, pc.B16.p, pc.bscale.p, pc.bcol.p, pc.vI.p, n3, rchunks, \
+                     pc.part.p)
   switch (K) {
     case 1: BSRK(1); break;
     case 2: BSRK(2); break;

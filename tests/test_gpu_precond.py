@@ -57,16 +57,19 @@ def test_preconditioned_mobility_matches_oracle(tiny_cases, prec, tol):
     assert rel(U[:, :3], Uo[:, :3]) < tol and rel(U[:, 3:], Uo[:, 3:]) < tol
 
 
-def test_lone_near_pair_is_solved_in_one_iteration():
+def test_lone_near_pair_is_solved_in_a_few_iterations():
     """Two spheres that are each other's only near partner: P is the inverse of the operator
-    (Schur complement), so GMRES ends after one iteration."""
+    (Schur complement) up to the FP16 rounding of its blocks (~1e-3), so GMRES reaches 1e-10
+    in about three iterations (plain GMRES: about 25)."""
     c = np.array([[0.0, 0.0, 0.0], [2.04, 0.2, -0.1]])
     rhs = np.random.default_rng(5).standard_normal((3, 2 * 128))
+    with binding.Context(c, None, 8, 16, gmres_tol=1e-10) as plain:
+        _, s0 = plain.bie_solve(rhs)
     with binding.Context(c, None, 8, 16, gmres_tol=1e-10, precond='eager') as ctx:
         q, st = ctx.bie_solve(rhs)
         y = ctx.bie_apply(q)
-    say('lone pair its', st['gmres_iters'])
-    assert st['gmres_iters'] <= 2
+    say('lone pair its', st['gmres_iters'], 'plain', s0['gmres_iters'])
+    assert st['gmres_iters'] <= 4 < s0['gmres_iters']
     assert rel(y, rhs) < 1e-9
 
 
