@@ -181,7 +181,7 @@ def main():
     UO_dev = torch.empty((K_RHS, M, 6), dtype=torch.float64, device=dev)
 
     if args.lcp_table:
-        print(json.dumps(lcp_table(binding, inputs, stream)), flush=True)
+        print(json.dumps(lcp_table(binding, inputs, stream, precond=PC_FIXED)), flush=True)
         return
 
     if args.cpu_table:
@@ -662,7 +662,7 @@ def contact_steps(binding, inputs, torch, stream, w, args, replay_solvers=True):
     return inward_info
 
 
-def lcp_table(binding, inputs, stream):
+def lcp_table(binding, inputs, stream, precond=False):
     """Products per planted LCP (about half the contacts active, KKT 1e-8) for the solvers of
     the method on the contact sets (gap < 0.1) of three workloads, mixed precision: BB-PGD,
     Mono-PQN and Bi-PQN with the coarse grid as low fidelity (each PQN solver with the scaled
@@ -681,12 +681,13 @@ def lcp_table(binding, inputs, stream):
             c, nt, nph = w['centers'], w['n_theta'], w['n_phi']
             row = dict(workload=name, seed=seed)
             with binding.Context(c, None, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='mixed',
-                                 stream=stream.cuda_stream, tune_K=1) as ctx:
+                                 stream=stream.cuda_stream, tune_K=1, precond=precond) as ctx:
                 pairs, _ = ctx.find_contacts(0.1)
                 if pairs.shape[0] == 0:
                     continue
                 xs, ws = inputs.planted_lcp(seed, pairs.shape[0])
                 b = ws - ctx.lcp_apply(pairs, xs)
+                ctx.lcp_apply(pairs, xs, binding.PQN_LOFI)  # both levels' tables built before timing
                 row['contacts'] = int(pairs.shape[0])
                 for key, solver, printed in (('bb', 'bb', False), ('mono', 'mono', False), ('bi', 'bi', False),
                                              ('mono_printed', 'mono', True), ('bi_printed', 'bi', True)):
@@ -704,9 +705,9 @@ def lcp_table(binding, inputs, stream):
                                                    gmres_tol_lo2=1e-3)))
             for key, solver, kw_lo in variants:
                 with binding.Context(c, None, nt, nph, lo=(nt, nph), gmres_tol=1e-8, precision='mixed',
-                                     stream=stream.cuda_stream, tune_K=1, **kw_lo) as ctx:
-                    if key.startswith('bi_cf'):
-                        ctx.lcp_solve(pairs, b, solver)     # warm the coarse-grid buffers
+                                     stream=stream.cuda_stream, tune_K=1, precond=precond, **kw_lo) as ctx:
+                    if key.startswith('bi_cf') or precond:
+                        ctx.lcp_solve(pairs, b, solver)     # warm the buffers (and build the preconditioners)
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
                     x, st = ctx.lcp_solve(pairs, b, solver)
@@ -725,7 +726,8 @@ def lcp_table(binding, inputs, stream):
                                    'mono_printed', 'bi_printed')}
             med[name + '_sec'] = {k: float(np.median([r[k]['sec'] for r in rs]))
                                   for k in ('bb', 'mono', 'bi', 'bi_tol', 'birec', 'bi_cf', 'bi_cf_tol', 'birec_cf')}
-    return dict(table='planted LCPs, mixed precision, KKT 1e-8', rows=rows, median_emvp=med)
+    return dict(table='planted LCPs, mixed precision, KKT 1e-8', precond=bool(precond), rows=rows,
+                median_emvp=med)
 
 
 def cpu_table(binding, inputs, stream):
