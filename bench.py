@@ -494,6 +494,22 @@ def main():
             torch.cuda.synchronize()
             tb64 = (time.perf_counter() - t0) / reps
         err_b = float(max(np.abs(a - b_).max() / np.abs(b_).max() for a, b_ in zip(Ubm, Ub64)))
+        # every suspension with its own preconditioner (built in the warm-up product; eager
+        # lockstep iterations, the preconditioners applied in segmented launches)
+        bpc = None
+        if PC:
+            with binding.BatchContext(inst, precond='eager', **kw) as bc:
+                _, bs0 = bc.mobility_apply(FTb)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    Ubp, bsp = bc.mobility_apply(FTb)
+                torch.cuda.synchronize()
+                tbp = (time.perf_counter() - t0) / reps
+            bpc = dict(batched_sec=round(tbp, 4), mvps_batched=round(len(inst) / tbp, 2),
+                       lockstep_iterations=bsp['n_far'], setup_ms=round(bs0['t_precond_ms'], 1),
+                       rel_diff_vs_plain=float(max(np.abs(a - b_).max() / np.abs(b_).max()
+                                                   for a, b_ in zip(Ubp, Ubm))))
         singles = [binding.Context(ci, None, nti, npi, **kw) for ci, nti, npi in inst]
         for ctx_b, F in zip(singles, FTb):
             ctx_b.mobility_apply(F)
@@ -511,7 +527,8 @@ def main():
                           mvps_batched_eager=round(len(inst) / tb_eager, 2),
                           mvps_batched_fp64=round(len(inst) / tb64, 2), mixed_rel_err_vs_fp64=err_b,
                           one_by_one_sec=round(ts, 4), mvps_one_by_one=round(len(inst) / ts, 2),
-                          speedup=round(ts / tb, 3), lockstep_iterations=bst['n_far'], far_layout=batch_shape)
+                          speedup=round(ts / tb, 3), lockstep_iterations=bst['n_far'], far_layout=batch_shape,
+                          precond=bpc)
         log('batch', batch_info)
 
     m6 = res['mixed6']

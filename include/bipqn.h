@@ -129,7 +129,9 @@ typedef struct {
                                configuration and fidelity: 1 = built when a configuration is solved
                                a second time (its first solve is plain), 2 = built at the first
                                solve; 0 = plain GMRES. Device memory about (2 n_near + 4 M) (3n)^2
-                               doubles. Not for batch contexts [0] */
+                               doubles. In a batch context each suspension has its own (built at
+                               the same points; its GMRES iterations then run eagerly, not from
+                               captured graphs) [0] */
 } pqn_config_desc;
 
 typedef struct {

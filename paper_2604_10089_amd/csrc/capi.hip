@@ -150,8 +150,6 @@ pqn_status pqn_batch_create(int32_t n_inst, const pqn_config_desc* descs, const 
       fill_defaults(c);
       const std::string bad = check_desc(c);
       if (!bad.empty()) return fail(PQN_ERR_INVALID, "instance " + std::to_string(b) + ": " + bad);
-      if (c.precond) return fail(PQN_ERR_INVALID, "instance " + std::to_string(b) + ": precond is not available "
-                                                 "for batch contexts");
       if (!centers[b]) return fail(PQN_ERR_INVALID, "pqn_batch_create: NULL centres");
       if (c.precision != c0.precision || c.gmres_restart != c0.gmres_restart || c.device != c0.device ||
           c.targets_per_thread != c0.targets_per_thread || c.far_split != c0.far_split ||
@@ -204,6 +202,10 @@ static pqn_status batch_apply_common(pqn_ctx* ctx, const double* const* FT, doub
   ctx->pc_fallback = 0;
   ctx->pc_applies = 0;
   ctx->n_far = 0;
+  for (auto& ch : ctx->children) {
+    ch->pc_setup_ms = 0.0;
+    ch->pc_fallback = 0;
+  }
   std::vector<SysRef> sys;
   for (int b = 0; b < nb; ++b) {
     pqn_ctx_impl& c = *ctx->children[b];
@@ -232,6 +234,10 @@ static pqn_status batch_apply_common(pqn_ctx* ctx, const double* const* FT, doub
   HIPCHK(hipStreamSynchronize(ctx->stream));
   st.t_far_ms = ctx->end_far_timing();
   stage_stats(*ctx, st);
+  for (auto& ch : ctx->children) {  // the suspensions' preconditioner set-ups
+    st.t_precond_ms += ch->pc_setup_ms;
+    st.precond_fallback += ch->pc_fallback;
+  }
   st.matvecs = ctx->n_matvec;
   st.n_far = ctx->n_far;
   st.graph_launches = ctx->n_graph_launch;

@@ -770,7 +770,7 @@ struct GmState {
 
 void pqn_ctx_impl::gmres_lockstep(std::vector<SysRef>& sys, int precision) {
   bool graph = is_batch && cfg.use_graphs && !cfg.profile && sys.size() > 1 && precision == cfg.precision;
-  for (SysRef& r : sys) graph = graph && !r.x0 && !r.res_out;
+  for (SysRef& r : sys) graph = graph && !r.x0 && !r.res_out && !r.c->cfg.precond;
   if (graph)
     gmres_batch_graph(sys, precision);
   else
@@ -1162,7 +1162,7 @@ void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision)
             SysBuf& b = sys[i].lv->sb(sys[i].slot);
             add_to_groups(pg, sys[i].c, sys[i].lv, sys[i].slot, b.V.p + (size_t)st[i].k * len_of(i), b.z.p);
           }
-        for (MvGroup& gr : pg) gr.c->precond_apply(gr);
+        precond_apply_groups(pg);
       }
       std::vector<MvGroup> groups = build_groups(act, false);
       matvec_groups(groups, precision);

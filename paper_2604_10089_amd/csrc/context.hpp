@@ -415,6 +415,7 @@ struct pqn_ctx_impl {
   // be in_r: every read of the input precedes the write of the output)
   void precond_setup(Level& lv);
   void precond_apply(MvGroup& gr);
+  void precond_apply_groups(std::vector<MvGroup>& groups);
   // near tiles only: near_part of the group's slots from its densities (with their
   // coefficient and upsampling GEMMs), on the main stream
   void near_stage(MvGroup& gr);

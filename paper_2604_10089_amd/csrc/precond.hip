@@ -45,6 +45,9 @@
 #include "context.hpp"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace bipqn {
 
@@ -118,6 +121,30 @@ void invert_gauss_jordan(std::vector<double>& A, int n) {
     for (int c = 0; c < n; ++c) tmp[perm[c]] = ar[c];
     std::copy(tmp.begin(), tmp.end(), ar);
   }
+}
+
+// D, D^{-1} and D^{-1} by columns of one grid, built once per process (the same for
+// every context and suspension on that grid; batch contexts have many).
+struct SphereBlock {
+  std::vector<double> D, Dinv, DinvT;
+};
+
+static const SphereBlock& sphere_block_cached(const SphereTables& t) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, double>, std::unique_ptr<SphereBlock>> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto key = std::make_tuple(t.n_theta, t.n_phi, t.radius);
+  auto it = cache.find(key);
+  if (it != cache.end()) return *it->second;
+  auto sb = std::make_unique<SphereBlock>();
+  const int n3 = 3 * t.n;
+  single_sphere_block(t, sb->D);
+  sb->Dinv = sb->D;
+  invert_gauss_jordan(sb->Dinv, n3);
+  sb->DinvT.resize((size_t)n3 * n3);
+  for (int r = 0; r < n3; ++r)
+    for (int c = 0; c < n3; ++c) sb->DinvT[(size_t)c * n3 + r] = sb->Dinv[(size_t)r * n3 + c];
+  return *(cache[key] = std::move(sb));
 }
 
 // ------------------------------------------------------------------ kernels
@@ -241,11 +268,11 @@ __global__ __launch_bounds__(256) void k_blocks_f16(const double* const* __restr
 // enough waves to keep the loads in flight that stream the blocks from HBM.
 // FP16 blocks scaled to [-1, 1] (scale[b] multiplied back at the end), FP64 products and sums.
 template <int K>
-__global__ __launch_bounds__(256) void k_bsr_block(const _Float16* __restrict__ B, const float* __restrict__ scale,
-                                                   const int* __restrict__ bcol, const double* __restrict__ vI,
-                                                   int n3, int rchunks, double* __restrict__ part) {
-  const int b = blockIdx.x / rchunks;
-  const int row = (blockIdx.x - b * rchunks) * 256 + threadIdx.x;
+__device__ __forceinline__ void bsr_block_body(const _Float16* __restrict__ B, const float* __restrict__ scale,
+                                               const int* __restrict__ bcol, const double* __restrict__ vI,
+                                               int n3, int rchunks, int wg, double* __restrict__ part) {
+  const int b = wg / rchunks;
+  const int row = (wg - b * rchunks) * 256 + threadIdx.x;
   const bool valid = row < n3;
   const int rr = valid ? row : n3 - 1;
   const _Float16* Bb = B + (size_t)b * n3 * n3 + rr;
@@ -264,6 +291,82 @@ __global__ __launch_bounds__(256) void k_bsr_block(const _Float16* __restrict__ 
 #pragma unroll
     for (int r = 0; r < K; ++r) part[((size_t)b * K + r) * n3 + row] = sc * acc[r];
   }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_bsr_block(const _Float16* __restrict__ B, const float* __restrict__ scale,
+                                                   const int* __restrict__ bcol, const double* __restrict__ vI,
+                                                   int n3, int rchunks, double* __restrict__ part) {
+  bsr_block_body<K>(B, scale, bcol, vI, n3, rchunks, blockIdx.x, part);
+}
+
+// Many suspensions in one launch (one density each): segment descriptors, workgroups
+// [start, ...) of a segment for the block products, elements [estart, estart + M 3n)
+// for the interleave and the sum.
+struct PcDesc {
+  const _Float16* B;
+  const float* scale;
+  const int* bcol;
+  const int* bptr;
+  const double* in;
+  double* out;
+  double* vI;
+  double* part;
+  int n, N, M, rchunks, start;
+  long estart;
+};
+
+__device__ __forceinline__ int pc_seg_blocks(const PcDesc* __restrict__ d, int nd, int wg) {
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].start <= wg)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int pc_seg_elems(const PcDesc* __restrict__ d, int nd, long e) {
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].estart <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_pc_interleave_multi(const PcDesc* __restrict__ d, int nd, long total) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const PcDesc D = d[pc_seg_elems(d, nd, e)];
+  const long l = e - D.estart;
+  const int n3 = 3 * D.n;
+  const int j = (int)(l / n3), m = (int)(l - (long)j * n3);
+  const int c = m / D.n, x = m - c * D.n;
+  D.vI[l] = D.in[(size_t)c * D.N + (size_t)j * D.n + x];
+}
+
+__global__ __launch_bounds__(256) void k_bsr_block_multi(const PcDesc* __restrict__ d, int nd) {
+  const PcDesc D = d[pc_seg_blocks(d, nd, blockIdx.x)];
+  bsr_block_body<1>(D.B, D.scale, D.bcol, D.vI, 3 * D.n, D.rchunks, blockIdx.x - D.start, D.part);
+}
+
+__global__ __launch_bounds__(256) void k_bsr_sum_multi(const PcDesc* __restrict__ d, int nd, long total) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const PcDesc D = d[pc_seg_elems(d, nd, e)];
+  const long l = e - D.estart;
+  const int n3 = 3 * D.n;
+  const int i = (int)(l / n3), row = (int)(l - (long)i * n3);
+  double v = 0.0;
+  for (int b = D.bptr[i]; b < D.bptr[i + 1]; ++b) v += D.part[(size_t)b * n3 + row];
+  const int c = row / D.n, x = row - c * D.n;
+  D.out[(size_t)c * D.N + (size_t)i * D.n + x] = v;
 }
 
 // out_r[c N + i n + x] = sum of the partials of sphere i's blocks (in block order), row = c n + x.
@@ -321,16 +424,10 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
   const int n = lv.n, n3 = 3 * n, M = lv.M, N = lv.N;
   const size_t nn = (size_t)n3 * n3;
   if (!pc.has_d) {
-    std::vector<double> D;
-    single_sphere_block(lv.tab, D);
-    std::vector<double> Di = D;
-    invert_gauss_jordan(Di, n3);
-    std::vector<double> DiT(nn);
-    for (int r = 0; r < n3; ++r)
-      for (int c = 0; c < n3; ++c) DiT[(size_t)c * n3 + r] = Di[(size_t)r * n3 + c];
-    pc.D.upload(D.data(), nn, s);
-    pc.Dinv.upload(Di.data(), nn, s);
-    pc.DinvT.upload(DiT.data(), nn, s);
+    const SphereBlock& sb = sphere_block_cached(lv.tab);
+    pc.D.upload(sb.D.data(), nn, s);
+    pc.Dinv.upload(sb.Dinv.data(), nn, s);
+    pc.DinvT.upload(sb.DinvT.data(), nn, s);
     HIPCHK(hipStreamSynchronize(s));
     pc.has_d = true;
   }
@@ -488,6 +585,46 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
 }
 
 // ------------------------------------------------------------ application
+
+// Every group's densities through its own level's preconditioner: one segmented launch
+// per phase when the groups are single densities of different contexts (the suspensions
+// of a batch), else one application per group.
+void pqn_ctx_impl::precond_apply_groups(std::vector<MvGroup>& groups) {
+  bool multi = groups.size() > 1;
+  for (MvGroup& gr : groups) multi = multi && gr.K == 1;
+  if (!multi) {
+    for (MvGroup& gr : groups) gr.c->precond_apply(gr);
+    return;
+  }
+  hipStream_t s = stream;
+  std::vector<PcDesc> pd;
+  int wg = 0;
+  long el = 0;
+  for (MvGroup& gr : groups) {
+    pqn_ctx_impl& c = *gr.c;
+    Level& lv = *gr.lv;
+    Precond& pc = lv.pc;
+    if (pc.epoch != c.config_epoch) throw Error(PQN_ERR_STATE, "internal: preconditioner not set up");
+    const int n3 = 3 * lv.n;
+    pc.vI.alloc((size_t)lv.M * n3 * kMaxRhs);
+    pc.part.alloc((size_t)pc.nblk * kMaxRhs * n3);
+    const int rchunks = (n3 + 255) / 256;
+    pd.push_back(PcDesc{pc.B16.p, pc.bscale.p, pc.bcol.p, pc.bptr.p, gr.in[0], gr.out[0], pc.vI.p, pc.part.p, lv.n,
+                        lv.N, lv.M, rchunks, wg, el});
+    wg += pc.nblk * rchunks;
+    el += (long)lv.M * n3;
+  }
+  DescPack dp;
+  const size_t od = dp.add(pd);
+  const PcDesc* dd = (const PcDesc*)(push_desc_pack(dp.host) + od);
+  const int nd = (int)pd.size();
+  stage_begin(kStagePrecond);
+  hipLaunchKernelGGL(k_pc_interleave_multi, dim3(nblocks(el)), dim3(256), 0, s, dd, nd, el);
+  hipLaunchKernelGGL(k_bsr_block_multi, dim3(wg), dim3(256), 0, s, dd, nd);
+  hipLaunchKernelGGL(k_bsr_sum_multi, dim3(nblocks(el)), dim3(256), 0, s, dd, nd, el);
+  stage_end(kStagePrecond);
+  ++pc_applies;
+}
 
 void pqn_ctx_impl::precond_apply(MvGroup& gr) {
   Level& lv = *gr.lv;

@@ -150,11 +150,28 @@ def test_preconditioned_lcp_and_step_equal_plain(tiny_cases):
     assert np.abs(res[True][1] - res[False][1]).max() < 1e-10
 
 
-def test_batch_contexts_reject_precond():
-    inst = inputs.batched_suspensions(0, n_inst=2)
-    with pytest.raises(binding.PqnError) as e:
-        binding.BatchContext(inst, precond='eager')
-    assert e.value.status == -1  # PQN_ERR_INVALID
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
+def test_batch_preconditioned_equals_plain(prec, tol):
+    """Uneven suspensions in one batch context, each with its own preconditioner (segmented
+    launches): the plain batch's velocities, in fewer lockstep iterations; per-instance
+    statistics and a second product without a new set-up."""
+    inst = inputs.batched_suspensions(0, n_inst=8)
+    FTs = [inputs.random_forces(600 + b, c.shape[0]) for b, (c, _, _) in enumerate(inst)]
+    with binding.BatchContext(inst, gmres_tol=1e-10, precision=prec) as bc:
+        U0, s0 = bc.mobility_apply(FTs, per_instance=True)
+    with binding.BatchContext(inst, gmres_tol=1e-10, precision=prec, precond='eager') as bc:
+        U1, s1 = bc.mobility_apply(FTs, per_instance=True)
+        U2, s2 = bc.mobility_apply(FTs, per_instance=True)
+    its0 = [p['gmres_iters'] for p in s0['per_instance']]
+    its1 = [p['gmres_iters'] for p in s1['per_instance']]
+    say('batch', prec, 'its plain', its0, 'precond', its1, 'set-up ms', round(s1['t_precond_ms'], 1),
+        round(s2['t_precond_ms'], 1), 'lockstep', s0['n_far'], s1['n_far'])
+    assert s1['converged'] == 1 and s1['precond_fallback'] == 0
+    assert s1['t_precond_ms'] > 0 and s2['t_precond_ms'] == 0
+    assert all(a < 0.7 * b for a, b in zip(its1, its0))
+    for a, b, c in zip(U1, U0, U2):
+        assert rel(a, b) < tol
+        assert np.array_equal(a, c)
 
 
 def test_precond_on_reuse_builds_at_the_second_solve_of_a_configuration(tiny_cases):
