@@ -1019,38 +1019,17 @@ void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision)
     HIPCHK(hipStreamSynchronize(s));
   };
   auto nrm_slot = [&](int i) { return hdev.p + (size_t)i * hs + 2 * (m + 1); };
-  // right preconditioning (config precond): the Arnoldi vectors enter the operator as
-  // z = P V[k] and a cycle ends with x += P (V y). The preconditioner of a level is built
-  // for the current configuration at its first solve (precond = 2) or when the
-  // configuration is solved a second time (precond = 1: a configuration solved once, such
-  // as a time step without contacts, never pays for the set-up); decided once per level.
+  // right preconditioning (config precond; whether this solve applies it was decided in
+  // solve_lockstep): the Arnoldi vectors enter the operator as z = P V[k] and a cycle ends
+  // with x += P (V y)
   std::vector<char> pcs(ns, 0);
   bool any_pc = false;
-  {
-    std::vector<std::pair<Level*, bool>> decided;
-    for (int i = 0; i < ns; ++i) {
-      pqn_ctx_impl& c = *sys[i].c;
-      Level& lv = *sys[i].lv;
-      if (!c.cfg.precond) continue;
-      int use = -1;
-      for (auto& d : decided)
-        if (d.first == &lv) use = d.second;
-      if (use < 0) {
-        bool u = lv.pc.epoch == c.config_epoch;
-        if (!u && (c.cfg.precond == 2 || lv.pc.seen == c.config_epoch)) {
-          c.precond_setup(lv);
-          u = true;
-        } else if (!u) {
-          lv.pc.seen = c.config_epoch;
-        }
-        decided.emplace_back(&lv, u);
-        use = u;
-      }
-      if (use) {
-        lv.sb(sys[i].slot).z.alloc((size_t)len_of(i));
-        pcs[i] = 1;
-        any_pc = true;
-      }
+  for (int i = 0; i < ns; ++i) {
+    Level& lv = *sys[i].lv;
+    if (sys[i].c->cfg.precond && lv.pc.use && lv.pc.epoch == sys[i].c->config_epoch) {
+      lv.sb(sys[i].slot).z.alloc((size_t)len_of(i));
+      pcs[i] = 1;
+      any_pc = true;
     }
   }
   // right-hand side norms
@@ -1335,6 +1314,27 @@ void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision)
 // residual uses the FP64 operator.
 void pqn_ctx_impl::solve_lockstep(std::vector<SysRef>& sys, pqn_mvp_stats* st, std::vector<int>* its_per) {
   const int prec = cfg.precision;
+  // The preconditioner of a level (config precond) is built for the current configuration
+  // at its first solve (precond = 2) or when the configuration is solved a second time
+  // (precond = 1: a configuration solved once, such as a time step without contacts, never
+  // pays for the set-up); decided once per level for this solve, refinement solves included.
+  std::vector<Level*> decided;
+  for (SysRef& r : sys) {
+    pqn_ctx_impl& c = *r.c;
+    Level& lv = *r.lv;
+    if (!c.cfg.precond || std::find(decided.begin(), decided.end(), &lv) != decided.end()) continue;
+    decided.push_back(&lv);
+    lv.pc.use = false;
+    if (lv.pc.epoch != c.config_epoch) {
+      if (c.cfg.precond == 2 || lv.pc.seen == c.config_epoch) {
+        c.precond_setup(lv);
+      } else {
+        lv.pc.seen = c.config_epoch;
+        continue;
+      }
+    }
+    lv.pc.use = true;
+  }
   gmres_lockstep(sys, prec);
   int its = 0;
   for (SysRef& r : sys) its += r.its;

@@ -135,6 +135,7 @@ struct Precond {
   bool has_d = false;
   unsigned long epoch = 0;       // configuration of the tables below (0 = none yet)
   unsigned long seen = 0;        // configuration last solved without them (precond = 1)
+  bool use = false;              // the current solve (solve_lockstep) applies them
   DevArray<double> D, Dinv;      // [3n][3n] row-major
   DevArray<double> DinvT;        // D^{-1} by columns ([3n][3n] row-major of its transpose)
   DevArray<double> NB, TB;       // per sphere [3n][npart_i 3n] row-major, at nbo[i] doubles

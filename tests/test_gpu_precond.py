@@ -198,3 +198,17 @@ def test_precond_on_reuse_builds_at_the_second_solve_of_a_configuration(tiny_cas
     assert rel(U2, U1) < 1e-9
     assert s4['t_precond_ms'] == 0 and s4['precond_applies'] == 0
     assert s5['t_precond_ms'] > 0
+
+
+def test_precond_on_reuse_counts_a_refined_solve_once(tiny_cases):
+    """Mixed precision with an FP64 refinement sweep: the correction solves belong to the same
+    solve, so precond = 1 still builds nothing in a configuration's first product."""
+    _, g, _ = tiny_cases[0]
+    FT = inputs.random_forces(19, g.M)
+    with binding.Context(g.c, None, 8, 16, gmres_tol=1e-9, precision='mixed', refine=1, precond=True) as ctx:
+        _, s1 = ctx.mobility_apply(FT)
+        _, s2 = ctx.mobility_apply(FT)
+    say('refined: sweeps', s1['refine_sweeps'], s2['refine_sweeps'], 'set-up', s1['t_precond_ms'],
+        s2['t_precond_ms'])
+    assert s1['t_precond_ms'] == 0 and s1['precond_applies'] == 0
+    assert s2['t_precond_ms'] > 0 and s2['precond_applies'] > 0
