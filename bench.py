@@ -121,8 +121,8 @@ def main():
                          'WRITE_SIZE) and one six-force-set product on the 216-sphere workload')
     ap.add_argument('--batch-probe', action='store_true',
                     help='short run for rocprofv3 --kernel-trace: only the 32-suspension batch, mixed precision, '
-                         'GMRES iterations from captured graphs (one warm-up product and three timed ones), one '
-                         'JSON line')
+                         'preconditioned (with --no-precond: plain GMRES iterations from captured graphs); one '
+                         'warm-up product and three timed ones, one JSON line')
     ap.add_argument('--contact-probe', action='store_true',
                     help='short run for rocprofv3 --kernel-trace: only the five time steps with active contacts '
                          '(FP64, then the mixed replay), one JSON line')
@@ -196,8 +196,11 @@ def main():
         inst = inputs.batched_suspensions(args.seed)
         FTb = [inputs.random_forces(500 + b, ci.shape[0]) for b, (ci, _, _) in enumerate(inst)]
         kwp = dict(tpt=args.tpt) if args.tpt else {}
+        # preconditioned (eager lockstep iterations), or with --no-precond plain GMRES replayed
+        # from captured graphs
+        kwp.update(dict(precond='eager') if PC else dict(graphs=True))
         with binding.BatchContext(inst, gmres_tol=1e-8, precision='mixed', stream=stream.cuda_stream,
-                                  side_stream=not args.serial, graphs=True, **kwp) as bc:
+                                  side_stream=not args.serial, **kwp) as bc:
             bc.mobility_apply(FTb)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -207,7 +210,7 @@ def main():
             tb = (time.perf_counter() - t0) / 3
         print(json.dumps({'instances': len(inst), 'ms_per_product': round(tb * 1e3, 3),
                           'mvps_batched': round(len(inst) / tb, 2), 'lockstep_iterations': bst['n_far'],
-                          'side_stream': not args.serial}), flush=True)
+                          'side_stream': not args.serial, 'precond': PC}), flush=True)
         return
 
     if args.counters_probe:

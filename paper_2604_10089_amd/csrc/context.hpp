@@ -141,7 +141,7 @@ struct Precond {
   DevArray<double> NB, TB;       // per sphere [3n][npart_i 3n] row-major, at nbo[i] doubles
   std::vector<long> nbo;
   DevArray<double> S, X, X2, W;  // [M][3n][3n]; S row-major, X (= S^{-1}), X2, W by columns
-  DevArray<double> res;          // [M] Newton-Schulz residuals
+  DevArray<double> res;          // Newton-Schulz residuals, partial sums [M][slices]
   DevArray<double> ug;           // kMaxRhs unit densities [3][N] (near-block assembly)
   DevArray<_Float16> B16;        // the preconditioner's blocks in FP16, by columns, row of sphere i
   DevArray<float> bscale;        // each block's largest magnitude (its FP16 copy is divided by it)
@@ -149,6 +149,7 @@ struct Precond {
   DevArray<double> vI;           // input densities interleaved per node [M][3n][K]
   DevArray<double> part;         // per-block partial products [nblk][K][3n]
   int nblk = 0;                  // blocks: M + the ordered near pairs
+  int ld = 0;                    // padded column length of the FP16 blocks (multiple of 64)
   int fallback = 0;              // spheres left on D^{-1} (Newton-Schulz did not converge)
   int ns_iters = 0;              // Newton-Schulz steps of the last set-up
   double setup_ms = 0.0;         // wall time of the last set-up

@@ -41,7 +41,8 @@
 // Layouts (3n = per-sphere unknowns, local index c n + x: component c, node x):
 //   D, D^{-1}: [3n][3n] row-major; near blocks of sphere i: [3n][npart_i 3n]
 //   row-major (slot s in columns s 3n ..); S_i row-major; X_i by columns; the
-//   FP16 blocks by columns, sphere i's row of blocks contiguous (S_i^{-1} first).
+//   FP16 blocks by columns padded to a multiple of 64 rows, sphere i's row of
+//   blocks contiguous (S_i^{-1} first).
 #include "context.hpp"
 
 #include <algorithm>
@@ -200,13 +201,15 @@ __global__ __launch_bounds__(256) void k_two_minus(double* __restrict__ W, int n
   for (int r = threadIdx.x; r < n3; r += 256) w[r] = (r == col ? 2.0 : 0.0) - w[r];
 }
 
-// res_i = ||I - W_i||_F^2 / 3n, one block per sphere (fixed-order reduction).
+// Partial sums of ||I - W_i||_F^2: block (i, g) covers the columns c = g, g + kNsSlices, ...
+// of sphere i; res[i kNsSlices + g] (the host adds the slices in order).
+constexpr int kNsSlices = 32;
 __global__ __launch_bounds__(256) void k_ns_residual(const double* __restrict__ W, int n3, double* __restrict__ res) {
   __shared__ double sh[256];
-  const int i = blockIdx.x;
+  const int i = blockIdx.x / kNsSlices, g = blockIdx.x % kNsSlices;
   const double* Wi = W + (size_t)i * n3 * n3;
   double acc = 0.0;
-  for (int c = 0; c < n3; ++c)
+  for (int c = g; c < n3; c += kNsSlices)
     for (int r = threadIdx.x; r < n3; r += 256) {
       const double d = (r == c ? 1.0 : 0.0) - Wi[(size_t)c * n3 + r];
       acc = fma(d, d, acc);
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(256) void k_ns_residual(const double* __restrict__ 
     if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) res[i] = sh[0] / n3;
+  if (threadIdx.x == 0) res[blockIdx.x] = sh[0];
 }
 
 // vI[(j 3n + m) K + r] = v_r[c N + j n + x], m = c n + x: the K densities of a node
@@ -251,14 +254,18 @@ __global__ __launch_bounds__(256) void k_block_absmax(const double* const* __res
 }
 
 // FP16 copies of FP64 blocks stored by columns: block b of the list is sgn[b] src[b] / scale[b]
-// (entries in [-1, 1]; the product multiplies the scale back).
+// (entries in [-1, 1]; the product multiplies the scale back), each column padded with zeros
+// to ld entries (a multiple of 64: every column starts on a 128-byte line).
 __global__ __launch_bounds__(256) void k_blocks_f16(const double* const* __restrict__ src,
                                                     const double* __restrict__ sgn, const float* __restrict__ scale,
-                                                    long nn, long nb, _Float16* __restrict__ dst) {
+                                                    int n3, int ld, long nb, _Float16* __restrict__ dst) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= nb * nn) return;
-  const long b = e / nn;
-  dst[e] = (_Float16)(float)(sgn[b] / scale[b] * src[b][e - b * nn]);
+  const long per = (long)n3 * ld;
+  if (e >= nb * per) return;
+  const long b = e / per;
+  const long l = e - b * per;
+  const int m = (int)(l / ld), r = (int)(l - (long)m * ld);
+  dst[e] = r < n3 ? (_Float16)(float)(sgn[b] / scale[b] * src[b][(size_t)m * n3 + r]) : (_Float16)0.0f;
 }
 
 // part[(b K + r) 3n + row] = sum_m B_b(row, m) vI[(j 3n + m) K + r], j the column sphere of
@@ -270,19 +277,19 @@ __global__ __launch_bounds__(256) void k_blocks_f16(const double* const* __restr
 template <int K>
 __device__ __forceinline__ void bsr_block_body(const _Float16* __restrict__ B, const float* __restrict__ scale,
                                                const int* __restrict__ bcol, const double* __restrict__ vI,
-                                               int n3, int rchunks, int wg, double* __restrict__ part) {
+                                               int n3, int ld, int rchunks, int wg, double* __restrict__ part) {
   const int b = wg / rchunks;
   const int row = (wg - b * rchunks) * 256 + threadIdx.x;
   const bool valid = row < n3;
   const int rr = valid ? row : n3 - 1;
-  const _Float16* Bb = B + (size_t)b * n3 * n3 + rr;
+  const _Float16* Bb = B + (size_t)b * n3 * ld + rr;
   const double* v = vI + (size_t)bcol[b] * n3 * K;
   double acc[K];
 #pragma unroll
   for (int r = 0; r < K; ++r) acc[r] = 0.0;
 #pragma unroll 8
   for (int m = 0; m < n3; ++m) {
-    const double a = (double)(float)Bb[(size_t)m * n3];
+    const double a = (double)(float)Bb[(size_t)m * ld];
 #pragma unroll
     for (int r = 0; r < K; ++r) acc[r] = fma(a, v[m * K + r], acc[r]);
   }
@@ -296,8 +303,8 @@ __device__ __forceinline__ void bsr_block_body(const _Float16* __restrict__ B, c
 template <int K>
 __global__ __launch_bounds__(256) void k_bsr_block(const _Float16* __restrict__ B, const float* __restrict__ scale,
                                                    const int* __restrict__ bcol, const double* __restrict__ vI,
-                                                   int n3, int rchunks, double* __restrict__ part) {
-  bsr_block_body<K>(B, scale, bcol, vI, n3, rchunks, blockIdx.x, part);
+                                                   int n3, int ld, int rchunks, double* __restrict__ part) {
+  bsr_block_body<K>(B, scale, bcol, vI, n3, ld, rchunks, blockIdx.x, part);
 }
 
 // Many suspensions in one launch (one density each): segment descriptors, workgroups
@@ -312,7 +319,7 @@ struct PcDesc {
   double* out;
   double* vI;
   double* part;
-  int n, N, M, rchunks, start;
+  int n, N, M, ld, rchunks, start;
   long estart;
 };
 
@@ -353,7 +360,7 @@ __global__ __launch_bounds__(256) void k_pc_interleave_multi(const PcDesc* __res
 
 __global__ __launch_bounds__(256) void k_bsr_block_multi(const PcDesc* __restrict__ d, int nd) {
   const PcDesc D = d[pc_seg_blocks(d, nd, blockIdx.x)];
-  bsr_block_body<1>(D.B, D.scale, D.bcol, D.vI, 3 * D.n, D.rchunks, blockIdx.x - D.start, D.part);
+  bsr_block_body<1>(D.B, D.scale, D.bcol, D.vI, 3 * D.n, D.ld, D.rchunks, blockIdx.x - D.start, D.part);
 }
 
 __global__ __launch_bounds__(256) void k_bsr_sum_multi(const PcDesc* __restrict__ d, int nd, long total) {
@@ -432,7 +439,7 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
     pc.has_d = true;
   }
   pc.X.alloc((size_t)M * nn);
-  pc.res.alloc((size_t)M);
+  pc.res.alloc((size_t)M * kNsSlices);
   long total = 0;
   pc.nbo.assign(M, 0);
   for (int i = 0; i < M; ++i) {
@@ -503,13 +510,18 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
     pc.W.alloc((size_t)M * nn);
     for (int i = 0; i < M; ++i)
       HIPCHK(hipMemcpyAsync(pc.X.p + (size_t)i * nn, pc.DinvT.p, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
-    std::vector<double> res(M);
+    std::vector<double> res(M), resp((size_t)M * kNsSlices);
     for (int step = 0;; ++step) {
       // W = S X (by columns): C(r, c) = sum_k S(r, k) X(k, c)
       launch_gemm64_big(s, n3, n3, n3, pc.S.p, n3, (long)nn, pc.X.p, (long)nn, n3, pc.W.p, (long)nn, n3, 0, n3, M, 0);
-      hipLaunchKernelGGL(k_ns_residual, dim3(M), dim3(256), 0, s, pc.W.p, n3, pc.res.p);
-      HIPCHK(hipMemcpyAsync(res.data(), pc.res.p, M * sizeof(double), hipMemcpyDeviceToHost, s));
+      hipLaunchKernelGGL(k_ns_residual, dim3(M * kNsSlices), dim3(256), 0, s, pc.W.p, n3, pc.res.p);
+      HIPCHK(hipMemcpyAsync(resp.data(), pc.res.p, resp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      for (int i = 0; i < M; ++i) {
+        double t = 0.0;
+        for (int g = 0; g < kNsSlices; ++g) t += resp[(size_t)i * kNsSlices + g];
+        res[i] = t / n3;
+      }
       double worst = 0.0;
       for (double v : res) worst = std::isfinite(v) ? std::max(worst, std::sqrt(v)) : 1e300;
       if (worst <= kNsTol || step == kNsMaxSteps) break;
@@ -564,7 +576,8 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
     bp[M] = (int)bc.size();
     const long nb = (long)bc.size();
     pc.nblk = (int)nb;
-    pc.B16.alloc((size_t)nb * nn);
+    pc.ld = (n3 + 63) / 64 * 64;
+    pc.B16.alloc((size_t)nb * n3 * pc.ld);
     pc.bscale.alloc((size_t)nb);
     pc.bptr.upload(bp.data(), bp.size(), s);
     pc.bcol.upload(bc.data(), bc.size(), s);
@@ -573,8 +586,8 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
     dsrc.upload(src.data(), src.size(), s);
     dsg.upload(sg.data(), sg.size(), s);
     hipLaunchKernelGGL(k_block_absmax, dim3(nb), dim3(256), 0, s, dsrc.p, (long)nn, pc.bscale.p);
-    hipLaunchKernelGGL(k_blocks_f16, dim3(nblocks(nb * (long)nn)), dim3(256), 0, s, dsrc.p, dsg.p, pc.bscale.p,
-                       (long)nn, nb, pc.B16.p);
+    hipLaunchKernelGGL(k_blocks_f16, dim3(nblocks(nb * (long)n3 * pc.ld)), dim3(256), 0, s, dsrc.p, dsg.p,
+                       pc.bscale.p, n3, pc.ld, nb, pc.B16.p);
     HIPCHK(hipStreamSynchronize(s));  // dsrc is released after this
   }
   HIPCHK(hipGetLastError());
@@ -610,7 +623,7 @@ void pqn_ctx_impl::precond_apply_groups(std::vector<MvGroup>& groups) {
     pc.part.alloc((size_t)pc.nblk * kMaxRhs * n3);
     const int rchunks = (n3 + 255) / 256;
     pd.push_back(PcDesc{pc.B16.p, pc.bscale.p, pc.bcol.p, pc.bptr.p, gr.in[0], gr.out[0], pc.vI.p, pc.part.p, lv.n,
-                        lv.N, lv.M, rchunks, wg, el});
+                        lv.N, lv.M, pc.ld, rchunks, wg, el});
     wg += pc.nblk * rchunks;
     el += (long)lv.M * n3;
   }
@@ -645,8 +658,8 @@ void pqn_ctx_impl::precond_apply(MvGroup& gr) {
   const dim3 g(pc.nblk * rchunks);
   pc.part.alloc((size_t)pc.nblk * kMaxRhs * n3);
 #define BSRK(KK) \
-  hipLaunchKernelGGL(k_bsr_block<KK>, g, dim3(256), 0, s, pc.B16.p, pc.bscale.p, pc.bcol.p, pc.vI.p, n3, rchunks, \
-                     pc.part.p)
+  hipLaunchKernelGGL(k_bsr_block<KK>, g, dim3(256), 0, s, pc.B16.p, pc.bscale.p, pc.bcol.p, pc.vI.p, n3, pc.ld, \
+                     rchunks, pc.part.p)
   switch (K) {
     case 1: BSRK(1); break;
     case 2: BSRK(2); break;
