@@ -142,7 +142,8 @@ struct Precond {
   std::vector<long> nbo;
   DevArray<double> S, X, X2, W;  // [M][3n][3n]; S row-major, X (= S^{-1}), X2, W by columns
   DevArray<double> res;          // Newton-Schulz residuals, partial sums [M][slices]
-  DevArray<double> ug;           // kMaxRhs unit densities [3][N] (near-block assembly)
+  DevArray<double> NBc;          // near blocks on harmonic coefficients, sphere i's row [3n][npart_i 3L]
+  DevArray<double> TT;           // the analysis T by columns [n][L]
   DevArray<_Float16> B16;        // the preconditioner's blocks in FP16, by columns, row of sphere i
   DevArray<float> bscale;        // each block's largest magnitude (its FP16 copy is divided by it)
   DevArray<int> bptr, bcol;      // first block of sphere i's row [M + 1]; column sphere of each block
@@ -419,8 +420,9 @@ struct pqn_ctx_impl {
   void precond_apply(MvGroup& gr);
   void precond_apply_groups(std::vector<MvGroup>& groups);
   // near tiles only: near_part of the group's slots from its densities (with their
-  // coefficient and upsampling GEMMs), on the main stream
-  void near_stage(MvGroup& gr);
+  // coefficient and upsampling GEMMs; from_coef: from the coefficients already in the
+  // group's buffer), on the main stream
+  void near_stage(MvGroup& gr, bool from_coef = false);
   double pc_setup_ms = 0.0;  // preconditioner set-up time, fallbacks and applications since the last reset
   int pc_fallback = 0;
   int pc_applies = 0;

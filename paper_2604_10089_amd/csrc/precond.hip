@@ -21,8 +21,10 @@
 // Set-up, once per configuration and level (at the first solve after a change):
 //   - D on the host from the self block and the rigid projection, D^{-1} by
 //     Gauss-Jordan elimination with partial pivoting (once per level);
-//   - the near blocks, six columns at a time, from the near stage of the
-//     operator applied to unit densities (the same kernels as every product);
+//   - the near blocks from the near stage of the operator (the same kernels as
+//     every product) applied to unit harmonic-coefficient vectors, six at a
+//     time (the near rule reads a density only through its coefficients), then
+//     mapped to node space by the analysis T;
 //   - S_i by FP64 matrix-core GEMMs, S_i^{-1} by the Newton-Schulz iteration
 //     X <- X (2I - S_i X) from X = D^{-1} until every sphere's residual
 //     ||I - S_i X||_F / sqrt(3n) is below kNsTol. A sphere whose iteration does
@@ -150,22 +152,22 @@ static const SphereBlock& sphere_block_cached(const SphereTables& t) {
 
 // ------------------------------------------------------------------ kernels
 
-// K densities holding unit vectors: u_r = e_{k0 + r} on every sphere (local index).
-__global__ __launch_bounds__(256) void k_unit_cols(double* __restrict__ u, int K, int k0, int n, int N) {
+// Harmonic coefficients of K unit columns of the coefficient space, the same on every
+// sphere: coef[(i 3K + 3r + c) L + l] = 1 where c L + l = k0 + r ([M][3K][L] layout).
+__global__ __launch_bounds__(256) void k_unit_coef(double* __restrict__ coef, int K, int k0, int L, int M) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  const long len = 3L * N;
-  if (e >= (long)K * len) return;
-  const int r = (int)(e / len);
-  const long g = e - (long)r * len;
-  const int c = (int)(g / N), t = (int)(g - (long)c * N);
-  const int x = t % n;
-  u[e] = (c * n + x == k0 + r) ? 1.0 : 0.0;
+  const long per = 3L * K * L;
+  if (e >= (long)M * per) return;
+  const long q = e % per;
+  const int row = (int)(q / L), l = (int)(q - (long)row * L);
+  const int r = row / 3, c = row - 3 * r;
+  coef[e] = (c * L + l == k0 + r) ? 1.0 : 0.0;
 }
 
-// Columns k0 .. k0 + K - 1 of the near blocks from the near partials of unit densities:
-// NB_i(row, s 3n + k0 + r) = near_part_r[s 3N + c N + i n + x], row = c n + x.
+// Columns k0 .. k0 + K - 1 of the coefficient-space near blocks from the near partials:
+// NBc_i(row, s ncol + k0 + r) = near_part_r[s 3N + c N + i n + x], row = c n + x, ncol = 3L.
 // Thread per (sphere, slot, row), writing its K consecutive columns.
-__global__ __launch_bounds__(256) void k_nb_scatter(OPtrs np, int K, int k0, const int* __restrict__ npart,
+__global__ __launch_bounds__(256) void k_nb_scatter(OPtrs np, int K, int k0, int ncol, const int* __restrict__ npart,
                                                     const long* __restrict__ nbo, int n, int M, int N,
                                                     double* __restrict__ NB) {
   const int n3 = 3 * n;
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(256) void k_nb_scatter(OPtrs np, int K, int k0, con
   const int ns = npart[i];
   if (s >= ns) return;
   const int c = row / n, x = row - c * n;
-  double* dst = NB + nbo[i] + (size_t)row * ns * n3 + (size_t)s * n3 + k0;
+  double* dst = NB + nbo[i] + (size_t)row * ns * ncol + (size_t)s * ncol + k0;
   const size_t src = (size_t)s * 3 * N + (size_t)c * N + (size_t)i * n + x;
   for (int r = 0; r < K; ++r) dst[r] = np.p[r][src];
 }
@@ -395,7 +397,7 @@ static unsigned nblocks(long count) { return (unsigned)((count + 255) / 256); }
 
 // ------------------------------------------------------------ near stage only
 
-void pqn_ctx_impl::near_stage(MvGroup& gr) {
+void pqn_ctx_impl::near_stage(MvGroup& gr, bool from_coef) {
   Level& lv = *gr.lv;
   hipStream_t s = stream;
   if (n_near + n_near2 == 0) return;
@@ -408,7 +410,7 @@ void pqn_ctx_impl::near_stage(MvGroup& gr) {
   DescPack dp;
   const size_t oa = dp.add(ga), ob = dp.add(gb);
   char* base = push_desc_pack(dp.host);
-  launch_gemm64_multi(s, (const GemmDesc*)(base + oa), (int)ga.size(), nga);
+  if (!from_coef) launch_gemm64_multi(s, (const GemmDesc*)(base + oa), (int)ga.size(), nga);
   launch_gemm64_multi(s, (const GemmDesc*)(base + ob), (int)gb.size(), ngb);
   OPtrs np{};
   for (int r = 0; r < gr.K; ++r) np.p[r] = lv.wk(gr.slot[r]).near_part.p;
@@ -455,23 +457,56 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
   } else {
     pc.NB.alloc((size_t)total);
     pc.TB.alloc((size_t)total);
-    DevArray<long> dnbo;
-    dnbo.upload(pc.nbo.data(), pc.nbo.size(), s);
-    // near blocks, kMaxRhs columns per pass, from unit densities through the near stage
-    pc.ug.alloc((size_t)kMaxRhs * 3 * N);
-    for (int k0 = 0; k0 < n3; k0 += kMaxRhs) {
-      const int K = std::min(kMaxRhs, n3 - k0);
-      hipLaunchKernelGGL(k_unit_cols, dim3(nblocks((long)K * 3 * N)), dim3(256), 0, s, pc.ug.p, K, k0, n, N);
+    // Near blocks. The near rule reads a density only through its harmonic coefficients
+    // (coef = T q: the upsampled values and the foot-point expansion), so A_ij = Ac_ij (I3 x T)
+    // with Ac_ij [3n][3L]: Ac from unit coefficient columns through the near stage (3L / 6
+    // passes instead of 3n / 6), then A = Ac (I3 x T) by GEMMs into NB.
+    const int L = lv.L, n3L = 3 * L;
+    std::vector<long> nbco(M);
+    long totc = 0;
+    for (int i = 0; i < M; ++i) {
+      nbco[i] = totc;
+      totc += (long)h_npart[i] * n3 * n3L;
+    }
+    pc.NBc.alloc((size_t)totc);
+    DevArray<long> dnbco;
+    dnbco.upload(nbco.data(), nbco.size(), s);
+    for (int k0 = 0; k0 < n3L; k0 += kMaxRhs) {
+      const int K = std::min(kMaxRhs, n3L - k0);
       MvGroup g{this, &lv, K, {}, {}, {}};
       OPtrs np{};
       for (int r = 0; r < K; ++r) {
         g.slot[r] = r;
-        g.in[r] = pc.ug.p + (size_t)r * 3 * N;
+        g.in[r] = lv.off.p;  // not read: the coefficients are given
         np.p[r] = lv.wk(r).near_part.p;
       }
-      near_stage(g);
-      hipLaunchKernelGGL(k_nb_scatter, dim3(nblocks((long)M * kMaxNear * n3)), dim3(256), 0, s, np, K, k0, npart.p,
-                         dnbo.p, n, M, N, pc.NB.p);
+      double* coef = group_coef(g);
+      hipLaunchKernelGGL(k_unit_coef, dim3(nblocks((long)M * 3 * K * L)), dim3(256), 0, s, coef, K, k0, L, M);
+      near_stage(g, true);
+      hipLaunchKernelGGL(k_nb_scatter, dim3(nblocks((long)M * kMaxNear * n3)), dim3(256), 0, s, np, K, k0, n3L,
+                         npart.p, dnbco.p, n, M, N, pc.NBc.p);
+    }
+    {
+      // NB_i(:, s 3n + d n + m) = sum_l Ac_i(:, s 3L + d L + l) T(l, m), T read by columns (TT)
+      if (!pc.TT.p) {
+        std::vector<double> tt((size_t)n * L);
+        for (int l = 0; l < L; ++l)
+          for (int m = 0; m < n; ++m) tt[(size_t)m * L + l] = lv.tab.T[(size_t)l * n + m];
+        pc.TT.upload(tt.data(), tt.size(), s);
+      }
+      std::vector<GemmDesc> gc;
+      int ngc = 0;
+      for (int i = 0; i < M; ++i) {
+        const int ns = h_npart[i];
+        for (int sl = 0; sl < ns; ++sl)
+          for (int d = 0; d < 3; ++d)
+            push_gemm(gc, ngc, n3, n, L, pc.NBc.p + nbco[i] + (size_t)sl * n3L + (size_t)d * L, ns * n3L, pc.TT.p, L,
+                      pc.NB.p + pc.nbo[i] + (size_t)sl * n3 + (size_t)d * n, n3, 0, 1, ns * n3, n, 0, 0, 1);
+      }
+      DescPack dc;
+      const size_t occ = dc.add(gc);
+      char* cb = push_desc_pack(dc.host);
+      launch_gemm64_multi_big(s, (const GemmDesc*)(cb + occ), (int)gc.size(), ngc);
     }
     // T_(i,s) = D^{-1} A_(j,s'), j the partner in slot s of i and s' the slot of i in j's list,
     // stored as TB_i(c, s 3n + m) = T_(i,s)(m, c): computed as C(c, m) = sum_k A_(j,s')(k, c) D^{-1}(m, k)
@@ -555,7 +590,7 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
     char* qb = push_desc_pack(dq.host);
     launch_gemm64_multi_big(s, (const GemmDesc*)(qb + oh), (int)gh.size(), ngh);
     launch_gemm64_multi_big(s, (const GemmDesc*)(qb + og), (int)gg.size(), ngg);
-    HIPCHK(hipStreamSynchronize(s));  // dnbo and the descriptor tables are released/reused after this
+    HIPCHK(hipStreamSynchronize(s));  // dnbco and the descriptor tables are released/reused after this
   }
   // block rows in FP16: sphere i holds S_i^{-1} (or D^{-1}) then G_(i,s) for its slots
   {
