@@ -71,15 +71,18 @@ def far_kernel_name(layout, K):
 
 
 def pc_blocks(c, near_gap=0.5, radius=1.0):
-    """Blocks of the preconditioner: one per sphere and one per ordered near pair (gap < near_gap)."""
+    """Blocks of the preconditioner: one per sphere with a near partner (gap < near_gap) and one
+    per ordered near pair."""
     d = np.linalg.norm(c[:, None, :] - c[None, :, :], axis=2) - 2 * radius
     np.fill_diagonal(d, np.inf)
-    return int(c.shape[0] + (d < near_gap).sum())
+    near = d < near_gap
+    return int(near.any(axis=1).sum() + near.sum())
 
 
-def precond_bytes(M, n, nblocks):
-    """HBM bytes of one preconditioner application: the FP16 blocks (3n)^2 each, streamed once."""
-    return int(nblocks * (3 * n) ** 2 * 2)
+def precond_bytes(n, L, nblocks):
+    """HBM bytes of one preconditioner application: the FP16 blocks (3n x 3L each, n nodes and
+    L harmonic coefficients per sphere), streamed once."""
+    return int(nblocks * (3 * n) * (3 * L) * 2)
 
 
 def flop_per_pair(K):
@@ -569,9 +572,9 @@ def main():
             'setup_ms': round(m6['precond_setup_ms'], 1),
             'setup_ms_in_timed_region': round(m6['precond_setup_in_timed_ms'], 1),
             'apply_ms_k6': round(prof6['precond_apply_ms'], 4),
-            'apply_hbm_gbs_k6': round(precond_bytes(M, n, pc_blocks(c)) / (prof6['precond_apply_ms'] * 1e-3) / 1e9, 1)
+            'apply_hbm_gbs_k6': round(precond_bytes(n, nt * nt, pc_blocks(c)) / (prof6['precond_apply_ms'] * 1e-3) / 1e9, 1)
             if prof6['precond_apply_ms'] > 0 else None,
-            'block_bytes': precond_bytes(M, n, pc_blocks(c)),
+            'block_bytes': precond_bytes(n, nt * nt, pc_blocks(c)),
             'plain_gmres': {'mvps': round(plain6['mvps'], 4), 'gmres_iters_per_mvp': round(plain6['gmres_iters'], 2),
                             'ms_per_step': round(1e3 * plain6['sec'] / plain6['steps'], 3)},
             'speedup_vs_plain': round(m6['mvps'] / plain6['mvps'], 3)},

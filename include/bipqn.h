@@ -122,14 +122,17 @@ typedef struct {
                                solves without fixing one): for sphere i with near partners j,
                                (P v)_i = inv(S_i) (v_i - sum_j A_ij inv(D) v_j),
                                S_i = D - sum_j A_ij inv(D) A_ji, D the single-sphere block and A_ij
-                               the near blocks; applied as one block-sparse product with FP16
-                               blocks (each scaled by its largest magnitude). Same solution and
-                               stopping rule (true residual), fewer
+                               the near blocks. The near blocks act through the L = n_theta^2
+                               harmonic coefficients of a density, so inv(S_i) is inv(D) plus a
+                               rank-3L term; applied as inv(D) v (FP64) plus one block-sparse
+                               product with 3n x 3L blocks in FP16 (each scaled by its largest
+                               magnitude). Same solution and stopping rule (true residual), fewer
                                iterations. The set-up (pqn_mvp_stats.t_precond_ms) is per
                                configuration and fidelity: 1 = built when a configuration is solved
                                a second time (its first solve is plain), 2 = built at the first
-                               solve; 0 = plain GMRES. Device memory about (2 n_near + 4 M) (3n)^2
-                               doubles. In a batch context each suspension has its own (built at
+                               solve; 0 = plain GMRES. Device memory about (2 n_near + 3 M) 3n 3L
+                               + (n_near + 4 M) (3L)^2 doubles during the set-up, (M + n_near) 3n 3L FP16
+                               values after it. In a batch context each suspension has its own (built at
                                the same points; its GMRES iterations then run eagerly, not from
                                captured graphs) [0] */
 } pqn_config_desc;

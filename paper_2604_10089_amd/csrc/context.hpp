@@ -132,24 +132,30 @@ struct SysBuf {
 // S_i = D - sum_j A_ij D^{-1} A_ji and their inverses, rebuilt at the first solve
 // after a configuration change.
 struct Precond {
-  bool has_d = false;
+  bool has_d = false;            // D^{-1}, TD and the application's GEMM descriptors are built
   unsigned long epoch = 0;       // configuration of the tables below (0 = none yet)
   unsigned long seen = 0;        // configuration last solved without them (precond = 1)
   bool use = false;              // the current solve (solve_lockstep) applies them
-  DevArray<double> D, Dinv;      // [3n][3n] row-major
+  DevArray<double> Dinv;         // [3n][3n] row-major
   DevArray<double> DinvT;        // D^{-1} by columns ([3n][3n] row-major of its transpose)
-  DevArray<double> NB, TB;       // per sphere [3n][npart_i 3n] row-major, at nbo[i] doubles
-  std::vector<long> nbo;
-  DevArray<double> S, X, X2, W;  // [M][3n][3n]; S row-major, X (= S^{-1}), X2, W by columns
-  DevArray<double> res;          // Newton-Schulz residuals, partial sums [M][slices]
-  DevArray<double> NBc;          // near blocks on harmonic coefficients, sphere i's row [3n][npart_i 3L]
   DevArray<double> TT;           // the analysis T by columns [n][L]
-  DevArray<_Float16> B16;        // the preconditioner's blocks in FP16, by columns, row of sphere i
+  DevArray<double> TD;           // (I3 x T) D^{-1} [3L][3n] row-major
+  DevArray<double> Ac, Gc;       // near blocks on coefficients / S_i^{-1} Ac: per slot [3L][3n] by columns, at aco[i]
+  DevArray<double> Rr;           // TD Ac of the reverse slots: sphere i [npart_i 3L][3L] by columns, at rro[i]
+  std::vector<long> aco, rro;
+  DevArray<double> Q, Z, E;      // [M] x 3n x 3L by columns: Q_i, D^{-1} Q_i, E_i
+  DevArray<double> Kc, Y, Y2, W; // [M] x 3L x 3L by columns: I - TD Q_i, its inverse (Newton-Schulz)
+  DevArray<double> res;          // Newton-Schulz residuals, partial sums [M][slices]
+  DevArray<_Float16> B16;        // the E_i and -Gc blocks in FP16, by columns, row of sphere i
   DevArray<float> bscale;        // each block's largest magnitude (its FP16 copy is divided by it)
   DevArray<int> bptr, bcol;      // first block of sphere i's row [M + 1]; column sphere of each block
-  DevArray<double> vI;           // input densities interleaved per node [M][3n][K]
+  DevArray<double> vC;           // input densities by (density, sphere) columns [K][M][3n]
+  DevArray<double> wI, yI;       // TD v [M][3L][K] and D^{-1} v [M][3n][K]
   DevArray<double> part;         // per-block partial products [nblk][K][3n]
-  int nblk = 0;                  // blocks: M + the ordered near pairs
+  DevArray<GemmDesc> adesc;      // y and w GEMMs for K = 1 .. kMaxRhs (2 per K)
+  std::vector<GemmDesc> adesc_h; // host copy (the batch path concatenates the K = 1 pairs)
+  int aty[kMaxRhs] = {}, atw[kMaxRhs] = {};  // 64x64 tiles of those GEMMs
+  int nblk = 0;                  // blocks: the spheres with near partners + the ordered near pairs
   int ld = 0;                    // padded column length of the FP16 blocks (multiple of 64)
   int fallback = 0;              // spheres left on D^{-1} (Newton-Schulz did not converge)
   int ns_iters = 0;              // Newton-Schulz steps of the last set-up

@@ -783,7 +783,9 @@ __device__ __forceinline__ void gemm_tile(int bx, int by, int R, int Cn, int K, 
 // on the current ones.
 __device__ __forceinline__ void gemm_tile_big(int bx, int by, int R, int Cn, int K, const double* __restrict__ A,
                                               int lda, const double* __restrict__ B, int ldb, double* __restrict__ C,
-                                              int rb, long rbs, int ldc, int rs, int cb, long cbs, int at) {
+                                              int rb, long rbs, int ldc, int rs, int cb, long cbs, int at_acc) {
+  // at_acc bit 0: A stored by columns; bit 1: C += A B instead of C = A B
+  const int at = at_acc & 1, accum = at_acc & 2;
   __shared__ double As[2 * GBM * GLS], Bs[2 * GBN * GLS];
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -857,7 +859,10 @@ __device__ __forceinline__ void gemm_tile_big(int bx, int by, int R, int Cn, int
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int gc = c0 + qc + 16 * j + li;
-        if (gc < Cn) C[rowbase + (size_t)(gc / cb) * cbs + (size_t)(gc % cb) * ldc] = acc[i][j][q];
+        if (gc < Cn) {
+          double* c = C + rowbase + (size_t)(gc / cb) * cbs + (size_t)(gc % cb) * ldc;
+          *c = accum ? *c + acc[i][j][q] : acc[i][j][q];
+        }
       }
     }
 }

@@ -40,7 +40,8 @@ struct GemmDesc {
   int rs, cb;  // C(r, col) at C[(r / rb) rbs + (r % rb) rs + (col / cb) cbs + (col % cb) ldc]
   long cbs;
   const int* live;  // null, or a flag: 0 = the segment's system is done (its blocks exit)
-  int at;           // 1: A(r, k) = A[k * lda + r] (A stored by columns), else A[r * lda + k]
+  int at;           // bit 0: A(r, k) = A[k * lda + r] (A stored by columns), else A[r * lda + k];
+                    // bit 1 (64x64-tile launches only): C += A B
 };
 struct PackDesc {
   const double* q;
@@ -156,7 +157,8 @@ void launch_near(hipStream_t s, int K, int npairs_count, const double* ctr, cons
 void launch_gemm64(hipStream_t s, int R, int Cn, int K, const double* A, int lda, long Az, const double* B, long Bz,
                    int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch, int at = 0);
 // The same with 64x64 tiles (large products); the segmented form takes descriptors whose
-// tr and start count 64x64 tiles.
+// tr and start count 64x64 tiles. With 64x64 tiles, at = 2 | (A by columns) accumulates
+// into C (C += A B).
 void launch_gemm64_big(hipStream_t s, int R, int Cn, int K, const double* A, int lda, long Az, const double* B,
                        long Bz, int ldb, double* C, long Cz, int rb, long rbs, int ldc, int batch, int at = 0);
 void launch_gemm64_multi_big(hipStream_t s, const GemmDesc* d, int nd, int nblocks);

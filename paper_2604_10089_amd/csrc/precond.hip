@@ -18,33 +18,56 @@
 // complements. For a lone near pair it is the pair's exact inverse; far
 // interactions stay out (smooth, few GMRES iterations).
 //
-// Set-up, once per configuration and level (at the first solve after a change):
+// Factorisation through harmonic coefficients. The near rule reads a density
+// only through its coefficients coef = T q (the upsampled values and the
+// foot-point expansion are both synthesised from them), so every near block is
+// A_ij = Ac_ij (I3 x T) with Ac_ij [3n][3L]. With TD = (I3 x T) D^{-1} [3L][3n]
+// (one matrix per grid) and R_ij = TD Ac_ij [3L][3L]:
+//
+//   sum_j A_ij D^{-1} A_ji = Q_i (I3 x T),  Q_i = sum_j Ac_ij R_ji,
+//
+// a correction of D of rank at most 3L, so (Sherman-Morrison-Woodbury)
+//
+//   S_i^{-1} = D^{-1} + E_i TD,  E_i = D^{-1} Q_i Y_i,  Y_i = (I - TD Q_i)^{-1} [3L][3L],
+//
+// and with w_j = TD v_j, the coefficient-space image of every sphere's input,
+//
+//   (P_r v)_i = D^{-1} v_i + E_i w_i - sum_j Gc_ij w_j,  Gc_ij = S_i^{-1} Ac_ij = D^{-1} Ac_ij + E_i R_ij.
+//
+// Set-up, once per configuration and level (at the first solve it applies to):
 //   - D on the host from the self block and the rigid projection, D^{-1} by
-//     Gauss-Jordan elimination with partial pivoting (once per level);
-//   - the near blocks from the near stage of the operator (the same kernels as
-//     every product) applied to unit harmonic-coefficient vectors, six at a
-//     time (the near rule reads a density only through its coefficients), then
-//     mapped to node space by the analysis T;
-//   - S_i by FP64 matrix-core GEMMs, S_i^{-1} by the Newton-Schulz iteration
-//     X <- X (2I - S_i X) from X = D^{-1} until every sphere's residual
-//     ||I - S_i X||_F / sqrt(3n) is below kNsTol. A sphere whose iteration does
-//     not get below kNsKeep keeps X = D^{-1} (block Jacobi for that sphere).
+//     Gauss-Jordan elimination with partial pivoting (once per grid and
+//     process), TD by FP64 GEMMs (once per level);
+//   - Ac_ij from the near stage of the operator (the same kernels as every
+//     product) applied to unit harmonic-coefficient vectors, six at a time;
+//   - R, Q_i, TD Q_i, E_i and Gc_ij by FP64 matrix-core GEMMs; Y_i by the
+//     Newton-Schulz iteration Y <- Y (2I - K_i Y), K_i = I - TD Q_i, from Y = I
+//     until every sphere's residual ||I - K_i Y||_F / sqrt(3L) is below kNsTol.
+//     At Y = I the residual is TD Q_i, whose nonzero eigenvalues are those of
+//     I - S_i D^{-1}: the iteration converges as one on S_i from D^{-1} would,
+//     on matrices of (3L)^2 instead of (3n)^2 entries. A sphere still above
+//     kNsKeep gets Y_i = 0, i.e. S_i^{-1} replaced by D^{-1} (block Jacobi for
+//     that sphere).
+// Application: w = TD v and y = D^{-1} v for all spheres and densities by one
+// FP64 GEMM launch (the two matrices are shared by all spheres), then one
+// block-sparse product over the E_i and Gc_ij (3n x 3L each) stored in FP16,
+// each scaled by its largest magnitude (one FP32 factor per block). P_r is a
+// fixed linear map either way, so GMRES keeps its convergence theory and the
+// solution its accuracy; the rounding only perturbs the correction terms (the
+// D^{-1} v part is exact FP64). Each application streams the blocks once from
+// HBM ((M' + n_near) 3n 3L 2 bytes, M' the spheres with near partners: 0.5 GB
+// at 216 spheres and 12x24 nodes), whatever the number of densities K.
 //
-//   - G_ij = S_i^{-1} A_ij D^{-1} for every near pair, so that
-//     (P_r v)_i = S_i^{-1} v_i - sum_j G_ij v_j: one block-sparse product whose
-//     blocks (S_i^{-1} and the G_ij, 3n x 3n each) are stored in FP16, each
-//     scaled by its largest magnitude (one FP32 factor per block). P_r is a
-//     fixed linear map either way, so GMRES keeps its convergence theory and the
-//     solution its accuracy; the rounding only perturbs the preconditioner (the
-//     iteration counts on the test workloads are those of FP64 blocks).
-// Each application streams the blocks once from HBM ((M + n_near) (3n)^2 2 bytes:
-// 1.1 GB at 216 spheres and 12x24 nodes), whatever the number of densities K.
-//
-// Layouts (3n = per-sphere unknowns, local index c n + x: component c, node x):
-//   D, D^{-1}: [3n][3n] row-major; near blocks of sphere i: [3n][npart_i 3n]
-//   row-major (slot s in columns s 3n ..); S_i row-major; X_i by columns; the
-//   FP16 blocks by columns padded to a multiple of 64 rows, sphere i's row of
-//   blocks contiguous (S_i^{-1} first).
+// Layouts (3n = per-sphere unknowns, local index c n + x: component c, node x;
+// 3L = coefficient unknowns, index d L + l):
+//   Dinv [3n][3n] row-major, DinvT its transpose; TD [3L][3n] row-major;
+//   Ac_ij, Gc_ij: by columns (column c' holds 3n rows), sphere i's slot s at
+//   aco[i] + s 3n 3L; R: sphere i's [npart_i 3L][3L] by columns at rro[i], its
+//   slot s holding R_(j s') = TD Ac_(j s') for the reverse (j, s') of (i, s);
+//   Q, Z = D^{-1} Q, E: [M] x 3n x 3L by columns; K_i, Y, W: [M] x 3L x 3L by
+//   columns; the FP16 blocks by columns padded to a multiple of 64 rows, sphere
+//   i's row of blocks contiguous (E_i first); vC [K][M][3n] (column (r, j):
+//   density r on sphere j), wI [M][3L][K], yI [M][3n][K].
 #include "context.hpp"
 
 #include <algorithm>
@@ -164,56 +187,54 @@ __global__ __launch_bounds__(256) void k_unit_coef(double* __restrict__ coef, in
   coef[e] = (c * L + l == k0 + r) ? 1.0 : 0.0;
 }
 
+
 // Columns k0 .. k0 + K - 1 of the coefficient-space near blocks from the near partials:
-// NBc_i(row, s ncol + k0 + r) = near_part_r[s 3N + c N + i n + x], row = c n + x, ncol = 3L.
-// Thread per (sphere, slot, row), writing its K consecutive columns.
+// Ac_(i,s)(row, k0 + r) = near_part_r[s 3N + c N + i n + x], row = c n + x, stored by columns
+// (aco[i] + (s ncol + k0 + r) 3n + row, ncol = 3L). Thread per (sphere, slot, row).
 __global__ __launch_bounds__(256) void k_nb_scatter(OPtrs np, int K, int k0, int ncol, const int* __restrict__ npart,
-                                                    const long* __restrict__ nbo, int n, int M, int N,
-                                                    double* __restrict__ NB) {
+                                                    const long* __restrict__ aco, int n, int M, int N,
+                                                    double* __restrict__ Ac) {
   const int n3 = 3 * n;
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= (long)M * kMaxNear * n3) return;
   const int row = (int)(e % n3);
   const int s = (int)((e / n3) % kMaxNear);
   const int i = (int)(e / ((long)n3 * kMaxNear));
-  const int ns = npart[i];
-  if (s >= ns) return;
+  if (s >= npart[i]) return;
   const int c = row / n, x = row - c * n;
-  double* dst = NB + nbo[i] + (size_t)row * ns * ncol + (size_t)s * ncol + k0;
+  double* dst = Ac + aco[i] + ((size_t)s * ncol + k0) * n3 + row;
   const size_t src = (size_t)s * 3 * N + (size_t)c * N + (size_t)i * n + x;
-  for (int r = 0; r < K; ++r) dst[r] = np.p[r][src];
+  for (int r = 0; r < K; ++r) dst[(size_t)r * n3] = np.p[r][src];
 }
 
-// The set-up's elementwise passes over [M][3n][3n] matrices: one block per (sphere,
+// The set-up's elementwise passes over [M][m][m] matrices by columns: one block per (sphere,
 // column), threads along the column (no 64-bit index division per element).
 
-// S_i = D - C_i (row-major, in place over C), for every sphere.
-__global__ __launch_bounds__(256) void k_schur_finish(const double* __restrict__ D, int n3,
-                                                      double* __restrict__ S) {
-  const size_t col = (size_t)blockIdx.x % n3, i = (size_t)blockIdx.x / n3;
-  double* s = S + (i * n3 + col) * n3;
-  const double* d = D + col * n3;
-  for (int r = threadIdx.x; r < n3; r += 256) s[r] = d[r] - s[r];
+// W <- dg I - W for every sphere.
+__global__ __launch_bounds__(256) void k_diag_minus(double* __restrict__ W, int m, double dg) {
+  const int col = blockIdx.x % m;
+  double* w = W + (size_t)blockIdx.x * m;
+  for (int r = threadIdx.x; r < m; r += 256) w[r] = (r == col ? dg : 0.0) - w[r];
 }
 
-// W <- 2I - W for every sphere (by columns; the diagonal is the same either way).
-__global__ __launch_bounds__(256) void k_two_minus(double* __restrict__ W, int n3) {
-  const int col = blockIdx.x % n3;
-  double* w = W + (size_t)blockIdx.x * n3;
-  for (int r = threadIdx.x; r < n3; r += 256) w[r] = (r == col ? 2.0 : 0.0) - w[r];
+// W <- I for every sphere.
+__global__ __launch_bounds__(256) void k_eye(double* __restrict__ W, int m) {
+  const int col = blockIdx.x % m;
+  double* w = W + (size_t)blockIdx.x * m;
+  for (int r = threadIdx.x; r < m; r += 256) w[r] = r == col ? 1.0 : 0.0;
 }
 
 // Partial sums of ||I - W_i||_F^2: block (i, g) covers the columns c = g, g + kNsSlices, ...
 // of sphere i; res[i kNsSlices + g] (the host adds the slices in order).
 constexpr int kNsSlices = 32;
-__global__ __launch_bounds__(256) void k_ns_residual(const double* __restrict__ W, int n3, double* __restrict__ res) {
+__global__ __launch_bounds__(256) void k_ns_residual(const double* __restrict__ W, int m, double* __restrict__ res) {
   __shared__ double sh[256];
   const int i = blockIdx.x / kNsSlices, g = blockIdx.x % kNsSlices;
-  const double* Wi = W + (size_t)i * n3 * n3;
+  const double* Wi = W + (size_t)i * m * m;
   double acc = 0.0;
-  for (int c = g; c < n3; c += kNsSlices)
-    for (int r = threadIdx.x; r < n3; r += 256) {
-      const double d = (r == c ? 1.0 : 0.0) - Wi[(size_t)c * n3 + r];
+  for (int c = g; c < m; c += kNsSlices)
+    for (int r = threadIdx.x; r < m; r += 256) {
+      const double d = (r == c ? 1.0 : 0.0) - Wi[(size_t)c * m + r];
       acc = fma(d, d, acc);
     }
   sh[threadIdx.x] = acc;
@@ -223,20 +244,6 @@ __global__ __launch_bounds__(256) void k_ns_residual(const double* __restrict__ 
     __syncthreads();
   }
   if (threadIdx.x == 0) res[blockIdx.x] = sh[0];
-}
-
-// vI[(j 3n + m) K + r] = v_r[c N + j n + x], m = c n + x: the K densities of a node
-// next to each other, one scalar-load stream per block column.
-__global__ __launch_bounds__(256) void k_pc_interleave(QPtrs v, int K, int n, int M, int N,
-                                                       double* __restrict__ vI) {
-  const int n3 = 3 * n;
-  const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (long)M * n3 * K) return;
-  const int r = (int)(e % K);
-  const long jm = e / K;
-  const int m = (int)(jm % n3), j = (int)(jm / n3);
-  const int c = m / n, x = m - c * n;
-  vI[e] = v.p[r][(size_t)c * N + (size_t)j * n + x];
 }
 
 // Largest magnitude of each FP64 block (one workgroup per block, fixed-order reduction).
@@ -255,42 +262,56 @@ __global__ __launch_bounds__(256) void k_block_absmax(const double* const* __res
   if (threadIdx.x == 0) scale[blockIdx.x] = sh[0] > 0.0 ? (float)sh[0] : 1.0f;
 }
 
-// FP16 copies of FP64 blocks stored by columns: block b of the list is sgn[b] src[b] / scale[b]
-// (entries in [-1, 1]; the product multiplies the scale back), each column padded with zeros
-// to ld entries (a multiple of 64: every column starts on a 128-byte line).
+// FP16 copies of FP64 blocks of rows x cols entries stored by columns: block b of the list is
+// sgn[b] src[b] / scale[b] (entries in [-1, 1]; the product multiplies the scale back), each
+// column padded with zeros to ld entries (a multiple of 64: every column starts on a 128-byte line).
 __global__ __launch_bounds__(256) void k_blocks_f16(const double* const* __restrict__ src,
                                                     const double* __restrict__ sgn, const float* __restrict__ scale,
-                                                    int n3, int ld, long nb, _Float16* __restrict__ dst) {
+                                                    int rows, int cols, int ld, long nb, _Float16* __restrict__ dst) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  const long per = (long)n3 * ld;
+  const long per = (long)cols * ld;
   if (e >= nb * per) return;
   const long b = e / per;
   const long l = e - b * per;
   const int m = (int)(l / ld), r = (int)(l - (long)m * ld);
-  dst[e] = r < n3 ? (_Float16)(float)(sgn[b] / scale[b] * src[b][(size_t)m * n3 + r]) : (_Float16)0.0f;
+  dst[e] = r < rows ? (_Float16)(float)(sgn[b] / scale[b] * src[b][(size_t)m * rows + r]) : (_Float16)0.0f;
 }
 
-// part[(b K + r) 3n + row] = sum_m B_b(row, m) vI[(j 3n + m) K + r], j the column sphere of
-// block b. Thread per (block, row): the block's columns are read by consecutive rows
-// (coalesced), the densities of node m of sphere j are wave-uniform (scalar loads). A
-// workgroup per (block, 256 rows), rather than per (sphere, rows), gives the launch
-// enough waves to keep the loads in flight that stream the blocks from HBM.
-// FP16 blocks scaled to [-1, 1] (scale[b] multiplied back at the end), FP64 products and sums.
+// ------------------------------------------------------------ application kernels
+
+// vC[(r M + j) 3n + m] = v_r[c N + j n + x], m = c n + x: every (density, sphere) a column.
+__global__ __launch_bounds__(256) void k_pc_gather(QPtrs v, int K, int n, int M, int N, double* __restrict__ vC) {
+  const int n3 = 3 * n;
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)K * M * n3) return;
+  const int m = (int)(e % n3);
+  const long rj = e / n3;
+  const int j = (int)(rj % M), r = (int)(rj / M);
+  const int c = m / n, x = m - c * n;
+  vC[e] = v.p[r][(size_t)c * N + (size_t)j * n + x];
+}
+
+// part[(b K + r) 3n + row] = sum_m B_b(row, m) wI[(j 3L + m) K + r], j the column sphere of
+// block b, m < 3L. Thread per (block, row): the block's columns are read by consecutive rows
+// (coalesced), the coefficients of sphere j are wave-uniform (scalar loads). A workgroup per
+// (block, 256 rows) gives the launch enough waves to keep the loads in flight that stream the
+// blocks from HBM. FP16 blocks scaled to [-1, 1] (scale[b] multiplied back at the end), FP64
+// products and sums.
 template <int K>
 __device__ __forceinline__ void bsr_block_body(const _Float16* __restrict__ B, const float* __restrict__ scale,
-                                               const int* __restrict__ bcol, const double* __restrict__ vI,
-                                               int n3, int ld, int rchunks, int wg, double* __restrict__ part) {
+                                               const int* __restrict__ bcol, const double* __restrict__ wI,
+                                               int n3, int nc, int ld, int rchunks, int wg, double* __restrict__ part) {
   const int b = wg / rchunks;
   const int row = (wg - b * rchunks) * 256 + threadIdx.x;
   const bool valid = row < n3;
   const int rr = valid ? row : n3 - 1;
-  const _Float16* Bb = B + (size_t)b * n3 * ld + rr;
-  const double* v = vI + (size_t)bcol[b] * n3 * K;
+  const _Float16* Bb = B + (size_t)b * nc * ld + rr;
+  const double* v = wI + (size_t)bcol[b] * nc * K;
   double acc[K];
 #pragma unroll
   for (int r = 0; r < K; ++r) acc[r] = 0.0;
 #pragma unroll 8
-  for (int m = 0; m < n3; ++m) {
+  for (int m = 0; m < nc; ++m) {
     const double a = (double)(float)Bb[(size_t)m * ld];
 #pragma unroll
     for (int r = 0; r < K; ++r) acc[r] = fma(a, v[m * K + r], acc[r]);
@@ -304,14 +325,30 @@ __device__ __forceinline__ void bsr_block_body(const _Float16* __restrict__ B, c
 
 template <int K>
 __global__ __launch_bounds__(256) void k_bsr_block(const _Float16* __restrict__ B, const float* __restrict__ scale,
-                                                   const int* __restrict__ bcol, const double* __restrict__ vI,
-                                                   int n3, int ld, int rchunks, double* __restrict__ part) {
-  bsr_block_body<K>(B, scale, bcol, vI, n3, ld, rchunks, blockIdx.x, part);
+                                                   const int* __restrict__ bcol, const double* __restrict__ wI,
+                                                   int n3, int nc, int ld, int rchunks, double* __restrict__ part) {
+  bsr_block_body<K>(B, scale, bcol, wI, n3, nc, ld, rchunks, blockIdx.x, part);
+}
+
+// out_r[c N + i n + x] = yI[(i 3n + row) K + r] + the partials of sphere i's blocks (in block
+// order), row = c n + x.
+__global__ __launch_bounds__(256) void k_pc_sum(const double* __restrict__ yI, const double* __restrict__ part,
+                                                const int* __restrict__ bptr, int K, int n, int M, int N, OPtrs out) {
+  const int n3 = 3 * n;
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)M * K * n3) return;
+  const int row = (int)(e % n3);
+  const int r = (int)((e / n3) % K);
+  const int i = (int)(e / ((long)n3 * K));
+  double v = yI[((size_t)i * n3 + row) * K + r];
+  for (int b = bptr[i]; b < bptr[i + 1]; ++b) v += part[((size_t)b * K + r) * n3 + row];
+  const int c = row / n, x = row - c * n;
+  out.p[r][(size_t)c * N + (size_t)i * n + x] = v;
 }
 
 // Many suspensions in one launch (one density each): segment descriptors, workgroups
 // [start, ...) of a segment for the block products, elements [estart, estart + M 3n)
-// for the interleave and the sum.
+// for the gather and the sum.
 struct PcDesc {
   const _Float16* B;
   const float* scale;
@@ -319,9 +356,11 @@ struct PcDesc {
   const int* bptr;
   const double* in;
   double* out;
-  double* vI;
+  double* vC;
+  const double* wI;
+  const double* yI;
   double* part;
-  int n, N, M, ld, rchunks, start;
+  int n, N, M, nc, ld, rchunks, start;
   long estart;
 };
 
@@ -349,7 +388,7 @@ __device__ __forceinline__ int pc_seg_elems(const PcDesc* __restrict__ d, int nd
   return lo;
 }
 
-__global__ __launch_bounds__(256) void k_pc_interleave_multi(const PcDesc* __restrict__ d, int nd, long total) {
+__global__ __launch_bounds__(256) void k_pc_gather_multi(const PcDesc* __restrict__ d, int nd, long total) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= total) return;
   const PcDesc D = d[pc_seg_elems(d, nd, e)];
@@ -357,44 +396,28 @@ __global__ __launch_bounds__(256) void k_pc_interleave_multi(const PcDesc* __res
   const int n3 = 3 * D.n;
   const int j = (int)(l / n3), m = (int)(l - (long)j * n3);
   const int c = m / D.n, x = m - c * D.n;
-  D.vI[l] = D.in[(size_t)c * D.N + (size_t)j * D.n + x];
+  D.vC[l] = D.in[(size_t)c * D.N + (size_t)j * D.n + x];
 }
 
 __global__ __launch_bounds__(256) void k_bsr_block_multi(const PcDesc* __restrict__ d, int nd) {
   const PcDesc D = d[pc_seg_blocks(d, nd, blockIdx.x)];
-  bsr_block_body<1>(D.B, D.scale, D.bcol, D.vI, 3 * D.n, D.ld, D.rchunks, blockIdx.x - D.start, D.part);
+  bsr_block_body<1>(D.B, D.scale, D.bcol, D.wI, 3 * D.n, D.nc, D.ld, D.rchunks, blockIdx.x - D.start, D.part);
 }
 
-__global__ __launch_bounds__(256) void k_bsr_sum_multi(const PcDesc* __restrict__ d, int nd, long total) {
+__global__ __launch_bounds__(256) void k_pc_sum_multi(const PcDesc* __restrict__ d, int nd, long total) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= total) return;
   const PcDesc D = d[pc_seg_elems(d, nd, e)];
   const long l = e - D.estart;
   const int n3 = 3 * D.n;
   const int i = (int)(l / n3), row = (int)(l - (long)i * n3);
-  double v = 0.0;
+  double v = D.yI[l];
   for (int b = D.bptr[i]; b < D.bptr[i + 1]; ++b) v += D.part[(size_t)b * n3 + row];
   const int c = row / D.n, x = row - c * D.n;
   D.out[(size_t)c * D.N + (size_t)i * D.n + x] = v;
 }
 
-// out_r[c N + i n + x] = sum of the partials of sphere i's blocks (in block order), row = c n + x.
-__global__ __launch_bounds__(256) void k_bsr_sum(const double* __restrict__ part, const int* __restrict__ bptr,
-                                                 int K, int n, int M, int N, OPtrs out) {
-  const int n3 = 3 * n;
-  const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (long)M * K * n3) return;
-  const int row = (int)(e % n3);
-  const int r = (int)((e / n3) % K);
-  const int i = (int)(e / ((long)n3 * K));
-  double v = 0.0;
-  for (int b = bptr[i]; b < bptr[i + 1]; ++b) v += part[((size_t)b * K + r) * n3 + row];
-  const int c = row / n, x = row - c * n;
-  out.p[r][(size_t)c * N + (size_t)i * n + x] = v;
-}
-
 static unsigned nblocks(long count) { return (unsigned)((count + 255) / 256); }
-
 // ------------------------------------------------------------ near stage only
 
 void pqn_ctx_impl::near_stage(MvGroup& gr, bool from_coef) {
@@ -423,6 +446,21 @@ void pqn_ctx_impl::near_stage(MvGroup& gr, bool from_coef) {
 
 // ----------------------------------------------------------------- set-up
 
+// The application's GEMMs for K = 1 .. kMaxRhs densities, two descriptors each (y = D^{-1} v
+// first, then w = TD v), over the level's fixed buffers: vC columns (r, j) = (r M + j),
+// yI[(j 3n + m) K + r], wI[(j 3L + l) K + r].
+static void build_apply_descs(Precond& pc, int n3, int nc, int M, hipStream_t s) {
+  pc.adesc_h.clear();
+  for (int K = 1; K <= kMaxRhs; ++K) {
+    int blocks = 0;
+    push_gemm(pc.adesc_h, blocks, n3, K * M, n3, pc.Dinv.p, n3, pc.vC.p, n3, pc.yI.p, n3, 0, n3 * K, K, M, 1, 0, 1);
+    pc.aty[K - 1] = blocks;
+    push_gemm(pc.adesc_h, blocks, nc, K * M, n3, pc.TD.p, n3, pc.vC.p, n3, pc.wI.p, nc, 0, nc * K, K, M, 1, 0, 1);
+    pc.atw[K - 1] = blocks - pc.aty[K - 1];
+  }
+  pc.adesc.upload(pc.adesc_h.data(), pc.adesc_h.size(), s);
+}
+
 void pqn_ctx_impl::precond_setup(Level& lv) {
   Precond& pc = lv.pc;
   if (!cfg.precond || pc.epoch == config_epoch) return;
@@ -430,49 +468,65 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
   HIPCHK(hipStreamSynchronize(stream));
   Timer tm;
   hipStream_t s = stream;
-  const int n = lv.n, n3 = 3 * n, M = lv.M, N = lv.N;
-  const size_t nn = (size_t)n3 * n3;
+  const int n = lv.n, n3 = 3 * n, M = lv.M, N = lv.N, L = lv.L, nc = 3 * L;
+  const size_t nn = (size_t)n3 * n3, ncn = (size_t)nc * n3, ncc = (size_t)nc * nc;
   if (!pc.has_d) {
     const SphereBlock& sb = sphere_block_cached(lv.tab);
-    pc.D.upload(sb.D.data(), nn, s);
     pc.Dinv.upload(sb.Dinv.data(), nn, s);
     pc.DinvT.upload(sb.DinvT.data(), nn, s);
-    HIPCHK(hipStreamSynchronize(s));
+    std::vector<double> tt((size_t)n * L);  // T by columns
+    for (int l = 0; l < L; ++l)
+      for (int m = 0; m < n; ++m) tt[(size_t)m * L + l] = lv.tab.T[(size_t)l * n + m];
+    pc.TT.upload(tt.data(), tt.size(), s);
+    // TD(d L + l, :) = sum_x T(l, x) D^{-1}(d n + x, :), row-major
+    pc.TD.alloc(ncn);
+    std::vector<GemmDesc> gd;
+    int ngd = 0;
+    for (int d = 0; d < 3; ++d)
+      push_gemm(gd, ngd, L, n3, n, pc.TT.p, L, pc.DinvT.p + (size_t)d * n, n3, pc.TD.p + (size_t)d * L * n3, L, 0, 1,
+                n3, n3, 0, 1, 1);
+    DescPack dd;
+    const size_t od = dd.add(gd);
+    char* db = push_desc_pack(dd.host);
+    launch_gemm64_multi_big(s, (const GemmDesc*)(db + od), (int)gd.size(), ngd);
+    pc.vC.alloc((size_t)kMaxRhs * M * n3);
+    pc.yI.alloc((size_t)M * n3 * kMaxRhs);
+    pc.wI.alloc((size_t)M * nc * kMaxRhs);
+    build_apply_descs(pc, n3, nc, M, s);
+    HIPCHK(hipStreamSynchronize(s));  // the descriptor staging is reused after this
     pc.has_d = true;
-  }
-  pc.X.alloc((size_t)M * nn);
-  pc.res.alloc((size_t)M * kNsSlices);
-  long total = 0;
-  pc.nbo.assign(M, 0);
-  for (int i = 0; i < M; ++i) {
-    pc.nbo[i] = total;
-    total += (long)h_npart[i] * nn;
   }
   pc.fallback = 0;
   pc.ns_iters = 0;
-  if (total == 0) {
-    // no near pairs: block Jacobi
-    for (int i = 0; i < M; ++i)
-      HIPCHK(hipMemcpyAsync(pc.X.p + (size_t)i * nn, pc.DinvT.p, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
-  } else {
-    pc.NB.alloc((size_t)total);
-    pc.TB.alloc((size_t)total);
-    // Near blocks. The near rule reads a density only through its harmonic coefficients
-    // (coef = T q: the upsampled values and the foot-point expansion), so A_ij = Ac_ij (I3 x T)
-    // with Ac_ij [3n][3L]: Ac from unit coefficient columns through the near stage (3L / 6
-    // passes instead of 3n / 6), then A = Ac (I3 x T) by GEMMs into NB.
-    const int L = lv.L, n3L = 3 * L;
-    std::vector<long> nbco(M);
-    long totc = 0;
-    for (int i = 0; i < M; ++i) {
-      nbco[i] = totc;
-      totc += (long)h_npart[i] * n3 * n3L;
+  pc.aco.assign(M, 0);
+  pc.rro.assign(M, 0);
+  long tota = 0, totr = 0;
+  int nslots = 0;
+  for (int i = 0; i < M; ++i) {
+    pc.aco[i] = tota;
+    pc.rro[i] = totr;
+    tota += (long)h_npart[i] * ncn;
+    totr += (long)h_npart[i] * ncc;
+    nslots += h_npart[i];
+  }
+  // rev[i kMaxNear + s]: the slot of sphere i in the list of its partner in slot s
+  std::vector<int> rev((size_t)M * kMaxNear, -1);
+  for (int i = 0; i < M; ++i)
+    for (int sl = 0; sl < h_npart[i]; ++sl) {
+      const int j = h_partners[(size_t)i * kMaxNear + sl];
+      for (int q = 0; q < h_npart[j]; ++q)
+        if (h_partners[(size_t)j * kMaxNear + q] == i) rev[(size_t)i * kMaxNear + sl] = q;
+      if (rev[(size_t)i * kMaxNear + sl] < 0) throw Error(PQN_ERR_STATE, "internal: near pair list is not symmetric");
     }
-    pc.NBc.alloc((size_t)totc);
-    DevArray<long> dnbco;
-    dnbco.upload(nbco.data(), nbco.size(), s);
-    for (int k0 = 0; k0 < n3L; k0 += kMaxRhs) {
-      const int K = std::min(kMaxRhs, n3L - k0);
+  if (nslots > 0) {
+    pc.Ac.alloc((size_t)tota);
+    pc.Gc.alloc((size_t)tota);
+    pc.Rr.alloc((size_t)totr);
+    DevArray<long> daco;
+    daco.upload(pc.aco.data(), pc.aco.size(), s);
+    // Ac from unit coefficient columns through the near stage (3L / 6 passes)
+    for (int k0 = 0; k0 < nc; k0 += kMaxRhs) {
+      const int K = std::min(kMaxRhs, nc - k0);
       MvGroup g{this, &lv, K, {}, {}, {}};
       OPtrs np{};
       for (int r = 0; r < K; ++r) {
@@ -483,128 +537,107 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
       double* coef = group_coef(g);
       hipLaunchKernelGGL(k_unit_coef, dim3(nblocks((long)M * 3 * K * L)), dim3(256), 0, s, coef, K, k0, L, M);
       near_stage(g, true);
-      hipLaunchKernelGGL(k_nb_scatter, dim3(nblocks((long)M * kMaxNear * n3)), dim3(256), 0, s, np, K, k0, n3L,
-                         npart.p, dnbco.p, n, M, N, pc.NBc.p);
+      hipLaunchKernelGGL(k_nb_scatter, dim3(nblocks((long)M * kMaxNear * n3)), dim3(256), 0, s, np, K, k0, nc,
+                         npart.p, daco.p, n, M, N, pc.Ac.p);
     }
-    {
-      // NB_i(:, s 3n + d n + m) = sum_l Ac_i(:, s 3L + d L + l) T(l, m), T read by columns (TT)
-      if (!pc.TT.p) {
-        std::vector<double> tt((size_t)n * L);
-        for (int l = 0; l < L; ++l)
-          for (int m = 0; m < n; ++m) tt[(size_t)m * L + l] = lv.tab.T[(size_t)l * n + m];
-        pc.TT.upload(tt.data(), tt.size(), s);
-      }
-      std::vector<GemmDesc> gc;
-      int ngc = 0;
-      for (int i = 0; i < M; ++i) {
-        const int ns = h_npart[i];
-        for (int sl = 0; sl < ns; ++sl)
-          for (int d = 0; d < 3; ++d)
-            push_gemm(gc, ngc, n3, n, L, pc.NBc.p + nbco[i] + (size_t)sl * n3L + (size_t)d * L, ns * n3L, pc.TT.p, L,
-                      pc.NB.p + pc.nbo[i] + (size_t)sl * n3 + (size_t)d * n, n3, 0, 1, ns * n3, n, 0, 0, 1);
-      }
-      DescPack dc;
-      const size_t occ = dc.add(gc);
-      char* cb = push_desc_pack(dc.host);
-      launch_gemm64_multi_big(s, (const GemmDesc*)(cb + occ), (int)gc.size(), ngc);
-    }
-    // T_(i,s) = D^{-1} A_(j,s'), j the partner in slot s of i and s' the slot of i in j's list,
-    // stored as TB_i(c, s 3n + m) = T_(i,s)(m, c): computed as C(c, m) = sum_k A_(j,s')(k, c) D^{-1}(m, k)
-    pc.S.alloc((size_t)M * nn);
-    std::vector<GemmDesc> gt, gs;
-    int ngt = 0, ngs = 0;
+    // R: slot s of sphere i holds TD Ac_(j, s'), (j, s') the reverse of (i, s); then
+    // Q_i = sum_s Ac_(i,s) R-slot s over the concatenated slots (a sphere without
+    // partners gets Q_i = 0: a product with no terms writes zeros)
+    pc.Q.alloc((size_t)M * ncn);
+    std::vector<GemmDesc> gr, gq;
+    int ngr = 0, ngq = 0;
     for (int i = 0; i < M; ++i) {
       const int ns = h_npart[i];
-      if (ns == 0) {  // C_i = 0: a product with no terms writes zeros
-        push_gemm(gs, ngs, n3, n3, 0, pc.Dinv.p, n3, pc.Dinv.p, n3, pc.S.p + (size_t)i * nn, n3, 0, 1, n3, n3, 0, 0, 1);
-        continue;
-      }
-      const int ldi = ns * n3;
       for (int sl = 0; sl < ns; ++sl) {
-        const int j = h_partners[(size_t)i * kMaxNear + sl];
-        int sj = -1;
-        for (int q = 0; q < h_npart[j]; ++q)
-          if (h_partners[(size_t)j * kMaxNear + q] == i) sj = q;
-        if (sj < 0) throw Error(PQN_ERR_STATE, "internal: near pair list is not symmetric");
-        const int ldj = h_npart[j] * n3;
-        push_gemm(gt, ngt, n3, n3, n3, pc.NB.p + pc.nbo[j] + (size_t)sj * n3, ldj, pc.Dinv.p, n3,
-                  pc.TB.p + pc.nbo[i] + (size_t)sl * n3, n3, 0, 1, ldi, n3, 0, 1, 1);
+        const int j = h_partners[(size_t)i * kMaxNear + sl], sj = rev[(size_t)i * kMaxNear + sl];
+        push_gemm(gr, ngr, nc, nc, n3, pc.TD.p, n3, pc.Ac.p + pc.aco[j] + (size_t)sj * ncn, n3,
+                  pc.Rr.p + pc.rro[i] + (size_t)sl * nc, nc, 0, ns * nc, 1, nc, 0, 0, 1);
       }
-      // C_i = sum_s A_(i,s) T_(i,s): one product over the concatenated slots, row-major into S_i
-      push_gemm(gs, ngs, n3, n3, ldi, pc.NB.p + pc.nbo[i], ldi, pc.TB.p + pc.nbo[i], ldi, pc.S.p + (size_t)i * nn,
-                n3, 0, 1, n3, n3, 0, 0, 1);
+      push_gemm(gq, ngq, n3, nc, ns * nc, ns ? pc.Ac.p + pc.aco[i] : pc.TD.p, n3, ns ? pc.Rr.p + pc.rro[i] : pc.TD.p,
+                std::max(ns * nc, 1), pc.Q.p + (size_t)i * ncn, n3, 0, n3, 1, nc, 0, 1, 1);
     }
     DescPack dp;
-    const size_t ot = dp.add(gt), os = dp.add(gs);
+    const size_t orr = dp.add(gr), oq = dp.add(gq);
     char* base = push_desc_pack(dp.host);
-    launch_gemm64_multi_big(s, (const GemmDesc*)(base + ot), (int)gt.size(), ngt);
-    launch_gemm64_multi_big(s, (const GemmDesc*)(base + os), (int)gs.size(), ngs);
-    hipLaunchKernelGGL(k_schur_finish, dim3(M * n3), dim3(256), 0, s, pc.D.p, n3, pc.S.p);
-    // Newton-Schulz from X = D^{-1}
-    pc.X2.alloc((size_t)M * nn);
-    pc.W.alloc((size_t)M * nn);
-    for (int i = 0; i < M; ++i)
-      HIPCHK(hipMemcpyAsync(pc.X.p + (size_t)i * nn, pc.DinvT.p, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_gemm64_multi_big(s, (const GemmDesc*)(base + orr), (int)gr.size(), ngr);
+    launch_gemm64_multi_big(s, (const GemmDesc*)(base + oq), (int)gq.size(), ngq);
+    // K_i = I - TD Q_i (by columns)
+    pc.Kc.alloc((size_t)M * ncc);
+    launch_gemm64_big(s, nc, nc, n3, pc.TD.p, n3, 0, pc.Q.p, (long)ncn, n3, pc.Kc.p, (long)ncc, nc, 0, nc, M, 0);
+    hipLaunchKernelGGL(k_diag_minus, dim3(M * nc), dim3(256), 0, s, pc.Kc.p, nc, 1.0);
+    // Newton-Schulz from Y = I
+    pc.Y.alloc((size_t)M * ncc);
+    pc.Y2.alloc((size_t)M * ncc);
+    pc.W.alloc((size_t)M * ncc);
+    pc.res.alloc((size_t)M * kNsSlices);
+    hipLaunchKernelGGL(k_eye, dim3(M * nc), dim3(256), 0, s, pc.Y.p, nc);
     std::vector<double> res(M), resp((size_t)M * kNsSlices);
     for (int step = 0;; ++step) {
-      // W = S X (by columns): C(r, c) = sum_k S(r, k) X(k, c)
-      launch_gemm64_big(s, n3, n3, n3, pc.S.p, n3, (long)nn, pc.X.p, (long)nn, n3, pc.W.p, (long)nn, n3, 0, n3, M, 0);
-      hipLaunchKernelGGL(k_ns_residual, dim3(M * kNsSlices), dim3(256), 0, s, pc.W.p, n3, pc.res.p);
+      // W = K Y: C(r, c) = sum_k K(r, k) Y(k, c), K read by columns
+      launch_gemm64_big(s, nc, nc, nc, pc.Kc.p, nc, (long)ncc, pc.Y.p, (long)ncc, nc, pc.W.p, (long)ncc, nc, 0, nc, M,
+                        1);
+      hipLaunchKernelGGL(k_ns_residual, dim3(M * kNsSlices), dim3(256), 0, s, pc.W.p, nc, pc.res.p);
       HIPCHK(hipMemcpyAsync(resp.data(), pc.res.p, resp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       for (int i = 0; i < M; ++i) {
         double t = 0.0;
         for (int g = 0; g < kNsSlices; ++g) t += resp[(size_t)i * kNsSlices + g];
-        res[i] = t / n3;
+        res[i] = t / nc;
       }
       double worst = 0.0;
       for (double v : res) worst = std::isfinite(v) ? std::max(worst, std::sqrt(v)) : 1e300;
       if (worst <= kNsTol || step == kNsMaxSteps) break;
-      // X <- X (2I - W): C(r, c) = sum_k X(r, k) F(k, c), X read by columns
-      hipLaunchKernelGGL(k_two_minus, dim3(M * n3), dim3(256), 0, s, pc.W.p, n3);
-      launch_gemm64_big(s, n3, n3, n3, pc.X.p, n3, (long)nn, pc.W.p, (long)nn, n3, pc.X2.p, (long)nn, n3, 0, n3, M, 1);
-      std::swap(pc.X.p, pc.X2.p);
+      // Y <- Y (2I - W): C(r, c) = sum_k Y(r, k) F(k, c), Y read by columns
+      hipLaunchKernelGGL(k_diag_minus, dim3(M * nc), dim3(256), 0, s, pc.W.p, nc, 2.0);
+      launch_gemm64_big(s, nc, nc, nc, pc.Y.p, nc, (long)ncc, pc.W.p, (long)ncc, nc, pc.Y2.p, (long)ncc, nc, 0, nc, M,
+                        1);
+      std::swap(pc.Y.p, pc.Y2.p);
       ++pc.ns_iters;
     }
     for (int i = 0; i < M; ++i)
       if (!(std::sqrt(res[i]) <= kNsKeep)) {
-        HIPCHK(hipMemcpyAsync(pc.X.p + (size_t)i * nn, pc.DinvT.p, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemsetAsync(pc.Y.p + (size_t)i * ncc, 0, ncc * sizeof(double), s));
         ++pc.fallback;
       }
-    // G_(i,s) = X_i A_(i,s) D^{-1}: H = A_(i,s) D^{-1} by columns into TB (slot s at s (3n)^2),
-    // then G = X_i H by columns into NB (the near blocks are no longer needed)
-    std::vector<GemmDesc> gh, gg;
-    int ngh = 0, ngg = 0;
-    for (int i = 0; i < M; ++i) {
-      const int ns = h_npart[i];
-      const int ldi = ns * n3;
-      for (int sl = 0; sl < ns; ++sl) {
-        push_gemm(gh, ngh, n3, n3, n3, pc.NB.p + pc.nbo[i] + (size_t)sl * n3, ldi, pc.DinvT.p, n3,
-                  pc.TB.p + pc.nbo[i] + (size_t)sl * nn, n3, 0, n3, 1, n3, 0, 0, 1);
-        push_gemm(gg, ngg, n3, n3, n3, pc.X.p + (size_t)i * nn, n3, pc.TB.p + pc.nbo[i] + (size_t)sl * nn, n3,
-                  pc.NB.p + pc.nbo[i] + (size_t)sl * nn, n3, 0, n3, 1, n3, 0, 1, 1);
+    // Z = D^{-1} Q_i, E_i = Z_i Y_i (by columns)
+    pc.Z.alloc((size_t)M * ncn);
+    pc.E.alloc((size_t)M * ncn);
+    launch_gemm64_big(s, n3, nc, n3, pc.Dinv.p, n3, 0, pc.Q.p, (long)ncn, n3, pc.Z.p, (long)ncn, n3, 0, n3, M, 0);
+    launch_gemm64_big(s, n3, nc, nc, pc.Z.p, n3, (long)ncn, pc.Y.p, (long)ncc, nc, pc.E.p, (long)ncn, n3, 0, n3, M, 1);
+    // Gc_(i,s) = D^{-1} Ac_(i,s), then += E_i R_(i,s); R_(i,s) = TD Ac_(i,s) is slot s' of
+    // partner j's R
+    std::vector<GemmDesc> ga, gb;
+    int nga = 0, ngb = 0;
+    for (int i = 0; i < M; ++i)
+      for (int sl = 0; sl < h_npart[i]; ++sl) {
+        const int j = h_partners[(size_t)i * kMaxNear + sl], sj = rev[(size_t)i * kMaxNear + sl];
+        double* gcb = pc.Gc.p + pc.aco[i] + (size_t)sl * ncn;
+        push_gemm(ga, nga, n3, nc, n3, pc.Dinv.p, n3, pc.Ac.p + pc.aco[i] + (size_t)sl * ncn, n3, gcb, n3, 0, n3, 1,
+                  nc, 0, 0, 1);
+        push_gemm(gb, ngb, n3, nc, nc, pc.E.p + (size_t)i * ncn, n3, pc.Rr.p + pc.rro[j] + (size_t)sj * nc,
+                  h_npart[j] * nc, gcb, n3, 0, n3, 1, nc, 0, 1 | 2, 1);
       }
-    }
     DescPack dq;
-    const size_t oh = dq.add(gh), og = dq.add(gg);
+    const size_t oa = dq.add(ga), ob = dq.add(gb);
     char* qb = push_desc_pack(dq.host);
-    launch_gemm64_multi_big(s, (const GemmDesc*)(qb + oh), (int)gh.size(), ngh);
-    launch_gemm64_multi_big(s, (const GemmDesc*)(qb + og), (int)gg.size(), ngg);
-    HIPCHK(hipStreamSynchronize(s));  // dnbco and the descriptor tables are released/reused after this
+    launch_gemm64_multi_big(s, (const GemmDesc*)(qb + oa), (int)ga.size(), nga);
+    launch_gemm64_multi_big(s, (const GemmDesc*)(qb + ob), (int)gb.size(), ngb);
+    HIPCHK(hipStreamSynchronize(s));  // daco and the descriptor tables are released/reused after this
   }
-  // block rows in FP16: sphere i holds S_i^{-1} (or D^{-1}) then G_(i,s) for its slots
+  // block rows in FP16: sphere i (if it has near partners) holds E_i, then -Gc_(i,s) for its slots
   {
     std::vector<int> bp(M + 1, 0), bc;
     std::vector<const double*> src;
     std::vector<double> sg;
     for (int i = 0; i < M; ++i) {
       bp[i] = (int)bc.size();
+      if (h_npart[i] == 0) continue;
       bc.push_back(i);
-      src.push_back(pc.X.p + (size_t)i * nn);
+      src.push_back(pc.E.p + (size_t)i * ncn);
       sg.push_back(1.0);
       for (int sl = 0; sl < h_npart[i]; ++sl) {
         bc.push_back(h_partners[(size_t)i * kMaxNear + sl]);
-        src.push_back(pc.NB.p + pc.nbo[i] + (size_t)sl * nn);
+        src.push_back(pc.Gc.p + pc.aco[i] + (size_t)sl * ncn);
         sg.push_back(-1.0);
       }
     }
@@ -612,18 +645,21 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
     const long nb = (long)bc.size();
     pc.nblk = (int)nb;
     pc.ld = (n3 + 63) / 64 * 64;
-    pc.B16.alloc((size_t)nb * n3 * pc.ld);
-    pc.bscale.alloc((size_t)nb);
     pc.bptr.upload(bp.data(), bp.size(), s);
-    pc.bcol.upload(bc.data(), bc.size(), s);
-    DevArray<const double*> dsrc;
-    DevArray<double> dsg;
-    dsrc.upload(src.data(), src.size(), s);
-    dsg.upload(sg.data(), sg.size(), s);
-    hipLaunchKernelGGL(k_block_absmax, dim3(nb), dim3(256), 0, s, dsrc.p, (long)nn, pc.bscale.p);
-    hipLaunchKernelGGL(k_blocks_f16, dim3(nblocks(nb * (long)n3 * pc.ld)), dim3(256), 0, s, dsrc.p, dsg.p,
-                       pc.bscale.p, n3, pc.ld, nb, pc.B16.p);
-    HIPCHK(hipStreamSynchronize(s));  // dsrc is released after this
+    if (nb > 0) {
+      pc.B16.alloc((size_t)nb * nc * pc.ld);
+      pc.bscale.alloc((size_t)nb);
+      pc.bcol.upload(bc.data(), bc.size(), s);
+      pc.part.alloc((size_t)nb * kMaxRhs * n3);
+      DevArray<const double*> dsrc;
+      DevArray<double> dsg;
+      dsrc.upload(src.data(), src.size(), s);
+      dsg.upload(sg.data(), sg.size(), s);
+      hipLaunchKernelGGL(k_block_absmax, dim3(nb), dim3(256), 0, s, dsrc.p, (long)ncn, pc.bscale.p);
+      hipLaunchKernelGGL(k_blocks_f16, dim3(nblocks(nb * (long)nc * pc.ld)), dim3(256), 0, s, dsrc.p, dsg.p,
+                         pc.bscale.p, n3, nc, pc.ld, nb, pc.B16.p);
+    }
+    HIPCHK(hipStreamSynchronize(s));  // dsrc and the host tables are released after this
   }
   HIPCHK(hipGetLastError());
   pc.epoch = config_epoch;
@@ -646,7 +682,8 @@ void pqn_ctx_impl::precond_apply_groups(std::vector<MvGroup>& groups) {
   }
   hipStream_t s = stream;
   std::vector<PcDesc> pd;
-  int wg = 0;
+  std::vector<GemmDesc> gd;
+  int wg = 0, ngd = 0;
   long el = 0;
   for (MvGroup& gr : groups) {
     pqn_ctx_impl& c = *gr.c;
@@ -654,22 +691,29 @@ void pqn_ctx_impl::precond_apply_groups(std::vector<MvGroup>& groups) {
     Precond& pc = lv.pc;
     if (pc.epoch != c.config_epoch) throw Error(PQN_ERR_STATE, "internal: preconditioner not set up");
     const int n3 = 3 * lv.n;
-    pc.vI.alloc((size_t)lv.M * n3 * kMaxRhs);
-    pc.part.alloc((size_t)pc.nblk * kMaxRhs * n3);
     const int rchunks = (n3 + 255) / 256;
-    pd.push_back(PcDesc{pc.B16.p, pc.bscale.p, pc.bcol.p, pc.bptr.p, gr.in[0], gr.out[0], pc.vI.p, pc.part.p, lv.n,
-                        lv.N, lv.M, pc.ld, rchunks, wg, el});
+    pd.push_back(PcDesc{pc.B16.p, pc.bscale.p, pc.bcol.p, pc.bptr.p, gr.in[0], gr.out[0], pc.vC.p, pc.wI.p, pc.yI.p,
+                        pc.part.p, lv.n, lv.N, lv.M, 3 * lv.L, pc.ld, rchunks, wg, el});
     wg += pc.nblk * rchunks;
     el += (long)lv.M * n3;
+    // the suspension's K = 1 GEMMs (y, then w when it has blocks), shifted to this launch
+    for (int q = 0; q < (pc.nblk > 0 ? 2 : 1); ++q) {
+      GemmDesc d = pc.adesc_h[q];
+      d.start = ngd;
+      ngd += q == 0 ? pc.aty[0] : pc.atw[0];
+      gd.push_back(d);
+    }
   }
   DescPack dp;
-  const size_t od = dp.add(pd);
-  const PcDesc* dd = (const PcDesc*)(push_desc_pack(dp.host) + od);
+  const size_t od = dp.add(pd), og = dp.add(gd);
+  char* base = push_desc_pack(dp.host);
+  const PcDesc* dd = (const PcDesc*)(base + od);
   const int nd = (int)pd.size();
   stage_begin(kStagePrecond);
-  hipLaunchKernelGGL(k_pc_interleave_multi, dim3(nblocks(el)), dim3(256), 0, s, dd, nd, el);
-  hipLaunchKernelGGL(k_bsr_block_multi, dim3(wg), dim3(256), 0, s, dd, nd);
-  hipLaunchKernelGGL(k_bsr_sum_multi, dim3(nblocks(el)), dim3(256), 0, s, dd, nd, el);
+  hipLaunchKernelGGL(k_pc_gather_multi, dim3(nblocks(el)), dim3(256), 0, s, dd, nd, el);
+  launch_gemm64_multi_big(s, (const GemmDesc*)(base + og), (int)gd.size(), ngd);
+  if (wg > 0) hipLaunchKernelGGL(k_bsr_block_multi, dim3(wg), dim3(256), 0, s, dd, nd);
+  hipLaunchKernelGGL(k_pc_sum_multi, dim3(nblocks(el)), dim3(256), 0, s, dd, nd, el);
   stage_end(kStagePrecond);
   ++pc_applies;
 }
@@ -679,8 +723,7 @@ void pqn_ctx_impl::precond_apply(MvGroup& gr) {
   Precond& pc = lv.pc;
   if (pc.epoch != config_epoch) throw Error(PQN_ERR_STATE, "internal: preconditioner not set up");
   hipStream_t s = stream;
-  const int n = lv.n, n3 = 3 * n, M = lv.M, N = lv.N, K = gr.K;
-  pc.vI.alloc((size_t)M * n3 * kMaxRhs);
+  const int n = lv.n, n3 = 3 * n, nc = 3 * lv.L, M = lv.M, N = lv.N, K = gr.K;
   QPtrs vin{};
   OPtrs out{};
   for (int r = 0; r < K; ++r) {
@@ -688,24 +731,28 @@ void pqn_ctx_impl::precond_apply(MvGroup& gr) {
     out.p[r] = gr.out[r];
   }
   stage_begin(kStagePrecond);
-  hipLaunchKernelGGL(k_pc_interleave, dim3(nblocks((long)M * n3 * K)), dim3(256), 0, s, vin, K, n, M, N, pc.vI.p);
-  const int rchunks = (n3 + 255) / 256;
-  const dim3 g(pc.nblk * rchunks);
-  pc.part.alloc((size_t)pc.nblk * kMaxRhs * n3);
+  hipLaunchKernelGGL(k_pc_gather, dim3(nblocks((long)K * M * n3)), dim3(256), 0, s, vin, K, n, M, N, pc.vC.p);
+  // y = D^{-1} v and (with blocks) w = TD v; out may be the input: v is not read after the gather
+  launch_gemm64_multi_big(s, pc.adesc.p + 2 * (K - 1), pc.nblk > 0 ? 2 : 1,
+                          pc.aty[K - 1] + (pc.nblk > 0 ? pc.atw[K - 1] : 0));
+  if (pc.nblk > 0) {
+    const int rchunks = (n3 + 255) / 256;
+    const dim3 g(pc.nblk * rchunks);
 #define BSRK(KK) \
-  hipLaunchKernelGGL(k_bsr_block<KK>, g, dim3(256), 0, s, pc.B16.p, pc.bscale.p, pc.bcol.p, pc.vI.p, n3, pc.ld, \
+  hipLaunchKernelGGL(k_bsr_block<KK>, g, dim3(256), 0, s, pc.B16.p, pc.bscale.p, pc.bcol.p, pc.wI.p, n3, nc, pc.ld, \
                      rchunks, pc.part.p)
-  switch (K) {
-    case 1: BSRK(1); break;
-    case 2: BSRK(2); break;
-    case 3: BSRK(3); break;
-    case 4: BSRK(4); break;
-    case 5: BSRK(5); break;
-    default: BSRK(6); break;
-  }
+    switch (K) {
+      case 1: BSRK(1); break;
+      case 2: BSRK(2); break;
+      case 3: BSRK(3); break;
+      case 4: BSRK(4); break;
+      case 5: BSRK(5); break;
+      default: BSRK(6); break;
+    }
 #undef BSRK
-  hipLaunchKernelGGL(k_bsr_sum, dim3(nblocks((long)M * K * n3)), dim3(256), 0, s, pc.part.p, pc.bptr.p, K, n, M, N,
-                     out);
+  }
+  hipLaunchKernelGGL(k_pc_sum, dim3(nblocks((long)M * K * n3)), dim3(256), 0, s, pc.yI.p, pc.part.p, pc.bptr.p, K, n,
+                     M, N, out);
   stage_end(kStagePrecond);
   ++pc_applies;
 }
