@@ -446,9 +446,10 @@ void pqn_ctx_impl::near_stage(MvGroup& gr, bool from_coef) {
 
 // ----------------------------------------------------------------- set-up
 
-// The application's GEMMs for K = 1 .. kMaxRhs densities, two descriptors each (y = D^{-1} v
-// first, then w = TD v), over the level's fixed buffers: vC columns (r, j) = (r M + j),
-// yI[(j 3n + m) K + r], wI[(j 3L + l) K + r].
+// The application's GEMMs for K = 1 .. kMaxRhs densities over the level's fixed buffers
+// (vC columns (r, j) = (r M + j), yI[(j 3n + m) K + r], wI[(j 3L + l) K + r]), three
+// descriptors each: y = D^{-1} v and w = TD v for one launch, and w alone (for a launch
+// of its own while y runs on the side stream).
 static void build_apply_descs(Precond& pc, int n3, int nc, int M, hipStream_t s) {
   pc.adesc_h.clear();
   for (int K = 1; K <= kMaxRhs; ++K) {
@@ -457,6 +458,8 @@ static void build_apply_descs(Precond& pc, int n3, int nc, int M, hipStream_t s)
     pc.aty[K - 1] = blocks;
     push_gemm(pc.adesc_h, blocks, nc, K * M, n3, pc.TD.p, n3, pc.vC.p, n3, pc.wI.p, nc, 0, nc * K, K, M, 1, 0, 1);
     pc.atw[K - 1] = blocks - pc.aty[K - 1];
+    blocks = 0;
+    push_gemm(pc.adesc_h, blocks, nc, K * M, n3, pc.TD.p, n3, pc.vC.p, n3, pc.wI.p, nc, 0, nc * K, K, M, 1, 0, 1);
   }
   pc.adesc.upload(pc.adesc_h.data(), pc.adesc_h.size(), s);
 }
@@ -732,9 +735,21 @@ void pqn_ctx_impl::precond_apply(MvGroup& gr) {
   }
   stage_begin(kStagePrecond);
   hipLaunchKernelGGL(k_pc_gather, dim3(nblocks((long)K * M * n3)), dim3(256), 0, s, vin, K, n, M, N, pc.vC.p);
-  // y = D^{-1} v and (with blocks) w = TD v; out may be the input: v is not read after the gather
-  launch_gemm64_multi_big(s, pc.adesc.p + 2 * (K - 1), pc.nblk > 0 ? 2 : 1,
-                          pc.aty[K - 1] + (pc.nblk > 0 ? pc.atw[K - 1] : 0));
+  // y = D^{-1} v and (with blocks) w = TD v; out may be the input: v is not read after the
+  // gather. With the side stream on, y (matrix cores) runs there beside the block product
+  // (HBM), and the sum waits for both.
+  const GemmDesc* ad = pc.adesc.p + 3 * (K - 1);
+  const bool ov = cfg.side_stream && !cfg.profile && pc.nblk > 0;
+  if (ov) {
+    hipStream_t sa = side_stream();
+    HIPCHK(hipEventRecord(ev_in, s));
+    HIPCHK(hipStreamWaitEvent(sa, ev_in, 0));
+    launch_gemm64_multi_big(sa, ad, 1, pc.aty[K - 1]);
+    HIPCHK(hipEventRecord(ev_side, sa));
+    launch_gemm64_multi_big(s, ad + 2, 1, pc.atw[K - 1]);
+  } else {
+    launch_gemm64_multi_big(s, ad, pc.nblk > 0 ? 2 : 1, pc.aty[K - 1] + (pc.nblk > 0 ? pc.atw[K - 1] : 0));
+  }
   if (pc.nblk > 0) {
     const int rchunks = (n3 + 255) / 256;
     const dim3 g(pc.nblk * rchunks);
@@ -751,6 +766,7 @@ void pqn_ctx_impl::precond_apply(MvGroup& gr) {
     }
 #undef BSRK
   }
+  if (ov) HIPCHK(hipStreamWaitEvent(s, ev_side, 0));
   hipLaunchKernelGGL(k_pc_sum, dim3(nblocks((long)M * K * n3)), dim3(256), 0, s, pc.yI.p, pc.part.p, pc.bptr.p, K, n,
                      M, N, out);
   stage_end(kStagePrecond);

@@ -212,3 +212,25 @@ def test_precond_on_reuse_counts_a_refined_solve_once(tiny_cases):
         s2['t_precond_ms'])
     assert s1['t_precond_ms'] == 0 and s1['precond_applies'] == 0
     assert s2['t_precond_ms'] > 0 and s2['precond_applies'] > 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_side_stream_preconditioned_is_bit_identical(prec):
+    """With the side stream on, the preconditioner's D^-1 v GEMM runs there beside the
+    block product: K = 1 and 6 densities reproduce the one-stream context bit for bit
+    (same kernels, same sums; the final sum waits for both streams)."""
+    w = inputs.workload('lattice27', 1)
+    c = w['centers']
+    out = {}
+    for side in (False, True):
+        with binding.Context(c, None, 8, 16, precision=prec, gmres_tol=1e-10, side_stream=side,
+                             precond='eager') as ctx:
+            r = []
+            for K in (1, 6):
+                U, st = ctx.mobility_apply_multi(inputs.random_forces(30 + K, c.shape[0], k=K))
+                assert st['converged'] == 1 and st['precond_applies'] > 0
+                r.append(U)
+            out[side] = r
+    say('side stream precond', prec, 'equal', [np.array_equal(a, b) for a, b in zip(out[False], out[True])])
+    for a, b in zip(out[False], out[True]):
+        assert np.array_equal(a, b)
