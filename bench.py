@@ -116,6 +116,10 @@ def main():
     ap.add_argument('--no-precond', action='store_true',
                     help='plain GMRES everywhere (default: the near-patch preconditioner on every '
                          'single-suspension context; the headline is also measured without it)')
+    ap.add_argument('--no-coarse', action='store_true',
+                    help='one-level preconditioner (default: two levels, a coarse correction on every '
+                         "sphere's degree <= 2 harmonics before the near patches, on every preconditioned "
+                         'single-suspension context; the headline is also measured with one level)')
     ap.add_argument('--serial', action='store_true',
                     help='one stream everywhere (no side stream beside the far pair sum): every kernel runs '
                          'alone, as in the profiles of individual kernels')
@@ -164,19 +168,21 @@ def main():
     # (the MVP passes and LCP solves), when a configuration is solved a second time in the
     # time steps (a step without contacts solves once and never pays for the set-up)
     PC_FIXED = 'eager' if PC else False
+    PC_COARSE = PC and not args.no_coarse
 
-    def ctx_for(prec, kr=K_RHS, profile=True, warm_start=False, side=None, precond=None):
+    def ctx_for(prec, kr=K_RHS, profile=True, warm_start=False, side=None, precond=None, coarse=None):
         """Context with the launch layout tuned for kr densities per pass (unless fixed on the command line).
         side: run the GEMM / near / moment work on a second stream beside the far pair sum (default: for the
         mixed path, where it measured 5-7% faster; the FP64 K = 6 pass was 2.5% slower with it). Profiled
         contexts time the far kernel alone and keep one stream. precond: right-preconditioned GMRES
-        (default: on unless --no-precond)."""
+        (default: on unless --no-precond); coarse: its two-level form (default: on unless --no-coarse)."""
         if side is None:
             side = prec == 'mixed' and not profile and not args.serial
         return binding.Context(c, None, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision=prec, tpt=args.tpt,
                                far_chunks=args.chunks, far_split=args.split, stream=stream.cuda_stream,
                                profile=profile, tune_K=kr, warm_start=warm_start, side_stream=side,
-                               precond=PC_FIXED if precond is None else precond)
+                               precond=PC_FIXED if precond is None else precond,
+                               precond_coarse=PC_COARSE if coarse is None else coarse)
 
     FT6 = [inputs.random_forces(100 + k, M, k=K_RHS) for k in range(max(K, 2) + W + 2)]
     # the timed products read forces from and write velocities to HBM (no host copies)
@@ -184,7 +190,7 @@ def main():
     UO_dev = torch.empty((K_RHS, M, 6), dtype=torch.float64, device=dev)
 
     if args.lcp_table:
-        print(json.dumps(lcp_table(binding, inputs, stream, precond=PC_FIXED)), flush=True)
+        print(json.dumps(lcp_table(binding, inputs, stream, precond=PC_FIXED, coarse=PC_COARSE)), flush=True)
         return
 
     if args.cpu_table:
@@ -278,6 +284,11 @@ def main():
     with ctx_for('mixed', profile=False, precond=False) as cpl:
         plain6 = run_multi(cpl, K, W, K_RHS)
     log('mixed K=6 plain GMRES', plain6)
+    one6 = None
+    if PC_COARSE:  # and with the one-level preconditioner
+        with ctx_for('mixed', profile=False, coarse=False) as cpo:
+            one6 = run_multi(cpo, K, W, K_RHS)
+        log('mixed K=6 one-level preconditioner', one6)
     cf = ctx_for('fp64')
     res['fp64_6'] = run_multi(cf, max(1, K // 3), 1, K_RHS)
     log('fp64 K=6', res['fp64_6'], cf.far_shape)
@@ -312,7 +323,8 @@ def main():
         # and recursive Bi-PQN over three fidelities: that model, then the coarse grid at 1e-3
         with binding.Context(c, None, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3, lo2=w['lo'],
                              gmres_tol_lo2=1e-3, precision='mixed', tpt=args.tpt, far_chunks=args.chunks,
-                             far_split=args.split, stream=stream.cuda_stream, tune_K=1, precond=PC_FIXED) as cb:
+                             far_split=args.split, stream=stream.cuda_stream, tune_K=1, precond=PC_FIXED,
+                             precond_coarse=PC_COARSE) as cb:
             t3 = time.perf_counter()
             x4, lt = cb.lcp_solve(pairs, b, 'bi')
             t4 = time.perf_counter()
@@ -325,7 +337,8 @@ def main():
             with binding.Context(c, None, nt, nph, lo=(nt, nph), far_coarse_lo=6, gmres_tol=1e-8,
                                  gmres_tol_lo=tol_lo, precision='mixed', tpt=args.tpt, far_chunks=args.chunks,
                                  far_split=args.split, stream=stream.cuda_stream, tune_K=1,
-                                 side_stream=not args.serial, precond=PC_FIXED) as ccf:
+                                 side_stream=not args.serial, precond=PC_FIXED,
+                                 precond_coarse=PC_COARSE) as ccf:
                 ccf.lcp_solve(pairs, b, 'bi')       # the coarse-grid tables and buffers warm
                 torch.cuda.synchronize()
                 t0c = time.perf_counter()
@@ -367,7 +380,7 @@ def main():
         tight = dict(kkt_tol_abs=1e-10, gmres_tol=1e-10, b_from='FP64 product at GMRES 1e-12')
         xe = lambda x_: float(np.abs(x_ - xs).max() / np.abs(xs).max())
         kw_t = dict(lo=w['lo'], tpt=args.tpt, far_chunks=args.chunks, far_split=args.split,
-                    stream=stream.cuda_stream, tune_K=1, precond=PC_FIXED)
+                    stream=stream.cuda_stream, tune_K=1, precond=PC_FIXED, precond_coarse=PC_COARSE)
         with binding.Context(c, None, nt, nph, precision='fp64', gmres_tol=1e-12, **kw_t) as cref:
             b_t = ws - cref.lcp_apply(pairs, xs)
         with binding.Context(c, None, nt, nph, precision='fp64', gmres_tol=1e-10, **kw_t) as cf64, \
@@ -434,7 +447,7 @@ def main():
             with binding.Context(c, None, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='mixed', refine=refine,
                                  tpt=args.tpt, far_chunks=args.chunks, far_split=args.split,
                                  stream=stream.cuda_stream, tune_K=1, warm_start=True,
-                                 side_stream=not args.serial, precond=PC) as cs:
+                                 side_stream=not args.serial, precond=PC, precond_coarse=PC_COARSE) as cs:
                 for k in range(nsteps):
                     cs.set_state(*states[k])
                     torch.cuda.synchronize()
@@ -568,7 +581,8 @@ def main():
         'gmres_iters_per_mvp': {k: round(v['gmres_iters'], 2) for k, v in res.items()},
         'far_kernel_ms': {k: round(v['far_ms'], 4) for k, v in res.items()},
         'precond': None if not PC else {
-            'kind': 'near-patch Schur complements, right preconditioning (config precond)',
+            'kind': 'near-patch Schur complements, right preconditioning (config precond)'
+                    + (', with a coarse correction on degree <= 2 harmonics (precond_coarse)' if PC_COARSE else ''),
             'setup_ms': round(m6['precond_setup_ms'], 1),
             'setup_ms_in_timed_region': round(m6['precond_setup_in_timed_ms'], 1),
             'apply_ms_k6': round(prof6['precond_apply_ms'], 4),
@@ -577,6 +591,11 @@ def main():
             'block_bytes': precond_bytes(n, nt * nt, pc_blocks(c)),
             'plain_gmres': {'mvps': round(plain6['mvps'], 4), 'gmres_iters_per_mvp': round(plain6['gmres_iters'], 2),
                             'ms_per_step': round(1e3 * plain6['sec'] / plain6['steps'], 3)},
+            'levels': 2 if PC_COARSE else 1,
+            'one_level': None if one6 is None else {
+                'mvps': round(one6['mvps'], 4), 'gmres_iters_per_mvp': round(one6['gmres_iters'], 2),
+                'ms_per_step': round(1e3 * one6['sec'] / one6['steps'], 3),
+                'setup_ms': round(one6['precond_setup_ms'], 1)},
             'speedup_vs_plain': round(m6['mvps'] / plain6['mvps'], 3)},
         'roofline': {'bound': 'alu', 'kernel': far_kernel_name(cm_layout, K_RHS), 'achieved': round(achieved, 3),
                      'peak': PEAK_FP32_VECTOR, 'unit': 'TFLOP/s', 'frac': round(achieved / PEAK_FP32_VECTOR, 4),
@@ -613,9 +632,10 @@ def contact_steps(binding, inputs, torch, stream, w, args, replay_solvers=True):
     try:
         states_in, rows = [(c, ax_in)], []
         pc = not getattr(args, 'no_precond', False)
+        pcc = pc and not getattr(args, 'no_coarse', False)
         with binding.Context(c, ax_in, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='fp64', tune_K=1,
                              warm_start=True, near_close_gap=0.02, near_close_up=3,
-                             stream=stream.cuda_stream, precond=pc) as cs:
+                             stream=stream.cuda_stream, precond=pc, precond_coarse=pcc) as cs:
             for _ in range(nin):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -642,7 +662,8 @@ def contact_steps(binding, inputs, torch, stream, w, args, replay_solvers=True):
 
         with binding.Context(c, ax_in, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='mixed', tune_K=1,
                              warm_start=True, near_close_gap=0.02, near_close_up=3,
-                             stream=stream.cuda_stream, side_stream=not args.serial, precond=pc) as cs:
+                             stream=stream.cuda_stream, side_stream=not args.serial, precond=pc,
+                             precond_coarse=pcc) as cs:
             for k in range(nin):
                 cs.set_state(*states_in[k])
                 torch.cuda.synchronize()
@@ -664,7 +685,7 @@ def contact_steps(binding, inputs, torch, stream, w, args, replay_solvers=True):
                 with binding.Context(c, ax_in, nt, nph, lo=(nt, nph), gmres_tol=1e-8, gmres_tol_lo=1e-3,
                                      precision='mixed', tune_K=1, warm_start=True, near_close_gap=0.02,
                                      near_close_up=3, stream=stream.cuda_stream, side_stream=not args.serial,
-                                     precond=pc, **kw_lo) as cs:
+                                     precond=pc, precond_coarse=pcc, **kw_lo) as cs:
                     replay(cs, 'bi', name, active_k)
         inward_info = dict(steps=nin, dt=dt_in, near_close_gap=0.02, near_close_up=3,
                            precond='on reuse' if pc else 'off',
@@ -685,7 +706,7 @@ def contact_steps(binding, inputs, torch, stream, w, args, replay_solvers=True):
     return inward_info
 
 
-def lcp_table(binding, inputs, stream, precond=False):
+def lcp_table(binding, inputs, stream, precond=False, coarse=False):
     """Products per planted LCP (about half the contacts active, KKT 1e-8) for the solvers of
     the method on the contact sets (gap < 0.1) of three workloads, mixed precision: BB-PGD,
     Mono-PQN and Bi-PQN with the coarse grid as low fidelity (each PQN solver with the scaled
@@ -704,7 +725,8 @@ def lcp_table(binding, inputs, stream, precond=False):
             c, nt, nph = w['centers'], w['n_theta'], w['n_phi']
             row = dict(workload=name, seed=seed)
             with binding.Context(c, None, nt, nph, lo=w['lo'], gmres_tol=1e-8, precision='mixed',
-                                 stream=stream.cuda_stream, tune_K=1, precond=precond) as ctx:
+                                 stream=stream.cuda_stream, tune_K=1, precond=precond,
+                                 precond_coarse=coarse) as ctx:
                 pairs, _ = ctx.find_contacts(0.1)
                 if pairs.shape[0] == 0:
                     continue
@@ -728,7 +750,8 @@ def lcp_table(binding, inputs, stream, precond=False):
                                                    gmres_tol_lo2=1e-3)))
             for key, solver, kw_lo in variants:
                 with binding.Context(c, None, nt, nph, lo=(nt, nph), gmres_tol=1e-8, precision='mixed',
-                                     stream=stream.cuda_stream, tune_K=1, precond=precond, **kw_lo) as ctx:
+                                     stream=stream.cuda_stream, tune_K=1, precond=precond,
+                                     precond_coarse=coarse, **kw_lo) as ctx:
                     if key.startswith('bi_cf') or precond:
                         ctx.lcp_solve(pairs, b, solver)     # warm the buffers (and build the preconditioners)
                     torch.cuda.synchronize()

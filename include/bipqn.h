@@ -135,6 +135,17 @@ typedef struct {
                                values after it. In a batch context each suspension has its own (built at
                                the same points; its GMRES iterations then run eagerly, not from
                                captured graphs) [0] */
+  int32_t precond_coarse;   /* with precond: 1 = two levels. A coarse correction on every sphere's
+                               harmonics of degree <= 2 (27 unknowns per sphere) is applied before
+                               the near-patch preconditioner P_f: z1 = Z inv(E) R v,
+                               z = z1 + P_f (v - A~ z1), E = R A~ Z, R the projection on those
+                               harmonics, Z their synthesis, A~ the operator with its far pairs
+                               summed on a coarse source grid (n_theta / 2 rows, at least 3):
+                               the far field's smooth low modes, which the near patches cannot
+                               reach, are solved for directly. Built with the rest of the
+                               preconditioner; inv(E) by Newton-Schulz, stored in FP32 (about
+                               4 (27 M)^2 doubles during the set-up). Not for batch contexts
+                               (PQN_ERR_INVALID) [0] */
 } pqn_config_desc;
 
 typedef struct {

@@ -566,6 +566,56 @@ def near_patch_preconditioner(geom, A):
     return apply
 
 
+def two_level_preconditioner(geom, A, P, lmax=2, coarse_theta=None):
+    """Two-level right preconditioner: a coarse correction on every sphere's
+    harmonics of degree <= lmax (3 (lmax + 1)^2 unknowns per sphere) applied
+    before the near-patch preconditioner P (Sec. 2 leaves the preconditioner
+    open; the far field's smooth low modes are what the near patches miss):
+        c = E^{-1} R v,  z1 = Z c,  P2 v = z1 + P (v - A~ z1),  E = R A~ Z,
+    with Z the synthesis of those harmonics at the nodes (per sphere and
+    component), R the projection on them (quadrature-weighted analysis, R Z = I)
+    and A~ the operator with its far pairs summed on a coarse source grid of
+    coarse_theta x 2 coarse_theta nodes (far_coarse_rule; None: A~ = A). The
+    near and self blocks of A~ are A's. Returns P2 as a function of a flat
+    node-major vector. Pinned by: for one sphere P2 = A^{-1} when P is; and
+    P2 (A~ Z c) = Z c for every coarse vector c, whatever P
+    (tests/test_oracle_bie.py).
+    """
+    n, M = geom.n, geom.M
+    th, ph = _grid.grid_angles(geom.n_theta, geom.n_phi)
+    _, _, w_unit = _grid.sphere_grid(geom.n_theta, geom.n_phi, 1.0)
+    Y = _grid.real_sh(lmax, th, ph)                      # (n, nl)
+    nl = Y.shape[1]
+    nb = 3 * nl
+    Zb = np.zeros((3 * n, nb))
+    Rb = np.zeros((nb, 3 * n))
+    for c in range(3):
+        for k in range(nl):
+            Zb[np.arange(n) * 3 + c, c * nl + k] = Y[:, k]
+            Rb[c * nl + k, np.arange(n) * 3 + c] = Y[:, k] * w_unit
+    Z = np.zeros((3 * geom.N, M * nb))
+    R = np.zeros((M * nb, 3 * geom.N))
+    for i in range(M):
+        Z[i * 3 * n:(i + 1) * 3 * n, i * nb:(i + 1) * nb] = Zb
+        R[i * nb:(i + 1) * nb, i * 3 * n:(i + 1) * 3 * n] = Rb
+    if coarse_theta is None:
+        At = A
+    else:
+        gc = Geometry(geom.c, geom.a, geom.n_theta, geom.n_phi, geom.mu, near_gap=geom.near_gap,
+                      near_up=geom.near_up, near_close_gap=geom.near_close_gap,
+                      near_close_up=geom.near_close_up, far_coarse=(coarse_theta, 2 * coarse_theta))
+        At = dense_operator(gc)
+    AZ = At @ Z
+    Ei = np.linalg.inv(R @ AZ)
+
+    def apply(v):
+        v = np.asarray(v, dtype=np.float64).ravel()
+        c = Ei @ (R @ v)
+        return Z @ c + P(v - AZ @ c)
+    apply.Z, apply.At = Z, At
+    return apply
+
+
 # --------------------------------------------------------------- mobility
 
 def solve_density(geom, rhs, dense=None, tol=1e-13):

@@ -36,7 +36,7 @@ class ConfigDesc(C.Structure):
                 ('gmres_tol_lo2', C.c_double), ('dev_alloc', _ALLOC_FN), ('dev_free', _FREE_FN),
                 ('alloc_user', C.c_void_p), ('side_stream', C.c_int32), ('near_close_gap', C.c_double),
                 ('near_close_up', C.c_int32), ('far_coarse_lo', C.c_int32), ('far_coarse_lo2', C.c_int32),
-                ('precond', C.c_int32)]
+                ('precond', C.c_int32), ('precond_coarse', C.c_int32)]
 
 
 class TorchAllocator:
@@ -219,7 +219,7 @@ def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_
           max_iter=500, near_gap=0.0, near_up=2, slip=1.0, precision='fp64', refine=0, tpt=2, far_chunks=0,
           far_split=0, device=0, stream=None, profile=False, graphs=False, warm_start=False, lo2=None,
           gmres_tol_lo2=None, allocator=None, side_stream=False, near_close_gap=0.0, near_close_up=3,
-          far_coarse_lo=0, far_coarse_lo2=0, precond=False):
+          far_coarse_lo=0, far_coarse_lo2=0, precond=False, precond_coarse=False):
     d = ConfigDesc()
     d.n_particles = M
     d.radius, d.mu = radius, mu
@@ -251,6 +251,8 @@ def _desc(M, n_theta, n_phi, lo=None, radius=1.0, mu=1.0, gmres_tol=1e-8, gmres_
     # precond: False / 0 = plain GMRES, True / 1 = built when a configuration is solved a second
     # time, 'eager' / 2 = built at its first solve
     d.precond = 2 if precond in ('eager', 2) else (1 if precond else 0)
+    # precond_coarse: the two-level form (a coarse correction on degree <= 2 harmonics)
+    d.precond_coarse = 1 if precond_coarse else 0
     return d
 
 
@@ -363,7 +365,7 @@ class Context:
                  slip=1.0, precision='fp64', refine=0, tpt=None, far_chunks=None, far_split=None, device=0,
                  stream=None, profile=False, tune_K=1, graphs=False, warm_start=False, lo2=None,
                  gmres_tol_lo2=None, torch_alloc=False, side_stream=False, near_close_gap=0.0, near_close_up=3,
-                 far_coarse_lo=0, far_coarse_lo2=0, precond=False):
+                 far_coarse_lo=0, far_coarse_lo2=0, precond=False, precond_coarse=False):
         c = _f64(centers).reshape(-1, 3)
         self.M = c.shape[0]
         self._alloc = None
@@ -383,7 +385,7 @@ class Context:
                   graphs=graphs, warm_start=warm_start, lo2=lo2, gmres_tol_lo2=gmres_tol_lo2,
                   allocator=self._alloc, side_stream=side_stream, near_close_gap=near_close_gap,
                   near_close_up=near_close_up, far_coarse_lo=far_coarse_lo, far_coarse_lo2=far_coarse_lo2,
-                  precond=precond)
+                  precond=precond, precond_coarse=precond_coarse)
         self.n_theta, self.n_phi, self.lo, self.lo2 = n_theta, n_phi, lo, lo2
         ax = None if axes is None else _f64(axes).reshape(-1, 3)
         h = C.c_void_p()

@@ -84,6 +84,7 @@ static std::string check_desc(const pqn_config_desc& c) {
   if (c.far_coarse_lo2 != 0 && (c.n_theta_lo2 == 0 || c.far_coarse_lo2 < 2 || c.far_coarse_lo2 > c.n_theta_lo2))
     return "far_coarse_lo2 needs a second low-fidelity grid and 2 <= far_coarse_lo2 <= n_theta_lo2";
   if (c.precond < 0 || c.precond > 2) return "precond must be 0, 1 or 2";
+  if (c.precond_coarse < 0 || c.precond_coarse > 1) return "precond_coarse must be 0 or 1";
   return "";
 }
 
@@ -151,6 +152,8 @@ pqn_status pqn_batch_create(int32_t n_inst, const pqn_config_desc* descs, const 
       const std::string bad = check_desc(c);
       if (!bad.empty()) return fail(PQN_ERR_INVALID, "instance " + std::to_string(b) + ": " + bad);
       if (!centers[b]) return fail(PQN_ERR_INVALID, "pqn_batch_create: NULL centres");
+      if (c.precond_coarse)
+        return fail(PQN_ERR_INVALID, "instance " + std::to_string(b) + ": precond_coarse is not for batch contexts");
       if (c.precision != c0.precision || c.gmres_restart != c0.gmres_restart || c.device != c0.device ||
           c.targets_per_thread != c0.targets_per_thread || c.far_split != c0.far_split ||
           c.refine_sweeps != c0.refine_sweeps || c.dev_alloc != c0.dev_alloc || c.dev_free != c0.dev_free ||

@@ -94,6 +94,10 @@ struct SphereTables {
 std::vector<double> sh_recurrence_table(int p);
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+// Gauss-Legendre x trapezoid grid of ntc x npc nodes on a sphere of radius a: offsets [nc][3],
+// weights [nc] and the real harmonics of degree <= p at the nodes [nc][(p + 1)^2].
+void coarse_sh_grid(int ntc, int npc, double a, int p, std::vector<double>& off, std::vector<double>& w,
+                    std::vector<double>& Y);
 // close_up > 0: also the close-pair grid, close_up times finer per direction
 void build_sphere_tables(int n_theta, int n_phi, double radius, int near_up, SphereTables& t, int close_up = 0,
                          int far_theta = 0);

@@ -1007,6 +1007,7 @@ void pqn_ctx_impl::gmres_batch_graph(std::vector<SysRef>& sys, int precision) {
 void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision) {
   const int ns = (int)sys.size();
   if (ns == 0) return;
+  for (SysRef& r : sys) r.c->pc_prec = precision == PQN_MIXED ? 1 : 0;
   const int m = sys[0].lv->restart;
   const int hs = 2 * (m + 1) + 2;
   hdev.alloc((size_t)ns * hs);

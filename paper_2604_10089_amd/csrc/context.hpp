@@ -131,6 +131,34 @@ struct SysBuf {
 // single-sphere block D, its inverse, the near blocks A_ij, the Schur complements
 // S_i = D - sum_j A_ij D^{-1} A_ji and their inverses, rebuilt at the first solve
 // after a configuration change.
+// Coarse level of the two-level preconditioner (precond_coarse): per sphere and component
+// the real harmonics of degree <= 2 (kCoarseB = 27 unknowns per sphere, Mc = 27 M).
+constexpr int kCoarseL = 9, kCoarseB = 27;
+struct CoarsePc {
+  bool tab = false;                // the level's tables below are built
+  bool on = false;                 // the current configuration applies the coarse correction
+  int ncs = 0;                     // coarse far-source nodes per sphere
+  int ns_iters = 0;                // Newton-Schulz steps of inv(E) in the last set-up
+  double ns_res = 0.0;             // its final residual ||I - E X||_F / sqrt(Mc)
+  DevArray<double> R;              // [27][3n] row-major: the projection (rows c 9 + k)
+  DevArray<double> Z;              // [3n][27] row-major: the synthesis at the nodes
+  DevArray<double> DZ;             // [27][3n] by columns: D Z (the diagonal blocks of A~ Z)
+  DevArray<double> Tlow;           // [9][n]: rows k < 9 of the analysis T
+  DevArray<double> offc, wc, Yc;   // coarse far-source grid [ncs][3], [ncs], synthesis [ncs][9]
+  DevArray<double> X0, ES;         // inv(R D Z) and R D Z, [27][27] by columns
+  DevArray<double> NL;             // near low columns per ordered slot [27][3n] by columns
+  DevArray<_Float16> B16;          // D Z and the NL blocks in FP16 (by columns, ld rows)
+  DevArray<float> bscale;
+  DevArray<int> bptr, bcol;
+  int nblk = 0, ld = 0;
+  DevArray<double> E, X, X2, W;    // [Mc][Mc] by columns
+  DevArray<double> res;
+  DevArray<float> Ei;              // inv(E) in FP32 by columns
+  DevArray<double> cr, cpart, ccI, ccC, qc, bpart;  // application work arrays
+  DevArray<GemmDesc> desc;         // R v and the Z c accumulation for K = 1 .. kMaxRhs (2 per K)
+  int tr[kMaxRhs] = {}, tz[kMaxRhs] = {};
+};
+
 struct Precond {
   bool has_d = false;            // D^{-1}, TD and the application's GEMM descriptors are built
   unsigned long epoch = 0;       // configuration of the tables below (0 = none yet)
@@ -160,6 +188,7 @@ struct Precond {
   int fallback = 0;              // spheres left on D^{-1} (Newton-Schulz did not converge)
   int ns_iters = 0;              // Newton-Schulz steps of the last set-up
   double setup_ms = 0.0;         // wall time of the last set-up
+  CoarsePc co;                   // the coarse level (precond_coarse)
 };
 
 // Reuse of earlier solutions across the mobility products of one LCP solve (the
@@ -423,6 +452,9 @@ struct pqn_ctx_impl {
   // (no-op when up to date), and out_r = P in_r for the densities of a group (out_r may
   // be in_r: every read of the input precedes the write of the output)
   void precond_setup(Level& lv);
+  void coarse_tables(Level& lv);
+  void coarse_setup(Level& lv);
+  void coarse_pre(MvGroup& gr);
   void precond_apply(MvGroup& gr);
   void precond_apply_groups(std::vector<MvGroup>& groups);
   // near tiles only: near_part of the group's slots from its densities (with their
@@ -432,6 +464,7 @@ struct pqn_ctx_impl {
   double pc_setup_ms = 0.0;  // preconditioner set-up time, fallbacks and applications since the last reset
   int pc_fallback = 0;
   int pc_applies = 0;
+  int pc_prec = 0;  // 1: the current GMRES solve's operator is mixed (the coarse far sum in FP32)
   void mobility(Level& lv, const double* FT_dev, const double* axes_dev, double* UO_dev, pqn_mvp_stats* st) {
     mobility_multi(lv, 1, &FT_dev, axes_dev, &UO_dev, st);
   }

@@ -169,6 +169,18 @@ static void build_self_block(SphereTables& t) {
   }
 }
 
+void coarse_sh_grid(int ntc, int npc, double a, int p, std::vector<double>& off, std::vector<double>& w,
+                    std::vector<double>& Y) {
+  std::vector<double> ct, ph;
+  sphere_grid(ntc, npc, a, off, w, &ct, &ph);
+  const int nc = ntc * npc, L = (p + 1) * (p + 1);
+  Y.assign((size_t)nc * L, 0.0);
+  for (int f = 0; f < nc; ++f) {
+    const double st = std::sqrt(1.0 - ct[f] * ct[f]);
+    sh_row(p, ct[f], st, std::cos(ph[f]), std::sin(ph[f]), &Y[(size_t)f * L]);
+  }
+}
+
 std::vector<double> sh_recurrence_table(int p) {
   const int L = (p + 1) * (p + 1);
   std::vector<double> t(2 * (size_t)L, 0.0);

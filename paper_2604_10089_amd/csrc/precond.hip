@@ -417,6 +417,206 @@ __global__ __launch_bounds__(256) void k_pc_sum_multi(const PcDesc* __restrict__
   D.out[(size_t)c * D.N + (size_t)i * D.n + x] = v;
 }
 
+// ------------------------------------------------- coarse level (precond_coarse)
+
+constexpr int kMaxCoarseNodes = 256;   // coarse far-source nodes per sphere (ntc <= 11)
+constexpr double kCoarseTol = 1e-4;    // Newton-Schulz stop for inv(E)
+constexpr double kCoarseKeep = 1e-1;   // above this after the last step the coarse level stays off
+constexpr int kCoarseMaxSteps = 12;
+constexpr int kCmvCols = 256;          // columns of inv(E) per workgroup of the coarse product
+
+// NL[(g 27 + c 9 + k) 3n + row] = column c L + k of the coefficient near block of slot g (at
+// acs[g]): A_ij Z = Ac_ij (I3 x T) Z picks the coefficient columns of the degree <= 2
+// harmonics (T Z = I on them).
+__global__ __launch_bounds__(256) void k_low_cols(const double* __restrict__ Ac, const long* __restrict__ acs,
+                                                  int nslots, int n3, int L, double* __restrict__ NL) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)nslots * kCoarseB * n3) return;
+  const int row = (int)(e % n3);
+  const long gb = e / n3;
+  const int b = (int)(gb % kCoarseB), g = (int)(gb / kCoarseB);
+  const int c = b / kCoarseL, k = b - c * kCoarseL;
+  NL[e] = Ac[acs[g] + ((size_t)c * L + k) * n3 + row];
+}
+
+// The diagonal blocks of E (by columns): E(i 27 + b', i 27 + b) = ES(b', b) for every sphere.
+__global__ __launch_bounds__(256) void k_eself_fill(const double* __restrict__ ES, int M, long Mc,
+                                                    double* __restrict__ E) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)M * kCoarseB * kCoarseB) return;
+  const int i = (int)(e / (kCoarseB * kCoarseB)), q = (int)(e % (kCoarseB * kCoarseB));
+  const int b = q / kCoarseB, bp = q - b * kCoarseB;
+  E[((size_t)i * kCoarseB + b) * Mc + (size_t)i * kCoarseB + bp] = ES[q];
+}
+
+// X = blockdiag(X0) by columns (the Newton-Schulz start).
+__global__ __launch_bounds__(256) void k_blockdiag(const double* __restrict__ X0, long Mc, double* __restrict__ X) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= Mc * Mc) return;
+  const long col = e / Mc, r = e - col * Mc;
+  X[e] = (r / kCoarseB == col / kCoarseB) ? X0[(col % kCoarseB) * kCoarseB + r % kCoarseB] : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_to_f32(const double* __restrict__ x, long len, float* __restrict__ y) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e < len) y[e] = (float)x[e];
+}
+
+// Far blocks of E: for every far pair (i, j), E(i 27 + c' 9 + k', j 27 + c 9 + k) =
+// sum_x T(k', x) u_c'(x) with u the far double layer at sphere i's node x of the density
+// e_c Y_k on sphere j, summed on the coarse source grid (offsets offc, weights wc, harmonics
+// Yc): u_c'(x) = s sum_f (r.o_f) / |r|^5 r_c' r_c wc_f Y_k(f), r = x - y_f, s = 3 / (4 pi a).
+// Workgroup per sphere pair; thread per target (as many passes as needed); the six products
+// r_c r_c' (symmetric) x nine harmonics are accumulated per target, projected on the nine
+// analysis rows, summed over the wave by shuffles and over the waves in LDS (fixed order).
+__global__ __launch_bounds__(256) void k_coarse_far_blocks(const double* __restrict__ ctr,
+                                                           const double* __restrict__ off,
+                                                           const unsigned char* __restrict__ cls,
+                                                           const double* __restrict__ offc,
+                                                           const double* __restrict__ wc,
+                                                           const double* __restrict__ Yc,
+                                                           const double* __restrict__ Tlow, int n, int ncs, int M,
+                                                           double a, double* __restrict__ E) {
+  constexpr int NP = 6, NV = NP * kCoarseL, NQ = kCoarseL * NV;  // 54 per target, 486 projected
+  __shared__ double sy[kMaxCoarseNodes][6];                     // source position (rel. c_i), offset
+  __shared__ double swy[kMaxCoarseNodes][kCoarseL];             // s wc Y_k
+  __shared__ double red[4][NQ];
+  const int i = blockIdx.x / M, j = blockIdx.x - (blockIdx.x / M) * M;
+  if (i == j || cls[(size_t)i * M + j] != 0) return;  // uniform over the block
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const double dx = ctr[3 * j] - ctr[3 * i], dy = ctr[3 * j + 1] - ctr[3 * i + 1], dz = ctr[3 * j + 2] - ctr[3 * i + 2];
+  const double s = 3.0 / (4.0 * kPi * a);
+  for (int f = t; f < ncs; f += 256) {
+    sy[f][0] = dx + offc[3 * f];
+    sy[f][1] = dy + offc[3 * f + 1];
+    sy[f][2] = dz + offc[3 * f + 2];
+    sy[f][3] = offc[3 * f];
+    sy[f][4] = offc[3 * f + 1];
+    sy[f][5] = offc[3 * f + 2];
+    for (int k = 0; k < kCoarseL; ++k) swy[f][k] = s * wc[f] * Yc[f * kCoarseL + k];
+  }
+  for (int q = t; q < 4 * NQ; q += 256) (&red[0][0])[q] = 0.0;
+  __syncthreads();
+  for (int x0 = 0; x0 < n; x0 += 256) {
+    const int x = x0 + t;
+    const bool valid = x < n;
+    const int xx = valid ? x : n - 1;
+    const double Xx = off[3 * xx], Xy = off[3 * xx + 1], Xz = off[3 * xx + 2];
+    double u[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) u[q] = 0.0;
+    for (int f = 0; f < ncs; ++f) {
+      const double rx = Xx - sy[f][0], ry = Xy - sy[f][1], rz = Xz - sy[f][2];
+      const double r2 = rx * rx + ry * ry + rz * rz;
+      const double ri = 1.0 / sqrt(r2);
+      const double ri2 = ri * ri;
+      const double g = (rx * sy[f][3] + ry * sy[f][4] + rz * sy[f][5]) * ri * ri2 * ri2;
+      const double tp[NP] = {g * rx * rx, g * rx * ry, g * rx * rz, g * ry * ry, g * ry * rz, g * rz * rz};
+#pragma unroll
+      for (int k = 0; k < kCoarseL; ++k) {
+        const double wy = swy[f][k];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) u[p * kCoarseL + k] = fma(tp[p], wy, u[p * kCoarseL + k]);
+      }
+    }
+    if (__any(valid)) {
+      for (int kp = 0; kp < kCoarseL; ++kp) {
+        const double tw = valid ? Tlow[(size_t)kp * n + x] : 0.0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          double v = tw * u[q];
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+          if (lane == 0) red[wv][kp * NV + q] += v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = t; q < NQ; q += 256) {
+    const double v = red[0][q] + red[1][q] + red[2][q] + red[3][q];
+    const int kp = q / NV, pk = q - kp * NV, p = pk / kCoarseL, k = pk - p * kCoarseL;
+    // p -> (c, c'): 0 xx, 1 xy, 2 xz, 3 yy, 4 yz, 5 zz
+    const int ca = p < 3 ? 0 : (p < 5 ? 1 : 2);
+    const int cb = p < 3 ? p : (p < 5 ? p - 2 : 2);
+    const size_t Mc = (size_t)M * kCoarseB;
+    E[((size_t)j * kCoarseB + cb * kCoarseL + k) * Mc + (size_t)i * kCoarseB + ca * kCoarseL + kp] = v;
+    if (ca != cb) E[((size_t)j * kCoarseB + ca * kCoarseL + k) * Mc + (size_t)i * kCoarseB + cb * kCoarseL + kp] = v;
+  }
+}
+
+// cpart[(h Mc + r) K + k] = sum over the columns m of chunk h of inv(E)(r, m) cr[m K + k]
+// (inv(E) in FP32 by columns: consecutive rows read consecutive words; cr wave-uniform).
+template <int K>
+__global__ __launch_bounds__(256) void k_coarse_mv(const float* __restrict__ Ei, const double* __restrict__ cr,
+                                                   int Mc, double* __restrict__ cpart) {
+  const int r = blockIdx.x * 256 + threadIdx.x, h = blockIdx.y;
+  const bool valid = r < Mc;
+  const int rr = valid ? r : Mc - 1;
+  const int m0 = h * kCmvCols, m1 = min(Mc, m0 + kCmvCols);
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+#pragma unroll 4
+  for (int m = m0; m < m1; ++m) {
+    const double e = (double)Ei[(size_t)m * Mc + rr];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = fma(e, cr[(size_t)m * K + k], acc[k]);
+  }
+  if (valid)
+#pragma unroll
+    for (int k = 0; k < K; ++k) cpart[((size_t)h * Mc + r) * K + k] = acc[k];
+}
+
+// ccI[r K + k] = sum over the chunks (in order); ccC[(k M + j) 27 + b] the same, r = j 27 + b.
+__global__ __launch_bounds__(256) void k_coarse_mv_sum(const double* __restrict__ cpart, int nh, int Mc, int M, int K,
+                                                       double* __restrict__ ccI, double* __restrict__ ccC) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)Mc * K) return;
+  const int r = (int)(e / K), k = (int)(e - (long)r * K);
+  double v = 0.0;
+  for (int h = 0; h < nh; ++h) v += cpart[((size_t)h * Mc + r) * K + k];
+  ccI[e] = v;
+  const int j = r / kCoarseB, b = r - j * kCoarseB;
+  ccC[((size_t)k * M + j) * kCoarseB + b] = v;
+}
+
+// qc[(j ncs + f) 3K + 3k + c] = sum_l Yc(f, l) ccI[(j 27 + c 9 + l) K + k]: the coarse density
+// at the coarse far-source nodes, in the layout of the far source packing.
+__global__ __launch_bounds__(256) void k_coarse_qc(const double* __restrict__ Yc, const double* __restrict__ ccI,
+                                                   int ncs, int M, int K, double* __restrict__ qc) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  const int K3 = 3 * K;
+  if (e >= (long)M * ncs * K3) return;
+  const int q = (int)(e % K3);
+  const long jf = e / K3;
+  const int f = (int)(jf % ncs), j = (int)(jf / ncs);
+  const int k = q / 3, c = q - 3 * k;
+  double v = 0.0;
+#pragma unroll
+  for (int l = 0; l < kCoarseL; ++l)
+    v = fma(Yc[f * kCoarseL + l], ccI[((size_t)j * kCoarseB + c * kCoarseL + l) * K + k], v);
+  qc[e] = v;
+}
+
+// vC[(k M + i) 3n + m] -= (A~ z1) at node m of sphere i: the coarse block partials (self and
+// near) and the far partials of the coarse far sum (nchunks each), m = c n + x.
+__global__ __launch_bounds__(256) void k_coarse_resid(double* __restrict__ vC, const double* __restrict__ bpart,
+                                                      const int* __restrict__ bptr, OPtrs far, int nchunks, int K,
+                                                      int n, int M, int N) {
+  const int n3 = 3 * n;
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)K * M * n3) return;
+  const int m = (int)(e % n3);
+  const long ki = e / n3;
+  const int i = (int)(ki % M), k = (int)(ki / M);
+  const int c = m / n, x = m - c * n;
+  double v = 0.0;
+  for (int b = bptr[i]; b < bptr[i + 1]; ++b) v += bpart[((size_t)b * K + k) * n3 + m];
+  for (int h = 0; h < nchunks; ++h) v += far.p[k][(size_t)h * 3 * N + (size_t)c * N + (size_t)i * n + x];
+  vC[e] -= v;
+}
+
 static unsigned nblocks(long count) { return (unsigned)((count + 255) / 256); }
 // ------------------------------------------------------------ near stage only
 
@@ -664,11 +864,256 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
     }
     HIPCHK(hipStreamSynchronize(s));  // dsrc and the host tables are released after this
   }
+  if (cfg.precond_coarse)
+    coarse_setup(lv);
+  else
+    pc.co.on = false;
   HIPCHK(hipGetLastError());
   pc.epoch = config_epoch;
   pc.setup_ms = tm.ms();
   pc_setup_ms += pc.setup_ms;
   pc_fallback += pc.fallback;
+}
+
+// ------------------------------------------------- coarse level (precond_coarse): set-up
+
+// Tables of the level (once): R, Z, D Z, R D Z and its inverse, the analysis rows of the
+// degree <= 2 harmonics, the coarse far-source grid (n_theta / 2 rows, at least 3, at most
+// 11), and the application's GEMM descriptors (R v; y += Z c) for K = 1 .. kMaxRhs.
+void pqn_ctx_impl::coarse_tables(Level& lv) {
+  CoarsePc& co = lv.pc.co;
+  if (co.tab) return;
+  hipStream_t s = stream;
+  const SphereTables& t = lv.tab;
+  const int n = lv.n, n3 = 3 * n, M = lv.M, Mc = kCoarseB * M;
+  const double a = t.radius;
+  if (t.L < kCoarseL) throw Error(PQN_ERR_INVALID, "precond_coarse needs n_theta >= 3");
+  // Y_k(x) = T(k, x) / (w(x) / a^2) (the analysis is the synthesis times the unit-sphere weights)
+  std::vector<double> R((size_t)kCoarseB * n3, 0.0), Z((size_t)n3 * kCoarseB, 0.0), Tl((size_t)kCoarseL * n);
+  for (int k = 0; k < kCoarseL; ++k)
+    for (int x = 0; x < n; ++x) {
+      const double tk = t.T[(size_t)k * n + x];
+      Tl[(size_t)k * n + x] = tk;
+      for (int c = 0; c < 3; ++c) {
+        R[(size_t)(c * kCoarseL + k) * n3 + c * n + x] = tk;
+        Z[(size_t)(c * n + x) * kCoarseB + c * kCoarseL + k] = tk / (t.w[x] / (a * a));
+      }
+    }
+  const SphereBlock& sb = sphere_block_cached(t);
+  std::vector<double> DZ((size_t)kCoarseB * n3, 0.0), ES((size_t)kCoarseB * kCoarseB, 0.0);
+  for (int b = 0; b < kCoarseB; ++b)
+    for (int r = 0; r < n3; ++r) {
+      double v = 0.0;
+      for (int m = 0; m < n3; ++m) v += sb.D[(size_t)r * n3 + m] * Z[(size_t)m * kCoarseB + b];
+      DZ[(size_t)b * n3 + r] = v;
+    }
+  for (int b = 0; b < kCoarseB; ++b)
+    for (int bp = 0; bp < kCoarseB; ++bp) {
+      double v = 0.0;
+      for (int r = 0; r < n3; ++r) v += R[(size_t)bp * n3 + r] * DZ[(size_t)b * n3 + r];
+      ES[(size_t)b * kCoarseB + bp] = v;
+    }
+  std::vector<double> X0r((size_t)kCoarseB * kCoarseB), X0((size_t)kCoarseB * kCoarseB);
+  for (int b = 0; b < kCoarseB; ++b)
+    for (int bp = 0; bp < kCoarseB; ++bp) X0r[(size_t)bp * kCoarseB + b] = ES[(size_t)b * kCoarseB + bp];
+  invert_gauss_jordan(X0r, kCoarseB);  // row-major inverse of R D Z
+  for (int b = 0; b < kCoarseB; ++b)
+    for (int bp = 0; bp < kCoarseB; ++bp) X0[(size_t)b * kCoarseB + bp] = X0r[(size_t)bp * kCoarseB + b];
+  const int ntc = std::min(11, std::max(3, lv.tab.n_theta / 2));
+  std::vector<double> oc, wcv, Yc;
+  coarse_sh_grid(ntc, 2 * ntc, a, 2, oc, wcv, Yc);
+  co.ncs = ntc * 2 * ntc;
+  co.R.upload(R.data(), R.size(), s);
+  co.Z.upload(Z.data(), Z.size(), s);
+  co.DZ.upload(DZ.data(), DZ.size(), s);
+  co.Tlow.upload(Tl.data(), Tl.size(), s);
+  co.ES.upload(ES.data(), ES.size(), s);
+  co.X0.upload(X0.data(), X0.size(), s);
+  co.offc.upload(oc.data(), oc.size(), s);
+  co.wc.upload(wcv.data(), wcv.size(), s);
+  co.Yc.upload(Yc.data(), Yc.size(), s);
+  co.cr.alloc((size_t)Mc * kMaxRhs);
+  co.ccI.alloc((size_t)Mc * kMaxRhs);
+  co.ccC.alloc((size_t)Mc * kMaxRhs);
+  co.cpart.alloc((size_t)((Mc + kCmvCols - 1) / kCmvCols) * Mc * kMaxRhs);
+  co.qc.alloc((size_t)M * co.ncs * 3 * kMaxRhs);
+  std::vector<GemmDesc> d;
+  for (int K = 1; K <= kMaxRhs; ++K) {
+    int blocks = 0;
+    push_gemm(d, blocks, kCoarseB, K * M, n3, co.R.p, n3, lv.pc.vC.p, n3, co.cr.p, kCoarseB, 0, kCoarseB * K, K, M, 1,
+              0, 1);
+    co.tr[K - 1] = blocks;
+    blocks = 0;
+    push_gemm(d, blocks, n3, K * M, kCoarseB, co.Z.p, kCoarseB, co.ccC.p, kCoarseB, lv.pc.yI.p, n3, 0, n3 * K, K, M,
+              1, 2, 1);
+    co.tz[K - 1] = blocks;
+  }
+  co.desc.upload(d.data(), d.size(), s);
+  HIPCHK(hipStreamSynchronize(s));
+  co.tab = true;
+}
+
+// Per configuration (after the near-patch set-up; Ac still holds the coefficient near blocks):
+// the FP16 blocks of A~ Z restricted to self and near pairs, E = R A~ Z, inv(E) by Newton-Schulz.
+void pqn_ctx_impl::coarse_setup(Level& lv) {
+  Precond& pc = lv.pc;
+  CoarsePc& co = pc.co;
+  co.on = false;
+  coarse_tables(lv);
+  hipStream_t s = stream;
+  const int n = lv.n, n3 = 3 * n, M = lv.M, L = lv.L, nc = 3 * L;
+  const long Mc = (long)kCoarseB * M;
+  const size_t ncn = (size_t)nc * n3;
+  // near low columns, slot by slot
+  std::vector<long> acs;
+  for (int i = 0; i < M; ++i)
+    for (int sl = 0; sl < h_npart[i]; ++sl) acs.push_back(pc.aco[i] + (long)sl * (long)ncn);
+  const int nslots = (int)acs.size();
+  DevArray<long> dacs;
+  if (nslots > 0) {
+    co.NL.alloc((size_t)nslots * kCoarseB * n3);
+    dacs.upload(acs.data(), acs.size(), s);
+    hipLaunchKernelGGL(k_low_cols, dim3(nblocks((long)nslots * kCoarseB * n3)), dim3(256), 0, s, pc.Ac.p, dacs.p,
+                       nslots, n3, L, co.NL.p);
+  }
+  // blocks of A~ Z (self and near): sphere i's row holds D Z, then its slots' NL
+  {
+    std::vector<int> bp(M + 1, 0), bc;
+    std::vector<const double*> src;
+    std::vector<double> sg;
+    int g = 0;
+    for (int i = 0; i < M; ++i) {
+      bp[i] = (int)bc.size();
+      bc.push_back(i);
+      src.push_back(co.DZ.p);
+      sg.push_back(1.0);
+      for (int sl = 0; sl < h_npart[i]; ++sl, ++g) {
+        bc.push_back(h_partners[(size_t)i * kMaxNear + sl]);
+        src.push_back(co.NL.p + (size_t)g * kCoarseB * n3);
+        sg.push_back(1.0);
+      }
+    }
+    bp[M] = (int)bc.size();
+    const long nb = (long)bc.size();
+    co.nblk = (int)nb;
+    co.ld = (n3 + 63) / 64 * 64;
+    co.bptr.upload(bp.data(), bp.size(), s);
+    co.bcol.upload(bc.data(), bc.size(), s);
+    co.B16.alloc((size_t)nb * kCoarseB * co.ld);
+    co.bscale.alloc((size_t)nb);
+    co.bpart.alloc((size_t)nb * kMaxRhs * n3);
+    DevArray<const double*> dsrc;
+    DevArray<double> dsg;
+    dsrc.upload(src.data(), src.size(), s);
+    dsg.upload(sg.data(), sg.size(), s);
+    hipLaunchKernelGGL(k_block_absmax, dim3(nb), dim3(256), 0, s, dsrc.p, (long)kCoarseB * n3, co.bscale.p);
+    hipLaunchKernelGGL(k_blocks_f16, dim3(nblocks(nb * (long)kCoarseB * co.ld)), dim3(256), 0, s, dsrc.p, dsg.p,
+                       co.bscale.p, n3, kCoarseB, co.ld, nb, co.B16.p);
+    HIPCHK(hipStreamSynchronize(s));  // dsrc is released after this
+  }
+  // E = R A~ Z by columns: diagonal blocks, near blocks R NL (one 27 x 27 product per slot),
+  // far blocks on the coarse source grid
+  co.E.alloc((size_t)Mc * Mc);
+  hipLaunchKernelGGL(k_eself_fill, dim3(nblocks((long)M * kCoarseB * kCoarseB)), dim3(256), 0, s, co.ES.p, M, Mc,
+                     co.E.p);
+  if (nslots > 0) {
+    std::vector<GemmDesc> gn;
+    int ngn = 0, g = 0;
+    for (int i = 0; i < M; ++i)
+      for (int sl = 0; sl < h_npart[i]; ++sl, ++g) {
+        const int j = h_partners[(size_t)i * kMaxNear + sl];
+        push_gemm(gn, ngn, kCoarseB, kCoarseB, n3, co.R.p, n3, co.NL.p + (size_t)g * kCoarseB * n3, n3,
+                  co.E.p + (size_t)j * kCoarseB * Mc + (size_t)i * kCoarseB, kCoarseB, 0, (int)Mc, 1, kCoarseB, 0, 0,
+                  0);
+      }
+    DescPack dp;
+    const size_t on = dp.add(gn);
+    char* base = push_desc_pack(dp.host);
+    launch_gemm64_multi(s, (const GemmDesc*)(base + on), (int)gn.size(), ngn);
+  }
+  hipLaunchKernelGGL(k_coarse_far_blocks, dim3(M * M), dim3(256), 0, s, ctr.p, lv.off.p, cls.p, co.offc.p, co.wc.p,
+                     co.Yc.p, co.Tlow.p, n, co.ncs, M, a, co.E.p);
+  // inv(E): Newton-Schulz X <- X (2I - E X) from the block-diagonal inverse
+  co.X.alloc((size_t)Mc * Mc);
+  co.X2.alloc((size_t)Mc * Mc);
+  co.W.alloc((size_t)Mc * Mc);
+  co.res.alloc((size_t)kNsSlices);
+  hipLaunchKernelGGL(k_blockdiag, dim3(nblocks(Mc * Mc)), dim3(256), 0, s, co.X0.p, Mc, co.X.p);
+  std::vector<double> resp(kNsSlices);
+  co.ns_iters = 0;
+  double res = 1e300;
+  for (int step = 0;; ++step) {
+    launch_gemm64_big(s, (int)Mc, (int)Mc, (int)Mc, co.E.p, (int)Mc, 0, co.X.p, 0, (int)Mc, co.W.p, 0, (int)Mc, 0,
+                      (int)Mc, 1, 1);
+    hipLaunchKernelGGL(k_ns_residual, dim3(kNsSlices), dim3(256), 0, s, co.W.p, (int)Mc, co.res.p);
+    HIPCHK(hipMemcpyAsync(resp.data(), co.res.p, resp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double tot = 0.0;
+    for (double v : resp) tot += v;
+    res = std::isfinite(tot) ? std::sqrt(tot / Mc) : 1e300;
+    if (res <= kCoarseTol || step == kCoarseMaxSteps) break;
+    hipLaunchKernelGGL(k_diag_minus, dim3((unsigned)Mc), dim3(256), 0, s, co.W.p, (int)Mc, 2.0);
+    launch_gemm64_big(s, (int)Mc, (int)Mc, (int)Mc, co.X.p, (int)Mc, 0, co.W.p, 0, (int)Mc, co.X2.p, 0, (int)Mc, 0,
+                      (int)Mc, 1, 1);
+    std::swap(co.X.p, co.X2.p);
+    ++co.ns_iters;
+  }
+  co.ns_res = res;
+  if (res > kCoarseKeep) return;  // the coarse level stays off for this configuration
+  co.Ei.alloc((size_t)Mc * Mc);
+  hipLaunchKernelGGL(k_to_f32, dim3(nblocks(Mc * Mc)), dim3(256), 0, s, co.X.p, Mc * Mc, co.Ei.p);
+  HIPCHK(hipStreamSynchronize(s));  // dacs and the descriptor staging are released/reused after this
+  co.on = true;
+}
+
+// The coarse pre-correction of an application, on the gathered input vC: c = inv(E) R v
+// (into ccI and ccC), then vC <- v - A~ Z c. The caller's D^{-1} GEMM is followed by
+// y += Z c, so that the result is Z c + P_f (v - A~ Z c).
+void pqn_ctx_impl::coarse_pre(MvGroup& gr) {
+  Level& lv = *gr.lv;
+  CoarsePc& co = lv.pc.co;
+  hipStream_t s = stream;
+  const int n = lv.n, n3 = 3 * n, M = lv.M, N = lv.N, K = gr.K;
+  const int Mc = kCoarseB * M;
+  launch_gemm64_multi_big(s, co.desc.p + 2 * (K - 1), 1, co.tr[K - 1]);
+  const dim3 gm((Mc + 255) / 256, (Mc + kCmvCols - 1) / kCmvCols);
+#define CMV(KK) hipLaunchKernelGGL(k_coarse_mv<KK>, gm, dim3(256), 0, s, co.Ei.p, co.cr.p, Mc, co.cpart.p)
+  switch (K) {
+    case 1: CMV(1); break;
+    case 2: CMV(2); break;
+    case 3: CMV(3); break;
+    case 4: CMV(4); break;
+    case 5: CMV(5); break;
+    default: CMV(6); break;
+  }
+#undef CMV
+  hipLaunchKernelGGL(k_coarse_mv_sum, dim3(nblocks((long)Mc * K)), dim3(256), 0, s, co.cpart.p, (int)gm.y, Mc, M, K,
+                     co.ccI.p, co.ccC.p);
+  // self and near of A~ z1 from the FP16 blocks of A~ Z
+  const int rchunks = (n3 + 255) / 256;
+  const dim3 gb(co.nblk * rchunks);
+#define CBK(KK)                                                                                                  \
+  hipLaunchKernelGGL(k_bsr_block<KK>, gb, dim3(256), 0, s, co.B16.p, co.bscale.p, co.bcol.p, co.ccI.p, n3, kCoarseB, \
+                     co.ld, rchunks, co.bpart.p)
+  switch (K) {
+    case 1: CBK(1); break;
+    case 2: CBK(2); break;
+    case 3: CBK(3); break;
+    case 4: CBK(4); break;
+    case 5: CBK(5); break;
+    default: CBK(6); break;
+  }
+#undef CBK
+  // far of A~ z1: the coarse density at the coarse source grid, summed by the far kernel
+  hipLaunchKernelGGL(k_coarse_qc, dim3(nblocks((long)M * co.ncs * 3 * K)), dim3(256), 0, s, co.Yc.p, co.ccI.p, co.ncs,
+                     M, K, co.qc.p);
+  launch_pack_coarse(s, pc_prec, K, co.qc.p, co.offc.p, co.wc.p, co.ncs, M * co.ncs, lv.src.p);
+  OPtrs fp{};
+  for (int r = 0; r < K; ++r) fp.p[r] = lv.wk(r).far_part.p;
+  launch_far(s, pc_prec, K, lv.tpt, lv.src.p, lv.off.p, ctr.p, cls.p, n, co.ncs, M, N, lv.spc, lv.nchunks,
+             3.0 / (4.0 * kPi * a), fp);
+  hipLaunchKernelGGL(k_coarse_resid, dim3(nblocks((long)K * M * n3)), dim3(256), 0, s, lv.pc.vC.p, co.bpart.p,
+                     co.bptr.p, fp, lv.nchunks, K, n, M, N);
 }
 
 // ------------------------------------------------------------ application
@@ -678,7 +1123,7 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
 // of a batch), else one application per group.
 void pqn_ctx_impl::precond_apply_groups(std::vector<MvGroup>& groups) {
   bool multi = groups.size() > 1;
-  for (MvGroup& gr : groups) multi = multi && gr.K == 1;
+  for (MvGroup& gr : groups) multi = multi && gr.K == 1 && !gr.lv->pc.co.on;
   if (!multi) {
     for (MvGroup& gr : groups) gr.c->precond_apply(gr);
     return;
@@ -735,6 +1180,9 @@ void pqn_ctx_impl::precond_apply(MvGroup& gr) {
   }
   stage_begin(kStagePrecond);
   hipLaunchKernelGGL(k_pc_gather, dim3(nblocks((long)K * M * n3)), dim3(256), 0, s, vin, K, n, M, N, pc.vC.p);
+  // two levels: c = inv(E) R v, vC <- v - A~ Z c; below, y += Z c after y = D^{-1} vC
+  CoarsePc& co = pc.co;
+  if (co.on) coarse_pre(gr);
   // y = D^{-1} v and (with blocks) w = TD v; out may be the input: v is not read after the
   // gather. With the side stream on, y (matrix cores) runs there beside the block product
   // (HBM), and the sum waits for both.
@@ -745,10 +1193,12 @@ void pqn_ctx_impl::precond_apply(MvGroup& gr) {
     HIPCHK(hipEventRecord(ev_in, s));
     HIPCHK(hipStreamWaitEvent(sa, ev_in, 0));
     launch_gemm64_multi_big(sa, ad, 1, pc.aty[K - 1]);
+    if (co.on) launch_gemm64_multi_big(sa, co.desc.p + 2 * (K - 1) + 1, 1, co.tz[K - 1]);
     HIPCHK(hipEventRecord(ev_side, sa));
     launch_gemm64_multi_big(s, ad + 2, 1, pc.atw[K - 1]);
   } else {
     launch_gemm64_multi_big(s, ad, pc.nblk > 0 ? 2 : 1, pc.aty[K - 1] + (pc.nblk > 0 ? pc.atw[K - 1] : 0));
+    if (co.on) launch_gemm64_multi_big(s, co.desc.p + 2 * (K - 1) + 1, 1, co.tz[K - 1]);
   }
   if (pc.nblk > 0) {
     const int rchunks = (n3 + 255) / 256;

@@ -234,3 +234,107 @@ def test_side_stream_preconditioned_is_bit_identical(prec):
     say('side stream precond', prec, 'equal', [np.array_equal(a, b) for a, b in zip(out[False], out[True])])
     for a, b in zip(out[False], out[True]):
         assert np.array_equal(a, b)
+
+
+def test_two_level_matches_oracle_and_its_iteration_count(tiny_cases):
+    """precond_coarse (a coarse correction on every sphere's degree <= 2 harmonics before
+    the near patches; its far pairs on a 4x8 source grid at 8x16 nodes): the oracle's
+    density, in the oracle's two-level iteration count (+-1: inv(E) by Newton-Schulz to
+    1e-4 and stored in FP32 on the device), fewer than with one level."""
+    for seed, g, A in tiny_cases:
+        rhs = -bie.completion(g, inputs.random_forces(40 + seed, g.M))
+        q = np.linalg.solve(A, rhs.ravel())
+        P = bie.near_patch_preconditioner(g, A)
+        P2 = bie.two_level_preconditioner(g, A, P, coarse_theta=4)
+        _, its1, _ = bie.gmres(lambda v: A @ v.ravel(), rhs, tol=1e-10, right=P)
+        _, its2, _ = bie.gmres(lambda v: A @ v.ravel(), rhs, tol=1e-10, right=P2)
+        with binding.Context(g.c, None, 8, 16, gmres_tol=1e-10, precond='eager', precond_coarse=True) as ctx:
+            qd, st = ctx.bie_solve(soa(rhs))
+        say('two-level tiny seed', seed, 'gpu its', st['gmres_iters'], 'oracle', its2, 'one level', its1,
+            'setup ms', round(st['t_precond_ms'], 1))
+        assert st['converged'] == 1
+        assert rel(qd, soa(q)) < 1e-8
+        assert abs(st['gmres_iters'] - its2) <= 1
+        assert st['gmres_iters'] < its1
+
+
+def test_two_level_rsa216_six_force_sets_mixed():
+    """The timed configuration with the two-level preconditioner: the plain solves'
+    velocities within the mixed tolerance, in fewer iterations than one level."""
+    w = inputs.workload('rsa216', 0)
+    c = w['centers']
+    M = c.shape[0]
+    FT = inputs.random_forces(100, M, k=6)
+    out = {}
+    for mode in ('plain', 'one', 'two'):
+        with binding.Context(c, None, 12, 24, gmres_tol=1e-8, precision='mixed', tune_K=6, side_stream=True,
+                             precond=False if mode == 'plain' else 'eager', precond_coarse=mode == 'two') as ctx:
+            out[mode] = ctx.mobility_apply_multi(FT)
+    say('rsa216 K=6 its plain', out['plain'][1]['gmres_iters'], 'one level', out['one'][1]['gmres_iters'],
+        'two levels', out['two'][1]['gmres_iters'], 'setup ms', round(out['two'][1]['t_precond_ms'], 1),
+        'diff', rel(out['two'][0], out['plain'][0]))
+    assert out['two'][1]['converged'] == 1
+    assert rel(out['two'][0], out['plain'][0]) < 1e-6
+    assert out['two'][1]['gmres_iters'] < 0.8 * out['one'][1]['gmres_iters']
+
+
+def test_two_level_packing64_fp64_equals_plain():
+    """64 spheres at gaps down to 0.01 (close class on), FP64: the plain velocities."""
+    w = inputs.workload('packing64', 0)
+    c = w['centers']
+    FT = inputs.random_forces(7, c.shape[0])
+    kw = dict(gmres_tol=1e-10, near_close_gap=0.05, near_close_up=3)
+    out = {}
+    for mode in ('plain', 'two'):
+        with binding.Context(c, None, 12, 24, precond='eager' if mode == 'two' else False,
+                             precond_coarse=mode == 'two', **kw) as ctx:
+            out[mode] = ctx.mobility_apply(FT)
+    say('packing64 two-level its', out['plain'][1]['gmres_iters'], out['two'][1]['gmres_iters'], 'diff',
+        rel(out['two'][0], out['plain'][0]))
+    assert out['two'][1]['converged'] == 1
+    assert rel(out['two'][0], out['plain'][0]) < 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_two_level_side_stream_is_bit_identical(prec):
+    """With the side stream the coarse level's Z c accumulation follows the D^-1 v GEMM on
+    that stream: bit for bit the one-stream result, K = 1 and 6."""
+    w = inputs.workload('lattice27', 1)
+    c = w['centers']
+    out = {}
+    for side in (False, True):
+        with binding.Context(c, None, 8, 16, precision=prec, gmres_tol=1e-10, side_stream=side,
+                             precond='eager', precond_coarse=True) as ctx:
+            r = []
+            for K in (1, 6):
+                U, st = ctx.mobility_apply_multi(inputs.random_forces(30 + K, c.shape[0], k=K))
+                assert st['converged'] == 1
+                r.append(U)
+            out[side] = r
+    for a, b in zip(out[False], out[True]):
+        assert np.array_equal(a, b)
+
+
+def test_two_level_lcp_and_step_equal_plain(tiny_cases):
+    """An LCP solve and a time step with the two-level preconditioner (built on reuse)."""
+    _, g, _ = tiny_cases[0]
+    ax = inputs.janus_axes(3, g.M)
+    res = {}
+    b = None
+    for pc in (False, True):
+        with binding.Context(g.c, ax, 8, 16, lo=(4, 8), gmres_tol=1e-11, precond=pc, precond_coarse=pc) as ctx:
+            pairs, gaps = ctx.find_contacts(0.1)
+            if b is None:
+                xs, ws = inputs.planted_lcp(4, len(pairs))
+                b = ws - ctx.lcp_apply(pairs, xs)
+            x, lst = ctx.lcp_solve(pairs, b, 'bi')
+            ctx.step(0.1, 0.1, 'mono')
+            res[pc] = (x, ctx.get_state()[0])
+    assert rel(res[True][0], res[False][0]) < 1e-8
+    assert np.abs(res[True][1] - res[False][1]).max() < 1e-10
+
+
+def test_two_level_is_refused_for_batch_contexts():
+    inst = inputs.batched_suspensions(0, n_inst=2)
+    with pytest.raises(Exception, match='precond_coarse'):
+        binding.BatchContext(inst, gmres_tol=1e-10, precond=True, precond_coarse=True)

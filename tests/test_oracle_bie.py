@@ -461,3 +461,46 @@ def test_right_preconditioned_gmres_solves_the_same_system(tiny_cases):
     assert np.linalg.norm(A @ x1 - rhs.ravel()) <= 1.01e-11 * np.linalg.norm(rhs)
     assert np.abs(x1 - q).max() < 1e-9 * np.abs(q).max()
     assert i1 < 0.6 * i0
+
+
+def test_two_level_preconditioner_pins():
+    """The coarse correction of the two-level preconditioner (degree <= 2 harmonics per
+    sphere): R Z = I (the projection inverts the synthesis), one sphere gives A^{-1}
+    (its near-patch part already is), and A~ P2 maps every coarse vector Z c back to
+    itself whatever P: P2 (A~ Z c) = Z c, with A~ the operator whose far pairs use the
+    coarse source grid (checked with P = 0, so only the coarse part is tested)."""
+    rng = np.random.default_rng(5)
+    g = bie.Geometry([[0.2, -0.1, 0.4]], 1.0, 6, 12)
+    A = bie.dense_operator(g)
+    P2 = bie.two_level_preconditioner(g, A, bie.near_patch_preconditioner(g, A), coarse_theta=3)
+    v = rng.standard_normal(A.shape[0])
+    assert np.abs(A @ P2(v) - v).max() < 1e-11 * np.abs(v).max()
+    # four spheres, far pairs among them, a null fine part
+    c = [[0.0, 0.0, 0.0], [2.3, 0.2, 0.1], [0.1, 3.1, -0.2], [4.0, 3.0, 1.0]]
+    g = bie.Geometry(c, 1.0, 6, 12)
+    A = bie.dense_operator(g)
+    zero = lambda w: np.zeros_like(np.asarray(w).ravel())  # noqa: E731
+    P2 = bie.two_level_preconditioner(g, A, zero, coarse_theta=3)
+    Z, At = P2.Z, P2.At
+    assert np.abs(At - A).max() > 1e-6 * np.abs(A).max()  # the far pairs differ
+    cc = rng.standard_normal(Z.shape[1])
+    z = Z @ cc
+    assert np.abs(P2(At @ z) - z).max() < 1e-10 * np.abs(z).max()
+    # exact coarse far (A~ = A): the same on A
+    P2e = bie.two_level_preconditioner(g, A, zero)
+    assert np.abs(P2e(A @ z) - z).max() < 1e-10 * np.abs(z).max()
+
+
+def test_two_level_gmres_solves_the_same_system_in_fewer_iterations(tiny_cases):
+    """The two-level preconditioner changes the Krylov space only: the dense solve's
+    density, in no more iterations than the near-patch preconditioner alone."""
+    _, g, A = tiny_cases[0]
+    rhs = -bie.completion(g, inputs.random_forces(22, g.M))
+    q = np.linalg.solve(A, rhs.ravel())
+    P = bie.near_patch_preconditioner(g, A)
+    x1, i1, _ = bie.gmres(lambda v: A @ v.ravel(), rhs, tol=1e-11, right=P)
+    P2 = bie.two_level_preconditioner(g, A, P, coarse_theta=4)
+    x2, i2, rr = bie.gmres(lambda v: A @ v.ravel(), rhs, tol=1e-11, right=P2)
+    assert rr <= 1e-11
+    assert np.abs(x2 - q).max() < 1e-9 * np.abs(q).max()
+    assert i2 <= i1
