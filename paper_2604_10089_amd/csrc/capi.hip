@@ -85,6 +85,9 @@ static std::string check_desc(const pqn_config_desc& c) {
     return "far_coarse_lo2 needs a second low-fidelity grid and 2 <= far_coarse_lo2 <= n_theta_lo2";
   if (c.precond < 0 || c.precond > 2) return "precond must be 0, 1 or 2";
   if (c.precond_coarse < 0 || c.precond_coarse > 1) return "precond_coarse must be 0 or 1";
+  if (c.precond_coarse && (c.n_theta < 3 || (long)c.n_theta * c.n_phi > 512 ||
+                           (c.n_theta_lo != 0 && c.n_theta_lo < 3) || (c.n_theta_lo2 != 0 && c.n_theta_lo2 < 3)))
+    return "precond_coarse needs n_theta >= 3 on every grid and at most 512 nodes per sphere";
   return "";
 }
 

@@ -419,8 +419,7 @@ __global__ __launch_bounds__(256) void k_pc_sum_multi(const PcDesc* __restrict__
 
 // ------------------------------------------------- coarse level (precond_coarse)
 
-constexpr int kMaxCoarseNodes = 256;   // coarse far-source nodes per sphere (ntc <= 11)
-constexpr double kCoarseTol = 1e-4;    // Newton-Schulz stop for inv(E)
+constexpr double kCoarseTol = 1e-4;    // Newton-Schulz stop for inv(E) (FP32 storage: 1e-7)
 constexpr double kCoarseKeep = 1e-1;   // above this after the last step the coarse level stays off
 constexpr int kCoarseMaxSteps = 12;
 constexpr int kCmvCols = 256;          // columns of inv(E) per workgroup of the coarse product
@@ -457,6 +456,26 @@ __global__ __launch_bounds__(256) void k_blockdiag(const double* __restrict__ X0
   X[e] = (r / kCoarseB == col / kCoarseB) ? X0[(col % kCoarseB) * kCoarseB + r % kCoarseB] : 0.0;
 }
 
+// res[col] = sum over the rows of column col of (I - W)^2 (W by columns; the host adds the
+// columns in order).
+__global__ __launch_bounds__(256) void k_col_residual(const double* __restrict__ W, long m, double* __restrict__ res) {
+  __shared__ double sh[256];
+  const long col = blockIdx.x;
+  const double* w = W + col * m;
+  double acc = 0.0;
+  for (long r = threadIdx.x; r < m; r += 256) {
+    const double d = (r == col ? 1.0 : 0.0) - w[r];
+    acc = fma(d, d, acc);
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) res[col] = sh[0];
+}
+
 __global__ __launch_bounds__(256) void k_to_f32(const double* __restrict__ x, long len, float* __restrict__ y) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e < len) y[e] = (float)x[e];
@@ -466,27 +485,34 @@ __global__ __launch_bounds__(256) void k_to_f32(const double* __restrict__ x, lo
 // sum_x T(k', x) u_c'(x) with u the far double layer at sphere i's node x of the density
 // e_c Y_k on sphere j, summed on the coarse source grid (offsets offc, weights wc, harmonics
 // Yc): u_c'(x) = s sum_f (r.o_f) / |r|^5 r_c' r_c wc_f Y_k(f), r = x - y_f, s = 3 / (4 pi a).
-// Workgroup per sphere pair; thread per target (as many passes as needed); the six products
-// r_c r_c' (symmetric) x nine harmonics are accumulated per target, projected on the nine
-// analysis rows, summed over the wave by shuffles and over the waves in LDS (fixed order).
-__global__ __launch_bounds__(256) void k_coarse_far_blocks(const double* __restrict__ ctr,
-                                                           const double* __restrict__ off,
-                                                           const unsigned char* __restrict__ cls,
-                                                           const double* __restrict__ offc,
-                                                           const double* __restrict__ wc,
-                                                           const double* __restrict__ Yc,
-                                                           const double* __restrict__ Tlow, int n, int ncs, int M,
-                                                           double a, double* __restrict__ E) {
-  constexpr int NP = 6, NV = NP * kCoarseL, NQ = kCoarseL * NV;  // 54 per target, 486 projected
-  __shared__ double sy[kMaxCoarseNodes][6];                     // source position (rel. c_i), offset
-  __shared__ double swy[kMaxCoarseNodes][kCoarseL];             // s wc Y_k
-  __shared__ double red[4][NQ];
+// Workgroup per sphere pair, thread per target (64 ceil(n / 64) threads): the six products
+// r_c r_c' (symmetric) x nine harmonics are accumulated per target; the projection on the
+// nine analysis rows goes through LDS, a third of the 54 sums at a time (each output a dot
+// product over the targets in a fixed order).
+constexpr int kCfbMaxWaves = 8;  // one target per thread: n <= 512 nodes per sphere
+constexpr int kCfbChunk = 18;    // u values per target staged in LDS at a time (54 = 3 x 18)
+__global__ __launch_bounds__(64 * kCfbMaxWaves) void k_coarse_far_blocks(const double* __restrict__ ctr,
+                                                                         const double* __restrict__ off,
+                                                                         const unsigned char* __restrict__ cls,
+                                                                         const double* __restrict__ offc,
+                                                                         const double* __restrict__ wc,
+                                                                         const double* __restrict__ Yc,
+                                                                         const double* __restrict__ Tlow, int n,
+                                                                         int ncs, int M, double a,
+                                                                         double* __restrict__ E) {
+  constexpr int NP = 6, NV = NP * kCoarseL;  // 54 per target
+  // dynamic LDS: source positions (rel. c_i) and offsets [ncs][6], s wc Y_k [ncs][9], staged u
+  // [blockDim][kCfbChunk + 1] (padded rows)
+  extern __shared__ double lds_cfb[];
+  double(*sy)[6] = reinterpret_cast<double(*)[6]>(lds_cfb);
+  double(*swy)[kCoarseL] = reinterpret_cast<double(*)[kCoarseL]>(lds_cfb + 6 * ncs);
+  double(*su)[kCfbChunk + 1] = reinterpret_cast<double(*)[kCfbChunk + 1]>(lds_cfb + (6 + kCoarseL) * ncs);
   const int i = blockIdx.x / M, j = blockIdx.x - (blockIdx.x / M) * M;
   if (i == j || cls[(size_t)i * M + j] != 0) return;  // uniform over the block
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int t = threadIdx.x;
   const double dx = ctr[3 * j] - ctr[3 * i], dy = ctr[3 * j + 1] - ctr[3 * i + 1], dz = ctr[3 * j + 2] - ctr[3 * i + 2];
   const double s = 3.0 / (4.0 * kPi * a);
-  for (int f = t; f < ncs; f += 256) {
+  for (int f = t; f < ncs; f += blockDim.x) {
     sy[f][0] = dx + offc[3 * f];
     sy[f][1] = dy + offc[3 * f + 1];
     sy[f][2] = dz + offc[3 * f + 2];
@@ -495,53 +521,47 @@ __global__ __launch_bounds__(256) void k_coarse_far_blocks(const double* __restr
     sy[f][5] = offc[3 * f + 2];
     for (int k = 0; k < kCoarseL; ++k) swy[f][k] = s * wc[f] * Yc[f * kCoarseL + k];
   }
-  for (int q = t; q < 4 * NQ; q += 256) (&red[0][0])[q] = 0.0;
   __syncthreads();
-  for (int x0 = 0; x0 < n; x0 += 256) {
-    const int x = x0 + t;
-    const bool valid = x < n;
-    const int xx = valid ? x : n - 1;
-    const double Xx = off[3 * xx], Xy = off[3 * xx + 1], Xz = off[3 * xx + 2];
-    double u[NV];
+  const bool valid = t < n;
+  const int xx = valid ? t : n - 1;
+  const double Xx = off[3 * xx], Xy = off[3 * xx + 1], Xz = off[3 * xx + 2];
+  double u[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) u[q] = 0.0;
-    for (int f = 0; f < ncs; ++f) {
-      const double rx = Xx - sy[f][0], ry = Xy - sy[f][1], rz = Xz - sy[f][2];
-      const double r2 = rx * rx + ry * ry + rz * rz;
-      const double ri = 1.0 / sqrt(r2);
-      const double ri2 = ri * ri;
-      const double g = (rx * sy[f][3] + ry * sy[f][4] + rz * sy[f][5]) * ri * ri2 * ri2;
-      const double tp[NP] = {g * rx * rx, g * rx * ry, g * rx * rz, g * ry * ry, g * ry * rz, g * rz * rz};
+  for (int q = 0; q < NV; ++q) u[q] = 0.0;
+  for (int f = 0; f < ncs; ++f) {
+    const double rx = Xx - sy[f][0], ry = Xy - sy[f][1], rz = Xz - sy[f][2];
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    const double ri = 1.0 / sqrt(r2);
+    const double ri2 = ri * ri;
+    const double g = (rx * sy[f][3] + ry * sy[f][4] + rz * sy[f][5]) * ri * ri2 * ri2;
+    const double tp[NP] = {g * rx * rx, g * rx * ry, g * rx * rz, g * ry * ry, g * ry * rz, g * rz * rz};
 #pragma unroll
-      for (int k = 0; k < kCoarseL; ++k) {
-        const double wy = swy[f][k];
+    for (int k = 0; k < kCoarseL; ++k) {
+      const double wy = swy[f][k];
 #pragma unroll
-        for (int p = 0; p < NP; ++p) u[p * kCoarseL + k] = fma(tp[p], wy, u[p * kCoarseL + k]);
-      }
-    }
-    if (__any(valid)) {
-      for (int kp = 0; kp < kCoarseL; ++kp) {
-        const double tw = valid ? Tlow[(size_t)kp * n + x] : 0.0;
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-          double v = tw * u[q];
-#pragma unroll
-          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-          if (lane == 0) red[wv][kp * NV + q] += v;
-        }
-      }
+      for (int p = 0; p < NP; ++p) u[p * kCoarseL + k] = fma(tp[p], wy, u[p * kCoarseL + k]);
     }
   }
-  __syncthreads();
-  for (int q = t; q < NQ; q += 256) {
-    const double v = red[0][q] + red[1][q] + red[2][q] + red[3][q];
-    const int kp = q / NV, pk = q - kp * NV, p = pk / kCoarseL, k = pk - p * kCoarseL;
-    // p -> (c, c'): 0 xx, 1 xy, 2 xz, 3 yy, 4 yz, 5 zz
-    const int ca = p < 3 ? 0 : (p < 5 ? 1 : 2);
-    const int cb = p < 3 ? p : (p < 5 ? p - 2 : 2);
-    const size_t Mc = (size_t)M * kCoarseB;
-    E[((size_t)j * kCoarseB + cb * kCoarseL + k) * Mc + (size_t)i * kCoarseB + ca * kCoarseL + kp] = v;
-    if (ca != cb) E[((size_t)j * kCoarseB + ca * kCoarseL + k) * Mc + (size_t)i * kCoarseB + cb * kCoarseL + kp] = v;
+  const size_t Mc = (size_t)M * kCoarseB;
+#pragma unroll
+  for (int ch = 0; ch < NV / kCfbChunk; ++ch) {
+#pragma unroll
+    for (int q = 0; q < kCfbChunk; ++q) su[t][q] = valid ? u[ch * kCfbChunk + q] : 0.0;
+    __syncthreads();
+    // outputs (k', q) of this chunk: 9 x 18 dot products over the targets
+    for (int o = t; o < kCoarseL * kCfbChunk; o += blockDim.x) {
+      const int kp = o / kCfbChunk, q = o - kp * kCfbChunk;
+      const double* tr = Tlow + (size_t)kp * n;
+      double v = 0.0;
+      for (int x = 0; x < n; ++x) v = fma(tr[x], su[x][q], v);
+      const int pk = ch * kCfbChunk + q, p = pk / kCoarseL, k = pk - p * kCoarseL;
+      // p -> (c, c'): 0 xx, 1 xy, 2 xz, 3 yy, 4 yz, 5 zz
+      const int ca = p < 3 ? 0 : (p < 5 ? 1 : 2);
+      const int cb = p < 3 ? p : (p < 5 ? p - 2 : 2);
+      E[((size_t)j * kCoarseB + cb * kCoarseL + k) * Mc + (size_t)i * kCoarseB + ca * kCoarseL + kp] = v;
+      if (ca != cb) E[((size_t)j * kCoarseB + ca * kCoarseL + k) * Mc + (size_t)i * kCoarseB + cb * kCoarseL + kp] = v;
+    }
+    __syncthreads();  // su is rewritten by the next chunk
   }
 }
 
@@ -1031,32 +1051,45 @@ void pqn_ctx_impl::coarse_setup(Level& lv) {
     char* base = push_desc_pack(dp.host);
     launch_gemm64_multi(s, (const GemmDesc*)(base + on), (int)gn.size(), ngn);
   }
-  hipLaunchKernelGGL(k_coarse_far_blocks, dim3(M * M), dim3(256), 0, s, ctr.p, lv.off.p, cls.p, co.offc.p, co.wc.p,
+  if (n > 64 * kCfbMaxWaves) throw Error(PQN_ERR_INVALID, "precond_coarse supports at most 512 nodes per sphere");
+  const int cfb_threads = 64 * ((n + 63) / 64);
+  const size_t cfb_lds = sizeof(double) * ((size_t)(6 + kCoarseL) * co.ncs + (size_t)cfb_threads * (kCfbChunk + 1));
+  if (cfb_lds > 65536)
+    HIPCHK(hipFuncSetAttribute((const void*)k_coarse_far_blocks, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)cfb_lds));
+  hipLaunchKernelGGL(k_coarse_far_blocks, dim3(M * M), dim3(cfb_threads), cfb_lds, s, ctr.p, lv.off.p, cls.p, co.offc.p, co.wc.p,
                      co.Yc.p, co.Tlow.p, n, co.ncs, M, a, co.E.p);
-  // inv(E): Newton-Schulz X <- X (2I - E X) from the block-diagonal inverse
+  // inv(E): Newton-Schulz X <- X (2I - E X) from the block-diagonal inverse. The residual
+  // squares at every step, so once it is below sqrt(kCoarseTol / 10) one more step is taken
+  // without a new residual (its estimate, the square, is what ns_res reports).
   co.X.alloc((size_t)Mc * Mc);
   co.X2.alloc((size_t)Mc * Mc);
   co.W.alloc((size_t)Mc * Mc);
-  co.res.alloc((size_t)kNsSlices);
+  co.res.alloc((size_t)Mc);
   hipLaunchKernelGGL(k_blockdiag, dim3(nblocks(Mc * Mc)), dim3(256), 0, s, co.X0.p, Mc, co.X.p);
-  std::vector<double> resp(kNsSlices);
+  std::vector<double> resp(Mc);
   co.ns_iters = 0;
   double res = 1e300;
   for (int step = 0;; ++step) {
     launch_gemm64_big(s, (int)Mc, (int)Mc, (int)Mc, co.E.p, (int)Mc, 0, co.X.p, 0, (int)Mc, co.W.p, 0, (int)Mc, 0,
                       (int)Mc, 1, 1);
-    hipLaunchKernelGGL(k_ns_residual, dim3(kNsSlices), dim3(256), 0, s, co.W.p, (int)Mc, co.res.p);
+    hipLaunchKernelGGL(k_col_residual, dim3((unsigned)Mc), dim3(256), 0, s, co.W.p, Mc, co.res.p);
     HIPCHK(hipMemcpyAsync(resp.data(), co.res.p, resp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     double tot = 0.0;
     for (double v : resp) tot += v;
     res = std::isfinite(tot) ? std::sqrt(tot / Mc) : 1e300;
     if (res <= kCoarseTol || step == kCoarseMaxSteps) break;
+    const bool last = res * res <= 0.1 * kCoarseTol;
     hipLaunchKernelGGL(k_diag_minus, dim3((unsigned)Mc), dim3(256), 0, s, co.W.p, (int)Mc, 2.0);
     launch_gemm64_big(s, (int)Mc, (int)Mc, (int)Mc, co.X.p, (int)Mc, 0, co.W.p, 0, (int)Mc, co.X2.p, 0, (int)Mc, 0,
                       (int)Mc, 1, 1);
     std::swap(co.X.p, co.X2.p);
     ++co.ns_iters;
+    if (last) {
+      res = res * res;
+      break;
+    }
   }
   co.ns_res = res;
   if (res > kCoarseKeep) return;  // the coarse level stays off for this configuration

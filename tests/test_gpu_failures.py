@@ -120,7 +120,8 @@ def test_unresolved_contact_makes_lcp_indefinite_and_step_refuses():
 def test_documented_limits_are_rejected_at_create():
     """Limits stated in the header give PQN_ERR_INVALID at context creation: more than 16
     near partners of one sphere, harmonic degree above 40, a grid with n_phi < 2 n_theta
-    - 1, near upsampling factors above 8."""
+    - 1, near upsampling factors above 8, the two-level preconditioner above 512 nodes per
+    sphere or on a grid with n_theta < 3."""
     # 17 spheres around a central one at centre distance 3.5 (gap 1.5 < near gap 2.0)
     k = np.arange(17) + 0.5
     th, ph = np.arccos(1.0 - 2.0 * k / 17), np.pi * (1.0 + 5.0 ** 0.5) * k
@@ -135,7 +136,9 @@ def test_documented_limits_are_rejected_at_create():
         pass  # 16 partners are accepted
     one = np.zeros((1, 3))
     for kw in (dict(n_theta=42, n_phi=84), dict(n_theta=8, n_phi=12), dict(n_theta=4, n_phi=8, near_up=9),
-               dict(n_theta=4, n_phi=8, near_close_gap=0.1, near_close_up=9)):
+               dict(n_theta=4, n_phi=8, near_close_gap=0.1, near_close_up=9),
+               dict(n_theta=20, n_phi=40, precond=True, precond_coarse=True),
+               dict(n_theta=8, n_phi=16, lo=(2, 4), precond=True, precond_coarse=True)):
         with pytest.raises(binding.PqnError) as e:
             binding.Context(one, None, **kw)
         assert e.value.status == PQN_ERR_INVALID, kw

@@ -338,3 +338,21 @@ def test_two_level_is_refused_for_batch_contexts():
     inst = inputs.batched_suspensions(0, n_inst=2)
     with pytest.raises(Exception, match='precond_coarse'):
         binding.BatchContext(inst, gmres_tol=1e-10, precond=True, precond_coarse=True)
+
+
+def test_two_level_fine_grid_lattice27():
+    """27 spheres at 16x32 nodes (512 per sphere, the largest grid the two-level form takes;
+    its far-block kernel then needs more than 64 KB of LDS): the plain FP64 velocities."""
+    w = inputs.workload('lattice27', 1)
+    c = w['centers']
+    FT = inputs.random_forces(8, c.shape[0])
+    out = {}
+    for mode in ('plain', 'two'):
+        with binding.Context(c, None, 16, 32, gmres_tol=1e-10, precond='eager' if mode == 'two' else False,
+                             precond_coarse=mode == 'two') as ctx:
+            out[mode] = ctx.mobility_apply(FT)
+    say('lattice27 16x32 two-level its', out['plain'][1]['gmres_iters'], out['two'][1]['gmres_iters'],
+        'diff', rel(out['two'][0], out['plain'][0]))
+    assert out['two'][1]['converged'] == 1
+    assert rel(out['two'][0], out['plain'][0]) < 1e-8
+    assert out['two'][1]['gmres_iters'] < out['plain'][1]['gmres_iters']
