@@ -435,6 +435,29 @@ __global__ __launch_bounds__(256) void k_far64(const double* __restrict__ src, c
   far64_body<K>(item % ntb, item / ntb, src, off, ctr, cls, n, ns, M, N, spc, scale, part);
 }
 
+// The same pair sums launched by the preconditioner's coarse level (far pairs of its
+// coarse operator, sources on the coarse grid): kernels of their own, so that profiles
+// keep them apart from the operator's far launches.
+template <int K>
+__global__ __launch_bounds__(256) void k_far32c(const float* __restrict__ src, const double* __restrict__ off,
+                                                const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
+                                                int n, int ns, int M, int N, int spc, double scale, OPtrs part,
+                                                int ntb, int total, int per) {
+  const int item = xcd_item(blockIdx.x, per);
+  if (item >= total) return;
+  far32_body<1, K>(item % ntb, item / ntb, src, off, ctr, cls, n, ns, M, N, spc, scale, part);
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_far64c(const double* __restrict__ src, const double* __restrict__ off,
+                                                const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
+                                                int n, int ns, int M, int N, int spc, double scale, OPtrs part,
+                                                int ntb, int total, int per) {
+  const int item = xcd_item(blockIdx.x, per);
+  if (item >= total) return;
+  far64_body<K>(item % ntb, item / ntb, src, off, ctr, cls, n, ns, M, N, spc, scale, part);
+}
+
 __global__ __launch_bounds__(256) void k_far64_multi(const FarDesc* __restrict__ desc, int ndesc) {
   const int item = blockIdx.x;
   int d = 0;
@@ -1342,6 +1365,34 @@ void launch_far(hipStream_t s, int prec, int K, int tpt, const void* src, const 
     case 4: far_k<4>(s, prec, t1, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
     case 5: far_k<5>(s, prec, t1, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
     default: far_k<6>(s, prec, t1, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
+  }
+}
+
+template <int K>
+static void far_kc(hipStream_t s, int prec, const void* src, const double* off, const double* ctr,
+                   const unsigned char* cls, int n, int ns, int M, int N, int spc, int nchunks, double scale,
+                   const OPtrs& part) {
+  const int ntb = (int)nblk(N, 256);
+  const int total = ntb * nchunks, per = (total + kXcds - 1) / kXcds;
+  const dim3 grid(per * kXcds);
+  if (prec == 1)
+    hipLaunchKernelGGL(k_far32c<K>, grid, dim3(256), 0, s, (const float*)src, off, ctr, cls, n, ns, M, N, spc, scale,
+                       part, ntb, total, per);
+  else
+    hipLaunchKernelGGL(k_far64c<K>, grid, dim3(256), 0, s, (const double*)src, off, ctr, cls, n, ns, M, N, spc,
+                       scale, part, ntb, total, per);
+}
+
+void launch_far_coarse(hipStream_t s, int prec, int K, const void* src, const double* off, const double* ctr,
+                       const unsigned char* cls, int n, int ns, int M, int N, int spc, int nchunks, double scale,
+                       const OPtrs& part) {
+  switch (K) {
+    case 1: far_kc<1>(s, prec, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
+    case 2: far_kc<2>(s, prec, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
+    case 3: far_kc<3>(s, prec, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
+    case 4: far_kc<4>(s, prec, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
+    case 5: far_kc<5>(s, prec, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
+    default: far_kc<6>(s, prec, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
   }
 }
 

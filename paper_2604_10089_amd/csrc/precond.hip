@@ -1143,8 +1143,10 @@ void pqn_ctx_impl::coarse_pre(MvGroup& gr) {
   launch_pack_coarse(s, pc_prec, K, co.qc.p, co.offc.p, co.wc.p, co.ncs, M * co.ncs, lv.src.p);
   OPtrs fp{};
   for (int r = 0; r < K; ++r) fp.p[r] = lv.wk(r).far_part.p;
-  launch_far(s, pc_prec, K, lv.tpt, lv.src.p, lv.off.p, ctr.p, cls.p, n, co.ncs, M, N, lv.spc, lv.nchunks,
-             3.0 / (4.0 * kPi * a), fp);
+  // the level's source chunks (with fewer, e.g. 6 of 24, the launch has too few waves to
+  // balance: 1.22 against 0.90 ms for six densities at 216 spheres)
+  launch_far_coarse(s, pc_prec, K, lv.src.p, lv.off.p, ctr.p, cls.p, n, co.ncs, M, N, lv.spc, lv.nchunks,
+                    3.0 / (4.0 * kPi * a), fp);
   hipLaunchKernelGGL(k_coarse_resid, dim3(nblocks((long)K * M * n3)), dim3(256), 0, s, lv.pc.vC.p, co.bpart.p,
                      co.bptr.p, fp, lv.nchunks, K, n, M, N);
 }
