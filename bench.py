@@ -244,12 +244,14 @@ def main():
             setup_ms += st['t_precond_ms']
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        its = far_ms = nfar = mv = pc_ms = pc_n = pc_setup_timed = 0
+        its = far_ms = nfar = mv = pc_ms = pc_n = pc_setup_timed = far_k_ms = nfar_k = 0
         for k in range(steps):
             st = ctx.mobility_apply_multi_dev(kr, FT6_dev[warm + k].data_ptr(), UO_dev.data_ptr())
             its += st['gmres_iters']
             far_ms += st['t_far_ms']
             nfar += st['n_far']
+            far_k_ms += st['t_far_by_k_ms'][kr - 1]  # the launches with all kr densities
+            nfar_k += st['n_far_by_k'][kr - 1]
             mv += st['matvecs']
             pc_ms += st['t_precond_apply_ms']
             pc_n += st['precond_applies']
@@ -257,7 +259,8 @@ def main():
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         return dict(steps=steps, sec=sec, mvps=steps * kr / sec, gmres_iters=its / (steps * kr),
-                    far_ms=far_ms / max(nfar, 1), matvecs_per_mvp=mv / (steps * kr), far_launches=nfar,
+                    far_ms=far_k_ms / max(nfar_k, 1), far_ms_all=far_ms / max(nfar, 1), far_launches_full=nfar_k,
+                    matvecs_per_mvp=mv / (steps * kr), far_launches=nfar,
                     precond_setup_ms=setup_ms, precond_setup_in_timed_ms=pc_setup_timed,
                     precond_apply_ms=pc_ms / max(pc_n, 1), precond_applies=pc_n)
 

@@ -173,6 +173,10 @@ typedef struct {
   int32_t precond_applies;  /* precond = 1: applications of the preconditioner (one per group of
                                densities per GMRES iteration, one per system per cycle end) */
   double t_precond_apply_ms; /* profile = 1: summed HIP-event time of those applications */
+  double t_far_by_k_ms[6];  /* profile = 1: far pair-sum time of the launches with k + 1 densities
+                               (single-suspension contexts; the lockstep solves' tail launches
+                               have fewer densities than the call) */
+  int32_t n_far_by_k[6];    /* those launches' counts */
 } pqn_mvp_stats;
 
 typedef struct {

@@ -78,7 +78,8 @@ class MvpStats(C.Structure):
                 ('fp64_fallback', C.c_int32), ('t_near_ms', C.c_double), ('t_gemm_ms', C.c_double),
                 ('t_local_ms', C.c_double), ('t_arnoldi_ms', C.c_double), ('t_precond_ms', C.c_double),
                 ('precond_fallback', C.c_int32), ('precond_applies', C.c_int32),
-                ('t_precond_apply_ms', C.c_double)]
+                ('t_precond_apply_ms', C.c_double), ('t_far_by_k_ms', C.c_double * 6),
+                ('n_far_by_k', C.c_int32 * 6)]
 
 
 class LcpOpts(C.Structure):
@@ -105,7 +106,11 @@ def _struct_dict(s):
     out = {}
     for name, _ in s._fields_:
         v = getattr(s, name)
-        out[name] = _struct_dict(v) if isinstance(v, C.Structure) else v
+        if isinstance(v, C.Structure):
+            v = _struct_dict(v)
+        elif isinstance(v, C.Array):
+            v = list(v)
+        out[name] = v
     return out
 
 

@@ -1,4 +1,5 @@
 // extern "C" entry points: argument checks, host/device copies, error mapping.
+#include <algorithm>
 #include <cstring>
 
 #include "context.hpp"
@@ -54,6 +55,10 @@ static void stage_stats(const pqn_ctx_impl& c, pqn_mvp_stats& st) {
   st.precond_fallback = c.pc_fallback;
   st.precond_applies = c.pc_applies;
   st.t_precond_apply_ms = c.stage_ms[pqn_ctx_impl::kStagePrecond];
+  for (int k = 0; k < kMaxRhs; ++k) {
+    st.t_far_by_k_ms[k] = c.stage_ms[pqn_ctx_impl::kStageFarK + k];
+    st.n_far_by_k[k] = c.n_far_k[k];
+  }
 }
 
 // nullptr if the context has the fidelities the (valid) solver needs, else the reason.
@@ -208,6 +213,7 @@ static pqn_status batch_apply_common(pqn_ctx* ctx, const double* const* FT, doub
   ctx->pc_fallback = 0;
   ctx->pc_applies = 0;
   ctx->n_far = 0;
+  std::fill(ctx->n_far_k, ctx->n_far_k + kMaxRhs, 0);
   for (auto& ch : ctx->children) {
     ch->pc_setup_ms = 0.0;
     ch->pc_fallback = 0;
@@ -304,6 +310,7 @@ static pqn_status mobility_multi_common(pqn_ctx* ctx, int32_t k_rhs, const doubl
   ctx->pc_fallback = 0;
   ctx->pc_applies = 0;
   ctx->n_far = 0;
+  std::fill(ctx->n_far_k, ctx->n_far_k + kMaxRhs, 0);
   pqn_mvp_stats st{};
   ctx->mobility_multi(lv, k_rhs, fp, nullptr, up, &st);
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -401,6 +408,7 @@ static pqn_status mobility_common(pqn_ctx* ctx, const double* FT_dev, const doub
   ctx->pc_fallback = 0;
   ctx->pc_applies = 0;
   ctx->n_far = 0;
+  std::fill(ctx->n_far_k, ctx->n_far_k + kMaxRhs, 0);
   ctx->mobility(lv, FT_dev, axes_dev, UO_dev, &st);
   HIPCHK(hipStreamSynchronize(ctx->stream));
   st.t_far_ms = ctx->end_far_timing();
@@ -519,8 +527,9 @@ pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, doub
     ctx->n_graph_launch = 0;
     ctx->pc_setup_ms = 0.0;
     ctx->pc_fallback = 0;
-  ctx->pc_applies = 0;
+    ctx->pc_applies = 0;
     ctx->n_far = 0;
+    std::fill(ctx->n_far_k, ctx->n_far_k + kMaxRhs, 0);
     SysBuf& b = lv.sb(0);
     HIPCHK(hipMemcpyAsync(b.rhs.p, rhs, len * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     pqn_mvp_stats st{};

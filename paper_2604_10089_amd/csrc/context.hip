@@ -404,6 +404,8 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
     stage_end(kStageLocal);
   }
   begin_far_timing();
+  const int kf = groups.size() == 1 ? groups[0].K : 0;  // one group: its launches are also timed by K
+  if (kf) stage_begin(kStageFarK + kf - 1);
   {
     for (MvGroup& gr : groups) {
       Level& lv = *gr.lv;
@@ -412,6 +414,10 @@ void pqn_ctx_impl::matvec_groups(std::vector<MvGroup>& groups, int precision) {
       launch_far(s, prec, gr.K, lv.tpt, lv.src.p, lv.off.p, gr.c->ctr.p, gr.c->cls.p, lv.n, lv.nc > 0 ? lv.nc : lv.n,
                  lv.M, lv.N, lv.spc, lv.nchunks, 3.0 / (4.0 * kPi * gr.c->a), op);
     }
+  }
+  if (kf) {
+    stage_end(kStageFarK + kf - 1);
+    ++n_far_k[kf - 1];
   }
   end_far_launch();
   ++n_far;

@@ -389,13 +389,16 @@ struct pqn_ctx_impl {
   // profiling of far launches
   // profile = 1: HIP events around every launch of each stage of the operator, on the
   // main stream (the side stream is not used while profiling)
-  enum { kStageFar = 0, kStageNear, kStageGemm, kStageLocal, kStageArnoldi, kStagePrecond, kNumStages };
+  // kStageFarK + K - 1: the far launches of one group with K densities
+  enum { kStageFar = 0, kStageNear, kStageGemm, kStageLocal, kStageArnoldi, kStagePrecond, kStageFarK,
+         kNumStages = kStageFarK + kMaxRhs };
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[kNumStages];
   size_t ev_used[kNumStages] = {};
   double stage_ms[kNumStages] = {};  // totals of the last end_far_timing()
   void stage_begin(int st);
   void stage_end(int st);
   int n_matvec = 0, n_far = 0;
+  int n_far_k[kMaxRhs] = {};  // far launches of one group by its density count
   unsigned long config_epoch = 1;  // bumped by every configuration change (invalidates graphs)
   int n_graph_launch = 0;
   LcpState* lcp = nullptr;

@@ -110,7 +110,7 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         body = re.sub(r'/\*.*?\*/', '', body, flags=re.S)
         names = []
         for decl in body.split(';'):
-            decl = ' '.join(decl.split())
+            decl = re.sub(r'\[[^\]]*\]', '', ' '.join(decl.split()))
             if not decl:
                 continue
             m = re.match(r'.*\(\s*\*\s*(\w+)\s*\)', decl)
