@@ -140,7 +140,7 @@ typedef struct {
                                the near-patch preconditioner P_f: z1 = Z inv(E) R v,
                                z = z1 + P_f (v - A~ z1), E = R A~ Z, R the projection on those
                                harmonics, Z their synthesis, A~ the operator with its far pairs
-                               summed on a coarse source grid (n_theta / 2 rows, at least 3):
+                               summed on a coarse source grid of 4 x 8 nodes:
                                the far field's smooth low modes, which the near patches cannot
                                reach, are solved for directly. Built with the rest of the
                                preconditioner; inv(E) by Newton-Schulz, stored in FP32 (about

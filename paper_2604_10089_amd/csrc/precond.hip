@@ -419,6 +419,11 @@ __global__ __launch_bounds__(256) void k_pc_sum_multi(const PcDesc* __restrict__
 
 // ------------------------------------------------- coarse level (precond_coarse)
 
+// Coarse far-source grid: kCoarseTheta x 2 kCoarseTheta nodes whatever the grid (its error is
+// that of integrating the far kernel against degree <= 2 densities, set by the geometry). At
+// 216 spheres, 12x24: 3x6 gives 11.0 GMRES iterations per MVP, 4x8 10.0, 5x10 9.5, 6x12 9.25;
+// the six-force-set pass takes 59.1, 56.0, 56.3 and 58.2 ms.
+constexpr int kCoarseTheta = 4;
 constexpr double kCoarseTol = 1e-4;    // Newton-Schulz stop for inv(E) (FP32 storage: 1e-7)
 constexpr double kCoarseKeep = 1e-1;   // above this after the last step the coarse level stays off
 constexpr int kCoarseMaxSteps = 12;
@@ -898,8 +903,8 @@ void pqn_ctx_impl::precond_setup(Level& lv) {
 // ------------------------------------------------- coarse level (precond_coarse): set-up
 
 // Tables of the level (once): R, Z, D Z, R D Z and its inverse, the analysis rows of the
-// degree <= 2 harmonics, the coarse far-source grid (n_theta / 2 rows, at least 3, at most
-// 11), and the application's GEMM descriptors (R v; y += Z c) for K = 1 .. kMaxRhs.
+// degree <= 2 harmonics, the coarse far-source grid, and the application's GEMM descriptors
+// (R v; y += Z c) for K = 1 .. kMaxRhs.
 void pqn_ctx_impl::coarse_tables(Level& lv) {
   CoarsePc& co = lv.pc.co;
   if (co.tab) return;
@@ -939,7 +944,7 @@ void pqn_ctx_impl::coarse_tables(Level& lv) {
   invert_gauss_jordan(X0r, kCoarseB);  // row-major inverse of R D Z
   for (int b = 0; b < kCoarseB; ++b)
     for (int bp = 0; bp < kCoarseB; ++bp) X0[(size_t)b * kCoarseB + bp] = X0r[(size_t)bp * kCoarseB + b];
-  const int ntc = std::min(11, std::max(3, lv.tab.n_theta / 2));
+  const int ntc = kCoarseTheta;
   std::vector<double> oc, wcv, Yc;
   coarse_sh_grid(ntc, 2 * ntc, a, 2, oc, wcv, Yc);
   co.ncs = ntc * 2 * ntc;
