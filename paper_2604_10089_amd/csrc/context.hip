@@ -1202,7 +1202,7 @@ void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision)
       stage_end(kStageArnoldi);
     }
     readback();
-    std::vector<int> need_restart;
+    std::vector<int> need_restart, pc_end;
     std::vector<ComboDesc> scale_list;
     int scale_total = 0;
     for (int i : act) {
@@ -1250,11 +1250,10 @@ void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision)
       }
       HIPCHK(hipMemcpyAsync(b.ycoef.p, y.data(), dk * sizeof(double), hipMemcpyHostToDevice, s));
       if (pcs[i]) {
-        // x += P (V y) (in place in z; tmp may hold this system's right-hand side)
+        // x += P (V y): z = V y here (tmp may hold this system's right-hand side); P in
+        // place in z below, for all the systems whose cycle ends in this iteration at once
         launch_combo(s, b.z.p, 0.0, b.V.p, len, dk, b.ycoef.p, 1.0, len);
-        MvGroup g1{sr.c, sr.lv, 1, {sr.slot}, {b.z.p}, {b.z.p}};
-        sr.c->precond_apply(g1);
-        launch_axpby(s, sr.x, b.z.p, 1.0, 1.0, len);
+        pc_end.push_back(i);
       } else {
         launch_combo(s, sr.x, 1.0, b.V.p, len, dk, b.ycoef.p, 1.0, len);
       }
@@ -1281,6 +1280,15 @@ void pqn_ctx_impl::gmres_lockstep_eager(std::vector<SysRef>& sys, int precision)
       } else {
         need_restart.push_back(i);
       }
+    }
+    if (!pc_end.empty()) {
+      std::vector<MvGroup> eg;
+      for (int i : pc_end) {
+        SysBuf& b = sys[i].lv->sb(sys[i].slot);
+        add_to_groups(eg, sys[i].c, sys[i].lv, sys[i].slot, b.z.p, b.z.p);
+      }
+      precond_apply_groups(eg);
+      for (int i : pc_end) launch_axpby(s, sys[i].x, sys[i].lv->sb(sys[i].slot).z.p, 1.0, 1.0, len_of(i));
     }
     if (scale_list.size() == 1) {
       const ComboDesc& c0 = scale_list[0];
