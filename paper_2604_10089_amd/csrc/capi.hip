@@ -93,6 +93,8 @@ static std::string check_desc(const pqn_config_desc& c) {
   if (c.precond_coarse && (c.n_theta < 3 || (long)c.n_theta * c.n_phi > 512 ||
                            (c.n_theta_lo != 0 && c.n_theta_lo < 3) || (c.n_theta_lo2 != 0 && c.n_theta_lo2 < 3)))
     return "precond_coarse needs n_theta >= 3 on every grid and at most 512 nodes per sphere";
+  if (c.precond_coarse && c.n_particles > 1024)
+    return "precond_coarse supports at most 1024 spheres (its coarse matrix has (27 M)^2 entries)";
   return "";
 }
 

@@ -38,6 +38,12 @@ def test_invalid_create_rejected_without_device():
     d.n_theta, d.n_phi = 8, 8
     st = L.pqn_create(binding.C.byref(d), c.ctypes.data_as(binding._D), None, binding.C.byref(h))
     assert st == -1
+    # the two-level preconditioner's limit on the sphere count
+    d.n_particles, d.n_theta, d.n_phi, d.precond, d.precond_coarse = 1025, 8, 16, 1, 1
+    cc = np.zeros(3 * 1025)
+    st = L.pqn_create(binding.C.byref(d), cc.ctypes.data_as(binding._D), None, binding.C.byref(h))
+    assert st == -1 and h.value is None
+    assert b'precond_coarse' in L.pqn_last_error()
     assert L.pqn_destroy(None) == 0
 
 

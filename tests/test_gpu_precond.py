@@ -73,10 +73,14 @@ def test_lone_near_pair_is_solved_in_a_few_iterations():
     assert rel(y, rhs) < 1e-9
 
 
-def test_configuration_change_rebuilds_the_preconditioner(tiny_cases):
+@pytest.mark.parametrize("coarse", [False, True])
+def test_configuration_change_rebuilds_the_preconditioner(tiny_cases, coarse):
+    """A new configuration rebuilds the preconditioner (one or two levels) at its first solve;
+    a second product on the same configuration reuses it; both configurations' velocities are
+    the oracle's."""
     (_, g0, A0), (_, g1, A1) = tiny_cases
     FT = inputs.random_forces(11, g0.M)
-    with binding.Context(g0.c, None, 8, 16, gmres_tol=1e-11, precond='eager') as ctx:
+    with binding.Context(g0.c, None, 8, 16, gmres_tol=1e-11, precond='eager', precond_coarse=coarse) as ctx:
         U0, s0 = ctx.mobility_apply(FT)
         U0b, s0b = ctx.mobility_apply(FT)
         ctx.set_state(g1.c)
