@@ -360,3 +360,27 @@ def test_two_level_fine_grid_lattice27():
     assert out['two'][1]['converged'] == 1
     assert rel(out['two'][0], out['plain'][0]) < 1e-8
     assert out['two'][1]['gmres_iters'] < out['plain'][1]['gmres_iters']
+
+
+@pytest.mark.parametrize("case", ["one sphere", "no near pairs"])
+def test_two_level_without_near_pairs(case):
+    """The two-level preconditioner where the near patches are empty: one sphere (P2 is
+    then A^-1 up to the FP16 and Newton-Schulz roundings) and a dilute 2x2x2 lattice at
+    centre distance 3 (gap 1 > the near gap, so no near blocks at all: D^-1 plus the coarse
+    level). FP64 velocities as the oracle's dense solve."""
+    if case == "one sphere":
+        c = np.array([[0.3, -0.2, 0.1]])
+    else:
+        g = np.arange(2) * 3.0
+        c = np.array([[x, y, z] for x in g for y in g for z in g]) + 0.05 * np.random.default_rng(3).standard_normal((8, 3))
+    geo = bie.Geometry(c, 1.0, 8, 16)
+    A = bie.dense_operator(geo)
+    FT = inputs.random_forces(12, c.shape[0])
+    Uo = bie.mobility_apply(geo, FT, dense=A)
+    with binding.Context(c, None, 8, 16, gmres_tol=1e-11, precond='eager', precond_coarse=True) as ctx:
+        U, st = ctx.mobility_apply(FT)
+    say('two-level', case, 'its', st['gmres_iters'], 'err', rel(U, Uo))
+    assert st['converged'] == 1 and st['precond_applies'] > 0
+    assert rel(U, Uo) < 1e-9
+    if case == "one sphere":
+        assert st['gmres_iters'] <= 3
