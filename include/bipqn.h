@@ -145,7 +145,7 @@ typedef struct {
                                reach, are solved for directly. Built with the rest of the
                                preconditioner; inv(E) by Newton-Schulz, stored in FP32 (about
                                4 (27 M)^2 doubles during the set-up, whose Newton-Schulz GEMMs
-                               cost about 20 (27 M)^3 flop; n_theta >= 3, at most 512 nodes per
+                               cost about 14 (27 M)^3 flop; n_theta >= 3, at most 512 nodes per
                                sphere, at most 1024 spheres). Not for batch contexts
                                (PQN_ERR_INVALID) [0] */
 } pqn_config_desc;
