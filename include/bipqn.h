@@ -144,8 +144,10 @@ typedef struct {
                                the far field's smooth low modes, which the near patches cannot
                                reach, are solved for directly. Built with the rest of the
                                preconditioner; inv(E) by Newton-Schulz, stored in FP32 (about
-                               4 (27 M)^2 doubles during the set-up, whose Newton-Schulz GEMMs
-                               cost about 14 (27 M)^3 flop; n_theta >= 3, at most 512 nodes per
+                               4 (27 M)^2 doubles kept, whose Newton-Schulz GEMMs cost about
+                               14 (27 M)^3 flop from the block diagonal's inverse, fewer from the
+                               previous configuration's inverse, the start where it is close, as
+                               after a time step; n_theta >= 3, at most 512 nodes per
                                sphere, at most 1024 spheres). Not for batch contexts
                                (PQN_ERR_INVALID) [0] */
 } pqn_config_desc;
@@ -178,6 +180,10 @@ typedef struct {
                                (single-suspension contexts; the lockstep solves' tail launches
                                have fewer densities than the call) */
   int32_t n_far_by_k[6];    /* those launches' counts */
+  int32_t precond_coarse_steps; /* precond_coarse = 1: Newton-Schulz steps of the coarse inverse in
+                                   the set-ups of this call */
+  int32_t precond_coarse_warm;  /* those set-ups that started from the previous configuration's
+                                   coarse inverse */
 } pqn_mvp_stats;
 
 typedef struct {

@@ -79,7 +79,8 @@ class MvpStats(C.Structure):
                 ('t_local_ms', C.c_double), ('t_arnoldi_ms', C.c_double), ('t_precond_ms', C.c_double),
                 ('precond_fallback', C.c_int32), ('precond_applies', C.c_int32),
                 ('t_precond_apply_ms', C.c_double), ('t_far_by_k_ms', C.c_double * 6),
-                ('n_far_by_k', C.c_int32 * 6)]
+                ('n_far_by_k', C.c_int32 * 6), ('precond_coarse_steps', C.c_int32),
+                ('precond_coarse_warm', C.c_int32)]
 
 
 class LcpOpts(C.Structure):

@@ -53,6 +53,8 @@ static void stage_stats(const pqn_ctx_impl& c, pqn_mvp_stats& st) {
   st.t_arnoldi_ms = c.stage_ms[pqn_ctx_impl::kStageArnoldi];
   st.t_precond_ms = c.pc_setup_ms;
   st.precond_fallback = c.pc_fallback;
+  st.precond_coarse_steps = c.pc_coarse_steps;
+  st.precond_coarse_warm = c.pc_coarse_warm;
   st.precond_applies = c.pc_applies;
   st.t_precond_apply_ms = c.stage_ms[pqn_ctx_impl::kStagePrecond];
   for (int k = 0; k < kMaxRhs; ++k) {
@@ -213,12 +215,16 @@ static pqn_status batch_apply_common(pqn_ctx* ctx, const double* const* FT, doub
   ctx->n_graph_launch = 0;
   ctx->pc_setup_ms = 0.0;
   ctx->pc_fallback = 0;
+  ctx->pc_coarse_steps = 0;
+  ctx->pc_coarse_warm = 0;
   ctx->pc_applies = 0;
   ctx->n_far = 0;
   std::fill(ctx->n_far_k, ctx->n_far_k + kMaxRhs, 0);
   for (auto& ch : ctx->children) {
     ch->pc_setup_ms = 0.0;
     ch->pc_fallback = 0;
+    ch->pc_coarse_steps = 0;
+    ch->pc_coarse_warm = 0;
   }
   std::vector<SysRef> sys;
   for (int b = 0; b < nb; ++b) {
@@ -251,6 +257,8 @@ static pqn_status batch_apply_common(pqn_ctx* ctx, const double* const* FT, doub
   for (auto& ch : ctx->children) {  // the suspensions' preconditioner set-ups
     st.t_precond_ms += ch->pc_setup_ms;
     st.precond_fallback += ch->pc_fallback;
+    st.precond_coarse_steps += ch->pc_coarse_steps;
+    st.precond_coarse_warm += ch->pc_coarse_warm;
   }
   st.matvecs = ctx->n_matvec;
   st.n_far = ctx->n_far;
@@ -310,6 +318,8 @@ static pqn_status mobility_multi_common(pqn_ctx* ctx, int32_t k_rhs, const doubl
   ctx->n_graph_launch = 0;
   ctx->pc_setup_ms = 0.0;
   ctx->pc_fallback = 0;
+  ctx->pc_coarse_steps = 0;
+  ctx->pc_coarse_warm = 0;
   ctx->pc_applies = 0;
   ctx->n_far = 0;
   std::fill(ctx->n_far_k, ctx->n_far_k + kMaxRhs, 0);
@@ -408,6 +418,8 @@ static pqn_status mobility_common(pqn_ctx* ctx, const double* FT_dev, const doub
   ctx->n_graph_launch = 0;
   ctx->pc_setup_ms = 0.0;
   ctx->pc_fallback = 0;
+  ctx->pc_coarse_steps = 0;
+  ctx->pc_coarse_warm = 0;
   ctx->pc_applies = 0;
   ctx->n_far = 0;
   std::fill(ctx->n_far_k, ctx->n_far_k + kMaxRhs, 0);
@@ -529,6 +541,8 @@ pqn_status pqn_bie_solve(pqn_ctx* ctx, int32_t fidelity, const double* rhs, doub
     ctx->n_graph_launch = 0;
     ctx->pc_setup_ms = 0.0;
     ctx->pc_fallback = 0;
+    ctx->pc_coarse_steps = 0;
+    ctx->pc_coarse_warm = 0;
     ctx->pc_applies = 0;
     ctx->n_far = 0;
     std::fill(ctx->n_far_k, ctx->n_far_k + kMaxRhs, 0);

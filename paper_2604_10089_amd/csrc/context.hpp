@@ -139,6 +139,9 @@ struct CoarsePc {
   bool on = false;                 // the current configuration applies the coarse correction
   int ncs = 0;                     // coarse far-source nodes per sphere
   int ns_iters = 0;                // Newton-Schulz steps of inv(E) in the last set-up
+  bool have_x = false;             // X holds the last configuration's inverse (the next start)
+  long x_mc = 0;                   // ... of that size
+  bool warm = false;               // the last set-up started from it
   double ns_res = 0.0;             // its final residual ||I - E X||_F / sqrt(Mc)
   DevArray<double> R;              // [27][3n] row-major: the projection (rows c 9 + k)
   DevArray<double> Z;              // [3n][27] row-major: the synthesis at the nodes
@@ -466,6 +469,7 @@ struct pqn_ctx_impl {
   void near_stage(MvGroup& gr, bool from_coef = false);
   double pc_setup_ms = 0.0;  // preconditioner set-up time, fallbacks and applications since the last reset
   int pc_fallback = 0;
+  int pc_coarse_steps = 0, pc_coarse_warm = 0;
   int pc_applies = 0;
   int pc_prec = 0;  // 1: the current GMRES solve's operator is mixed (the coarse far sum in FP32)
   void mobility(Level& lv, const double* FT_dev, const double* axes_dev, double* UO_dev, pqn_mvp_stats* st) {

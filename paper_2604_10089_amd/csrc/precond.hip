@@ -427,6 +427,7 @@ constexpr int kCoarseTheta = 4;
 // Newton-Schulz stop for inv(E): it only shapes the preconditioner (at 216 spheres 1e-2 and
 // 1e-4 give the same 10.0 iterations per MVP; 1e-2 takes 7 instead of 10 GEMMs of (27 M)^3)
 constexpr double kCoarseTol = 1e-2;
+constexpr double kCoarseWarm = 0.5;    // largest residual of the previous inverse used as the start
 constexpr double kCoarseKeep = 1e-1;   // above this after the last step the coarse level stays off
 constexpr int kCoarseMaxSteps = 12;
 constexpr int kCmvCols = 256;          // columns of inv(E) per workgroup of the coarse product
@@ -1066,18 +1067,19 @@ void pqn_ctx_impl::coarse_setup(Level& lv) {
                                (int)cfb_lds));
   hipLaunchKernelGGL(k_coarse_far_blocks, dim3(M * M), dim3(cfb_threads), cfb_lds, s, ctr.p, lv.off.p, cls.p, co.offc.p, co.wc.p,
                      co.Yc.p, co.Tlow.p, n, co.ncs, M, a, co.E.p);
-  // inv(E): Newton-Schulz X <- X (2I - E X) from the block-diagonal inverse. The residual
-  // squares at every step, so once it is below sqrt(kCoarseTol / 10) one more step is taken
-  // without a new residual (its estimate, the square, is what ns_res reports).
+  // inv(E): Newton-Schulz X <- X (2I - E X). The residual squares at every step, so once it
+  // is below sqrt(kCoarseTol / 10) one more step is taken without a new residual (its
+  // estimate, the square, is what ns_res reports). The start is the previous configuration's
+  // inverse when there is one of the same size whose residual on this E is at most
+  // kCoarseWarm (the spheres move little between the configurations of a time-stepping run);
+  // otherwise, and when the iteration from it does not reach kCoarseTol, it is the inverse of
+  // E's block diagonal.
   co.X.alloc((size_t)Mc * Mc);
   co.X2.alloc((size_t)Mc * Mc);
   co.W.alloc((size_t)Mc * Mc);
   co.res.alloc((size_t)Mc);
-  hipLaunchKernelGGL(k_blockdiag, dim3(nblocks(Mc * Mc)), dim3(256), 0, s, co.X0.p, Mc, co.X.p);
   std::vector<double> resp(Mc);
-  co.ns_iters = 0;
-  double res = 1e300;
-  for (int step = 0;; ++step) {
+  auto residual = [&]() {  // W = E X and the RMS column residual of I - W
     launch_gemm64_big(s, (int)Mc, (int)Mc, (int)Mc, co.E.p, (int)Mc, 0, co.X.p, 0, (int)Mc, co.W.p, 0, (int)Mc, 0,
                       (int)Mc, 1, 1);
     hipLaunchKernelGGL(k_col_residual, dim3((unsigned)Mc), dim3(256), 0, s, co.W.p, Mc, co.res.p);
@@ -1085,24 +1087,44 @@ void pqn_ctx_impl::coarse_setup(Level& lv) {
     HIPCHK(hipStreamSynchronize(s));
     double tot = 0.0;
     for (double v : resp) tot += v;
-    res = std::isfinite(tot) ? std::sqrt(tot / Mc) : 1e300;
-    if (res <= kCoarseTol || step == kCoarseMaxSteps) break;
-    const bool last = res * res <= 0.1 * kCoarseTol;
-    hipLaunchKernelGGL(k_diag_minus, dim3((unsigned)Mc), dim3(256), 0, s, co.W.p, (int)Mc, 2.0);
-    launch_gemm64_big(s, (int)Mc, (int)Mc, (int)Mc, co.X.p, (int)Mc, 0, co.W.p, 0, (int)Mc, co.X2.p, 0, (int)Mc, 0,
-                      (int)Mc, 1, 1);
-    std::swap(co.X.p, co.X2.p);
-    ++co.ns_iters;
-    if (last) {
-      res = res * res;
-      break;
+    return std::isfinite(tot) ? std::sqrt(tot / Mc) : 1e300;
+  };
+  auto iterate = [&](double res) {  // from X, whose residual is res, with W = E X
+    for (int step = 0;; ++step) {
+      if (res <= kCoarseTol || step == kCoarseMaxSteps) return res;
+      const bool last = res * res <= 0.1 * kCoarseTol;
+      hipLaunchKernelGGL(k_diag_minus, dim3((unsigned)Mc), dim3(256), 0, s, co.W.p, (int)Mc, 2.0);
+      launch_gemm64_big(s, (int)Mc, (int)Mc, (int)Mc, co.X.p, (int)Mc, 0, co.W.p, 0, (int)Mc, co.X2.p, 0, (int)Mc,
+                        0, (int)Mc, 1, 1);
+      std::swap(co.X.p, co.X2.p);
+      ++co.ns_iters;
+      if (last) return res * res;
+      res = residual();
     }
+  };
+  co.ns_iters = 0;
+  bool warm = co.have_x && co.x_mc == Mc;
+  co.have_x = false;
+  double res = 1e300;
+  if (warm) {
+    res = residual();
+    if (res <= kCoarseWarm) res = iterate(res);
+    warm = res <= kCoarseTol;
+  }
+  if (!warm) {
+    hipLaunchKernelGGL(k_blockdiag, dim3(nblocks(Mc * Mc)), dim3(256), 0, s, co.X0.p, Mc, co.X.p);
+    res = iterate(residual());
   }
   co.ns_res = res;
+  co.warm = warm;
+  pc_coarse_steps += co.ns_iters;
+  pc_coarse_warm += warm ? 1 : 0;
   if (res > kCoarseKeep) return;  // the coarse level stays off for this configuration
   co.Ei.alloc((size_t)Mc * Mc);
   hipLaunchKernelGGL(k_to_f32, dim3(nblocks(Mc * Mc)), dim3(256), 0, s, co.X.p, Mc * Mc, co.Ei.p);
   HIPCHK(hipStreamSynchronize(s));  // dacs and the descriptor staging are released/reused after this
+  co.have_x = true;
+  co.x_mc = Mc;
   co.on = true;
 }
 

@@ -282,6 +282,34 @@ def test_two_level_rsa216_six_force_sets_mixed():
     assert out['two'][1]['gmres_iters'] < 0.8 * out['one'][1]['gmres_iters']
 
 
+def test_two_level_warm_start_after_a_small_move():
+    """A configuration moved a little, as by a time step (every sphere by 1e-3 radii), starts
+    the coarse inverse's Newton-Schulz iteration from the previous configuration's inverse: in
+    fewer steps than a cold set-up, with the plain solve's velocities."""
+    w = inputs.workload('rsa216', 0)
+    c0 = w['centers']
+    M = c0.shape[0]
+    d = np.random.default_rng(5).standard_normal(c0.shape)
+    c1 = c0 + 1e-3 * d / np.linalg.norm(d, axis=1, keepdims=True)
+    FT = inputs.random_forces(7, M)
+    kw = dict(gmres_tol=1e-10, precision='fp64', precond='eager', precond_coarse=True)
+    with binding.Context(c0, None, 12, 24, **kw) as ctx:
+        _, s0 = ctx.mobility_apply(FT)
+        ctx.set_state(c1)
+        Uw, sw = ctx.mobility_apply(FT)
+    with binding.Context(c1, None, 12, 24, **kw) as ctx:
+        Uc, sc = ctx.mobility_apply(FT)
+    with binding.Context(c1, None, 12, 24, gmres_tol=1e-10, precision='fp64') as ctx:
+        Up, _ = ctx.mobility_apply(FT)
+    say('warm start: Newton-Schulz steps cold', s0['precond_coarse_steps'], sc['precond_coarse_steps'], 'warm',
+        sw['precond_coarse_steps'], 'its', sc['gmres_iters'], sw['gmres_iters'], 'set-up ms',
+        round(sc['t_precond_ms'], 1), round(sw['t_precond_ms'], 1))
+    assert s0['precond_coarse_warm'] == 0 and sc['precond_coarse_warm'] == 0 and sw['precond_coarse_warm'] == 1
+    assert sw['precond_coarse_steps'] < sc['precond_coarse_steps']
+    assert abs(sw['gmres_iters'] - sc['gmres_iters']) <= 1
+    assert rel(Uw, Up) < 1e-8 and rel(Uc, Up) < 1e-8
+
+
 def test_two_level_packing64_fp64_equals_plain():
     """64 spheres at gaps down to 0.01 (close class on), FP64: the plain velocities."""
     w = inputs.workload('packing64', 0)
