@@ -566,7 +566,7 @@ def near_patch_preconditioner(geom, A):
     return apply
 
 
-def two_level_preconditioner(geom, A, P, lmax=2, coarse_theta=None):
+def two_level_preconditioner(geom, A, P, lmax=2, coarse_theta=None, coarse_close=None):
     """Two-level right preconditioner: a coarse correction on every sphere's
     harmonics of degree <= lmax (3 (lmax + 1)^2 unknowns per sphere) applied
     before the near-patch preconditioner P (Sec. 2 leaves the preconditioner
@@ -575,7 +575,10 @@ def two_level_preconditioner(geom, A, P, lmax=2, coarse_theta=None):
     with Z the synthesis of those harmonics at the nodes (per sphere and
     component), R the projection on them (quadrature-weighted analysis, R Z = I)
     and A~ the operator with its far pairs summed on a coarse source grid of
-    coarse_theta x 2 coarse_theta nodes (far_coarse_rule; None: A~ = A). The
+    coarse_theta x 2 coarse_theta nodes (far_coarse_rule; None: A~ = A). With
+    coarse_close = d and coarse_theta = (t1, t2), a far pair whose centres are
+    closer than d radii takes the t1 x 2 t1 grid and the others the t2 x 2 t2
+    grid (the closest far pairs carry most of the coarse operator's error). The
     near and self blocks of A~ are A's. Returns P2 as a function of a flat
     node-major vector. Pinned by: for one sphere P2 = A^{-1} when P is; and
     P2 (A~ Z c) = Z c for every coarse vector c, whatever P
@@ -598,13 +601,25 @@ def two_level_preconditioner(geom, A, P, lmax=2, coarse_theta=None):
     for i in range(M):
         Z[i * 3 * n:(i + 1) * 3 * n, i * nb:(i + 1) * nb] = Zb
         R[i * nb:(i + 1) * nb, i * 3 * n:(i + 1) * 3 * n] = Rb
+    def coarse_geometry(t):
+        return Geometry(geom.c, geom.a, geom.n_theta, geom.n_phi, geom.mu, near_gap=geom.near_gap,
+                        near_up=geom.near_up, near_close_gap=geom.near_close_gap,
+                        near_close_up=geom.near_close_up, far_coarse=(t, 2 * t))
+
     if coarse_theta is None:
         At = A
+    elif coarse_close is None:
+        At = dense_operator(coarse_geometry(coarse_theta))
     else:
-        gc = Geometry(geom.c, geom.a, geom.n_theta, geom.n_phi, geom.mu, near_gap=geom.near_gap,
-                      near_up=geom.near_up, near_close_gap=geom.near_close_gap,
-                      near_close_up=geom.near_close_up, far_coarse=(coarse_theta, 2 * coarse_theta))
-        At = dense_operator(gc)
+        At = A.copy()
+        g1, g2 = coarse_geometry(coarse_theta[0]), coarse_geometry(coarse_theta[1])
+        cls = geom.pair_class()
+        d = np.linalg.norm(geom.c[:, None, :] - geom.c[None, :, :], axis=2)
+        for i in range(M):
+            for j in range(M):
+                if cls[i, j] == 0:
+                    g = g1 if d[i, j] < coarse_close * geom.a else g2
+                    At[i * 3 * n:(i + 1) * 3 * n, j * 3 * n:(j + 1) * 3 * n] = offdiag_block(g, i, j, False)
     AZ = At @ Z
     Ei = np.linalg.inv(R @ AZ)
 

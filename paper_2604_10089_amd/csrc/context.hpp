@@ -137,7 +137,8 @@ constexpr int kCoarseL = 9, kCoarseB = 27;
 struct CoarsePc {
   bool tab = false;                // the level's tables below are built
   bool on = false;                 // the current configuration applies the coarse correction
-  int ncs = 0;                     // coarse far-source nodes per sphere
+  int ncs = 0;                     // coarse far-source nodes per sphere (both grids)
+  int ncs1 = 0;                    // ... of the close pairs' grid (the first ncs1)
   int ns_iters = 0;                // Newton-Schulz steps of inv(E) in the last set-up
   bool have_x = false;             // X holds the last configuration's inverse (the next start)
   long x_mc = 0;                   // ... of that size
@@ -147,7 +148,8 @@ struct CoarsePc {
   DevArray<double> Z;              // [3n][27] row-major: the synthesis at the nodes
   DevArray<double> DZ;             // [27][3n] by columns: D Z (the diagonal blocks of A~ Z)
   DevArray<double> Tlow;           // [9][n]: rows k < 9 of the analysis T
-  DevArray<double> offc, wc, Yc;   // coarse far-source grid [ncs][3], [ncs], synthesis [ncs][9]
+  DevArray<double> offc, wc, Yc;   // coarse far-source grids [ncs][3], [ncs], synthesis [ncs][9]
+  DevArray<unsigned char> t1, t2;  // [M][M]: 0 for the far pairs on the close / the distant grid
   DevArray<double> X0, ES;         // inv(R D Z) and R D Z, [27][27] by columns
   DevArray<double> NL;             // near low columns per ordered slot [27][3n] by columns
   DevArray<_Float16> B16;          // D Z and the NL blocks in FP16 (by columns, ld rows)
@@ -158,6 +160,7 @@ struct CoarsePc {
   DevArray<double> res;
   DevArray<float> Ei;              // inv(E) in FP32 by columns
   DevArray<double> cr, cpart, ccI, ccC, qc, bpart;  // application work arrays
+  DevArray<double> src;            // packed coarse far sources [M][ncs] (records of either precision)
   DevArray<GemmDesc> desc;         // R v and the Z c accumulation for K = 1 .. kMaxRhs (2 per K)
   int tr[kMaxRhs] = {}, tz[kMaxRhs] = {};
 };

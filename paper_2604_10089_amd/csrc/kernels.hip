@@ -99,6 +99,57 @@ __device__ __forceinline__ double rsqrt_pos(double x) {
   return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
+// One source sphere j of the FP64 pair sum: nodes [k0, k1) of its records (ns per sphere),
+// added to the target's accumulator when the pair is active (cls 0).
+template <int K>
+__device__ __forceinline__ void far64_tile(int j, int k0, int k1, const double* __restrict__ src,
+                                           const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
+                                           int ns, int M, bool valid, int i, double px, double py, double pz,
+                                           double ox, double oy, double oz, double (&acc)[K][3]) {
+  constexpr int S = src64_stride(K);
+  const bool act = valid && cls[i * M + j] == 0;
+  if (!__any(act)) return;
+  const double Xx = act ? (px - ctr[3 * j]) + ox : 1.0e4;
+  const double Xy = act ? (py - ctr[3 * j + 1]) + oy : 0.0;
+  const double Xz = act ? (pz - ctr[3 * j + 2]) + oz : 0.0;
+  double sm[K][3];
+#pragma unroll
+  for (int r = 0; r < K; ++r) sm[r][0] = sm[r][1] = sm[r][2] = 0.0;
+  const double* sp = src + (size_t)j * ns * S;
+  // r.y = Ct - r^2 / 2 (as in the FP32 tile); (w r).q for K >= 2
+  const double Ct = 0.5 * (Xx * Xx + Xy * Xy + Xz * Xz - (sp[0] * sp[0] + sp[1] * sp[1] + sp[2] * sp[2]));
+#pragma unroll 2
+  for (int kk = k0; kk < k1; ++kk) {
+    const double* e = sp + (size_t)kk * S;
+    const double rx = Xx - e[0], ry = Xy - e[1], rz = Xz - e[2];
+    const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+    const double ri = rsqrt_pos(r2);
+    const double ri2 = ri * ri;
+    const double rn = fma(-0.5, r2, Ct);
+    const double wgt = rn * ri * ri2 * ri2;
+    if constexpr (K == 1) {
+      const double c = wgt * fma(rx, e[3], fma(ry, e[4], rz * e[5]));
+      sm[0][0] = fma(c, rx, sm[0][0]);
+      sm[0][1] = fma(c, ry, sm[0][1]);
+      sm[0][2] = fma(c, rz, sm[0][2]);
+    } else {
+      const double wx = wgt * rx, wy = wgt * ry, wz = wgt * rz;
+#pragma unroll
+      for (int r = 0; r < K; ++r) {
+        const double c = fma(wx, e[3 + 3 * r], fma(wy, e[4 + 3 * r], wz * e[5 + 3 * r]));
+        sm[r][0] = fma(c, rx, sm[r][0]);
+        sm[r][1] = fma(c, ry, sm[r][1]);
+        sm[r][2] = fma(c, rz, sm[r][2]);
+      }
+    }
+  }
+  if (act)
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[r][c] += sm[r][c];
+}
+
 // ----------------------------------------------------------- far pair sum
 //
 // u_r(x) += 3/(4 pi a) sum_y r (r.wq_r,y)(r.o_y)/|r|^5, r = x - y, for every
@@ -358,8 +409,11 @@ template <int K>
 __device__ __forceinline__ void far64_body(int tb, int chunk, const double* __restrict__ src,
                                            const double* __restrict__ off, const double* __restrict__ ctr,
                                            const unsigned char* __restrict__ cls, int n, int ns, int M, int N,
-                                           int spc, double scale, const OPtrs& part) {
-  constexpr int S = src64_stride(K);
+                                           int spc, double scale, const OPtrs& part,
+                                           const unsigned char* __restrict__ cls2 = nullptr, int ns1 = 0) {
+  // FP64 pair sum, one target per thread. With cls2 set, sphere j's records are two source
+  // grids (nodes [0, ns1) and [ns1, ns)), the first summed for the pairs active in cls, the
+  // second for those active in cls2 (the coarse level's two far grids).
   const int t = tb * 256 + threadIdx.x;
   const bool valid = t < N;
   const int tt = valid ? t : N - 1;
@@ -373,47 +427,12 @@ __device__ __forceinline__ void far64_body(int tb, int chunk, const double* __re
 #pragma unroll
   for (int r = 0; r < K; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
   for (int j = j0; j < j1; ++j) {
-    const bool act = valid && cls[i * M + j] == 0;
-    if (!__any(act)) continue;
-    const double Xx = act ? (px - ctr[3 * j]) + ox : 1.0e4;
-    const double Xy = act ? (py - ctr[3 * j + 1]) + oy : 0.0;
-    const double Xz = act ? (pz - ctr[3 * j + 2]) + oz : 0.0;
-    double sm[K][3];
-#pragma unroll
-    for (int r = 0; r < K; ++r) sm[r][0] = sm[r][1] = sm[r][2] = 0.0;
-    const double* sp = src + (size_t)j * ns * S;
-    // r.y = Ct - r^2 / 2 (as in the FP32 tile); (w r).q for K >= 2
-    const double Ct = 0.5 * (Xx * Xx + Xy * Xy + Xz * Xz - (sp[0] * sp[0] + sp[1] * sp[1] + sp[2] * sp[2]));
-#pragma unroll 2
-    for (int kk = 0; kk < ns; ++kk) {
-      const double* e = sp + (size_t)kk * S;
-      const double rx = Xx - e[0], ry = Xy - e[1], rz = Xz - e[2];
-      const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-      const double ri = rsqrt_pos(r2);
-      const double ri2 = ri * ri;
-      const double rn = fma(-0.5, r2, Ct);
-      const double wgt = rn * ri * ri2 * ri2;
-      if constexpr (K == 1) {
-        const double c = wgt * fma(rx, e[3], fma(ry, e[4], rz * e[5]));
-        sm[0][0] = fma(c, rx, sm[0][0]);
-        sm[0][1] = fma(c, ry, sm[0][1]);
-        sm[0][2] = fma(c, rz, sm[0][2]);
-      } else {
-        const double wx = wgt * rx, wy = wgt * ry, wz = wgt * rz;
-#pragma unroll
-        for (int r = 0; r < K; ++r) {
-          const double c = fma(wx, e[3 + 3 * r], fma(wy, e[4 + 3 * r], wz * e[5 + 3 * r]));
-          sm[r][0] = fma(c, rx, sm[r][0]);
-          sm[r][1] = fma(c, ry, sm[r][1]);
-          sm[r][2] = fma(c, rz, sm[r][2]);
-        }
-      }
+    if (cls2) {
+      far64_tile<K>(j, 0, ns1, src, ctr, cls, ns, M, valid, i, px, py, pz, ox, oy, oz, acc);
+      far64_tile<K>(j, ns1, ns, src, ctr, cls2, ns, M, valid, i, px, py, pz, ox, oy, oz, acc);
+    } else {
+      far64_tile<K>(j, 0, ns, src, ctr, cls, ns, M, valid, i, px, py, pz, ox, oy, oz, acc);
     }
-    if (act)
-#pragma unroll
-      for (int r = 0; r < K; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc[r][c] += sm[r][c];
   }
   if (valid)
 #pragma unroll
@@ -422,6 +441,50 @@ __device__ __forceinline__ void far64_body(int tb, int chunk, const double* __re
       pb[t] = scale * acc[r][0];
       pb[N + t] = scale * acc[r][1];
       pb[2 * N + t] = scale * acc[r][2];
+    }
+}
+
+// The FP32 pair sum over two source grids per sphere (as far64_body with cls2), one target
+// per thread.
+template <int K>
+__device__ __forceinline__ void far32c_body(int tb, int chunk, const float* __restrict__ src,
+                                            const double* __restrict__ off, const double* __restrict__ ctr,
+                                            const unsigned char* __restrict__ cls,
+                                            const unsigned char* __restrict__ cls2, int n, int ns, int ns1, int M,
+                                            int N, int spc, double scale, const OPtrs& part) {
+  const int j0 = chunk * spc;
+  const int j1 = min(M, j0 + spc);
+  int ti[1];
+  bool valid[1];
+  double px[1], py[1], pz[1], ox[1], oy[1], oz[1];
+  double acc[1][K][3];
+  const int t = tb * 256 + threadIdx.x;
+  valid[0] = t < N;
+  {
+    const int tt = valid[0] ? t : N - 1;
+    const int i = tt / n;
+    const int k = tt - i * n;
+    ti[0] = i;
+    px[0] = ctr[3 * i];
+    py[0] = ctr[3 * i + 1];
+    pz[0] = ctr[3 * i + 2];
+    ox[0] = off[3 * k];
+    oy[0] = off[3 * k + 1];
+    oz[0] = off[3 * k + 2];
+  }
+#pragma unroll
+  for (int r = 0; r < K; ++r) acc[0][r][0] = acc[0][r][1] = acc[0][r][2] = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    far32_tile<1, K>(j, 0, ns1, src, ctr, cls, ns, M, valid, ti, px, py, pz, ox, oy, oz, acc);
+    far32_tile<1, K>(j, ns1, ns, src, ctr, cls2, ns, M, valid, ti, px, py, pz, ox, oy, oz, acc);
+  }
+  if (valid[0])
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      double* pb = part.p[r] + (size_t)chunk * 3 * N;
+      pb[t] = scale * acc[0][r][0];
+      pb[N + t] = scale * acc[0][r][1];
+      pb[2 * N + t] = scale * acc[0][r][2];
     }
 }
 
@@ -436,26 +499,29 @@ __global__ __launch_bounds__(256) void k_far64(const double* __restrict__ src, c
 }
 
 // The same pair sums launched by the preconditioner's coarse level (far pairs of its
-// coarse operator, sources on the coarse grid): kernels of their own, so that profiles
-// keep them apart from the operator's far launches.
+// coarse operator, sources on its two coarse grids: the pairs active in cls on the first
+// ns1 records of a sphere, those active in cls2 on the rest): kernels of their own, so that
+// profiles keep them apart from the operator's far launches.
 template <int K>
 __global__ __launch_bounds__(256) void k_far32c(const float* __restrict__ src, const double* __restrict__ off,
                                                 const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
-                                                int n, int ns, int M, int N, int spc, double scale, OPtrs part,
-                                                int ntb, int total, int per) {
+                                                const unsigned char* __restrict__ cls2, int n, int ns, int ns1, int M,
+                                                int N, int spc, double scale, OPtrs part, int ntb, int total,
+                                                int per) {
   const int item = xcd_item(blockIdx.x, per);
   if (item >= total) return;
-  far32_body<1, K>(item % ntb, item / ntb, src, off, ctr, cls, n, ns, M, N, spc, scale, part);
+  far32c_body<K>(item % ntb, item / ntb, src, off, ctr, cls, cls2, n, ns, ns1, M, N, spc, scale, part);
 }
 
 template <int K>
 __global__ __launch_bounds__(256) void k_far64c(const double* __restrict__ src, const double* __restrict__ off,
                                                 const double* __restrict__ ctr, const unsigned char* __restrict__ cls,
-                                                int n, int ns, int M, int N, int spc, double scale, OPtrs part,
-                                                int ntb, int total, int per) {
+                                                const unsigned char* __restrict__ cls2, int n, int ns, int ns1, int M,
+                                                int N, int spc, double scale, OPtrs part, int ntb, int total,
+                                                int per) {
   const int item = xcd_item(blockIdx.x, per);
   if (item >= total) return;
-  far64_body<K>(item % ntb, item / ntb, src, off, ctr, cls, n, ns, M, N, spc, scale, part);
+  far64_body<K>(item % ntb, item / ntb, src, off, ctr, cls, n, ns, M, N, spc, scale, part, cls2, ns1);
 }
 
 __global__ __launch_bounds__(256) void k_far64_multi(const FarDesc* __restrict__ desc, int ndesc) {
@@ -1370,29 +1436,29 @@ void launch_far(hipStream_t s, int prec, int K, int tpt, const void* src, const 
 
 template <int K>
 static void far_kc(hipStream_t s, int prec, const void* src, const double* off, const double* ctr,
-                   const unsigned char* cls, int n, int ns, int M, int N, int spc, int nchunks, double scale,
-                   const OPtrs& part) {
+                   const unsigned char* cls, const unsigned char* cls2, int n, int ns, int ns1, int M, int N, int spc,
+                   int nchunks, double scale, const OPtrs& part) {
   const int ntb = (int)nblk(N, 256);
   const int total = ntb * nchunks, per = (total + kXcds - 1) / kXcds;
   const dim3 grid(per * kXcds);
   if (prec == 1)
-    hipLaunchKernelGGL(k_far32c<K>, grid, dim3(256), 0, s, (const float*)src, off, ctr, cls, n, ns, M, N, spc, scale,
-                       part, ntb, total, per);
+    hipLaunchKernelGGL(k_far32c<K>, grid, dim3(256), 0, s, (const float*)src, off, ctr, cls, cls2, n, ns, ns1, M, N,
+                       spc, scale, part, ntb, total, per);
   else
-    hipLaunchKernelGGL(k_far64c<K>, grid, dim3(256), 0, s, (const double*)src, off, ctr, cls, n, ns, M, N, spc,
-                       scale, part, ntb, total, per);
+    hipLaunchKernelGGL(k_far64c<K>, grid, dim3(256), 0, s, (const double*)src, off, ctr, cls, cls2, n, ns, ns1, M, N,
+                       spc, scale, part, ntb, total, per);
 }
 
 void launch_far_coarse(hipStream_t s, int prec, int K, const void* src, const double* off, const double* ctr,
-                       const unsigned char* cls, int n, int ns, int M, int N, int spc, int nchunks, double scale,
-                       const OPtrs& part) {
+                       const unsigned char* cls, const unsigned char* cls2, int n, int ns, int ns1, int M, int N,
+                       int spc, int nchunks, double scale, const OPtrs& part) {
   switch (K) {
-    case 1: far_kc<1>(s, prec, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
-    case 2: far_kc<2>(s, prec, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
-    case 3: far_kc<3>(s, prec, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
-    case 4: far_kc<4>(s, prec, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
-    case 5: far_kc<5>(s, prec, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
-    default: far_kc<6>(s, prec, src, off, ctr, cls, n, ns, M, N, spc, nchunks, scale, part); break;
+    case 1: far_kc<1>(s, prec, src, off, ctr, cls, cls2, n, ns, ns1, M, N, spc, nchunks, scale, part); break;
+    case 2: far_kc<2>(s, prec, src, off, ctr, cls, cls2, n, ns, ns1, M, N, spc, nchunks, scale, part); break;
+    case 3: far_kc<3>(s, prec, src, off, ctr, cls, cls2, n, ns, ns1, M, N, spc, nchunks, scale, part); break;
+    case 4: far_kc<4>(s, prec, src, off, ctr, cls, cls2, n, ns, ns1, M, N, spc, nchunks, scale, part); break;
+    case 5: far_kc<5>(s, prec, src, off, ctr, cls, cls2, n, ns, ns1, M, N, spc, nchunks, scale, part); break;
+    default: far_kc<6>(s, prec, src, off, ctr, cls, cls2, n, ns, ns1, M, N, spc, nchunks, scale, part); break;
   }
 }
 

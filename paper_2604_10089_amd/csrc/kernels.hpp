@@ -145,10 +145,12 @@ void launch_far(hipStream_t s, int prec, int K, int tpt, const void* src, const 
                 const unsigned char* cls, int n, int ns, int M, int N, int spc, int nchunks, double scale,
                 const OPtrs& part);
 // The far pair sum of the preconditioner's coarse level (kernels k_far32c / k_far64c, one
-// target per thread; otherwise as launch_far).
+// target per thread; otherwise as launch_far): ns records per source sphere, the first ns1
+// (one coarse grid) summed for the pairs with cls 0, the rest (the other grid) for those
+// with cls2 0.
 void launch_far_coarse(hipStream_t s, int prec, int K, const void* src, const double* off, const double* ctr,
-                       const unsigned char* cls, int n, int ns, int M, int N, int spc, int nchunks, double scale,
-                       const OPtrs& part);
+                       const unsigned char* cls, const unsigned char* cls2, int n, int ns, int ns1, int M, int N,
+                       int spc, int nchunks, double scale, const OPtrs& part);
 // far sources from the coarse densities qc [M][nc][3K] at the coarse grid (offsets off, weights w)
 void launch_pack_coarse(hipStream_t s, int prec, int K, const double* qc, const double* off, const double* w, int nc,
                         int Nc, void* src);

@@ -419,11 +419,16 @@ __global__ __launch_bounds__(256) void k_pc_sum_multi(const PcDesc* __restrict__
 
 // ------------------------------------------------- coarse level (precond_coarse)
 
-// Coarse far-source grid: kCoarseTheta x 2 kCoarseTheta nodes whatever the grid (its error is
-// that of integrating the far kernel against degree <= 2 densities, set by the geometry). At
-// 216 spheres, 12x24: 3x6 gives 11.0 GMRES iterations per MVP, 4x8 10.0, 5x10 9.5, 6x12 9.25;
-// the six-force-set pass takes 59.1, 56.0, 56.3 and 58.2 ms.
-constexpr int kCoarseTheta = 4;
+// Coarse far-source grids, whatever the discretisation (their error is that of integrating
+// the far kernel against degree <= 2 densities, set by the geometry): far pairs whose centres
+// are closer than kCoarseClose radii on kCoarseThetaClose x 2 kCoarseThetaClose nodes, the
+// others on kCoarseTheta x 2 kCoarseTheta. One grid for all far pairs, at 216 spheres and
+// 12x24: 3x6 gives 11.0 GMRES iterations per MVP, 4x8 10.0, 5x10 9.5, 6x12 9.25 (the
+// six-force-set pass 59.1, 56.0, 56.3 and 58.2 ms): the closest far pairs carry most of the
+// coarse operator's error, and the distant ones, most of its cost.
+constexpr int kCoarseTheta = 3;
+constexpr int kCoarseThetaClose = 6;
+constexpr double kCoarseClose = 3.5;
 // Newton-Schulz stop for inv(E): it only shapes the preconditioner (at 216 spheres 1e-2 and
 // 1e-4 give the same 10.0 iterations per MVP; 1e-2 takes 7 instead of 10 GEMMs of (27 M)^3)
 constexpr double kCoarseTol = 1e-2;
@@ -502,21 +507,29 @@ constexpr int kCfbChunk = 18;    // u values per target staged in LDS at a time 
 __global__ __launch_bounds__(64 * kCfbMaxWaves) void k_coarse_far_blocks(const double* __restrict__ ctr,
                                                                          const double* __restrict__ off,
                                                                          const unsigned char* __restrict__ cls,
+                                                                         const unsigned char* __restrict__ t1,
                                                                          const double* __restrict__ offc,
                                                                          const double* __restrict__ wc,
                                                                          const double* __restrict__ Yc,
                                                                          const double* __restrict__ Tlow, int n,
-                                                                         int ncs, int M, double a,
+                                                                         int ncs_all, int ncs1, int M, double a,
                                                                          double* __restrict__ E) {
   constexpr int NP = 6, NV = NP * kCoarseL;  // 54 per target
-  // dynamic LDS: source positions (rel. c_i) and offsets [ncs][6], s wc Y_k [ncs][9], staged u
-  // [blockDim][kCfbChunk + 1] (padded rows)
+  // dynamic LDS: source positions (rel. c_i) and offsets [nmax][6], s wc Y_k [nmax][9], staged
+  // u [blockDim][kCfbChunk + 1] (padded rows); nmax the larger grid's node count
   extern __shared__ double lds_cfb[];
+  const int nmax = max(ncs1, ncs_all - ncs1);
   double(*sy)[6] = reinterpret_cast<double(*)[6]>(lds_cfb);
-  double(*swy)[kCoarseL] = reinterpret_cast<double(*)[kCoarseL]>(lds_cfb + 6 * ncs);
-  double(*su)[kCfbChunk + 1] = reinterpret_cast<double(*)[kCfbChunk + 1]>(lds_cfb + (6 + kCoarseL) * ncs);
+  double(*swy)[kCoarseL] = reinterpret_cast<double(*)[kCoarseL]>(lds_cfb + 6 * nmax);
+  double(*su)[kCfbChunk + 1] = reinterpret_cast<double(*)[kCfbChunk + 1]>(lds_cfb + (6 + kCoarseL) * nmax);
   const int i = blockIdx.x / M, j = blockIdx.x - (blockIdx.x / M) * M;
   if (i == j || cls[(size_t)i * M + j] != 0) return;  // uniform over the block
+  // the pair's grid: the first ncs1 nodes of the tables (close pairs) or the rest
+  const int f0 = t1[(size_t)i * M + j] == 0 ? 0 : ncs1;
+  const int ncs = f0 == 0 ? ncs1 : ncs_all - ncs1;
+  offc += 3 * f0;
+  wc += f0;
+  Yc += (size_t)f0 * kCoarseL;
   const int t = threadIdx.x;
   const double dx = ctr[3 * j] - ctr[3 * i], dy = ctr[3 * j + 1] - ctr[3 * i + 1], dz = ctr[3 * j + 2] - ctr[3 * i + 2];
   const double s = 3.0 / (4.0 * kPi * a);
@@ -947,10 +960,18 @@ void pqn_ctx_impl::coarse_tables(Level& lv) {
   invert_gauss_jordan(X0r, kCoarseB);  // row-major inverse of R D Z
   for (int b = 0; b < kCoarseB; ++b)
     for (int bp = 0; bp < kCoarseB; ++bp) X0[(size_t)b * kCoarseB + bp] = X0r[(size_t)bp * kCoarseB + b];
-  const int ntc = kCoarseTheta;
+  // the two coarse grids' tables, close grid first: offsets [ncs][3], weights [ncs], Y [ncs][9]
   std::vector<double> oc, wcv, Yc;
-  coarse_sh_grid(ntc, 2 * ntc, a, 2, oc, wcv, Yc);
-  co.ncs = ntc * 2 * ntc;
+  coarse_sh_grid(kCoarseThetaClose, 2 * kCoarseThetaClose, a, 2, oc, wcv, Yc);
+  {
+    std::vector<double> oc2, wc2, Yc2;
+    coarse_sh_grid(kCoarseTheta, 2 * kCoarseTheta, a, 2, oc2, wc2, Yc2);
+    oc.insert(oc.end(), oc2.begin(), oc2.end());
+    wcv.insert(wcv.end(), wc2.begin(), wc2.end());
+    Yc.insert(Yc.end(), Yc2.begin(), Yc2.end());
+  }
+  co.ncs1 = 2 * kCoarseThetaClose * kCoarseThetaClose;
+  co.ncs = co.ncs1 + 2 * kCoarseTheta * kCoarseTheta;
   co.R.upload(R.data(), R.size(), s);
   co.Z.upload(Z.data(), Z.size(), s);
   co.DZ.upload(DZ.data(), DZ.size(), s);
@@ -965,6 +986,7 @@ void pqn_ctx_impl::coarse_tables(Level& lv) {
   co.ccC.alloc((size_t)Mc * kMaxRhs);
   co.cpart.alloc((size_t)((Mc + kCmvCols - 1) / kCmvCols) * Mc * kMaxRhs);
   co.qc.alloc((size_t)M * co.ncs * 3 * kMaxRhs);
+  co.src.alloc((size_t)M * co.ncs * src64_stride(kMaxRhs));
   std::vector<GemmDesc> d;
   for (int K = 1; K <= kMaxRhs; ++K) {
     int blocks = 0;
@@ -992,6 +1014,24 @@ void pqn_ctx_impl::coarse_setup(Level& lv) {
   const int n = lv.n, n3 = 3 * n, M = lv.M, L = lv.L, nc = 3 * L;
   const long Mc = (long)kCoarseB * M;
   const size_t ncn = (size_t)nc * n3;
+  // which far pairs take the close grid (centres closer than kCoarseClose radii)
+  {
+    std::vector<unsigned char> t1((size_t)M * M, 1), t2((size_t)M * M, 1);
+    for (int i = 0; i < M; ++i) {
+      std::vector<char> nb(M, 0);
+      nb[i] = 1;
+      for (int sl = 0; sl < h_npart[i]; ++sl) nb[h_partners[(size_t)i * kMaxNear + sl]] = 1;
+      for (int j = 0; j < M; ++j) {
+        if (nb[j]) continue;
+        const double dx = centers[3 * j] - centers[3 * i], dy = centers[3 * j + 1] - centers[3 * i + 1],
+                     dz = centers[3 * j + 2] - centers[3 * i + 2];
+        const bool close = dx * dx + dy * dy + dz * dz < (kCoarseClose * a) * (kCoarseClose * a);
+        (close ? t1 : t2)[(size_t)i * M + j] = 0;
+      }
+    }
+    co.t1.upload(t1.data(), t1.size(), s);
+    co.t2.upload(t2.data(), t2.size(), s);
+  }
   // near low columns, slot by slot
   std::vector<long> acs;
   for (int i = 0; i < M; ++i)
@@ -1061,12 +1101,13 @@ void pqn_ctx_impl::coarse_setup(Level& lv) {
   }
   if (n > 64 * kCfbMaxWaves) throw Error(PQN_ERR_INVALID, "precond_coarse supports at most 512 nodes per sphere");
   const int cfb_threads = 64 * ((n + 63) / 64);
-  const size_t cfb_lds = sizeof(double) * ((size_t)(6 + kCoarseL) * co.ncs + (size_t)cfb_threads * (kCfbChunk + 1));
+  const int cfb_nodes = std::max(co.ncs1, co.ncs - co.ncs1);  // the larger of the two grids
+  const size_t cfb_lds = sizeof(double) * ((size_t)(6 + kCoarseL) * cfb_nodes + (size_t)cfb_threads * (kCfbChunk + 1));
   if (cfb_lds > 65536)
     HIPCHK(hipFuncSetAttribute((const void*)k_coarse_far_blocks, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)cfb_lds));
-  hipLaunchKernelGGL(k_coarse_far_blocks, dim3(M * M), dim3(cfb_threads), cfb_lds, s, ctr.p, lv.off.p, cls.p, co.offc.p, co.wc.p,
-                     co.Yc.p, co.Tlow.p, n, co.ncs, M, a, co.E.p);
+  hipLaunchKernelGGL(k_coarse_far_blocks, dim3(M * M), dim3(cfb_threads), cfb_lds, s, ctr.p, lv.off.p, cls.p, co.t1.p,
+                     co.offc.p, co.wc.p, co.Yc.p, co.Tlow.p, n, co.ncs, co.ncs1, M, a, co.E.p);
   // inv(E): Newton-Schulz X <- X (2I - E X). The residual squares at every step, so once it
   // is below sqrt(kCoarseTol / 10) one more step is taken without a new residual (its
   // estimate, the square, is what ns_res reports). The start is the previous configuration's
@@ -1169,13 +1210,13 @@ void pqn_ctx_impl::coarse_pre(MvGroup& gr) {
   // far of A~ z1: the coarse density at the coarse source grid, summed by the far kernel
   hipLaunchKernelGGL(k_coarse_qc, dim3(nblocks((long)M * co.ncs * 3 * K)), dim3(256), 0, s, co.Yc.p, co.ccI.p, co.ncs,
                      M, K, co.qc.p);
-  launch_pack_coarse(s, pc_prec, K, co.qc.p, co.offc.p, co.wc.p, co.ncs, M * co.ncs, lv.src.p);
+  launch_pack_coarse(s, pc_prec, K, co.qc.p, co.offc.p, co.wc.p, co.ncs, M * co.ncs, co.src.p);
   OPtrs fp{};
   for (int r = 0; r < K; ++r) fp.p[r] = lv.wk(r).far_part.p;
   // the level's source chunks (with fewer, e.g. 6 of 24, the launch has too few waves to
   // balance: 1.22 against 0.90 ms for six densities at 216 spheres)
-  launch_far_coarse(s, pc_prec, K, lv.src.p, lv.off.p, ctr.p, cls.p, n, co.ncs, M, N, lv.spc, lv.nchunks,
-                    3.0 / (4.0 * kPi * a), fp);
+  launch_far_coarse(s, pc_prec, K, co.src.p, lv.off.p, ctr.p, co.t1.p, co.t2.p, n, co.ncs, co.ncs1, M, N, lv.spc,
+                    lv.nchunks, 3.0 / (4.0 * kPi * a), fp);
   hipLaunchKernelGGL(k_coarse_resid, dim3(nblocks((long)K * M * n3)), dim3(256), 0, s, lv.pc.vC.p, co.bpart.p,
                      co.bptr.p, fp, lv.nchunks, K, n, M, N);
 }

@@ -242,14 +242,18 @@ def test_side_stream_preconditioned_is_bit_identical(prec):
 
 def test_two_level_matches_oracle_and_its_iteration_count(tiny_cases):
     """precond_coarse (a coarse correction on every sphere's degree <= 2 harmonics before
-    the near patches; its far pairs on a 4x8 source grid at 8x16 nodes): the oracle's
-    density, in the oracle's two-level iteration count (+-1: inv(E) by Newton-Schulz to
-    1e-4 and stored in FP32 on the device), fewer than with one level."""
+    the near patches; its far pairs on a 6x12 source grid when their centres are closer
+    than 3.5 radii, else on a 3x6 grid, at 8x16 nodes): the oracle's density, in the
+    oracle's two-level iteration count (+-1: inv(E) by Newton-Schulz to 1e-2 and stored in
+    FP32 on the device), fewer than with one level."""
     for seed, g, A in tiny_cases:
         rhs = -bie.completion(g, inputs.random_forces(40 + seed, g.M))
         q = np.linalg.solve(A, rhs.ravel())
         P = bie.near_patch_preconditioner(g, A)
-        P2 = bie.two_level_preconditioner(g, A, P, coarse_theta=4)
+        d = np.linalg.norm(g.c[:, None] - g.c[None], axis=2)
+        far = g.pair_class() == 0
+        say('far pairs closer than 3.5:', int((far & (d < 3.5)).sum()), 'of', int(far.sum()))
+        P2 = bie.two_level_preconditioner(g, A, P, coarse_theta=(6, 3), coarse_close=3.5)
         _, its1, _ = bie.gmres(lambda v: A @ v.ravel(), rhs, tol=1e-10, right=P)
         _, its2, _ = bie.gmres(lambda v: A @ v.ravel(), rhs, tol=1e-10, right=P2)
         with binding.Context(g.c, None, 8, 16, gmres_tol=1e-10, precond='eager', precond_coarse=True) as ctx:

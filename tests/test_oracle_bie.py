@@ -489,6 +489,20 @@ def test_two_level_preconditioner_pins():
     # exact coarse far (A~ = A): the same on A
     P2e = bie.two_level_preconditioner(g, A, zero)
     assert np.abs(P2e(A @ z) - z).max() < 1e-10 * np.abs(z).max()
+    # two grids by distance: spheres 0 and 2 (centres 3.1 apart, far) take the 6 x 12 grid,
+    # which on this 6 x 12 discretisation sums the coarse densities (degree <= 2) exactly as
+    # the node rule does; 0 and 3 (5.1 apart) the 3 x 6 grid; the near pair 0-1 and the self
+    # blocks are A's
+    P2t = bie.two_level_preconditioner(g, A, zero, coarse_theta=(6, 3), coarse_close=3.5)
+    Att, n3, nb = P2t.At, 3 * g.n, Z.shape[1] // g.M
+    blk = lambda X, i, j: X[i * n3:(i + 1) * n3, j * n3:(j + 1) * n3]  # noqa: E731
+    Zb = Z[:n3, :nb]
+    assert g.pair_class()[0, 2] == 0 and g.pair_class()[0, 3] == 0 and g.pair_class()[0, 1] == 1
+    assert np.abs((blk(Att, 0, 2) - blk(A, 0, 2)) @ Zb).max() < 1e-12 * np.abs(blk(A, 0, 2) @ Zb).max()
+    assert np.abs(blk(Att, 0, 3) - blk(At, 0, 3)).max() < 1e-14 * np.abs(blk(At, 0, 3)).max()
+    assert np.abs((blk(At, 0, 2) - blk(A, 0, 2)) @ Zb).max() > 1e-6 * np.abs(blk(A, 0, 2) @ Zb).max()
+    assert np.array_equal(blk(Att, 0, 1), blk(A, 0, 1)) and np.array_equal(blk(Att, 1, 1), blk(A, 1, 1))
+    assert np.abs(P2t(Att @ z) - z).max() < 1e-10 * np.abs(z).max()
 
 
 def test_two_level_gmres_solves_the_same_system_in_fewer_iterations(tiny_cases):
