@@ -140,7 +140,9 @@ typedef struct {
                                the near-patch preconditioner P_f: z1 = Z inv(E) R v,
                                z = z1 + P_f (v - A~ z1), E = R A~ Z, R the projection on those
                                harmonics, Z their synthesis, A~ the operator with its far pairs
-                               summed on a coarse source grid of 4 x 8 nodes:
+                               summed on coarse source grids (6 x 12 nodes for
+                               far pairs whose centres are closer than 3.5
+                               radii, 3 x 6 for the others):
                                the far field's smooth low modes, which the near patches cannot
                                reach, are solved for directly. Built with the rest of the
                                preconditioner; inv(E) by Newton-Schulz, stored in FP32 (about
