@@ -1031,6 +1031,7 @@ void pqn_ctx_impl::coarse_setup(Level& lv) {
     }
     co.t1.upload(t1.data(), t1.size(), s);
     co.t2.upload(t2.data(), t2.size(), s);
+    HIPCHK(hipStreamSynchronize(s));  // t1 and t2 are released after this
   }
   // near low columns, slot by slot
   std::vector<long> acs;
