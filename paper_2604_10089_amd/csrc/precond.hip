@@ -1215,7 +1215,9 @@ void pqn_ctx_impl::coarse_pre(MvGroup& gr) {
   OPtrs fp{};
   for (int r = 0; r < K; ++r) fp.p[r] = lv.wk(r).far_part.p;
   // the level's source chunks (with fewer, e.g. 6 of 24, the launch has too few waves to
-  // balance: 1.22 against 0.90 ms for six densities at 216 spheres)
+  // balance: 1.22 against 0.90 ms for six densities at 216 spheres on one 6x12 grid; with
+  // the two grids, 12 or 8 chunks gave 51.2-51.7 against 51.0-51.2 ms per six-force-set
+  // pass, although their partials are two or three times fewer)
   launch_far_coarse(s, pc_prec, K, co.src.p, lv.off.p, ctr.p, co.t1.p, co.t2.p, n, co.ncs, co.ncs1, M, N, lv.spc,
                     lv.nchunks, 3.0 / (4.0 * kPi * a), fp);
   hipLaunchKernelGGL(k_coarse_resid, dim3(nblocks((long)K * M * n3)), dim3(256), 0, s, lv.pc.vC.p, co.bpart.p,
